@@ -1,0 +1,257 @@
+/*
+ * grainenv — MI355X (gfx950) implementation of the per-step update of the
+ * particle-based grain-envelope method for solidification microstructures
+ * (Mosbah, Gomez Vazquez, Zenz, Tourret, Otto, arXiv:2504.12858).
+ *
+ * One step of the method, for every tracking particle of every grain:
+ *   - undercooling at the particle from the thermal field (Sec. 2.3: the
+ *     field is interpolated at particle positions),
+ *   - growth velocity from the kinetic law Eq. (1)/(2) (Sec. 2.1.2),
+ *   - advance along the grain's rotated <100> direction (Sec. 2.1.2),
+ *   - branching into outer directions after lambda0 of travel (Sec. 2.1.2,
+ *     Fig. 2),
+ *   - rebinning into a uniform cell list and deactivation of particles that
+ *     meet another grain's particles (grain-boundary formation, Sec. 2.1.2;
+ *     neighbour search, Sec. 2.3),
+ *   - nucleation of liquid sites whose undercooling reaches their drawn
+ *     threshold (Sec. 2.1.1).
+ *
+ * Conventions
+ *   - SI units.  Undercooling dT = T_L - T in kelvin, minus the offset theta.
+ *   - Every function returns a ge_status; nothing throws across the ABI.
+ *   - A context owns no device memory: the caller passes a workspace of
+ *     ge_workspace_size() bytes (device memory) and a HIP stream; every
+ *     device operation of the context is issued on that stream.
+ *   - Host arrays passed in are copied before the call returns.  Device
+ *     arrays passed in are read in stream order: keep them alive until the
+ *     stream has passed the call.
+ *   - One context per stream; a context is not thread-safe.
+ *   - Errors found on the device (capacity, non-finite values, CFL) are
+ *     sticky: they surface at the next call that synchronises (ge_step with
+ *     non-null stats, ge_query_envelope) and leave the context unusable for
+ *     further steps (GE_ESTATE).  Recover by re-creating the context with
+ *     larger capacities and reloading a saved state.
+ */
+#ifndef GRAINENV_H
+#define GRAINENV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ge_status;
+#define GE_OK 0
+#define GE_EINVAL (-1)     /* invalid argument or parameter set */
+#define GE_ECAPACITY (-2)  /* a capacity of the context was exceeded */
+#define GE_ENUMERIC (-3)   /* non-finite undercooling or travel */
+#define GE_ECFL (-4)       /* v dt > rc / 2, or travel >= 2 lambda0 before branching */
+#define GE_EDEVICE (-5)    /* HIP runtime error */
+#define GE_ESTATE (-6)     /* context unusable after an earlier device error */
+
+/* Thermal field kinds (values of ge_field.kind). */
+#define GE_FIELD_UNIFORM 0   /* dT(x, t) = dT */
+#define GE_FIELD_LINEAR 1    /* dT(x, t) = dT0 + grad . x + rate t */
+#define GE_FIELD_GRID 2      /* trilinear interpolation of node values */
+#define GE_FIELD_ROSENTHAL 3 /* LINEAR background minus a moving point source,
+                                resampled onto the node grid every step */
+
+/* Particle states in exported records. */
+#define GE_ACTIVE 0
+#define GE_STOPPED 1
+#define GE_RETIRED 2
+
+/* Nucleation-site states. */
+#define GE_SITE_DORMANT 0
+#define GE_SITE_FIRED 1
+#define GE_SITE_ENGULFED 2 /* inside a grain's claims: can never fire */
+
+/*
+ * Model and capacity parameters.
+ *
+ * Kinetic law, Eq. (2) (Sec. 2.1.2):  v = a[0] dT^b[0] + a[1] dT^b[1] for
+ * dT > 0, v = 0 otherwise (Eq. (1) is a[1] = 0).  Exponents (2, 3) take a
+ * polynomial path, any other exponents the power path.
+ *
+ * Geometry: the box is [lo, hi); the cell list has cells of edge h covering
+ * it (ceil((hi - lo) / h) per axis), grouped in bricks of 8^3 cells.  The
+ * contact radius rc must satisfy rc <= h (the 27-cell stencil is then
+ * complete) and rc <= lambda0.  Lattice sites must stay within +-16383 of a
+ * grain's centre: (box diagonal) / lambda0 < 16383.
+ */
+typedef struct ge_params {
+  double lo[3], hi[3];   /* box [m] */
+  double lambda0;        /* branching spacing: distance between tracking points [m] */
+  double h;              /* cell edge [m] */
+  double rc;             /* contact radius: particles of two grains closer than rc meet [m] */
+  double a[2], b[2];     /* kinetic law coefficients [m s^-1 K^-b] and exponents */
+  double theta;          /* undercooling offset [K], subtracted from the field */
+  int32_t branching;     /* 1: particles branch after lambda0 of travel; 0: they never do */
+  int32_t box_exit;      /* 1: particles leaving the box stop */
+  int64_t cap_particles; /* capacity of the active particle store */
+  int64_t cap_stopped;   /* capacity of the stopped particle store */
+  int32_t cap_grains;    /* maximum number of grains (< 2^28 - 1) */
+  int32_t cap_sites;     /* maximum number of nucleation sites */
+  int64_t cap_claim_bricks; /* slots of the claim hash (rounded up to a power of two);
+                               each slot holds 8^3 lattice sites of one grain */
+  int32_t field_n[3];    /* largest field grid the context will hold (nodes per axis) */
+} ge_params;
+
+/* Thermal field (Sec. 2.3 interpolation; Sec. 3.1 / 3.4 imposed fields). */
+typedef struct ge_field {
+  int32_t kind;
+  double dT;                /* UNIFORM */
+  double dT0, grad[3], rate;/* LINEAR, and ROSENTHAL background [K, K/m, K/s] */
+  int32_t n[3];             /* GRID / ROSENTHAL: nodes per axis (>= 2, <= field_n) */
+  double origin[3];         /* node (0,0,0) [m] */
+  double spacing[3];        /* node spacing [m] */
+  const float* data;        /* GRID: node values, index (k*ny + j)*nx + i */
+  int32_t data_on_device;   /* 1: data is device memory read in stream order */
+  /* ROSENTHAL source: dT -= q / (2 pi r) exp(-U (xi + r) / (2 alpha)),
+     r = max(|x - x_s(t)|, r_min), xi = signed distance along the travel
+     direction; the source rasters back and forth along x between x_start
+     and x_end at speed U, at (y, z) = (ys, zs); dT is floored at dT_min. */
+  double q, U, alpha, x_start, x_end, ys, zs, r_min, dT_min;
+} ge_field;
+
+/* Counters of a ge_step call (sums over its steps) and the state after it. */
+typedef struct ge_step_stats {
+  int64_t n_active;   /* active particles after the last step */
+  int64_t n_stopped;  /* stopped particles after the last step */
+  int64_t n_grains;
+  int64_t n_claim_bricks;
+  int64_t advanced;   /* particle updates: active particles advanced */
+  int64_t exited;     /* particles stopped by leaving the box */
+  int64_t spawners;   /* particles that reached their target */
+  int64_t children;   /* particles created by branching */
+  int64_t contained;  /* particles stopped by meeting another grain */
+  int64_t nucleated;  /* sites fired */
+  double max_step;    /* largest v dt of the call [m] */
+  double t;           /* time after the call [s] */
+  int64_t step;       /* steps taken since creation or the last state load */
+} ge_step_stats;
+
+/* Query kinds of ge_query_envelope. */
+#define GE_QUERY_COUNTS 0    /* out: ge_step_stats (counters zero) */
+#define GE_QUERY_PARTICLES 1 /* out: ge_particle_rec[n_active + n_stopped] */
+#define GE_QUERY_GRAIN_MAP 2 /* out: uint32 labels [n2][n1][n0], 0 = liquid, g + 1 = grain g */
+#define GE_QUERY_CLAIMS 3    /* out: ge_claim_rec[...] */
+#define GE_QUERY_SITES 4     /* out: int32 site states [n_sites] */
+#define GE_QUERY_GRAINS 5    /* out: float [n_grains][24]: centre, pad, R (row-major), lambda0 R */
+
+/* Exported particle: position computed on the device, binning cell. */
+typedef struct ge_particle_rec {
+  float x, y, z;
+  float s;           /* travel since the departure site [m] */
+  int32_t site[3];   /* departure lattice site (crystal frame) */
+  uint32_t grain;
+  uint8_t dir;       /* 0..5 = +x,-x,+y,-y,+z,-z of the crystal frame */
+  uint8_t state;     /* GE_ACTIVE / GE_STOPPED */
+  uint16_t pad;
+  int32_t cell[3];   /* cell of the uniform cell list holding the particle */
+} ge_particle_rec;   /* 48 bytes */
+
+/* Exported claimed lattice site. */
+typedef struct ge_claim_rec {
+  uint32_t grain;
+  int32_t site[3];
+  uint32_t flags;    /* 1 = claimed as a target, 2 = reached */
+} ge_claim_rec;      /* 20 bytes */
+
+/* Arguments of GE_QUERY_GRAIN_MAP: voxel centre = origin + (i + 1/2) spacing.
+   A voxel takes the grain whose reached lattice site nearest to the voxel
+   centre is the voxel's own rounded site (Voronoi interpolation, Sec. 2.3). */
+typedef struct ge_query_args {
+  int32_t n[3];
+  double origin[3];
+  double spacing[3];
+} ge_query_args;
+
+/* Full state for ge_load_state (host arrays). */
+typedef struct ge_state_in {
+  int32_t n_grains;
+  const double* centre;    /* [n_grains][3] */
+  const double* quat;      /* [n_grains][4] (w, x, y, z), crystal -> world */
+  int64_t n_particles;
+  const int32_t* grain;    /* [n] */
+  const int32_t* site;     /* [n][3] */
+  const int32_t* dir;      /* [n] */
+  const float* s;          /* [n] */
+  const int32_t* state;    /* [n] GE_ACTIVE / GE_STOPPED (GE_RETIRED entries are dropped) */
+  int64_t n_claims;
+  const int32_t* c_grain;  /* [m] */
+  const int32_t* c_site;   /* [m][3] */
+  const uint8_t* c_flags;  /* [m] */
+  int32_t n_sites;         /* must equal the number of registered sites */
+  const int32_t* site_state; /* [n_sites] */
+  double t;
+  int64_t step;
+} ge_state_in;
+
+typedef struct ge_ctx ge_ctx;
+
+/* Bytes of device workspace the parameters need.  EINVAL on invalid params. */
+ge_status ge_workspace_size(const ge_params* p, size_t* bytes);
+
+/* Checks the parameters without touching a device. */
+ge_status ge_validate_params(const ge_params* p);
+
+/* Creates a context over a caller-owned device workspace of at least
+   ge_workspace_size() bytes (256-byte aligned) and a caller-owned HIP stream
+   (hipStream_t, may be NULL for the null stream).  The workspace is
+   initialised on the stream. */
+ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* stream,
+                    ge_ctx** out);
+
+/* Destroys the context (host memory only; the workspace stays the caller's). */
+ge_status ge_destroy(ge_ctx* ctx);
+
+/* Text of the last error of the context ("" if none). */
+const char* ge_last_error(const ge_ctx* ctx);
+
+/* Appends n grains (Sec. 2.1.2).  shell_r[i] = 0: a nucleus of six particles
+   at the centre moving along the six <100> directions (Step 0 of Fig. 2),
+   the centre site claimed.  shell_r[i] = r > 0: an octahedral envelope of L1
+   radius r lattice steps: one particle per lattice site of the L1 shell r,
+   moving along its axis of largest |offset| (lowest axis on ties), all sites
+   of the L1 ball r claimed as reached.  Particles outside the box start
+   stopped.  first_id (nullable) receives the index of the first new grain.
+   ECAPACITY when a capacity would be exceeded. */
+ge_status ge_init_grains(ge_ctx* ctx, int32_t n, const double* centre /*[n][3]*/,
+                         const double* quat /*[n][4]*/, const int32_t* shell_r /*[n]*/,
+                         uint32_t* first_id);
+
+/* Sets the thermal field used from the next step on (undercooling values).
+   ENUMERIC on non-finite scalars; EINVAL on a grid larger than field_n. */
+ge_status ge_set_thermal_field(ge_ctx* ctx, const ge_field* f);
+
+/* Registers n dormant nucleation sites (Sec. 2.1.1): position, nucleation
+   undercooling and orientation.  A site fires inside ge_step when the
+   undercooling at the site reaches its threshold and the site is liquid (no
+   particle within rc, not inside any grain's claims); it then becomes a new
+   grain with six particles at the site.  Sites fired in the same step get
+   grain ids in site order.  ECAPACITY when cap_sites would be exceeded. */
+ge_status ge_nucleate(ge_ctx* ctx, int32_t n, const double* xyz /*[n][3]*/,
+                      const double* dT_nuc /*[n]*/, const double* quat /*[n][4]*/);
+
+/* Advances n_steps steps of dt seconds on the context's stream.  Returns at
+   once unless stats is non-null; then it synchronises, fills stats and
+   returns any sticky device error. */
+ge_status ge_step(ge_ctx* ctx, double dt, int32_t n_steps, ge_step_stats* stats);
+
+/* Exports part of the state into a caller-owned buffer (host or device).
+   With out == NULL (or out_bytes too small) only *needed is set.  The call
+   synchronises when out is host memory. */
+ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args, void* out,
+                            size_t out_bytes, size_t* needed);
+
+/* Replaces grains, particles, claims, site states, time and step. */
+ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAINENV_H */

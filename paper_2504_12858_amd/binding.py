@@ -1,0 +1,341 @@
+"""Python binding of libgrainenv: argument marshalling over the C ABI.
+
+Every step of the method runs in the library's HIP kernels.  PyTorch supplies
+the device workspace and the stream; numpy arrays carry host inputs.  The
+binding fails loudly when the library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrainenv.so")
+
+GE_OK, GE_EINVAL, GE_ECAPACITY, GE_ENUMERIC, GE_ECFL, GE_EDEVICE, GE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "ENUMERIC", -4: "ECFL",
+                -5: "EDEVICE", -6: "ESTATE"}
+FIELD_UNIFORM, FIELD_LINEAR, FIELD_GRID, FIELD_ROSENTHAL = 0, 1, 2, 3
+QUERY_COUNTS, QUERY_PARTICLES, QUERY_GRAIN_MAP, QUERY_CLAIMS, QUERY_SITES, QUERY_GRAINS = range(6)
+ACTIVE, STOPPED, RETIRED = 0, 1, 2
+
+PARTICLE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("s", "<f4"),
+                           ("site", "<i4", 3), ("grain", "<u4"), ("dir", "u1"), ("state", "u1"),
+                           ("pad", "<u2"), ("cell", "<i4", 3)])
+CLAIM_DTYPE = np.dtype([("grain", "<u4"), ("site", "<i4", 3), ("flags", "<u4")])
+assert PARTICLE_DTYPE.itemsize == 48 and CLAIM_DTYPE.itemsize == 20
+
+
+class GrainEnvError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ge_params(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("lambda0", C.c_double),
+                ("h", C.c_double), ("rc", C.c_double), ("a", C.c_double * 2),
+                ("b", C.c_double * 2), ("theta", C.c_double), ("branching", C.c_int32),
+                ("box_exit", C.c_int32), ("cap_particles", C.c_int64),
+                ("cap_stopped", C.c_int64), ("cap_grains", C.c_int32), ("cap_sites", C.c_int32),
+                ("cap_claim_bricks", C.c_int64), ("field_n", C.c_int32 * 3)]
+
+
+class ge_field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dT", C.c_double), ("dT0", C.c_double),
+                ("grad", C.c_double * 3), ("rate", C.c_double), ("n", C.c_int32 * 3),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+                ("data", C.c_void_p), ("data_on_device", C.c_int32), ("q", C.c_double),
+                ("U", C.c_double), ("alpha", C.c_double), ("x_start", C.c_double),
+                ("x_end", C.c_double), ("ys", C.c_double), ("zs", C.c_double),
+                ("r_min", C.c_double), ("dT_min", C.c_double)]
+
+
+class ge_step_stats(C.Structure):
+    _fields_ = [("n_active", C.c_int64), ("n_stopped", C.c_int64), ("n_grains", C.c_int64),
+                ("n_claim_bricks", C.c_int64), ("advanced", C.c_int64), ("exited", C.c_int64),
+                ("spawners", C.c_int64), ("children", C.c_int64), ("contained", C.c_int64),
+                ("nucleated", C.c_int64), ("max_step", C.c_double), ("t", C.c_double),
+                ("step", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ge_query_args(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3)]
+
+
+class ge_state_in(C.Structure):
+    _fields_ = [("n_grains", C.c_int32), ("centre", C.c_void_p), ("quat", C.c_void_p),
+                ("n_particles", C.c_int64), ("grain", C.c_void_p), ("site", C.c_void_p),
+                ("dir", C.c_void_p), ("s", C.c_void_p), ("state", C.c_void_p),
+                ("n_claims", C.c_int64), ("c_grain", C.c_void_p), ("c_site", C.c_void_p),
+                ("c_flags", C.c_void_p), ("n_sites", C.c_int32), ("site_state", C.c_void_p),
+                ("t", C.c_double), ("step", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libgrainenv.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no fallback path)")
+    lib = C.CDLL(path)
+    vp, P = C.c_void_p, C.POINTER
+    sig = {
+        "ge_workspace_size": ([P(ge_params), P(C.c_size_t)], C.c_int32),
+        "ge_validate_params": ([P(ge_params)], C.c_int32),
+        "ge_create": ([P(ge_params), vp, C.c_size_t, vp, P(vp)], C.c_int32),
+        "ge_destroy": ([vp], C.c_int32),
+        "ge_last_error": ([vp], C.c_char_p),
+        "ge_init_grains": ([vp, C.c_int32, vp, vp, vp, P(C.c_uint32)], C.c_int32),
+        "ge_set_thermal_field": ([vp, P(ge_field)], C.c_int32),
+        "ge_nucleate": ([vp, C.c_int32, vp, vp, vp], C.c_int32),
+        "ge_step": ([vp, C.c_double, C.c_int32, P(ge_step_stats)], C.c_int32),
+        "ge_query_envelope": ([vp, C.c_int32, P(ge_query_args), vp, C.c_size_t,
+                               P(C.c_size_t)], C.c_int32),
+        "ge_load_state": ([vp, P(ge_state_in)], C.c_int32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy",
+            "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_nucleate", "ge_step",
+            "ge_query_envelope", "ge_load_state")
+
+
+def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,
+                cap_particles=1 << 20, cap_stopped=1 << 20, cap_grains=1 << 12,
+                cap_sites=1 << 12, cap_claim_bricks=1 << 16, field_n=(0, 0, 0)) -> ge_params:
+    p = ge_params()
+    p.lo[:] = [float(v) for v in lo]
+    p.hi[:] = [float(v) for v in hi]
+    p.lambda0, p.h, p.rc = float(lambda0), float(h), float(rc)
+    p.a[:] = [float(v) for v in a]
+    p.b[:] = [float(v) for v in b]
+    p.theta = float(theta)
+    p.branching, p.box_exit = int(branching), int(box_exit)
+    p.cap_particles, p.cap_stopped = int(cap_particles), int(cap_stopped)
+    p.cap_grains, p.cap_sites = int(cap_grains), int(cap_sites)
+    p.cap_claim_bricks = int(cap_claim_bricks)
+    p.field_n[:] = [int(v) for v in field_n]
+    return p
+
+
+def params_from_workload(w, **caps) -> ge_params:
+    fn = tuple(w.field.n) if w.field.kind in (FIELD_GRID, FIELD_ROSENTHAL) else (0, 0, 0)
+    caps.setdefault("field_n", fn)
+    caps.setdefault("cap_sites", max(len(w.site_dTn), 1))
+    return make_params(w.lo, w.hi, w.lambda0, w.h, w.rc, w.a, w.b, w.theta, w.branching,
+                       w.box_exit, **caps)
+
+
+def workspace_size(p: ge_params) -> int:
+    lib = load_library()
+    n = C.c_size_t()
+    rc = lib.ge_workspace_size(C.byref(p), C.byref(n))
+    if rc != GE_OK:
+        raise GrainEnvError(rc, "invalid parameters")
+    return n.value
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """A grain-envelope simulation on one GPU (the C context plus its
+    workspace, a torch uint8 tensor)."""
+
+    def __init__(self, params: ge_params, device="cuda:0", stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = params
+        nbytes = workspace_size(params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        rc = self.lib.ge_create(C.byref(params), C.c_void_p(self.workspace.data_ptr()),
+                                nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if rc != GE_OK:
+            raise GrainEnvError(rc, "ge_create failed")
+        self.ctx = ctx
+        self.n_sites = 0
+
+    @classmethod
+    def from_workload(cls, w, device="cuda:0", init=True, **caps):
+        c = cls(params_from_workload(w, **caps), device=device)
+        c.set_thermal_field(w.field)
+        if init:
+            if len(w.grain_centre):
+                c.init_grains(w.grain_centre, w.grain_quat, w.grain_shell)
+            if len(w.site_dTn):
+                c.nucleate(w.site_xyz, w.site_dTn, w.site_quat)
+        return c
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ge_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != GE_OK:
+            msg = self.lib.ge_last_error(self.ctx)
+            raise GrainEnvError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # ------------------------------------------------------------ C ABI ---
+    def init_grains(self, centre, quat, shell_r):
+        centre = np.ascontiguousarray(centre, np.float64).reshape(-1, 3)
+        quat = np.ascontiguousarray(quat, np.float64).reshape(-1, 4)
+        shell = np.ascontiguousarray(shell_r, np.int32).reshape(-1)
+        first = C.c_uint32()
+        self._check(self.lib.ge_init_grains(self.ctx, len(shell), _ptr(centre), _ptr(quat),
+                                            _ptr(shell), C.byref(first)), "ge_init_grains")
+        return first.value
+
+    def set_thermal_field(self, f):
+        fs = ge_field()
+        fs.kind = f.kind
+        fs.dT, fs.dT0, fs.rate = f.dT, f.dT0, f.rate
+        fs.grad[:] = list(f.grad)
+        fs.n[:] = list(f.n)
+        fs.origin[:] = list(f.origin)
+        fs.spacing[:] = list(f.spacing)
+        keep = None
+        if f.kind == FIELD_GRID:
+            if hasattr(f.data, "data_ptr"):
+                keep = f.data.contiguous()
+                fs.data = keep.data_ptr()
+                fs.data_on_device = 1 if keep.is_cuda else 0
+            else:
+                keep = np.ascontiguousarray(f.data, np.float32)
+                fs.data = keep.ctypes.data
+                fs.data_on_device = 0
+        for k in ("q", "U", "alpha", "x_start", "x_end", "ys", "zs", "r_min", "dT_min"):
+            setattr(fs, k, float(getattr(f, k)))
+        self._check(self.lib.ge_set_thermal_field(self.ctx, C.byref(fs)), "ge_set_thermal_field")
+        del keep
+
+    def nucleate(self, xyz, dT_nuc, quat):
+        xyz = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+        dT = np.ascontiguousarray(dT_nuc, np.float64).reshape(-1)
+        quat = np.ascontiguousarray(quat, np.float64).reshape(-1, 4)
+        self._check(self.lib.ge_nucleate(self.ctx, len(dT), _ptr(xyz), _ptr(dT), _ptr(quat)),
+                    "ge_nucleate")
+        self.n_sites += len(dT)
+
+    def step(self, dt, n_steps=1, stats=True):
+        st = ge_step_stats()
+        rc = self.lib.ge_step(self.ctx, float(dt), int(n_steps), C.byref(st) if stats else None)
+        self._check(rc, "ge_step")
+        return st.as_dict() if stats else None
+
+    def query_envelope(self, kind, out=None, args: Optional[ge_query_args] = None):
+        """Raw query: returns the needed byte count, fills `out` (numpy array
+        or torch tensor) when given."""
+        need = C.c_size_t()
+        if out is None:
+            self._check(self.lib.ge_query_envelope(self.ctx, kind, C.byref(args) if args else None,
+                                                   None, 0, C.byref(need)), "ge_query_envelope")
+            return need.value
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else out.ctypes.data
+        nbytes = out.numel() * out.element_size() if hasattr(out, "numel") else out.nbytes
+        self._check(self.lib.ge_query_envelope(self.ctx, kind, C.byref(args) if args else None,
+                                               C.c_void_p(ptr), nbytes, C.byref(need)),
+                    "ge_query_envelope")
+        return need.value
+
+    def load_state(self, grain_centre, grain_quat, parts, claims, site_state, t, step):
+        gc = np.ascontiguousarray(grain_centre, np.float64).reshape(-1, 3)
+        gq = np.ascontiguousarray(grain_quat, np.float64).reshape(-1, 4)
+        pg = np.ascontiguousarray(parts["grain"], np.int32)
+        ps = np.ascontiguousarray(parts["site"], np.int32).reshape(-1, 3)
+        pdir = np.ascontiguousarray(parts["dir"], np.int32)
+        pss = np.ascontiguousarray(parts["s"], np.float32)
+        pst = np.ascontiguousarray(parts["state"], np.int32)
+        cg = np.ascontiguousarray(claims["grain"], np.int32)
+        cs = np.ascontiguousarray(claims["site"], np.int32).reshape(-1, 3)
+        cf = np.ascontiguousarray(claims["flags"], np.uint8)
+        ss = np.ascontiguousarray(site_state, np.int32)
+        st = ge_state_in()
+        st.n_grains = len(gc)
+        st.centre, st.quat = _ptr(gc), _ptr(gq)
+        st.n_particles = len(pg)
+        st.grain, st.site, st.dir, st.s, st.state = _ptr(pg), _ptr(ps), _ptr(pdir), _ptr(pss), _ptr(pst)
+        st.n_claims = len(cg)
+        st.c_grain, st.c_site, st.c_flags = _ptr(cg), _ptr(cs), _ptr(cf)
+        st.n_sites = len(ss)
+        st.site_state = _ptr(ss)
+        st.t, st.step = float(t), int(step)
+        self._check(self.lib.ge_load_state(self.ctx, C.byref(st)), "ge_load_state")
+
+    # ---------------------------------------------------------- helpers ---
+    def counts(self):
+        st = ge_step_stats()
+        buf = np.zeros(C.sizeof(ge_step_stats), np.uint8)
+        self.query_envelope(QUERY_COUNTS, buf)
+        C.memmove(C.addressof(st), buf.ctypes.data, C.sizeof(st))
+        return st.as_dict()
+
+    def particles(self) -> np.ndarray:
+        need = self.query_envelope(QUERY_PARTICLES)
+        out = np.zeros(need // PARTICLE_DTYPE.itemsize, PARTICLE_DTYPE)
+        if need:
+            self.query_envelope(QUERY_PARTICLES, out)
+        return out
+
+    def claims(self) -> np.ndarray:
+        need = self.query_envelope(QUERY_CLAIMS)
+        out = np.zeros(need // CLAIM_DTYPE.itemsize, CLAIM_DTYPE)
+        if need:
+            self.query_envelope(QUERY_CLAIMS, out)
+        return out
+
+    def site_states(self) -> np.ndarray:
+        out = np.zeros(self.n_sites, np.int32)
+        if self.n_sites:
+            self.query_envelope(QUERY_SITES, out)
+        return out
+
+    def grains(self) -> np.ndarray:
+        need = self.query_envelope(QUERY_GRAINS)
+        out = np.zeros(need // 4, np.float32)
+        if need:
+            self.query_envelope(QUERY_GRAINS, out)
+        return out.reshape(-1, 24)
+
+    def grain_map(self, n, origin, spacing, device_out=False):
+        a = ge_query_args()
+        a.n[:] = [int(v) for v in n]
+        a.origin[:] = [float(v) for v in origin]
+        a.spacing[:] = [float(v) for v in spacing]
+        if device_out:
+            out = self.torch.zeros(int(np.prod(n)), dtype=self.torch.int32, device=self.device)
+        else:
+            out = np.zeros(int(np.prod(n)), np.uint32)
+        self.query_envelope(QUERY_GRAIN_MAP, out, a)
+        return out.reshape(int(n[2]), int(n[1]), int(n[0]))

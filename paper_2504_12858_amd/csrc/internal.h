@@ -1,0 +1,146 @@
+// Internal layout shared by the device kernels and the host runtime of
+// libgrainenv.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ge {
+
+// ---------------------------------------------------------------- layout --
+// Particle record, 16 bytes, stored as uint4:
+//   x: travel s since the departure site (float bits)
+//   y: grain << 3 | direction (0..5 = +x,-x,+y,-y,+z,-z of the crystal frame)
+//   z: site x (int16, low half) | site y (int16, high half)
+//   w: site z (int16, low half) | flags (high half)
+// Flags: bits 0-1 state, bit 2 spawner this step, bit 3 kept (active,
+// forwarded), bits 8-13 child-direction mask.
+enum : uint32_t { ST_ACTIVE = 0, ST_STOPPED = 1, ST_RETIRED = 2 };
+enum : uint32_t { FL_SPAWN = 4, FL_KEEP = 8 };
+
+// Site states.
+enum : uint32_t { SITE_DORMANT = 0, SITE_FIRED = 1, SITE_ENGULFED = 2 };
+
+// Error bits of the sticky error word.
+enum : uint32_t { ERR_CAPACITY = 1, ERR_NUMERIC = 2, ERR_CFL = 4 };
+
+// Grain table row: 24 floats.
+//   [0..2] centre, [3] spare (site tables: nucleation undercooling),
+//   [4..12] R row-major (crystal -> world), [13..21] lambda0 * R, [22..23] spare.
+constexpr int GT_STRIDE = 24;
+
+// Cells per brick edge (bricks of 8^3 cells) and the largest brick the
+// in-LDS cell sort takes.
+constexpr int BRICK = 8;
+constexpr int CS_CAP = 2048;
+
+// Claim hash: 8^3 lattice sites per slot, three 512-bit masks per slot
+// (claimed as target, reached, reached during the current step).
+constexpr uint64_t CLAIM_EMPTY = ~0ull;
+constexpr uint32_t NIL = 0xFFFFFFFFu;
+
+// Field kinds.
+enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3 };
+
+struct Counters {
+  uint32_t n_active;   // records in A (sorted region + nucleated tail)
+  uint32_t n_spawn;    // spawner list length this step
+  uint32_t n_out;      // records after scatter = sorted region of A
+  uint32_t n_occ;      // occupied bricks this step
+  uint32_t n_stopped;  // stopped store length
+  uint32_t n_newstop;  // particles stopped by containment this step
+  uint32_t n_grains;
+  uint32_t claim_used; // occupied claim slots
+  uint32_t err;        // sticky error bits
+  uint32_t n_cand;     // nucleation candidates this step
+  uint32_t max_step;   // float bits of max v dt (non-negative floats order as uints)
+  uint32_t n_fired;    // sites fired this step
+  uint32_t n_live;     // active particles (A also holds records stopped at the end of a step)
+  uint32_t pad0;
+  unsigned long long advanced, exited, spawners, children, contained, nucleated;
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+  // geometry
+  float lo[3], hi[3];
+  float inv_h;
+  int32_t n[3];    // cells per axis
+  int32_t nb[3];   // bricks per axis
+  uint32_t n_bricks;
+  float lambda0, rc2, rc_half;
+  float ka[2], kb[2];
+  int32_t kin_poly;
+  float theta;
+  int32_t branching, box_exit;
+  // field
+  int32_t fkind;
+  float fdT, fgrad[3];
+  int32_t fn[3];
+  float fo[3], finv[3];
+  float* fgrid;
+  // grains
+  float* gtab;     // [cap_grains][GT_STRIDE]
+  int32_t* gbox;   // [cap_grains][6] lattice bbox of claims: lo xyz, hi xyz
+  uint32_t cap_grains;
+  // active store (ping-pong) and per-step lists
+  uint4* A;
+  uint4* B;
+  uint32_t cap_p;
+  uint32_t* spawn;     // [cap_p]
+  uint32_t* newstop;   // [cap_p]
+  // stopped store with linked cell lists
+  uint4* S;
+  uint32_t* snext;
+  uint32_t cap_s;
+  uint32_t* shead;     // [cells]
+  uint2* sbsum;        // [bricks] stopped grain min / max
+  // bricks and cells
+  uint32_t* bcnt;      // [bricks]
+  uint4* binfo;        // [bricks] start, count, grain min, grain max
+  uint32_t* occ;       // [bricks]
+  unsigned long long* ctab;  // [cells] start | (count | epoch << 8) << 32
+  uint64_t* scan_tmp;  // block partial sums of the brick scan
+  // claims
+  unsigned long long* ckeys;   // [slots]
+  unsigned long long* cbits;   // [slots][3][8]: claimed, reached, now
+  uint64_t cmask;              // slots - 1
+  uint32_t claim_limit;        // occupancy limit of the hash
+  // sites
+  float* stab;         // [cap_sites][GT_STRIDE], [3] = nucleation undercooling
+  uint32_t* sstate;    // [cap_sites]
+  uint32_t* cand;      // [cap_sites]
+  uint32_t n_sites;
+  // counters
+  Counters* cnt;
+};
+
+// -------------------------------------------------- host-side launchers --
+void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s);
+void launch_branch(const Dev& d, hipStream_t s);
+void launch_scan(const Dev& d, hipStream_t s);
+void launch_scatter(const Dev& d, hipStream_t s);
+void launch_cellsort(const Dev& d, uint32_t epoch, hipStream_t s);
+void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s);
+void launch_stoplink(const Dev& d, hipStream_t s);
+void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s);
+void launch_finish(const Dev& d, hipStream_t s);
+void launch_reset_stats(const Dev& d, hipStream_t s);
+void launch_resample(const Dev& d, double dT0, const double grad[3], double rate, double q,
+                     double U, double alpha, double x_start, double x_end, double ys, double zs,
+                     double r_min, double dT_min, double ox, double oy, double oz, double sx,
+                     double sy, double sz, double t, hipStream_t s);
+void launch_init_workspace(const Dev& d, uint64_t n_cells, hipStream_t s);
+void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s);
+void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);
+void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
+                       const uint8_t* flags, uint32_t n, hipStream_t s);
+void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
+                             hipStream_t s);
+void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
+                          hipStream_t s);
+void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
+                      const float spacing[3], uint32_t* out, hipStream_t s);
+void launch_clear_ctab(const Dev& d, uint64_t n_cells, hipStream_t s);
+
+}  // namespace ge

@@ -1,0 +1,1326 @@
+// Device kernels of the grain-envelope step for gfx950 (wave64).
+//
+// One step (Sec. 2.1.2 growth and branching, Sec. 2.3 cell partitioning and
+// collision detection, Sec. 2.1.1 nucleation) runs as:
+//   k_advance   undercooling at each active particle, kinetic law Eq. (2),
+//               advance along R e_d, box exit, spawner detection, brick counts
+//   k_branch    outer directions of each spawner against the grain's claims,
+//               same-step competitors resolved by lowest direction
+//   k_scan_*    exclusive scan of brick counts -> brick starts, occupied list
+//   k_scatter   records -> brick-ordered store (wave-aggregated ranks)
+//   k_cellsort  per occupied brick, an LDS counting sort by cell with an
+//               identity tie-break; writes the dense cell table
+//   k_contain   27-cell stencil test against other grains' particles
+//   k_stoplink  moves newly stopped particles to the stopped store
+//   k_nuc_test / k_nuc_fire   nucleation of liquid sites past threshold
+//   k_finish    counters for the next step
+//
+// Particle positions are never stored: every kernel recomputes them from the
+// record (grain, departure site, direction, travel) with the same function, so
+// binning, containment and export see identical FP32 values.
+#include "internal.h"
+
+#include <math.h>
+
+namespace ge {
+
+constexpr int TPB = 256;
+constexpr int STREAM_GRID = 2048;  // 8 blocks per CU on 256 CUs
+
+enum : int { CB_CLAIMED = 0, CB_REACHED = 8, CB_NOW = 16 };
+enum : uint32_t { M_CLAIMED = 1, M_REACHED = 2, M_NOW = 4 };
+
+// ------------------------------------------------------------- records ----
+__device__ __forceinline__ uint32_t rec_grain(uint4 r) { return r.y >> 3; }
+__device__ __forceinline__ int rec_dir(uint4 r) { return (int)(r.y & 7u); }
+__device__ __forceinline__ float rec_s(uint4 r) { return __uint_as_float(r.x); }
+__device__ __forceinline__ int rec_sx(uint4 r) { return (int)(int16_t)(r.z & 0xFFFFu); }
+__device__ __forceinline__ int rec_sy(uint4 r) { return (int)(int16_t)(r.z >> 16); }
+__device__ __forceinline__ int rec_sz(uint4 r) { return (int)(int16_t)(r.w & 0xFFFFu); }
+__device__ __forceinline__ uint32_t rec_fl(uint4 r) { return r.w >> 16; }
+__device__ __forceinline__ uint4 make_rec(float s, uint32_t g, int d, int sx, int sy, int sz,
+                                          uint32_t fl) {
+  return make_uint4(__float_as_uint(s), (g << 3) | (uint32_t)d,
+                    ((uint32_t)(uint16_t)sx) | ((uint32_t)(uint16_t)sy << 16),
+                    ((uint32_t)(uint16_t)sz) | (fl << 16));
+}
+__device__ __forceinline__ uint4 with_fl(uint4 r, uint32_t fl) {
+  r.w = (r.w & 0xFFFFu) | (fl << 16);
+  return r;
+}
+
+struct P3 {
+  float x, y, z;
+};
+
+// World position of departure site (sx, sy, sz) plus travel s along d:
+// x = c + (lambda0 R) site + s R e_d, with explicit FMAs (no contraction
+// freedom is left to the compiler, so every kernel gets the same bits).
+__device__ __forceinline__ P3 lattice_pos(const float* __restrict__ G, int sx, int sy, int sz,
+                                          int d, float s) {
+  const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+  const int a = d >> 1;
+  const float ss = (d & 1) ? -s : s;
+  P3 p;
+  p.x = fmaf(ss, G[4 + a], fmaf(G[13], fx, fmaf(G[14], fy, fmaf(G[15], fz, G[0]))));
+  p.y = fmaf(ss, G[7 + a], fmaf(G[16], fx, fmaf(G[17], fy, fmaf(G[18], fz, G[1]))));
+  p.z = fmaf(ss, G[10 + a], fmaf(G[19], fx, fmaf(G[20], fy, fmaf(G[21], fz, G[2]))));
+  return p;
+}
+
+__device__ __forceinline__ P3 rec_pos(const Dev& D, uint4 r) {
+  return lattice_pos(D.gtab + (size_t)rec_grain(r) * GT_STRIDE, rec_sx(r), rec_sy(r), rec_sz(r),
+                     rec_dir(r), rec_s(r));
+}
+
+// ---------------------------------------------------------------- cells ---
+// Single-rounded FP32 binning: floor((x - lo) * inv_h), clamped to [0, n-1].
+__device__ __forceinline__ int cell_axis(float x, float lo, float inv_h, int n) {
+  float u = (x - lo) * inv_h;
+  float f = floorf(u);
+  f = fmaxf(f, 0.0f);
+  f = fminf(f, (float)(n - 1));
+  return (int)f;
+}
+
+struct C3 {
+  int x, y, z;
+};
+
+__device__ __forceinline__ C3 cell_of(const Dev& D, P3 p) {
+  C3 c;
+  c.x = cell_axis(p.x, D.lo[0], D.inv_h, D.n[0]);
+  c.y = cell_axis(p.y, D.lo[1], D.inv_h, D.n[1]);
+  c.z = cell_axis(p.z, D.lo[2], D.inv_h, D.n[2]);
+  return c;
+}
+
+__device__ __forceinline__ uint64_t cell_index(const Dev& D, int cx, int cy, int cz) {
+  return ((uint64_t)cz * (uint64_t)D.n[1] + (uint64_t)cy) * (uint64_t)D.n[0] + (uint64_t)cx;
+}
+
+__device__ __forceinline__ uint32_t brick_index(const Dev& D, int cx, int cy, int cz) {
+  return ((uint32_t)(cz >> 3) * (uint32_t)D.nb[1] + (uint32_t)(cy >> 3)) * (uint32_t)D.nb[0] +
+         (uint32_t)(cx >> 3);
+}
+
+__device__ __forceinline__ uint32_t brick_of(const Dev& D, P3 p) {
+  C3 c = cell_of(D, p);
+  return brick_index(D, c.x, c.y, c.z);
+}
+
+__device__ __forceinline__ float dist2(P3 a, P3 b) {
+  float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// ---------------------------------------------------------------- field ---
+__device__ __forceinline__ float trilinear(const Dev& D, P3 p) {
+  float u[3] = {(p.x - D.fo[0]) * D.finv[0], (p.y - D.fo[1]) * D.finv[1],
+                (p.z - D.fo[2]) * D.finv[2]};
+  int i0[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float fl = floorf(u[a]);
+    fl = fmaxf(fl, 0.0f);
+    fl = fminf(fl, (float)(D.fn[a] - 2));
+    i0[a] = (int)fl;
+    float w = u[a] - fl;
+    w = fminf(fmaxf(w, 0.0f), 1.0f);
+    f[a] = w;
+  }
+  const size_t sy = (size_t)D.fn[0], sz = (size_t)D.fn[0] * (size_t)D.fn[1];
+  const size_t b = (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
+  const float* __restrict__ g = D.fgrid;
+  float c000 = g[b], c100 = g[b + 1], c010 = g[b + sy], c110 = g[b + sy + 1];
+  float c001 = g[b + sz], c101 = g[b + sz + 1], c011 = g[b + sz + sy], c111 = g[b + sz + sy + 1];
+  float c00 = fmaf(f[0], c100 - c000, c000);
+  float c10 = fmaf(f[0], c110 - c010, c010);
+  float c01 = fmaf(f[0], c101 - c001, c001);
+  float c11 = fmaf(f[0], c111 - c011, c011);
+  float c0 = fmaf(f[1], c10 - c00, c00);
+  float c1 = fmaf(f[1], c11 - c01, c01);
+  return fmaf(f[2], c1 - c0, c0);
+}
+
+// Undercooling at p (without theta).  lin_c = dT0 + rate t for LINEAR.
+__device__ __forceinline__ float field_at(const Dev& D, P3 p, float lin_c) {
+  if (D.fkind == F_UNIFORM) return D.fdT;
+  if (D.fkind == F_LINEAR)
+    return ((lin_c + D.fgrad[0] * p.x) + D.fgrad[1] * p.y) + D.fgrad[2] * p.z;
+  return trilinear(D, p);
+}
+
+// Kinetic law, Eq. (2): v = a0 dT^b0 + a1 dT^b1 for dT > 0, else 0.
+__device__ __forceinline__ float velocity(const Dev& D, float dT) {
+  if (!(dT > 0.0f)) return 0.0f;
+  if (D.kin_poly) return dT * dT * fmaf(D.ka[1], dT, D.ka[0]);
+  float l = log2f(dT);
+  return D.ka[0] * exp2f(D.kb[0] * l) + D.ka[1] * exp2f(D.kb[1] * l);
+}
+
+// --------------------------------------------------------------- claims ---
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xbf58476d1ce4e5b9ull;
+  z ^= z >> 27;
+  z *= 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return z;
+}
+
+__device__ __forceinline__ uint64_t claim_key(uint32_t g, int sx, int sy, int sz) {
+  const uint64_t bx = (uint64_t)((sx >> 3) + 2048) & 0xFFFull;
+  const uint64_t by = (uint64_t)((sy >> 3) + 2048) & 0xFFFull;
+  const uint64_t bz = (uint64_t)((sz >> 3) + 2048) & 0xFFFull;
+  return ((uint64_t)g << 36) | (bx << 24) | (by << 12) | bz;
+}
+
+__device__ __forceinline__ uint32_t site_bit(int sx, int sy, int sz) {
+  return (uint32_t)((sx & 7) | ((sy & 7) << 3) | ((sz & 7) << 6));
+}
+
+constexpr uint32_t MAX_PROBE = 4096;
+
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Read-only probe: slot or -1.
+__device__ int64_t claim_find(const Dev& D, uint64_t key) {
+  uint64_t h = mix64(key) & D.cmask;
+  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
+    uint64_t idx = (h + p) & D.cmask;
+    uint64_t k = load_relaxed(&D.ckeys[idx]);
+    if (k == key) return (int64_t)idx;
+    if (k == CLAIM_EMPTY) return -1;
+  }
+  return -1;
+}
+
+// Find or insert: slot or -1 (capacity error raised).
+__device__ int64_t claim_get(const Dev& D, uint64_t key) {
+  uint64_t h = mix64(key) & D.cmask;
+  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
+    uint64_t idx = (h + p) & D.cmask;
+    unsigned long long k = load_relaxed(&D.ckeys[idx]);
+    if (k == key) return (int64_t)idx;
+    if (k == CLAIM_EMPTY) {
+      if (__hip_atomic_load(&D.cnt->claim_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+          D.claim_limit) {
+        atomicOr(&D.cnt->err, ERR_CAPACITY);
+        return -1;
+      }
+      unsigned long long prev = atomicCAS(&D.ckeys[idx], CLAIM_EMPTY, (unsigned long long)key);
+      if (prev == CLAIM_EMPTY) {
+        atomicAdd(&D.cnt->claim_used, 1u);
+        return (int64_t)idx;
+      }
+      if (prev == key) return (int64_t)idx;
+    }
+  }
+  atomicOr(&D.cnt->err, ERR_CAPACITY);
+  return -1;
+}
+
+__device__ __forceinline__ void claim_or(const Dev& D, uint32_t g, int sx, int sy, int sz,
+                                         uint32_t which) {
+  int64_t slot = claim_get(D, claim_key(g, sx, sy, sz));
+  if (slot < 0) return;
+  const uint32_t b = site_bit(sx, sy, sz);
+  const unsigned long long m = 1ull << (b & 63);
+  unsigned long long* w = D.cbits + (size_t)slot * 24 + (b >> 6);
+  if (which & M_CLAIMED) atomicOr(w + CB_CLAIMED, m);
+  if (which & M_REACHED) atomicOr(w + CB_REACHED, m);
+  if (which & M_NOW) atomicOr(w + CB_NOW, m);
+}
+
+__device__ __forceinline__ void claim_clear_now(const Dev& D, uint32_t g, int sx, int sy, int sz) {
+  int64_t slot = claim_find(D, claim_key(g, sx, sy, sz));
+  if (slot < 0) return;
+  const uint32_t b = site_bit(sx, sy, sz);
+  atomicAnd(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), ~(1ull << (b & 63)));
+}
+
+// True if the site is in any of the masks selected by `which`.
+__device__ __forceinline__ bool claim_test(const Dev& D, uint32_t g, int sx, int sy, int sz,
+                                           uint32_t which) {
+  int64_t slot = claim_find(D, claim_key(g, sx, sy, sz));
+  if (slot < 0) return false;
+  const uint32_t b = site_bit(sx, sy, sz);
+  const unsigned long long m = 1ull << (b & 63);
+  const unsigned long long* w = D.cbits + (size_t)slot * 24 + (b >> 6);
+  unsigned long long v = 0;
+  if (which & M_CLAIMED) v |= load_relaxed(w + CB_CLAIMED);
+  if (which & M_REACHED) v |= load_relaxed(w + CB_REACHED);
+  if (which & M_NOW) v |= load_relaxed(w + CB_NOW);
+  return (v & m) != 0;
+}
+
+__device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int sy, int sz) {
+  int32_t* b = D.gbox + (size_t)g * 6;
+  atomicMin(b + 0, sx);
+  atomicMin(b + 1, sy);
+  atomicMin(b + 2, sz);
+  atomicMax(b + 3, sx);
+  atomicMax(b + 4, sy);
+  atomicMax(b + 5, sz);
+}
+
+// Rounded lattice position of world point y in grain G (crystal frame).
+__device__ __forceinline__ void lattice_round(const float* __restrict__ G, float inv_lambda, P3 y,
+                                              int out[3]) {
+  const float dx = y.x - G[0], dy = y.y - G[1], dz = y.z - G[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float l = fmaf(G[10 + k], dz, fmaf(G[7 + k], dy, G[4 + k] * dx));
+    out[k] = (int)rintf(l * inv_lambda);
+  }
+}
+
+// ----------------------------------------------------------- wave tools ---
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Appends for lanes with pred; one atomic per wave.  Returns the slot or NIL.
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
+  const int lane = lane_id();
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return NIL;
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  return pred ? base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)) : NIL;
+}
+
+// Groups runs of equal keys in consecutive lanes.
+struct Run {
+  int head, off, len;
+};
+__device__ __forceinline__ Run wave_run(uint32_t key) {
+  const int lane = lane_id();
+  const uint32_t prev = __shfl_up(key, 1u);
+  const bool head = (lane == 0) || (prev != key);
+  const unsigned long long H = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const unsigned long long below = H & upto;
+  const unsigned long long above = H & ~upto;
+  Run r;
+  r.head = 63 - __clzll((long long)below);
+  const int next = above ? (__ffsll((long long)above) - 1) : 64;
+  r.len = next - r.head;
+  r.off = lane - r.head;
+  return r;
+}
+
+// Contiguous chunk of [0, n) per block; blocks on one XCD (round-robin
+// dispatch: block b runs on XCD b % 8) get neighbouring chunks so that they
+// share that XCD's L2.
+struct Chunk {
+  uint32_t begin, end;
+};
+__device__ __forceinline__ uint32_t logical_block() {
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  return ((G & 7u) == 0u) ? (b & 7u) * (G >> 3) + (b >> 3) : b;
+}
+__device__ __forceinline__ Chunk chunk_of(uint32_t n, uint32_t granule) {
+  const uint32_t G = gridDim.x;
+  uint32_t per = (n + G - 1u) / G;
+  per = (per + granule - 1u) / granule * granule;
+  const uint64_t b = (uint64_t)logical_block() * per;
+  Chunk c;
+  c.begin = (uint32_t)(b < n ? b : n);
+  const uint64_t e = b + per;
+  c.end = (uint32_t)(e < n ? e : n);
+  return c;
+}
+
+__device__ __forceinline__ bool dead(const Dev& D) {
+  return (__hip_atomic_load(&D.cnt->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+          ERR_CAPACITY) != 0u;
+}
+
+// Block-wide exclusive scan of one uint32 per thread (TPB threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+  const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(incl, (unsigned)o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; ++w) {
+    uint32_t s = wsum[w];
+    if (w < wid) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - v;
+}
+
+__device__ __forceinline__ unsigned long long block_excl_scan64(unsigned long long v,
+                                                                unsigned long long* wsum,
+                                                                unsigned long long& total) {
+  const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
+  unsigned long long incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    unsigned long long y = __shfl_up(incl, (unsigned)o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  unsigned long long off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; ++w) {
+    unsigned long long s = wsum[w];
+    if (w < wid) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - v;
+}
+
+// ------------------------------------------------------- stopped store ----
+// Appends record r (state STOPPED) at slot j and links it into the cell list
+// of stopped particles.  Callers run in kernels that never read that list.
+__device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r) {
+  if (j == NIL) return;
+  if (j >= D.cap_s) {
+    atomicOr(&D.cnt->err, ERR_CAPACITY);
+    return;
+  }
+  D.S[j] = r;
+  P3 p = rec_pos(D, r);
+  C3 c = cell_of(D, p);
+  const uint64_t ci = cell_index(D, c.x, c.y, c.z);
+  const uint32_t old = atomicExch(&D.shead[ci], j);
+  D.snext[j] = old;
+  const uint32_t b = brick_index(D, c.x, c.y, c.z);
+  const uint32_t g = rec_grain(r);
+  atomicMin(&D.sbsum[b].x, g);
+  atomicMax(&D.sbsum[b].y, g);
+}
+
+// ==================================================================== step
+__global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
+  if (dead(D)) return;
+  const uint32_t n = D.cnt->n_active;
+  const Chunk ch = chunk_of(n, TPB);
+  float max_step = 0.0f;
+  uint32_t nadv = 0, nexit = 0;
+  uint32_t bad = 0;
+  for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
+    const uint32_t i = base + threadIdx.x;
+    const bool valid = i < ch.end;
+    uint4 r = valid ? D.A[i] : make_uint4(0u, 0u, 0u, 0u);
+    const bool act = valid && ((rec_fl(r) & 3u) == ST_ACTIVE);
+    uint32_t bkey = NIL;
+    bool spawn = false, exited = false;
+    if (act) {
+      const uint32_t g = rec_grain(r);
+      const int d = rec_dir(r);
+      const int sx = rec_sx(r), sy = rec_sy(r), sz = rec_sz(r);
+      const float s = rec_s(r);
+      const float* G = D.gtab + (size_t)g * GT_STRIDE;
+      const P3 x = lattice_pos(G, sx, sy, sz, d, s);
+      const float dT = field_at(D, x, lin_c) - D.theta;
+      float delta = velocity(D, dT) * dt;
+      if (!isfinite(delta)) {
+        bad |= ERR_NUMERIC;
+        delta = 0.0f;
+      }
+      if (delta > D.rc_half) bad |= ERR_CFL;
+      max_step = fmaxf(max_step, delta);
+      const float s2 = s + delta;
+      const P3 x2 = lattice_pos(G, sx, sy, sz, d, s2);
+      nadv += 1;
+      const bool inside = x2.x >= D.lo[0] && x2.x < D.hi[0] && x2.y >= D.lo[1] &&
+                          x2.y < D.hi[1] && x2.z >= D.lo[2] && x2.z < D.hi[2];
+      uint32_t fl;
+      if (D.box_exit && !inside) {
+        exited = true;
+        fl = ST_STOPPED;
+        nexit += 1;
+      } else if (D.branching && s2 >= D.lambda0) {
+        spawn = true;
+        fl = ST_ACTIVE | FL_SPAWN;
+        if (s2 >= 2.0f * D.lambda0) bad |= ERR_CFL;
+      } else {
+        fl = ST_ACTIVE | FL_KEEP;
+        bkey = brick_of(D, x2);
+      }
+      r = make_rec(s2, g, d, sx, sy, sz, fl);
+      D.A[i] = r;
+      if (spawn) {
+        int S[3] = {sx, sy, sz};
+        S[d >> 1] += (d & 1) ? -1 : 1;
+        claim_or(D, g, S[0], S[1], S[2], M_NOW);
+      }
+    }
+    // Brick counts of kept particles, one atomic per run of equal bricks.
+    const Run run = wave_run(bkey);
+    if (bkey != NIL && run.off == 0) atomicAdd(&D.bcnt[bkey], (uint32_t)run.len);
+    const uint32_t sp = wave_append(spawn, &D.cnt->n_spawn);
+    if (spawn && sp < D.cap_p) D.spawn[sp] = i;
+    const uint32_t sj = wave_append(exited, &D.cnt->n_stopped);
+    if (exited) stopped_put(D, sj, r);
+  }
+  // Block reductions of the counters.
+  __shared__ uint32_t s_adv, s_exit, s_bad, s_max;
+  if (threadIdx.x == 0) {
+    s_adv = 0;
+    s_exit = 0;
+    s_bad = 0;
+    s_max = 0;
+  }
+  __syncthreads();
+  if (nadv) atomicAdd(&s_adv, nadv);
+  if (nexit) atomicAdd(&s_exit, nexit);
+  if (bad) atomicOr(&s_bad, bad);
+  if (max_step > 0.0f) atomicMax(&s_max, __float_as_uint(max_step));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_adv) atomicAdd(&D.cnt->advanced, (unsigned long long)s_adv);
+    if (s_exit) atomicAdd(&D.cnt->exited, (unsigned long long)s_exit);
+    if (s_bad) atomicOr(&D.cnt->err, s_bad);
+    if (s_max) atomicMax(&D.cnt->max_step, s_max);
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_branch(Dev D) {
+  if (dead(D)) return;
+  const uint32_t n = D.cnt->n_spawn;
+  const uint32_t nn = n < D.cap_p ? n : D.cap_p;
+  if (n > D.cap_p && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&D.cnt->err, ERR_CAPACITY);
+  uint32_t nsp = 0, nch = 0;
+  for (uint32_t k = blockIdx.x * TPB + threadIdx.x; k < nn; k += gridDim.x * TPB) {
+    const uint32_t i = D.spawn[k];
+    uint4 r = D.A[i];
+    const uint32_t g = rec_grain(r);
+    const int d = rec_dir(r);
+    const float s2 = rec_s(r);
+    int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
+    S[d >> 1] += (d & 1) ? -1 : 1;
+    uint32_t mask = 0;
+    for (int dd = 0; dd < 6; ++dd) {
+      const int a = dd >> 1;
+      const int sg = (dd & 1) ? -1 : 1;
+      if (sg * S[a] < 0) continue;  // octant rule: only outer directions
+      int T[3] = {S[0], S[1], S[2]};
+      T[a] += sg;
+      if (claim_test(D, g, T[0], T[1], T[2], M_CLAIMED | M_REACHED | M_NOW)) continue;
+      bool lose = false;
+      for (int d2 = 0; d2 < dd && !lose; ++d2) {
+        const int a2 = d2 >> 1;
+        const int sg2 = (d2 & 1) ? -1 : 1;
+        int S2[3] = {T[0], T[1], T[2]};
+        S2[a2] -= sg2;
+        if (sg2 * S2[a2] < 0) continue;
+        if (claim_test(D, g, S2[0], S2[1], S2[2], M_NOW)) lose = true;
+      }
+      if (!lose) mask |= 1u << dd;
+    }
+    const float* G = D.gtab + (size_t)g * GT_STRIDE;
+    if (mask == 0u) {
+      r = with_fl(r, ST_STOPPED | FL_SPAWN);
+      D.A[i] = r;
+      const uint32_t j = atomicAdd(&D.cnt->n_stopped, 1u);
+      stopped_put(D, j, with_fl(r, ST_STOPPED));
+    } else {
+      D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
+      const float sc = s2 - D.lambda0;
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!(mask & (1u << dd))) continue;
+        const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
+        atomicAdd(&D.bcnt[brick_of(D, xc)], 1u);
+        int T[3] = {S[0], S[1], S[2]};
+        T[dd >> 1] += (dd & 1) ? -1 : 1;
+        claim_or(D, g, T[0], T[1], T[2], M_CLAIMED);
+        bbox_add(D, g, T[0], T[1], T[2]);
+        nch += 1;
+      }
+    }
+    claim_or(D, g, S[0], S[1], S[2], M_REACHED);
+    bbox_add(D, g, S[0], S[1], S[2]);
+    nsp += 1;
+  }
+  __shared__ uint32_t s_sp, s_ch;
+  if (threadIdx.x == 0) {
+    s_sp = 0;
+    s_ch = 0;
+  }
+  __syncthreads();
+  if (nsp) atomicAdd(&s_sp, nsp);
+  if (nch) atomicAdd(&s_ch, nch);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_sp) atomicAdd(&D.cnt->spawners, (unsigned long long)s_sp);
+    if (s_ch) atomicAdd(&D.cnt->children, (unsigned long long)s_ch);
+  }
+}
+
+// ----------------------------------------------------------- brick scan ---
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+
+__global__ __launch_bounds__(TPB) void k_scan_reduce(Dev D) {
+  if (dead(D)) return;
+  __shared__ unsigned long long wsum[TPB / 64];
+  const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
+  unsigned long long v = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+    if (b < D.n_bricks) {
+      const uint32_t c = D.bcnt[b];
+      v += (unsigned long long)c | ((unsigned long long)(c > 0u) << 32);
+    }
+  }
+  unsigned long long total;
+  block_excl_scan64(v, wsum, total);
+  if (threadIdx.x == 0) D.scan_tmp[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_top(Dev D, uint32_t ntiles) {
+  if (dead(D)) return;
+  __shared__ unsigned long long wsum[TPB / 64];
+  unsigned long long carry = 0;
+  for (uint32_t base = 0; base < ntiles; base += TPB) {
+    const uint32_t t = base + threadIdx.x;
+    const unsigned long long v = t < ntiles ? D.scan_tmp[t] : 0ull;
+    unsigned long long total;
+    const unsigned long long ex = block_excl_scan64(v, wsum, total);
+    if (t < ntiles) D.scan_tmp[t] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t n_out = (uint32_t)(carry & 0xFFFFFFFFull);
+    D.cnt->n_out = n_out;
+    D.cnt->n_occ = (uint32_t)(carry >> 32);
+    if (n_out > D.cap_p) atomicOr(&D.cnt->err, ERR_CAPACITY);
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_write(Dev D) {
+  if (dead(D)) return;
+  __shared__ unsigned long long wsum[TPB / 64];
+  const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
+  uint32_t c[SCAN_ITEMS];
+  unsigned long long v = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+    c[k] = b < D.n_bricks ? D.bcnt[b] : 0u;
+    v += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
+  }
+  unsigned long long total;
+  unsigned long long ex = block_excl_scan64(v, wsum, total) + D.scan_tmp[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+    if (b < D.n_bricks) {
+      const uint32_t start = (uint32_t)(ex & 0xFFFFFFFFull);
+      const uint32_t occ = (uint32_t)(ex >> 32);
+      D.binfo[b] = make_uint4(start, c[k], NIL, 0u);
+      if (c[k] > 0u) D.occ[occ] = (uint32_t)b;
+      ex += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
+    }
+  }
+}
+
+// ------------------------------------------------------------- scatter ----
+__global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
+  if (dead(D)) return;
+  const uint32_t n = D.cnt->n_active;
+  const Chunk ch = chunk_of(n, TPB);
+  for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
+    const uint32_t i = base + threadIdx.x;
+    const bool valid = i < ch.end;
+    const uint4 r = valid ? D.A[i] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t fl = valid ? rec_fl(r) : 0u;
+    uint32_t bkey = NIL;
+    if (fl & FL_KEEP) bkey = brick_of(D, rec_pos(D, r));
+    const Run run = wave_run(bkey);
+    uint32_t rbase = 0;
+    if (bkey != NIL && run.off == 0) rbase = atomicSub(&D.bcnt[bkey], (uint32_t)run.len);
+    rbase = __shfl(rbase, run.head);
+    if (bkey != NIL) {
+      const uint32_t rank = rbase - (uint32_t)run.len + (uint32_t)run.off;
+      const uint32_t dst = D.binfo[bkey].x + rank;
+      if (dst < D.cap_p) D.B[dst] = with_fl(r, ST_ACTIVE);
+    }
+    if (fl & FL_SPAWN) {
+      const uint32_t g = rec_grain(r);
+      const int d = rec_dir(r);
+      int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
+      S[d >> 1] += (d & 1) ? -1 : 1;
+      claim_clear_now(D, g, S[0], S[1], S[2]);
+      const uint32_t mask = (fl >> 8) & 63u;
+      if (mask) {
+        const float* G = D.gtab + (size_t)g * GT_STRIDE;
+        const float sc = rec_s(r) - D.lambda0;
+        for (int dd = 0; dd < 6; ++dd) {
+          if (!(mask & (1u << dd))) continue;
+          const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
+          const uint32_t bc = brick_of(D, xc);
+          const uint32_t rank = atomicSub(&D.bcnt[bc], 1u) - 1u;
+          const uint32_t dst = D.binfo[bc].x + rank;
+          if (dst < D.cap_p) D.B[dst] = make_rec(sc, g, dd, S[0], S[1], S[2], ST_ACTIVE);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ cell sort ---
+// Identity of a particle within its cell: grain, departure site modulo 32
+// per axis, direction.  Two particles of one grain in one cell have sites
+// closer than 32 lattice steps, so the key is unique within a cell.
+__device__ __forceinline__ unsigned long long id_key(uint4 r) {
+  return ((unsigned long long)rec_grain(r) << 18) |
+         ((unsigned long long)(rec_sx(r) & 31) << 13) |
+         ((unsigned long long)(rec_sy(r) & 31) << 8) |
+         ((unsigned long long)(rec_sz(r) & 31) << 3) | (unsigned long long)rec_dir(r);
+}
+
+__global__ __launch_bounds__(TPB) void k_cellsort(Dev D, uint32_t epoch) {
+  if (dead(D)) return;
+  __shared__ uint4 srec[CS_CAP];
+  __shared__ uint32_t sinfo[CS_CAP];
+  __shared__ uint16_t sidx[CS_CAP];
+  __shared__ uint32_t hist[512];
+  __shared__ uint32_t off[512];
+  __shared__ uint32_t wsum[TPB / 64];
+  __shared__ uint32_t gmin_s, gmax_s;
+  const uint32_t nocc = D.cnt->n_occ;
+  const Chunk ch = chunk_of(nocc, 1u);
+  for (uint32_t k = ch.begin; k < ch.end; ++k) {
+    const uint32_t b = D.occ[k];
+    const uint4 info = D.binfo[b];
+    const uint32_t start = info.x, count = info.y;
+    if (count > (uint32_t)CS_CAP) {
+      if (threadIdx.x == 0) atomicOr(&D.cnt->err, ERR_CAPACITY);
+      continue;
+    }
+    const int bx = (int)(b % (uint32_t)D.nb[0]);
+    const int by = (int)((b / (uint32_t)D.nb[0]) % (uint32_t)D.nb[1]);
+    const int bz = (int)(b / ((uint32_t)D.nb[0] * (uint32_t)D.nb[1]));
+    for (int j = threadIdx.x; j < 512; j += TPB) hist[j] = 0;
+    if (threadIdx.x == 0) {
+      gmin_s = NIL;
+      gmax_s = 0;
+    }
+    __syncthreads();
+    uint32_t gmin = NIL, gmax = 0;
+    for (uint32_t j = threadIdx.x; j < count; j += TPB) {
+      const uint4 r = D.B[start + j];
+      srec[j] = r;
+      const C3 c = cell_of(D, rec_pos(D, r));
+      const uint32_t lc = (uint32_t)((c.x - bx * BRICK) | ((c.y - by * BRICK) << 3) |
+                                     ((c.z - bz * BRICK) << 6)) & 511u;
+      const uint32_t rk = atomicAdd(&hist[lc], 1u);
+      sinfo[j] = lc | (rk << 9);
+      const uint32_t g = rec_grain(r);
+      gmin = min(gmin, g);
+      gmax = max(gmax, g);
+    }
+    if (gmin != NIL) {
+      atomicMin(&gmin_s, gmin);
+      atomicMax(&gmax_s, gmax);
+    }
+    __syncthreads();
+    const uint32_t h0 = hist[2 * threadIdx.x], h1 = hist[2 * threadIdx.x + 1];
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(h0 + h1, wsum, tot);
+    off[2 * threadIdx.x] = ex;
+    off[2 * threadIdx.x + 1] = ex + h0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < count; j += TPB) {
+      const uint32_t lc = sinfo[j] & 511u;
+      sidx[off[lc] + (sinfo[j] >> 9)] = (uint16_t)j;
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < count; q += TPB) {
+      const uint32_t j = sidx[q];
+      const uint32_t lc = sinfo[j] & 511u;
+      const uint32_t beg = off[lc], cnt = hist[lc];
+      const uint4 r = srec[j];
+      const unsigned long long key = id_key(r);
+      uint32_t rank = 0;
+      for (uint32_t u = beg; u < beg + cnt; ++u) {
+        const uint32_t jj = sidx[u];
+        if (jj != j && id_key(srec[jj]) < key) ++rank;
+      }
+      D.A[start + beg + rank] = r;
+    }
+    for (uint32_t lc = threadIdx.x; lc < 512u; lc += TPB) {
+      const uint32_t c = hist[lc];
+      if (c == 0u) continue;
+      if (c > 255u) atomicOr(&D.cnt->err, ERR_CAPACITY);
+      const int cx = bx * BRICK + (int)(lc & 7u);
+      const int cy = by * BRICK + (int)((lc >> 3) & 7u);
+      const int cz = bz * BRICK + (int)(lc >> 6);
+      const uint64_t ci = cell_index(D, cx, cy, cz);
+      const unsigned long long hi = (unsigned long long)((c > 255u ? 255u : c) | (epoch << 8));
+      D.ctab[ci] = (unsigned long long)(start + off[lc]) | (hi << 32);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      D.binfo[b].z = gmin_s;
+      D.binfo[b].w = gmax_s;
+    }
+  }
+}
+
+// ---------------------------------------------------------- containment ---
+// True if any particle of another grain than g (g = NIL: any grain) lies
+// within rc of p, among this step's active particles and the stopped ones.
+__device__ __forceinline__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, C3 c,
+                                               uint32_t g) {
+  const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, D.n[0] - 1);
+  const int y0 = max(c.y - 1, 0), y1 = min(c.y + 1, D.n[1] - 1);
+  const int z0 = max(c.z - 1, 0), z1 = min(c.z + 1, D.n[2] - 1);
+  if (g != NIL) {
+    // Brick summaries: skip the stencil when every touched brick holds only
+    // grain g (or nothing).
+    bool maybe = false;
+    for (int bz = z0 >> 3; bz <= (z1 >> 3) && !maybe; ++bz)
+      for (int by = y0 >> 3; by <= (y1 >> 3) && !maybe; ++by)
+        for (int bx = x0 >> 3; bx <= (x1 >> 3) && !maybe; ++bx) {
+          const uint32_t b = ((uint32_t)bz * (uint32_t)D.nb[1] + (uint32_t)by) * (uint32_t)D.nb[0] +
+                             (uint32_t)bx;
+          const uint4 inf = D.binfo[b];
+          if (inf.y > 0u && !(inf.z == g && inf.w == g)) maybe = true;
+          const uint2 sb = D.sbsum[b];
+          if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) maybe = true;
+        }
+    if (!maybe) return false;
+  }
+  for (int z = z0; z <= z1; ++z)
+    for (int y = y0; y <= y1; ++y)
+      for (int x = x0; x <= x1; ++x) {
+        const uint64_t ci = cell_index(D, x, y, z);
+        const unsigned long long e = D.ctab[ci];
+        if ((uint32_t)(e >> 40) == epoch) {
+          const uint32_t st = (uint32_t)(e & 0xFFFFFFFFull);
+          const uint32_t cnt = (uint32_t)((e >> 32) & 255ull);
+          for (uint32_t j = st; j < st + cnt; ++j) {
+            const uint4 q = D.A[j];
+            if (rec_grain(q) == g) continue;
+            if (dist2(p, rec_pos(D, q)) < D.rc2) return true;
+          }
+        }
+        for (uint32_t j = D.shead[ci]; j != NIL; j = D.snext[j]) {
+          const uint4 q = D.S[j];
+          if (rec_grain(q) == g) continue;
+          if (dist2(p, rec_pos(D, q)) < D.rc2) return true;
+        }
+      }
+  return false;
+}
+
+__global__ __launch_bounds__(TPB) void k_contain(Dev D, uint32_t epoch) {
+  if (dead(D)) return;
+  const uint32_t n = D.cnt->n_out;
+  const Chunk ch = chunk_of(n, TPB);
+  for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
+    const uint32_t i = base + threadIdx.x;
+    bool hit = false;
+    if (i < ch.end) {
+      const uint4 r = D.A[i];
+      const P3 p = rec_pos(D, r);
+      hit = foreign_within(D, epoch, p, cell_of(D, p), rec_grain(r));
+    }
+    const uint32_t k = wave_append(hit, &D.cnt->n_newstop);
+    if (hit && k < D.cap_p) D.newstop[k] = i;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
+  if (dead(D)) return;
+  const uint32_t n = D.cnt->n_newstop;
+  const uint32_t nn = n < D.cap_p ? n : D.cap_p;
+  for (uint32_t k0 = blockIdx.x * TPB; k0 < nn; k0 += gridDim.x * TPB) {
+    const uint32_t k = k0 + threadIdx.x;
+    const bool valid = k < nn;
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t i = 0;
+    if (valid) {
+      i = D.newstop[k];
+      r = with_fl(D.A[i], ST_STOPPED);
+      D.A[i] = r;
+    }
+    const uint32_t j = wave_append(valid, &D.cnt->n_stopped);
+    if (valid) stopped_put(D, j, r);
+  }
+}
+
+// ----------------------------------------------------------- nucleation ---
+__global__ __launch_bounds__(TPB) void k_nuc_test(Dev D, float lin_c, uint32_t epoch) {
+  if (dead(D)) return;
+  const uint32_t ng = D.cnt->n_grains;
+  const float inv_l = 1.0f / D.lambda0;
+  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < D.n_sites; i += gridDim.x * TPB) {
+    if (D.sstate[i] != SITE_DORMANT) continue;
+    const float* T = D.stab + (size_t)i * GT_STRIDE;
+    const P3 y = {T[0], T[1], T[2]};
+    const float dT = field_at(D, y, lin_c) - D.theta;
+    if (!(dT >= T[3])) continue;
+    bool claimed = false;
+    for (uint32_t g = 0; g < ng && !claimed; ++g) {
+      int l[3];
+      lattice_round(D.gtab + (size_t)g * GT_STRIDE, inv_l, y, l);
+      const int32_t* bb = D.gbox + (size_t)g * 6;
+      if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] ||
+          l[2] > bb[5])
+        continue;
+      claimed = claim_test(D, g, l[0], l[1], l[2], M_CLAIMED | M_REACHED);
+    }
+    if (claimed) {
+      D.sstate[i] = SITE_ENGULFED;  // claims never shrink: permanent
+      continue;
+    }
+    if (foreign_within(D, epoch, y, cell_of(D, y), NIL)) continue;
+    D.cand[i] = 1u;
+    atomicAdd(&D.cnt->n_cand, 1u);
+  }
+}
+
+// One block: candidates in site order; a candidate is blocked by a site fired
+// earlier in the same step when it lies within rc of that site or rounds to
+// that grain's origin site.
+__global__ __launch_bounds__(TPB) void k_nuc_fire(Dev D) {
+  if (dead(D)) return;
+  if (D.cnt->n_cand == 0u) return;
+  __shared__ uint32_t list[TPB];
+  __shared__ uint32_t wsum[TPB / 64];
+  __shared__ uint32_t s_nlist, s_nfired, s_blocked;
+  const uint32_t ng0 = D.cnt->n_grains;
+  const uint32_t n_out = D.cnt->n_out;
+  const float inv_l = 1.0f / D.lambda0;
+  if (threadIdx.x == 0) s_nfired = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < D.n_sites; c0 += TPB) {
+    const uint32_t i = c0 + threadIdx.x;
+    uint32_t c = 0;
+    if (i < D.n_sites) {
+      c = D.cand[i];
+      if (c) D.cand[i] = 0u;
+    }
+    uint32_t tot;
+    const uint32_t pos = block_excl_scan(c, wsum, tot);
+    if (c) list[pos] = i;
+    if (threadIdx.x == 0) s_nlist = tot;
+    __syncthreads();
+    const uint32_t nl = s_nlist;
+    for (uint32_t q = 0; q < nl; ++q) {
+      const uint32_t si = list[q];
+      const float* T = D.stab + (size_t)si * GT_STRIDE;
+      const P3 y = {T[0], T[1], T[2]};
+      if (threadIdx.x == 0) s_blocked = 0;
+      __syncthreads();
+      const uint32_t nf = s_nfired;
+      for (uint32_t g = ng0 + threadIdx.x; g < ng0 + nf; g += TPB) {
+        const float* G = D.gtab + (size_t)g * GT_STRIDE;
+        const P3 cg = {G[0], G[1], G[2]};
+        int l[3];
+        lattice_round(G, inv_l, y, l);
+        if (dist2(y, cg) < D.rc2 || (l[0] == 0 && l[1] == 0 && l[2] == 0))
+          atomicOr(&s_blocked, 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0 && s_blocked == 0u) {
+        const uint32_t g = ng0 + nf;
+        if (g >= D.cap_grains || (uint64_t)n_out + 6ull * (nf + 1) > (uint64_t)D.cap_p) {
+          atomicOr(&D.cnt->err, ERR_CAPACITY);
+        } else {
+          float* Gd = D.gtab + (size_t)g * GT_STRIDE;
+          for (int k = 0; k < GT_STRIDE; ++k) Gd[k] = T[k];
+          Gd[3] = 0.0f;
+          int32_t* bb = D.gbox + (size_t)g * 6;
+          for (int k = 0; k < 6; ++k) bb[k] = 0;
+          claim_or(D, g, 0, 0, 0, M_CLAIMED | M_REACHED);
+          for (int d = 0; d < 6; ++d) D.A[n_out + 6 * nf + d] = make_rec(0.0f, g, d, 0, 0, 0, ST_ACTIVE);
+          D.sstate[si] = SITE_FIRED;
+          s_nfired = nf + 1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    D.cnt->n_fired = s_nfired;
+    D.cnt->n_grains = ng0 + s_nfired;
+    D.cnt->nucleated += s_nfired;
+  }
+}
+
+__global__ void k_finish(Dev D) {
+  Counters* c = D.cnt;
+  if (c->err & ERR_CAPACITY) return;
+  c->n_active = c->n_out + 6u * c->n_fired;
+  c->n_live = c->n_out - c->n_newstop + 6u * c->n_fired;
+  c->contained += c->n_newstop;
+  c->n_spawn = 0;
+  c->n_newstop = 0;
+  c->n_cand = 0;
+  c->n_fired = 0;
+}
+
+__global__ void k_reset_stats(Dev D) {
+  Counters* c = D.cnt;
+  c->advanced = 0;
+  c->exited = 0;
+  c->spawners = 0;
+  c->children = 0;
+  c->contained = 0;
+  c->nucleated = 0;
+  c->max_step = 0;
+}
+
+// ------------------------------------------------------------- resample ---
+struct RosenthalArgs {
+  double dT0, grad[3], rate, q, U, alpha, x_start, x_end, ys, zs, r_min, dT_min;
+  double o[3], sp[3], t;
+};
+
+// Rosenthal moving point source on a linear background, evaluated in FP64
+// at every node and stored as FP32 undercooling.
+__global__ __launch_bounds__(TPB) void k_resample(Dev D, RosenthalArgs a) {
+  const uint64_t total = (uint64_t)D.fn[0] * D.fn[1] * D.fn[2];
+  const double L = a.x_end - a.x_start;
+  const double phase = fmod(a.U * a.t, 2.0 * L);
+  double xs, sg;
+  if (phase < L) {
+    xs = a.x_start + phase;
+    sg = 1.0;
+  } else {
+    xs = a.x_start + 2.0 * L - phase;
+    sg = -1.0;
+  }
+  const double base_t = a.dT0 + a.rate * a.t;
+  const double k2 = -a.U / (2.0 * a.alpha);
+  const double qn = a.q / (2.0 * M_PI);
+  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
+       v += (uint64_t)gridDim.x * TPB) {
+    const uint64_t i = v % (uint64_t)D.fn[0];
+    const uint64_t j = (v / (uint64_t)D.fn[0]) % (uint64_t)D.fn[1];
+    const uint64_t k = v / ((uint64_t)D.fn[0] * D.fn[1]);
+    const double X = a.o[0] + (double)i * a.sp[0];
+    const double Y = a.o[1] + (double)j * a.sp[1];
+    const double Z = a.o[2] + (double)k * a.sp[2];
+    const double xi = sg * (X - xs), dy = Y - a.ys, dz = Z - a.zs;
+    double r = sqrt(xi * xi + dy * dy + dz * dz);
+    if (r < a.r_min) r = a.r_min;
+    const double rise = qn / r * exp(k2 * (xi + r));
+    double dT = base_t + a.grad[0] * X + a.grad[1] * Y + a.grad[2] * Z - rise;
+    if (dT < a.dT_min) dT = a.dT_min;
+    D.fgrid[v] = (float)dT;
+  }
+}
+
+// --------------------------------------------------------- init / load ----
+__global__ __launch_bounds__(TPB) void k_fill_sbsum(Dev D) {
+  for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
+       b += (uint64_t)gridDim.x * TPB)
+    D.sbsum[b] = make_uint2(NIL, 0u);
+}
+
+// New records A[first, first+count) (all active): those outside the box stop.
+__global__ __launch_bounds__(TPB) void k_classify_new(Dev D, uint32_t first, uint32_t count) {
+  for (uint32_t k0 = blockIdx.x * TPB; k0 < count; k0 += gridDim.x * TPB) {
+    const uint32_t k = k0 + threadIdx.x;
+    bool out = false;
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t i = first + k;
+    if (k < count) {
+      r = D.A[i];
+      if ((rec_fl(r) & 3u) == ST_STOPPED) {
+        out = true;
+      } else if (D.box_exit) {
+        const P3 x = rec_pos(D, r);
+        const bool inside = x.x >= D.lo[0] && x.x < D.hi[0] && x.y >= D.lo[1] &&
+                            x.y < D.hi[1] && x.z >= D.lo[2] && x.z < D.hi[2];
+        out = !inside;
+      }
+      if (out) {
+        r = with_fl(r, ST_STOPPED);
+        D.A[i] = r;
+        atomicSub(&D.cnt->n_live, 1u);
+      }
+    }
+    const uint32_t j = wave_append(out, &D.cnt->n_stopped);
+    if (out) stopped_put(D, j, r);
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_claim_ball(Dev D, uint32_t g, int32_t r) {
+  const int32_t w = 2 * r + 1;
+  const uint64_t total = (uint64_t)w * w * w;
+  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
+       v += (uint64_t)gridDim.x * TPB) {
+    const int x = (int)(v % w) - r;
+    const int y = (int)((v / w) % w) - r;
+    const int z = (int)(v / ((uint64_t)w * w)) - r;
+    if (abs(x) + abs(y) + abs(z) <= r) claim_or(D, g, x, y, z, M_CLAIMED | M_REACHED);
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_claim_list(Dev D, const int32_t* grain, const int32_t* site,
+                                                    const uint8_t* flags, uint32_t n) {
+  for (uint32_t k = blockIdx.x * TPB + threadIdx.x; k < n; k += gridDim.x * TPB) {
+    const uint32_t g = (uint32_t)grain[k];
+    const int x = site[3 * k], y = site[3 * k + 1], z = site[3 * k + 2];
+    uint32_t m = 0;
+    if (flags[k] & 1u) m |= M_CLAIMED;
+    if (flags[k] & 2u) m |= M_REACHED;
+    if (m) {
+      claim_or(D, g, x, y, z, m);
+      bbox_add(D, g, x, y, z);
+    }
+  }
+}
+
+// --------------------------------------------------------------- export ---
+struct PartOut {
+  float x, y, z, s;
+  int32_t site[3];
+  uint32_t grain;
+  uint8_t dir, state;
+  uint16_t pad;
+  int32_t cell[3];
+};
+static_assert(sizeof(PartOut) == 48, "particle record layout");
+
+__device__ __forceinline__ void put_particle(const Dev& D, uint4 r, uint32_t state, PartOut* o) {
+  const P3 p = rec_pos(D, r);
+  const C3 c = cell_of(D, p);
+  PartOut v;
+  v.x = p.x;
+  v.y = p.y;
+  v.z = p.z;
+  v.s = rec_s(r);
+  v.site[0] = rec_sx(r);
+  v.site[1] = rec_sy(r);
+  v.site[2] = rec_sz(r);
+  v.grain = rec_grain(r);
+  v.dir = (uint8_t)rec_dir(r);
+  v.state = (uint8_t)state;
+  v.pad = 0;
+  v.cell[0] = c.x;
+  v.cell[1] = c.y;
+  v.cell[2] = c.z;
+  *o = v;
+}
+
+__global__ __launch_bounds__(TPB) void k_export_particles(Dev D, uint32_t* counter, PartOut* out,
+                                                          uint32_t cap_out) {
+  const uint32_t na = D.cnt->n_active, ns = min(D.cnt->n_stopped, D.cap_s);
+  for (uint32_t k0 = blockIdx.x * TPB; k0 < na + ns; k0 += gridDim.x * TPB) {
+    const uint32_t k = k0 + threadIdx.x;
+    bool take = false;
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t st = ST_ACTIVE;
+    if (k < na) {
+      r = D.A[k];
+      take = (rec_fl(r) & 3u) == ST_ACTIVE;
+    } else if (k < na + ns) {
+      r = D.S[k - na];
+      take = true;
+      st = ST_STOPPED;
+    }
+    const uint32_t j = wave_append(take, counter);
+    if (take && j < cap_out) put_particle(D, r, st, out + j);
+  }
+}
+
+struct ClaimOut {
+  uint32_t grain;
+  int32_t site[3];
+  uint32_t flags;
+};
+static_assert(sizeof(ClaimOut) == 20, "claim record layout");
+
+__global__ __launch_bounds__(TPB) void k_export_claims(Dev D, uint32_t* counter, ClaimOut* out,
+                                                       uint32_t cap_out) {
+  const uint64_t slots = D.cmask + 1;
+  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < slots * 8;
+       v += (uint64_t)gridDim.x * TPB) {
+    const uint64_t slot = v >> 3;
+    const uint32_t w = (uint32_t)(v & 7u);
+    const unsigned long long key = D.ckeys[slot];
+    if (key == CLAIM_EMPTY) continue;
+    const unsigned long long cm = D.cbits[slot * 24 + CB_CLAIMED + w];
+    const unsigned long long rm = D.cbits[slot * 24 + CB_REACHED + w];
+    unsigned long long any = cm | rm;
+    if (!any) continue;
+    const uint32_t g = (uint32_t)(key >> 36);
+    const int bx = (int)((key >> 24) & 0xFFFull) - 2048;
+    const int by = (int)((key >> 12) & 0xFFFull) - 2048;
+    const int bz = (int)(key & 0xFFFull) - 2048;
+    const uint32_t base = atomicAdd(counter, (uint32_t)__popcll(any));
+    uint32_t k = 0;
+    while (any) {
+      const int bit = __ffsll((long long)any) - 1;
+      any &= any - 1ull;
+      const uint32_t j = base + k++;
+      if (j >= cap_out) continue;
+      ClaimOut o;
+      o.grain = g;
+      o.site[0] = bx * 8 + (bit & 7);
+      o.site[1] = by * 8 + ((bit >> 3) & 7);
+      o.site[2] = bz * 8 + (int)w;
+      o.flags = (uint32_t)((cm >> bit) & 1ull) | ((uint32_t)((rm >> bit) & 1ull) << 1);
+      out[j] = o;
+    }
+  }
+}
+
+// Grain map: voxel centre y takes the grain whose reached site is y's rounded
+// lattice position; nearest such site wins, then the lower grain.
+__global__ __launch_bounds__(TPB) void k_grain_map(Dev D, int32_t n0, int32_t n1, int32_t n2,
+                                                   float o0, float o1, float o2, float s0, float s1,
+                                                   float s2, uint32_t* out) {
+  const uint64_t total = (uint64_t)n0 * n1 * n2;
+  const uint32_t ng = D.cnt->n_grains;
+  const float inv_l = 1.0f / D.lambda0;
+  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
+       v += (uint64_t)gridDim.x * TPB) {
+    const uint64_t i = v % (uint64_t)n0, j = (v / (uint64_t)n0) % (uint64_t)n1,
+                   k = v / ((uint64_t)n0 * n1);
+    const P3 y = {o0 + ((float)i + 0.5f) * s0, o1 + ((float)j + 0.5f) * s1,
+                  o2 + ((float)k + 0.5f) * s2};
+    uint32_t best = 0;
+    float bd = INFINITY;
+    for (uint32_t g = 0; g < ng; ++g) {
+      const float* G = D.gtab + (size_t)g * GT_STRIDE;
+      int l[3];
+      lattice_round(G, inv_l, y, l);
+      const int32_t* bb = D.gbox + (size_t)g * 6;
+      if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] ||
+          l[2] > bb[5])
+        continue;
+      if (!claim_test(D, g, l[0], l[1], l[2], M_REACHED)) continue;
+      const P3 ps = lattice_pos(G, l[0], l[1], l[2], 0, 0.0f);
+      const float d = dist2(y, ps);
+      if (d < bd) {
+        bd = d;
+        best = g + 1;
+      }
+    }
+    out[v] = best;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_clear_ctab(Dev D, uint64_t n_cells) {
+  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < n_cells;
+       v += (uint64_t)gridDim.x * TPB)
+    D.ctab[v] = 0ull;
+}
+
+// ============================================================ launchers ===
+static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
+  uint64_t g = (n + TPB - 1) / TPB;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
+  k_advance<<<STREAM_GRID, TPB, 0, s>>>(d, lin_c, dt);
+}
+void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_scan(const Dev& d, hipStream_t s) {
+  const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
+  k_scan_reduce<<<ntiles, TPB, 0, s>>>(d);
+  k_scan_top<<<1, TPB, 0, s>>>(d, ntiles);
+  k_scan_write<<<ntiles, TPB, 0, s>>>(d);
+}
+void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_cellsort(const Dev& d, uint32_t epoch, hipStream_t s) {
+  k_cellsort<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
+}
+void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s) {
+  k_contain<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
+}
+void launch_stoplink(const Dev& d, hipStream_t s) { k_stoplink<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s) {
+  if (d.n_sites == 0) return;
+  k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(d, lin_c, epoch);
+  k_nuc_fire<<<1, TPB, 0, s>>>(d);
+}
+void launch_finish(const Dev& d, hipStream_t s) { k_finish<<<1, 1, 0, s>>>(d); }
+void launch_reset_stats(const Dev& d, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(d); }
+void launch_resample(const Dev& d, double dT0, const double grad[3], double rate, double q,
+                     double U, double alpha, double x_start, double x_end, double ys, double zs,
+                     double r_min, double dT_min, double ox, double oy, double oz, double sx,
+                     double sy, double sz, double t, hipStream_t s) {
+  RosenthalArgs a;
+  a.dT0 = dT0;
+  a.grad[0] = grad[0];
+  a.grad[1] = grad[1];
+  a.grad[2] = grad[2];
+  a.rate = rate;
+  a.q = q;
+  a.U = U;
+  a.alpha = alpha;
+  a.x_start = x_start;
+  a.x_end = x_end;
+  a.ys = ys;
+  a.zs = zs;
+  a.r_min = r_min;
+  a.dT_min = dT_min;
+  a.o[0] = ox;
+  a.o[1] = oy;
+  a.o[2] = oz;
+  a.sp[0] = sx;
+  a.sp[1] = sy;
+  a.sp[2] = sz;
+  a.t = t;
+  const uint64_t total = (uint64_t)d.fn[0] * d.fn[1] * d.fn[2];
+  k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(d, a);
+}
+void launch_init_workspace(const Dev& d, uint64_t, hipStream_t s) {
+  k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
+}
+void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s) {
+  if (count == 0) return;
+  k_classify_new<<<grid_for(count, 4096), TPB, 0, s>>>(d, first, count);
+}
+void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s) {
+  const uint64_t w = 2ull * (uint64_t)r + 1ull;
+  k_claim_ball<<<grid_for(w * w * w, 8192), TPB, 0, s>>>(d, grain, r);
+}
+void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
+                       const uint8_t* flags, uint32_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_claim_list<<<grid_for(n, 8192), TPB, 0, s>>>(d, grain, site, flags, n);
+}
+void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
+                             hipStream_t s) {
+  k_export_particles<<<1024, TPB, 0, s>>>(d, counter, (PartOut*)out, cap_out);
+}
+void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
+                          hipStream_t s) {
+  k_export_claims<<<4096, TPB, 0, s>>>(d, counter, (ClaimOut*)out, cap_out);
+}
+void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
+                      const float spacing[3], uint32_t* out, hipStream_t s) {
+  const uint64_t total = (uint64_t)n[0] * n[1] * n[2];
+  k_grain_map<<<grid_for(total, 8192), TPB, 0, s>>>(d, n[0], n[1], n[2], origin[0], origin[1],
+                                                    origin[2], spacing[0], spacing[1], spacing[2],
+                                                    out);
+}
+void launch_clear_ctab(const Dev& d, uint64_t n_cells, hipStream_t s) {
+  k_clear_ctab<<<grid_for(n_cells, 8192), TPB, 0, s>>>(d, n_cells);
+}
+
+}  // namespace ge

@@ -1,0 +1,743 @@
+// Host runtime and C ABI of libgrainenv (see include/grainenv.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "grainenv.h"
+#include "internal.h"
+
+using ge::Dev;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int64_t MAX_CAP_PARTICLES = 1ll << 28;
+constexpr int64_t MAX_SITE_RANGE = 16000;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Geometry {
+  int32_t n[3];
+  int32_t nb[3];
+  uint64_t n_cells;
+  uint64_t n_bricks;
+  uint64_t slots;
+  uint64_t field_nodes;
+};
+
+struct Layout {
+  size_t A, B, spawn, newstop, S, snext, shead, ctab, bcnt, binfo, occ, sbsum, scan_tmp, ckeys,
+      cbits, gtab, gbox, stab, sstate, cand, fgrid, cnt, total;
+};
+
+uint64_t next_pow2(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+const char* check_params(const ge_params* p) {
+  if (!p) return "null params";
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(p->lo[a]) || !std::isfinite(p->hi[a])) return "non-finite box";
+    if (!(p->hi[a] > p->lo[a])) return "empty or inverted box";
+  }
+  if (!(std::isfinite(p->lambda0) && p->lambda0 > 0)) return "lambda0 must be positive";
+  if (!(std::isfinite(p->h) && p->h > 0)) return "h must be positive";
+  if (!(std::isfinite(p->rc) && p->rc > 0)) return "rc must be positive";
+  if (p->rc > p->h) return "rc must not exceed h (27-cell stencil)";
+  if (p->rc > p->lambda0) return "rc must not exceed lambda0";
+  for (int k = 0; k < 2; ++k)
+    if (!std::isfinite(p->a[k]) || !std::isfinite(p->b[k]) || p->a[k] < 0) return "bad kinetics";
+  if (!std::isfinite(p->theta)) return "non-finite theta";
+  if (p->cap_particles < 6 || p->cap_particles > MAX_CAP_PARTICLES) return "cap_particles out of range";
+  if (p->cap_stopped < 1 || p->cap_stopped > (1ll << 31)) return "cap_stopped out of range";
+  if (p->cap_grains < 1 || p->cap_grains > (1 << 28) - 2) return "cap_grains out of range";
+  if (p->cap_sites < 0) return "cap_sites out of range";
+  if (p->cap_claim_bricks < 1 || p->cap_claim_bricks > (1ll << 32)) return "cap_claim_bricks out of range";
+  double diag = 0;
+  for (int a = 0; a < 3; ++a) {
+    double L = p->hi[a] - p->lo[a];
+    diag += L * L;
+    double nc = std::ceil(L / p->h);
+    if (nc > (1 << 20)) return "too many cells along an axis";
+    if (p->field_n[a] < 0 || p->field_n[a] == 1) return "field_n must be 0 or >= 2";
+  }
+  if (std::sqrt(diag) / p->lambda0 > MAX_SITE_RANGE) return "box too large for lambda0 (site range)";
+  return nullptr;
+}
+
+Geometry geometry(const ge_params* p) {
+  Geometry g{};
+  g.n_cells = 1;
+  g.n_bricks = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = (int32_t)std::max(1.0, std::ceil((p->hi[a] - p->lo[a]) / p->h));
+    g.nb[a] = (g.n[a] + ge::BRICK - 1) / ge::BRICK;
+    g.n_cells *= (uint64_t)g.n[a];
+    g.n_bricks *= (uint64_t)g.nb[a];
+  }
+  g.slots = next_pow2((uint64_t)std::max<int64_t>(p->cap_claim_bricks, 1024));
+  g.field_nodes = 1;
+  for (int a = 0; a < 3; ++a) g.field_nodes *= (uint64_t)std::max(p->field_n[a], 0);
+  if (p->field_n[0] == 0) g.field_nodes = 0;
+  return g;
+}
+
+Layout layout(const ge_params* p, const Geometry& g) {
+  Layout L{};
+  size_t off = 0;
+  auto put = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const uint64_t cp = (uint64_t)p->cap_particles, cs = (uint64_t)p->cap_stopped;
+  const uint64_t ntiles = (g.n_bricks + 2047) / 2048;
+  L.A = put(16 * cp);
+  L.B = put(16 * cp);
+  L.spawn = put(4 * cp);
+  L.newstop = put(4 * cp);
+  L.S = put(16 * cs);
+  L.snext = put(4 * cs);
+  L.shead = put(4 * g.n_cells);
+  L.ctab = put(8 * g.n_cells);
+  L.bcnt = put(4 * g.n_bricks);
+  L.binfo = put(16 * g.n_bricks);
+  L.occ = put(4 * g.n_bricks);
+  L.sbsum = put(8 * g.n_bricks);
+  L.scan_tmp = put(8 * ntiles);
+  L.ckeys = put(8 * g.slots);
+  L.cbits = put(192 * g.slots);
+  L.gtab = put(4 * ge::GT_STRIDE * (uint64_t)p->cap_grains);
+  L.gbox = put(24 * (uint64_t)p->cap_grains);
+  L.stab = put(4 * ge::GT_STRIDE * (uint64_t)std::max(p->cap_sites, 1));
+  L.sstate = put(4 * (uint64_t)std::max(p->cap_sites, 1));
+  L.cand = put(4 * (uint64_t)std::max(p->cap_sites, 1));
+  L.fgrid = put(4 * std::max<uint64_t>(g.field_nodes, 8));
+  L.cnt = put(sizeof(ge::Counters));
+  L.total = off;
+  return L;
+}
+
+// Grain-table row from centre and quaternion (FP64 maths, FP32 storage).
+void grain_row(const double c[3], const double q_in[4], double lambda0, float* row) {
+  double w = q_in[0], x = q_in[1], y = q_in[2], z = q_in[3];
+  double nq = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= nq; x /= nq; y /= nq; z /= nq;
+  double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                 2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                 2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  std::memset(row, 0, sizeof(float) * ge::GT_STRIDE);
+  for (int a = 0; a < 3; ++a) row[a] = (float)c[a];
+  for (int k = 0; k < 9; ++k) {
+    row[4 + k] = (float)R[k];
+    row[13 + k] = (float)(lambda0 * R[k]);
+  }
+}
+
+uint4 host_rec(float s, uint32_t g, int d, int sx, int sy, int sz, uint32_t fl) {
+  uint4 r;
+  std::memcpy(&r.x, &s, 4);
+  r.y = (g << 3) | (uint32_t)d;
+  r.z = ((uint32_t)(uint16_t)sx) | ((uint32_t)(uint16_t)sy << 16);
+  r.w = ((uint32_t)(uint16_t)sz) | (fl << 16);
+  return r;
+}
+
+}  // namespace
+
+struct ge_ctx {
+  ge_params p;
+  Geometry geo;
+  Layout lay;
+  hipStream_t stream;
+  char* ws;
+  Dev d;
+  ge::Counters* host_cnt;  // pinned
+  ge_field field;
+  std::vector<float> grid_copy;
+  double t;
+  int64_t step;
+  uint32_t epoch;
+  uint32_t n_sites;
+  bool dead;
+  std::string err;
+};
+
+static ge_status fail(ge_ctx* c, ge_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+static ge_status hip_check(ge_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GE_OK;
+  if (c) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    c->dead = true;
+  }
+  return GE_EDEVICE;
+}
+
+#define HIPCHK(c, call)                                         \
+  do {                                                          \
+    ge_status _s = hip_check((c), (call), #call);               \
+    if (_s != GE_OK) return _s;                                 \
+  } while (0)
+
+static ge_status read_counters(ge_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->host_cnt, c->d.cnt, sizeof(ge::Counters), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GE_OK;
+}
+
+static ge_status write_counters(ge_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->d.cnt, c->host_cnt, sizeof(ge::Counters), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GE_OK;
+}
+
+static ge_status error_status(ge_ctx* c, uint32_t err) {
+  if (err == 0) return GE_OK;
+  c->dead = true;
+  if (err & ge::ERR_CAPACITY) return fail(c, GE_ECAPACITY, "capacity exceeded on the device");
+  if (err & ge::ERR_NUMERIC) return fail(c, GE_ENUMERIC, "non-finite undercooling or travel");
+  return fail(c, GE_ECFL, "CFL violated: v dt > rc/2 or travel >= 2 lambda0");
+}
+
+// Resets the device state (cell lists, claims, counters) to empty.
+static ge_status reset_device(ge_ctx* c) {
+  const Layout& L = c->lay;
+  const Geometry& g = c->geo;
+  hipStream_t s = c->stream;
+  char* w = c->ws;
+  HIPCHK(c, hipMemsetAsync(w + L.shead, 0xFF, 4 * g.n_cells, s));
+  HIPCHK(c, hipMemsetAsync(w + L.ctab, 0, 8 * g.n_cells, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bcnt, 0, 4 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.ckeys, 0xFF, 8 * g.slots, s));
+  HIPCHK(c, hipMemsetAsync(w + L.cbits, 0, 192 * g.slots, s));
+  HIPCHK(c, hipMemsetAsync(w + L.cnt, 0, sizeof(ge::Counters), s));
+  HIPCHK(c, hipMemsetAsync(w + L.cand, 0, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
+  ge::launch_init_workspace(c->d, g.n_cells, s);
+  HIPCHK(c, hipGetLastError());
+  c->epoch = 0;
+  return GE_OK;
+}
+
+extern "C" {
+
+ge_status ge_validate_params(const ge_params* p) { return check_params(p) ? GE_EINVAL : GE_OK; }
+
+ge_status ge_workspace_size(const ge_params* p, size_t* bytes) {
+  if (!bytes || check_params(p)) return GE_EINVAL;
+  Geometry g = geometry(p);
+  *bytes = layout(p, g).total;
+  return GE_OK;
+}
+
+ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* stream,
+                    ge_ctx** out) {
+  if (!out || !workspace) return GE_EINVAL;
+  *out = nullptr;
+  if (check_params(p)) return GE_EINVAL;
+  if (((uintptr_t)workspace) % ALIGN) return GE_EINVAL;
+  ge_ctx* c = new ge_ctx();
+  c->p = *p;
+  c->geo = geometry(p);
+  c->lay = layout(p, c->geo);
+  if (bytes < c->lay.total) {
+    delete c;
+    return GE_EINVAL;
+  }
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  c->t = 0;
+  c->step = 0;
+  c->epoch = 0;
+  c->n_sites = 0;
+  c->dead = false;
+  c->field = ge_field{};
+  c->field.kind = GE_FIELD_UNIFORM;
+  if (hipHostMalloc((void**)&c->host_cnt, sizeof(ge::Counters), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return GE_EDEVICE;
+  }
+  std::memset(c->host_cnt, 0, sizeof(ge::Counters));
+  const Layout& L = c->lay;
+  const Geometry& g = c->geo;
+  char* w = c->ws;
+  Dev& d = c->d;
+  std::memset(&d, 0, sizeof(Dev));
+  for (int a = 0; a < 3; ++a) {
+    d.lo[a] = (float)p->lo[a];
+    d.hi[a] = (float)p->hi[a];
+    d.n[a] = g.n[a];
+    d.nb[a] = g.nb[a];
+  }
+  d.inv_h = (float)(1.0 / p->h);
+  d.n_bricks = (uint32_t)g.n_bricks;
+  d.lambda0 = (float)p->lambda0;
+  d.rc2 = (float)(p->rc * p->rc);
+  d.rc_half = (float)(0.5 * p->rc);
+  d.ka[0] = (float)p->a[0];
+  d.ka[1] = (float)p->a[1];
+  d.kb[0] = (float)p->b[0];
+  d.kb[1] = (float)p->b[1];
+  d.kin_poly = (p->b[0] == 2.0 && p->b[1] == 3.0) ? 1 : 0;
+  d.theta = (float)p->theta;
+  d.branching = p->branching;
+  d.box_exit = p->box_exit;
+  d.fkind = ge::F_UNIFORM;
+  d.fdT = 0.0f;
+  d.fgrid = (float*)(w + L.fgrid);
+  d.gtab = (float*)(w + L.gtab);
+  d.gbox = (int32_t*)(w + L.gbox);
+  d.cap_grains = (uint32_t)p->cap_grains;
+  d.A = (uint4*)(w + L.A);
+  d.B = (uint4*)(w + L.B);
+  d.cap_p = (uint32_t)p->cap_particles;
+  d.spawn = (uint32_t*)(w + L.spawn);
+  d.newstop = (uint32_t*)(w + L.newstop);
+  d.S = (uint4*)(w + L.S);
+  d.snext = (uint32_t*)(w + L.snext);
+  d.cap_s = (uint32_t)std::min<int64_t>(p->cap_stopped, 0xFFFFFFFEll);
+  d.shead = (uint32_t*)(w + L.shead);
+  d.sbsum = (uint2*)(w + L.sbsum);
+  d.bcnt = (uint32_t*)(w + L.bcnt);
+  d.binfo = (uint4*)(w + L.binfo);
+  d.occ = (uint32_t*)(w + L.occ);
+  d.ctab = (unsigned long long*)(w + L.ctab);
+  d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
+  d.ckeys = (unsigned long long*)(w + L.ckeys);
+  d.cbits = (unsigned long long*)(w + L.cbits);
+  d.cmask = g.slots - 1;
+  d.claim_limit = (uint32_t)std::min<uint64_t>(g.slots - g.slots / 4, 0xFFFFFFFFull);
+  d.stab = (float*)(w + L.stab);
+  d.sstate = (uint32_t*)(w + L.sstate);
+  d.cand = (uint32_t*)(w + L.cand);
+  d.n_sites = 0;
+  d.cnt = (ge::Counters*)(w + L.cnt);
+  ge_status st = reset_device(c);
+  if (st == GE_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "create");
+  if (st != GE_OK) {
+    (void)hipHostFree(c->host_cnt);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return GE_OK;
+}
+
+ge_status ge_destroy(ge_ctx* c) {
+  if (!c) return GE_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipHostFree(c->host_cnt);
+  delete c;
+  return GE_OK;
+}
+
+const char* ge_last_error(const ge_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+ge_status ge_init_grains(ge_ctx* c, int32_t n, const double* centre, const double* quat,
+                         const int32_t* shell_r, uint32_t* first_id) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (n < 0 || (n > 0 && (!centre || !quat || !shell_r))) return fail(c, GE_EINVAL, "bad arguments");
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  ge::Counters& H = *c->host_cnt;
+  if (H.err) return error_status(c, H.err);
+  const uint32_t g0 = H.n_grains;
+  if ((int64_t)g0 + n > c->p.cap_grains) return fail(c, GE_ECAPACITY, "cap_grains exceeded");
+  std::vector<float> rows((size_t)n * ge::GT_STRIDE);
+  std::vector<int32_t> boxes((size_t)n * 6);
+  std::vector<uint4> recs;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(centre[3 * i + a])) return fail(c, GE_EINVAL, "non-finite centre");
+    const int32_t r = shell_r[i];
+    if (r < 0 || r > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "shell_r out of range");
+    grain_row(centre + 3 * i, quat + 4 * i, c->p.lambda0, rows.data() + (size_t)i * ge::GT_STRIDE);
+    for (int a = 0; a < 3; ++a) {
+      boxes[6 * i + a] = -r;
+      boxes[6 * i + 3 + a] = r;
+    }
+    const uint32_t g = g0 + (uint32_t)i;
+    if (r == 0) {
+      for (int d = 0; d < 6; ++d) recs.push_back(host_rec(0.0f, g, d, 0, 0, 0, ge::ST_ACTIVE));
+    } else {
+      for (int x = -r; x <= r; ++x)
+        for (int y = -(r - std::abs(x)); y <= r - std::abs(x); ++y) {
+          const int rz = r - std::abs(x) - std::abs(y);
+          const int zs[2] = {-rz, rz};
+          for (int k = 0; k < (rz == 0 ? 1 : 2); ++k) {
+            const int s[3] = {x, y, zs[k]};
+            int a = 0;
+            for (int b = 1; b < 3; ++b)
+              if (std::abs(s[b]) > std::abs(s[a])) a = b;
+            const int d = 2 * a + (s[a] < 0 ? 1 : 0);
+            recs.push_back(host_rec(0.0f, g, d, s[0], s[1], s[2], ge::ST_ACTIVE));
+          }
+        }
+    }
+  }
+  const uint32_t na = H.n_active;
+  if ((uint64_t)na + recs.size() > (uint64_t)c->p.cap_particles)
+    return fail(c, GE_ECAPACITY, "cap_particles exceeded");
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(c->d.gtab + (size_t)g0 * ge::GT_STRIDE, rows.data(),
+                           rows.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d.gbox + (size_t)g0 * 6, boxes.data(), boxes.size() * 4,
+                           hipMemcpyHostToDevice, s));
+  if (!recs.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d.A + na, recs.data(), recs.size() * sizeof(uint4),
+                             hipMemcpyHostToDevice, s));
+  H.n_grains = g0 + (uint32_t)n;
+  H.n_active = na + (uint32_t)recs.size();
+  H.n_live += (uint32_t)recs.size();
+  st = write_counters(c);
+  if (st != GE_OK) return st;
+  ge::launch_classify_new(c->d, na, (uint32_t)recs.size(), s);
+  for (int32_t i = 0; i < n; ++i) {
+    if (shell_r[i] == 0) ge::launch_claim_ball(c->d, g0 + (uint32_t)i, 0, s);
+    else ge::launch_claim_ball(c->d, g0 + (uint32_t)i, shell_r[i], s);
+  }
+  HIPCHK(c, hipGetLastError());
+  st = read_counters(c);
+  if (st != GE_OK) return st;
+  if (c->host_cnt->err) return error_status(c, c->host_cnt->err);
+  if (first_id) *first_id = g0;
+  return GE_OK;
+}
+
+ge_status ge_set_thermal_field(ge_ctx* c, const ge_field* f) {
+  if (!c || !f) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  auto fin = [](double v) { return std::isfinite(v); };
+  Dev& d = c->d;
+  switch (f->kind) {
+    case GE_FIELD_UNIFORM:
+      if (!fin(f->dT)) return fail(c, GE_ENUMERIC, "non-finite field");
+      break;
+    case GE_FIELD_LINEAR:
+      if (!fin(f->dT0) || !fin(f->rate) || !fin(f->grad[0]) || !fin(f->grad[1]) || !fin(f->grad[2]))
+        return fail(c, GE_ENUMERIC, "non-finite field");
+      break;
+    case GE_FIELD_GRID:
+    case GE_FIELD_ROSENTHAL: {
+      uint64_t nodes = 1;
+      for (int a = 0; a < 3; ++a) {
+        if (f->n[a] < 2 || f->n[a] > c->p.field_n[a]) return fail(c, GE_EINVAL, "grid larger than field_n");
+        if (!fin(f->origin[a]) || !(f->spacing[a] > 0) || !fin(f->spacing[a]))
+          return fail(c, GE_EINVAL, "bad grid geometry");
+        nodes *= (uint64_t)f->n[a];
+      }
+      if (f->kind == GE_FIELD_GRID) {
+        if (!f->data) return fail(c, GE_EINVAL, "GRID needs data");
+        HIPCHK(c, hipMemcpyAsync(d.fgrid, f->data, nodes * 4,
+                                 f->data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+      } else {
+        const double v[] = {f->dT0, f->rate, f->q, f->U, f->alpha, f->x_start, f->x_end, f->ys,
+                            f->zs, f->r_min, f->dT_min, f->grad[0], f->grad[1], f->grad[2]};
+        for (double x : v)
+          if (!fin(x)) return fail(c, GE_ENUMERIC, "non-finite field");
+        if (!(f->alpha > 0) || !(f->x_end > f->x_start)) return fail(c, GE_EINVAL, "bad source");
+      }
+      break;
+    }
+    default:
+      return fail(c, GE_EINVAL, "unknown field kind");
+  }
+  c->field = *f;
+  c->field.data = nullptr;
+  d.fkind = f->kind;
+  d.fdT = (float)f->dT;
+  for (int a = 0; a < 3; ++a) {
+    d.fgrad[a] = (float)f->grad[a];
+    d.fn[a] = f->n[a];
+    d.fo[a] = (float)f->origin[a];
+    d.finv[a] = f->spacing[a] > 0 ? (float)(1.0 / f->spacing[a]) : 0.0f;
+  }
+  return GE_OK;
+}
+
+ge_status ge_nucleate(ge_ctx* c, int32_t n, const double* xyz, const double* dT_nuc,
+                      const double* quat) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (n < 0 || (n > 0 && (!xyz || !dT_nuc || !quat))) return fail(c, GE_EINVAL, "bad arguments");
+  if ((int64_t)c->n_sites + n > c->p.cap_sites) return fail(c, GE_ECAPACITY, "cap_sites exceeded");
+  if (n == 0) return GE_OK;
+  std::vector<float> rows((size_t)n * ge::GT_STRIDE);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!std::isfinite(dT_nuc[i])) return fail(c, GE_ENUMERIC, "non-finite nucleation undercooling");
+    float* row = rows.data() + (size_t)i * ge::GT_STRIDE;
+    grain_row(xyz + 3 * i, quat + 4 * i, c->p.lambda0, row);
+    row[3] = (float)dT_nuc[i];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d.stab + (size_t)c->n_sites * ge::GT_STRIDE, rows.data(),
+                           rows.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d.sstate + c->n_sites, 0, 4 * (size_t)n, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->n_sites += (uint32_t)n;
+  c->d.n_sites = c->n_sites;
+  return GE_OK;
+}
+
+
+static void fill_stats(ge_ctx* c, ge_step_stats* st) {
+  const ge::Counters& H = *c->host_cnt;
+  st->n_active = (int64_t)H.n_live;
+  st->n_stopped = (int64_t)H.n_stopped;
+  st->n_grains = (int64_t)H.n_grains;
+  st->n_claim_bricks = (int64_t)H.claim_used;
+  st->advanced = (int64_t)H.advanced;
+  st->exited = (int64_t)H.exited;
+  st->spawners = (int64_t)H.spawners;
+  st->children = (int64_t)H.children;
+  st->contained = (int64_t)H.contained;
+  st->nucleated = (int64_t)H.nucleated;
+  float ms;
+  std::memcpy(&ms, &H.max_step, 4);
+  st->max_step = ms;
+  st->t = c->t;
+  st->step = c->step;
+}
+
+ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (!(std::isfinite(dt) && dt > 0) || n_steps < 0) return fail(c, GE_EINVAL, "bad dt or n_steps");
+  hipStream_t s = c->stream;
+  Dev& d = c->d;
+  ge::launch_reset_stats(d, s);
+  for (int32_t k = 0; k < n_steps; ++k) {
+    c->epoch += 1;
+    if (c->epoch > 0xFFFFFFu) {
+      ge::launch_clear_ctab(d, c->geo.n_cells, s);
+      c->epoch = 1;
+    }
+    const double t = c->t;
+    float lin_c = 0.0f;
+    if (c->field.kind == GE_FIELD_LINEAR) lin_c = (float)(c->field.dT0 + c->field.rate * t);
+    if (c->field.kind == GE_FIELD_ROSENTHAL) {
+      const ge_field& f = c->field;
+      ge::launch_resample(d, f.dT0, f.grad, f.rate, f.q, f.U, f.alpha, f.x_start, f.x_end, f.ys,
+                          f.zs, f.r_min, f.dT_min, f.origin[0], f.origin[1], f.origin[2],
+                          f.spacing[0], f.spacing[1], f.spacing[2], t, s);
+    }
+    ge::launch_advance(d, lin_c, (float)dt, s);
+    ge::launch_branch(d, s);
+    ge::launch_scan(d, s);
+    ge::launch_scatter(d, s);
+    ge::launch_cellsort(d, c->epoch, s);
+    ge::launch_contain(d, c->epoch, s);
+    ge::launch_stoplink(d, s);
+    ge::launch_nucleate(d, lin_c, c->epoch, s);
+    ge::launch_finish(d, s);
+    c->t = t + dt;
+    c->step += 1;
+  }
+  HIPCHK(c, hipGetLastError());
+  if (!stats) return GE_OK;
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  fill_stats(c, stats);
+  return error_status(c, c->host_cnt->err);
+}
+
+// Copies `bytes` of device data at src to out (host or device).
+static ge_status deliver(ge_ctx* c, const void* src, void* out, size_t bytes) {
+  hipPointerAttribute_t attr;
+  bool dev_out = false;
+  if (hipPointerGetAttributes(&attr, out) == hipSuccess)
+    dev_out = attr.type == hipMemoryTypeDevice;
+  (void)hipGetLastError();
+  HIPCHK(c, hipMemcpyAsync(out, src, bytes, dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GE_OK;
+}
+
+ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, void* out,
+                            size_t out_bytes, size_t* needed) {
+  if (!c) return GE_EINVAL;
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  const ge::Counters H = *c->host_cnt;
+  hipStream_t s = c->stream;
+  size_t need = 0;
+  switch (kind) {
+    case GE_QUERY_COUNTS: {
+      need = sizeof(ge_step_stats);
+      if (needed) *needed = need;
+      if (!out || out_bytes < need) return GE_OK;
+      ge_step_stats v{};
+      fill_stats(c, &v);
+      v.advanced = v.exited = v.spawners = v.children = v.contained = v.nucleated = 0;
+      v.max_step = 0;
+      std::memcpy(out, &v, sizeof(v));
+      return error_status(c, H.err);
+    }
+    case GE_QUERY_PARTICLES:
+    case GE_QUERY_CLAIMS: {
+      const bool parts = kind == GE_QUERY_PARTICLES;
+      const size_t rec = parts ? sizeof(ge_particle_rec) : sizeof(ge_claim_rec);
+      uint32_t* counter = nullptr;
+      HIPCHK(c, hipMalloc((void**)&counter, 4));
+      HIPCHK(c, hipMemsetAsync(counter, 0, 4, s));
+      if (parts) ge::launch_export_particles(c->d, counter, nullptr, 0, s);
+      else ge::launch_export_claims(c->d, counter, nullptr, 0, s);
+      uint32_t count = 0;
+      HIPCHK(c, hipMemcpyAsync(&count, counter, 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      need = (size_t)count * rec;
+      if (needed) *needed = need;
+      if (!out || out_bytes < need || count == 0) {
+        (void)hipFree(counter);
+        return GE_OK;
+      }
+      void* stage = nullptr;
+      HIPCHK(c, hipMalloc(&stage, need));
+      HIPCHK(c, hipMemsetAsync(counter, 0, 4, s));
+      if (parts) ge::launch_export_particles(c->d, counter, stage, count, s);
+      else ge::launch_export_claims(c->d, counter, stage, count, s);
+      HIPCHK(c, hipGetLastError());
+      st = deliver(c, stage, out, need);
+      (void)hipFree(stage);
+      (void)hipFree(counter);
+      return st;
+    }
+    case GE_QUERY_GRAIN_MAP: {
+      if (!args) return fail(c, GE_EINVAL, "GRAIN_MAP needs args");
+      uint64_t nv = 1;
+      int32_t n[3];
+      float o[3], sp[3];
+      for (int a = 0; a < 3; ++a) {
+        if (args->n[a] < 1 || !(args->spacing[a] > 0)) return fail(c, GE_EINVAL, "bad voxel grid");
+        n[a] = args->n[a];
+        o[a] = (float)args->origin[a];
+        sp[a] = (float)args->spacing[a];
+        nv *= (uint64_t)n[a];
+      }
+      need = nv * 4;
+      if (needed) *needed = need;
+      if (!out || out_bytes < need) return GE_OK;
+      void* stage = nullptr;
+      HIPCHK(c, hipMalloc(&stage, need));
+      ge::launch_grain_map(c->d, n, o, sp, (uint32_t*)stage, s);
+      HIPCHK(c, hipGetLastError());
+      st = deliver(c, stage, out, need);
+      (void)hipFree(stage);
+      return st;
+    }
+    case GE_QUERY_SITES: {
+      need = (size_t)c->n_sites * 4;
+      if (needed) *needed = need;
+      if (!out || out_bytes < need || need == 0) return GE_OK;
+      return deliver(c, c->d.sstate, out, need);
+    }
+    case GE_QUERY_GRAINS: {
+      need = (size_t)H.n_grains * ge::GT_STRIDE * 4;
+      if (needed) *needed = need;
+      if (!out || out_bytes < need || need == 0) return GE_OK;
+      return deliver(c, c->d.gtab, out, need);
+    }
+    default:
+      return fail(c, GE_EINVAL, "unknown query kind");
+  }
+}
+
+ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
+  if (!c || !st_in) return GE_EINVAL;
+  const ge_state_in& S = *st_in;
+  if (S.n_grains < 0 || S.n_grains > c->p.cap_grains) return fail(c, GE_ECAPACITY, "cap_grains exceeded");
+  if (S.n_particles < 0 || S.n_claims < 0) return fail(c, GE_EINVAL, "negative counts");
+  if ((uint32_t)S.n_sites != c->n_sites) return fail(c, GE_EINVAL, "site count differs from registered sites");
+  hipStream_t s = c->stream;
+  c->dead = false;
+  c->err.clear();
+  ge_status st = reset_device(c);
+  if (st != GE_OK) return st;
+  // Grains.
+  std::vector<float> rows((size_t)S.n_grains * ge::GT_STRIDE);
+  std::vector<int32_t> boxes((size_t)S.n_grains * 6);
+  for (int32_t g = 0; g < S.n_grains; ++g) {
+    grain_row(S.centre + 3 * g, S.quat + 4 * g, c->p.lambda0, rows.data() + (size_t)g * ge::GT_STRIDE);
+    for (int a = 0; a < 3; ++a) {
+      boxes[6 * g + a] = INT_MAX;
+      boxes[6 * g + 3 + a] = INT_MIN;
+    }
+  }
+  // Particles: active and stopped (retired ones are dropped).
+  std::vector<uint4> recs;
+  recs.reserve((size_t)S.n_particles);
+  for (int64_t i = 0; i < S.n_particles; ++i) {
+    if (S.state[i] == GE_RETIRED) continue;
+    if (S.grain[i] < 0 || S.grain[i] >= S.n_grains || S.dir[i] < 0 || S.dir[i] > 5)
+      return fail(c, GE_EINVAL, "bad particle");
+    for (int a = 0; a < 3; ++a)
+      if (std::abs(S.site[3 * i + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "site out of range");
+    recs.push_back(host_rec(S.s[i], (uint32_t)S.grain[i], S.dir[i], S.site[3 * i], S.site[3 * i + 1],
+                            S.site[3 * i + 2],
+                            S.state[i] == GE_STOPPED ? ge::ST_STOPPED : ge::ST_ACTIVE));
+  }
+  if ((int64_t)recs.size() > c->p.cap_particles) return fail(c, GE_ECAPACITY, "cap_particles exceeded");
+  if (!rows.empty()) {
+    HIPCHK(c, hipMemcpyAsync(c->d.gtab, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d.gbox, boxes.data(), boxes.size() * 4, hipMemcpyHostToDevice, s));
+  }
+  if (!recs.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d.A, recs.data(), recs.size() * sizeof(uint4), hipMemcpyHostToDevice, s));
+  if (S.n_sites > 0) {
+    std::vector<uint32_t> ss(S.site_state, S.site_state + S.n_sites);
+    HIPCHK(c, hipMemcpyAsync(c->d.sstate, ss.data(), ss.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  ge::Counters& H = *c->host_cnt;
+  std::memset(&H, 0, sizeof(H));
+  H.n_grains = (uint32_t)S.n_grains;
+  H.n_active = (uint32_t)recs.size();
+  H.n_live = (uint32_t)recs.size();
+  st = write_counters(c);
+  if (st != GE_OK) return st;
+  ge::launch_classify_new(c->d, 0, (uint32_t)recs.size(), s);
+  for (int64_t k = 0; k < S.n_claims; ++k) {
+    if (S.c_grain[k] < 0 || S.c_grain[k] >= S.n_grains) return fail(c, GE_EINVAL, "bad claim grain");
+    for (int a = 0; a < 3; ++a)
+      if (std::abs(S.c_site[3 * k + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "claim site out of range");
+  }
+  if (S.n_claims > 0) {
+    const size_t m = (size_t)S.n_claims;
+    char* buf = nullptr;
+    HIPCHK(c, hipMalloc((void**)&buf, m * 17 + 64));
+    int32_t* dg = (int32_t*)buf;
+    int32_t* ds = (int32_t*)(buf + m * 4);
+    uint8_t* df = (uint8_t*)(buf + m * 16);
+    HIPCHK(c, hipMemcpyAsync(dg, S.c_grain, m * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(ds, S.c_site, m * 12, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(df, S.c_flags, m, hipMemcpyHostToDevice, s));
+    ge::launch_claim_list(c->d, dg, ds, df, (uint32_t)m, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    (void)hipFree(buf);
+  }
+  HIPCHK(c, hipGetLastError());
+  st = read_counters(c);
+  if (st != GE_OK) return st;
+  c->t = S.t;
+  c->step = S.step;
+  return error_status(c, c->host_cnt->err);
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+"""Multi-step GPU runs against the FP64 oracle: scaled directional and CET
+workloads (grain maps agree on >= 99.9% of voxels), nucleation firing steps,
+determinism, and the device error paths."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2504_12858_amd import binding as B
+from paper_2504_12858_amd import workloads as W
+from tests.gpu_helpers import context_for, gpu_claims, gpu_parts, orc_claims, orc_parts, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _scaled_directional(seed=2):
+    return W.directional(seed=seed, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0,
+                         dt=5e-4, n_steps=240)
+
+
+def _scaled_cet(seed=3):
+    w = W.cet(seed=seed, size=(0.4e-3, 0.2e-3, 0.1e-3), lambda0=4e-6, grid_n=24, dT0=6.0,
+              rate=2.0, bulk_density=2e12, face_density=2e8, dt=1.5e-3, n_steps=300, U=0.005,
+              q=0.004)
+    return w
+
+
+def _map_agreement(ctx, o, w, vox):
+    n = [int(round((h - l) / vox)) for l, h in zip(w.lo, w.hi)]
+    gm = ctx.grain_map(n, w.lo, [vox] * 3)
+    om = o.grain_map(np.array(n, np.int32), np.array(w.lo), np.array([vox] * 3))
+    return (gm == om).mean(), (om > 0).mean()
+
+
+def test_directional_scaled_grain_map_parity():
+    require_gpu()
+    w = _scaled_directional()
+    print(f"directional scaled: {w.n_steps} steps", flush=True)
+    ctx = context_for(w)
+    st = ctx.step(w.dt, w.n_steps)
+    o = Oracle.from_workload(w)
+    o.step(w.dt, w.n_steps)
+    assert o.error == 0
+    agree, solid = _map_agreement(ctx, o, w, 5e-6)
+    print(f"map agreement {agree:.6f} solid fraction {solid:.3f} active {st['n_active']} "
+          f"oracle active {o.n_active()}", flush=True)
+    assert solid > 0.2
+    assert agree >= 0.999
+    assert abs(st["n_active"] - o.n_active()) <= 0.01 * o.n_active()
+
+
+def test_cet_scaled_grain_map_parity():
+    """Moving Rosenthal source resampled each step, bulk and face nuclei."""
+    require_gpu()
+    w = _scaled_cet()
+    print(f"cet scaled: {len(w.site_dTn)} sites, {w.n_steps} steps", flush=True)
+    ctx = context_for(w)
+    st = ctx.step(w.dt, w.n_steps)
+    o = Oracle.from_workload(w)
+    o.step(w.dt, w.n_steps)
+    assert o.error == 0
+    ss = ctx.site_states()
+    fired_gpu = ss == 1
+    fired_orc = o.site_states() == 1
+    print(f"fired gpu {fired_gpu.sum()} oracle {fired_orc.sum()} nucleated {st['nucleated']}",
+          flush=True)
+    assert fired_gpu.sum() > 10
+    assert (fired_gpu != fired_orc).sum() <= max(1, 0.01 * fired_orc.sum())
+    agree, solid = _map_agreement(ctx, o, w, 4e-6)
+    print(f"map agreement {agree:.6f} solid {solid:.3f}", flush=True)
+    assert solid > 0.05
+    assert agree >= 0.999
+
+
+def test_fire_steps_in_uniform_cooling_on_gpu():
+    require_gpu()
+    dT0, rate, dt = 0.5, 10.0, 1e-3
+    g = W.rng(8)
+    n_sites = 12
+    xyz = np.array([[1e-4 + 6e-5 * i, 2e-4 + 5e-5 * (i % 4), 3e-4 + 4e-5 * (i % 3)] for i in range(n_sites)])
+    dTn = 0.5 + g.random(n_sites) * 4.0
+    p = B.make_params((0, 0, 0), (1e-3,) * 3, 5e-6, 5e-6, 5e-6, (1e-12, 0.0), W.KIN_B,
+                      cap_particles=4096, cap_stopped=4096, cap_grains=64, cap_sites=64,
+                      cap_claim_bricks=1024)
+    ctx = B.Context(p)
+    ctx.set_thermal_field(W.Field(W.FIELD_LINEAR, dT0=dT0, rate=rate))
+    ctx.nucleate(xyz, dTn, W.shoemake_quaternions(g, n_sites))
+    expect = np.array([math.ceil((d - dT0) / (rate * dt)) for d in dTn])
+    fired_at = np.full(n_sites, -1)
+    for n in range(0, int(expect.max()) + 2):
+        ctx.step(dt, 1)
+        st = ctx.site_states()
+        fired_at[(st == 1) & (fired_at < 0)] = n
+    np.testing.assert_array_equal(fired_at, expect)
+    rows = ctx.grains()
+    order = np.lexsort((np.arange(n_sites), expect))
+    np.testing.assert_allclose(rows[:, :3], xyz[order].astype(np.float32))
+
+
+def test_same_step_sites_and_engulfed_sites_on_gpu():
+    require_gpu()
+    lam = 5e-6
+    p = B.make_params((0, 0, 0), (1e-3,) * 3, lam, lam, lam, W.KIN_A, W.KIN_B,
+                      cap_particles=1 << 16, cap_stopped=1 << 16, cap_grains=16, cap_sites=16,
+                      cap_claim_bricks=1 << 12)
+    ctx = B.Context(p)
+    ctx.set_thermal_field(W.Field(W.FIELD_UNIFORM, dT=5.0))
+    c = np.array([[2e-4, 2e-4, 2e-4]])
+    ctx.init_grains(c, np.array([[1.0, 0, 0, 0]]), np.array([8], np.int32))
+    y0 = np.array([5e-4, 5e-4, 5e-4])
+    xyz = np.stack([y0 + [0.1 * lam] * 3, y0, y0 + [2e-4, 0, 0], c[0] + [1.2e-6, 0.9e-6, 0]])
+    ctx.nucleate(xyz, np.array([1.0, 0.5, 1.0, 0.0]), np.array([[1.0, 0, 0, 0]] * 4))
+    ctx.step(1e-4, 1)
+    # Site 0 fires, site 1 is blocked by it, site 2 fires, site 3 lies inside
+    # grain 0's claimed ball and is marked engulfed.
+    np.testing.assert_array_equal(ctx.site_states(), [1, 0, 1, 2])
+
+
+def test_runs_are_deterministic():
+    require_gpu()
+    w = _scaled_directional(seed=5)
+    outs = []
+    for _ in range(2):
+        ctx = context_for(w)
+        ctx.step(w.dt, 120)
+        p, key = gpu_parts(ctx)
+        c, ckey = gpu_claims(ctx)
+        outs.append((p.tobytes(), c.tobytes()))
+        ctx.close()
+    assert outs[0] == outs[1]
+
+
+def test_capacity_error_is_reported_and_sticky():
+    require_gpu()
+    w = W.nucleus_uniform(lambda0=5e-6, dT=4.7)
+    ctx = context_for(w, cap_particles=64, cap_stopped=64)
+    with pytest.raises(B.GrainEnvError) as e:
+        ctx.step(1e-3, 200)
+    assert e.value.status == B.GE_ECAPACITY
+    with pytest.raises(B.GrainEnvError) as e2:
+        ctx.step(1e-3, 1)
+    assert e2.value.status == B.GE_ESTATE
+
+
+def test_cfl_error():
+    require_gpu()
+    w = W.nucleus_uniform(lambda0=5e-6, dT=5.0)
+    ctx = context_for(w)
+    with pytest.raises(B.GrainEnvError) as e:
+        ctx.step(1.0, 1)     # v dt = 3.75e-4 m >> rc / 2
+    assert e.value.status == B.GE_ECFL
+
+
+def test_host_validation_errors():
+    require_gpu()
+    w = W.nucleus_uniform()
+    ctx = context_for(w)
+    with pytest.raises(B.GrainEnvError) as e:
+        ctx.set_thermal_field(W.Field(W.FIELD_UNIFORM, dT=float("nan")))
+    assert e.value.status == B.GE_ENUMERIC
+    with pytest.raises(B.GrainEnvError) as e:
+        ctx.step(-1.0, 1)
+    assert e.value.status == B.GE_EINVAL
