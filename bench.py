@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Envelope particle-updates/s of the plain grain-envelope step on one MI355X.
+
+Workload: columnar-to-equiaxed transition under a moving Rosenthal source
+(4 x 2 x 1 mm box, 256^3 FP32 undercooling grid resampled every step, 800
+face and 800 bulk nuclei, lambda0 = h = rc = 1 um, dT0 = 12 K), advanced
+untimed from t = 0 to the first step with >= 20M active particles.  Then W
+warm-up steps and K timed steps, bracketed by stream synchronisations.
+
+value     = particle updates (active particles advanced) over the K steps / s
+roofline  = the dominant phase's algorithmic bytes per launch / its average
+            launch duration (HIP events on the context's stream over the
+            timed region), against the 8 TB/s HBM peak
+cpu_baseline = the FP64 oracle stepping a spatial window of the same snapshot
+            on the host cores
+
+Progress goes to stderr; one JSON line goes to stdout.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "envelope particle-updates/s @20M FP32 vs plain; batched & adjoint vs plain"
+CET_KNOBS = dict(dT0=12.0, lambda0=1e-6)
+TARGET_ACTIVE = 20_000_000
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit of each phase (what the method must move):
+#   advance  : read and write the 16-B record of each active particle
+#   scatter  : read a record, write it to its brick slot
+#   cellsort : read and write each record, one 8-B cell-table entry per record
+#   contain  : read each active record once (neighbours counted in their own tile)
+#   branch   : read and write the spawner's record, write one 16-B record per child
+#   resample : write one FP32 node value
+PHASE_BYTES = {"advance": 32, "scatter": 32, "cellsort": 40, "contain": 16, "branch": 32,
+               "resample": 4}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cet_workload():
+    from paper_2504_12858_amd import workloads as W
+    return W.cet(**CET_KNOBS)
+
+
+def make_context(w):
+    from paper_2504_12858_amd import binding as B
+    return B.Context.from_workload(w, cap_particles=1 << 26, cap_stopped=1 << 27,
+                                   cap_claim_bricks=1 << 24, cap_grains=4096)
+
+
+def advance_to_snapshot(ctx, w, target, max_steps=6000, chunk=50):
+    steps = 0
+    st = None
+    while steps < max_steps:
+        st = ctx.step(w.dt, chunk)
+        steps += chunk
+        log(f"[snapshot] step {steps} active {st['n_active']} stopped {st['n_stopped']} "
+            f"grains {st['n_grains']}")
+        if st["n_active"] >= target:
+            break
+    return steps, st
+
+
+def grain_quaternions(ctx, w):
+    """Centres and quaternions of the context's grains: every grain of the
+    CET workload comes from a fired site, identified by its FP32 centre."""
+    import numpy as np
+    rows = ctx.grains()
+    key = {tuple(np.float32(v) for v in xyz): i for i, xyz in enumerate(w.site_xyz)}
+    idx = np.array([key[tuple(r[:3])] for r in rows])
+    return w.site_xyz[idx], w.site_quat[idx]
+
+
+def cpu_baseline(ctx, w, budget_s=15.0, max_steps=8):
+    """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot."""
+    import numpy as np
+    from oracle import Oracle
+    from oracle import oracle as orc
+    lo = np.array([1.875e-3, 0.875e-3, 0.0])
+    hi = np.array([2.125e-3, 1.125e-3, 1.0e-3])
+    margin = 4 * w.lambda0
+    parts = ctx.particles(window=(lo, hi))
+    claims = ctx.claims(window=(lo - margin, hi + margin))
+    centre, quat = grain_quaternions(ctx, w)
+    o = Oracle.from_workload(w, init=False)
+    o.nucleate(w.site_xyz, w.site_dTn, w.site_quat)
+    st = ctx.counts()
+    o.load_state(centre, quat,
+                 dict(grain=parts["grain"], site=parts["site"], dir=parts["dir"],
+                      s=parts["s"].astype(np.float64), state=parts["state"]),
+                 dict(grain=claims["grain"], site=claims["site"], flags=claims["flags"]),
+                 ctx.site_states(), st["t"], st["step"])
+    n_act = int((parts["state"] == 0).sum())
+    log(f"[cpu] window {n_act} active, {len(parts) - n_act} stopped, {len(claims)} claims")
+    updates = 0
+    t0 = time.perf_counter()
+    k = 0
+    while k < max_steps:
+        o.step(w.dt, 1)
+        updates += o.last_stats()["advanced"]
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    log(f"[cpu] {k} oracle steps in {dt:.2f} s")
+    return {"value": updates / dt, "unit": "particle-updates/s", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {k} steps of the 0.25x0.25x1 mm column "
+                      f"x in [1.875,2.125] mm, y in [0.875,1.125] mm of the same snapshot "
+                      f"({n_act} active particles, {len(parts) - n_act} stopped, "
+                      f"{len(claims)} claimed sites)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--target", type=int, default=TARGET_ACTIVE)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = cet_workload()
+    t_build = time.perf_counter()
+    ctx = make_context(w)
+    snap_steps, st = advance_to_snapshot(ctx, w, args.target)
+    log(f"[snapshot] reached in {time.perf_counter() - t_build:.1f} s")
+    if args.warmup:
+        ctx.step(w.dt, args.warmup)
+    torch.cuda.synchronize()
+    ctx.profile(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = ctx.step(w.dt, args.steps)           # synchronises at the end
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases, n_prof = ctx.profile_read()
+    ctx.profile(0)
+    elapsed = t1 - t0
+    value = stats["advanced"] / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    log(f"[timed] {args.steps} steps {elapsed:.3f} s, {stats['advanced']} updates, "
+        f"active {stats['n_active']} stopped {stats['n_stopped']}")
+    for k, v in sorted(phases.items(), key=lambda kv: -kv[1]):
+        log(f"[phase] {k:9s} {v / max(n_prof, 1):8.3f} ms/step")
+    dom = max((k for k in phases if k in PHASE_BYTES), key=lambda k: phases[k])
+    avg_ms = phases[dom] / max(n_prof, 1)
+    units = stats["advanced"] / args.steps
+    if dom == "resample":
+        units = float(w.field.n[0] * w.field.n[1] * w.field.n[2])
+    elif dom == "branch":
+        units = stats["spawners"] / args.steps
+    achieved = PHASE_BYTES[dom] * units / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom, "bytes_per_unit": PHASE_BYTES[dom],
+                "units_per_launch": round(units), "avg_launch_ms": round(avg_ms, 4)}
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cet-moving-source-20M", "box_mm": [4, 2, 1],
+                   "lambda0_um": 1.0, "dT0_K": CET_KNOBS["dT0"], "grid": 256, "sites": 1600,
+                   "dt_s": w.dt, "snapshot_step": snap_steps,
+                   "active_at_snapshot": st["n_active"], "stopped_at_snapshot": st["n_stopped"],
+                   "active_after": stats["n_active"], "stopped_after": stats["n_stopped"]},
+        "phases_ms_per_step": {k: round(v / max(n_prof, 1), 4) for k, v in phases.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ctx, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

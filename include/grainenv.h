@@ -243,12 +243,26 @@ ge_status ge_step(ge_ctx* ctx, double dt, int32_t n_steps, ge_step_stats* stats)
 
 /* Exports part of the state into a caller-owned buffer (host or device).
    With out == NULL (or out_bytes too small) only *needed is set.  The call
-   synchronises when out is host memory. */
+   synchronises when out is host memory.  For PARTICLES and CLAIMS, non-null
+   args select a window: only particles (claimed sites) whose world position
+   lies in [origin, origin + n * spacing) are exported; with args == NULL
+   everything is.  GRAIN_MAP requires args. */
 ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args, void* out,
                             size_t out_bytes, size_t* needed);
 
 /* Replaces grains, particles, claims, site states, time and step. */
 ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
+
+/* Phase timing of ge_step with HIP events recorded on the context's stream
+   between the phases of every step (field resample, advance, branch, brick
+   scan, scatter, cell sort, containment, stop linking, nucleation, finish).
+   ge_profile(ctx, 1) starts recording and clears the totals; ge_profile(ctx, 0)
+   stops.  ge_profile_read synchronises and returns, per phase, the summed
+   GPU time in milliseconds and the number of steps recorded. */
+#define GE_N_PHASES 10
+ge_status ge_profile(ge_ctx* ctx, int32_t on);
+ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);
+const char* ge_phase_name(int32_t phase);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,10 @@
 //      >= 0 (the octant rule), whose target S + step(d') is not yet claimed by
 //      the grain.  Same-step competitors for one target: the lowest d' wins
 //      (competitors always differ in d').  Overshoot s - lambda0 is carried
-//      into the children.  A parent with >= 1 child retires, else it stops.
+//      into the children.  The parent always retires: with no surviving child
+//      every outer neighbour of S already belongs to the grain, so S is inside
+//      the envelope, and the stored point cloud keeps only envelope points
+//      (shell-like cloud, Sec. 2.3).
 //   R4 two particles of different grains "meet" when their distance is < rc.
 //      Decisions are collected first and applied together (Jacobi).
 //   R5 a particle leaving the box [lo, hi) stops.
@@ -52,6 +55,9 @@
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -487,7 +493,7 @@ void phase_branch(Oracle& o) {
   for (size_t k = 0; k < spawners.size(); ++k) {
     Particle& q = o.parts[spawners[k]];
     add_claim(o.claims[q.g], S[k].data(), C_REACHED);
-    q.state = nchild[k] > 0 ? P_RETIRED : P_STOPPED;
+    q.state = P_RETIRED;
   }
   o.last.spawners = (int64_t)spawners.size();
   o.last.children = (int64_t)born.size();
@@ -789,6 +795,14 @@ void orc_last_stats(void* h, int64_t out[6], double* max_step) {
 }
 
 double orc_time(void* h) { return ((Oracle*)h)->t; }
+
+int32_t orc_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void orc_get_particles(void* h, int32_t* grain, int32_t* site, int32_t* dir, double* s, double* x,
                        int32_t* state) {

@@ -68,6 +68,8 @@ def _load():
     lib.orc_count.argtypes = [vp, C.c_int32]
     lib.orc_count.restype = C.c_int64
     lib.orc_last_stats.argtypes = [vp, P(np.int64), C.POINTER(C.c_double)]
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = C.c_int32
     lib.orc_time.argtypes = [vp]
     lib.orc_time.restype = C.c_double
     lib.orc_get_particles.argtypes = [vp, P(np.int32), P(np.int32), P(np.int32), P(np.float64),
@@ -297,6 +299,10 @@ class Oracle:
         if rc != 0:
             raise ValueError(rc)
         return g
+
+
+def threads():
+    return _load().orc_threads()
 
 
 def f32_cells(xyz, lo, inv_h, ncell):

@@ -104,6 +104,9 @@ def load_library(path: str = LIB_PATH):
         "ge_query_envelope": ([vp, C.c_int32, P(ge_query_args), vp, C.c_size_t,
                                P(C.c_size_t)], C.c_int32),
         "ge_load_state": ([vp, P(ge_state_in)], C.c_int32),
+        "ge_profile": ([vp, C.c_int32], C.c_int32),
+        "ge_profile_read": ([vp, P(C.c_double), P(C.c_int64)], C.c_int32),
+        "ge_phase_name": ([C.c_int32], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -115,7 +118,9 @@ def load_library(path: str = LIB_PATH):
 
 EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy",
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_nucleate", "ge_step",
-            "ge_query_envelope", "ge_load_state")
+            "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
+            "ge_phase_name")
+N_PHASES = 10
 
 
 def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,
@@ -293,6 +298,16 @@ class Context:
         st.t, st.step = float(t), int(step)
         self._check(self.lib.ge_load_state(self.ctx, C.byref(st)), "ge_load_state")
 
+    def profile(self, on):
+        self._check(self.lib.ge_profile(self.ctx, int(on)), "ge_profile")
+
+    def profile_read(self):
+        ms = (C.c_double * N_PHASES)()
+        steps = C.c_int64()
+        self._check(self.lib.ge_profile_read(self.ctx, ms, C.byref(steps)), "ge_profile_read")
+        names = [self.lib.ge_phase_name(k).decode() for k in range(N_PHASES)]
+        return dict(zip(names, list(ms))), steps.value
+
     # ---------------------------------------------------------- helpers ---
     def counts(self):
         st = ge_step_stats()
@@ -301,18 +316,32 @@ class Context:
         C.memmove(C.addressof(st), buf.ctypes.data, C.sizeof(st))
         return st.as_dict()
 
-    def particles(self) -> np.ndarray:
-        need = self.query_envelope(QUERY_PARTICLES)
+    @staticmethod
+    def _window(window):
+        if window is None:
+            return None
+        lo, hi = window
+        a = ge_query_args()
+        a.n[:] = [1, 1, 1]
+        a.origin[:] = [float(v) for v in lo]
+        a.spacing[:] = [float(h - l) for l, h in zip(lo, hi)]
+        return a
+
+    def particles(self, window=None) -> np.ndarray:
+        """Active and stopped particles; window = (lo, hi) restricts to a box."""
+        a = self._window(window)
+        need = self.query_envelope(QUERY_PARTICLES, args=a)
         out = np.zeros(need // PARTICLE_DTYPE.itemsize, PARTICLE_DTYPE)
         if need:
-            self.query_envelope(QUERY_PARTICLES, out)
+            self.query_envelope(QUERY_PARTICLES, out, args=a)
         return out
 
-    def claims(self) -> np.ndarray:
-        need = self.query_envelope(QUERY_CLAIMS)
+    def claims(self, window=None) -> np.ndarray:
+        a = self._window(window)
+        need = self.query_envelope(QUERY_CLAIMS, args=a)
         out = np.zeros(need // CLAIM_DTYPE.itemsize, CLAIM_DTYPE)
         if need:
-            self.query_envelope(QUERY_CLAIMS, out)
+            self.query_envelope(QUERY_CLAIMS, out, args=a)
         return out
 
     def site_states(self) -> np.ndarray:

@@ -136,9 +136,9 @@ void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);
 void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
                        const uint8_t* flags, uint32_t n, hipStream_t s);
 void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
-                             hipStream_t s);
+                             const float* window /* lo xyz, hi xyz or null */, hipStream_t s);
 void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
-                          hipStream_t s);
+                          const float* window, hipStream_t s);
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s);
 void launch_clear_ctab(const Dev& d, uint64_t n_cells, hipStream_t s);

@@ -529,13 +529,10 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
       if (!lose) mask |= 1u << dd;
     }
     const float* G = D.gtab + (size_t)g * GT_STRIDE;
-    if (mask == 0u) {
-      r = with_fl(r, ST_STOPPED | FL_SPAWN);
-      D.A[i] = r;
-      const uint32_t j = atomicAdd(&D.cnt->n_stopped, 1u);
-      stopped_put(D, j, with_fl(r, ST_STOPPED));
-    } else {
-      D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
+    // The parent retires whether or not a child survives: without one, every
+    // outer neighbour of S already belongs to the grain (interior point).
+    D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
+    {
       const float sc = s2 - D.lambda0;
       for (int dd = 0; dd < 6; ++dd) {
         if (!(mask & (1u << dd))) continue;
@@ -1121,8 +1118,18 @@ __device__ __forceinline__ void put_particle(const Dev& D, uint4 r, uint32_t sta
   *o = v;
 }
 
+struct Window {
+  float lo[3], hi[3];
+  int32_t on;
+};
+
+__device__ __forceinline__ bool in_window(const Window& w, P3 p) {
+  return !w.on || (p.x >= w.lo[0] && p.x < w.hi[0] && p.y >= w.lo[1] && p.y < w.hi[1] &&
+                   p.z >= w.lo[2] && p.z < w.hi[2]);
+}
+
 __global__ __launch_bounds__(TPB) void k_export_particles(Dev D, uint32_t* counter, PartOut* out,
-                                                          uint32_t cap_out) {
+                                                          uint32_t cap_out, Window win) {
   const uint32_t na = D.cnt->n_active, ns = min(D.cnt->n_stopped, D.cap_s);
   for (uint32_t k0 = blockIdx.x * TPB; k0 < na + ns; k0 += gridDim.x * TPB) {
     const uint32_t k = k0 + threadIdx.x;
@@ -1137,6 +1144,7 @@ __global__ __launch_bounds__(TPB) void k_export_particles(Dev D, uint32_t* count
       take = true;
       st = ST_STOPPED;
     }
+    if (take && win.on) take = in_window(win, rec_pos(D, r));
     const uint32_t j = wave_append(take, counter);
     if (take && j < cap_out) put_particle(D, r, st, out + j);
   }
@@ -1150,7 +1158,7 @@ struct ClaimOut {
 static_assert(sizeof(ClaimOut) == 20, "claim record layout");
 
 __global__ __launch_bounds__(TPB) void k_export_claims(Dev D, uint32_t* counter, ClaimOut* out,
-                                                       uint32_t cap_out) {
+                                                       uint32_t cap_out, Window win) {
   const uint64_t slots = D.cmask + 1;
   for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < slots * 8;
        v += (uint64_t)gridDim.x * TPB) {
@@ -1166,6 +1174,20 @@ __global__ __launch_bounds__(TPB) void k_export_claims(Dev D, uint32_t* counter,
     const int bx = (int)((key >> 24) & 0xFFFull) - 2048;
     const int by = (int)((key >> 12) & 0xFFFull) - 2048;
     const int bz = (int)(key & 0xFFFull) - 2048;
+    if (win.on) {
+      const float* G = D.gtab + (size_t)g * GT_STRIDE;
+      unsigned long long keep = 0;
+      unsigned long long m = any;
+      while (m) {
+        const int bit = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const P3 p = lattice_pos(G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + (int)w,
+                                 0, 0.0f);
+        if (in_window(win, p)) keep |= 1ull << bit;
+      }
+      any = keep;
+      if (!any) continue;
+    }
     const uint32_t base = atomicAdd(counter, (uint32_t)__popcll(any));
     uint32_t k = 0;
     while (any) {
@@ -1304,13 +1326,22 @@ void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
   if (n == 0) return;
   k_claim_list<<<grid_for(n, 8192), TPB, 0, s>>>(d, grain, site, flags, n);
 }
+static Window make_window(const float* win) {
+  Window w;
+  w.on = win ? 1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    w.lo[a] = win ? win[a] : 0.0f;
+    w.hi[a] = win ? win[3 + a] : 0.0f;
+  }
+  return w;
+}
 void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
-                             hipStream_t s) {
-  k_export_particles<<<1024, TPB, 0, s>>>(d, counter, (PartOut*)out, cap_out);
+                             const float* win, hipStream_t s) {
+  k_export_particles<<<1024, TPB, 0, s>>>(d, counter, (PartOut*)out, cap_out, make_window(win));
 }
 void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
-                          hipStream_t s) {
-  k_export_claims<<<4096, TPB, 0, s>>>(d, counter, (ClaimOut*)out, cap_out);
+                          const float* win, hipStream_t s) {
+  k_export_claims<<<4096, TPB, 0, s>>>(d, counter, (ClaimOut*)out, cap_out, make_window(win));
 }
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s) {

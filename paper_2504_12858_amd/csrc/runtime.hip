@@ -169,7 +169,49 @@ struct ge_ctx {
   uint32_t n_sites;
   bool dead;
   std::string err;
+  // phase timing
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;   // GE_N_PHASES + 1 events per recorded step
+  size_t ev_used = 0;                // events recorded since the last read
+  double prof_ms[GE_N_PHASES] = {0};
+  int64_t prof_steps = 0;
 };
+
+static const char* PHASE_NAMES[GE_N_PHASES] = {"resample", "advance",  "branch", "scan",
+                                               "scatter",  "cellsort", "contain", "stoplink",
+                                               "nucleate", "finish"};
+
+// Records the event that closes phase `k` of the current step (k = -1 opens
+// the step).
+static void prof_mark(ge_ctx* c, int k) {
+  if (!c->prof_on) return;
+  (void)k;
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      c->prof_on = false;
+      return;
+    }
+    c->ev_pool.push_back(e);
+  }
+  (void)hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
+}
+
+static void prof_collect(ge_ctx* c) {
+  if (c->ev_used == 0) return;
+  (void)hipStreamSynchronize(c->stream);
+  const size_t per = GE_N_PHASES + 1;
+  const size_t steps = c->ev_used / per;
+  for (size_t st = 0; st < steps; ++st)
+    for (int k = 0; k < GE_N_PHASES; ++k) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, c->ev_pool[st * per + k], c->ev_pool[st * per + k + 1]) ==
+          hipSuccess)
+        c->prof_ms[k] += ms;
+    }
+  c->prof_steps += (int64_t)steps;
+  c->ev_used = 0;
+}
 
 static ge_status fail(ge_ctx* c, ge_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -340,6 +382,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
 ge_status ge_destroy(ge_ctx* c) {
   if (!c) return GE_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   (void)hipHostFree(c->host_cnt);
   delete c;
   return GE_OK;
@@ -523,6 +566,8 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
   Dev& d = c->d;
   ge::launch_reset_stats(d, s);
   for (int32_t k = 0; k < n_steps; ++k) {
+    if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
+    prof_mark(c, -1);
     c->epoch += 1;
     if (c->epoch > 0xFFFFFFu) {
       ge::launch_clear_ctab(d, c->geo.n_cells, s);
@@ -537,15 +582,25 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
                           f.zs, f.r_min, f.dT_min, f.origin[0], f.origin[1], f.origin[2],
                           f.spacing[0], f.spacing[1], f.spacing[2], t, s);
     }
+    prof_mark(c, 0);
     ge::launch_advance(d, lin_c, (float)dt, s);
+    prof_mark(c, 1);
     ge::launch_branch(d, s);
+    prof_mark(c, 2);
     ge::launch_scan(d, s);
+    prof_mark(c, 3);
     ge::launch_scatter(d, s);
+    prof_mark(c, 4);
     ge::launch_cellsort(d, c->epoch, s);
+    prof_mark(c, 5);
     ge::launch_contain(d, c->epoch, s);
+    prof_mark(c, 6);
     ge::launch_stoplink(d, s);
+    prof_mark(c, 7);
     ge::launch_nucleate(d, lin_c, c->epoch, s);
+    prof_mark(c, 8);
     ge::launch_finish(d, s);
+    prof_mark(c, 9);
     c->t = t + dt;
     c->step += 1;
   }
@@ -594,11 +649,20 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
     case GE_QUERY_CLAIMS: {
       const bool parts = kind == GE_QUERY_PARTICLES;
       const size_t rec = parts ? sizeof(ge_particle_rec) : sizeof(ge_claim_rec);
+      float winbuf[6];
+      const float* win = nullptr;
+      if (args) {
+        for (int a = 0; a < 3; ++a) {
+          winbuf[a] = (float)args->origin[a];
+          winbuf[3 + a] = (float)(args->origin[a] + args->n[a] * args->spacing[a]);
+        }
+        win = winbuf;
+      }
       uint32_t* counter = nullptr;
       HIPCHK(c, hipMalloc((void**)&counter, 4));
       HIPCHK(c, hipMemsetAsync(counter, 0, 4, s));
-      if (parts) ge::launch_export_particles(c->d, counter, nullptr, 0, s);
-      else ge::launch_export_claims(c->d, counter, nullptr, 0, s);
+      if (parts) ge::launch_export_particles(c->d, counter, nullptr, 0, win, s);
+      else ge::launch_export_claims(c->d, counter, nullptr, 0, win, s);
       uint32_t count = 0;
       HIPCHK(c, hipMemcpyAsync(&count, counter, 4, hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipStreamSynchronize(s));
@@ -611,8 +675,8 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
       void* stage = nullptr;
       HIPCHK(c, hipMalloc(&stage, need));
       HIPCHK(c, hipMemsetAsync(counter, 0, 4, s));
-      if (parts) ge::launch_export_particles(c->d, counter, stage, count, s);
-      else ge::launch_export_claims(c->d, counter, stage, count, s);
+      if (parts) ge::launch_export_particles(c->d, counter, stage, count, win, s);
+      else ge::launch_export_claims(c->d, counter, stage, count, win, s);
       HIPCHK(c, hipGetLastError());
       st = deliver(c, stage, out, need);
       (void)hipFree(stage);
@@ -657,6 +721,32 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
     default:
       return fail(c, GE_EINVAL, "unknown query kind");
   }
+}
+
+ge_status ge_profile(ge_ctx* c, int32_t on) {
+  if (!c) return GE_EINVAL;
+  if (on) {
+    prof_collect(c);
+    for (double& v : c->prof_ms) v = 0;
+    c->prof_steps = 0;
+    c->prof_on = true;
+  } else {
+    prof_collect(c);
+    c->prof_on = false;
+  }
+  return GE_OK;
+}
+
+ge_status ge_profile_read(ge_ctx* c, double* ms, int64_t* steps) {
+  if (!c || !ms) return GE_EINVAL;
+  prof_collect(c);
+  for (int k = 0; k < GE_N_PHASES; ++k) ms[k] = c->prof_ms[k];
+  if (steps) *steps = c->prof_steps;
+  return GE_OK;
+}
+
+const char* ge_phase_name(int32_t k) {
+  return (k >= 0 && k < GE_N_PHASES) ? PHASE_NAMES[k] : "";
 }
 
 ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
