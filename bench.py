@@ -3,7 +3,7 @@
 
 Workload: columnar-to-equiaxed transition under a moving Rosenthal source
 (4 x 2 x 1 mm box, 256^3 FP32 undercooling grid resampled every step, 800
-face and 800 bulk nuclei, lambda0 = h = rc = 1 um, dT0 = 12 K), advanced
+face and 800 bulk nuclei, lambda0 = rc = 1 um, cells of h = 2 um, dT0 = 12 K), advanced
 untimed from t = 0 to the first step with >= 20M active particles.  Then W
 warm-up steps and K timed steps, bracketed by stream synchronisations.
 
@@ -27,19 +27,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "envelope particle-updates/s @20M FP32 vs plain; batched & adjoint vs plain"
-CET_KNOBS = dict(dT0=12.0, lambda0=1e-6)
+CET_KNOBS = dict(dT0=12.0, lambda0=1e-6, h=2e-6)
 TARGET_ACTIVE = 20_000_000
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per unit of each phase (what the method must move):
 #   advance  : read and write the 16-B record of each active particle
-#   scatter  : read a record, write it to its brick slot
-#   cellsort : read and write each record, one 8-B cell-table entry per record
-#   contain  : read each active record once (neighbours counted in their own tile)
-#   branch   : read and write the spawner's record, write one 16-B record per child
+#   scatter  : read a record, write it and its 16-B position to their cell slot
+#   contain  : read each active position once (neighbours counted in their own cell)
+#   branch   : read and write the spawner's record
+#   resort   : read and write record and position of each stopped particle
 #   resample : write one FP32 node value
-PHASE_BYTES = {"advance": 32, "scatter": 32, "cellsort": 40, "contain": 16, "branch": 32,
-               "resample": 4}
+PHASE_BYTES = {"advance": 32, "scatter": 48, "contain": 16, "branch": 32, "resample": 4}
 
 
 def log(*a):
@@ -154,7 +153,9 @@ def main():
     value = stats["advanced"] / elapsed
     ms_step = 1e3 * elapsed / args.steps
     log(f"[timed] {args.steps} steps {elapsed:.3f} s, {stats['advanced']} updates, "
-        f"active {stats['n_active']} stopped {stats['n_stopped']}")
+        f"active {stats['n_active']} stopped {stats['n_stopped']} spawners "
+        f"{stats['spawners']} children {stats['children']} contained {stats['contained']} "
+        f"pair tests {stats['pair_tests']}")
     for k, v in sorted(phases.items(), key=lambda kv: -kv[1]):
         log(f"[phase] {k:9s} {v / max(n_prof, 1):8.3f} ms/step")
     dom = max((k for k in phases if k in PHASE_BYTES), key=lambda k: phases[k])
@@ -175,7 +176,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "cet-moving-source-20M", "box_mm": [4, 2, 1],
-                   "lambda0_um": 1.0, "dT0_K": CET_KNOBS["dT0"], "grid": 256, "sites": 1600,
+                   "lambda0_um": 1.0, "h_um": 2.0, "dT0_K": CET_KNOBS["dT0"], "grid": 256,
+                   "sites": 1600,
                    "dt_s": w.dt, "snapshot_step": snap_steps,
                    "active_at_snapshot": st["n_active"], "stopped_at_snapshot": st["n_stopped"],
                    "active_after": stats["n_active"], "stopped_after": stats["n_stopped"]},

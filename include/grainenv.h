@@ -76,10 +76,12 @@ typedef int32_t ge_status;
  * polynomial path, any other exponents the power path.
  *
  * Geometry: the box is [lo, hi); the cell list has cells of edge h covering
- * it (ceil((hi - lo) / h) per axis), grouped in bricks of 8^3 cells.  The
- * contact radius rc must satisfy rc <= h (the 27-cell stencil is then
- * complete) and rc <= lambda0.  Lattice sites must stay within +-16383 of a
- * grain's centre: (box diagonal) / lambda0 < 16383.
+ * it (ceil((hi - lo) / h) per axis), grouped in bricks of 4^3 cells.  The
+ * contact radius rc must satisfy rc <= h and rc <= lambda0; with rc <= h/2
+ * the containment test visits 2^3 cells per particle, otherwise 3^3.
+ * Lattice sites must stay within +-16000 of a grain's centre:
+ * (box diagonal) / lambda0 < 16000.  Dense per-cell tables take 16 bytes per
+ * cell (padded to whole bricks).
  */
 typedef struct ge_params {
   double lo[3], hi[3];   /* box [m] */
@@ -97,6 +99,7 @@ typedef struct ge_params {
   int64_t cap_claim_bricks; /* slots of the claim hash (rounded up to a power of two);
                                each slot holds 8^3 lattice sites of one grain */
   int32_t field_n[3];    /* largest field grid the context will hold (nodes per axis) */
+  int32_t resort_every;  /* steps between re-sorts of the stopped store by cell (0: 16) */
 } ge_params;
 
 /* Thermal field (Sec. 2.3 interpolation; Sec. 3.1 / 3.4 imposed fields). */
@@ -131,6 +134,7 @@ typedef struct ge_step_stats {
   double max_step;    /* largest v dt of the call [m] */
   double t;           /* time after the call [s] */
   int64_t step;       /* steps taken since creation or the last state load */
+  int64_t pair_tests; /* candidate particles examined by the containment test */
 } ge_step_stats;
 
 /* Query kinds of ge_query_envelope. */
@@ -254,11 +258,12 @@ ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args
 ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
 
 /* Phase timing of ge_step with HIP events recorded on the context's stream
-   between the phases of every step (field resample, advance, branch, brick
-   scan, scatter, cell sort, containment, stop linking, nucleation, finish).
+   between the phases of every step.
    ge_profile(ctx, 1) starts recording and clears the totals; ge_profile(ctx, 0)
    stops.  ge_profile_read synchronises and returns, per phase, the summed
-   GPU time in milliseconds and the number of steps recorded. */
+   GPU time in milliseconds and the number of steps recorded.  Phases: field
+   resample, advance, branch, brick and cell scan, scatter, containment,
+   stop linking, nucleation, finish, stopped-store re-sort. */
 #define GE_N_PHASES 10
 ge_status ge_profile(ge_ctx* ctx, int32_t on);
 ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);

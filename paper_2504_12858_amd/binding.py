@@ -41,7 +41,8 @@ class ge_params(C.Structure):
                 ("b", C.c_double * 2), ("theta", C.c_double), ("branching", C.c_int32),
                 ("box_exit", C.c_int32), ("cap_particles", C.c_int64),
                 ("cap_stopped", C.c_int64), ("cap_grains", C.c_int32), ("cap_sites", C.c_int32),
-                ("cap_claim_bricks", C.c_int64), ("field_n", C.c_int32 * 3)]
+                ("cap_claim_bricks", C.c_int64), ("field_n", C.c_int32 * 3),
+                ("resort_every", C.c_int32)]
 
 
 class ge_field(C.Structure):
@@ -59,7 +60,7 @@ class ge_step_stats(C.Structure):
                 ("n_claim_bricks", C.c_int64), ("advanced", C.c_int64), ("exited", C.c_int64),
                 ("spawners", C.c_int64), ("children", C.c_int64), ("contained", C.c_int64),
                 ("nucleated", C.c_int64), ("max_step", C.c_double), ("t", C.c_double),
-                ("step", C.c_int64)]
+                ("step", C.c_int64), ("pair_tests", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -125,7 +126,8 @@ N_PHASES = 10
 
 def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,
                 cap_particles=1 << 20, cap_stopped=1 << 20, cap_grains=1 << 12,
-                cap_sites=1 << 12, cap_claim_bricks=1 << 16, field_n=(0, 0, 0)) -> ge_params:
+                cap_sites=1 << 12, cap_claim_bricks=1 << 16, field_n=(0, 0, 0),
+                resort_every=0) -> ge_params:
     p = ge_params()
     p.lo[:] = [float(v) for v in lo]
     p.hi[:] = [float(v) for v in hi]
@@ -138,6 +140,7 @@ def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1
     p.cap_grains, p.cap_sites = int(cap_grains), int(cap_sites)
     p.cap_claim_bricks = int(cap_claim_bricks)
     p.field_n[:] = [int(v) for v in field_n]
+    p.resort_every = int(resort_every)
     return p
 
 

@@ -29,10 +29,15 @@ enum : uint32_t { ERR_CAPACITY = 1, ERR_NUMERIC = 2, ERR_CFL = 4 };
 //   [4..12] R row-major (crystal -> world), [13..21] lambda0 * R, [22..23] spare.
 constexpr int GT_STRIDE = 24;
 
-// Cells per brick edge (bricks of 8^3 cells) and the largest brick the
-// in-LDS cell sort takes.
-constexpr int BRICK = 8;
-constexpr int CS_CAP = 2048;
+// Cells are grouped in bricks of 4^3; cell storage is brick-major
+// (cell index = brick * 64 + local index), so a brick's 64 cells are
+// contiguous and one wave64 lane serves one cell of a brick.
+constexpr int BRICK = 4;
+constexpr int BRICK_CELLS = 64;
+
+// Streaming kernels run on a fixed grid; per-block lists (spawners, newly
+// stopped particles) live in the block's own region of a particle-sized array.
+constexpr int STREAM_GRID = 2048;
 
 // Claim hash: 8^3 lattice sites per slot, three 512-bit masks per slot
 // (claimed as target, reached, reached during the current step).
@@ -44,11 +49,11 @@ enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3 };
 
 struct Counters {
   uint32_t n_active;   // records in A (sorted region + nucleated tail)
-  uint32_t n_spawn;    // spawner list length this step
-  uint32_t n_out;      // records after scatter = sorted region of A
+  uint32_t n_out;      // records written by the scatter = sorted region of B
   uint32_t n_occ;      // occupied bricks this step
   uint32_t n_stopped;  // stopped store length
-  uint32_t n_newstop;  // particles stopped by containment this step
+  uint32_t n_sorted;   // cell-sorted prefix of the stopped store
+  uint32_t n_socc;     // bricks holding sorted stopped particles
   uint32_t n_grains;
   uint32_t claim_used; // occupied claim slots
   uint32_t err;        // sticky error bits
@@ -56,8 +61,9 @@ struct Counters {
   uint32_t max_step;   // float bits of max v dt (non-negative floats order as uints)
   uint32_t n_fired;    // sites fired this step
   uint32_t n_live;     // active particles (A also holds records stopped at the end of a step)
-  uint32_t pad0;
+  uint32_t n_newstop;  // particles stopped by containment this step
   unsigned long long advanced, exited, spawners, children, contained, nucleated;
+  unsigned long long pair_tests;  // candidate particles examined by containment
 };
 
 // Everything a kernel needs, passed by value.
@@ -65,9 +71,10 @@ struct Dev {
   // geometry
   float lo[3], hi[3];
   float inv_h;
-  int32_t n[3];    // cells per axis
-  int32_t nb[3];   // bricks per axis
+  int32_t n[3];      // cells per axis
+  int32_t nb[3];     // bricks per axis
   uint32_t n_bricks;
+  int32_t stencil8;  // rc <= h/2: 2x2x2 cell stencil, else 3x3x3
   float lambda0, rc2, rc_half;
   float ka[2], kb[2];
   int32_t kin_poly;
@@ -83,23 +90,35 @@ struct Dev {
   float* gtab;     // [cap_grains][GT_STRIDE]
   int32_t* gbox;   // [cap_grains][6] lattice bbox of claims: lo xyz, hi xyz
   uint32_t cap_grains;
-  // active store (ping-pong) and per-step lists
+  // active store: A is this step's input, B its cell-sorted output, P the
+  // positions (xyz, grain bits) of B
   uint4* A;
   uint4* B;
+  float4* P;
   uint32_t cap_p;
-  uint32_t* spawn;     // [cap_p]
-  uint32_t* newstop;   // [cap_p]
-  // stopped store with linked cell lists
+  uint32_t* spawn;        // [cap_p], per-block regions
+  uint32_t* spawn_cnt;    // [STREAM_GRID]
+  uint32_t* newstop;      // [cap_p], per-block regions
+  uint32_t* newstop_cnt;  // [STREAM_GRID]
+  // stopped store: records S, positions PS; [0, n_sorted) cell-sorted
+  // (sstart, bsinfo), the rest in linked cell lists (shead, snext)
   uint4* S;
+  float4* PS;
+  uint4* S2;
+  float4* PS2;
   uint32_t* snext;
   uint32_t cap_s;
   uint32_t* shead;     // [cells]
-  uint2* sbsum;        // [bricks] stopped grain min / max
-  // bricks and cells
-  uint32_t* bcnt;      // [bricks]
+  uint32_t* sstart;    // [cells]
+  uint2* bsinfo;       // [bricks] start, count of the sorted stopped particles
+  uint2* sbsum;        // [bricks] grain min / max of all stopped particles
+  // per-step cell list of the active particles
+  uint32_t* ccnt;      // [cells] counts, back to zero after the scatter
+  uint32_t* cstart;    // [cells]
+  uint32_t* bcnt;      // [bricks] counts, reset by the scan
   uint4* binfo;        // [bricks] start, count, grain min, grain max
-  uint32_t* occ;       // [bricks]
-  unsigned long long* ctab;  // [cells] start | (count | epoch << 8) << 32
+  uint32_t* bepoch;    // [bricks] step at which binfo was written
+  uint32_t* occ;       // [bricks] occupied-brick list
   uint64_t* scan_tmp;  // block partial sums of the brick scan
   // claims
   unsigned long long* ckeys;   // [slots]
@@ -118,19 +137,19 @@ struct Dev {
 // -------------------------------------------------- host-side launchers --
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s);
 void launch_branch(const Dev& d, hipStream_t s);
-void launch_scan(const Dev& d, hipStream_t s);
+void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s);
 void launch_scatter(const Dev& d, hipStream_t s);
-void launch_cellsort(const Dev& d, uint32_t epoch, hipStream_t s);
 void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s);
 void launch_stoplink(const Dev& d, hipStream_t s);
 void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s);
 void launch_finish(const Dev& d, hipStream_t s);
 void launch_reset_stats(const Dev& d, hipStream_t s);
+void launch_stopped_rebuild(const Dev& d, hipStream_t s);  // S -> S2 (caller swaps)
 void launch_resample(const Dev& d, double dT0, const double grad[3], double rate, double q,
                      double U, double alpha, double x_start, double x_end, double ys, double zs,
                      double r_min, double dT_min, double ox, double oy, double oz, double sx,
                      double sy, double sz, double t, hipStream_t s);
-void launch_init_workspace(const Dev& d, uint64_t n_cells, hipStream_t s);
+void launch_init_workspace(const Dev& d, hipStream_t s);
 void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s);
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);
 void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
@@ -141,6 +160,6 @@ void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t c
                           const float* window, hipStream_t s);
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s);
-void launch_clear_ctab(const Dev& d, uint64_t n_cells, hipStream_t s);
+void launch_clear_bepoch(const Dev& d, hipStream_t s);
 
 }  // namespace ge

@@ -2,22 +2,29 @@
 //
 // One step (Sec. 2.1.2 growth and branching, Sec. 2.3 cell partitioning and
 // collision detection, Sec. 2.1.1 nucleation) runs as:
-//   k_advance   undercooling at each active particle, kinetic law Eq. (2),
-//               advance along R e_d, box exit, spawner detection, brick counts
-//   k_branch    outer directions of each spawner against the grain's claims,
-//               same-step competitors resolved by lowest direction
-//   k_scan_*    exclusive scan of brick counts -> brick starts, occupied list
-//   k_scatter   records -> brick-ordered store (wave-aggregated ranks)
-//   k_cellsort  per occupied brick, an LDS counting sort by cell with an
-//               identity tie-break; writes the dense cell table
-//   k_contain   27-cell stencil test against other grains' particles
-//   k_stoplink  moves newly stopped particles to the stopped store
+//   k_advance    undercooling at each active particle, kinetic law Eq. (2),
+//                advance along R e_d, box exit, spawner list, per-cell and
+//                per-brick counts of the particles that stay active
+//   k_mark_now   marks each spawner's reached site for this step
+//   k_branch     outer directions of each spawner against the grain's claims;
+//                same-step competitors for one target resolved by lowest
+//                direction; counts of the children
+//   k_scan_*     exclusive scan of brick counts -> brick starts, occupied list
+//   k_cellscan   one wave per occupied brick, one lane per cell: cell starts
+//   k_scatter    records and positions -> cell-sorted arrays (ranks from
+//                wave-aggregated decrements of the cell counts)
+//   k_contain    cell-stencil test against other grains' particles
+//   k_stoplink   moves newly stopped particles to the stopped store
 //   k_nuc_test / k_nuc_fire   nucleation of liquid sites past threshold
-//   k_finish    counters for the next step
+//   k_finish     counters for the next step
+// Every few steps the stopped store is re-sorted by cell with the same
+// counting machinery (k_srb_*), so that containment reads it as contiguous
+// cell ranges; particles stopped since the last re-sort sit in short linked
+// cell lists.
 //
-// Particle positions are never stored: every kernel recomputes them from the
-// record (grain, departure site, direction, travel) with the same function, so
-// binning, containment and export see identical FP32 values.
+// Particle positions are recomputed from the record (grain, departure site,
+// direction, travel) with one function everywhere, so binning, containment
+// and export see identical FP32 values.
 #include "internal.h"
 
 #include <math.h>
@@ -25,7 +32,6 @@
 namespace ge {
 
 constexpr int TPB = 256;
-constexpr int STREAM_GRID = 2048;  // 8 blocks per CU on 256 CUs
 
 enum : int { CB_CLAIMED = 0, CB_REACHED = 8, CB_NOW = 16 };
 enum : uint32_t { M_CLAIMED = 1, M_REACHED = 2, M_NOW = 4 };
@@ -95,23 +101,49 @@ __device__ __forceinline__ C3 cell_of(const Dev& D, P3 p) {
   return c;
 }
 
-__device__ __forceinline__ uint64_t cell_index(const Dev& D, int cx, int cy, int cz) {
-  return ((uint64_t)cz * (uint64_t)D.n[1] + (uint64_t)cy) * (uint64_t)D.n[0] + (uint64_t)cx;
-}
-
 __device__ __forceinline__ uint32_t brick_index(const Dev& D, int cx, int cy, int cz) {
-  return ((uint32_t)(cz >> 3) * (uint32_t)D.nb[1] + (uint32_t)(cy >> 3)) * (uint32_t)D.nb[0] +
-         (uint32_t)(cx >> 3);
+  return ((uint32_t)(cz >> 2) * (uint32_t)D.nb[1] + (uint32_t)(cy >> 2)) * (uint32_t)D.nb[0] +
+         (uint32_t)(cx >> 2);
 }
 
-__device__ __forceinline__ uint32_t brick_of(const Dev& D, P3 p) {
-  C3 c = cell_of(D, p);
-  return brick_index(D, c.x, c.y, c.z);
+__device__ __forceinline__ uint32_t local_index(int cx, int cy, int cz) {
+  return (uint32_t)((cx & 3) | ((cy & 3) << 2) | ((cz & 3) << 4));
+}
+
+// Brick-major cell index: the 64 cells of a brick are contiguous.
+__device__ __forceinline__ uint32_t cell_index(const Dev& D, int cx, int cy, int cz) {
+  return brick_index(D, cx, cy, cz) * (uint32_t)BRICK_CELLS + local_index(cx, cy, cz);
 }
 
 __device__ __forceinline__ float dist2(P3 a, P3 b) {
   float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
   return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ P3 p3_of(float4 q) { return P3{q.x, q.y, q.z}; }
+__device__ __forceinline__ uint32_t grain_of(float4 q) { return __float_as_uint(q.w); }
+__device__ __forceinline__ float4 pos4(P3 p, uint32_t g) {
+  return make_float4(p.x, p.y, p.z, __uint_as_float(g));
+}
+
+// Cells that can hold a particle within rc of p along one axis: with
+// rc <= h/2 the cell of p and its neighbour on the side of the nearer face,
+// otherwise the cell and both neighbours; clamped to the grid.
+__device__ __forceinline__ void stencil_axis(const Dev& D, float x, int a, int& c0, int& c1) {
+  const int n = D.n[a];
+  const float u = (x - D.lo[a]) * D.inv_h;
+  const float fl = floorf(u);
+  const int c = (int)fminf(fmaxf(fl, 0.0f), (float)(n - 1));
+  if (D.stencil8) {
+    const bool up = (u - fl) >= 0.5f;
+    c0 = up ? c : c - 1;
+    c1 = up ? c + 1 : c;
+  } else {
+    c0 = c - 1;
+    c1 = c + 1;
+  }
+  c0 = max(c0, 0);
+  c1 = min(c1, n - 1);
 }
 
 // ---------------------------------------------------------------- field ---
@@ -258,14 +290,19 @@ __device__ __forceinline__ bool claim_test(const Dev& D, uint32_t g, int sx, int
   return (v & m) != 0;
 }
 
+// Grows grain g's lattice bounding box to include the site.  Plain reads
+// first: the box changes only at its extremes, and skipping the atomics in
+// the common case keeps thousands of spawners of one grain off six hot words.
 __device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int sy, int sz) {
   int32_t* b = D.gbox + (size_t)g * 6;
-  atomicMin(b + 0, sx);
-  atomicMin(b + 1, sy);
-  atomicMin(b + 2, sz);
-  atomicMax(b + 3, sx);
-  atomicMax(b + 4, sy);
-  atomicMax(b + 5, sz);
+  const int s[3] = {sx, sy, sz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (s[a] < __hip_atomic_load(b + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(b + a, s[a]);
+    if (s[a] > __hip_atomic_load(b + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(b + 3 + a, s[a]);
+  }
 }
 
 // Rounded lattice position of world point y in grain G (crystal frame).
@@ -388,23 +425,87 @@ __device__ __forceinline__ unsigned long long block_excl_scan64(unsigned long lo
   return off + incl - v;
 }
 
+// Exclusive scan over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
+  const int lane = lane_id();
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(incl, (unsigned)o);
+    if (lane >= o) incl += y;
+  }
+  total = __shfl(incl, 63);
+  return incl - v;
+}
+
+// Start of a block's region in a particle-indexed list: the chunk that
+// chunk_of(n, TPB) gives the logical block lb on a STREAM_GRID grid.
+__device__ __forceinline__ uint32_t region_begin(uint32_t n, uint32_t lb) {
+  uint32_t per = (n + (uint32_t)STREAM_GRID - 1u) / (uint32_t)STREAM_GRID;
+  per = (per + TPB - 1u) / TPB * TPB;
+  const uint64_t b = (uint64_t)lb * per;
+  return (uint32_t)(b < n ? b : n);
+}
+
+// One-entry cache of claim-hash slots: the sites a spawner tests lie within
+// two lattice steps of its reached site, mostly in the same 8^3 slot brick.
+struct SlotCache {
+  uint64_t key;
+  int64_t slot;
+};
+
+__device__ __forceinline__ bool cached_test(const Dev& D, SlotCache& c, uint32_t g, int sx, int sy,
+                                            int sz, uint32_t which) {
+  const uint64_t key = claim_key(g, sx, sy, sz);
+  if (key != c.key) {
+    c.key = key;
+    c.slot = claim_find(D, key);
+  }
+  if (c.slot < 0) return false;
+  const uint32_t b = site_bit(sx, sy, sz);
+  const unsigned long long m = 1ull << (b & 63);
+  const unsigned long long* w = D.cbits + (size_t)c.slot * 24 + (b >> 6);
+  unsigned long long v = 0;
+  if (which & M_CLAIMED) v |= load_relaxed(w + CB_CLAIMED);
+  if (which & M_REACHED) v |= load_relaxed(w + CB_REACHED);
+  if (which & M_NOW) v |= load_relaxed(w + CB_NOW);
+  return (v & m) != 0;
+}
+
+// claim_or through a one-entry find-or-insert cache.
+__device__ __forceinline__ void cached_or(const Dev& D, SlotCache& c, uint32_t g, int sx, int sy,
+                                          int sz, uint32_t which) {
+  const uint64_t key = claim_key(g, sx, sy, sz);
+  if (key != c.key || c.slot < 0) {
+    c.key = key;
+    c.slot = claim_get(D, key);
+  }
+  if (c.slot < 0) return;
+  const uint32_t b = site_bit(sx, sy, sz);
+  const unsigned long long m = 1ull << (b & 63);
+  unsigned long long* w = D.cbits + (size_t)c.slot * 24 + (b >> 6);
+  if (which & M_CLAIMED) atomicOr(w + CB_CLAIMED, m);
+  if (which & M_REACHED) atomicOr(w + CB_REACHED, m);
+  if (which & M_NOW) atomicOr(w + CB_NOW, m);
+}
+
 // ------------------------------------------------------- stopped store ----
-// Appends record r (state STOPPED) at slot j and links it into the cell list
-// of stopped particles.  Callers run in kernels that never read that list.
-__device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r) {
-  if (j == NIL) return;
+// Writes record r (state STOPPED) and its position at slot j of the stopped
+// store and links it into the cell list of recently stopped particles.
+// Callers run in kernels that never read those lists.
+__device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P3 p) {
   if (j >= D.cap_s) {
     atomicOr(&D.cnt->err, ERR_CAPACITY);
     return;
   }
+  const uint32_t g = rec_grain(r);
   D.S[j] = r;
-  P3 p = rec_pos(D, r);
-  C3 c = cell_of(D, p);
-  const uint64_t ci = cell_index(D, c.x, c.y, c.z);
+  D.PS[j] = pos4(p, g);
+  const C3 c = cell_of(D, p);
+  const uint32_t ci = cell_index(D, c.x, c.y, c.z);
   const uint32_t old = atomicExch(&D.shead[ci], j);
   D.snext[j] = old;
-  const uint32_t b = brick_index(D, c.x, c.y, c.z);
-  const uint32_t g = rec_grain(r);
+  const uint32_t b = ci / (uint32_t)BRICK_CELLS;
   atomicMin(&D.sbsum[b].x, g);
   atomicMax(&D.sbsum[b].y, g);
 }
@@ -412,18 +513,28 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r) {
 // ==================================================================== step
 __global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
   if (dead(D)) return;
+  __shared__ uint32_t s_nsp, s_adv, s_exit, s_bad, s_max;
+  if (threadIdx.x == 0) {
+    s_nsp = 0;
+    s_adv = 0;
+    s_exit = 0;
+    s_bad = 0;
+    s_max = 0;
+  }
+  __syncthreads();
   const uint32_t n = D.cnt->n_active;
   const Chunk ch = chunk_of(n, TPB);
+  const int lane = lane_id();
   float max_step = 0.0f;
-  uint32_t nadv = 0, nexit = 0;
-  uint32_t bad = 0;
+  uint32_t nadv = 0, nexit = 0, bad = 0;
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t i = base + threadIdx.x;
     const bool valid = i < ch.end;
     uint4 r = valid ? D.A[i] : make_uint4(0u, 0u, 0u, 0u);
     const bool act = valid && ((rec_fl(r) & 3u) == ST_ACTIVE);
-    uint32_t bkey = NIL;
+    uint32_t ckey = NIL, bkey = NIL;
     bool spawn = false, exited = false;
+    P3 x2 = {0.0f, 0.0f, 0.0f};
     if (act) {
       const uint32_t g = rec_grain(r);
       const int d = rec_dir(r);
@@ -440,7 +551,7 @@ __global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
       if (delta > D.rc_half) bad |= ERR_CFL;
       max_step = fmaxf(max_step, delta);
       const float s2 = s + delta;
-      const P3 x2 = lattice_pos(G, sx, sy, sz, d, s2);
+      x2 = lattice_pos(G, sx, sy, sz, d, s2);
       nadv += 1;
       const bool inside = x2.x >= D.lo[0] && x2.x < D.hi[0] && x2.y >= D.lo[1] &&
                           x2.y < D.hi[1] && x2.z >= D.lo[2] && x2.z < D.hi[2];
@@ -455,39 +566,38 @@ __global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
         if (s2 >= 2.0f * D.lambda0) bad |= ERR_CFL;
       } else {
         fl = ST_ACTIVE | FL_KEEP;
-        bkey = brick_of(D, x2);
+        const C3 c = cell_of(D, x2);
+        ckey = cell_index(D, c.x, c.y, c.z);
+        bkey = ckey / (uint32_t)BRICK_CELLS;
       }
       r = make_rec(s2, g, d, sx, sy, sz, fl);
       D.A[i] = r;
-      if (spawn) {
-        int S[3] = {sx, sy, sz};
-        S[d >> 1] += (d & 1) ? -1 : 1;
-        claim_or(D, g, S[0], S[1], S[2], M_NOW);
-      }
     }
-    // Brick counts of kept particles, one atomic per run of equal bricks.
-    const Run run = wave_run(bkey);
-    if (bkey != NIL && run.off == 0) atomicAdd(&D.bcnt[bkey], (uint32_t)run.len);
-    const uint32_t sp = wave_append(spawn, &D.cnt->n_spawn);
-    if (spawn && sp < D.cap_p) D.spawn[sp] = i;
+    // Cell and brick counts of the particles that stay active: one atomic
+    // per run of equal keys in consecutive lanes (the input is cell-sorted).
+    const Run rc = wave_run(ckey);
+    if (ckey != NIL && rc.off == 0) atomicAdd(&D.ccnt[ckey], (uint32_t)rc.len);
+    const Run rb = wave_run(bkey);
+    if (bkey != NIL && rb.off == 0) atomicAdd(&D.bcnt[bkey], (uint32_t)rb.len);
+    // Spawners go to the block's region of the spawner list.
+    const unsigned long long m = __ballot(spawn);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      uint32_t wb = 0;
+      if (lane == leader) wb = atomicAdd(&s_nsp, (uint32_t)__popcll(m));
+      wb = __shfl(wb, leader);
+      if (spawn) D.spawn[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
     const uint32_t sj = wave_append(exited, &D.cnt->n_stopped);
-    if (exited) stopped_put(D, sj, r);
+    if (exited) stopped_put(D, sj, r, x2);
   }
-  // Block reductions of the counters.
-  __shared__ uint32_t s_adv, s_exit, s_bad, s_max;
-  if (threadIdx.x == 0) {
-    s_adv = 0;
-    s_exit = 0;
-    s_bad = 0;
-    s_max = 0;
-  }
-  __syncthreads();
   if (nadv) atomicAdd(&s_adv, nadv);
   if (nexit) atomicAdd(&s_exit, nexit);
   if (bad) atomicOr(&s_bad, bad);
   if (max_step > 0.0f) atomicMax(&s_max, __float_as_uint(max_step));
   __syncthreads();
   if (threadIdx.x == 0) {
+    D.spawn_cnt[logical_block()] = s_nsp;
     if (s_adv) atomicAdd(&D.cnt->advanced, (unsigned long long)s_adv);
     if (s_exit) atomicAdd(&D.cnt->exited, (unsigned long long)s_exit);
     if (s_bad) atomicOr(&D.cnt->err, s_bad);
@@ -495,20 +605,42 @@ __global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
   }
 }
 
+// Marks the site each spawner has reached as reached during this step.
+__global__ __launch_bounds__(TPB) void k_mark_now(Dev D) {
+  if (dead(D)) return;
+  const uint32_t lb = logical_block();
+  const uint32_t beg = region_begin(D.cnt->n_active, lb);
+  const uint32_t cnt = D.spawn_cnt[lb];
+  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
+    const uint4 r = D.A[D.spawn[beg + k]];
+    const int d = rec_dir(r);
+    int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
+    S[d >> 1] += (d & 1) ? -1 : 1;
+    claim_or(D, rec_grain(r), S[0], S[1], S[2], M_NOW);
+  }
+}
+
 __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
   if (dead(D)) return;
-  const uint32_t n = D.cnt->n_spawn;
-  const uint32_t nn = n < D.cap_p ? n : D.cap_p;
-  if (n > D.cap_p && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&D.cnt->err, ERR_CAPACITY);
+  __shared__ uint32_t s_sp, s_ch;
+  if (threadIdx.x == 0) {
+    s_sp = 0;
+    s_ch = 0;
+  }
+  __syncthreads();
+  const uint32_t lb = logical_block();
+  const uint32_t beg = region_begin(D.cnt->n_active, lb);
+  const uint32_t cnt = D.spawn_cnt[lb];
   uint32_t nsp = 0, nch = 0;
-  for (uint32_t k = blockIdx.x * TPB + threadIdx.x; k < nn; k += gridDim.x * TPB) {
-    const uint32_t i = D.spawn[k];
-    uint4 r = D.A[i];
+  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
+    const uint32_t i = D.spawn[beg + k];
+    const uint4 r = D.A[i];
     const uint32_t g = rec_grain(r);
     const int d = rec_dir(r);
     const float s2 = rec_s(r);
     int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
     S[d >> 1] += (d & 1) ? -1 : 1;
+    SlotCache sc{~0ull, -1};
     uint32_t mask = 0;
     for (int dd = 0; dd < 6; ++dd) {
       const int a = dd >> 1;
@@ -516,7 +648,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
       if (sg * S[a] < 0) continue;  // octant rule: only outer directions
       int T[3] = {S[0], S[1], S[2]};
       T[a] += sg;
-      if (claim_test(D, g, T[0], T[1], T[2], M_CLAIMED | M_REACHED | M_NOW)) continue;
+      if (cached_test(D, sc, g, T[0], T[1], T[2], M_CLAIMED | M_REACHED | M_NOW)) continue;
       bool lose = false;
       for (int d2 = 0; d2 < dd && !lose; ++d2) {
         const int a2 = d2 >> 1;
@@ -524,37 +656,33 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
         int S2[3] = {T[0], T[1], T[2]};
         S2[a2] -= sg2;
         if (sg2 * S2[a2] < 0) continue;
-        if (claim_test(D, g, S2[0], S2[1], S2[2], M_NOW)) lose = true;
+        if (cached_test(D, sc, g, S2[0], S2[1], S2[2], M_NOW)) lose = true;
       }
       if (!lose) mask |= 1u << dd;
     }
-    const float* G = D.gtab + (size_t)g * GT_STRIDE;
     // The parent retires whether or not a child survives: without one, every
     // outer neighbour of S already belongs to the grain (interior point).
     D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
-    {
-      const float sc = s2 - D.lambda0;
-      for (int dd = 0; dd < 6; ++dd) {
-        if (!(mask & (1u << dd))) continue;
-        const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
-        atomicAdd(&D.bcnt[brick_of(D, xc)], 1u);
-        int T[3] = {S[0], S[1], S[2]};
-        T[dd >> 1] += (dd & 1) ? -1 : 1;
-        claim_or(D, g, T[0], T[1], T[2], M_CLAIMED);
-        bbox_add(D, g, T[0], T[1], T[2]);
-        nch += 1;
-      }
+    const float* G = D.gtab + (size_t)g * GT_STRIDE;
+    const float sc2 = s2 - D.lambda0;
+    SlotCache wc{~0ull, -1};
+    for (int dd = 0; dd < 6; ++dd) {
+      if (!(mask & (1u << dd))) continue;
+      const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc2);
+      const C3 c = cell_of(D, xc);
+      const uint32_t ci = cell_index(D, c.x, c.y, c.z);
+      atomicAdd(&D.ccnt[ci], 1u);
+      atomicAdd(&D.bcnt[ci / (uint32_t)BRICK_CELLS], 1u);
+      int T[3] = {S[0], S[1], S[2]};
+      T[dd >> 1] += (dd & 1) ? -1 : 1;
+      cached_or(D, wc, g, T[0], T[1], T[2], M_CLAIMED);
+      bbox_add(D, g, T[0], T[1], T[2]);
+      nch += 1;
     }
-    claim_or(D, g, S[0], S[1], S[2], M_REACHED);
+    cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
     bbox_add(D, g, S[0], S[1], S[2]);
     nsp += 1;
   }
-  __shared__ uint32_t s_sp, s_ch;
-  if (threadIdx.x == 0) {
-    s_sp = 0;
-    s_ch = 0;
-  }
-  __syncthreads();
   if (nsp) atomicAdd(&s_sp, nsp);
   if (nch) atomicAdd(&s_ch, nch);
   __syncthreads();
@@ -565,6 +693,9 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
 }
 
 // ----------------------------------------------------------- brick scan ---
+// Mode 0 (active particles of the step): writes start, count and the epoch
+// of each occupied brick.  Mode 1 (stopped-store re-sort): writes start and
+// count of every brick.  Both list the occupied bricks and reset the counts.
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 
@@ -586,7 +717,7 @@ __global__ __launch_bounds__(TPB) void k_scan_reduce(Dev D) {
   if (threadIdx.x == 0) D.scan_tmp[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_top(Dev D, uint32_t ntiles) {
+__global__ __launch_bounds__(TPB) void k_scan_top(Dev D, uint32_t ntiles, int mode) {
   if (dead(D)) return;
   __shared__ unsigned long long wsum[TPB / 64];
   unsigned long long carry = 0;
@@ -600,13 +731,18 @@ __global__ __launch_bounds__(TPB) void k_scan_top(Dev D, uint32_t ntiles) {
   }
   if (threadIdx.x == 0) {
     const uint32_t n_out = (uint32_t)(carry & 0xFFFFFFFFull);
-    D.cnt->n_out = n_out;
-    D.cnt->n_occ = (uint32_t)(carry >> 32);
-    if (n_out > D.cap_p) atomicOr(&D.cnt->err, ERR_CAPACITY);
+    const uint32_t n_occ = (uint32_t)(carry >> 32);
+    if (mode == 0) {
+      D.cnt->n_out = n_out;
+      D.cnt->n_occ = n_occ;
+      if (n_out > D.cap_p) atomicOr(&D.cnt->err, ERR_CAPACITY);
+    } else {
+      D.cnt->n_socc = n_occ;
+    }
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_write(Dev D) {
+__global__ __launch_bounds__(TPB) void k_scan_write(Dev D, uint32_t epoch, int mode) {
   if (dead(D)) return;
   __shared__ unsigned long long wsum[TPB / 64];
   const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
@@ -626,14 +762,44 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Dev D) {
     if (b < D.n_bricks) {
       const uint32_t start = (uint32_t)(ex & 0xFFFFFFFFull);
       const uint32_t occ = (uint32_t)(ex >> 32);
-      D.binfo[b] = make_uint4(start, c[k], NIL, 0u);
-      if (c[k] > 0u) D.occ[occ] = (uint32_t)b;
+      if (mode == 1) D.bsinfo[b] = make_uint2(start, c[k]);
+      if (c[k] > 0u) {
+        if (mode == 0) {
+          D.binfo[b] = make_uint4(start, c[k], NIL, 0u);
+          D.bepoch[b] = epoch;
+        }
+        D.occ[occ] = (uint32_t)b;
+        D.bcnt[b] = 0u;
+      }
       ex += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
     }
   }
 }
 
+// One wave per occupied brick, one lane per cell: cell starts from the
+// brick start and an exclusive scan of the 64 cell counts.
+__global__ __launch_bounds__(TPB) void k_cellscan(Dev D, int mode) {
+  if (dead(D)) return;
+  const uint32_t nocc = mode == 0 ? D.cnt->n_occ : D.cnt->n_socc;
+  const uint32_t waves = gridDim.x * (TPB / 64);
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t k = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6); k < nocc; k += waves) {
+    const uint32_t b = D.occ[k];
+    const uint32_t start = mode == 0 ? D.binfo[b].x : D.bsinfo[b].x;
+    const uint32_t ci = b * (uint32_t)BRICK_CELLS + lane;
+    uint32_t tot;
+    const uint32_t ex = wave_excl_scan(D.ccnt[ci], tot);
+    if (mode == 0) D.cstart[ci] = start + ex;
+    else D.sstart[ci] = start + ex;
+  }
+}
+
 // ------------------------------------------------------------- scatter ----
+__device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g) {
+  atomicMin(&D.binfo[b].z, g);
+  atomicMax(&D.binfo[b].w, g);
+}
+
 __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
   if (dead(D)) return;
   const uint32_t n = D.cnt->n_active;
@@ -643,182 +809,110 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
     const bool valid = i < ch.end;
     const uint4 r = valid ? D.A[i] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t fl = valid ? rec_fl(r) : 0u;
-    uint32_t bkey = NIL;
-    if (fl & FL_KEEP) bkey = brick_of(D, rec_pos(D, r));
-    const Run run = wave_run(bkey);
+    uint32_t ckey = NIL;
+    uint32_t g = NIL;
+    P3 p = {0.0f, 0.0f, 0.0f};
+    if (fl & FL_KEEP) {
+      g = rec_grain(r);
+      p = rec_pos(D, r);
+      const C3 c = cell_of(D, p);
+      ckey = cell_index(D, c.x, c.y, c.z);
+    }
+    // Ranks within the cell: one decrement per run of equal cells; the cell
+    // counts return to zero once every particle has been placed.
+    const Run run = wave_run(ckey);
     uint32_t rbase = 0;
-    if (bkey != NIL && run.off == 0) rbase = atomicSub(&D.bcnt[bkey], (uint32_t)run.len);
+    if (ckey != NIL && run.off == 0) rbase = atomicSub(&D.ccnt[ckey], (uint32_t)run.len);
     rbase = __shfl(rbase, run.head);
-    if (bkey != NIL) {
+    // Grain range per brick: one update per run of equal (brick, grain).
+    const uint32_t bkey = ckey == NIL ? NIL : ckey / (uint32_t)BRICK_CELLS;
+    const uint32_t pb = __shfl_up(bkey, 1u), pg = __shfl_up(g, 1u);
+    const bool head = lane_id() == 0 || pb != bkey || pg != g;
+    if (ckey != NIL) {
       const uint32_t rank = rbase - (uint32_t)run.len + (uint32_t)run.off;
-      const uint32_t dst = D.binfo[bkey].x + rank;
-      if (dst < D.cap_p) D.B[dst] = with_fl(r, ST_ACTIVE);
+      const uint32_t dst = D.cstart[ckey] + rank;
+      if (dst < D.cap_p) {
+        D.B[dst] = with_fl(r, ST_ACTIVE);
+        D.P[dst] = pos4(p, g);
+      }
+      if (head) note_grain(D, bkey, g);
     }
     if (fl & FL_SPAWN) {
-      const uint32_t g = rec_grain(r);
+      const uint32_t gs = rec_grain(r);
       const int d = rec_dir(r);
       int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
       S[d >> 1] += (d & 1) ? -1 : 1;
-      claim_clear_now(D, g, S[0], S[1], S[2]);
+      claim_clear_now(D, gs, S[0], S[1], S[2]);
       const uint32_t mask = (fl >> 8) & 63u;
       if (mask) {
-        const float* G = D.gtab + (size_t)g * GT_STRIDE;
+        const float* G = D.gtab + (size_t)gs * GT_STRIDE;
         const float sc = rec_s(r) - D.lambda0;
         for (int dd = 0; dd < 6; ++dd) {
           if (!(mask & (1u << dd))) continue;
           const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
-          const uint32_t bc = brick_of(D, xc);
-          const uint32_t rank = atomicSub(&D.bcnt[bc], 1u) - 1u;
-          const uint32_t dst = D.binfo[bc].x + rank;
-          if (dst < D.cap_p) D.B[dst] = make_rec(sc, g, dd, S[0], S[1], S[2], ST_ACTIVE);
+          const C3 c = cell_of(D, xc);
+          const uint32_t ci = cell_index(D, c.x, c.y, c.z);
+          const uint32_t rank = atomicSub(&D.ccnt[ci], 1u) - 1u;
+          const uint32_t dst = D.cstart[ci] + rank;
+          if (dst < D.cap_p) {
+            D.B[dst] = make_rec(sc, gs, dd, S[0], S[1], S[2], ST_ACTIVE);
+            D.P[dst] = pos4(xc, gs);
+          }
+          note_grain(D, ci / (uint32_t)BRICK_CELLS, gs);
         }
       }
-    }
-  }
-}
-
-// ------------------------------------------------------------ cell sort ---
-// Identity of a particle within its cell: grain, departure site modulo 32
-// per axis, direction.  Two particles of one grain in one cell have sites
-// closer than 32 lattice steps, so the key is unique within a cell.
-__device__ __forceinline__ unsigned long long id_key(uint4 r) {
-  return ((unsigned long long)rec_grain(r) << 18) |
-         ((unsigned long long)(rec_sx(r) & 31) << 13) |
-         ((unsigned long long)(rec_sy(r) & 31) << 8) |
-         ((unsigned long long)(rec_sz(r) & 31) << 3) | (unsigned long long)rec_dir(r);
-}
-
-__global__ __launch_bounds__(TPB) void k_cellsort(Dev D, uint32_t epoch) {
-  if (dead(D)) return;
-  __shared__ uint4 srec[CS_CAP];
-  __shared__ uint32_t sinfo[CS_CAP];
-  __shared__ uint16_t sidx[CS_CAP];
-  __shared__ uint32_t hist[512];
-  __shared__ uint32_t off[512];
-  __shared__ uint32_t wsum[TPB / 64];
-  __shared__ uint32_t gmin_s, gmax_s;
-  const uint32_t nocc = D.cnt->n_occ;
-  const Chunk ch = chunk_of(nocc, 1u);
-  for (uint32_t k = ch.begin; k < ch.end; ++k) {
-    const uint32_t b = D.occ[k];
-    const uint4 info = D.binfo[b];
-    const uint32_t start = info.x, count = info.y;
-    if (count > (uint32_t)CS_CAP) {
-      if (threadIdx.x == 0) atomicOr(&D.cnt->err, ERR_CAPACITY);
-      continue;
-    }
-    const int bx = (int)(b % (uint32_t)D.nb[0]);
-    const int by = (int)((b / (uint32_t)D.nb[0]) % (uint32_t)D.nb[1]);
-    const int bz = (int)(b / ((uint32_t)D.nb[0] * (uint32_t)D.nb[1]));
-    for (int j = threadIdx.x; j < 512; j += TPB) hist[j] = 0;
-    if (threadIdx.x == 0) {
-      gmin_s = NIL;
-      gmax_s = 0;
-    }
-    __syncthreads();
-    uint32_t gmin = NIL, gmax = 0;
-    for (uint32_t j = threadIdx.x; j < count; j += TPB) {
-      const uint4 r = D.B[start + j];
-      srec[j] = r;
-      const C3 c = cell_of(D, rec_pos(D, r));
-      const uint32_t lc = (uint32_t)((c.x - bx * BRICK) | ((c.y - by * BRICK) << 3) |
-                                     ((c.z - bz * BRICK) << 6)) & 511u;
-      const uint32_t rk = atomicAdd(&hist[lc], 1u);
-      sinfo[j] = lc | (rk << 9);
-      const uint32_t g = rec_grain(r);
-      gmin = min(gmin, g);
-      gmax = max(gmax, g);
-    }
-    if (gmin != NIL) {
-      atomicMin(&gmin_s, gmin);
-      atomicMax(&gmax_s, gmax);
-    }
-    __syncthreads();
-    const uint32_t h0 = hist[2 * threadIdx.x], h1 = hist[2 * threadIdx.x + 1];
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(h0 + h1, wsum, tot);
-    off[2 * threadIdx.x] = ex;
-    off[2 * threadIdx.x + 1] = ex + h0;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < count; j += TPB) {
-      const uint32_t lc = sinfo[j] & 511u;
-      sidx[off[lc] + (sinfo[j] >> 9)] = (uint16_t)j;
-    }
-    __syncthreads();
-    for (uint32_t q = threadIdx.x; q < count; q += TPB) {
-      const uint32_t j = sidx[q];
-      const uint32_t lc = sinfo[j] & 511u;
-      const uint32_t beg = off[lc], cnt = hist[lc];
-      const uint4 r = srec[j];
-      const unsigned long long key = id_key(r);
-      uint32_t rank = 0;
-      for (uint32_t u = beg; u < beg + cnt; ++u) {
-        const uint32_t jj = sidx[u];
-        if (jj != j && id_key(srec[jj]) < key) ++rank;
-      }
-      D.A[start + beg + rank] = r;
-    }
-    for (uint32_t lc = threadIdx.x; lc < 512u; lc += TPB) {
-      const uint32_t c = hist[lc];
-      if (c == 0u) continue;
-      if (c > 255u) atomicOr(&D.cnt->err, ERR_CAPACITY);
-      const int cx = bx * BRICK + (int)(lc & 7u);
-      const int cy = by * BRICK + (int)((lc >> 3) & 7u);
-      const int cz = bz * BRICK + (int)(lc >> 6);
-      const uint64_t ci = cell_index(D, cx, cy, cz);
-      const unsigned long long hi = (unsigned long long)((c > 255u ? 255u : c) | (epoch << 8));
-      D.ctab[ci] = (unsigned long long)(start + off[lc]) | (hi << 32);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      D.binfo[b].z = gmin_s;
-      D.binfo[b].w = gmax_s;
     }
   }
 }
 
 // ---------------------------------------------------------- containment ---
-// True if any particle of another grain than g (g = NIL: any grain) lies
+// True if a particle of a grain other than g (g = NIL: of any grain) lies
 // within rc of p, among this step's active particles and the stopped ones.
-__device__ __forceinline__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, C3 c,
-                                               uint32_t g) {
-  const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, D.n[0] - 1);
-  const int y0 = max(c.y - 1, 0), y1 = min(c.y + 1, D.n[1] - 1);
-  const int z0 = max(c.z - 1, 0), z1 = min(c.z + 1, D.n[2] - 1);
-  if (g != NIL) {
-    // Brick summaries: skip the stencil when every touched brick holds only
-    // grain g (or nothing).
-    bool maybe = false;
-    for (int bz = z0 >> 3; bz <= (z1 >> 3) && !maybe; ++bz)
-      for (int by = y0 >> 3; by <= (y1 >> 3) && !maybe; ++by)
-        for (int bx = x0 >> 3; bx <= (x1 >> 3) && !maybe; ++bx) {
-          const uint32_t b = ((uint32_t)bz * (uint32_t)D.nb[1] + (uint32_t)by) * (uint32_t)D.nb[0] +
-                             (uint32_t)bx;
-          const uint4 inf = D.binfo[b];
-          if (inf.y > 0u && !(inf.z == g && inf.w == g)) maybe = true;
-          const uint2 sb = D.sbsum[b];
-          if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) maybe = true;
-        }
-    if (!maybe) return false;
-  }
+// `tests` counts the candidate particles examined (diagnostics).
+__device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t& tests) {
+  int x0, x1, y0, y1, z0, z1;
+  stencil_axis(D, p.x, 0, x0, x1);
+  stencil_axis(D, p.y, 1, y0, y1);
+  stencil_axis(D, p.z, 2, z0, z1);
   for (int z = z0; z <= z1; ++z)
     for (int y = y0; y <= y1; ++y)
       for (int x = x0; x <= x1; ++x) {
-        const uint64_t ci = cell_index(D, x, y, z);
-        const unsigned long long e = D.ctab[ci];
-        if ((uint32_t)(e >> 40) == epoch) {
-          const uint32_t st = (uint32_t)(e & 0xFFFFFFFFull);
-          const uint32_t cnt = (uint32_t)((e >> 32) & 255ull);
-          for (uint32_t j = st; j < st + cnt; ++j) {
-            const uint4 q = D.A[j];
-            if (rec_grain(q) == g) continue;
-            if (dist2(p, rec_pos(D, q)) < D.rc2) return true;
+        const uint32_t b = brick_index(D, x, y, z);
+        const uint32_t loc = local_index(x, y, z);
+        const uint32_t ci = b * (uint32_t)BRICK_CELLS + loc;
+        // Brick summaries: a source whose brick holds grain g only (or
+        // nothing) cannot hold a foreign particle.
+        if (D.bepoch[b] == epoch) {
+          const uint4 inf = D.binfo[b];
+          if (!(inf.z == g && inf.w == g)) {
+            const uint32_t st = D.cstart[ci];
+            const uint32_t en =
+                (loc + 1u < (uint32_t)BRICK_CELLS) ? D.cstart[ci + 1] : inf.x + inf.y;
+            for (uint32_t j = st; j < en; ++j) {
+              const float4 q = D.P[j];
+              ++tests;
+              if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+            }
           }
         }
-        for (uint32_t j = D.shead[ci]; j != NIL; j = D.snext[j]) {
-          const uint4 q = D.S[j];
-          if (rec_grain(q) == g) continue;
-          if (dist2(p, rec_pos(D, q)) < D.rc2) return true;
+        const uint2 sb = D.sbsum[b];
+        if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) {
+          const uint2 bs = D.bsinfo[b];
+          if (bs.y > 0u) {
+            const uint32_t st = D.sstart[ci];
+            const uint32_t en =
+                (loc + 1u < (uint32_t)BRICK_CELLS) ? D.sstart[ci + 1] : bs.x + bs.y;
+            for (uint32_t j = st; j < en; ++j) {
+              const float4 q = D.PS[j];
+              ++tests;
+              if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+            }
+          }
+          for (uint32_t j = D.shead[ci]; j != NIL; j = D.snext[j]) {
+            const float4 q = D.PS[j];
+            ++tests;
+            if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+          }
         }
       }
   return false;
@@ -826,37 +920,53 @@ __device__ __forceinline__ bool foreign_within(const Dev& D, uint32_t epoch, P3 
 
 __global__ __launch_bounds__(TPB) void k_contain(Dev D, uint32_t epoch) {
   if (dead(D)) return;
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
   const uint32_t n = D.cnt->n_out;
   const Chunk ch = chunk_of(n, TPB);
+  const int lane = lane_id();
+  uint32_t tests = 0;
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t i = base + threadIdx.x;
     bool hit = false;
     if (i < ch.end) {
-      const uint4 r = D.A[i];
-      const P3 p = rec_pos(D, r);
-      hit = foreign_within(D, epoch, p, cell_of(D, p), rec_grain(r));
+      const float4 q = D.P[i];
+      hit = foreign_within(D, epoch, p3_of(q), grain_of(q), tests);
     }
-    const uint32_t k = wave_append(hit, &D.cnt->n_newstop);
-    if (hit && k < D.cap_p) D.newstop[k] = i;
+    const unsigned long long m = __ballot(hit);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      uint32_t wb = 0;
+      if (lane == leader) wb = atomicAdd(&s_n, (uint32_t)__popcll(m));
+      wb = __shfl(wb, leader);
+      if (hit) D.newstop[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
   }
+  // Diagnostics: candidate tests of the block.
+  if (tests) atomicAdd(&D.cnt->pair_tests, (unsigned long long)tests);
+  __syncthreads();
+  if (threadIdx.x == 0) D.newstop_cnt[logical_block()] = s_n;
 }
 
 __global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
   if (dead(D)) return;
-  const uint32_t n = D.cnt->n_newstop;
-  const uint32_t nn = n < D.cap_p ? n : D.cap_p;
-  for (uint32_t k0 = blockIdx.x * TPB; k0 < nn; k0 += gridDim.x * TPB) {
-    const uint32_t k = k0 + threadIdx.x;
-    const bool valid = k < nn;
-    uint4 r = make_uint4(0u, 0u, 0u, 0u);
-    uint32_t i = 0;
-    if (valid) {
-      i = D.newstop[k];
-      r = with_fl(D.A[i], ST_STOPPED);
-      D.A[i] = r;
-    }
-    const uint32_t j = wave_append(valid, &D.cnt->n_stopped);
-    if (valid) stopped_put(D, j, r);
+  __shared__ uint32_t s_base;
+  const uint32_t lb = logical_block();
+  const uint32_t beg = region_begin(D.cnt->n_out, lb);
+  const uint32_t cnt = D.newstop_cnt[lb];
+  if (cnt == 0u) return;
+  if (threadIdx.x == 0) {
+    s_base = atomicAdd(&D.cnt->n_stopped, cnt);
+    atomicAdd(&D.cnt->n_newstop, cnt);
+  }
+  __syncthreads();
+  const uint32_t base = s_base;
+  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
+    const uint32_t i = D.newstop[beg + k];
+    const uint4 r = with_fl(D.B[i], ST_STOPPED);
+    D.B[i] = r;
+    stopped_put(D, base + k, r, p3_of(D.P[i]));
   }
 }
 
@@ -885,7 +995,8 @@ __global__ __launch_bounds__(TPB) void k_nuc_test(Dev D, float lin_c, uint32_t e
       D.sstate[i] = SITE_ENGULFED;  // claims never shrink: permanent
       continue;
     }
-    if (foreign_within(D, epoch, y, cell_of(D, y), NIL)) continue;
+    uint32_t tests = 0;
+    if (foreign_within(D, epoch, y, NIL, tests)) continue;
     D.cand[i] = 1u;
     atomicAdd(&D.cnt->n_cand, 1u);
   }
@@ -945,7 +1056,8 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Dev D) {
           int32_t* bb = D.gbox + (size_t)g * 6;
           for (int k = 0; k < 6; ++k) bb[k] = 0;
           claim_or(D, g, 0, 0, 0, M_CLAIMED | M_REACHED);
-          for (int d = 0; d < 6; ++d) D.A[n_out + 6 * nf + d] = make_rec(0.0f, g, d, 0, 0, 0, ST_ACTIVE);
+          for (int d = 0; d < 6; ++d)
+            D.B[n_out + 6 * nf + d] = make_rec(0.0f, g, d, 0, 0, 0, ST_ACTIVE);
           D.sstate[si] = SITE_FIRED;
           s_nfired = nf + 1;
         }
@@ -966,7 +1078,6 @@ __global__ void k_finish(Dev D) {
   c->n_active = c->n_out + 6u * c->n_fired;
   c->n_live = c->n_out - c->n_newstop + 6u * c->n_fired;
   c->contained += c->n_newstop;
-  c->n_spawn = 0;
   c->n_newstop = 0;
   c->n_cand = 0;
   c->n_fired = 0;
@@ -981,6 +1092,63 @@ __global__ void k_reset_stats(Dev D) {
   c->contained = 0;
   c->nucleated = 0;
   c->max_step = 0;
+  c->pair_tests = 0;
+}
+
+// ------------------------------------------------ stopped-store re-sort ---
+// Counting sort of S[0, n_stopped) by cell into S2: counts, brick scan
+// (mode 1), cell scan (mode 1), scatter.  Clears the recent-particle lists.
+__global__ __launch_bounds__(TPB) void k_srb_count(Dev D) {
+  if (dead(D)) return;
+  const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
+  const uint32_t ns = D.cnt->n_sorted;
+  const Chunk ch = chunk_of(n, TPB);
+  for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t ckey = NIL;
+    if (j < ch.end) {
+      const C3 c = cell_of(D, p3_of(D.PS[j]));
+      ckey = cell_index(D, c.x, c.y, c.z);
+      if (j >= ns) D.shead[ckey] = NIL;
+    }
+    const Run rc = wave_run(ckey);
+    if (ckey != NIL && rc.off == 0) atomicAdd(&D.ccnt[ckey], (uint32_t)rc.len);
+    const uint32_t bkey = ckey == NIL ? NIL : ckey / (uint32_t)BRICK_CELLS;
+    const Run rb = wave_run(bkey);
+    if (bkey != NIL && rb.off == 0) atomicAdd(&D.bcnt[bkey], (uint32_t)rb.len);
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_srb_scatter(Dev D) {
+  if (dead(D)) return;
+  const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
+  const Chunk ch = chunk_of(n, TPB);
+  for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t ckey = NIL;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j < ch.end) {
+      q = D.PS[j];
+      const C3 c = cell_of(D, p3_of(q));
+      ckey = cell_index(D, c.x, c.y, c.z);
+    }
+    const Run run = wave_run(ckey);
+    uint32_t rbase = 0;
+    if (ckey != NIL && run.off == 0) rbase = atomicSub(&D.ccnt[ckey], (uint32_t)run.len);
+    rbase = __shfl(rbase, run.head);
+    if (ckey != NIL) {
+      const uint32_t dst = D.sstart[ckey] + rbase - (uint32_t)run.len + (uint32_t)run.off;
+      if (dst < D.cap_s) {
+        D.S2[dst] = D.S[j];
+        D.PS2[dst] = q;
+      }
+    }
+  }
+}
+
+__global__ void k_srb_finish(Dev D) {
+  if (D.cnt->err & ERR_CAPACITY) return;
+  D.cnt->n_sorted = min(D.cnt->n_stopped, D.cap_s);
 }
 
 // ------------------------------------------------------------- resample ---
@@ -1031,19 +1199,21 @@ __global__ __launch_bounds__(TPB) void k_fill_sbsum(Dev D) {
     D.sbsum[b] = make_uint2(NIL, 0u);
 }
 
-// New records A[first, first+count) (all active): those outside the box stop.
+// New records A[first, first+count): those marked stopped, and (with box
+// exit) those outside the box, move to the stopped store.
 __global__ __launch_bounds__(TPB) void k_classify_new(Dev D, uint32_t first, uint32_t count) {
   for (uint32_t k0 = blockIdx.x * TPB; k0 < count; k0 += gridDim.x * TPB) {
     const uint32_t k = k0 + threadIdx.x;
     bool out = false;
     uint4 r = make_uint4(0u, 0u, 0u, 0u);
-    uint32_t i = first + k;
+    P3 x = {0.0f, 0.0f, 0.0f};
+    const uint32_t i = first + k;
     if (k < count) {
       r = D.A[i];
+      x = rec_pos(D, r);
       if ((rec_fl(r) & 3u) == ST_STOPPED) {
         out = true;
       } else if (D.box_exit) {
-        const P3 x = rec_pos(D, r);
         const bool inside = x.x >= D.lo[0] && x.x < D.hi[0] && x.y >= D.lo[1] &&
                             x.y < D.hi[1] && x.z >= D.lo[2] && x.z < D.hi[2];
         out = !inside;
@@ -1055,7 +1225,7 @@ __global__ __launch_bounds__(TPB) void k_classify_new(Dev D, uint32_t first, uin
       }
     }
     const uint32_t j = wave_append(out, &D.cnt->n_stopped);
-    if (out) stopped_put(D, j, r);
+    if (out) stopped_put(D, j, r, x);
   }
 }
 
@@ -1084,6 +1254,12 @@ __global__ __launch_bounds__(TPB) void k_claim_list(Dev D, const int32_t* grain,
       bbox_add(D, g, x, y, z);
     }
   }
+}
+
+__global__ __launch_bounds__(TPB) void k_clear_bepoch(Dev D) {
+  for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
+       b += (uint64_t)gridDim.x * TPB)
+    D.bepoch[b] = 0u;
 }
 
 // --------------------------------------------------------------- export ---
@@ -1242,12 +1418,6 @@ __global__ __launch_bounds__(TPB) void k_grain_map(Dev D, int32_t n0, int32_t n1
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_clear_ctab(Dev D, uint64_t n_cells) {
-  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < n_cells;
-       v += (uint64_t)gridDim.x * TPB)
-    D.ctab[v] = 0ull;
-}
-
 // ============================================================ launchers ===
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
   uint64_t g = (n + TPB - 1) / TPB;
@@ -1259,17 +1429,19 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
   k_advance<<<STREAM_GRID, TPB, 0, s>>>(d, lin_c, dt);
 }
-void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<STREAM_GRID, TPB, 0, s>>>(d); }
-void launch_scan(const Dev& d, hipStream_t s) {
+void launch_branch(const Dev& d, hipStream_t s) {
+  k_mark_now<<<STREAM_GRID, TPB, 0, s>>>(d);
+  k_branch<<<STREAM_GRID, TPB, 0, s>>>(d);
+}
+static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
   const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   k_scan_reduce<<<ntiles, TPB, 0, s>>>(d);
-  k_scan_top<<<1, TPB, 0, s>>>(d, ntiles);
-  k_scan_write<<<ntiles, TPB, 0, s>>>(d);
+  k_scan_top<<<1, TPB, 0, s>>>(d, ntiles, mode);
+  k_scan_write<<<ntiles, TPB, 0, s>>>(d, epoch, mode);
+  k_cellscan<<<STREAM_GRID, TPB, 0, s>>>(d, mode);
 }
+void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s) { scan_bricks(d, epoch, 0, s); }
 void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<STREAM_GRID, TPB, 0, s>>>(d); }
-void launch_cellsort(const Dev& d, uint32_t epoch, hipStream_t s) {
-  k_cellsort<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
-}
 void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s) {
   k_contain<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
 }
@@ -1281,6 +1453,12 @@ void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s) {
 }
 void launch_finish(const Dev& d, hipStream_t s) { k_finish<<<1, 1, 0, s>>>(d); }
 void launch_reset_stats(const Dev& d, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(d); }
+void launch_stopped_rebuild(const Dev& d, hipStream_t s) {
+  k_srb_count<<<STREAM_GRID, TPB, 0, s>>>(d);
+  scan_bricks(d, 0u, 1, s);
+  k_srb_scatter<<<STREAM_GRID, TPB, 0, s>>>(d);
+  k_srb_finish<<<1, 1, 0, s>>>(d);
+}
 void launch_resample(const Dev& d, double dT0, const double grad[3], double rate, double q,
                      double U, double alpha, double x_start, double x_end, double ys, double zs,
                      double r_min, double dT_min, double ox, double oy, double oz, double sx,
@@ -1310,7 +1488,7 @@ void launch_resample(const Dev& d, double dT0, const double grad[3], double rate
   const uint64_t total = (uint64_t)d.fn[0] * d.fn[1] * d.fn[2];
   k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(d, a);
 }
-void launch_init_workspace(const Dev& d, uint64_t, hipStream_t s) {
+void launch_init_workspace(const Dev& d, hipStream_t s) {
   k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
 }
 void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s) {
@@ -1350,8 +1528,8 @@ void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                                                     origin[2], spacing[0], spacing[1], spacing[2],
                                                     out);
 }
-void launch_clear_ctab(const Dev& d, uint64_t n_cells, hipStream_t s) {
-  k_clear_ctab<<<grid_for(n_cells, 8192), TPB, 0, s>>>(d, n_cells);
+void launch_clear_bepoch(const Dev& d, hipStream_t s) {
+  k_clear_bepoch<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
 }
 
 }  // namespace ge

@@ -32,8 +32,9 @@ struct Geometry {
 };
 
 struct Layout {
-  size_t A, B, spawn, newstop, S, snext, shead, ctab, bcnt, binfo, occ, sbsum, scan_tmp, ckeys,
-      cbits, gtab, gbox, stab, sstate, cand, fgrid, cnt, total;
+  size_t A, B, P, spawn, spawn_cnt, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
+      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, occ, scan_tmp, ckeys, cbits, gtab, gbox,
+      stab, sstate, cand, fgrid, cnt, total;
 };
 
 uint64_t next_pow2(uint64_t v) {
@@ -62,14 +63,18 @@ const char* check_params(const ge_params* p) {
   if (p->cap_sites < 0) return "cap_sites out of range";
   if (p->cap_claim_bricks < 1 || p->cap_claim_bricks > (1ll << 32)) return "cap_claim_bricks out of range";
   double diag = 0;
+  double nb_total = 1;
   for (int a = 0; a < 3; ++a) {
     double L = p->hi[a] - p->lo[a];
     diag += L * L;
     double nc = std::ceil(L / p->h);
     if (nc > (1 << 20)) return "too many cells along an axis";
+    nb_total *= std::ceil(nc / ge::BRICK);
     if (p->field_n[a] < 0 || p->field_n[a] == 1) return "field_n must be 0 or >= 2";
   }
   if (std::sqrt(diag) / p->lambda0 > MAX_SITE_RANGE) return "box too large for lambda0 (site range)";
+  if (nb_total * ge::BRICK_CELLS > 4294967295.0) return "too many cells (2^32)";
+  if (p->resort_every < 0) return "resort_every must be >= 0";
   return nullptr;
 }
 
@@ -80,9 +85,9 @@ Geometry geometry(const ge_params* p) {
   for (int a = 0; a < 3; ++a) {
     g.n[a] = (int32_t)std::max(1.0, std::ceil((p->hi[a] - p->lo[a]) / p->h));
     g.nb[a] = (g.n[a] + ge::BRICK - 1) / ge::BRICK;
-    g.n_cells *= (uint64_t)g.n[a];
     g.n_bricks *= (uint64_t)g.nb[a];
   }
+  g.n_cells = g.n_bricks * ge::BRICK_CELLS;  // brick-major, padded to whole bricks
   g.slots = next_pow2((uint64_t)std::max<int64_t>(p->cap_claim_bricks, 1024));
   g.field_nodes = 1;
   for (int a = 0; a < 3; ++a) g.field_nodes *= (uint64_t)std::max(p->field_n[a], 0);
@@ -102,16 +107,26 @@ Layout layout(const ge_params* p, const Geometry& g) {
   const uint64_t ntiles = (g.n_bricks + 2047) / 2048;
   L.A = put(16 * cp);
   L.B = put(16 * cp);
+  L.P = put(16 * cp);
   L.spawn = put(4 * cp);
+  L.spawn_cnt = put(4 * ge::STREAM_GRID);
   L.newstop = put(4 * cp);
+  L.newstop_cnt = put(4 * ge::STREAM_GRID);
   L.S = put(16 * cs);
+  L.PS = put(16 * cs);
+  L.S2 = put(16 * cs);
+  L.PS2 = put(16 * cs);
   L.snext = put(4 * cs);
   L.shead = put(4 * g.n_cells);
-  L.ctab = put(8 * g.n_cells);
+  L.sstart = put(4 * g.n_cells);
+  L.bsinfo = put(8 * g.n_bricks);
+  L.sbsum = put(8 * g.n_bricks);
+  L.ccnt = put(4 * g.n_cells);
+  L.cstart = put(4 * g.n_cells);
   L.bcnt = put(4 * g.n_bricks);
   L.binfo = put(16 * g.n_bricks);
+  L.bepoch = put(4 * g.n_bricks);
   L.occ = put(4 * g.n_bricks);
-  L.sbsum = put(8 * g.n_bricks);
   L.scan_tmp = put(8 * ntiles);
   L.ckeys = put(8 * g.slots);
   L.cbits = put(192 * g.slots);
@@ -166,6 +181,7 @@ struct ge_ctx {
   double t;
   int64_t step;
   uint32_t epoch;
+  int32_t resort_every;
   uint32_t n_sites;
   bool dead;
   std::string err;
@@ -177,9 +193,9 @@ struct ge_ctx {
   int64_t prof_steps = 0;
 };
 
-static const char* PHASE_NAMES[GE_N_PHASES] = {"resample", "advance",  "branch", "scan",
-                                               "scatter",  "cellsort", "contain", "stoplink",
-                                               "nucleate", "finish"};
+static const char* PHASE_NAMES[GE_N_PHASES] = {"resample", "advance",  "branch",   "scan",
+                                               "scatter",  "contain",  "stoplink", "nucleate",
+                                               "finish",   "resort"};
 
 // Records the event that closes phase `k` of the current step (k = -1 opens
 // the step).
@@ -262,13 +278,17 @@ static ge_status reset_device(ge_ctx* c) {
   hipStream_t s = c->stream;
   char* w = c->ws;
   HIPCHK(c, hipMemsetAsync(w + L.shead, 0xFF, 4 * g.n_cells, s));
-  HIPCHK(c, hipMemsetAsync(w + L.ctab, 0, 8 * g.n_cells, s));
+  HIPCHK(c, hipMemsetAsync(w + L.ccnt, 0, 4 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.bcnt, 0, 4 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bepoch, 0, 4 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bsinfo, 0, 8 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.spawn_cnt, 0, 4 * ge::STREAM_GRID, s));
+  HIPCHK(c, hipMemsetAsync(w + L.newstop_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.ckeys, 0xFF, 8 * g.slots, s));
   HIPCHK(c, hipMemsetAsync(w + L.cbits, 0, 192 * g.slots, s));
   HIPCHK(c, hipMemsetAsync(w + L.cnt, 0, sizeof(ge::Counters), s));
   HIPCHK(c, hipMemsetAsync(w + L.cand, 0, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
-  ge::launch_init_workspace(c->d, g.n_cells, s);
+  ge::launch_init_workspace(c->d, s);
   HIPCHK(c, hipGetLastError());
   c->epoch = 0;
   return GE_OK;
@@ -304,6 +324,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   c->t = 0;
   c->step = 0;
   c->epoch = 0;
+  c->resort_every = p->resort_every > 0 ? p->resort_every : 16;
   c->n_sites = 0;
   c->dead = false;
   c->field = ge_field{};
@@ -327,6 +348,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   }
   d.inv_h = (float)(1.0 / p->h);
   d.n_bricks = (uint32_t)g.n_bricks;
+  d.stencil8 = (2.0 * p->rc <= p->h) ? 1 : 0;
   d.lambda0 = (float)p->lambda0;
   d.rc2 = (float)(p->rc * p->rc);
   d.rc_half = (float)(0.5 * p->rc);
@@ -346,18 +368,28 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.cap_grains = (uint32_t)p->cap_grains;
   d.A = (uint4*)(w + L.A);
   d.B = (uint4*)(w + L.B);
+  d.P = (float4*)(w + L.P);
   d.cap_p = (uint32_t)p->cap_particles;
   d.spawn = (uint32_t*)(w + L.spawn);
+  d.spawn_cnt = (uint32_t*)(w + L.spawn_cnt);
   d.newstop = (uint32_t*)(w + L.newstop);
+  d.newstop_cnt = (uint32_t*)(w + L.newstop_cnt);
   d.S = (uint4*)(w + L.S);
+  d.PS = (float4*)(w + L.PS);
+  d.S2 = (uint4*)(w + L.S2);
+  d.PS2 = (float4*)(w + L.PS2);
   d.snext = (uint32_t*)(w + L.snext);
   d.cap_s = (uint32_t)std::min<int64_t>(p->cap_stopped, 0xFFFFFFFEll);
   d.shead = (uint32_t*)(w + L.shead);
+  d.sstart = (uint32_t*)(w + L.sstart);
+  d.bsinfo = (uint2*)(w + L.bsinfo);
   d.sbsum = (uint2*)(w + L.sbsum);
+  d.ccnt = (uint32_t*)(w + L.ccnt);
+  d.cstart = (uint32_t*)(w + L.cstart);
   d.bcnt = (uint32_t*)(w + L.bcnt);
   d.binfo = (uint4*)(w + L.binfo);
+  d.bepoch = (uint32_t*)(w + L.bepoch);
   d.occ = (uint32_t*)(w + L.occ);
-  d.ctab = (unsigned long long*)(w + L.ctab);
   d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
   d.ckeys = (unsigned long long*)(w + L.ckeys);
   d.cbits = (unsigned long long*)(w + L.cbits);
@@ -556,6 +588,7 @@ static void fill_stats(ge_ctx* c, ge_step_stats* st) {
   st->max_step = ms;
   st->t = c->t;
   st->step = c->step;
+  st->pair_tests = (int64_t)H.pair_tests;
 }
 
 ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
@@ -569,8 +602,8 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
     if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
     prof_mark(c, -1);
     c->epoch += 1;
-    if (c->epoch > 0xFFFFFFu) {
-      ge::launch_clear_ctab(d, c->geo.n_cells, s);
+    if (c->epoch == 0u) {  // wrapped: brick epochs restart
+      ge::launch_clear_bepoch(d, s);
       c->epoch = 1;
     }
     const double t = c->t;
@@ -587,19 +620,25 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
     prof_mark(c, 1);
     ge::launch_branch(d, s);
     prof_mark(c, 2);
-    ge::launch_scan(d, s);
+    ge::launch_scan(d, c->epoch, s);
     prof_mark(c, 3);
     ge::launch_scatter(d, s);
     prof_mark(c, 4);
-    ge::launch_cellsort(d, c->epoch, s);
-    prof_mark(c, 5);
     ge::launch_contain(d, c->epoch, s);
-    prof_mark(c, 6);
+    prof_mark(c, 5);
     ge::launch_stoplink(d, s);
-    prof_mark(c, 7);
+    prof_mark(c, 6);
     ge::launch_nucleate(d, lin_c, c->epoch, s);
-    prof_mark(c, 8);
+    prof_mark(c, 7);
     ge::launch_finish(d, s);
+    prof_mark(c, 8);
+    // This step's sorted output becomes the next step's input.
+    std::swap(d.A, d.B);
+    if ((c->step + 1) % c->resort_every == 0) {
+      ge::launch_stopped_rebuild(d, s);
+      std::swap(d.S, d.S2);
+      std::swap(d.PS, d.PS2);
+    }
     prof_mark(c, 9);
     c->t = t + dt;
     c->step += 1;
@@ -641,6 +680,7 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
       ge_step_stats v{};
       fill_stats(c, &v);
       v.advanced = v.exited = v.spawners = v.children = v.contained = v.nucleated = 0;
+      v.pair_tests = 0;
       v.max_step = 0;
       std::memcpy(out, &v, sizeof(v));
       return error_status(c, H.err);

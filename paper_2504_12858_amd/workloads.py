@@ -197,7 +197,8 @@ def nucleus_uniform(lambda0: float = 5e-6, dT: float = 5.0, quat=None) -> Worklo
 
 def directional(seed: int = 2, n_grains: int = 64, size=(2e-3, 2e-3, 4e-3),
                 lambda0: float = 5e-6, dT0: float = 10.0, G: float = 1e4,
-                rate: float = 10.0, dt: float = 5e-5, n_steps: int = 2000) -> Workload:
+                rate: float = 10.0, dt: float = 5e-5, n_steps: int = 2000,
+                h: Optional[float] = None) -> Workload:
     """Directional competitive growth: grains on the bottom face, linear field
     dT = dT0 - G z + rate t."""
     g = rng(seed)
@@ -206,7 +207,7 @@ def directional(seed: int = 2, n_grains: int = 64, size=(2e-3, 2e-3, 4e-3),
     quat = shoemake_quaternions(g, n_grains)
     return Workload(
         name="directional", lo=(0.0, 0.0, 0.0), hi=tuple(size),
-        lambda0=lambda0, h=lambda0, rc=lambda0, a=KIN_A, b=KIN_B, theta=0.0,
+        lambda0=lambda0, h=lambda0 if h is None else h, rc=lambda0, a=KIN_A, b=KIN_B, theta=0.0,
         dt=dt, n_steps=n_steps,
         field=Field(FIELD_LINEAR, dT0=dT0, grad=(0.0, 0.0, -G), rate=rate),
         grain_centre=centre, grain_quat=quat,
@@ -219,7 +220,7 @@ def cet(seed: int = 3, size=(4e-3, 2e-3, 1e-3), lambda0: float = 2e-6,
         bulk_density: float = 1e11, face_density: float = 1e8,
         dTn_mu: float = 5.0, dTn_sigma: float = 1.0, grid_n: int = 256,
         U: float = 0.05, alpha: float = 4.9e-6, q: float = 0.0264,
-        dt: float = 5e-5, n_steps: int = 4000) -> Workload:
+        dt: float = 5e-5, n_steps: int = 4000, h: Optional[float] = None) -> Workload:
     """Columnar-to-equiaxed transition under a moving Rosenthal source.
 
     Bulk nuclei: round(density * volume) sites, uniform iid positions,
@@ -250,7 +251,7 @@ def cet(seed: int = 3, size=(4e-3, 2e-3, 1e-3), lambda0: float = 2e-6,
                 dT_min=-1000.0)
     return Workload(
         name="cet", lo=(0.0, 0.0, 0.0), hi=tuple(size), lambda0=lambda0,
-        h=lambda0, rc=lambda0, a=KIN_A, b=KIN_B, theta=0.0, dt=dt,
+        h=lambda0 if h is None else h, rc=lambda0, a=KIN_A, b=KIN_B, theta=0.0, dt=dt,
         n_steps=n_steps, field=fld, site_xyz=xyz, site_dTn=dTn, site_quat=quat,
         notes=f"seed={seed} n_face={n_face} n_bulk={n_bulk}")
 

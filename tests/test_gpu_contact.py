@@ -39,18 +39,21 @@ EMPTY_CLAIMS = dict(grain=np.zeros(0, np.int32), site=np.zeros((0, 3), np.int32)
                     flags=np.zeros(0, np.uint8))
 
 
-@pytest.mark.parametrize("seed,n_grains,per_grain,m,spread", [
-    (1, 6, 400, 4, 30e-6),
-    (2, 12, 1500, 8, 60e-6),
-    (3, 40, 3000, 12, 150e-6),   # several tiles of 8^3 cells, ragged brick fill
+@pytest.mark.parametrize("seed,n_grains,per_grain,m,spread,h_factor", [
+    (1, 6, 400, 4, 30e-6, 1.0),
+    (2, 12, 1500, 8, 60e-6, 1.0),
+    (3, 40, 3000, 12, 150e-6, 1.0),   # many 4^3-cell bricks, ragged fill
+    (4, 12, 1500, 8, 60e-6, 2.0),     # cells of 2 rc: 2x2x2 stencil
+    (5, 40, 3000, 12, 150e-6, 2.0),
 ])
-def test_single_step_contact_parity(seed, n_grains, per_grain, m, spread):
+def test_single_step_contact_parity(seed, n_grains, per_grain, m, spread, h_factor):
     require_gpu()
     lam = 5e-6
+    h = h_factor * lam
     dT, dt = 3.0, 1e-4
     centre, quat, parts = _cloud(seed, n_grains, per_grain, lam, m, 0.3, spread)
     print(f"contact parity seed={seed} n={len(parts['grain'])}", flush=True)
-    p = B.make_params((0, 0, 0), (1e-3,) * 3, lam, lam, lam, W.KIN_A, W.KIN_B, branching=0,
+    p = B.make_params((0, 0, 0), (1e-3,) * 3, lam, h, lam, W.KIN_A, W.KIN_B, branching=0,
                       cap_particles=1 << 18, cap_stopped=1 << 18, cap_grains=64,
                       cap_claim_bricks=1 << 12)
     ctx = B.Context(p)
@@ -61,7 +64,8 @@ def test_single_step_contact_parity(seed, n_grains, per_grain, m, spread):
     xyz = np.stack([g["x"], g["y"], g["z"]], 1)
     # Binning: exported cells equal single-rounded FP32 binning of the
     # exported positions.
-    cells = f32_cells(xyz, np.zeros(3, np.float32), np.float32(1.0 / lam), np.array([200] * 3, np.int32))
+    ncell = int(np.ceil(1e-3 / h))
+    cells = f32_cells(xyz, np.zeros(3, np.float32), np.float32(1.0 / h), np.array([ncell] * 3, np.int32))
     np.testing.assert_array_equal(cells, g["cell"])
     # Roles before the step: active particles are tested, stopped ones are obstacles.
     pk = ident(parts["grain"], parts["site"], parts["dir"])
@@ -75,7 +79,7 @@ def test_single_step_contact_parity(seed, n_grains, per_grain, m, spread):
     np.testing.assert_array_equal(gpu_dec, dec)
     assert dec.sum() > 0
     # FP64 oracle: same decisions except pairs within 1e-5 of rc.
-    o = Oracle((0, 0, 0), (1e-3,) * 3, lam, lam, lam, W.KIN_A, W.KIN_B, branching=0)
+    o = Oracle((0, 0, 0), (1e-3,) * 3, lam, h, lam, W.KIN_A, W.KIN_B, branching=0)
     o.set_field(W.Field(W.FIELD_UNIFORM, dT=dT))
     o.load_state(centre, quat, parts, EMPTY_CLAIMS, np.zeros(0, np.int32), 0.0, 0)
     o.step(dt, 1)

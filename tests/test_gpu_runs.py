@@ -14,15 +14,15 @@ from tests.gpu_helpers import context_for, gpu_claims, gpu_parts, orc_claims, or
 pytestmark = pytest.mark.gpu
 
 
-def _scaled_directional(seed=2):
+def _scaled_directional(seed=2, h=None):
     return W.directional(seed=seed, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0,
-                         dt=5e-4, n_steps=240)
+                         dt=5e-4, n_steps=240, h=h)
 
 
-def _scaled_cet(seed=3):
+def _scaled_cet(seed=3, h=None):
     w = W.cet(seed=seed, size=(0.4e-3, 0.2e-3, 0.1e-3), lambda0=4e-6, grid_n=24, dT0=6.0,
               rate=2.0, bulk_density=2e12, face_density=2e8, dt=1.5e-3, n_steps=300, U=0.005,
-              q=0.004)
+              q=0.004, h=h)
     return w
 
 
@@ -33,9 +33,10 @@ def _map_agreement(ctx, o, w, vox):
     return (gm == om).mean(), (om > 0).mean()
 
 
-def test_directional_scaled_grain_map_parity():
+@pytest.mark.parametrize("h", [None, 10e-6])
+def test_directional_scaled_grain_map_parity(h):
     require_gpu()
-    w = _scaled_directional()
+    w = _scaled_directional(h=h)
     print(f"directional scaled: {w.n_steps} steps", flush=True)
     ctx = context_for(w)
     st = ctx.step(w.dt, w.n_steps)
@@ -50,10 +51,11 @@ def test_directional_scaled_grain_map_parity():
     assert abs(st["n_active"] - o.n_active()) <= 0.01 * o.n_active()
 
 
-def test_cet_scaled_grain_map_parity():
+@pytest.mark.parametrize("h", [None, 8e-6])
+def test_cet_scaled_grain_map_parity(h):
     """Moving Rosenthal source resampled each step, bulk and face nuclei."""
     require_gpu()
-    w = _scaled_cet()
+    w = _scaled_cet(h=h)
     print(f"cet scaled: {len(w.site_dTn)} sites, {w.n_steps} steps", flush=True)
     ctx = context_for(w)
     st = ctx.step(w.dt, w.n_steps)
