@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 #   branch   : read and write the spawner's record
 #   resort   : read and write record and position of each stopped particle
 #   resample : write one FP32 node value
-PHASE_BYTES = {"advance": 32, "scatter": 48, "contain": 16, "branch": 32, "resample": 4}
+PHASE_BYTES = {"advance": 32, "scatter": 48, "contain": 16, "branch": 32, "resample": 4,
+               "children": 48, "dirty": 16, "marknow": 16}
 
 
 def log(*a):
@@ -155,7 +156,7 @@ def main():
     log(f"[timed] {args.steps} steps {elapsed:.3f} s, {stats['advanced']} updates, "
         f"active {stats['n_active']} stopped {stats['n_stopped']} spawners "
         f"{stats['spawners']} children {stats['children']} contained {stats['contained']} "
-        f"pair tests {stats['pair_tests']}")
+        f"pair tests {stats['pair_tests']} dirty {stats['dirty_tests']}")
     for k, v in sorted(phases.items(), key=lambda kv: -kv[1]):
         log(f"[phase] {k:9s} {v / max(n_prof, 1):8.3f} ms/step")
     dom = max((k for k in phases if k in PHASE_BYTES), key=lambda k: phases[k])

@@ -135,6 +135,7 @@ typedef struct ge_step_stats {
   double t;           /* time after the call [s] */
   int64_t step;       /* steps taken since creation or the last state load */
   int64_t pair_tests; /* candidate particles examined by the containment test */
+  int64_t dirty_tests;/* active particles whose brick neighbourhood holds another grain */
 } ge_step_stats;
 
 /* Query kinds of ge_query_envelope. */
@@ -262,9 +263,10 @@ ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
    ge_profile(ctx, 1) starts recording and clears the totals; ge_profile(ctx, 0)
    stops.  ge_profile_read synchronises and returns, per phase, the summed
    GPU time in milliseconds and the number of steps recorded.  Phases: field
-   resample, advance, branch, brick and cell scan, scatter, containment,
-   stop linking, nucleation, finish, stopped-store re-sort. */
-#define GE_N_PHASES 10
+   resample, advance, reached-site marks, branch, brick and cell scan,
+   scatter, child scatter, dirty-brick pass, containment, stop linking,
+   nucleation, finish, stopped-store re-sort. */
+#define GE_N_PHASES 13
 ge_status ge_profile(ge_ctx* ctx, int32_t on);
 ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);
 const char* ge_phase_name(int32_t phase);

@@ -60,7 +60,7 @@ class ge_step_stats(C.Structure):
                 ("n_claim_bricks", C.c_int64), ("advanced", C.c_int64), ("exited", C.c_int64),
                 ("spawners", C.c_int64), ("children", C.c_int64), ("contained", C.c_int64),
                 ("nucleated", C.c_int64), ("max_step", C.c_double), ("t", C.c_double),
-                ("step", C.c_int64), ("pair_tests", C.c_int64)]
+                ("step", C.c_int64), ("pair_tests", C.c_int64), ("dirty_tests", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,7 +121,7 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_nucleate", "ge_step",
             "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
             "ge_phase_name")
-N_PHASES = 10
+N_PHASES = 13
 
 
 def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,

@@ -43,6 +43,7 @@ constexpr int STREAM_GRID = 2048;
 // (claimed as target, reached, reached during the current step).
 constexpr uint64_t CLAIM_EMPTY = ~0ull;
 constexpr uint32_t NIL = 0xFFFFFFFFu;
+constexpr uint32_t MIXED = 0xFFFFFFFEu;  // cell owner word: particles of several grains
 
 // Field kinds.
 enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3 };
@@ -62,8 +63,10 @@ struct Counters {
   uint32_t n_fired;    // sites fired this step
   uint32_t n_live;     // active particles (A also holds records stopped at the end of a step)
   uint32_t n_newstop;  // particles stopped by containment this step
+  uint32_t n_dpart;    // particles of dirty bricks this step
   unsigned long long advanced, exited, spawners, children, contained, nucleated;
   unsigned long long pair_tests;  // candidate particles examined by containment
+  unsigned long long dirty_tests; // active particles in dirty bricks
 };
 
 // Everything a kernel needs, passed by value.
@@ -118,6 +121,12 @@ struct Dev {
   uint32_t* bcnt;      // [bricks] counts, reset by the scan
   uint4* binfo;        // [bricks] start, count, grain min, grain max
   uint32_t* bepoch;    // [bricks] step at which binfo was written
+  uint32_t* dlist;     // [bricks] dirty bricks, per-block regions of the occupied list
+  uint32_t* dlist_cnt; // [STREAM_GRID]
+  uint32_t* dpart;     // [cap_p] particles of dirty bricks (indices into B, P)
+  uint32_t* bdirty;    // [bricks] step at which the brick was dirty
+  uint32_t* csa;       // [cells] owner word of the active particles (dirty bricks, this step)
+  uint32_t* css;       // [cells] owner word of the stopped particles
   uint32_t* occ;       // [bricks] occupied-brick list
   uint64_t* scan_tmp;  // block partial sums of the brick scan
   // claims
@@ -136,9 +145,12 @@ struct Dev {
 
 // -------------------------------------------------- host-side launchers --
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s);
+void launch_mark_now(const Dev& d, hipStream_t s);
 void launch_branch(const Dev& d, hipStream_t s);
 void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s);
 void launch_scatter(const Dev& d, hipStream_t s);
+void launch_scatter_children(const Dev& d, hipStream_t s);
+void launch_dirty(const Dev& d, uint32_t epoch, hipStream_t s);
 void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s);
 void launch_stoplink(const Dev& d, hipStream_t s);
 void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s);

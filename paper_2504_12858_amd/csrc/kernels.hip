@@ -489,6 +489,11 @@ __device__ __forceinline__ void cached_or(const Dev& D, SlotCache& c, uint32_t g
   if (which & M_NOW) atomicOr(w + CB_NOW, m);
 }
 
+// Owner word of a cell: NIL (empty), the one grain of its particles, or MIXED.
+__device__ __forceinline__ uint32_t owner_merge(uint32_t own, uint32_t g) {
+  return own == NIL ? g : (own == g ? g : MIXED);
+}
+
 // ------------------------------------------------------- stopped store ----
 // Writes record r (state STOPPED) and its position at slot j of the stopped
 // store and links it into the cell list of recently stopped particles.
@@ -505,6 +510,16 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P
   const uint32_t ci = cell_index(D, c.x, c.y, c.z);
   const uint32_t old = atomicExch(&D.shead[ci], j);
   D.snext[j] = old;
+  // Owner word of the cell's stopped particles; it only moves from NIL to a
+  // grain to MIXED, so a stale read costs one failed compare-and-swap.
+  uint32_t own = D.css[ci];
+  for (;;) {
+    const uint32_t nw = owner_merge(own, g);
+    if (nw == own) break;
+    const uint32_t prev = atomicCAS(&D.css[ci], own, nw);
+    if (prev == own) break;
+    own = prev;
+  }
   const uint32_t b = ci / (uint32_t)BRICK_CELLS;
   atomicMin(&D.sbsum[b].x, g);
   atomicMax(&D.sbsum[b].y, g);
@@ -837,31 +852,114 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
       }
       if (head) note_grain(D, bkey, g);
     }
-    if (fl & FL_SPAWN) {
-      const uint32_t gs = rec_grain(r);
-      const int d = rec_dir(r);
-      int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
-      S[d >> 1] += (d & 1) ? -1 : 1;
-      claim_clear_now(D, gs, S[0], S[1], S[2]);
-      const uint32_t mask = (fl >> 8) & 63u;
-      if (mask) {
-        const float* G = D.gtab + (size_t)gs * GT_STRIDE;
-        const float sc = rec_s(r) - D.lambda0;
-        for (int dd = 0; dd < 6; ++dd) {
-          if (!(mask & (1u << dd))) continue;
-          const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
-          const C3 c = cell_of(D, xc);
-          const uint32_t ci = cell_index(D, c.x, c.y, c.z);
-          const uint32_t rank = atomicSub(&D.ccnt[ci], 1u) - 1u;
-          const uint32_t dst = D.cstart[ci] + rank;
-          if (dst < D.cap_p) {
-            D.B[dst] = make_rec(sc, gs, dd, S[0], S[1], S[2], ST_ACTIVE);
-            D.P[dst] = pos4(xc, gs);
-          }
-          note_grain(D, ci / (uint32_t)BRICK_CELLS, gs);
+  }
+}
+
+// Children of the spawners (from the per-block spawner lists) to their cell
+// slots; clears the spawners' marks of the current step.
+__global__ __launch_bounds__(TPB) void k_scatter_children(Dev D) {
+  if (dead(D)) return;
+  const uint32_t lb = logical_block();
+  const uint32_t beg = region_begin(D.cnt->n_active, lb);
+  const uint32_t cnt = D.spawn_cnt[lb];
+  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
+    const uint4 r = D.A[D.spawn[beg + k]];
+    const uint32_t fl = rec_fl(r);
+    const uint32_t gs = rec_grain(r);
+    const int d = rec_dir(r);
+    int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
+    S[d >> 1] += (d & 1) ? -1 : 1;
+    claim_clear_now(D, gs, S[0], S[1], S[2]);
+    const uint32_t mask = (fl >> 8) & 63u;
+    if (!mask) continue;
+    const float* G = D.gtab + (size_t)gs * GT_STRIDE;
+    const float sc = rec_s(r) - D.lambda0;
+    for (int dd = 0; dd < 6; ++dd) {
+      if (!(mask & (1u << dd))) continue;
+      const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
+      const C3 c = cell_of(D, xc);
+      const uint32_t ci = cell_index(D, c.x, c.y, c.z);
+      const uint32_t rank = atomicSub(&D.ccnt[ci], 1u) - 1u;
+      const uint32_t dst = D.cstart[ci] + rank;
+      if (dst < D.cap_p) {
+        D.B[dst] = make_rec(sc, gs, dd, S[0], S[1], S[2], ST_ACTIVE);
+        D.P[dst] = pos4(xc, gs);
+      }
+      note_grain(D, ci / (uint32_t)BRICK_CELLS, gs);
+    }
+  }
+}
+
+// One wave per occupied brick: the brick is "dirty" when it holds particles
+// of several grains or one of its 27 neighbourhood bricks (itself included)
+// holds a particle of another grain, active this step or stopped.  A
+// particle's contact stencil lies inside its brick's neighbourhood, so
+// particles of clean bricks cannot meet another grain.  Each block takes a
+// contiguous chunk of the occupied-brick list and lists its dirty bricks in
+// its own region of `dlist`.
+__global__ __launch_bounds__(TPB) void k_dirty(Dev D, uint32_t epoch) {
+  if (dead(D)) return;
+  __shared__ uint32_t s_n, s_np, s_base;
+  if (threadIdx.x == 0) {
+    s_n = 0;
+    s_np = 0;
+  }
+  __syncthreads();
+  const uint32_t nocc = D.cnt->n_occ;
+  const Chunk ch = chunk_of(nocc, TPB / 64);
+  const int lane = lane_id();
+  const int nbx = D.nb[0], nby = D.nb[1], nbz = D.nb[2];
+  for (uint32_t k = ch.begin + (threadIdx.x >> 6); k < ch.end; k += TPB / 64) {
+    const uint32_t b = D.occ[k];
+    const uint4 own = D.binfo[b];
+    const uint32_t g = own.z;
+    bool foreign = false;
+    if (lane < 27) {
+      const int bx = (int)(b % (uint32_t)nbx) + lane % 3 - 1;
+      const int by = (int)((b / (uint32_t)nbx) % (uint32_t)nby) + (lane / 3) % 3 - 1;
+      const int bz = (int)(b / ((uint32_t)nbx * (uint32_t)nby)) + lane / 9 - 1;
+      if (bx >= 0 && by >= 0 && bz >= 0 && bx < nbx && by < nby && bz < nbz) {
+        const uint32_t nb = ((uint32_t)bz * (uint32_t)nby + (uint32_t)by) * (uint32_t)nbx + (uint32_t)bx;
+        if (D.bepoch[nb] == epoch) {
+          const uint4 inf = D.binfo[nb];
+          if (!(inf.z == g && inf.w == g)) foreign = true;
         }
+        const uint2 sb = D.sbsum[nb];
+        if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) foreign = true;
       }
     }
+    const bool dirty = (own.z != own.w) || (__ballot(foreign) != 0ull);
+    if (!dirty) continue;
+    if (lane == 0) {
+      D.dlist[ch.begin + atomicAdd(&s_n, 1u)] = b;
+      D.bdirty[b] = epoch;
+      atomicAdd(&s_np, own.y);
+    }
+    // Owner grain of the active particles of each of the brick's 64 cells
+    // (one lane per cell).
+    const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
+    const uint32_t st = D.cstart[ci];
+    const uint32_t en = lane + 1 < BRICK_CELLS ? D.cstart[ci + 1] : own.x + own.y;
+    uint32_t owner = NIL;
+    for (uint32_t j = st; j < en; ++j) owner = owner_merge(owner, grain_of(D.P[j]));
+    D.csa[ci] = owner;
+  }
+  __syncthreads();
+  // The particles of the block's dirty bricks go to one contiguous stretch
+  // of the global dirty-particle list.
+  if (threadIdx.x == 0) {
+    D.dlist_cnt[logical_block()] = s_n;
+    s_base = s_np ? atomicAdd(&D.cnt->n_dpart, s_np) : 0u;
+    s_np = 0;
+  }
+  __syncthreads();
+  const uint32_t nd = s_n, base = s_base;
+  for (uint32_t k = threadIdx.x >> 6; k < nd; k += TPB / 64) {
+    const uint4 own = D.binfo[D.dlist[ch.begin + k]];
+    uint32_t off = 0;
+    if (lane == 0) off = atomicAdd(&s_np, own.y);
+    off = __shfl(off, 0);
+    for (uint32_t i = (uint32_t)lane; i < own.y; i += 64u) D.dpart[base + off + i] = own.x + i;
   }
 }
 
@@ -918,21 +1016,120 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
   return false;
 }
 
+// Owner words of one cell for a particle of grain g: whether the cell holds
+// active (this step) or stopped particles of another grain.  All loads are
+// independent.  Active owner: the cell's own word for dirty bricks; a clean
+// occupied brick holds a single grain (its binfo grain); an unoccupied brick
+// holds no active particle.
+struct CellOwners {
+  uint32_t ci, b;
+  bool act, stp;
+};
+
+__device__ __forceinline__ CellOwners cell_owners(const Dev& D, uint32_t epoch, int x, int y,
+                                                  int z, uint32_t g) {
+  CellOwners o;
+  o.b = brick_index(D, x, y, z);
+  o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
+  const uint32_t be = D.bepoch[o.b];
+  const uint32_t bd = D.bdirty[o.b];
+  const uint32_t bg = D.binfo[o.b].z;
+  const uint32_t ca = D.csa[o.ci];
+  const uint32_t cs = D.css[o.ci];
+  const uint32_t aown = be != epoch ? NIL : (bd == epoch ? ca : bg);
+  o.act = aown != NIL && aown != g;
+  o.stp = cs != NIL && cs != g;
+  return o;
+}
+
+// Candidates of one cell: its active particles and, when it holds stopped
+// particles of another grain, its cell-sorted and recent stopped particles.
+__device__ bool cell_hit(const Dev& D, const CellOwners& o, P3 p, uint32_t g, uint32_t& tests) {
+  const bool last = (o.ci & (uint32_t)(BRICK_CELLS - 1)) == (uint32_t)(BRICK_CELLS - 1);
+  if (o.act) {
+    const uint4 inf = D.binfo[o.b];
+    const uint32_t st = D.cstart[o.ci];
+    const uint32_t en = last ? inf.x + inf.y : D.cstart[o.ci + 1];
+    for (uint32_t j = st; j < en; ++j) {
+      const float4 q = D.P[j];
+      ++tests;
+      if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+    }
+  }
+  if (o.stp) {
+    const uint2 bs = D.bsinfo[o.b];
+    if (bs.y > 0u) {
+      const uint32_t st = D.sstart[o.ci];
+      const uint32_t en = last ? bs.x + bs.y : D.sstart[o.ci + 1];
+      for (uint32_t j = st; j < en; ++j) {
+        const float4 q = D.PS[j];
+        ++tests;
+        if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+      }
+    }
+    for (uint32_t j = D.shead[o.ci]; j != NIL; j = D.snext[j]) {
+      const float4 q = D.PS[j];
+      ++tests;
+      if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+    }
+  }
+  return false;
+}
+
+// Containment test of one particle of grain g: the owner words of all
+// stencil cells are read first (one memory round trip); candidates are
+// examined only in cells that hold another grain.  A clamped axis repeats
+// its cell; the repeat is skipped.
+__device__ bool contact(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t& tests) {
+  int x0, x1, y0, y1, z0, z1;
+  stencil_axis(D, p.x, 0, x0, x1);
+  stencil_axis(D, p.y, 1, y0, y1);
+  stencil_axis(D, p.z, 2, z0, z1);
+  if (D.stencil8) {
+    CellOwners o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int x = (k & 1) ? x1 : x0, y = (k & 2) ? y1 : y0, z = (k & 4) ? z1 : z0;
+      o[k] = cell_owners(D, epoch, x, y, z, g);
+      const bool dup = ((k & 1) && x1 == x0) || ((k & 2) && y1 == y0) || ((k & 4) && z1 == z0);
+      if (dup) o[k].act = o[k].stp = false;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if ((o[k].act || o[k].stp) && cell_hit(D, o[k], p, g, tests)) return true;
+    return false;
+  }
+  for (int z = z0; z <= z1; ++z)
+    for (int y = y0; y <= y1; ++y)
+      for (int x = x0; x <= x1; ++x) {
+        const CellOwners o = cell_owners(D, epoch, x, y, z, g);
+        if ((o.act || o.stp) && cell_hit(D, o, p, g, tests)) return true;
+      }
+  return false;
+}
+
+// Containment (Sec. 2.4): one wave per dirty brick of the block's chunk of
+// the occupied list, one lane per particle.  Particles of clean bricks cannot
+// meet another grain and are not visited.  Hits go to the block's region of
+// the stop list.
 __global__ __launch_bounds__(TPB) void k_contain(Dev D, uint32_t epoch) {
   if (dead(D)) return;
   __shared__ uint32_t s_n;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  const uint32_t n = D.cnt->n_out;
-  const Chunk ch = chunk_of(n, TPB);
+  const uint32_t lb = logical_block();
+  const uint32_t nd = D.cnt->n_dpart;
+  const Chunk ch = chunk_of(nd, TPB);
   const int lane = lane_id();
   uint32_t tests = 0;
-  for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
-    const uint32_t i = base + threadIdx.x;
+  for (uint32_t k0 = ch.begin; k0 < ch.end; k0 += TPB) {
+    const uint32_t k = k0 + threadIdx.x;
+    uint32_t i = 0;
     bool hit = false;
-    if (i < ch.end) {
+    if (k < ch.end) {
+      i = D.dpart[k];
       const float4 q = D.P[i];
-      hit = foreign_within(D, epoch, p3_of(q), grain_of(q), tests);
+      hit = contact(D, epoch, p3_of(q), grain_of(q), tests);
     }
     const unsigned long long m = __ballot(hit);
     if (m) {
@@ -943,19 +1140,21 @@ __global__ __launch_bounds__(TPB) void k_contain(Dev D, uint32_t epoch) {
       if (hit) D.newstop[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
     }
   }
-  // Diagnostics: candidate tests of the block.
   if (tests) atomicAdd(&D.cnt->pair_tests, (unsigned long long)tests);
   __syncthreads();
-  if (threadIdx.x == 0) D.newstop_cnt[logical_block()] = s_n;
+  if (threadIdx.x == 0) {
+    D.newstop_cnt[lb] = s_n;
+    if (lb == 0) atomicAdd(&D.cnt->dirty_tests, (unsigned long long)nd);
+  }
 }
 
 __global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
   if (dead(D)) return;
   __shared__ uint32_t s_base;
   const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_out, lb);
   const uint32_t cnt = D.newstop_cnt[lb];
   if (cnt == 0u) return;
+  const uint32_t beg = chunk_of(D.cnt->n_dpart, TPB).begin;
   if (threadIdx.x == 0) {
     s_base = atomicAdd(&D.cnt->n_stopped, cnt);
     atomicAdd(&D.cnt->n_newstop, cnt);
@@ -1079,6 +1278,7 @@ __global__ void k_finish(Dev D) {
   c->n_live = c->n_out - c->n_newstop + 6u * c->n_fired;
   c->contained += c->n_newstop;
   c->n_newstop = 0;
+  c->n_dpart = 0;
   c->n_cand = 0;
   c->n_fired = 0;
 }
@@ -1093,6 +1293,7 @@ __global__ void k_reset_stats(Dev D) {
   c->nucleated = 0;
   c->max_step = 0;
   c->pair_tests = 0;
+  c->dirty_tests = 0;
 }
 
 // ------------------------------------------------ stopped-store re-sort ---
@@ -1258,8 +1459,10 @@ __global__ __launch_bounds__(TPB) void k_claim_list(Dev D, const int32_t* grain,
 
 __global__ __launch_bounds__(TPB) void k_clear_bepoch(Dev D) {
   for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
-       b += (uint64_t)gridDim.x * TPB)
+       b += (uint64_t)gridDim.x * TPB) {
     D.bepoch[b] = 0u;
+    D.bdirty[b] = 0u;
+  }
 }
 
 // --------------------------------------------------------------- export ---
@@ -1429,10 +1632,8 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
   k_advance<<<STREAM_GRID, TPB, 0, s>>>(d, lin_c, dt);
 }
-void launch_branch(const Dev& d, hipStream_t s) {
-  k_mark_now<<<STREAM_GRID, TPB, 0, s>>>(d);
-  k_branch<<<STREAM_GRID, TPB, 0, s>>>(d);
-}
+void launch_mark_now(const Dev& d, hipStream_t s) { k_mark_now<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<STREAM_GRID, TPB, 0, s>>>(d); }
 static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
   const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   k_scan_reduce<<<ntiles, TPB, 0, s>>>(d);
@@ -1442,6 +1643,12 @@ static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
 }
 void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s) { scan_bricks(d, epoch, 0, s); }
 void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_scatter_children(const Dev& d, hipStream_t s) {
+  k_scatter_children<<<STREAM_GRID, TPB, 0, s>>>(d);
+}
+void launch_dirty(const Dev& d, uint32_t epoch, hipStream_t s) {
+  k_dirty<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
+}
 void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s) {
   k_contain<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
 }

@@ -33,7 +33,7 @@ struct Geometry {
 
 struct Layout {
   size_t A, B, P, spawn, spawn_cnt, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
-      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, occ, scan_tmp, ckeys, cbits, gtab, gbox,
+      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, bdirty, csa, css, occ, scan_tmp, ckeys, cbits, gtab, gbox,
       stab, sstate, cand, fgrid, cnt, total;
 };
 
@@ -126,6 +126,12 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.bcnt = put(4 * g.n_bricks);
   L.binfo = put(16 * g.n_bricks);
   L.bepoch = put(4 * g.n_bricks);
+  L.dlist = put(4 * g.n_bricks);
+  L.dlist_cnt = put(4 * ge::STREAM_GRID);
+  L.dpart = put(4 * cp);
+  L.bdirty = put(4 * g.n_bricks);
+  L.csa = put(4 * g.n_cells);
+  L.css = put(4 * g.n_cells);
   L.occ = put(4 * g.n_bricks);
   L.scan_tmp = put(8 * ntiles);
   L.ckeys = put(8 * g.slots);
@@ -193,9 +199,9 @@ struct ge_ctx {
   int64_t prof_steps = 0;
 };
 
-static const char* PHASE_NAMES[GE_N_PHASES] = {"resample", "advance",  "branch",   "scan",
-                                               "scatter",  "contain",  "stoplink", "nucleate",
-                                               "finish",   "resort"};
+static const char* PHASE_NAMES[GE_N_PHASES] = {
+    "resample", "advance", "marknow",  "branch",   "scan",   "scatter", "children",
+    "dirty",    "contain", "stoplink", "nucleate", "finish", "resort"};
 
 // Records the event that closes phase `k` of the current step (k = -1 opens
 // the step).
@@ -281,6 +287,9 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.ccnt, 0, 4 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.bcnt, 0, 4 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.bepoch, 0, 4 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.dlist_cnt, 0, 4 * ge::STREAM_GRID, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bdirty, 0, 4 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.css, 0xFF, 4 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.bsinfo, 0, 8 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.spawn_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.newstop_cnt, 0, 4 * ge::STREAM_GRID, s));
@@ -389,6 +398,12 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.bcnt = (uint32_t*)(w + L.bcnt);
   d.binfo = (uint4*)(w + L.binfo);
   d.bepoch = (uint32_t*)(w + L.bepoch);
+  d.dlist = (uint32_t*)(w + L.dlist);
+  d.dlist_cnt = (uint32_t*)(w + L.dlist_cnt);
+  d.dpart = (uint32_t*)(w + L.dpart);
+  d.bdirty = (uint32_t*)(w + L.bdirty);
+  d.csa = (uint32_t*)(w + L.csa);
+  d.css = (uint32_t*)(w + L.css);
   d.occ = (uint32_t*)(w + L.occ);
   d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
   d.ckeys = (unsigned long long*)(w + L.ckeys);
@@ -589,6 +604,7 @@ static void fill_stats(ge_ctx* c, ge_step_stats* st) {
   st->t = c->t;
   st->step = c->step;
   st->pair_tests = (int64_t)H.pair_tests;
+  st->dirty_tests = (int64_t)H.dirty_tests;
 }
 
 ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
@@ -618,20 +634,26 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
     prof_mark(c, 0);
     ge::launch_advance(d, lin_c, (float)dt, s);
     prof_mark(c, 1);
-    ge::launch_branch(d, s);
+    ge::launch_mark_now(d, s);
     prof_mark(c, 2);
-    ge::launch_scan(d, c->epoch, s);
+    ge::launch_branch(d, s);
     prof_mark(c, 3);
-    ge::launch_scatter(d, s);
+    ge::launch_scan(d, c->epoch, s);
     prof_mark(c, 4);
-    ge::launch_contain(d, c->epoch, s);
+    ge::launch_scatter(d, s);
     prof_mark(c, 5);
-    ge::launch_stoplink(d, s);
+    ge::launch_scatter_children(d, s);
     prof_mark(c, 6);
-    ge::launch_nucleate(d, lin_c, c->epoch, s);
+    ge::launch_dirty(d, c->epoch, s);
     prof_mark(c, 7);
-    ge::launch_finish(d, s);
+    ge::launch_contain(d, c->epoch, s);
     prof_mark(c, 8);
+    ge::launch_stoplink(d, s);
+    prof_mark(c, 9);
+    ge::launch_nucleate(d, lin_c, c->epoch, s);
+    prof_mark(c, 10);
+    ge::launch_finish(d, s);
+    prof_mark(c, 11);
     // This step's sorted output becomes the next step's input.
     std::swap(d.A, d.B);
     if ((c->step + 1) % c->resort_every == 0) {
@@ -639,7 +661,7 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
       std::swap(d.S, d.S2);
       std::swap(d.PS, d.PS2);
     }
-    prof_mark(c, 9);
+    prof_mark(c, 12);
     c->t = t + dt;
     c->step += 1;
   }
@@ -681,6 +703,7 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
       fill_stats(c, &v);
       v.advanced = v.exited = v.spawners = v.children = v.contained = v.nucleated = 0;
       v.pair_tests = 0;
+      v.dirty_tests = 0;
       v.max_step = 0;
       std::memcpy(out, &v, sizeof(v));
       return error_status(c, H.err);
