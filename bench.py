@@ -11,14 +11,25 @@ value     = particle updates (active particles advanced) over the K steps / s
 roofline  = the dominant phase's algorithmic bytes per launch / its average
             launch duration (HIP events on the context's stream over the
             timed region), against the 8 TB/s HBM peak
+step_roofline = value x the method's algorithmic bytes per update of the whole
+            step (83 B at this workload) against the same peak
 cpu_baseline = the FP64 oracle stepping a spatial window of the same snapshot
             on the host cores
+
+The timed region is bracketed by roctxProfilerResume / roctxProfilerPause, so
+`rocprofv3 --selected-regions` records exactly the timed launches.
+`--copy-probe MB` instead runs a plain device copy of MB megabytes inside such
+a region (the calibration of the HBM byte counters) and exits.
 
 Progress goes to stderr; one JSON line goes to stdout.
 """
 import argparse
+import ctypes
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +41,12 @@ METRIC = "envelope particle-updates/s @20M FP32 vs plain; batched & adjoint vs p
 CET_KNOBS = dict(dT0=12.0, lambda0=1e-6, h=2e-6)
 TARGET_ACTIVE = 20_000_000
 HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per particle update of the whole step at this workload:
+# read state 20, write position and travel 16, write the cell-ordered record
+# 16, read it in the containment sweep 16, cell key 8, field resample write
+# and gather read 2 x 64 MiB per step over ~20M updates 6.7.
+STEP_BYTES_PER_UPDATE = 83.0
+KERNEL_SOURCES = ("paper_2504_12858_amd/csrc/kernels.hip", "paper_2504_12858_amd/csrc/internal.h")
 
 # Algorithmic bytes per unit of each phase (what the method must move):
 #   advance  : read and write the 16-B record of each active particle
@@ -44,6 +61,67 @@ PHASE_BYTES = {"advance": 32, "scatter": 48, "contain": 16, "branch": 32, "resam
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+class ProfilerRegion:
+    """roctxProfilerResume / Pause when the roctx library is present (a no-op
+    without a profiler attached)."""
+
+    def __init__(self):
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(ctypes.c_uint64(0))
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(ctypes.c_uint64(0))
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (profiles/*hbm_traffic*.md), or None when there is none for this kernel or
+    the kernel sources changed since the counters were taken."""
+    sha = kernel_sources_sha()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*hbm_traffic*.md"))):
+        text = open(path).read()
+        fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
+        if fields.get("kernel") == kernel and fields.get("kernel_sources_sha256") == sha:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
+def copy_probe(mb):
+    """A plain device copy (elementwise multiply by one) of `mb` MB, three
+    times, inside a profiler region: reads and writes mb MB per launch."""
+    import torch
+    n = int(mb * 1e6) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    reg = ProfilerRegion()
+    reg.resume()
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    reg.pause()
+    print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
 
 
 def cet_workload():
@@ -123,10 +201,11 @@ def cpu_baseline(ctx, w, budget_s=15.0, max_steps=8):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--target", type=int, default=TARGET_ACTIVE)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -134,6 +213,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     w = cet_workload()
     t_build = time.perf_counter()
     ctx = make_context(w)
@@ -143,11 +225,14 @@ def main():
         ctx.step(w.dt, args.warmup)
     torch.cuda.synchronize()
     ctx.profile(1)
+    region = ProfilerRegion()
     torch.cuda.synchronize()
+    region.resume()
     t0 = time.perf_counter()
     stats = ctx.step(w.dt, args.steps)           # synchronises at the end
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    region.pause()
     phases, n_prof = ctx.profile_read()
     ctx.profile(0)
     elapsed = t1 - t0
@@ -167,10 +252,16 @@ def main():
     elif dom == "branch":
         units = stats["spawners"] / args.steps
     achieved = PHASE_BYTES[dom] * units / (avg_ms * 1e-3) / 1e9
+    kname = "k_" + dom
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom, "bytes_per_unit": PHASE_BYTES[dom],
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kname),
+                "kernel": kname, "bytes_per_unit": PHASE_BYTES[dom],
                 "units_per_launch": round(units), "avg_launch_ms": round(avg_ms, 4)}
+    step_gbs = value * STEP_BYTES_PER_UPDATE / 1e9
+    step_roofline = {"bound": "hbm", "bytes_per_update": STEP_BYTES_PER_UPDATE,
+                     "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     out = {
         "metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -184,6 +275,7 @@ def main():
                    "active_after": stats["n_active"], "stopped_after": stats["n_stopped"]},
         "phases_ms_per_step": {k: round(v / max(n_prof, 1), 4) for k, v in phases.items()},
         "roofline": roofline,
+        "step_roofline": step_roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)

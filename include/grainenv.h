@@ -80,7 +80,7 @@ typedef int32_t ge_status;
  * contact radius rc must satisfy rc <= h and rc <= lambda0; with rc <= h/2
  * the containment test visits 2^3 cells per particle, otherwise 3^3.
  * Lattice sites must stay within +-16000 of a grain's centre:
- * (box diagonal) / lambda0 < 16000.  Dense per-cell tables take 16 bytes per
+ * (box diagonal) / lambda0 < 16000.  Dense per-cell tables take 24 bytes per
  * cell (padded to whole bricks).
  */
 typedef struct ge_params {

@@ -43,7 +43,8 @@ constexpr int STREAM_GRID = 2048;
 // (claimed as target, reached, reached during the current step).
 constexpr uint64_t CLAIM_EMPTY = ~0ull;
 constexpr uint32_t NIL = 0xFFFFFFFFu;
-constexpr uint32_t MIXED = 0xFFFFFFFEu;  // cell owner word: particles of several grains
+constexpr uint32_t MIXED = 0xFFFFFFFEu;  // owner word: particles of several grains
+constexpr uint32_t BOWN_CELLS = 0xFFFFFFFDu;  // brick owner word: see the cells' words
 
 // Field kinds.
 enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3 };
@@ -124,9 +125,10 @@ struct Dev {
   uint32_t* dlist;     // [bricks] dirty bricks, per-block regions of the occupied list
   uint32_t* dlist_cnt; // [STREAM_GRID]
   uint32_t* dpart;     // [cap_p] particles of dirty bricks (indices into B, P)
-  uint32_t* bdirty;    // [bricks] step at which the brick was dirty
-  uint32_t* csa;       // [cells] owner word of the active particles (dirty bricks, this step)
-  uint32_t* css;       // [cells] owner word of the stopped particles
+  uint2* bown;         // [bricks] {step, owner word of the active particles: the grain of a
+                       //  single-grain brick, or BOWN_CELLS for a dirty brick}
+  uint2* cown;         // [cells] {owner word of the active particles (dirty bricks, this
+                       //  step), owner word of the stopped particles}
   uint32_t* occ;       // [bricks] occupied-brick list
   uint64_t* scan_tmp;  // block partial sums of the brick scan
   // claims

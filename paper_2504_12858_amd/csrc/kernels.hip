@@ -512,11 +512,12 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P
   D.snext[j] = old;
   // Owner word of the cell's stopped particles; it only moves from NIL to a
   // grain to MIXED, so a stale read costs one failed compare-and-swap.
-  uint32_t own = D.css[ci];
+  uint32_t* sown = &D.cown[ci].y;
+  uint32_t own = *sown;
   for (;;) {
     const uint32_t nw = owner_merge(own, g);
     if (nw == own) break;
-    const uint32_t prev = atomicCAS(&D.css[ci], own, nw);
+    const uint32_t prev = atomicCAS(sown, own, nw);
     if (prev == own) break;
     own = prev;
   }
@@ -929,10 +930,10 @@ __global__ __launch_bounds__(TPB) void k_dirty(Dev D, uint32_t epoch) {
       }
     }
     const bool dirty = (own.z != own.w) || (__ballot(foreign) != 0ull);
+    if (lane == 0) D.bown[b] = make_uint2(epoch, dirty ? BOWN_CELLS : g);
     if (!dirty) continue;
     if (lane == 0) {
       D.dlist[ch.begin + atomicAdd(&s_n, 1u)] = b;
-      D.bdirty[b] = epoch;
       atomicAdd(&s_np, own.y);
     }
     // Owner grain of the active particles of each of the brick's 64 cells
@@ -942,7 +943,7 @@ __global__ __launch_bounds__(TPB) void k_dirty(Dev D, uint32_t epoch) {
     const uint32_t en = lane + 1 < BRICK_CELLS ? D.cstart[ci + 1] : own.x + own.y;
     uint32_t owner = NIL;
     for (uint32_t j = st; j < en; ++j) owner = owner_merge(owner, grain_of(D.P[j]));
-    D.csa[ci] = owner;
+    D.cown[ci].x = owner;
   }
   __syncthreads();
   // The particles of the block's dirty bricks go to one contiguous stretch
@@ -1017,10 +1018,10 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
 }
 
 // Owner words of one cell for a particle of grain g: whether the cell holds
-// active (this step) or stopped particles of another grain.  All loads are
-// independent.  Active owner: the cell's own word for dirty bricks; a clean
-// occupied brick holds a single grain (its binfo grain); an unoccupied brick
-// holds no active particle.
+// active (this step) or stopped particles of another grain.  Two independent
+// 8-byte loads: the brick word {step, grain of a single-grain brick or
+// BOWN_CELLS} and the cell word {active owner, stopped owner}.  A brick not
+// occupied this step holds no active particle.
 struct CellOwners {
   uint32_t ci, b;
   bool act, stp;
@@ -1031,79 +1032,120 @@ __device__ __forceinline__ CellOwners cell_owners(const Dev& D, uint32_t epoch, 
   CellOwners o;
   o.b = brick_index(D, x, y, z);
   o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
-  const uint32_t be = D.bepoch[o.b];
-  const uint32_t bd = D.bdirty[o.b];
-  const uint32_t bg = D.binfo[o.b].z;
-  const uint32_t ca = D.csa[o.ci];
-  const uint32_t cs = D.css[o.ci];
-  const uint32_t aown = be != epoch ? NIL : (bd == epoch ? ca : bg);
+  const uint2 bw = D.bown[o.b];
+  const uint2 cw = D.cown[o.ci];
+  const uint32_t aown = bw.x != epoch ? NIL : (bw.y == BOWN_CELLS ? cw.x : bw.y);
   o.act = aown != NIL && aown != g;
-  o.stp = cs != NIL && cs != g;
+  o.stp = cw.y != NIL && cw.y != g;
   return o;
 }
 
-// Candidates of one cell: its active particles and, when it holds stopped
-// particles of another grain, its cell-sorted and recent stopped particles.
-__device__ bool cell_hit(const Dev& D, const CellOwners& o, P3 p, uint32_t g, uint32_t& tests) {
-  const bool last = (o.ci & (uint32_t)(BRICK_CELLS - 1)) == (uint32_t)(BRICK_CELLS - 1);
-  if (o.act) {
-    const uint4 inf = D.binfo[o.b];
-    const uint32_t st = D.cstart[o.ci];
-    const uint32_t en = last ? inf.x + inf.y : D.cstart[o.ci + 1];
-    for (uint32_t j = st; j < en; ++j) {
-      const float4 q = D.P[j];
-      ++tests;
-      if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
-    }
-  }
-  if (o.stp) {
-    const uint2 bs = D.bsinfo[o.b];
-    if (bs.y > 0u) {
-      const uint32_t st = D.sstart[o.ci];
-      const uint32_t en = last ? bs.x + bs.y : D.sstart[o.ci + 1];
-      for (uint32_t j = st; j < en; ++j) {
-        const float4 q = D.PS[j];
-        ++tests;
-        if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
-      }
-    }
-    for (uint32_t j = D.shead[o.ci]; j != NIL; j = D.snext[j]) {
-      const float4 q = D.PS[j];
-      ++tests;
-      if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
-    }
+__device__ __forceinline__ bool meets(float4 q, P3 p, uint32_t g, float rc2) {
+  return grain_of(q) != g && dist2(p, p3_of(q)) < rc2;
+}
+
+// Candidates Q[st, en) in groups of four independent loads (the tail group
+// repeats its last candidate, which does not change the outcome).
+__device__ __forceinline__ bool scan_range(const float4* __restrict__ Q, uint32_t st,
+                                           uint32_t en, P3 p, uint32_t g, float rc2,
+                                           uint32_t& tests) {
+  for (uint32_t j = st; j < en; j += 4u) {
+    const uint32_t l = en - 1u;
+    const float4 q0 = Q[j];
+    const float4 q1 = Q[min(j + 1u, l)];
+    const float4 q2 = Q[min(j + 2u, l)];
+    const float4 q3 = Q[min(j + 3u, l)];
+    tests += min(en - j, 4u);
+    const int m = (int)meets(q0, p, g, rc2) | (int)meets(q1, p, g, rc2) |
+                  (int)meets(q2, p, g, rc2) | (int)meets(q3, p, g, rc2);
+    if (m) return true;
   }
   return false;
 }
 
-// Containment test of one particle of grain g: the owner words of all
-// stencil cells are read first (one memory round trip); candidates are
-// examined only in cells that hold another grain.  A clamped axis repeats
-// its cell; the repeat is skipped.
+// Candidate ranges of one cell: active particles [ast, aen), cell-sorted
+// stopped particles [sst, sen), recent stops from list head hd.
+struct CellRanges {
+  uint32_t ast, aen, sst, sen, hd;
+};
+
+__device__ __forceinline__ CellRanges cell_ranges(const Dev& D, const CellOwners& o) {
+  CellRanges r = {0u, 0u, 0u, 0u, NIL};
+  const bool last = (o.ci & (uint32_t)(BRICK_CELLS - 1)) == (uint32_t)(BRICK_CELLS - 1);
+  if (o.act) {
+    const uint4 inf = D.binfo[o.b];
+    const uint32_t c0 = D.cstart[o.ci];
+    const uint32_t c1 = last ? 0u : D.cstart[o.ci + 1];
+    r.ast = c0;
+    r.aen = last ? inf.x + inf.y : c1;
+  }
+  if (o.stp) {
+    const uint2 bs = D.bsinfo[o.b];
+    const uint32_t t0 = D.sstart[o.ci];
+    const uint32_t t1 = last ? 0u : D.sstart[o.ci + 1];
+    const uint32_t hd = D.shead[o.ci];
+    if (bs.y > 0u) {
+      r.sst = t0;
+      r.sen = last ? bs.x + bs.y : t1;
+    }
+    r.hd = hd;
+  }
+  return r;
+}
+
+__device__ __forceinline__ bool walk_recent(const Dev& D, uint32_t j, P3 p, uint32_t g,
+                                            uint32_t& tests) {
+  for (; j != NIL; j = D.snext[j]) {
+    ++tests;
+    if (meets(D.PS[j], p, g, D.rc2)) return true;
+  }
+  return false;
+}
+
+// Containment test of one particle of grain g.  The owner words of all
+// stencil cells are read first (one memory round trip), then the candidate
+// ranges of the cells that hold another grain (a second one), then the
+// candidates.  A clamped axis repeats its cell; the repeat is skipped.
 __device__ bool contact(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t& tests) {
   int x0, x1, y0, y1, z0, z1;
   stencil_axis(D, p.x, 0, x0, x1);
   stencil_axis(D, p.y, 1, y0, y1);
   stencil_axis(D, p.z, 2, z0, z1);
+  const float rc2 = D.rc2;
   if (D.stencil8) {
     CellOwners o[8];
+    bool any = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int x = (k & 1) ? x1 : x0, y = (k & 2) ? y1 : y0, z = (k & 4) ? z1 : z0;
       o[k] = cell_owners(D, epoch, x, y, z, g);
       const bool dup = ((k & 1) && x1 == x0) || ((k & 2) && y1 == y0) || ((k & 4) && z1 == z0);
       if (dup) o[k].act = o[k].stp = false;
+      any |= o[k].act | o[k].stp;
     }
+    if (!any) return false;
+    CellRanges r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = cell_ranges(D, o[k]);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if ((o[k].act || o[k].stp) && cell_hit(D, o[k], p, g, tests)) return true;
+      if (scan_range(D.P, r[k].ast, r[k].aen, p, g, rc2, tests) ||
+          scan_range(D.PS, r[k].sst, r[k].sen, p, g, rc2, tests))
+        return true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (walk_recent(D, r[k].hd, p, g, tests)) return true;
     return false;
   }
   for (int z = z0; z <= z1; ++z)
     for (int y = y0; y <= y1; ++y)
       for (int x = x0; x <= x1; ++x) {
         const CellOwners o = cell_owners(D, epoch, x, y, z, g);
-        if ((o.act || o.stp) && cell_hit(D, o, p, g, tests)) return true;
+        if (!(o.act || o.stp)) continue;
+        const CellRanges r = cell_ranges(D, o);
+        if (scan_range(D.P, r.ast, r.aen, p, g, rc2, tests) ||
+            scan_range(D.PS, r.sst, r.sen, p, g, rc2, tests) || walk_recent(D, r.hd, p, g, tests))
+          return true;
       }
   return false;
 }
@@ -1461,7 +1503,7 @@ __global__ __launch_bounds__(TPB) void k_clear_bepoch(Dev D) {
   for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
        b += (uint64_t)gridDim.x * TPB) {
     D.bepoch[b] = 0u;
-    D.bdirty[b] = 0u;
+    D.bown[b] = make_uint2(0u, NIL);
   }
 }
 

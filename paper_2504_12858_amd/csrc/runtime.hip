@@ -33,7 +33,7 @@ struct Geometry {
 
 struct Layout {
   size_t A, B, P, spawn, spawn_cnt, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
-      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, bdirty, csa, css, occ, scan_tmp, ckeys, cbits, gtab, gbox,
+      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
       stab, sstate, cand, fgrid, cnt, total;
 };
 
@@ -129,9 +129,8 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.dlist = put(4 * g.n_bricks);
   L.dlist_cnt = put(4 * ge::STREAM_GRID);
   L.dpart = put(4 * cp);
-  L.bdirty = put(4 * g.n_bricks);
-  L.csa = put(4 * g.n_cells);
-  L.css = put(4 * g.n_cells);
+  L.bown = put(8 * g.n_bricks);
+  L.cown = put(8 * g.n_cells);
   L.occ = put(4 * g.n_bricks);
   L.scan_tmp = put(8 * ntiles);
   L.ckeys = put(8 * g.slots);
@@ -288,8 +287,8 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.bcnt, 0, 4 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.bepoch, 0, 4 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.dlist_cnt, 0, 4 * ge::STREAM_GRID, s));
-  HIPCHK(c, hipMemsetAsync(w + L.bdirty, 0, 4 * g.n_bricks, s));
-  HIPCHK(c, hipMemsetAsync(w + L.css, 0xFF, 4 * g.n_cells, s));
+  HIPCHK(c, hipMemsetAsync(w + L.bown, 0, 8 * g.n_bricks, s));
+  HIPCHK(c, hipMemsetAsync(w + L.cown, 0xFF, 8 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.bsinfo, 0, 8 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.spawn_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.newstop_cnt, 0, 4 * ge::STREAM_GRID, s));
@@ -401,9 +400,8 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.dlist = (uint32_t*)(w + L.dlist);
   d.dlist_cnt = (uint32_t*)(w + L.dlist_cnt);
   d.dpart = (uint32_t*)(w + L.dpart);
-  d.bdirty = (uint32_t*)(w + L.bdirty);
-  d.csa = (uint32_t*)(w + L.csa);
-  d.css = (uint32_t*)(w + L.css);
+  d.bown = (uint2*)(w + L.bown);
+  d.cown = (uint2*)(w + L.cown);
   d.occ = (uint32_t*)(w + L.occ);
   d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
   d.ckeys = (unsigned long long*)(w + L.ckeys);

@@ -1,0 +1,143 @@
+"""The C ABI of libgrainenv without a GPU: every function declared in
+include/grainenv.h is exported by the built library and bound by the Python
+binding, the ctypes mirrors of the public structs have the C layout, and the
+host-side parameter validation accepts and rejects what the header says.
+No call here touches a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grainenv.h")
+
+from paper_2504_12858_amd import binding as B  # noqa: E402
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:ge_status|const char\s*\*)\s*(ge_\w+)\s*\(", text,
+                                 flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2504_12858_amd import build as hb
+        hb.build()
+    return B.load_library()
+
+
+def test_header_declares_the_binding_names():
+    assert declared_functions() == sorted(B.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], check=True,
+                         capture_output=True, text=True).stdout
+    dyn = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in declared_functions():
+        assert name in dyn, name
+        assert getattr(lib, name) is not None
+
+
+LAYOUT_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "grainenv.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("ge_params %zu\nge_field %zu\nge_step_stats %zu\nge_particle_rec %zu\n"
+         "ge_claim_rec %zu\nge_query_args %zu\nge_state_in %zu\n",
+         sizeof(ge_params), sizeof(ge_field), sizeof(ge_step_stats), sizeof(ge_particle_rec),
+         sizeof(ge_claim_rec), sizeof(ge_query_args), sizeof(ge_state_in));
+  F(ge_params, lambda0) F(ge_params, cap_particles) F(ge_params, cap_claim_bricks)
+  F(ge_params, field_n) F(ge_params, resort_every)
+  F(ge_field, data) F(ge_field, data_on_device) F(ge_field, q) F(ge_field, dT_min)
+  F(ge_step_stats, max_step) F(ge_step_stats, dirty_tests)
+  F(ge_particle_rec, grain) F(ge_particle_rec, dir) F(ge_particle_rec, cell)
+  F(ge_state_in, n_particles) F(ge_state_in, c_flags) F(ge_state_in, step)
+  return 0;
+}
+"""
+
+
+def test_ctypes_mirrors_match_the_c_layout(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(LAYOUT_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    c_side = dict(line.split() for line in subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    types = {"ge_params": B.ge_params, "ge_field": B.ge_field,
+             "ge_step_stats": B.ge_step_stats, "ge_query_args": B.ge_query_args,
+             "ge_state_in": B.ge_state_in}
+    records = {"ge_particle_rec": B.PARTICLE_DTYPE, "ge_claim_rec": B.CLAIM_DTYPE}
+    for key, val in c_side.items():
+        t, _, m = key.partition(".")
+        if t in records:
+            dt = records[t]
+            got = dt.fields[m][1] if m else dt.itemsize
+        else:
+            got = getattr(types[t], m).offset if m else C.sizeof(types[t])
+        assert got == int(val), key
+    assert int(c_side["ge_particle_rec"]) == 48 and int(c_side["ge_claim_rec"]) == 20
+
+
+def base_params(**kw):
+    args = dict(lo=(0, 0, 0), hi=(1e-3, 1e-3, 1e-3), lambda0=5e-6, h=10e-6, rc=5e-6,
+                a=(1e-5, 1e-6), b=(2.0, 3.0))
+    args.update(kw)
+    return B.make_params(**args)
+
+
+@pytest.mark.parametrize("change", [
+    dict(rc=11e-6),                 # rc > h
+    dict(rc=6e-6, lambda0=5e-6),    # rc > lambda0
+    dict(hi=(1e-3, 0.0, 1e-3)),     # empty box
+    dict(lambda0=-1.0),
+    dict(h=float("nan")),
+    dict(a=(-1e-5, 0.0)),           # negative kinetic coefficient
+    dict(cap_particles=5),
+    dict(cap_grains=0),
+    dict(field_n=(1, 2, 2)),
+    dict(lambda0=5e-8, rc=5e-8, h=1e-5),  # lattice sites beyond the 16-bit range
+    dict(hi=(1.0, 1.0, 1.0), h=1e-6, lambda0=1e-4, rc=1e-6),  # more than 2^32 cells
+    dict(resort_every=-1),
+])
+def test_validate_rejects(lib, change):
+    p = base_params(**change)
+    assert lib.ge_validate_params(C.byref(p)) == -1
+    n = C.c_size_t(0)
+    assert lib.ge_workspace_size(C.byref(p), C.byref(n)) == -1
+
+
+def test_validate_accepts_and_sizes(lib):
+    p = base_params()
+    assert lib.ge_validate_params(C.byref(p)) == 0
+    n1 = C.c_size_t(0)
+    assert lib.ge_workspace_size(C.byref(p), C.byref(n1)) == 0 and n1.value > 0
+    p2 = base_params(cap_particles=1 << 21)
+    n2 = C.c_size_t(0)
+    assert lib.ge_workspace_size(C.byref(p2), C.byref(n2)) == 0
+    # Active store: two 16-B record buffers, 16-B positions and three 4-B lists.
+    assert n2.value - n1.value >= (1 << 20) * (3 * 16 + 3 * 4)
+    assert lib.ge_validate_params(None) == -1
+
+
+def test_phase_names(lib):
+    names = [lib.ge_phase_name(i) for i in range(B.N_PHASES)]
+    assert all(isinstance(s, bytes) and s for s in names)
+    assert len(set(names)) == B.N_PHASES
+    assert b"contain" in names and b"advance" in names
+    assert lib.ge_phase_name(B.N_PHASES) in (None, b"")
+    assert lib.ge_phase_name(-1) in (None, b"")
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.ge_destroy(None) == -1
+    assert lib.ge_step(None, C.c_double(1e-4), 1, None) == -1
