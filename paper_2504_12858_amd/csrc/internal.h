@@ -143,9 +143,12 @@ struct Dev {
   uint32_t n_sites;
   // counters
   Counters* cnt;
+  // launch grids of the kernel families sharing per-block regions (host side)
+  uint32_t grid_spawn, grid_contain;
 };
 
 // -------------------------------------------------- host-side launchers --
+hipError_t resident_grids(Dev& d);  // fills grid_spawn, grid_contain for the current device
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s);
 void launch_mark_now(const Dev& d, hipStream_t s);
 void launch_branch(const Dev& d, hipStream_t s);

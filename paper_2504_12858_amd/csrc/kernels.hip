@@ -29,6 +29,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <initializer_list>
+
 namespace ge {
 
 constexpr int TPB = 256;
@@ -438,14 +441,9 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) 
   return incl - v;
 }
 
-// Start of a block's region in a particle-indexed list: the chunk that
-// chunk_of(n, TPB) gives the logical block lb on a STREAM_GRID grid.
-__device__ __forceinline__ uint32_t region_begin(uint32_t n, uint32_t lb) {
-  uint32_t per = (n + (uint32_t)STREAM_GRID - 1u) / (uint32_t)STREAM_GRID;
-  per = (per + TPB - 1u) / TPB * TPB;
-  const uint64_t b = (uint64_t)lb * per;
-  return (uint32_t)(b < n ? b : n);
-}
+// Start of this block's region in a particle-indexed list written by a
+// kernel of the same grid: its chunk_of(n, TPB).
+__device__ __forceinline__ uint32_t region_begin(uint32_t n) { return chunk_of(n, TPB).begin; }
 
 // One-entry cache of claim-hash slots: the sites a spawner tests lie within
 // two lattice steps of its reached site, mostly in the same 8^3 slot brick.
@@ -625,7 +623,7 @@ __global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
 __global__ __launch_bounds__(TPB) void k_mark_now(Dev D) {
   if (dead(D)) return;
   const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_active, lb);
+  const uint32_t beg = region_begin(D.cnt->n_active);
   const uint32_t cnt = D.spawn_cnt[lb];
   for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
     const uint4 r = D.A[D.spawn[beg + k]];
@@ -645,7 +643,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
   }
   __syncthreads();
   const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_active, lb);
+  const uint32_t beg = region_begin(D.cnt->n_active);
   const uint32_t cnt = D.spawn_cnt[lb];
   uint32_t nsp = 0, nch = 0;
   for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
@@ -861,7 +859,7 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
 __global__ __launch_bounds__(TPB) void k_scatter_children(Dev D) {
   if (dead(D)) return;
   const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_active, lb);
+  const uint32_t beg = region_begin(D.cnt->n_active);
   const uint32_t cnt = D.spawn_cnt[lb];
   for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
     const uint4 r = D.A[D.spawn[beg + k]];
@@ -1671,11 +1669,39 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
   return (unsigned)g;
 }
 
-void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
-  k_advance<<<STREAM_GRID, TPB, 0, s>>>(d, lin_c, dt);
+// Grids of the kernel families that share per-block regions: as many blocks
+// as the device keeps resident at once for the family's most register-hungry
+// kernel (a chunked kernel with a non-resident tail of blocks takes about two
+// block durations), a multiple of the 8 XCDs, at most STREAM_GRID.
+hipError_t resident_grids(Dev& d) {
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  auto family = [&](std::initializer_list<const void*> ks, uint32_t& grid) -> hipError_t {
+    int per_cu = 1 << 20;
+    for (const void* k : ks) {
+      int nb = 0;
+      const hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, TPB, 0);
+      if (r != hipSuccess) return r;
+      per_cu = std::min(per_cu, nb);
+    }
+    uint32_t g = (uint32_t)std::max(1, per_cu) * (uint32_t)std::max(1, cus);
+    g = std::min<uint32_t>(g, (uint32_t)STREAM_GRID);
+    grid = g >= 8u ? g / 8u * 8u : g;
+    return hipSuccess;
+  };
+  e = family({(const void*)k_advance, (const void*)k_mark_now, (const void*)k_branch,
+              (const void*)k_scatter_children}, d.grid_spawn);
+  if (e == hipSuccess) e = family({(const void*)k_contain, (const void*)k_stoplink}, d.grid_contain);
+  return e;
 }
-void launch_mark_now(const Dev& d, hipStream_t s) { k_mark_now<<<STREAM_GRID, TPB, 0, s>>>(d); }
-void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<STREAM_GRID, TPB, 0, s>>>(d); }
+
+void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
+  k_advance<<<d.grid_spawn, TPB, 0, s>>>(d, lin_c, dt);
+}
+void launch_mark_now(const Dev& d, hipStream_t s) { k_mark_now<<<d.grid_spawn, TPB, 0, s>>>(d); }
+void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.grid_spawn, TPB, 0, s>>>(d); }
 static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
   const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   k_scan_reduce<<<ntiles, TPB, 0, s>>>(d);
@@ -1686,15 +1712,15 @@ static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
 void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s) { scan_bricks(d, epoch, 0, s); }
 void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<STREAM_GRID, TPB, 0, s>>>(d); }
 void launch_scatter_children(const Dev& d, hipStream_t s) {
-  k_scatter_children<<<STREAM_GRID, TPB, 0, s>>>(d);
+  k_scatter_children<<<d.grid_spawn, TPB, 0, s>>>(d);
 }
 void launch_dirty(const Dev& d, uint32_t epoch, hipStream_t s) {
   k_dirty<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
 }
 void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s) {
-  k_contain<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
+  k_contain<<<d.grid_contain, TPB, 0, s>>>(d, epoch);
 }
-void launch_stoplink(const Dev& d, hipStream_t s) { k_stoplink<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_stoplink(const Dev& d, hipStream_t s) { k_stoplink<<<d.grid_contain, TPB, 0, s>>>(d); }
 void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s) {
   if (d.n_sites == 0) return;
   k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(d, lin_c, epoch);

@@ -413,7 +413,8 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.cand = (uint32_t*)(w + L.cand);
   d.n_sites = 0;
   d.cnt = (ge::Counters*)(w + L.cnt);
-  ge_status st = reset_device(c);
+  ge_status st = hip_check(c, ge::resident_grids(d), "occupancy query");
+  if (st == GE_OK) st = reset_device(c);
   if (st == GE_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "create");
   if (st != GE_OK) {
     (void)hipHostFree(c->host_cnt);
