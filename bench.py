@@ -210,6 +210,9 @@ def main():
     ap.add_argument("--target", type=int, default=TARGET_ACTIVE)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
+    ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
+                    help="autotune the launch schedule at the snapshot with STEPS steps per "
+                         "trial before the warm-up (0: default schedule)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -225,6 +228,10 @@ def main():
     ctx = make_context(w)
     snap_steps, st = advance_to_snapshot(ctx, w, args.target)
     log(f"[snapshot] reached in {time.perf_counter() - t_build:.1f} s")
+    if args.autotune:
+        t_tune = time.perf_counter()
+        best = ctx.autotune(w.dt, args.autotune)
+        log(f"[autotune] {best} in {time.perf_counter() - t_tune:.1f} s")
     if args.warmup:
         ctx.step(w.dt, args.warmup)
     torch.cuda.synchronize()
@@ -275,7 +282,9 @@ def main():
                    "sites": 1600,
                    "dt_s": w.dt, "snapshot_step": snap_steps,
                    "active_at_snapshot": st["n_active"], "stopped_at_snapshot": st["n_stopped"],
-                   "active_after": stats["n_active"], "stopped_after": stats["n_stopped"]},
+                   "active_after": stats["n_active"], "stopped_after": stats["n_stopped"],
+                   "timed_from_step": int(stats["step"]) - args.steps,
+                   "schedule": ctx.schedule(), "autotuned": bool(args.autotune)},
         "phases_ms_per_step": {k: round(v / max(n_prof, 1), 4) for k, v in phases.items()},
         "roofline": roofline,
         "step_roofline": step_roofline,

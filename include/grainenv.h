@@ -271,6 +271,29 @@ ge_status ge_profile(ge_ctx* ctx, int32_t on);
 ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);
 const char* ge_phase_name(int32_t phase);
 
+/* Launch schedule: the number of thread blocks (256 threads each) of every
+   tunable kernel of ge_step.  Kernels: advance, reached-site marks, branch,
+   cell scan, scatter, child scatter, dirty-brick pass, containment, stop
+   linking.  The schedule changes only speed, never results.  The default,
+   set by ge_create, is the number of blocks the device keeps resident at
+   once for each kernel.
+   ge_get_schedule writes the current schedule.  ge_set_schedule takes a new
+   one; an entry of 0 keeps the current value; EINVAL for an entry outside
+   [1, GE_MAX_BLOCKS].
+   ge_autotune searches the schedule kernel by kernel: for each candidate it
+   runs steps_per_trial real steps timed with the phase profiler (1 to 8
+   blocks per compute unit: the state advances by at most
+   8 * GE_N_TUNABLE * steps_per_trial steps in all), scores each by its
+   phase time per particle update and keeps the best.  It leaves the best schedule set, writes it to blocks_out
+   (nullable), and leaves phase profiling off. */
+#define GE_N_TUNABLE 9
+#define GE_MAX_BLOCKS 2048
+ge_status ge_get_schedule(ge_ctx* ctx, int32_t* blocks /*[GE_N_TUNABLE]*/);
+ge_status ge_set_schedule(ge_ctx* ctx, const int32_t* blocks /*[GE_N_TUNABLE]*/);
+ge_status ge_autotune(ge_ctx* ctx, double dt, int32_t steps_per_trial,
+                      int32_t* blocks_out /*[GE_N_TUNABLE], nullable*/);
+const char* ge_tunable_name(int32_t k);
+
 #ifdef __cplusplus
 }
 #endif

@@ -108,6 +108,10 @@ def load_library(path: str = LIB_PATH):
         "ge_profile": ([vp, C.c_int32], C.c_int32),
         "ge_profile_read": ([vp, P(C.c_double), P(C.c_int64)], C.c_int32),
         "ge_phase_name": ([C.c_int32], C.c_char_p),
+        "ge_get_schedule": ([vp, P(C.c_int32)], C.c_int32),
+        "ge_set_schedule": ([vp, P(C.c_int32)], C.c_int32),
+        "ge_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
+        "ge_tunable_name": ([C.c_int32], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -120,8 +124,11 @@ def load_library(path: str = LIB_PATH):
 EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy",
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_nucleate", "ge_step",
             "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
-            "ge_phase_name")
+            "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
+            "ge_tunable_name")
 N_PHASES = 13
+N_TUNABLE = 9
+MAX_BLOCKS = 2048
 
 
 def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,
@@ -310,6 +317,29 @@ class Context:
         self._check(self.lib.ge_profile_read(self.ctx, ms, C.byref(steps)), "ge_profile_read")
         names = [self.lib.ge_phase_name(k).decode() for k in range(N_PHASES)]
         return dict(zip(names, list(ms))), steps.value
+
+    def schedule(self):
+        """Blocks per launch of each tunable kernel, by kernel name."""
+        b = (C.c_int32 * N_TUNABLE)()
+        self._check(self.lib.ge_get_schedule(self.ctx, b), "ge_get_schedule")
+        names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
+        return dict(zip(names, list(b)))
+
+    def set_schedule(self, blocks):
+        """blocks: {kernel name: blocks}; kernels not named keep theirs."""
+        names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
+        unknown = set(blocks) - set(names)
+        if unknown:
+            raise ValueError(f"unknown kernels {sorted(unknown)}")
+        b = (C.c_int32 * N_TUNABLE)(*[int(blocks.get(n, 0)) for n in names])
+        self._check(self.lib.ge_set_schedule(self.ctx, b), "ge_set_schedule")
+
+    def autotune(self, dt, steps_per_trial=2):
+        b = (C.c_int32 * N_TUNABLE)()
+        self._check(self.lib.ge_autotune(self.ctx, float(dt), int(steps_per_trial), b),
+                    "ge_autotune")
+        names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
+        return dict(zip(names, list(b)))
 
     # ---------------------------------------------------------- helpers ---
     def counts(self):

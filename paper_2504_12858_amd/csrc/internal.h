@@ -46,6 +46,10 @@ constexpr uint32_t NIL = 0xFFFFFFFFu;
 constexpr uint32_t MIXED = 0xFFFFFFFEu;  // owner word: particles of several grains
 constexpr uint32_t BOWN_CELLS = 0xFFFFFFFDu;  // brick owner word: see the cells' words
 
+// Tunable kernels (index into Dev::sched).
+enum : int { TK_ADVANCE = 0, TK_MARKNOW, TK_BRANCH, TK_CELLSCAN, TK_SCATTER, TK_CHILDREN, TK_DIRTY,
+             TK_CONTAIN, TK_STOPLINK, TK_N };
+
 // Field kinds.
 enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3 };
 
@@ -102,6 +106,7 @@ struct Dev {
   uint32_t cap_p;
   uint32_t* spawn;        // [cap_p], per-block regions
   uint32_t* spawn_cnt;    // [STREAM_GRID]
+  uint32_t* spawn_off;    // [STREAM_GRID + 1] exclusive prefix of spawn_cnt
   uint32_t* newstop;      // [cap_p], per-block regions
   uint32_t* newstop_cnt;  // [STREAM_GRID]
   // stopped store: records S, positions PS; [0, n_sorted) cell-sorted
@@ -143,12 +148,13 @@ struct Dev {
   uint32_t n_sites;
   // counters
   Counters* cnt;
-  // launch grids of the kernel families sharing per-block regions (host side)
-  uint32_t grid_spawn, grid_contain;
+  // launch schedule: blocks per launch of each tunable kernel.  The spawn
+  // lists have sched[TK_ADVANCE] regions, the stop lists sched[TK_CONTAIN].
+  uint32_t sched[9];
 };
 
 // -------------------------------------------------- host-side launchers --
-hipError_t resident_grids(Dev& d);  // fills grid_spawn, grid_contain for the current device
+hipError_t resident_grids(Dev& d);  // default schedule for the current device
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s);
 void launch_mark_now(const Dev& d, hipStream_t s);
 void launch_branch(const Dev& d, hipStream_t s);

@@ -364,15 +364,28 @@ __device__ __forceinline__ uint32_t logical_block() {
   const uint32_t G = gridDim.x, b = blockIdx.x;
   return ((G & 7u) == 0u) ? (b & 7u) * (G >> 3) + (b >> 3) : b;
 }
-__device__ __forceinline__ Chunk chunk_of(uint32_t n, uint32_t granule) {
-  const uint32_t G = gridDim.x;
+// Chunk of [0, n) of logical block lb on a grid of G blocks (whole granules).
+__device__ __forceinline__ Chunk chunk_at(uint32_t n, uint32_t granule, uint32_t G, uint32_t lb) {
   uint32_t per = (n + G - 1u) / G;
   per = (per + granule - 1u) / granule * granule;
-  const uint64_t b = (uint64_t)logical_block() * per;
+  const uint64_t b = (uint64_t)lb * per;
   Chunk c;
   c.begin = (uint32_t)(b < n ? b : n);
   const uint64_t e = b + per;
   c.end = (uint32_t)(e < n ? e : n);
+  return c;
+}
+__device__ __forceinline__ Chunk chunk_of(uint32_t n, uint32_t granule) {
+  return chunk_at(n, granule, gridDim.x, logical_block());
+}
+// Regions of a per-block list written by a kernel of G_w blocks, as read by
+// this block: an even share [lb G_w / G, (lb + 1) G_w / G) of them, so that
+// with grids that are multiples of 8 a region is read on the XCD that wrote it.
+__device__ __forceinline__ Chunk regions_of(uint32_t G_w) {
+  const uint64_t lb = logical_block(), G = gridDim.x;
+  Chunk c;
+  c.begin = (uint32_t)(lb * G_w / G);
+  c.end = (uint32_t)((lb + 1u) * G_w / G);
   return c;
 }
 
@@ -441,9 +454,6 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) 
   return incl - v;
 }
 
-// Start of this block's region in a particle-indexed list written by a
-// kernel of the same grid: its chunk_of(n, TPB).
-__device__ __forceinline__ uint32_t region_begin(uint32_t n) { return chunk_of(n, TPB).begin; }
 
 // One-entry cache of claim-hash slots: the sites a spawner tests lie within
 // two lattice steps of its reached site, mostly in the same 8^3 slot brick.
@@ -525,7 +535,7 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P
 }
 
 // ==================================================================== step
-__global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
+__global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt) {
   if (dead(D)) return;
   __shared__ uint32_t s_nsp, s_adv, s_exit, s_bad, s_max;
   if (threadIdx.x == 0) {
@@ -619,14 +629,62 @@ __global__ __launch_bounds__(TPB) void k_advance(Dev D, float lin_c, float dt) {
   }
 }
 
+// Exclusive prefix of the per-block spawner counts (one block): spawner i
+// of the step is in the region r with spawn_off[r] <= i < spawn_off[r + 1].
+__global__ __launch_bounds__(1024) void k_spawn_scan(Dev D) {
+  __shared__ uint32_t s_w[16];
+  const uint32_t G = D.sched[TK_ADVANCE];
+  const uint32_t per = (G + 1023u) / 1024u;  // regions per thread, G <= STREAM_GRID
+  const uint32_t r0 = threadIdx.x * per;
+  uint32_t v[2] = {0u, 0u};
+  for (uint32_t k = 0; k < per && k < 2u; ++k) v[k] = r0 + k < G ? D.spawn_cnt[r0 + k] : 0u;
+  uint32_t tot;
+  const uint32_t ex = wave_excl_scan(v[0] + v[1], tot);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) wbase += s_w[w];
+  uint32_t acc = wbase + ex;
+  for (uint32_t k = 0; k < per && k < 2u; ++k) {
+    if (r0 + k < G) D.spawn_off[r0 + k] = acc;
+    acc += v[k];
+  }
+  if (threadIdx.x == 1023u) D.spawn_off[G] = acc;
+}
+
+// The step's spawners as one list: this block's even share of them, and the
+// lookup of spawner i (the region offsets are staged in LDS).
+struct SpawnView {
+  uint32_t n, G, total;
+};
+__device__ __forceinline__ SpawnView spawn_view(const Dev& D, uint32_t* s_off) {
+  SpawnView v;
+  v.n = D.cnt->n_active;
+  v.G = D.sched[TK_ADVANCE];
+  for (uint32_t r = threadIdx.x; r <= v.G; r += blockDim.x) s_off[r] = D.spawn_off[r];
+  __syncthreads();
+  v.total = s_off[v.G];
+  return v;
+}
+__device__ __forceinline__ uint32_t spawn_item(const Dev& D, const SpawnView& v,
+                                               const uint32_t* s_off, uint32_t i) {
+  uint32_t lo = 0, hi = v.G;  // s_off[lo] <= i < s_off[hi]
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_off[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return D.spawn[chunk_at(v.n, TPB, v.G, lo).begin + (i - s_off[lo])];
+}
+
 // Marks the site each spawner has reached as reached during this step.
 __global__ __launch_bounds__(TPB) void k_mark_now(Dev D) {
   if (dead(D)) return;
-  const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_active);
-  const uint32_t cnt = D.spawn_cnt[lb];
-  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
-    const uint4 r = D.A[D.spawn[beg + k]];
+  __shared__ uint32_t s_off[STREAM_GRID + 1];
+  const SpawnView v = spawn_view(D, s_off);
+  const Chunk it = chunk_of(v.total, 1u);
+  for (uint32_t i = it.begin + threadIdx.x; i < it.end; i += TPB) {
+    const uint4 r = D.A[spawn_item(D, v, s_off, i)];
     const int d = rec_dir(r);
     int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
     S[d >> 1] += (d & 1) ? -1 : 1;
@@ -642,12 +700,12 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
     s_ch = 0;
   }
   __syncthreads();
-  const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_active);
-  const uint32_t cnt = D.spawn_cnt[lb];
+  __shared__ uint32_t s_off[STREAM_GRID + 1];
+  const SpawnView v = spawn_view(D, s_off);
+  const Chunk it = chunk_of(v.total, 1u);
   uint32_t nsp = 0, nch = 0;
-  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
-    const uint32_t i = D.spawn[beg + k];
+  for (uint32_t k = it.begin + threadIdx.x; k < it.end; k += TPB) {
+    const uint32_t i = spawn_item(D, v, s_off, k);
     const uint4 r = D.A[i];
     const uint32_t g = rec_grain(r);
     const int d = rec_dir(r);
@@ -858,11 +916,11 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
 // slots; clears the spawners' marks of the current step.
 __global__ __launch_bounds__(TPB) void k_scatter_children(Dev D) {
   if (dead(D)) return;
-  const uint32_t lb = logical_block();
-  const uint32_t beg = region_begin(D.cnt->n_active);
-  const uint32_t cnt = D.spawn_cnt[lb];
-  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
-    const uint4 r = D.A[D.spawn[beg + k]];
+  __shared__ uint32_t s_off[STREAM_GRID + 1];
+  const SpawnView v = spawn_view(D, s_off);
+  const Chunk it = chunk_of(v.total, 1u);
+  for (uint32_t k = it.begin + threadIdx.x; k < it.end; k += TPB) {
+    const uint4 r = D.A[spawn_item(D, v, s_off, k)];
     const uint32_t fl = rec_fl(r);
     const uint32_t gs = rec_grain(r);
     const int d = rec_dir(r);
@@ -1152,7 +1210,7 @@ __device__ bool contact(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t
 // the occupied list, one lane per particle.  Particles of clean bricks cannot
 // meet another grain and are not visited.  Hits go to the block's region of
 // the stop list.
-__global__ __launch_bounds__(TPB) void k_contain(Dev D, uint32_t epoch) {
+__global__ __launch_bounds__(TPB, 6) void k_contain(Dev D, uint32_t epoch) {
   if (dead(D)) return;
   __shared__ uint32_t s_n;
   if (threadIdx.x == 0) s_n = 0;
@@ -1191,21 +1249,25 @@ __global__ __launch_bounds__(TPB) void k_contain(Dev D, uint32_t epoch) {
 __global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
   if (dead(D)) return;
   __shared__ uint32_t s_base;
-  const uint32_t lb = logical_block();
-  const uint32_t cnt = D.newstop_cnt[lb];
-  if (cnt == 0u) return;
-  const uint32_t beg = chunk_of(D.cnt->n_dpart, TPB).begin;
-  if (threadIdx.x == 0) {
-    s_base = atomicAdd(&D.cnt->n_stopped, cnt);
-    atomicAdd(&D.cnt->n_newstop, cnt);
-  }
-  __syncthreads();
-  const uint32_t base = s_base;
-  for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
-    const uint32_t i = D.newstop[beg + k];
-    const uint4 r = with_fl(D.B[i], ST_STOPPED);
-    D.B[i] = r;
-    stopped_put(D, base + k, r, p3_of(D.P[i]));
+  const uint32_t n = D.cnt->n_dpart, G = D.sched[TK_CONTAIN];
+  const Chunk rr = regions_of(G);
+  for (uint32_t rg = rr.begin; rg < rr.end; ++rg) {
+    const uint32_t cnt = D.newstop_cnt[rg];
+    if (cnt == 0u) continue;
+    const uint32_t beg = chunk_at(n, TPB, G, rg).begin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_base = atomicAdd(&D.cnt->n_stopped, cnt);
+      atomicAdd(&D.cnt->n_newstop, cnt);
+    }
+    __syncthreads();
+    const uint32_t base = s_base;
+    for (uint32_t k = threadIdx.x; k < cnt; k += TPB) {
+      const uint32_t i = D.newstop[beg + k];
+      const uint4 r = with_fl(D.B[i], ST_STOPPED);
+      D.B[i] = r;
+      stopped_put(D, base + k, r, p3_of(D.P[i]));
+    }
   }
 }
 
@@ -1669,10 +1731,10 @@ static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
   return (unsigned)g;
 }
 
-// Grids of the kernel families that share per-block regions: as many blocks
-// as the device keeps resident at once for the family's most register-hungry
-// kernel (a chunked kernel with a non-resident tail of blocks takes about two
-// block durations), a multiple of the 8 XCDs, at most STREAM_GRID.
+// Default launch schedule: for each tunable kernel, as many blocks as the
+// device keeps resident at once (a chunked kernel whose last blocks wait for
+// a second round takes about two block durations), a multiple of the 8 XCDs,
+// at most STREAM_GRID.
 hipError_t resident_grids(Dev& d) {
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1691,36 +1753,43 @@ hipError_t resident_grids(Dev& d) {
     grid = g >= 8u ? g / 8u * 8u : g;
     return hipSuccess;
   };
-  e = family({(const void*)k_advance, (const void*)k_mark_now, (const void*)k_branch,
-              (const void*)k_scatter_children}, d.grid_spawn);
-  if (e == hipSuccess) e = family({(const void*)k_contain, (const void*)k_stoplink}, d.grid_contain);
+  const void* ks[TK_N] = {(const void*)k_advance, (const void*)k_mark_now, (const void*)k_branch,
+                          (const void*)k_cellscan, (const void*)k_scatter,
+                          (const void*)k_scatter_children, (const void*)k_dirty,
+                          (const void*)k_contain, (const void*)k_stoplink};
+  for (int t = 0; t < TK_N && e == hipSuccess; ++t) e = family({ks[t]}, d.sched[t]);
   return e;
 }
 
 void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
-  k_advance<<<d.grid_spawn, TPB, 0, s>>>(d, lin_c, dt);
+  k_advance<<<d.sched[TK_ADVANCE], TPB, 0, s>>>(d, lin_c, dt);
+  k_spawn_scan<<<1, 1024, 0, s>>>(d);
 }
-void launch_mark_now(const Dev& d, hipStream_t s) { k_mark_now<<<d.grid_spawn, TPB, 0, s>>>(d); }
-void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.grid_spawn, TPB, 0, s>>>(d); }
+void launch_mark_now(const Dev& d, hipStream_t s) {
+  k_mark_now<<<d.sched[TK_MARKNOW], TPB, 0, s>>>(d);
+}
+void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.sched[TK_BRANCH], TPB, 0, s>>>(d); }
 static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
   const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   k_scan_reduce<<<ntiles, TPB, 0, s>>>(d);
   k_scan_top<<<1, TPB, 0, s>>>(d, ntiles, mode);
   k_scan_write<<<ntiles, TPB, 0, s>>>(d, epoch, mode);
-  k_cellscan<<<STREAM_GRID, TPB, 0, s>>>(d, mode);
+  k_cellscan<<<mode == 0 ? d.sched[TK_CELLSCAN] : (uint32_t)STREAM_GRID, TPB, 0, s>>>(d, mode);
 }
 void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s) { scan_bricks(d, epoch, 0, s); }
-void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<STREAM_GRID, TPB, 0, s>>>(d); }
+void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<d.sched[TK_SCATTER], TPB, 0, s>>>(d); }
 void launch_scatter_children(const Dev& d, hipStream_t s) {
-  k_scatter_children<<<d.grid_spawn, TPB, 0, s>>>(d);
+  k_scatter_children<<<d.sched[TK_CHILDREN], TPB, 0, s>>>(d);
 }
 void launch_dirty(const Dev& d, uint32_t epoch, hipStream_t s) {
-  k_dirty<<<STREAM_GRID, TPB, 0, s>>>(d, epoch);
+  k_dirty<<<d.sched[TK_DIRTY], TPB, 0, s>>>(d, epoch);
 }
 void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s) {
-  k_contain<<<d.grid_contain, TPB, 0, s>>>(d, epoch);
+  k_contain<<<d.sched[TK_CONTAIN], TPB, 0, s>>>(d, epoch);
 }
-void launch_stoplink(const Dev& d, hipStream_t s) { k_stoplink<<<d.grid_contain, TPB, 0, s>>>(d); }
+void launch_stoplink(const Dev& d, hipStream_t s) {
+  k_stoplink<<<d.sched[TK_STOPLINK], TPB, 0, s>>>(d);
+}
 void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s) {
   if (d.n_sites == 0) return;
   k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(d, lin_c, epoch);

@@ -32,7 +32,7 @@ struct Geometry {
 };
 
 struct Layout {
-  size_t A, B, P, spawn, spawn_cnt, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
+  size_t A, B, P, spawn, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
       bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
       stab, sstate, cand, fgrid, cnt, total;
 };
@@ -110,6 +110,7 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.P = put(16 * cp);
   L.spawn = put(4 * cp);
   L.spawn_cnt = put(4 * ge::STREAM_GRID);
+  L.spawn_off = put(4 * (ge::STREAM_GRID + 1));
   L.newstop = put(4 * cp);
   L.newstop_cnt = put(4 * ge::STREAM_GRID);
   L.S = put(16 * cs);
@@ -380,6 +381,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.cap_p = (uint32_t)p->cap_particles;
   d.spawn = (uint32_t*)(w + L.spawn);
   d.spawn_cnt = (uint32_t*)(w + L.spawn_cnt);
+  d.spawn_off = (uint32_t*)(w + L.spawn_off);
   d.newstop = (uint32_t*)(w + L.newstop);
   d.newstop_cnt = (uint32_t*)(w + L.newstop_cnt);
   d.S = (uint4*)(w + L.S);
@@ -809,6 +811,75 @@ ge_status ge_profile_read(ge_ctx* c, double* ms, int64_t* steps) {
 
 const char* ge_phase_name(int32_t k) {
   return (k >= 0 && k < GE_N_PHASES) ? PHASE_NAMES[k] : "";
+}
+
+static_assert(GE_N_TUNABLE == ge::TK_N, "tunable kernel count");
+static_assert(GE_MAX_BLOCKS == ge::STREAM_GRID, "per-block list capacity");
+static const char* TUNABLE_NAMES[GE_N_TUNABLE] = {"advance", "marknow", "branch", "cellscan",
+                                                   "scatter", "children", "dirty", "contain",
+                                                   "stoplink"};
+// Phase (profiler index) whose time each tunable kernel dominates.
+static const int TUNABLE_PHASE[GE_N_TUNABLE] = {1, 2, 3, 4, 5, 6, 7, 8, 9};
+
+const char* ge_tunable_name(int32_t k) {
+  return (k >= 0 && k < GE_N_TUNABLE) ? TUNABLE_NAMES[k] : "";
+}
+
+ge_status ge_get_schedule(ge_ctx* c, int32_t* blocks) {
+  if (!c || !blocks) return GE_EINVAL;
+  for (int k = 0; k < GE_N_TUNABLE; ++k) blocks[k] = (int32_t)c->d.sched[k];
+  return GE_OK;
+}
+
+ge_status ge_set_schedule(ge_ctx* c, const int32_t* blocks) {
+  if (!c || !blocks) return GE_EINVAL;
+  for (int k = 0; k < GE_N_TUNABLE; ++k)
+    if (blocks[k] < 0 || blocks[k] > GE_MAX_BLOCKS) return fail(c, GE_EINVAL, "schedule entry out of range");
+  for (int k = 0; k < GE_N_TUNABLE; ++k)
+    if (blocks[k] > 0) c->d.sched[k] = (uint32_t)blocks[k];
+  return GE_OK;
+}
+
+ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* blocks_out) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (steps_per_trial < 1) return fail(c, GE_EINVAL, "steps_per_trial must be >= 1");
+  int dev = 0, cus = 0;
+  ge_status st = hip_check(c, hipGetDevice(&dev), "autotune");
+  if (st == GE_OK)
+    st = hip_check(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                   "autotune");
+  if (st != GE_OK) return st;
+  // Candidates: 1..8 blocks per compute unit, whole multiples of 8 blocks.
+  std::vector<uint32_t> cand;
+  for (int per = 1; per <= 8; ++per) {
+    uint32_t g = (uint32_t)std::min(per * std::max(cus, 1), GE_MAX_BLOCKS);
+    g = g >= 8u ? g / 8u * 8u : g;
+    if (cand.empty() || cand.back() != g) cand.push_back(g);
+  }
+  for (int k = 0; k < GE_N_TUNABLE; ++k) {
+    uint32_t best = c->d.sched[k];
+    double best_cost = INFINITY;
+    for (uint32_t g : cand) {
+      c->d.sched[k] = g;
+      ge_profile(c, 1);
+      ge_step_stats s{};
+      st = ge_step(c, dt, steps_per_trial, &s);
+      double ms[GE_N_PHASES];
+      int64_t steps = 0;
+      if (st == GE_OK) st = ge_profile_read(c, ms, &steps);
+      ge_profile(c, 0);
+      if (st != GE_OK) return st;
+      const double cost = ms[TUNABLE_PHASE[k]] / (double)std::max<int64_t>(s.advanced, 1);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = g;
+      }
+    }
+    c->d.sched[k] = best;
+  }
+  if (blocks_out) return ge_get_schedule(c, blocks_out);
+  return GE_OK;
 }
 
 ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {

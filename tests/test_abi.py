@@ -138,6 +138,13 @@ def test_phase_names(lib):
     assert lib.ge_phase_name(-1) in (None, b"")
 
 
+def test_tunable_names(lib):
+    names = [lib.ge_tunable_name(i) for i in range(B.N_TUNABLE)]
+    assert len(set(names)) == B.N_TUNABLE and all(names)
+    assert b"branch" in names and b"contain" in names
+    assert lib.ge_tunable_name(B.N_TUNABLE) in (None, b"")
+
+
 def test_null_context_is_rejected(lib):
     assert lib.ge_destroy(None) == -1
     assert lib.ge_step(None, C.c_double(1e-4), 1, None) == -1

@@ -164,3 +164,68 @@ def test_host_validation_errors():
     with pytest.raises(B.GrainEnvError) as e:
         ctx.step(-1.0, 1)
     assert e.value.status == B.GE_EINVAL
+
+
+def _state_bytes(ctx):
+    p, _ = gpu_parts(ctx)
+    c, _ = gpu_claims(ctx)
+    return p.tobytes(), c.tobytes()
+
+
+def test_launch_schedule_does_not_change_results():
+    """Block counts of the tunable kernels change only speed: odd schedules
+    (fewer blocks than regions, more readers than writers, single blocks)
+    give bitwise the same state as the default one."""
+    require_gpu()
+    w = _scaled_directional(seed=7)
+    ref = context_for(w)
+    default = ref.schedule()
+    ref.step(w.dt, 150)
+    want = _state_bytes(ref)
+    ref.close()
+    for sched in ({"advance": 8, "marknow": 1, "branch": 24, "children": 2048, "contain": 16,
+                   "stoplink": 1, "dirty": 1, "scatter": 40, "cellscan": 8},
+                  {"advance": 2048, "marknow": 512, "branch": 1, "children": 8, "contain": 2048,
+                   "stoplink": 2048, "dirty": 2048, "scatter": 1, "cellscan": 2048}):
+        print(f"schedule {sched}", flush=True)
+        ctx = context_for(w)
+        ctx.set_schedule(sched)
+        got = ctx.schedule()
+        assert got == {k: sched.get(k, default[k]) for k in default}
+        ctx.step(w.dt, 150)
+        assert _state_bytes(ctx) == want
+        ctx.close()
+
+
+def test_schedule_validation():
+    require_gpu()
+    w = _scaled_directional(seed=7)
+    ctx = context_for(w)
+    before = ctx.schedule()
+    for bad in ({"branch": -1}, {"contain": B.MAX_BLOCKS + 1}):
+        with pytest.raises(B.GrainEnvError):
+            ctx.set_schedule(bad)
+    with pytest.raises(ValueError):
+        ctx.set_schedule({"nonsense": 8})
+    assert ctx.schedule() == before
+    ctx.close()
+
+
+def test_autotune_keeps_results():
+    """The autotuner runs real steps; the state after it equals a plain run
+    of the same number of steps."""
+    require_gpu()
+    w = _scaled_directional(seed=8)
+    ctx = context_for(w)
+    ctx.step(w.dt, 40)
+    best = ctx.autotune(w.dt, steps_per_trial=1)
+    assert all(1 <= v <= B.MAX_BLOCKS for v in best.values())
+    assert ctx.schedule() == best
+    n = ctx.counts()["step"]
+    assert 40 < n <= 40 + 8 * B.N_TUNABLE
+    got = _state_bytes(ctx)
+    ctx.close()
+    ref = context_for(w)
+    ref.step(w.dt, n)
+    assert _state_bytes(ref) == got
+    ref.close()
