@@ -294,6 +294,73 @@ ge_status ge_autotune(ge_ctx* ctx, double dt, int32_t steps_per_trial,
                       int32_t* blocks_out /*[GE_N_TUNABLE], nullable*/);
 const char* ge_tunable_name(int32_t k);
 
+/* ------------------------------------------------------------ model ---
+   Replaces the kinetic law (Eq. (2): coefficients a, exponents b), the
+   undercooling offset theta and the branching switch between steps.  The
+   same checks as ge_validate_params apply (EINVAL). */
+ge_status ge_set_model(ge_ctx* ctx, const double a[2], const double b[2], double theta,
+                       int32_t branching);
+
+/* ----------------------------------------------------------- adjoint ---
+   Gradients of the final positions of the envelope particles with respect
+   to the kinetic coefficients a[0], a[1] (Eq. (2)) and the undercooling
+   offset theta, with the deactivation masks frozen from a recorded run.
+
+   Under frozen masks a particle's travel obeys
+     s_{k+1} = s_k + dt v(dT(x(s_k), t_k) - theta)   for its first nact steps,
+   x(s) = c + R (lambda0 site + s e_d) (Sec. 2.1.2), and particles do not
+   interact, so reverse mode runs per particle.  lambda = dL/ds is FP32;
+   the three parameter gradients are accumulated in FP64 and reduced in a
+   fixed order (bitwise reproducible).
+
+   ge_adjoint_workspace_size: device bytes of the adjoint workspace for a
+   run of n_steps steps with a checkpoint of the travel every ckpt_every
+   steps (about 56 + 4 (ckpt_every + n_steps / ckpt_every) bytes per
+   particle of cap_particles).  The caller owns the workspace (256-byte
+   aligned) and keeps it until the last call that reads the run.
+
+   ge_adjoint_forward: tracks the records of the active store at the call
+   (n_tracked of them, in storage order: particle i of the tracked set) and
+   runs n_steps ordinary steps (ge_step) while recording, per tracked
+   particle, the number of steps in which it advanced (its mask: it stops at
+   most once, by containment or by leaving the box) and its travel every
+   ckpt_every steps.  Requires branching off (ge_set_model) and a field fixed
+   in time (UNIFORM, LINEAR or GRID; LINEAR may cool at a constant rate):
+   EINVAL otherwise.  Synchronises; surfaces sticky device errors.
+
+   ge_adjoint_positions: final positions x_N of the tracked particles,
+   float [n_tracked][3] (particles that stopped keep their stop position),
+   to device or host memory.
+
+   ge_adjoint_tracked: the tracked set (host copy): identity, travel at the
+   start, mask and final travel.
+
+   ge_adjoint_backward: grad = (dL/da0, dL/da1, dL/dtheta) for
+   L = sum_i <dLdx_i, x_N,i>, i.e. for any loss whose gradient with respect
+   to the final positions is dLdx (float [n_tracked][3], device memory when
+   on_device, else host).  Reads the context's grains, field and model:
+   ESTATE when the replay of the recorded run from its checkpoints does not
+   reproduce the recorded final travel bit for bit (they changed since the
+   run).  Synchronises. */
+typedef struct ge_adjoint_rec {
+  uint32_t grain;
+  int32_t site[3];   /* departure lattice site */
+  uint8_t dir;       /* 0..5 */
+  uint8_t state0;    /* state at the start: GE_ACTIVE or GE_STOPPED */
+  uint16_t pad;
+  float s0;          /* travel at the start [m] */
+  float s_final;     /* travel after the run or at its stop [m] */
+  int32_t nact;      /* steps in which the particle advanced */
+} ge_adjoint_rec;    /* 32 bytes */
+
+ge_status ge_adjoint_workspace_size(const ge_ctx* ctx, int32_t n_steps, int32_t ckpt_every,
+                                    size_t* bytes);
+ge_status ge_adjoint_forward(ge_ctx* ctx, double dt, int32_t n_steps, int32_t ckpt_every,
+                             void* workspace, size_t bytes, int64_t* n_tracked);
+ge_status ge_adjoint_positions(ge_ctx* ctx, float* xN, size_t bytes, int32_t on_device);
+ge_status ge_adjoint_tracked(ge_ctx* ctx, ge_adjoint_rec* out, size_t bytes);
+ge_status ge_adjoint_backward(ge_ctx* ctx, const float* dLdx, int32_t on_device, double grad[3]);
+
 #ifdef __cplusplus
 }
 #endif

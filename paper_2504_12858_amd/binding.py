@@ -26,6 +26,8 @@ PARTICLE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("s", "<f4"
                            ("site", "<i4", 3), ("grain", "<u4"), ("dir", "u1"), ("state", "u1"),
                            ("pad", "<u2"), ("cell", "<i4", 3)])
 CLAIM_DTYPE = np.dtype([("grain", "<u4"), ("site", "<i4", 3), ("flags", "<u4")])
+ADJOINT_DTYPE = np.dtype([("grain", "<u4"), ("site", "<i4", 3), ("dir", "u1"), ("state0", "u1"),
+                          ("pad", "<u2"), ("s0", "<f4"), ("s_final", "<f4"), ("nact", "<i4")])
 assert PARTICLE_DTYPE.itemsize == 48 and CLAIM_DTYPE.itemsize == 20
 
 
@@ -112,6 +114,13 @@ def load_library(path: str = LIB_PATH):
         "ge_set_schedule": ([vp, P(C.c_int32)], C.c_int32),
         "ge_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
         "ge_tunable_name": ([C.c_int32], C.c_char_p),
+        "ge_set_model": ([vp, P(C.c_double), P(C.c_double), C.c_double, C.c_int32], C.c_int32),
+        "ge_adjoint_workspace_size": ([vp, C.c_int32, C.c_int32, P(C.c_size_t)], C.c_int32),
+        "ge_adjoint_forward": ([vp, C.c_double, C.c_int32, C.c_int32, vp, C.c_size_t,
+                                P(C.c_int64)], C.c_int32),
+        "ge_adjoint_positions": ([vp, vp, C.c_size_t, C.c_int32], C.c_int32),
+        "ge_adjoint_tracked": ([vp, vp, C.c_size_t], C.c_int32),
+        "ge_adjoint_backward": ([vp, vp, C.c_int32, P(C.c_double)], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -125,7 +134,8 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_nucleate", "ge_step",
             "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
-            "ge_tunable_name")
+            "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
+            "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward")
 N_PHASES = 13
 N_TUNABLE = 9
 MAX_BLOCKS = 2048
@@ -333,6 +343,60 @@ class Context:
             raise ValueError(f"unknown kernels {sorted(unknown)}")
         b = (C.c_int32 * N_TUNABLE)(*[int(blocks.get(n, 0)) for n in names])
         self._check(self.lib.ge_set_schedule(self.ctx, b), "ge_set_schedule")
+
+    def set_model(self, a, b, theta, branching):
+        av = (C.c_double * 2)(*[float(v) for v in a])
+        bv = (C.c_double * 2)(*[float(v) for v in b])
+        self._check(self.lib.ge_set_model(self.ctx, av, bv, float(theta), int(branching)),
+                    "ge_set_model")
+
+    # ---------------------------------------------------------- adjoint ---
+    def adjoint_forward(self, dt, n_steps, ckpt_every=50):
+        """Recorded run of n_steps steps (branching must be off); returns the
+        number of tracked particles.  The adjoint workspace (a torch uint8
+        tensor) is kept on the context until the next recorded run."""
+        nbytes = C.c_size_t()
+        self._check(self.lib.ge_adjoint_workspace_size(self.ctx, int(n_steps), int(ckpt_every),
+                                                       C.byref(nbytes)),
+                    "ge_adjoint_workspace_size")
+        ws = getattr(self, "adj_workspace", None)
+        if ws is None or ws.numel() < nbytes.value:
+            self.adj_workspace = ws = self.torch.empty(nbytes.value, dtype=self.torch.uint8,
+                                                       device=self.device)
+        n = C.c_int64()
+        self._check(self.lib.ge_adjoint_forward(self.ctx, float(dt), int(n_steps), int(ckpt_every),
+                                                C.c_void_p(ws.data_ptr()), ws.numel(),
+                                                C.byref(n)), "ge_adjoint_forward")
+        self.adj_n = n.value
+        return n.value
+
+    def adjoint_positions(self):
+        """Final positions of the tracked particles: torch float32 [n, 3] on the device."""
+        out = self.torch.empty((self.adj_n, 3), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.ge_adjoint_positions(self.ctx, C.c_void_p(out.data_ptr()),
+                                                  4 * out.numel(), 1), "ge_adjoint_positions")
+        return out
+
+    def adjoint_tracked(self) -> np.ndarray:
+        out = np.zeros(self.adj_n, ADJOINT_DTYPE)
+        self._check(self.lib.ge_adjoint_tracked(self.ctx, _ptr(out), out.nbytes),
+                    "ge_adjoint_tracked")
+        return out
+
+    def adjoint_backward(self, dLdx):
+        """(dL/da0, dL/da1, dL/dtheta) for dL/dx_N = dLdx, a torch float32
+        [n, 3] tensor on the device or a numpy array."""
+        g = (C.c_double * 3)()
+        if isinstance(dLdx, np.ndarray):
+            arr = np.ascontiguousarray(dLdx, np.float32).reshape(-1, 3)
+            assert len(arr) == self.adj_n
+            rc = self.lib.ge_adjoint_backward(self.ctx, _ptr(arr), 0, g)
+        else:
+            t = dLdx.detach().to(device=self.device, dtype=self.torch.float32).contiguous()
+            assert tuple(t.shape) == (self.adj_n, 3)
+            rc = self.lib.ge_adjoint_backward(self.ctx, C.c_void_p(t.data_ptr()), 1, g)
+        self._check(rc, "ge_adjoint_backward")
+        return tuple(g)
 
     def autotune(self, dt, steps_per_trial=2):
         b = (C.c_int32 * N_TUNABLE)()

@@ -148,6 +148,16 @@ struct Dev {
   uint32_t n_sites;
   // counters
   Counters* cnt;
+  // adjoint recording (all null when off): tags travel with the records of
+  // A and B (tag = index into the tracked set, NIL for untracked particles)
+  uint32_t* tagA;
+  uint32_t* tagB;
+  uint4* adj_rec;      // [tracked] records at the start of the recorded run
+  int32_t* adj_nact;   // [tracked] steps in which the particle advanced
+  float* adj_sfin;     // [tracked] travel at the end of the run (or at its stop)
+  float* adj_ck;       // [checkpoints][adj_ncap] travel at steps c * adj_K
+  uint32_t adj_ncap;
+  int32_t adj_k, adj_K;  // step of the recorded run, checkpoint interval
   // launch schedule: blocks per launch of each tunable kernel.  The spawn
   // lists have sched[TK_ADVANCE] regions, the stop lists sched[TK_CONTAIN].
   uint32_t sched[9];
@@ -184,5 +194,13 @@ void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t c
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s);
 void launch_clear_bepoch(const Dev& d, hipStream_t s);
+void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s);
+void launch_adj_final(const Dev& d, hipStream_t s);
+void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s);
+// Reverse sweep and reduction; grad_out: 3 doubles (device), mismatch: 1 uint32 (device).
+constexpr uint32_t ADJ_BLOCKS = 1024;
+void launch_adj_backward(const Dev& d, uint32_t n, int32_t n_steps, int32_t K, const float* linc,
+                         float dt, const float* dLdx, float* seg, double* part, double* grad_out,
+                         uint32_t* mismatch, hipStream_t s);
 
 }  // namespace ge

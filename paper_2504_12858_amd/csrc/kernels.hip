@@ -559,11 +559,17 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt
     uint32_t ckey = NIL, bkey = NIL;
     bool spawn = false, exited = false;
     P3 x2 = {0.0f, 0.0f, 0.0f};
+    uint32_t tag = NIL;
     if (act) {
       const uint32_t g = rec_grain(r);
       const int d = rec_dir(r);
       const int sx = rec_sx(r), sy = rec_sy(r), sz = rec_sz(r);
       const float s = rec_s(r);
+      if (D.tagA) {  // adjoint recording: checkpoint of the travel every adj_K steps
+        tag = D.tagA[i];
+        if (tag != NIL && D.adj_k % D.adj_K == 0)
+          D.adj_ck[(size_t)(D.adj_k / D.adj_K) * D.adj_ncap + tag] = s;
+      }
       const float* G = D.gtab + (size_t)g * GT_STRIDE;
       const P3 x = lattice_pos(G, sx, sy, sz, d, s);
       const float dT = field_at(D, x, lin_c) - D.theta;
@@ -613,7 +619,13 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt
       if (spawn) D.spawn[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
     }
     const uint32_t sj = wave_append(exited, &D.cnt->n_stopped);
-    if (exited) stopped_put(D, sj, r, x2);
+    if (exited) {
+      stopped_put(D, sj, r, x2);
+      if (tag != NIL) {
+        D.adj_nact[tag] = D.adj_k + 1;
+        D.adj_sfin[tag] = rec_s(r);
+      }
+    }
   }
   if (nadv) atomicAdd(&s_adv, nadv);
   if (nexit) atomicAdd(&s_exit, nexit);
@@ -906,6 +918,7 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
       if (dst < D.cap_p) {
         D.B[dst] = with_fl(r, ST_ACTIVE);
         D.P[dst] = pos4(p, g);
+        if (D.tagA) D.tagB[dst] = D.tagA[i];
       }
       if (head) note_grain(D, bkey, g);
     }
@@ -941,6 +954,7 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Dev D) {
       if (dst < D.cap_p) {
         D.B[dst] = make_rec(sc, gs, dd, S[0], S[1], S[2], ST_ACTIVE);
         D.P[dst] = pos4(xc, gs);
+        if (D.tagA) D.tagB[dst] = NIL;
       }
       note_grain(D, ci / (uint32_t)BRICK_CELLS, gs);
     }
@@ -1267,6 +1281,13 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
       const uint4 r = with_fl(D.B[i], ST_STOPPED);
       D.B[i] = r;
       stopped_put(D, base + k, r, p3_of(D.P[i]));
+      if (D.tagA) {
+        const uint32_t tag = D.tagB[i];
+        if (tag != NIL) {
+          D.adj_nact[tag] = D.adj_k + 1;
+          D.adj_sfin[tag] = rec_s(r);
+        }
+      }
     }
   }
 }
@@ -1357,8 +1378,10 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Dev D) {
           int32_t* bb = D.gbox + (size_t)g * 6;
           for (int k = 0; k < 6; ++k) bb[k] = 0;
           claim_or(D, g, 0, 0, 0, M_CLAIMED | M_REACHED);
-          for (int d = 0; d < 6; ++d)
+          for (int d = 0; d < 6; ++d) {
             D.B[n_out + 6 * nf + d] = make_rec(0.0f, g, d, 0, 0, 0, ST_ACTIVE);
+            if (D.tagA) D.tagB[n_out + 6 * nf + d] = NIL;
+          }
           D.sstate[si] = SITE_FIRED;
           s_nfired = nf + 1;
         }
@@ -1723,6 +1746,186 @@ __global__ __launch_bounds__(TPB) void k_grain_map(Dev D, int32_t n0, int32_t n1
   }
 }
 
+// ============================================================== adjoint ===
+// Gradients of the final positions of the tracked particles with respect to
+// the kinetic coefficients a0, a1 and the undercooling offset theta, with
+// the deactivation masks frozen from a recorded forward run (Sec. 2.1.2
+// kinetics, Eq. (2)).  Under frozen masks a particle's travel obeys
+//   s_{k+1} = s_k + dt v(F(x(s_k), t_k) - theta)   for steps k < nact,
+// x(s) = c + R (lambda0 site + s e_d), and nothing else couples particles.
+// Reverse mode per particle, with u = R e_d and lambda = dL/ds:
+//   lambda_N = <dL/dx_N, u>;  for k = nact-1 .. 0:
+//     dL/da_j += lambda_{k+1} dt dT_k^b_j (dT_k > 0),
+//     dL/dtheta -= lambda_{k+1} dt v'(dT_k),
+//     lambda_k = lambda_{k+1} (1 + dt v'(dT_k) <grad F(x_k), u>).
+// lambda is FP32; the parameter gradients are accumulated in FP64 and
+// reduced in a fixed order.
+
+// dv/d(dT), Eq. (2) differentiated.
+__device__ __forceinline__ float velocity_slope(const Dev& D, float dT) {
+  if (!(dT > 0.0f)) return 0.0f;
+  if (D.kin_poly) return dT * fmaf(3.0f * D.ka[1], dT, 2.0f * D.ka[0]);
+  const float l = log2f(dT);
+  return D.ka[0] * D.kb[0] * exp2f((D.kb[0] - 1.0f) * l) +
+         D.ka[1] * D.kb[1] * exp2f((D.kb[1] - 1.0f) * l);
+}
+
+// Gradient of the undercooling interpolant at p: the derivative of the
+// trilinear form, zero along an axis clamped outside the grid.
+__device__ __forceinline__ P3 field_grad(const Dev& D, P3 p) {
+  if (D.fkind == F_UNIFORM) return P3{0.0f, 0.0f, 0.0f};
+  if (D.fkind == F_LINEAR) return P3{D.fgrad[0], D.fgrad[1], D.fgrad[2]};
+  float u[3] = {(p.x - D.fo[0]) * D.finv[0], (p.y - D.fo[1]) * D.finv[1],
+                (p.z - D.fo[2]) * D.finv[2]};
+  int i0[3];
+  float f[3];
+  bool cl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float fl = floorf(u[a]);
+    fl = fmaxf(fl, 0.0f);
+    fl = fminf(fl, (float)(D.fn[a] - 2));
+    i0[a] = (int)fl;
+    const float w = u[a] - fl;
+    cl[a] = w < 0.0f || w > 1.0f;
+    f[a] = fminf(fmaxf(w, 0.0f), 1.0f);
+  }
+  const size_t sy = (size_t)D.fn[0], sz = (size_t)D.fn[0] * (size_t)D.fn[1];
+  const size_t b = (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
+  const float* __restrict__ g = D.fgrid;
+  const float c000 = g[b], c100 = g[b + 1], c010 = g[b + sy], c110 = g[b + sy + 1];
+  const float c001 = g[b + sz], c101 = g[b + sz + 1], c011 = g[b + sz + sy], c111 = g[b + sz + sy + 1];
+  const float c00 = fmaf(f[0], c100 - c000, c000), c10 = fmaf(f[0], c110 - c010, c010);
+  const float c01 = fmaf(f[0], c101 - c001, c001), c11 = fmaf(f[0], c111 - c011, c011);
+  const float c0 = fmaf(f[1], c10 - c00, c00), c1 = fmaf(f[1], c11 - c01, c01);
+  const float d0y0 = fmaf(f[1], (c110 - c010) - (c100 - c000), c100 - c000);
+  const float d0y1 = fmaf(f[1], (c111 - c011) - (c101 - c001), c101 - c001);
+  const float gx = fmaf(f[2], d0y1 - d0y0, d0y0);
+  const float gy = fmaf(f[2], (c11 - c01) - (c10 - c00), c10 - c00);
+  const float gz = c1 - c0;
+  return P3{cl[0] ? 0.0f : gx * D.finv[0], cl[1] ? 0.0f : gy * D.finv[1],
+            cl[2] ? 0.0f : gz * D.finv[2]};
+}
+
+// Tracked set: the records of the active store at the start of the
+// recorded run, tag i = storage index i.
+__global__ __launch_bounds__(TPB) void k_adj_init(Dev D, uint32_t n, int32_t n_steps) {
+  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+    const uint4 r = D.A[i];
+    D.adj_rec[i] = r;
+    D.tagA[i] = i;
+    const bool act = (rec_fl(r) & 3u) == ST_ACTIVE;
+    D.adj_nact[i] = act ? n_steps : 0;
+    D.adj_sfin[i] = rec_s(r);
+  }
+}
+
+// After the last recorded step: travel of the tracked particles still active.
+__global__ __launch_bounds__(TPB) void k_adj_final(Dev D) {
+  const uint32_t n = D.cnt->n_active;
+  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+    const uint32_t t = D.tagA[i];
+    const uint4 r = D.A[i];
+    if (t != NIL && (rec_fl(r) & 3u) == ST_ACTIVE) D.adj_sfin[t] = rec_s(r);
+  }
+}
+
+// Final positions of the tracked particles, [n][3].
+__global__ __launch_bounds__(TPB) void k_adj_positions(Dev D, uint32_t n, float* xN) {
+  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+    const uint4 r = D.adj_rec[i];
+    const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
+    const P3 x = lattice_pos(G, rec_sx(r), rec_sy(r), rec_sz(r), rec_dir(r), D.adj_sfin[i]);
+    xN[3 * i] = x.x;
+    xN[3 * i + 1] = x.y;
+    xN[3 * i + 2] = x.z;
+  }
+}
+
+// Reverse sweep, one thread per tracked particle.  Each checkpoint segment
+// of K steps is recomputed from its checkpoint into seg[j][i] (step-major,
+// coalesced) with the forward's own arithmetic, then walked backwards.
+// Per-block FP64 partial sums go to part[block][3].
+__global__ __launch_bounds__(TPB) void k_adj_backward(Dev D, uint32_t n, int32_t n_steps,
+                                                      int32_t K, const float* linc, float dt,
+                                                      const float* dLdx, float* seg,
+                                                      double* part, uint32_t* mismatch) {
+  __shared__ double s_red[3][TPB / 64];
+  double ga0 = 0.0, ga1 = 0.0, gth = 0.0;
+  uint32_t bad = 0;
+  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+    const uint4 r = D.adj_rec[i];
+    const int32_t nact = D.adj_nact[i];
+    if (nact <= 0) continue;
+    const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
+    const int d = rec_dir(r), sx = rec_sx(r), sy = rec_sy(r), sz = rec_sz(r);
+    // u = R e_d: column axis(d) of R (rows at G[4..12]), with the sign of d.
+    const int ax = d >> 1;
+    const float sg = (d & 1) ? -1.0f : 1.0f;
+    const P3 u = {sg * G[4 + ax], sg * G[7 + ax], sg * G[10 + ax]};
+    float lam = (dLdx[3 * i] * u.x + dLdx[3 * i + 1] * u.y) + dLdx[3 * i + 2] * u.z;
+    const int32_t nck = (n_steps + K - 1) / K;
+    for (int32_t c = nck - 1; c >= 0; --c) {
+      const int32_t k0 = c * K;
+      if (k0 >= nact) continue;
+      const int32_t k1 = min(k0 + K, nact);
+      float s = D.adj_ck[(size_t)c * D.adj_ncap + i];
+      for (int32_t k = k0; k < k1; ++k) {
+        seg[(size_t)(k - k0) * n + i] = s;
+        const P3 x = lattice_pos(G, sx, sy, sz, d, s);
+        const float dT = field_at(D, x, linc[k]) - D.theta;
+        s = s + velocity(D, dT) * dt;
+      }
+      if (k1 == nact && s != D.adj_sfin[i]) bad += 1;
+      for (int32_t k = k1 - 1; k >= k0; --k) {
+        const float sk = seg[(size_t)(k - k0) * n + i];
+        const P3 x = lattice_pos(G, sx, sy, sz, d, sk);
+        const float dT = field_at(D, x, linc[k]) - D.theta;
+        const float vp = velocity_slope(D, dT);
+        if (dT > 0.0f) {
+          const double w = (double)lam * (double)dt;
+          if (D.kin_poly) {
+            const double t2 = (double)dT * (double)dT;
+            ga0 += w * t2;
+            ga1 += w * t2 * (double)dT;
+          } else {
+            ga0 += w * pow((double)dT, (double)D.kb[0]);
+            ga1 += w * pow((double)dT, (double)D.kb[1]);
+          }
+        }
+        gth -= (double)lam * (double)dt * (double)vp;
+        const P3 gF = field_grad(D, x);
+        const float du = (gF.x * u.x + gF.y * u.y) + gF.z * u.z;
+        lam = lam * fmaf(dt * vp, du, 1.0f);
+      }
+    }
+  }
+  // Fixed-order block reduction: wave sums, then the waves in order.
+  double v[3] = {ga0, ga1, gth};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double x = v[q];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+    if (lane_id() == 0) s_red[q][threadIdx.x >> 6] = x;
+  }
+  if (bad) atomicAdd(mismatch, bad);
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double x = 0.0;
+    for (int w = 0; w < TPB / 64; ++w) x += s_red[threadIdx.x][w];
+    part[(size_t)blockIdx.x * 3 + threadIdx.x] = x;
+  }
+}
+
+// Sum of the per-block partials in block order (one thread per component).
+__global__ void k_adj_reduce(const double* part, uint32_t nblocks, double* out) {
+  if (threadIdx.x < 3) {
+    double x = 0.0;
+    for (uint32_t b = 0; b < nblocks; ++b) x += part[(size_t)b * 3 + threadIdx.x];
+    out[threadIdx.x] = x;
+  }
+}
+
 // ============================================================ launchers ===
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
   uint64_t g = (n + TPB - 1) / TPB;
@@ -1874,6 +2077,19 @@ void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
 }
 void launch_clear_bepoch(const Dev& d, hipStream_t s) {
   k_clear_bepoch<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
+}
+void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s) {
+  if (n) k_adj_init<<<grid_for(n, 4096), TPB, 0, s>>>(d, n, n_steps);
+}
+void launch_adj_final(const Dev& d, hipStream_t s) { k_adj_final<<<4096, TPB, 0, s>>>(d); }
+void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s) {
+  if (n) k_adj_positions<<<grid_for(n, 4096), TPB, 0, s>>>(d, n, xN);
+}
+void launch_adj_backward(const Dev& d, uint32_t n, int32_t n_steps, int32_t K, const float* linc,
+                         float dt, const float* dLdx, float* seg, double* part, double* grad_out,
+                         uint32_t* mismatch, hipStream_t s) {
+  k_adj_backward<<<ADJ_BLOCKS, TPB, 0, s>>>(d, n, n_steps, K, linc, dt, dLdx, seg, part, mismatch);
+  k_adj_reduce<<<1, 64, 0, s>>>(part, ADJ_BLOCKS, grad_out);
 }
 
 }  // namespace ge

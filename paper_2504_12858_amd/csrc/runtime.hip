@@ -197,6 +197,15 @@ struct ge_ctx {
   size_t ev_used = 0;                // events recorded since the last read
   double prof_ms[GE_N_PHASES] = {0};
   int64_t prof_steps = 0;
+  // adjoint: the caller's workspace of the last recorded run
+  struct Adj {
+    bool valid = false;
+    char* ws = nullptr;
+    uint32_t n = 0;
+    int32_t n_steps = 0, K = 0;
+    float dt = 0.0f;
+    size_t tagA, tagB, rec, nact, sfin, ck, seg, xN, dldx, linc, part, grad, mis, total;
+  } adj;
 };
 
 static const char* PHASE_NAMES[GE_N_PHASES] = {
@@ -302,6 +311,8 @@ static ge_status reset_device(ge_ctx* c) {
   c->epoch = 0;
   return GE_OK;
 }
+
+static void step_once(ge_ctx* c, double dt, float* lin_c_out);
 
 extern "C" {
 
@@ -612,10 +623,24 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
   if (!c) return GE_EINVAL;
   if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
   if (!(std::isfinite(dt) && dt > 0) || n_steps < 0) return fail(c, GE_EINVAL, "bad dt or n_steps");
+  ge::launch_reset_stats(c->d, c->stream);
+  for (int32_t k = 0; k < n_steps; ++k) step_once(c, dt, nullptr);
+  HIPCHK(c, hipGetLastError());
+  if (!stats) return GE_OK;
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  fill_stats(c, stats);
+  return error_status(c, c->host_cnt->err);
+}
+
+}  // extern "C"
+
+// One step of the method on the context's stream (no synchronisation).
+// lin_c_out (nullable) receives the LINEAR field's constant of the step.
+static void step_once(ge_ctx* c, double dt, float* lin_c_out) {
   hipStream_t s = c->stream;
   Dev& d = c->d;
-  ge::launch_reset_stats(d, s);
-  for (int32_t k = 0; k < n_steps; ++k) {
+  {
     if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
     prof_mark(c, -1);
     c->epoch += 1;
@@ -657,22 +682,20 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
     prof_mark(c, 11);
     // This step's sorted output becomes the next step's input.
     std::swap(d.A, d.B);
+    std::swap(d.tagA, d.tagB);
     if ((c->step + 1) % c->resort_every == 0) {
       ge::launch_stopped_rebuild(d, s);
       std::swap(d.S, d.S2);
       std::swap(d.PS, d.PS2);
     }
     prof_mark(c, 12);
+    if (lin_c_out) *lin_c_out = lin_c;
     c->t = t + dt;
     c->step += 1;
   }
-  HIPCHK(c, hipGetLastError());
-  if (!stats) return GE_OK;
-  ge_status st = read_counters(c);
-  if (st != GE_OK) return st;
-  fill_stats(c, stats);
-  return error_status(c, c->host_cnt->err);
 }
+
+extern "C" {
 
 // Copies `bytes` of device data at src to out (host or device).
 static ge_status deliver(ge_ctx* c, const void* src, void* out, size_t bytes) {
@@ -888,6 +911,28 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   if (S.n_grains < 0 || S.n_grains > c->p.cap_grains) return fail(c, GE_ECAPACITY, "cap_grains exceeded");
   if (S.n_particles < 0 || S.n_claims < 0) return fail(c, GE_EINVAL, "negative counts");
   if ((uint32_t)S.n_sites != c->n_sites) return fail(c, GE_EINVAL, "site count differs from registered sites");
+  // Every argument is checked before the device state is touched.
+  if ((S.n_grains > 0 && (!S.centre || !S.quat)) ||
+      (S.n_particles > 0 && (!S.grain || !S.site || !S.dir || !S.s || !S.state)) ||
+      (S.n_claims > 0 && (!S.c_grain || !S.c_site || !S.c_flags)) ||
+      (S.n_sites > 0 && !S.site_state))
+    return fail(c, GE_EINVAL, "missing arrays");
+  int64_t n_keep = 0;
+  for (int64_t i = 0; i < S.n_particles; ++i) {
+    if (S.state[i] == GE_RETIRED) continue;
+    if (S.state[i] != GE_ACTIVE && S.state[i] != GE_STOPPED) return fail(c, GE_EINVAL, "bad particle state");
+    if (S.grain[i] < 0 || S.grain[i] >= S.n_grains || S.dir[i] < 0 || S.dir[i] > 5)
+      return fail(c, GE_EINVAL, "bad particle");
+    for (int a = 0; a < 3; ++a)
+      if (std::abs(S.site[3 * i + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "site out of range");
+    ++n_keep;
+  }
+  if (n_keep > c->p.cap_particles) return fail(c, GE_ECAPACITY, "cap_particles exceeded");
+  for (int64_t k = 0; k < S.n_claims; ++k) {
+    if (S.c_grain[k] < 0 || S.c_grain[k] >= S.n_grains) return fail(c, GE_EINVAL, "bad claim grain");
+    for (int a = 0; a < 3; ++a)
+      if (std::abs(S.c_site[3 * k + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "claim site out of range");
+  }
   hipStream_t s = c->stream;
   c->dead = false;
   c->err.clear();
@@ -908,15 +953,10 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   recs.reserve((size_t)S.n_particles);
   for (int64_t i = 0; i < S.n_particles; ++i) {
     if (S.state[i] == GE_RETIRED) continue;
-    if (S.grain[i] < 0 || S.grain[i] >= S.n_grains || S.dir[i] < 0 || S.dir[i] > 5)
-      return fail(c, GE_EINVAL, "bad particle");
-    for (int a = 0; a < 3; ++a)
-      if (std::abs(S.site[3 * i + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "site out of range");
     recs.push_back(host_rec(S.s[i], (uint32_t)S.grain[i], S.dir[i], S.site[3 * i], S.site[3 * i + 1],
                             S.site[3 * i + 2],
                             S.state[i] == GE_STOPPED ? ge::ST_STOPPED : ge::ST_ACTIVE));
   }
-  if ((int64_t)recs.size() > c->p.cap_particles) return fail(c, GE_ECAPACITY, "cap_particles exceeded");
   if (!rows.empty()) {
     HIPCHK(c, hipMemcpyAsync(c->d.gtab, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->d.gbox, boxes.data(), boxes.size() * 4, hipMemcpyHostToDevice, s));
@@ -936,11 +976,6 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   st = write_counters(c);
   if (st != GE_OK) return st;
   ge::launch_classify_new(c->d, 0, (uint32_t)recs.size(), s);
-  for (int64_t k = 0; k < S.n_claims; ++k) {
-    if (S.c_grain[k] < 0 || S.c_grain[k] >= S.n_grains) return fail(c, GE_EINVAL, "bad claim grain");
-    for (int a = 0; a < 3; ++a)
-      if (std::abs(S.c_site[3 * k + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "claim site out of range");
-  }
   if (S.n_claims > 0) {
     const size_t m = (size_t)S.n_claims;
     char* buf = nullptr;
@@ -961,6 +996,192 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   c->t = S.t;
   c->step = S.step;
   return error_status(c, c->host_cnt->err);
+}
+
+// ------------------------------------------------------------- model ----
+ge_status ge_set_model(ge_ctx* c, const double a[2], const double b[2], double theta,
+                       int32_t branching) {
+  if (!c || !a || !b) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  ge_params p = c->p;
+  p.a[0] = a[0];
+  p.a[1] = a[1];
+  p.b[0] = b[0];
+  p.b[1] = b[1];
+  p.theta = theta;
+  p.branching = branching ? 1 : 0;
+  if (const char* why = check_params(&p)) return fail(c, GE_EINVAL, why);
+  c->p = p;
+  Dev& d = c->d;
+  d.ka[0] = (float)p.a[0];
+  d.ka[1] = (float)p.a[1];
+  d.kb[0] = (float)p.b[0];
+  d.kb[1] = (float)p.b[1];
+  d.kin_poly = (p.b[0] == 2.0 && p.b[1] == 3.0) ? 1 : 0;
+  d.theta = (float)p.theta;
+  d.branching = p.branching;
+  return GE_OK;
+}
+
+// ----------------------------------------------------------- adjoint ----
+// Layout of the caller's adjoint workspace for n_cap tracked particles.
+static size_t adj_layout(ge_ctx::Adj& A, uint64_t n_cap, int32_t n_steps, int32_t K) {
+  size_t off = 0;
+  auto put = [&](uint64_t bytes) {
+    const size_t o = off;
+    off += align_up(std::max<size_t>((size_t)bytes, 1));
+    return o;
+  };
+  const uint64_t nck = ((uint64_t)n_steps + (uint64_t)K - 1) / (uint64_t)K;
+  A.tagA = put(4 * n_cap);
+  A.tagB = put(4 * n_cap);
+  A.rec = put(16 * n_cap);
+  A.nact = put(4 * n_cap);
+  A.sfin = put(4 * n_cap);
+  A.ck = put(4 * n_cap * nck);
+  A.seg = put(4 * n_cap * (uint64_t)K);
+  A.xN = put(12 * n_cap);
+  A.dldx = put(12 * n_cap);
+  A.linc = put(4 * (uint64_t)n_steps);
+  A.part = put(24 * (uint64_t)ge::ADJ_BLOCKS);
+  A.grad = put(24);
+  A.mis = put(4);
+  A.total = off;
+  return off;
+}
+
+ge_status ge_adjoint_workspace_size(const ge_ctx* c, int32_t n_steps, int32_t ckpt_every,
+                                    size_t* bytes) {
+  if (!c || !bytes || n_steps < 1 || ckpt_every < 1) return GE_EINVAL;
+  ge_ctx::Adj A;
+  *bytes = adj_layout(A, (uint64_t)c->p.cap_particles, n_steps, ckpt_every);
+  return GE_OK;
+}
+
+ge_status ge_adjoint_forward(ge_ctx* c, double dt, int32_t n_steps, int32_t ckpt_every,
+                             void* workspace, size_t bytes, int64_t* n_tracked) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (!(std::isfinite(dt) && dt > 0) || n_steps < 1 || ckpt_every < 1 || !workspace)
+    return fail(c, GE_EINVAL, "bad adjoint arguments");
+  if (((uintptr_t)workspace) % ALIGN) return fail(c, GE_EINVAL, "adjoint workspace not 256-byte aligned");
+  if (c->d.branching) return fail(c, GE_EINVAL, "the recorded run needs branching off");
+  if (c->field.kind == GE_FIELD_ROSENTHAL)
+    return fail(c, GE_EINVAL, "the recorded run needs a field that is fixed in time (not ROSENTHAL)");
+  ge_ctx::Adj A;
+  if (adj_layout(A, (uint64_t)c->p.cap_particles, n_steps, ckpt_every) > bytes)
+    return fail(c, GE_EINVAL, "adjoint workspace too small");
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  if ((st = error_status(c, c->host_cnt->err)) != GE_OK) return st;
+  const uint32_t n = c->host_cnt->n_active;  // records of the active store
+  char* w = (char*)workspace;
+  A.ws = w;
+  A.n = n;
+  A.n_steps = n_steps;
+  A.K = ckpt_every;
+  A.dt = (float)dt;
+  c->adj = A;
+  c->adj.valid = false;
+  Dev& d = c->d;
+  d.tagA = (uint32_t*)(w + A.tagA);
+  d.tagB = (uint32_t*)(w + A.tagB);
+  d.adj_rec = (uint4*)(w + A.rec);
+  d.adj_nact = (int32_t*)(w + A.nact);
+  d.adj_sfin = (float*)(w + A.sfin);
+  d.adj_ck = (float*)(w + A.ck);
+  d.adj_ncap = n;
+  d.adj_K = ckpt_every;
+  hipStream_t s = c->stream;
+  ge::launch_adj_init(d, n, n_steps, s);
+  std::vector<float> linc((size_t)n_steps);
+  ge::launch_reset_stats(d, s);
+  for (int32_t k = 0; k < n_steps; ++k) {
+    d.adj_k = k;
+    step_once(c, dt, &linc[(size_t)k]);
+  }
+  ge::launch_adj_final(d, s);
+  ge::launch_adj_positions(d, n, (float*)(w + A.xN), s);
+  d.tagA = d.tagB = nullptr;  // later steps run untracked
+  HIPCHK(c, hipMemcpyAsync(w + A.linc, linc.data(), 4 * (size_t)n_steps, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipGetLastError());
+  st = read_counters(c);  // synchronises: linc is copied before it goes out of scope
+  if (st != GE_OK) return st;
+  if ((st = error_status(c, c->host_cnt->err)) != GE_OK) return st;
+  c->adj.valid = true;
+  if (n_tracked) *n_tracked = (int64_t)n;
+  return GE_OK;
+}
+
+ge_status ge_adjoint_positions(ge_ctx* c, float* xN, size_t bytes, int32_t on_device) {
+  if (!c || !xN) return GE_EINVAL;
+  if (!c->adj.valid) return fail(c, GE_ESTATE, "no recorded run");
+  const size_t need = 12 * (size_t)c->adj.n;
+  if (bytes < need) return fail(c, GE_EINVAL, "output too small");
+  HIPCHK(c, hipMemcpyAsync(xN, c->adj.ws + c->adj.xN, need,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GE_OK;
+}
+
+ge_status ge_adjoint_tracked(ge_ctx* c, ge_adjoint_rec* out, size_t bytes) {
+  if (!c || !out) return GE_EINVAL;
+  if (!c->adj.valid) return fail(c, GE_ESTATE, "no recorded run");
+  const size_t n = c->adj.n;
+  if (bytes < n * sizeof(ge_adjoint_rec)) return fail(c, GE_EINVAL, "output too small");
+  std::vector<uint32_t> rec(4 * n);
+  std::vector<int32_t> nact(n);
+  std::vector<float> sfin(n);
+  const char* w = c->adj.ws;
+  hipStream_t s = c->stream;
+  if (n) {
+    HIPCHK(c, hipMemcpyAsync(rec.data(), w + c->adj.rec, 16 * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(nact.data(), w + c->adj.nact, 4 * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(sfin.data(), w + c->adj.sfin, 4 * n, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i) {
+    const uint32_t* r = &rec[4 * i];
+    ge_adjoint_rec& o = out[i];
+    std::memset(&o, 0, sizeof(o));
+    std::memcpy(&o.s0, &r[0], 4);
+    o.grain = r[1] >> 3;
+    o.dir = (uint8_t)(r[1] & 7u);
+    o.site[0] = (int16_t)(r[2] & 0xFFFFu);
+    o.site[1] = (int16_t)(r[2] >> 16);
+    o.site[2] = (int16_t)(r[3] & 0xFFFFu);
+    o.state0 = (uint8_t)((r[3] >> 16) & 3u);
+    o.nact = nact[i];
+    o.s_final = sfin[i];
+  }
+  return GE_OK;
+}
+
+ge_status ge_adjoint_backward(ge_ctx* c, const float* dLdx, int32_t on_device, double grad[3]) {
+  if (!c || !dLdx || !grad) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (!c->adj.valid) return fail(c, GE_ESTATE, "no recorded run");
+  const ge_ctx::Adj& A = c->adj;
+  char* w = A.ws;
+  hipStream_t s = c->stream;
+  const float* g = dLdx;
+  if (!on_device) {
+    if (A.n) HIPCHK(c, hipMemcpyAsync(w + A.dldx, dLdx, 12 * (size_t)A.n, hipMemcpyHostToDevice, s));
+    g = (const float*)(w + A.dldx);
+  }
+  HIPCHK(c, hipMemsetAsync(w + A.mis, 0, 4, s));
+  ge::launch_adj_backward(c->d, A.n, A.n_steps, A.K, (const float*)(w + A.linc), A.dt, g,
+                          (float*)(w + A.seg), (double*)(w + A.part), (double*)(w + A.grad),
+                          (uint32_t*)(w + A.mis), s);
+  double out[3];
+  uint32_t mis = 0;
+  HIPCHK(c, hipMemcpyAsync(out, w + A.grad, 24, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&mis, w + A.mis, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, hipGetLastError());
+  if (mis) return fail(c, GE_ESTATE, "the replay differs from the recorded run (model, field or grains changed)");
+  for (int k = 0; k < 3; ++k) grad[k] = out[k];
+  return GE_OK;
 }
 
 }  // extern "C"
