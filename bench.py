@@ -162,6 +162,76 @@ def grain_quaternions(ctx, w):
     return w.site_xyz[idx], w.site_quat[idx]
 
 
+ADJ_STORED = 512_000
+ADJ_STEPS = 500
+ADJ_CKPT = 50
+
+
+def adjoint_leg():
+    """Recorded forward + adjoint backward against the plain forward over the
+    same window: directional growth (2 x 2 x 4 mm, linear field), 16 grains
+    (seed 5), branching on until >= 512k stored particles, then a 500-step
+    window with branching off; checkpoints every 50 steps; gradients of
+    L = sum |x_N - xhat|^2 at (a0, a1, theta = 0), targets from a run with
+    a * 1.05 and theta = +2 K."""
+    import torch
+    from paper_2504_12858_amd import workloads as W
+    from paper_2504_12858_amd import binding as B
+    from paper_2504_12858_amd.adjoint import AdjointRun
+    w = W.directional(seed=5, n_grains=16)
+    ctx = B.Context.from_workload(w, cap_particles=1 << 21, cap_stopped=1 << 21,
+                                  cap_claim_bricks=1 << 18)
+    steps = 0
+    while steps < 6000:
+        st = ctx.step(w.dt, 50)
+        steps += 50
+        if st["n_active"] + st["n_stopped"] >= ADJ_STORED:
+            break
+    log(f"[adjoint] snapshot at step {steps}: {st['n_active']} active, {st['n_stopped']} stopped")
+    run = AdjointRun.capture(ctx, w.grain_centre, w.grain_quat, w.b, w.dt, ADJ_STEPS, ADJ_CKPT)
+    a = tuple(w.a)
+
+    def restore(a0, a1, th):
+        run.restore()
+        ctx.set_model((a0, a1), w.b, th, 0)
+        torch.cuda.synchronize()
+
+    restore(a[0] * 1.05, a[1] * 1.05, 2.0)
+    ctx.adjoint_forward(w.dt, ADJ_STEPS, ADJ_CKPT)
+    xhat = ctx.adjoint_positions().clone()
+    # Warm-up of both paths (first launches load code objects).
+    restore(a[0], a[1], 0.0)
+    ctx.step(w.dt, 20)
+    restore(a[0], a[1], 0.0)
+    ctx.adjoint_forward(w.dt, ADJ_STEPS, ADJ_CKPT)
+    ctx.adjoint_backward(2.0 * (ctx.adjoint_positions() - xhat))
+    restore(a[0], a[1], 0.0)
+    t0 = time.perf_counter()
+    plain = ctx.step(w.dt, ADJ_STEPS)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    restore(a[0], a[1], 0.0)
+    t0 = time.perf_counter()
+    n = ctx.adjoint_forward(w.dt, ADJ_STEPS, ADJ_CKPT)
+    x = ctx.adjoint_positions()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dLdx = 2.0 * (x - xhat)
+    grad = ctx.adjoint_backward(dLdx)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    loss = float(((x.double() - xhat.double()) ** 2).sum())
+    ctx.close()
+    return {"workload": "directional-16-grains-512k-500-steps", "tracked": int(n),
+            "snapshot_step": steps, "steps": ADJ_STEPS, "ckpt_every": ADJ_CKPT,
+            "plain_forward_ms": round(1e3 * t_plain, 3),
+            "recorded_forward_ms": round(1e3 * (t1 - t0), 3),
+            "backward_ms": round(1e3 * (t2 - t1), 3),
+            "ratio_vs_plain": round((t2 - t0) / t_plain, 4),
+            "plain_updates": int(plain["advanced"]), "loss": loss,
+            "grad_a0_a1_theta": [float(v) for v in grad]}
+
+
 def cpu_baseline(ctx, w, budget_s=15.0, max_steps=8):
     """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot."""
     import numpy as np
@@ -209,6 +279,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--target", type=int, default=TARGET_ACTIVE)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -291,6 +362,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
+    ctx.close()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg()
+        log(f"[adjoint] {out['adjoint']}")
     print(json.dumps(out), flush=True)
 
 

@@ -198,7 +198,7 @@ void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s);
 void launch_adj_final(const Dev& d, hipStream_t s);
 void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s);
 // Reverse sweep and reduction; grad_out: 3 doubles (device), mismatch: 1 uint32 (device).
-constexpr uint32_t ADJ_BLOCKS = 1024;
+constexpr uint32_t ADJ_BLOCKS = 4096;
 void launch_adj_backward(const Dev& d, uint32_t n, int32_t n_steps, int32_t K, const float* linc,
                          float dt, const float* dLdx, float* seg, double* part, double* grad_out,
                          uint32_t* mismatch, hipStream_t s);

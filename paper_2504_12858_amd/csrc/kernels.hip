@@ -1917,13 +1917,15 @@ __global__ __launch_bounds__(TPB) void k_adj_backward(Dev D, uint32_t n, int32_t
   }
 }
 
-// Sum of the per-block partials in block order (one thread per component).
+// Sum of the per-block partials in a fixed order: lane l of wave q adds
+// blocks l, l + 64, ... of component q, then a fixed shuffle tree.
 __global__ void k_adj_reduce(const double* part, uint32_t nblocks, double* out) {
-  if (threadIdx.x < 3) {
-    double x = 0.0;
-    for (uint32_t b = 0; b < nblocks; ++b) x += part[(size_t)b * 3 + threadIdx.x];
-    out[threadIdx.x] = x;
-  }
+  const int q = threadIdx.x >> 6, l = lane_id();
+  if (q >= 3) return;
+  double x = 0.0;
+  for (uint32_t b = (uint32_t)l; b < nblocks; b += 64u) x += part[(size_t)b * 3 + q];
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+  if (l == 0) out[q] = x;
 }
 
 // ============================================================ launchers ===
@@ -2089,7 +2091,7 @@ void launch_adj_backward(const Dev& d, uint32_t n, int32_t n_steps, int32_t K, c
                          float dt, const float* dLdx, float* seg, double* part, double* grad_out,
                          uint32_t* mismatch, hipStream_t s) {
   k_adj_backward<<<ADJ_BLOCKS, TPB, 0, s>>>(d, n, n_steps, K, linc, dt, dLdx, seg, part, mismatch);
-  k_adj_reduce<<<1, 64, 0, s>>>(part, ADJ_BLOCKS, grad_out);
+  k_adj_reduce<<<1, 192, 0, s>>>(part, ADJ_BLOCKS, grad_out);
 }
 
 }  // namespace ge
