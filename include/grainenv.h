@@ -134,7 +134,8 @@ typedef struct ge_step_stats {
   double max_step;    /* largest v dt of the call [m] */
   double t;           /* time after the call [s] */
   int64_t step;       /* steps taken since creation or the last state load */
-  int64_t pair_tests; /* candidate particles examined by the containment test */
+  int64_t pair_tests; /* candidate particles examined by the containment test (up to the
+                         first hit: depends on the order within a cell, not reproducible) */
   int64_t dirty_tests;/* active particles whose brick neighbourhood holds another grain */
 } ge_step_stats;
 
@@ -270,6 +271,17 @@ ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
 ge_status ge_profile(ge_ctx* ctx, int32_t on);
 ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);
 const char* ge_phase_name(int32_t phase);
+
+/* Recorded step sequences.  With graphs on (the default), a ge_step call of
+   at least 2 resort_every steps runs plain steps up to a step count that is
+   a multiple of resort_every, then replays a recorded hipGraph of
+   resort_every steps (one launch each), then the remaining steps plain.
+   Every argument of every kernel is the same from step to step (the step
+   state lives in device memory), so replays give the same results as plain
+   steps.  The recording is made again after any change of the launch
+   arguments (schedule, model, field, sites, time step).  Phase profiling
+   (ge_profile) runs plain steps.  ge_use_graphs(ctx, 0) turns it off. */
+ge_status ge_use_graphs(ge_ctx* ctx, int32_t on);
 
 /* Launch schedule: the number of thread blocks (256 threads each) of every
    tunable kernel of ge_step.  Kernels: advance, reached-site marks, branch,

@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH):
         "ge_set_schedule": ([vp, P(C.c_int32)], C.c_int32),
         "ge_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
         "ge_tunable_name": ([C.c_int32], C.c_char_p),
+        "ge_use_graphs": ([vp, C.c_int32], C.c_int32),
         "ge_set_model": ([vp, P(C.c_double), P(C.c_double), C.c_double, C.c_int32], C.c_int32),
         "ge_adjoint_workspace_size": ([vp, C.c_int32, C.c_int32, P(C.c_size_t)], C.c_int32),
         "ge_adjoint_forward": ([vp, C.c_double, C.c_int32, C.c_int32, vp, C.c_size_t,
@@ -135,7 +136,8 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
-            "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward")
+            "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward",
+            "ge_use_graphs")
 N_PHASES = 13
 N_TUNABLE = 9
 MAX_BLOCKS = 2048
@@ -343,6 +345,9 @@ class Context:
             raise ValueError(f"unknown kernels {sorted(unknown)}")
         b = (C.c_int32 * N_TUNABLE)(*[int(blocks.get(n, 0)) for n in names])
         self._check(self.lib.ge_set_schedule(self.ctx, b), "ge_set_schedule")
+
+    def use_graphs(self, on):
+        self._check(self.lib.ge_use_graphs(self.ctx, int(bool(on))), "ge_use_graphs")
 
     def set_model(self, a, b, theta, branching):
         av = (C.c_double * 2)(*[float(v) for v in a])

@@ -72,9 +72,26 @@ struct Counters {
   unsigned long long advanced, exited, spawners, children, contained, nucleated;
   unsigned long long pair_tests;  // candidate particles examined by containment
   unsigned long long dirty_tests; // active particles in dirty bricks
+  // step state, advanced on the device by k_finish (so that a captured
+  // sequence of steps replays without host involvement)
+  uint32_t par;        // 1: the active-store roles of A and B (and their tags) are swapped
+  uint32_t spar;       // 1: the roles of S, PS and S2, PS2 are swapped
+  uint32_t epoch;      // step stamp of occupied bricks (starts at 1)
+  uint32_t pad0;
+  double t;            // time
+  unsigned long long step;  // steps taken
 };
 
-// Everything a kernel needs, passed by value.
+// Rosenthal moving point source over a linear background (field kind 3).
+struct Rosenthal {
+  double dT0, grad[3], rate, q, U, alpha, x_start, x_end, ys, zs, r_min, dT_min;
+  double o[3], sp[3];
+};
+
+// Everything a kernel needs, passed by value.  It does not change from step
+// to step: the roles of the double-buffered stores, the step stamp and the
+// time live in the counters (device memory), so a recorded sequence of steps
+// replays without host involvement.
 struct Dev {
   // geometry
   float lo[3], hi[3];
@@ -91,6 +108,8 @@ struct Dev {
   // field
   int32_t fkind;
   float fdT, fgrad[3];
+  double fdT0, frate;  // LINEAR: dT0 + rate t, evaluated in FP64 on the device
+  Rosenthal ros;
   int32_t fn[3];
   float fo[3], finv[3];
   float* fgrid;
@@ -156,8 +175,11 @@ struct Dev {
   int32_t* adj_nact;   // [tracked] steps in which the particle advanced
   float* adj_sfin;     // [tracked] travel at the end of the run (or at its stop)
   float* adj_ck;       // [checkpoints][adj_ncap] travel at steps c * adj_K
+  float* adj_linc;      // [steps] LINEAR field constant of each recorded step
   uint32_t adj_ncap;
-  int32_t adj_k, adj_K;  // step of the recorded run, checkpoint interval
+  int32_t adj_K;        // checkpoint interval
+  unsigned long long adj_step0;  // step count at the start of the recorded run
+  int32_t resort_every;  // steps between re-sorts of the stopped store
   // launch schedule: blocks per launch of each tunable kernel.  The spawn
   // lists have sched[TK_ADVANCE] regions, the stop lists sched[TK_CONTAIN].
   uint32_t sched[9];
@@ -165,23 +187,20 @@ struct Dev {
 
 // -------------------------------------------------- host-side launchers --
 hipError_t resident_grids(Dev& d);  // default schedule for the current device
-void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s);
+void launch_advance(const Dev& d, float dt, hipStream_t s);
 void launch_mark_now(const Dev& d, hipStream_t s);
 void launch_branch(const Dev& d, hipStream_t s);
-void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s);
+void launch_scan(const Dev& d, hipStream_t s);
 void launch_scatter(const Dev& d, hipStream_t s);
 void launch_scatter_children(const Dev& d, hipStream_t s);
-void launch_dirty(const Dev& d, uint32_t epoch, hipStream_t s);
-void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s);
+void launch_dirty(const Dev& d, hipStream_t s);
+void launch_contain(const Dev& d, hipStream_t s);
 void launch_stoplink(const Dev& d, hipStream_t s);
-void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s);
-void launch_finish(const Dev& d, hipStream_t s);
+void launch_nucleate(const Dev& d, hipStream_t s);
+void launch_finish(const Dev& d, double dt, hipStream_t s);
 void launch_reset_stats(const Dev& d, hipStream_t s);
 void launch_stopped_rebuild(const Dev& d, hipStream_t s);  // S -> S2 (caller swaps)
-void launch_resample(const Dev& d, double dT0, const double grad[3], double rate, double q,
-                     double U, double alpha, double x_start, double x_end, double ys, double zs,
-                     double r_min, double dT_min, double ox, double oy, double oz, double sx,
-                     double sy, double sz, double t, hipStream_t s);
+void launch_resample(const Dev& d, hipStream_t s);
 void launch_init_workspace(const Dev& d, hipStream_t s);
 void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s);
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);
@@ -193,7 +212,6 @@ void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t c
                           const float* window, hipStream_t s);
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s);
-void launch_clear_bepoch(const Dev& d, hipStream_t s);
 void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s);
 void launch_adj_final(const Dev& d, hipStream_t s);
 void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s);

@@ -394,6 +394,53 @@ __device__ __forceinline__ bool dead(const Dev& D) {
           ERR_CAPACITY) != 0u;
 }
 
+// The context as seen by a kernel of the current step: the launch argument
+// (the same for every step) with the roles of the double-buffered stores set
+// by the step state in the counters.
+// Step state read from the counters is the same for every lane: kept in
+// scalar registers.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ double uniform_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = uniform_u32((uint32_t)b), hi = uniform_u32((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ uint32_t step_epoch(const Dev& D) { return uniform_u32(D.cnt->epoch); }
+
+__device__ __forceinline__ Dev dev_view(const Dev& Dv) {
+  Dev D = Dv;
+  if (uniform_u32(D.cnt->par) & 1u) {
+    uint4* r = D.A;
+    D.A = D.B;
+    D.B = r;
+    uint32_t* t = D.tagA;
+    D.tagA = D.tagB;
+    D.tagB = t;
+  }
+  if (uniform_u32(D.cnt->spar) & 1u) {
+    uint4* r = D.S;
+    D.S = D.S2;
+    D.S2 = r;
+    float4* p = D.PS;
+    D.PS = D.PS2;
+    D.PS2 = p;
+  }
+  return D;
+}
+
+// LINEAR field constant dT0 + rate t of the current step (FP64, then FP32).
+__device__ __forceinline__ float lin_const(const Dev& D) {
+  return D.fkind == F_LINEAR ? (float)(D.fdT0 + D.frate * uniform_f64(D.cnt->t)) : 0.0f;
+}
+
+// The stopped store is re-sorted after every resort_every-th step (the
+// re-sort kernels run after k_finish has counted the step).
+__device__ __forceinline__ bool resort_due(const Dev& D) {
+  return uniform_u32((uint32_t)(D.cnt->step % (unsigned long long)D.resort_every)) == 0u;
+}
+
 // Block-wide exclusive scan of one uint32 per thread (TPB threads).
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
   const int lane = lane_id(), wid = (int)(threadIdx.x >> 6);
@@ -535,7 +582,12 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P
 }
 
 // ==================================================================== step
-__global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt) {
+__global__ __launch_bounds__(TPB, 8) void k_advance(Dev Dv, float dt) {
+  const Dev D = dev_view(Dv);
+  const float lin_c = lin_const(D);
+  // Step of an adjoint recording (tagged particles only).
+  const int32_t adj_k = D.tagA ? (int32_t)(D.cnt->step - D.adj_step0) : 0;
+  if (D.tagA && blockIdx.x == 0 && threadIdx.x == 0) D.adj_linc[adj_k] = lin_c;
   if (dead(D)) return;
   __shared__ uint32_t s_nsp, s_adv, s_exit, s_bad, s_max;
   if (threadIdx.x == 0) {
@@ -567,8 +619,8 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt
       const float s = rec_s(r);
       if (D.tagA) {  // adjoint recording: checkpoint of the travel every adj_K steps
         tag = D.tagA[i];
-        if (tag != NIL && D.adj_k % D.adj_K == 0)
-          D.adj_ck[(size_t)(D.adj_k / D.adj_K) * D.adj_ncap + tag] = s;
+        if (tag != NIL && adj_k % D.adj_K == 0)
+          D.adj_ck[(size_t)(adj_k / D.adj_K) * D.adj_ncap + tag] = s;
       }
       const float* G = D.gtab + (size_t)g * GT_STRIDE;
       const P3 x = lattice_pos(G, sx, sy, sz, d, s);
@@ -622,7 +674,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt
     if (exited) {
       stopped_put(D, sj, r, x2);
       if (tag != NIL) {
-        D.adj_nact[tag] = D.adj_k + 1;
+        D.adj_nact[tag] = adj_k + 1;
         D.adj_sfin[tag] = rec_s(r);
       }
     }
@@ -643,7 +695,8 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev D, float lin_c, float dt
 
 // Exclusive prefix of the per-block spawner counts (one block): spawner i
 // of the step is in the region r with spawn_off[r] <= i < spawn_off[r + 1].
-__global__ __launch_bounds__(1024) void k_spawn_scan(Dev D) {
+__global__ __launch_bounds__(1024) void k_spawn_scan(Dev Dv) {
+  const Dev D = dev_view(Dv);
   __shared__ uint32_t s_w[16];
   const uint32_t G = D.sched[TK_ADVANCE];
   const uint32_t per = (G + 1023u) / 1024u;  // regions per thread, G <= STREAM_GRID
@@ -690,7 +743,8 @@ __device__ __forceinline__ uint32_t spawn_item(const Dev& D, const SpawnView& v,
 }
 
 // Marks the site each spawner has reached as reached during this step.
-__global__ __launch_bounds__(TPB) void k_mark_now(Dev D) {
+__global__ __launch_bounds__(TPB) void k_mark_now(Dev Dv) {
+  const Dev D = dev_view(Dv);
   if (dead(D)) return;
   __shared__ uint32_t s_off[STREAM_GRID + 1];
   const SpawnView v = spawn_view(D, s_off);
@@ -704,7 +758,8 @@ __global__ __launch_bounds__(TPB) void k_mark_now(Dev D) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_branch(Dev D) {
+__global__ __launch_bounds__(TPB) void k_branch(Dev Dv) {
+  const Dev D = dev_view(Dv);
   if (dead(D)) return;
   __shared__ uint32_t s_sp, s_ch;
   if (threadIdx.x == 0) {
@@ -783,8 +838,9 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev D) {
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 
-__global__ __launch_bounds__(TPB) void k_scan_reduce(Dev D) {
-  if (dead(D)) return;
+__global__ __launch_bounds__(TPB) void k_scan_reduce(Dev Dv, int mode) {
+  const Dev D = dev_view(Dv);
+  if (dead(D) || (mode == 1 && !resort_due(D))) return;
   __shared__ unsigned long long wsum[TPB / 64];
   const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
   unsigned long long v = 0;
@@ -801,8 +857,9 @@ __global__ __launch_bounds__(TPB) void k_scan_reduce(Dev D) {
   if (threadIdx.x == 0) D.scan_tmp[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_top(Dev D, uint32_t ntiles, int mode) {
-  if (dead(D)) return;
+__global__ __launch_bounds__(TPB) void k_scan_top(Dev Dv, uint32_t ntiles, int mode) {
+  const Dev D = dev_view(Dv);
+  if (dead(D) || (mode == 1 && !resort_due(D))) return;
   __shared__ unsigned long long wsum[TPB / 64];
   unsigned long long carry = 0;
   for (uint32_t base = 0; base < ntiles; base += TPB) {
@@ -826,8 +883,10 @@ __global__ __launch_bounds__(TPB) void k_scan_top(Dev D, uint32_t ntiles, int mo
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_write(Dev D, uint32_t epoch, int mode) {
-  if (dead(D)) return;
+__global__ __launch_bounds__(TPB) void k_scan_write(Dev Dv, int mode) {
+  const Dev D = dev_view(Dv);
+  if (dead(D) || (mode == 1 && !resort_due(D))) return;
+  const uint32_t epoch = step_epoch(D);
   __shared__ unsigned long long wsum[TPB / 64];
   const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
   uint32_t c[SCAN_ITEMS];
@@ -862,8 +921,9 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Dev D, uint32_t epoch, int m
 
 // One wave per occupied brick, one lane per cell: cell starts from the
 // brick start and an exclusive scan of the 64 cell counts.
-__global__ __launch_bounds__(TPB) void k_cellscan(Dev D, int mode) {
-  if (dead(D)) return;
+__global__ __launch_bounds__(TPB) void k_cellscan(Dev Dv, int mode) {
+  const Dev D = dev_view(Dv);
+  if (dead(D) || (mode == 1 && !resort_due(D))) return;
   const uint32_t nocc = mode == 0 ? D.cnt->n_occ : D.cnt->n_socc;
   const uint32_t waves = gridDim.x * (TPB / 64);
   const uint32_t lane = (uint32_t)lane_id();
@@ -884,7 +944,8 @@ __device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g)
   atomicMax(&D.binfo[b].w, g);
 }
 
-__global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
+__global__ __launch_bounds__(TPB) void k_scatter(Dev Dv) {
+  const Dev D = dev_view(Dv);
   if (dead(D)) return;
   const uint32_t n = D.cnt->n_active;
   const Chunk ch = chunk_of(n, TPB);
@@ -927,7 +988,8 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev D) {
 
 // Children of the spawners (from the per-block spawner lists) to their cell
 // slots; clears the spawners' marks of the current step.
-__global__ __launch_bounds__(TPB) void k_scatter_children(Dev D) {
+__global__ __launch_bounds__(TPB) void k_scatter_children(Dev Dv) {
+  const Dev D = dev_view(Dv);
   if (dead(D)) return;
   __shared__ uint32_t s_off[STREAM_GRID + 1];
   const SpawnView v = spawn_view(D, s_off);
@@ -968,7 +1030,9 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Dev D) {
 // particles of clean bricks cannot meet another grain.  Each block takes a
 // contiguous chunk of the occupied-brick list and lists its dirty bricks in
 // its own region of `dlist`.
-__global__ __launch_bounds__(TPB) void k_dirty(Dev D, uint32_t epoch) {
+__global__ __launch_bounds__(TPB) void k_dirty(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  const uint32_t epoch = step_epoch(D);
   if (dead(D)) return;
   __shared__ uint32_t s_n, s_np, s_base;
   if (threadIdx.x == 0) {
@@ -1224,7 +1288,9 @@ __device__ bool contact(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t
 // the occupied list, one lane per particle.  Particles of clean bricks cannot
 // meet another grain and are not visited.  Hits go to the block's region of
 // the stop list.
-__global__ __launch_bounds__(TPB, 6) void k_contain(Dev D, uint32_t epoch) {
+__global__ __launch_bounds__(TPB, 6) void k_contain(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  const uint32_t epoch = step_epoch(D);
   if (dead(D)) return;
   __shared__ uint32_t s_n;
   if (threadIdx.x == 0) s_n = 0;
@@ -1260,7 +1326,8 @@ __global__ __launch_bounds__(TPB, 6) void k_contain(Dev D, uint32_t epoch) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
+__global__ __launch_bounds__(TPB) void k_stoplink(Dev Dv) {
+  const Dev D = dev_view(Dv);
   if (dead(D)) return;
   __shared__ uint32_t s_base;
   const uint32_t n = D.cnt->n_dpart, G = D.sched[TK_CONTAIN];
@@ -1284,7 +1351,7 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
       if (D.tagA) {
         const uint32_t tag = D.tagB[i];
         if (tag != NIL) {
-          D.adj_nact[tag] = D.adj_k + 1;
+          D.adj_nact[tag] = (int32_t)(D.cnt->step - D.adj_step0) + 1;
           D.adj_sfin[tag] = rec_s(r);
         }
       }
@@ -1293,7 +1360,10 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Dev D) {
 }
 
 // ----------------------------------------------------------- nucleation ---
-__global__ __launch_bounds__(TPB) void k_nuc_test(Dev D, float lin_c, uint32_t epoch) {
+__global__ __launch_bounds__(TPB) void k_nuc_test(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  const uint32_t epoch = step_epoch(D);
+  const float lin_c = lin_const(D);
   if (dead(D)) return;
   const uint32_t ng = D.cnt->n_grains;
   const float inv_l = 1.0f / D.lambda0;
@@ -1327,7 +1397,8 @@ __global__ __launch_bounds__(TPB) void k_nuc_test(Dev D, float lin_c, uint32_t e
 // One block: candidates in site order; a candidate is blocked by a site fired
 // earlier in the same step when it lies within rc of that site or rounds to
 // that grain's origin site.
-__global__ __launch_bounds__(TPB) void k_nuc_fire(Dev D) {
+__global__ __launch_bounds__(TPB) void k_nuc_fire(Dev Dv) {
+  const Dev D = dev_view(Dv);
   if (dead(D)) return;
   if (D.cnt->n_cand == 0u) return;
   __shared__ uint32_t list[TPB];
@@ -1396,9 +1467,16 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Dev D) {
   }
 }
 
-__global__ void k_finish(Dev D) {
+__global__ void k_finish(Dev Dv, double dt) {
+  const Dev D = dev_view(Dv);
   Counters* c = D.cnt;
   if (c->err & ERR_CAPACITY) return;
+  // The step's sorted output becomes the next step's input; the step ends.
+  c->par ^= 1u;
+  c->t = c->t + dt;
+  c->step += 1ull;
+  c->epoch += 1u;
+  if (c->epoch == 0u) c->err |= ERR_CAPACITY;  // brick step stamps exhausted (2^32 steps)
   c->n_active = c->n_out + 6u * c->n_fired;
   c->n_live = c->n_out - c->n_newstop + 6u * c->n_fired;
   c->contained += c->n_newstop;
@@ -1408,7 +1486,8 @@ __global__ void k_finish(Dev D) {
   c->n_fired = 0;
 }
 
-__global__ void k_reset_stats(Dev D) {
+__global__ void k_reset_stats(Dev Dv) {
+  const Dev D = dev_view(Dv);
   Counters* c = D.cnt;
   c->advanced = 0;
   c->exited = 0;
@@ -1424,8 +1503,9 @@ __global__ void k_reset_stats(Dev D) {
 // ------------------------------------------------ stopped-store re-sort ---
 // Counting sort of S[0, n_stopped) by cell into S2: counts, brick scan
 // (mode 1), cell scan (mode 1), scatter.  Clears the recent-particle lists.
-__global__ __launch_bounds__(TPB) void k_srb_count(Dev D) {
-  if (dead(D)) return;
+__global__ __launch_bounds__(TPB) void k_srb_count(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  if (dead(D) || !resort_due(D)) return;
   const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
   const uint32_t ns = D.cnt->n_sorted;
   const Chunk ch = chunk_of(n, TPB);
@@ -1445,8 +1525,9 @@ __global__ __launch_bounds__(TPB) void k_srb_count(Dev D) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_srb_scatter(Dev D) {
-  if (dead(D)) return;
+__global__ __launch_bounds__(TPB) void k_srb_scatter(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  if (dead(D) || !resort_due(D)) return;
   const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
   const Chunk ch = chunk_of(n, TPB);
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
@@ -1472,23 +1553,24 @@ __global__ __launch_bounds__(TPB) void k_srb_scatter(Dev D) {
   }
 }
 
-__global__ void k_srb_finish(Dev D) {
-  if (D.cnt->err & ERR_CAPACITY) return;
+__global__ void k_srb_finish(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  if ((D.cnt->err & ERR_CAPACITY) || !resort_due(D)) return;
   D.cnt->n_sorted = min(D.cnt->n_stopped, D.cap_s);
+  D.cnt->spar ^= 1u;  // the re-sorted copy becomes the stopped store
 }
 
 // ------------------------------------------------------------- resample ---
-struct RosenthalArgs {
-  double dT0, grad[3], rate, q, U, alpha, x_start, x_end, ys, zs, r_min, dT_min;
-  double o[3], sp[3], t;
-};
 
 // Rosenthal moving point source on a linear background, evaluated in FP64
 // at every node and stored as FP32 undercooling.
-__global__ __launch_bounds__(TPB) void k_resample(Dev D, RosenthalArgs a) {
+__global__ __launch_bounds__(TPB) void k_resample(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  const Rosenthal& a = D.ros;
+  const double t = D.cnt->t;
   const uint64_t total = (uint64_t)D.fn[0] * D.fn[1] * D.fn[2];
   const double L = a.x_end - a.x_start;
-  const double phase = fmod(a.U * a.t, 2.0 * L);
+  const double phase = fmod(a.U * t, 2.0 * L);
   double xs, sg;
   if (phase < L) {
     xs = a.x_start + phase;
@@ -1497,7 +1579,7 @@ __global__ __launch_bounds__(TPB) void k_resample(Dev D, RosenthalArgs a) {
     xs = a.x_start + 2.0 * L - phase;
     sg = -1.0;
   }
-  const double base_t = a.dT0 + a.rate * a.t;
+  const double base_t = a.dT0 + a.rate * t;
   const double k2 = -a.U / (2.0 * a.alpha);
   const double qn = a.q / (2.0 * M_PI);
   for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
@@ -1519,7 +1601,11 @@ __global__ __launch_bounds__(TPB) void k_resample(Dev D, RosenthalArgs a) {
 }
 
 // --------------------------------------------------------- init / load ----
-__global__ __launch_bounds__(TPB) void k_fill_sbsum(Dev D) {
+// Empty stopped-grain ranges; the step stamps start at 1 (0 marks bricks
+// never occupied).
+__global__ __launch_bounds__(TPB) void k_fill_sbsum(Dev Dv) {
+  const Dev D = dev_view(Dv);
+  if (blockIdx.x == 0 && threadIdx.x == 0) D.cnt->epoch = 1u;
   for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
        b += (uint64_t)gridDim.x * TPB)
     D.sbsum[b] = make_uint2(NIL, 0u);
@@ -1527,7 +1613,8 @@ __global__ __launch_bounds__(TPB) void k_fill_sbsum(Dev D) {
 
 // New records A[first, first+count): those marked stopped, and (with box
 // exit) those outside the box, move to the stopped store.
-__global__ __launch_bounds__(TPB) void k_classify_new(Dev D, uint32_t first, uint32_t count) {
+__global__ __launch_bounds__(TPB) void k_classify_new(Dev Dv, uint32_t first, uint32_t count) {
+  const Dev D = dev_view(Dv);
   for (uint32_t k0 = blockIdx.x * TPB; k0 < count; k0 += gridDim.x * TPB) {
     const uint32_t k = k0 + threadIdx.x;
     bool out = false;
@@ -1555,7 +1642,8 @@ __global__ __launch_bounds__(TPB) void k_classify_new(Dev D, uint32_t first, uin
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_claim_ball(Dev D, uint32_t g, int32_t r) {
+__global__ __launch_bounds__(TPB) void k_claim_ball(Dev Dv, uint32_t g, int32_t r) {
+  const Dev D = dev_view(Dv);
   const int32_t w = 2 * r + 1;
   const uint64_t total = (uint64_t)w * w * w;
   for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
@@ -1567,8 +1655,9 @@ __global__ __launch_bounds__(TPB) void k_claim_ball(Dev D, uint32_t g, int32_t r
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_claim_list(Dev D, const int32_t* grain, const int32_t* site,
+__global__ __launch_bounds__(TPB) void k_claim_list(Dev Dv, const int32_t* grain, const int32_t* site,
                                                     const uint8_t* flags, uint32_t n) {
+  const Dev D = dev_view(Dv);
   for (uint32_t k = blockIdx.x * TPB + threadIdx.x; k < n; k += gridDim.x * TPB) {
     const uint32_t g = (uint32_t)grain[k];
     const int x = site[3 * k], y = site[3 * k + 1], z = site[3 * k + 2];
@@ -1582,13 +1671,6 @@ __global__ __launch_bounds__(TPB) void k_claim_list(Dev D, const int32_t* grain,
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_clear_bepoch(Dev D) {
-  for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
-       b += (uint64_t)gridDim.x * TPB) {
-    D.bepoch[b] = 0u;
-    D.bown[b] = make_uint2(0u, NIL);
-  }
-}
 
 // --------------------------------------------------------------- export ---
 struct PartOut {
@@ -1632,8 +1714,9 @@ __device__ __forceinline__ bool in_window(const Window& w, P3 p) {
                    p.z >= w.lo[2] && p.z < w.hi[2]);
 }
 
-__global__ __launch_bounds__(TPB) void k_export_particles(Dev D, uint32_t* counter, PartOut* out,
+__global__ __launch_bounds__(TPB) void k_export_particles(Dev Dv, uint32_t* counter, PartOut* out,
                                                           uint32_t cap_out, Window win) {
+  const Dev D = dev_view(Dv);
   const uint32_t na = D.cnt->n_active, ns = min(D.cnt->n_stopped, D.cap_s);
   for (uint32_t k0 = blockIdx.x * TPB; k0 < na + ns; k0 += gridDim.x * TPB) {
     const uint32_t k = k0 + threadIdx.x;
@@ -1661,8 +1744,9 @@ struct ClaimOut {
 };
 static_assert(sizeof(ClaimOut) == 20, "claim record layout");
 
-__global__ __launch_bounds__(TPB) void k_export_claims(Dev D, uint32_t* counter, ClaimOut* out,
+__global__ __launch_bounds__(TPB) void k_export_claims(Dev Dv, uint32_t* counter, ClaimOut* out,
                                                        uint32_t cap_out, Window win) {
+  const Dev D = dev_view(Dv);
   const uint64_t slots = D.cmask + 1;
   for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < slots * 8;
        v += (uint64_t)gridDim.x * TPB) {
@@ -1712,9 +1796,10 @@ __global__ __launch_bounds__(TPB) void k_export_claims(Dev D, uint32_t* counter,
 
 // Grain map: voxel centre y takes the grain whose reached site is y's rounded
 // lattice position; nearest such site wins, then the lower grain.
-__global__ __launch_bounds__(TPB) void k_grain_map(Dev D, int32_t n0, int32_t n1, int32_t n2,
+__global__ __launch_bounds__(TPB) void k_grain_map(Dev Dv, int32_t n0, int32_t n1, int32_t n2,
                                                    float o0, float o1, float o2, float s0, float s1,
                                                    float s2, uint32_t* out) {
+  const Dev D = dev_view(Dv);
   const uint64_t total = (uint64_t)n0 * n1 * n2;
   const uint32_t ng = D.cnt->n_grains;
   const float inv_l = 1.0f / D.lambda0;
@@ -1809,7 +1894,8 @@ __device__ __forceinline__ P3 field_grad(const Dev& D, P3 p) {
 
 // Tracked set: the records of the active store at the start of the
 // recorded run, tag i = storage index i.
-__global__ __launch_bounds__(TPB) void k_adj_init(Dev D, uint32_t n, int32_t n_steps) {
+__global__ __launch_bounds__(TPB) void k_adj_init(Dev Dv, uint32_t n, int32_t n_steps) {
+  const Dev D = dev_view(Dv);
   for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
     const uint4 r = D.A[i];
     D.adj_rec[i] = r;
@@ -1821,7 +1907,8 @@ __global__ __launch_bounds__(TPB) void k_adj_init(Dev D, uint32_t n, int32_t n_s
 }
 
 // After the last recorded step: travel of the tracked particles still active.
-__global__ __launch_bounds__(TPB) void k_adj_final(Dev D) {
+__global__ __launch_bounds__(TPB) void k_adj_final(Dev Dv) {
+  const Dev D = dev_view(Dv);
   const uint32_t n = D.cnt->n_active;
   for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
     const uint32_t t = D.tagA[i];
@@ -1831,7 +1918,8 @@ __global__ __launch_bounds__(TPB) void k_adj_final(Dev D) {
 }
 
 // Final positions of the tracked particles, [n][3].
-__global__ __launch_bounds__(TPB) void k_adj_positions(Dev D, uint32_t n, float* xN) {
+__global__ __launch_bounds__(TPB) void k_adj_positions(Dev Dv, uint32_t n, float* xN) {
+  const Dev D = dev_view(Dv);
   for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
     const uint4 r = D.adj_rec[i];
     const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
@@ -1846,10 +1934,11 @@ __global__ __launch_bounds__(TPB) void k_adj_positions(Dev D, uint32_t n, float*
 // of K steps is recomputed from its checkpoint into seg[j][i] (step-major,
 // coalesced) with the forward's own arithmetic, then walked backwards.
 // Per-block FP64 partial sums go to part[block][3].
-__global__ __launch_bounds__(TPB) void k_adj_backward(Dev D, uint32_t n, int32_t n_steps,
+__global__ __launch_bounds__(TPB) void k_adj_backward(Dev Dv, uint32_t n, int32_t n_steps,
                                                       int32_t K, const float* linc, float dt,
                                                       const float* dLdx, float* seg,
                                                       double* part, uint32_t* mismatch) {
+  const Dev D = dev_view(Dv);
   __shared__ double s_red[3][TPB / 64];
   double ga0 = 0.0, ga1 = 0.0, gth = 0.0;
   uint32_t bad = 0;
@@ -1966,76 +2055,51 @@ hipError_t resident_grids(Dev& d) {
   return e;
 }
 
-void launch_advance(const Dev& d, float lin_c, float dt, hipStream_t s) {
-  k_advance<<<d.sched[TK_ADVANCE], TPB, 0, s>>>(d, lin_c, dt);
+void launch_advance(const Dev& d, float dt, hipStream_t s) {
+  k_advance<<<d.sched[TK_ADVANCE], TPB, 0, s>>>(d, dt);
   k_spawn_scan<<<1, 1024, 0, s>>>(d);
 }
 void launch_mark_now(const Dev& d, hipStream_t s) {
   k_mark_now<<<d.sched[TK_MARKNOW], TPB, 0, s>>>(d);
 }
 void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.sched[TK_BRANCH], TPB, 0, s>>>(d); }
-static void scan_bricks(const Dev& d, uint32_t epoch, int mode, hipStream_t s) {
+static void scan_bricks(const Dev& d, int mode, hipStream_t s) {
   const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
-  k_scan_reduce<<<ntiles, TPB, 0, s>>>(d);
+  k_scan_reduce<<<ntiles, TPB, 0, s>>>(d, mode);
   k_scan_top<<<1, TPB, 0, s>>>(d, ntiles, mode);
-  k_scan_write<<<ntiles, TPB, 0, s>>>(d, epoch, mode);
+  k_scan_write<<<ntiles, TPB, 0, s>>>(d, mode);
   k_cellscan<<<mode == 0 ? d.sched[TK_CELLSCAN] : (uint32_t)STREAM_GRID, TPB, 0, s>>>(d, mode);
 }
-void launch_scan(const Dev& d, uint32_t epoch, hipStream_t s) { scan_bricks(d, epoch, 0, s); }
+void launch_scan(const Dev& d, hipStream_t s) { scan_bricks(d, 0, s); }
 void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<d.sched[TK_SCATTER], TPB, 0, s>>>(d); }
 void launch_scatter_children(const Dev& d, hipStream_t s) {
   k_scatter_children<<<d.sched[TK_CHILDREN], TPB, 0, s>>>(d);
 }
-void launch_dirty(const Dev& d, uint32_t epoch, hipStream_t s) {
-  k_dirty<<<d.sched[TK_DIRTY], TPB, 0, s>>>(d, epoch);
+void launch_dirty(const Dev& d, hipStream_t s) {
+  k_dirty<<<d.sched[TK_DIRTY], TPB, 0, s>>>(d);
 }
-void launch_contain(const Dev& d, uint32_t epoch, hipStream_t s) {
-  k_contain<<<d.sched[TK_CONTAIN], TPB, 0, s>>>(d, epoch);
+void launch_contain(const Dev& d, hipStream_t s) {
+  k_contain<<<d.sched[TK_CONTAIN], TPB, 0, s>>>(d);
 }
 void launch_stoplink(const Dev& d, hipStream_t s) {
   k_stoplink<<<d.sched[TK_STOPLINK], TPB, 0, s>>>(d);
 }
-void launch_nucleate(const Dev& d, float lin_c, uint32_t epoch, hipStream_t s) {
+void launch_nucleate(const Dev& d, hipStream_t s) {
   if (d.n_sites == 0) return;
-  k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(d, lin_c, epoch);
+  k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(d);
   k_nuc_fire<<<1, TPB, 0, s>>>(d);
 }
-void launch_finish(const Dev& d, hipStream_t s) { k_finish<<<1, 1, 0, s>>>(d); }
+void launch_finish(const Dev& d, double dt, hipStream_t s) { k_finish<<<1, 1, 0, s>>>(d, dt); }
 void launch_reset_stats(const Dev& d, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(d); }
 void launch_stopped_rebuild(const Dev& d, hipStream_t s) {
   k_srb_count<<<STREAM_GRID, TPB, 0, s>>>(d);
-  scan_bricks(d, 0u, 1, s);
+  scan_bricks(d, 1, s);
   k_srb_scatter<<<STREAM_GRID, TPB, 0, s>>>(d);
   k_srb_finish<<<1, 1, 0, s>>>(d);
 }
-void launch_resample(const Dev& d, double dT0, const double grad[3], double rate, double q,
-                     double U, double alpha, double x_start, double x_end, double ys, double zs,
-                     double r_min, double dT_min, double ox, double oy, double oz, double sx,
-                     double sy, double sz, double t, hipStream_t s) {
-  RosenthalArgs a;
-  a.dT0 = dT0;
-  a.grad[0] = grad[0];
-  a.grad[1] = grad[1];
-  a.grad[2] = grad[2];
-  a.rate = rate;
-  a.q = q;
-  a.U = U;
-  a.alpha = alpha;
-  a.x_start = x_start;
-  a.x_end = x_end;
-  a.ys = ys;
-  a.zs = zs;
-  a.r_min = r_min;
-  a.dT_min = dT_min;
-  a.o[0] = ox;
-  a.o[1] = oy;
-  a.o[2] = oz;
-  a.sp[0] = sx;
-  a.sp[1] = sy;
-  a.sp[2] = sz;
-  a.t = t;
+void launch_resample(const Dev& d, hipStream_t s) {
   const uint64_t total = (uint64_t)d.fn[0] * d.fn[1] * d.fn[2];
-  k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(d, a);
+  k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(d);
 }
 void launch_init_workspace(const Dev& d, hipStream_t s) {
   k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
@@ -2076,9 +2140,6 @@ void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
   k_grain_map<<<grid_for(total, 8192), TPB, 0, s>>>(d, n[0], n[1], n[2], origin[0], origin[1],
                                                     origin[2], spacing[0], spacing[1], spacing[2],
                                                     out);
-}
-void launch_clear_bepoch(const Dev& d, hipStream_t s) {
-  k_clear_bepoch<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
 }
 void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s) {
   if (n) k_adj_init<<<grid_for(n, 4096), TPB, 0, s>>>(d, n, n_steps);

@@ -184,11 +184,18 @@ struct ge_ctx {
   ge::Counters* host_cnt;  // pinned
   ge_field field;
   std::vector<float> grid_copy;
-  double t;
-  int64_t step;
-  uint32_t epoch;
   int32_t resort_every;
   uint32_t n_sites;
+  uint64_t dev_version = 0;  // bumped whenever the launch arguments change
+  uint64_t hstep = 0;        // steps taken (host mirror of the device count)
+  // recorded step sequence: resort_every steps starting at a multiple of
+  // resort_every, replayed with one hipGraphLaunch
+  bool use_graphs = true;
+  bool graph_valid = false;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t gversion = 0;
+  double gdt = 0.0;
+  hipStream_t cap_stream = nullptr;  // capture stream (the context's stream may be the null stream)
   bool dead;
   std::string err;
   // phase timing
@@ -306,13 +313,21 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.cbits, 0, 192 * g.slots, s));
   HIPCHK(c, hipMemsetAsync(w + L.cnt, 0, sizeof(ge::Counters), s));
   HIPCHK(c, hipMemsetAsync(w + L.cand, 0, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
-  ge::launch_init_workspace(c->d, s);
+  ge::launch_init_workspace(c->d, s);  // also starts the step stamps at 1
   HIPCHK(c, hipGetLastError());
-  c->epoch = 0;
   return GE_OK;
 }
 
-static void step_once(ge_ctx* c, double dt, float* lin_c_out);
+// The launch arguments changed (schedule, model, field, sites, adjoint
+// recording): recorded step sequences must be recorded again.
+static ge_status sync_dev(ge_ctx* c) {
+  c->dev_version += 1;
+  return GE_OK;
+}
+
+static void step_once(ge_ctx* c, double dt);
+static ge_status sync_dev(ge_ctx* c);
+static ge_status ensure_graph(ge_ctx* c, double dt);
 
 extern "C" {
 
@@ -341,9 +356,6 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   }
   c->stream = (hipStream_t)stream;
   c->ws = (char*)workspace;
-  c->t = 0;
-  c->step = 0;
-  c->epoch = 0;
   c->resort_every = p->resort_every > 0 ? p->resort_every : 16;
   c->n_sites = 0;
   c->dead = false;
@@ -426,7 +438,9 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.cand = (uint32_t*)(w + L.cand);
   d.n_sites = 0;
   d.cnt = (ge::Counters*)(w + L.cnt);
+  d.resort_every = c->resort_every;
   ge_status st = hip_check(c, ge::resident_grids(d), "occupancy query");
+  if (st == GE_OK) st = sync_dev(c);
   if (st == GE_OK) st = reset_device(c);
   if (st == GE_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "create");
   if (st != GE_OK) {
@@ -441,6 +455,8 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
 ge_status ge_destroy(ge_ctx* c) {
   if (!c) return GE_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   (void)hipHostFree(c->host_cnt);
   delete c;
@@ -501,8 +517,8 @@ ge_status ge_init_grains(ge_ctx* c, int32_t n, const double* centre, const doubl
   HIPCHK(c, hipMemcpyAsync(c->d.gbox + (size_t)g0 * 6, boxes.data(), boxes.size() * 4,
                            hipMemcpyHostToDevice, s));
   if (!recs.empty())
-    HIPCHK(c, hipMemcpyAsync(c->d.A + na, recs.data(), recs.size() * sizeof(uint4),
-                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(((H.par & 1u) ? c->d.B : c->d.A) + na, recs.data(),
+                             recs.size() * sizeof(uint4), hipMemcpyHostToDevice, s));
   H.n_grains = g0 + (uint32_t)n;
   H.n_active = na + (uint32_t)recs.size();
   H.n_live += (uint32_t)recs.size();
@@ -571,7 +587,26 @@ ge_status ge_set_thermal_field(ge_ctx* c, const ge_field* f) {
     d.fo[a] = (float)f->origin[a];
     d.finv[a] = f->spacing[a] > 0 ? (float)(1.0 / f->spacing[a]) : 0.0f;
   }
-  return GE_OK;
+  d.fdT0 = f->dT0;
+  d.frate = f->rate;
+  ge::Rosenthal& r = d.ros;
+  r.dT0 = f->dT0;
+  r.rate = f->rate;
+  r.q = f->q;
+  r.U = f->U;
+  r.alpha = f->alpha;
+  r.x_start = f->x_start;
+  r.x_end = f->x_end;
+  r.ys = f->ys;
+  r.zs = f->zs;
+  r.r_min = f->r_min;
+  r.dT_min = f->dT_min;
+  for (int a = 0; a < 3; ++a) {
+    r.grad[a] = f->grad[a];
+    r.o[a] = f->origin[a];
+    r.sp[a] = f->spacing[a];
+  }
+  return sync_dev(c);
 }
 
 ge_status ge_nucleate(ge_ctx* c, int32_t n, const double* xyz, const double* dT_nuc,
@@ -594,6 +629,8 @@ ge_status ge_nucleate(ge_ctx* c, int32_t n, const double* xyz, const double* dT_
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->n_sites += (uint32_t)n;
   c->d.n_sites = c->n_sites;
+  ge_status st = sync_dev(c);
+  if (st != GE_OK) return st;
   return GE_OK;
 }
 
@@ -613,8 +650,8 @@ static void fill_stats(ge_ctx* c, ge_step_stats* st) {
   float ms;
   std::memcpy(&ms, &H.max_step, 4);
   st->max_step = ms;
-  st->t = c->t;
-  st->step = c->step;
+  st->t = H.t;
+  st->step = (int64_t)H.step;
   st->pair_tests = (int64_t)H.pair_tests;
   st->dirty_tests = (int64_t)H.dirty_tests;
 }
@@ -624,7 +661,25 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
   if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
   if (!(std::isfinite(dt) && dt > 0) || n_steps < 0) return fail(c, GE_EINVAL, "bad dt or n_steps");
   ge::launch_reset_stats(c->d, c->stream);
-  for (int32_t k = 0; k < n_steps; ++k) step_once(c, dt, nullptr);
+  int32_t k = 0;
+  const int32_t R = c->resort_every;
+  if (c->use_graphs && !c->prof_on && n_steps >= 2 * R) {
+    // Plain steps up to a multiple of resort_every, then whole recorded
+    // sequences of resort_every steps, then the rest plain.
+    while (k < n_steps && c->hstep % (uint64_t)R != 0) {
+      step_once(c, dt);
+      ++k;
+    }
+    const int32_t reps = (n_steps - k) / R;
+    if (reps > 0) {
+      ge_status st = ensure_graph(c, dt);
+      if (st != GE_OK) return st;
+      for (int32_t r = 0; r < reps; ++r) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      k += reps * R;
+      c->hstep += (uint64_t)reps * (uint64_t)R;
+    }
+  }
+  for (; k < n_steps; ++k) step_once(c, dt);
   HIPCHK(c, hipGetLastError());
   if (!stats) return GE_OK;
   ge_status st = read_counters(c);
@@ -637,62 +692,72 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
 
 // One step of the method on the context's stream (no synchronisation).
 // lin_c_out (nullable) receives the LINEAR field's constant of the step.
-static void step_once(ge_ctx* c, double dt, float* lin_c_out) {
+static void step_once(ge_ctx* c, double dt) {
   hipStream_t s = c->stream;
-  Dev& d = c->d;
-  {
-    if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
-    prof_mark(c, -1);
-    c->epoch += 1;
-    if (c->epoch == 0u) {  // wrapped: brick epochs restart
-      ge::launch_clear_bepoch(d, s);
-      c->epoch = 1;
-    }
-    const double t = c->t;
-    float lin_c = 0.0f;
-    if (c->field.kind == GE_FIELD_LINEAR) lin_c = (float)(c->field.dT0 + c->field.rate * t);
-    if (c->field.kind == GE_FIELD_ROSENTHAL) {
-      const ge_field& f = c->field;
-      ge::launch_resample(d, f.dT0, f.grad, f.rate, f.q, f.U, f.alpha, f.x_start, f.x_end, f.ys,
-                          f.zs, f.r_min, f.dT_min, f.origin[0], f.origin[1], f.origin[2],
-                          f.spacing[0], f.spacing[1], f.spacing[2], t, s);
-    }
-    prof_mark(c, 0);
-    ge::launch_advance(d, lin_c, (float)dt, s);
-    prof_mark(c, 1);
-    ge::launch_mark_now(d, s);
-    prof_mark(c, 2);
-    ge::launch_branch(d, s);
-    prof_mark(c, 3);
-    ge::launch_scan(d, c->epoch, s);
-    prof_mark(c, 4);
-    ge::launch_scatter(d, s);
-    prof_mark(c, 5);
-    ge::launch_scatter_children(d, s);
-    prof_mark(c, 6);
-    ge::launch_dirty(d, c->epoch, s);
-    prof_mark(c, 7);
-    ge::launch_contain(d, c->epoch, s);
-    prof_mark(c, 8);
-    ge::launch_stoplink(d, s);
-    prof_mark(c, 9);
-    ge::launch_nucleate(d, lin_c, c->epoch, s);
-    prof_mark(c, 10);
-    ge::launch_finish(d, s);
-    prof_mark(c, 11);
-    // This step's sorted output becomes the next step's input.
-    std::swap(d.A, d.B);
-    std::swap(d.tagA, d.tagB);
-    if ((c->step + 1) % c->resort_every == 0) {
-      ge::launch_stopped_rebuild(d, s);
-      std::swap(d.S, d.S2);
-      std::swap(d.PS, d.PS2);
-    }
-    prof_mark(c, 12);
-    if (lin_c_out) *lin_c_out = lin_c;
-    c->t = t + dt;
-    c->step += 1;
+  const Dev& d = c->d;
+  if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
+  prof_mark(c, -1);
+  if (c->field.kind == GE_FIELD_ROSENTHAL) ge::launch_resample(d, s);
+  prof_mark(c, 0);
+  ge::launch_advance(d, (float)dt, s);
+  prof_mark(c, 1);
+  ge::launch_mark_now(d, s);
+  prof_mark(c, 2);
+  ge::launch_branch(d, s);
+  prof_mark(c, 3);
+  ge::launch_scan(d, s);
+  prof_mark(c, 4);
+  ge::launch_scatter(d, s);
+  prof_mark(c, 5);
+  ge::launch_scatter_children(d, s);
+  prof_mark(c, 6);
+  ge::launch_dirty(d, s);
+  prof_mark(c, 7);
+  ge::launch_contain(d, s);
+  prof_mark(c, 8);
+  ge::launch_stoplink(d, s);
+  prof_mark(c, 9);
+  ge::launch_nucleate(d, s);
+  prof_mark(c, 10);
+  // Counts the step, advances time, swaps the roles of the active stores.
+  ge::launch_finish(d, dt, s);
+  prof_mark(c, 11);
+  // Re-sort of the stopped store after every resort_every-th step (the
+  // kernels check the device step count as well).
+  c->hstep += 1;
+  if (c->hstep % (uint64_t)c->resort_every == 0) ge::launch_stopped_rebuild(d, s);
+  prof_mark(c, 12);
+}
+
+// Records resort_every steps from a step count that is a multiple of
+// resort_every (nothing runs during the recording) and instantiates them.
+static ge_status ensure_graph(ge_ctx* c, double dt) {
+  if (c->graph_valid && c->gversion == c->dev_version && c->gdt == dt) return GE_OK;
+  if (c->gexec) {
+    HIPCHK(c, hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
   }
+  c->graph_valid = false;
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const uint64_t h0 = c->hstep;
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int32_t k = 0; k < c->resort_every; ++k) step_once(c, dt);
+    e = hipStreamEndCapture(c->cap_stream, &g);
+  }
+  c->stream = user;
+  c->hstep = h0;
+  HIPCHK(c, e);
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(c, e);
+  c->graph_valid = true;
+  c->gversion = c->dev_version;
+  c->gdt = dt;
+  return GE_OK;
 }
 
 extern "C" {
@@ -848,6 +913,12 @@ const char* ge_tunable_name(int32_t k) {
   return (k >= 0 && k < GE_N_TUNABLE) ? TUNABLE_NAMES[k] : "";
 }
 
+ge_status ge_use_graphs(ge_ctx* c, int32_t on) {
+  if (!c) return GE_EINVAL;
+  c->use_graphs = on != 0;
+  return GE_OK;
+}
+
 ge_status ge_get_schedule(ge_ctx* c, int32_t* blocks) {
   if (!c || !blocks) return GE_EINVAL;
   for (int k = 0; k < GE_N_TUNABLE; ++k) blocks[k] = (int32_t)c->d.sched[k];
@@ -860,7 +931,7 @@ ge_status ge_set_schedule(ge_ctx* c, const int32_t* blocks) {
     if (blocks[k] < 0 || blocks[k] > GE_MAX_BLOCKS) return fail(c, GE_EINVAL, "schedule entry out of range");
   for (int k = 0; k < GE_N_TUNABLE; ++k)
     if (blocks[k] > 0) c->d.sched[k] = (uint32_t)blocks[k];
-  return GE_OK;
+  return sync_dev(c);
 }
 
 ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* blocks_out) {
@@ -885,6 +956,7 @@ ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* bl
     double best_cost = INFINITY;
     for (uint32_t g : cand) {
       c->d.sched[k] = g;
+      if ((st = sync_dev(c)) != GE_OK) return st;
       ge_profile(c, 1);
       ge_step_stats s{};
       st = ge_step(c, dt, steps_per_trial, &s);
@@ -901,6 +973,7 @@ ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* bl
     }
     c->d.sched[k] = best;
   }
+  if ((st = sync_dev(c)) != GE_OK) return st;
   if (blocks_out) return ge_get_schedule(c, blocks_out);
   return GE_OK;
 }
@@ -973,6 +1046,10 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   H.n_grains = (uint32_t)S.n_grains;
   H.n_active = (uint32_t)recs.size();
   H.n_live = (uint32_t)recs.size();
+  H.epoch = 1;
+  H.t = S.t;
+  H.step = (unsigned long long)S.step;
+  c->hstep = (uint64_t)S.step;
   st = write_counters(c);
   if (st != GE_OK) return st;
   ge::launch_classify_new(c->d, 0, (uint32_t)recs.size(), s);
@@ -993,8 +1070,6 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   HIPCHK(c, hipGetLastError());
   st = read_counters(c);
   if (st != GE_OK) return st;
-  c->t = S.t;
-  c->step = S.step;
   return error_status(c, c->host_cnt->err);
 }
 
@@ -1020,7 +1095,7 @@ ge_status ge_set_model(ge_ctx* c, const double a[2], const double b[2], double t
   d.kin_poly = (p.b[0] == 2.0 && p.b[1] == 3.0) ? 1 : 0;
   d.theta = (float)p.theta;
   d.branching = p.branching;
-  return GE_OK;
+  return sync_dev(c);
 }
 
 // ----------------------------------------------------------- adjoint ----
@@ -1092,20 +1167,19 @@ ge_status ge_adjoint_forward(ge_ctx* c, double dt, int32_t n_steps, int32_t ckpt
   d.adj_ck = (float*)(w + A.ck);
   d.adj_ncap = n;
   d.adj_K = ckpt_every;
+  d.adj_step0 = c->host_cnt->step;
+  d.adj_linc = (float*)(w + A.linc);
+  if ((st = sync_dev(c)) != GE_OK) return st;
   hipStream_t s = c->stream;
   ge::launch_adj_init(d, n, n_steps, s);
-  std::vector<float> linc((size_t)n_steps);
   ge::launch_reset_stats(d, s);
-  for (int32_t k = 0; k < n_steps; ++k) {
-    d.adj_k = k;
-    step_once(c, dt, &linc[(size_t)k]);
-  }
+  for (int32_t k = 0; k < n_steps; ++k) step_once(c, dt);
   ge::launch_adj_final(d, s);
   ge::launch_adj_positions(d, n, (float*)(w + A.xN), s);
   d.tagA = d.tagB = nullptr;  // later steps run untracked
-  HIPCHK(c, hipMemcpyAsync(w + A.linc, linc.data(), 4 * (size_t)n_steps, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipGetLastError());
-  st = read_counters(c);  // synchronises: linc is copied before it goes out of scope
+  if ((st = sync_dev(c)) != GE_OK) return st;
+  st = read_counters(c);
   if (st != GE_OK) return st;
   if ((st = error_status(c, c->host_cnt->err)) != GE_OK) return st;
   c->adj.valid = true;
