@@ -373,6 +373,45 @@ ge_status ge_adjoint_positions(ge_ctx* ctx, float* xN, size_t bytes, int32_t on_
 ge_status ge_adjoint_tracked(ge_ctx* ctx, ge_adjoint_rec* out, size_t bytes);
 ge_status ge_adjoint_backward(ge_ctx* ctx, const float* dLdx, int32_t on_device, double grad[3]);
 
+/* ------------------------------------------------------------ batches ---
+   Many independent contexts (for instance realisations of one problem with
+   different nucleation sites and orientations, and uneven particle counts)
+   advanced together: each phase of a step is one launch covering every
+   context, whose blocks are shared out among the contexts in proportion to
+   their active particles (at least 8 blocks each).  Steps of whole
+   resort_every sequences are replayed from a recorded hipGraph.  Results
+   are those of plain ge_step calls on each context, bit for bit.
+
+   ge_batch_workspace_size / ge_batch_create: n contexts with parameters
+   params[i] (different sizes allowed), in one caller-owned device workspace
+   (256-byte aligned), all on one stream.  1 <= n <= 4096.
+   ge_batch_member: context i, a full ge_ctx (initialise, load states, query
+   and step it alone with the ordinary calls; it stays owned by the batch).
+   ge_batch_step: n_steps steps of every context; stats (nullable) receives
+   one ge_step_stats per context.  Synchronises.  On a device error of a
+   context the first such status is returned (ge_batch_last_error names the
+   context) and that context is unusable.
+   ge_batch_get_blocks / ge_batch_set_blocks: total blocks of each shared
+   launch, indexed like the schedule of ge_get_schedule (kernels without a
+   shared launch: 0; at most 65536 each; a context gets at most 2048 blocks of
+   a launch).  ge_batch_autotune: coordinate search of those totals
+   (1 to 8 blocks per compute unit) scored by batched step time per active
+   particle; its trials run real steps (steps_per_trial per candidate).
+   ge_batch_use_graphs: replays on (default) or off. */
+typedef struct ge_batch ge_batch;
+ge_status ge_batch_workspace_size(int32_t n, const ge_params* params /*[n]*/, size_t* bytes);
+ge_status ge_batch_create(int32_t n, const ge_params* params /*[n]*/, void* workspace, size_t bytes,
+                          void* stream, ge_batch** out);
+ge_status ge_batch_destroy(ge_batch* b);
+ge_status ge_batch_member(ge_batch* b, int32_t i, ge_ctx** out);
+const char* ge_batch_last_error(const ge_batch* b);
+ge_status ge_batch_step(ge_batch* b, double dt, int32_t n_steps, ge_step_stats* stats /*[n]*/);
+ge_status ge_batch_use_graphs(ge_batch* b, int32_t on);
+ge_status ge_batch_get_blocks(ge_batch* b, int32_t* blocks /*[GE_N_TUNABLE]*/);
+ge_status ge_batch_set_blocks(ge_batch* b, const int32_t* blocks /*[GE_N_TUNABLE]*/);
+ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial,
+                            int32_t* blocks_out /*[GE_N_TUNABLE], nullable*/);
+
 #ifdef __cplusplus
 }
 #endif

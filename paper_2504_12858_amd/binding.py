@@ -115,6 +115,16 @@ def load_library(path: str = LIB_PATH):
         "ge_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
         "ge_tunable_name": ([C.c_int32], C.c_char_p),
         "ge_use_graphs": ([vp, C.c_int32], C.c_int32),
+        "ge_batch_workspace_size": ([C.c_int32, P(ge_params), P(C.c_size_t)], C.c_int32),
+        "ge_batch_create": ([C.c_int32, P(ge_params), vp, C.c_size_t, vp, P(vp)], C.c_int32),
+        "ge_batch_destroy": ([vp], C.c_int32),
+        "ge_batch_member": ([vp, C.c_int32, P(vp)], C.c_int32),
+        "ge_batch_last_error": ([vp], C.c_char_p),
+        "ge_batch_step": ([vp, C.c_double, C.c_int32, P(ge_step_stats)], C.c_int32),
+        "ge_batch_use_graphs": ([vp, C.c_int32], C.c_int32),
+        "ge_batch_get_blocks": ([vp, P(C.c_int32)], C.c_int32),
+        "ge_batch_set_blocks": ([vp, P(C.c_int32)], C.c_int32),
+        "ge_batch_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
         "ge_set_model": ([vp, P(C.c_double), P(C.c_double), C.c_double, C.c_int32], C.c_int32),
         "ge_adjoint_workspace_size": ([vp, C.c_int32, C.c_int32, P(C.c_size_t)], C.c_int32),
         "ge_adjoint_forward": ([vp, C.c_double, C.c_int32, C.c_int32, vp, C.c_size_t,
@@ -137,7 +147,9 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
             "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward",
-            "ge_use_graphs")
+            "ge_use_graphs", "ge_batch_workspace_size", "ge_batch_create", "ge_batch_destroy",
+            "ge_batch_member", "ge_batch_last_error", "ge_batch_step", "ge_batch_use_graphs",
+            "ge_batch_get_blocks", "ge_batch_set_blocks", "ge_batch_autotune")
 N_PHASES = 13
 N_TUNABLE = 9
 MAX_BLOCKS = 2048
@@ -210,15 +222,38 @@ class Context:
     @classmethod
     def from_workload(cls, w, device="cuda:0", init=True, **caps):
         c = cls(params_from_workload(w, **caps), device=device)
-        c.set_thermal_field(w.field)
+        c.init_from_workload(w, init)
+        return c
+
+    def init_from_workload(self, w, init=True):
+        """Field, grains and nucleation sites of a workload."""
+        self.set_thermal_field(w.field)
         if init:
             if len(w.grain_centre):
-                c.init_grains(w.grain_centre, w.grain_quat, w.grain_shell)
+                self.init_grains(w.grain_centre, w.grain_quat, w.grain_shell)
             if len(w.site_dTn):
-                c.nucleate(w.site_xyz, w.site_dTn, w.site_quat)
+                self.nucleate(w.site_xyz, w.site_dTn, w.site_quat)
+
+    @classmethod
+    def borrowed(cls, ctx_ptr, params, owner, device="cuda:0"):
+        """A view of a context owned by a batch (not destroyed by close())."""
+        import torch
+        c = cls.__new__(cls)
+        c.lib = load_library()
+        c.torch = torch
+        c.device = torch.device(device)
+        c.params = params
+        c.workspace = None
+        c.stream = owner.stream
+        c.ctx = ctx_ptr
+        c.n_sites = 0
+        c._owner = owner
         return c
 
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self.ctx = None
+            return
         if getattr(self, "ctx", None):
             self.lib.ge_destroy(self.ctx)
             self.ctx = None
@@ -470,3 +505,77 @@ class Context:
             out = np.zeros(int(np.prod(n)), np.uint32)
         self.query_envelope(QUERY_GRAIN_MAP, out, a)
         return out.reshape(int(n[2]), int(n[1]), int(n[0]))
+
+
+class Batch:
+    """Many contexts in one device workspace, advanced together by batched
+    launches (ge_batch_*).  members[i] is a borrowed Context."""
+
+    def __init__(self, params_list, device="cuda:0", stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        n = len(params_list)
+        arr = (ge_params * n)(*params_list)
+        nbytes = C.c_size_t()
+        rc = self.lib.ge_batch_workspace_size(n, arr, C.byref(nbytes))
+        if rc != GE_OK:
+            raise GrainEnvError(rc, "ge_batch_workspace_size: invalid parameters")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = C.c_void_p()
+        rc = self.lib.ge_batch_create(n, arr, C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(b))
+        if rc != GE_OK:
+            raise GrainEnvError(rc, "ge_batch_create failed")
+        self.b = b
+        self.members = []
+        for i in range(n):
+            p = C.c_void_p()
+            self._check(self.lib.ge_batch_member(self.b, i, C.byref(p)), "ge_batch_member")
+            self.members.append(Context.borrowed(p, params_list[i], self, device))
+
+    def _check(self, rc, what):
+        if rc != GE_OK:
+            msg = self.lib.ge_batch_last_error(self.b)
+            raise GrainEnvError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def step(self, dt, n_steps=1):
+        st = (ge_step_stats * len(self.members))()
+        self._check(self.lib.ge_batch_step(self.b, float(dt), int(n_steps), st), "ge_batch_step")
+        return [s.as_dict() for s in st]
+
+    def use_graphs(self, on):
+        self._check(self.lib.ge_batch_use_graphs(self.b, int(bool(on))), "ge_batch_use_graphs")
+
+    def blocks(self):
+        b = (C.c_int32 * N_TUNABLE)()
+        self._check(self.lib.ge_batch_get_blocks(self.b, b), "ge_batch_get_blocks")
+        names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
+        return dict(zip(names, list(b)))
+
+    def set_blocks(self, blocks):
+        names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
+        b = (C.c_int32 * N_TUNABLE)(*[int(blocks.get(n, 0)) for n in names])
+        self._check(self.lib.ge_batch_set_blocks(self.b, b), "ge_batch_set_blocks")
+
+    def autotune(self, dt, steps_per_trial=1):
+        b = (C.c_int32 * N_TUNABLE)()
+        self._check(self.lib.ge_batch_autotune(self.b, float(dt), int(steps_per_trial), b),
+                    "ge_batch_autotune")
+        names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
+        return dict(zip(names, list(b)))
+
+    def close(self):
+        if getattr(self, "b", None):
+            for m in self.members:
+                m.ctx = None
+            self.lib.ge_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -185,6 +185,37 @@ struct Dev {
   uint32_t sched[9];
 };
 
+// Every pointer member of Dev (a batched launch stores them as offsets from
+// the batch workspace and rebuilds them on the device).
+#define GE_DEV_POINTERS(X)                                                                   \
+  X(fgrid) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spawn_cnt) X(spawn_off) X(newstop)      \
+  X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
+  X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(bown)        \
+  X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(stab) X(sstate) X(cand) X(cnt) X(tagA)      \
+  X(tagB) X(adj_rec) X(adj_nact) X(adj_sfin) X(adj_ck) X(adj_linc)
+constexpr uintptr_t NULL_OFFSET = ~(uintptr_t)0;
+
+// Batched launches: for each launch site, the blocks of every context
+// (map: per block, context | virtual block << 12; gsz: per context, its
+// blocks; total: blocks of the launch).
+enum : int {
+  BS_RESAMPLE = 0, BS_ADVANCE, BS_ONE, BS_MARKNOW, BS_BRANCH, BS_TILES, BS_CELLSCAN,
+  BS_SCATTER, BS_CHILDREN, BS_DIRTY, BS_CONTAIN, BS_STOPLINK, BS_NUCTEST, BS_NUCFIRE,
+  BS_RESORT, BS_N
+};
+constexpr uint32_t BATCH_MAX = 4096;  // contexts per batch (12 bits of a map entry)
+constexpr uint64_t SCAN_TILE_HOST = 2048;  // bricks per tile of the brick scan
+struct BatchSite {
+  const uint32_t* map;
+  const uint32_t* gsz;
+  uint32_t total;
+};
+struct BatchLaunch {
+  const Dev* tab;  // per context: Dev with pointers stored as offsets from base
+  char* base;
+  BatchSite site[BS_N];
+};
+
 // -------------------------------------------------- host-side launchers --
 hipError_t resident_grids(Dev& d);  // default schedule for the current device
 void launch_advance(const Dev& d, float dt, hipStream_t s);
@@ -212,6 +243,8 @@ void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t c
                           const float* window, hipStream_t s);
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s);
+void launch_batch_reset_stats(const BatchLaunch& L, hipStream_t s);
+void launch_batch_step(const BatchLaunch& L, double dt, hipStream_t s);
 void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s);
 void launch_adj_final(const Dev& d, hipStream_t s);
 void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s);

@@ -360,8 +360,14 @@ __device__ __forceinline__ Run wave_run(uint32_t key) {
 struct Chunk {
   uint32_t begin, end;
 };
-__device__ __forceinline__ uint32_t logical_block() {
-  const uint32_t G = gridDim.x, b = blockIdx.x;
+// Block index and grid size of a launch as seen by one context: the real
+// ones for a plain launch, the context's share of the blocks for a batched
+// launch.
+struct VGrid {
+  uint32_t b, G;
+};
+__device__ __forceinline__ uint32_t logical_block(const VGrid& V) {
+  const uint32_t G = V.G, b = V.b;
   return ((G & 7u) == 0u) ? (b & 7u) * (G >> 3) + (b >> 3) : b;
 }
 // Chunk of [0, n) of logical block lb on a grid of G blocks (whole granules).
@@ -375,14 +381,14 @@ __device__ __forceinline__ Chunk chunk_at(uint32_t n, uint32_t granule, uint32_t
   c.end = (uint32_t)(e < n ? e : n);
   return c;
 }
-__device__ __forceinline__ Chunk chunk_of(uint32_t n, uint32_t granule) {
-  return chunk_at(n, granule, gridDim.x, logical_block());
+__device__ __forceinline__ Chunk chunk_of(const VGrid& V, uint32_t n, uint32_t granule) {
+  return chunk_at(n, granule, V.G, logical_block(V));
 }
 // Regions of a per-block list written by a kernel of G_w blocks, as read by
 // this block: an even share [lb G_w / G, (lb + 1) G_w / G) of them, so that
 // with grids that are multiples of 8 a region is read on the XCD that wrote it.
-__device__ __forceinline__ Chunk regions_of(uint32_t G_w) {
-  const uint64_t lb = logical_block(), G = gridDim.x;
+__device__ __forceinline__ Chunk regions_of(const VGrid& V, uint32_t G_w) {
+  const uint64_t lb = logical_block(V), G = V.G;
   Chunk c;
   c.begin = (uint32_t)(lb * G_w / G);
   c.end = (uint32_t)((lb + 1u) * G_w / G);
@@ -429,6 +435,39 @@ __device__ __forceinline__ Dev dev_view(const Dev& Dv) {
   }
   return D;
 }
+
+// Launch bindings.  Plain: one context, passed by value.  Batch: many
+// contexts in one launch; block b serves context map[b] & 0xFFF as its
+// virtual block map[b] >> 12 of gsz[context] blocks.  The contexts' tables
+// hold offsets from `base` (their common workspace) in place of pointers,
+// so that the rebuilt pointers stay global-memory pointers.
+struct Plain {
+  Dev d;
+  __device__ __forceinline__ void bind(Dev& D, VGrid& V) const {
+    D = dev_view(d);
+    V.b = blockIdx.x;
+    V.G = gridDim.x;
+  }
+};
+
+struct Batch {
+  const Dev* __restrict__ tab;
+  char* __restrict__ base;
+  const uint32_t* __restrict__ map;
+  const uint32_t* __restrict__ gsz;
+  __device__ __forceinline__ void bind(Dev& D, VGrid& V) const {
+    const uint32_t e = map[blockIdx.x];
+    const uint32_t m = e & 0xFFFu;
+    V.b = e >> 12;
+    V.G = gsz[m];
+    Dev t = tab[m];
+#define GE_REBASE(f)                                                                 \
+  t.f = ((uintptr_t)t.f == NULL_OFFSET) ? nullptr : (decltype(t.f))(base + (uintptr_t)t.f);
+    GE_DEV_POINTERS(GE_REBASE)
+#undef GE_REBASE
+    D = dev_view(t);
+  }
+};
 
 // LINEAR field constant dT0 + rate t of the current step (FP64, then FP32).
 __device__ __forceinline__ float lin_const(const Dev& D) {
@@ -582,12 +621,15 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P
 }
 
 // ==================================================================== step
-__global__ __launch_bounds__(TPB, 8) void k_advance(Dev Dv, float dt) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const float lin_c = lin_const(D);
   // Step of an adjoint recording (tagged particles only).
   const int32_t adj_k = D.tagA ? (int32_t)(D.cnt->step - D.adj_step0) : 0;
-  if (D.tagA && blockIdx.x == 0 && threadIdx.x == 0) D.adj_linc[adj_k] = lin_c;
+  if (D.tagA && V.b == 0 && threadIdx.x == 0) D.adj_linc[adj_k] = lin_c;
   if (dead(D)) return;
   __shared__ uint32_t s_nsp, s_adv, s_exit, s_bad, s_max;
   if (threadIdx.x == 0) {
@@ -599,7 +641,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev Dv, float dt) {
   }
   __syncthreads();
   const uint32_t n = D.cnt->n_active;
-  const Chunk ch = chunk_of(n, TPB);
+  const Chunk ch = chunk_of(V, n, TPB);
   const int lane = lane_id();
   float max_step = 0.0f;
   uint32_t nadv = 0, nexit = 0, bad = 0;
@@ -685,7 +727,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev Dv, float dt) {
   if (max_step > 0.0f) atomicMax(&s_max, __float_as_uint(max_step));
   __syncthreads();
   if (threadIdx.x == 0) {
-    D.spawn_cnt[logical_block()] = s_nsp;
+    D.spawn_cnt[logical_block(V)] = s_nsp;
     if (s_adv) atomicAdd(&D.cnt->advanced, (unsigned long long)s_adv);
     if (s_exit) atomicAdd(&D.cnt->exited, (unsigned long long)s_exit);
     if (s_bad) atomicOr(&D.cnt->err, s_bad);
@@ -695,8 +737,11 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Dev Dv, float dt) {
 
 // Exclusive prefix of the per-block spawner counts (one block): spawner i
 // of the step is in the region r with spawn_off[r] <= i < spawn_off[r + 1].
-__global__ __launch_bounds__(1024) void k_spawn_scan(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(1024) void k_spawn_scan(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   __shared__ uint32_t s_w[16];
   const uint32_t G = D.sched[TK_ADVANCE];
   const uint32_t per = (G + 1023u) / 1024u;  // regions per thread, G <= STREAM_GRID
@@ -743,12 +788,15 @@ __device__ __forceinline__ uint32_t spawn_item(const Dev& D, const SpawnView& v,
 }
 
 // Marks the site each spawner has reached as reached during this step.
-__global__ __launch_bounds__(TPB) void k_mark_now(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_mark_now(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D)) return;
   __shared__ uint32_t s_off[STREAM_GRID + 1];
   const SpawnView v = spawn_view(D, s_off);
-  const Chunk it = chunk_of(v.total, 1u);
+  const Chunk it = chunk_of(V, v.total, 1u);
   for (uint32_t i = it.begin + threadIdx.x; i < it.end; i += TPB) {
     const uint4 r = D.A[spawn_item(D, v, s_off, i)];
     const int d = rec_dir(r);
@@ -758,8 +806,11 @@ __global__ __launch_bounds__(TPB) void k_mark_now(Dev Dv) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_branch(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D)) return;
   __shared__ uint32_t s_sp, s_ch;
   if (threadIdx.x == 0) {
@@ -769,7 +820,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev Dv) {
   __syncthreads();
   __shared__ uint32_t s_off[STREAM_GRID + 1];
   const SpawnView v = spawn_view(D, s_off);
-  const Chunk it = chunk_of(v.total, 1u);
+  const Chunk it = chunk_of(V, v.total, 1u);
   uint32_t nsp = 0, nch = 0;
   for (uint32_t k = it.begin + threadIdx.x; k < it.end; k += TPB) {
     const uint32_t i = spawn_item(D, v, s_off, k);
@@ -837,12 +888,16 @@ __global__ __launch_bounds__(TPB) void k_branch(Dev Dv) {
 // count of every brick.  Both list the occupied bricks and reset the counts.
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+static_assert(SCAN_TILE == (int)SCAN_TILE_HOST, "brick-scan tile of the host launchers");
 
-__global__ __launch_bounds__(TPB) void k_scan_reduce(Dev Dv, int mode) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_scan_reduce(Bind Bd, int mode) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
   __shared__ unsigned long long wsum[TPB / 64];
-  const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
+  const uint64_t tile0 = (uint64_t)V.b * SCAN_TILE;
   unsigned long long v = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -854,12 +909,16 @@ __global__ __launch_bounds__(TPB) void k_scan_reduce(Dev Dv, int mode) {
   }
   unsigned long long total;
   block_excl_scan64(v, wsum, total);
-  if (threadIdx.x == 0) D.scan_tmp[blockIdx.x] = total;
+  if (threadIdx.x == 0) D.scan_tmp[V.b] = total;
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_top(Dev Dv, uint32_t ntiles, int mode) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_scan_top(Bind Bd, int mode) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
+  const uint32_t ntiles = (uint32_t)((D.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   __shared__ unsigned long long wsum[TPB / 64];
   unsigned long long carry = 0;
   for (uint32_t base = 0; base < ntiles; base += TPB) {
@@ -883,12 +942,15 @@ __global__ __launch_bounds__(TPB) void k_scan_top(Dev Dv, uint32_t ntiles, int m
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_write(Dev Dv, int mode) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_scan_write(Bind Bd, int mode) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
   const uint32_t epoch = step_epoch(D);
   __shared__ unsigned long long wsum[TPB / 64];
-  const uint64_t tile0 = (uint64_t)blockIdx.x * SCAN_TILE;
+  const uint64_t tile0 = (uint64_t)V.b * SCAN_TILE;
   uint32_t c[SCAN_ITEMS];
   unsigned long long v = 0;
 #pragma unroll
@@ -898,7 +960,7 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Dev Dv, int mode) {
     v += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
   }
   unsigned long long total;
-  unsigned long long ex = block_excl_scan64(v, wsum, total) + D.scan_tmp[blockIdx.x];
+  unsigned long long ex = block_excl_scan64(v, wsum, total) + D.scan_tmp[V.b];
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
@@ -921,13 +983,16 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Dev Dv, int mode) {
 
 // One wave per occupied brick, one lane per cell: cell starts from the
 // brick start and an exclusive scan of the 64 cell counts.
-__global__ __launch_bounds__(TPB) void k_cellscan(Dev Dv, int mode) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_cellscan(Bind Bd, int mode) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
   const uint32_t nocc = mode == 0 ? D.cnt->n_occ : D.cnt->n_socc;
-  const uint32_t waves = gridDim.x * (TPB / 64);
+  const uint32_t waves = V.G * (TPB / 64);
   const uint32_t lane = (uint32_t)lane_id();
-  for (uint32_t k = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6); k < nocc; k += waves) {
+  for (uint32_t k = V.b * (TPB / 64) + (threadIdx.x >> 6); k < nocc; k += waves) {
     const uint32_t b = D.occ[k];
     const uint32_t start = mode == 0 ? D.binfo[b].x : D.bsinfo[b].x;
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + lane;
@@ -944,11 +1009,14 @@ __device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g)
   atomicMax(&D.binfo[b].w, g);
 }
 
-__global__ __launch_bounds__(TPB) void k_scatter(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_scatter(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D)) return;
   const uint32_t n = D.cnt->n_active;
-  const Chunk ch = chunk_of(n, TPB);
+  const Chunk ch = chunk_of(V, n, TPB);
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t i = base + threadIdx.x;
     const bool valid = i < ch.end;
@@ -988,12 +1056,15 @@ __global__ __launch_bounds__(TPB) void k_scatter(Dev Dv) {
 
 // Children of the spawners (from the per-block spawner lists) to their cell
 // slots; clears the spawners' marks of the current step.
-__global__ __launch_bounds__(TPB) void k_scatter_children(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D)) return;
   __shared__ uint32_t s_off[STREAM_GRID + 1];
   const SpawnView v = spawn_view(D, s_off);
-  const Chunk it = chunk_of(v.total, 1u);
+  const Chunk it = chunk_of(V, v.total, 1u);
   for (uint32_t k = it.begin + threadIdx.x; k < it.end; k += TPB) {
     const uint4 r = D.A[spawn_item(D, v, s_off, k)];
     const uint32_t fl = rec_fl(r);
@@ -1030,8 +1101,11 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Dev Dv) {
 // particles of clean bricks cannot meet another grain.  Each block takes a
 // contiguous chunk of the occupied-brick list and lists its dirty bricks in
 // its own region of `dlist`.
-__global__ __launch_bounds__(TPB) void k_dirty(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint32_t epoch = step_epoch(D);
   if (dead(D)) return;
   __shared__ uint32_t s_n, s_np, s_base;
@@ -1041,7 +1115,7 @@ __global__ __launch_bounds__(TPB) void k_dirty(Dev Dv) {
   }
   __syncthreads();
   const uint32_t nocc = D.cnt->n_occ;
-  const Chunk ch = chunk_of(nocc, TPB / 64);
+  const Chunk ch = chunk_of(V, nocc, TPB / 64);
   const int lane = lane_id();
   const int nbx = D.nb[0], nby = D.nb[1], nbz = D.nb[2];
   for (uint32_t k = ch.begin + (threadIdx.x >> 6); k < ch.end; k += TPB / 64) {
@@ -1083,7 +1157,7 @@ __global__ __launch_bounds__(TPB) void k_dirty(Dev Dv) {
   // The particles of the block's dirty bricks go to one contiguous stretch
   // of the global dirty-particle list.
   if (threadIdx.x == 0) {
-    D.dlist_cnt[logical_block()] = s_n;
+    D.dlist_cnt[logical_block(V)] = s_n;
     s_base = s_np ? atomicAdd(&D.cnt->n_dpart, s_np) : 0u;
     s_np = 0;
   }
@@ -1288,16 +1362,19 @@ __device__ bool contact(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t
 // the occupied list, one lane per particle.  Particles of clean bricks cannot
 // meet another grain and are not visited.  Hits go to the block's region of
 // the stop list.
-__global__ __launch_bounds__(TPB, 6) void k_contain(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB, 6) void k_contain(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint32_t epoch = step_epoch(D);
   if (dead(D)) return;
   __shared__ uint32_t s_n;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  const uint32_t lb = logical_block();
+  const uint32_t lb = logical_block(V);
   const uint32_t nd = D.cnt->n_dpart;
-  const Chunk ch = chunk_of(nd, TPB);
+  const Chunk ch = chunk_of(V, nd, TPB);
   const int lane = lane_id();
   uint32_t tests = 0;
   for (uint32_t k0 = ch.begin; k0 < ch.end; k0 += TPB) {
@@ -1326,12 +1403,15 @@ __global__ __launch_bounds__(TPB, 6) void k_contain(Dev Dv) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_stoplink(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_stoplink(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D)) return;
   __shared__ uint32_t s_base;
   const uint32_t n = D.cnt->n_dpart, G = D.sched[TK_CONTAIN];
-  const Chunk rr = regions_of(G);
+  const Chunk rr = regions_of(V, G);
   for (uint32_t rg = rr.begin; rg < rr.end; ++rg) {
     const uint32_t cnt = D.newstop_cnt[rg];
     if (cnt == 0u) continue;
@@ -1360,14 +1440,17 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Dev Dv) {
 }
 
 // ----------------------------------------------------------- nucleation ---
-__global__ __launch_bounds__(TPB) void k_nuc_test(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_nuc_test(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint32_t epoch = step_epoch(D);
   const float lin_c = lin_const(D);
   if (dead(D)) return;
   const uint32_t ng = D.cnt->n_grains;
   const float inv_l = 1.0f / D.lambda0;
-  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < D.n_sites; i += gridDim.x * TPB) {
+  for (uint32_t i = V.b * TPB + threadIdx.x; i < D.n_sites; i += V.G * TPB) {
     if (D.sstate[i] != SITE_DORMANT) continue;
     const float* T = D.stab + (size_t)i * GT_STRIDE;
     const P3 y = {T[0], T[1], T[2]};
@@ -1397,8 +1480,11 @@ __global__ __launch_bounds__(TPB) void k_nuc_test(Dev Dv) {
 // One block: candidates in site order; a candidate is blocked by a site fired
 // earlier in the same step when it lies within rc of that site or rounds to
 // that grain's origin site.
-__global__ __launch_bounds__(TPB) void k_nuc_fire(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_nuc_fire(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D)) return;
   if (D.cnt->n_cand == 0u) return;
   __shared__ uint32_t list[TPB];
@@ -1467,8 +1553,11 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Dev Dv) {
   }
 }
 
-__global__ void k_finish(Dev Dv, double dt) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ void k_finish(Bind Bd, double dt) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   Counters* c = D.cnt;
   if (c->err & ERR_CAPACITY) return;
   // The step's sorted output becomes the next step's input; the step ends.
@@ -1486,8 +1575,11 @@ __global__ void k_finish(Dev Dv, double dt) {
   c->n_fired = 0;
 }
 
-__global__ void k_reset_stats(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ void k_reset_stats(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   Counters* c = D.cnt;
   c->advanced = 0;
   c->exited = 0;
@@ -1503,12 +1595,15 @@ __global__ void k_reset_stats(Dev Dv) {
 // ------------------------------------------------ stopped-store re-sort ---
 // Counting sort of S[0, n_stopped) by cell into S2: counts, brick scan
 // (mode 1), cell scan (mode 1), scatter.  Clears the recent-particle lists.
-__global__ __launch_bounds__(TPB) void k_srb_count(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_srb_count(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D) || !resort_due(D)) return;
   const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
   const uint32_t ns = D.cnt->n_sorted;
-  const Chunk ch = chunk_of(n, TPB);
+  const Chunk ch = chunk_of(V, n, TPB);
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t j = base + threadIdx.x;
     uint32_t ckey = NIL;
@@ -1525,11 +1620,14 @@ __global__ __launch_bounds__(TPB) void k_srb_count(Dev Dv) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_srb_scatter(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_srb_scatter(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if (dead(D) || !resort_due(D)) return;
   const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
-  const Chunk ch = chunk_of(n, TPB);
+  const Chunk ch = chunk_of(V, n, TPB);
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t j = base + threadIdx.x;
     uint32_t ckey = NIL;
@@ -1553,8 +1651,11 @@ __global__ __launch_bounds__(TPB) void k_srb_scatter(Dev Dv) {
   }
 }
 
-__global__ void k_srb_finish(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ void k_srb_finish(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   if ((D.cnt->err & ERR_CAPACITY) || !resort_due(D)) return;
   D.cnt->n_sorted = min(D.cnt->n_stopped, D.cap_s);
   D.cnt->spar ^= 1u;  // the re-sorted copy becomes the stopped store
@@ -1564,8 +1665,11 @@ __global__ void k_srb_finish(Dev Dv) {
 
 // Rosenthal moving point source on a linear background, evaluated in FP64
 // at every node and stored as FP32 undercooling.
-__global__ __launch_bounds__(TPB) void k_resample(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const Rosenthal& a = D.ros;
   const double t = D.cnt->t;
   const uint64_t total = (uint64_t)D.fn[0] * D.fn[1] * D.fn[2];
@@ -1582,8 +1686,8 @@ __global__ __launch_bounds__(TPB) void k_resample(Dev Dv) {
   const double base_t = a.dT0 + a.rate * t;
   const double k2 = -a.U / (2.0 * a.alpha);
   const double qn = a.q / (2.0 * M_PI);
-  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
-       v += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total;
+       v += (uint64_t)V.G * TPB) {
     const uint64_t i = v % (uint64_t)D.fn[0];
     const uint64_t j = (v / (uint64_t)D.fn[0]) % (uint64_t)D.fn[1];
     const uint64_t k = v / ((uint64_t)D.fn[0] * D.fn[1]);
@@ -1603,19 +1707,25 @@ __global__ __launch_bounds__(TPB) void k_resample(Dev Dv) {
 // --------------------------------------------------------- init / load ----
 // Empty stopped-grain ranges; the step stamps start at 1 (0 marks bricks
 // never occupied).
-__global__ __launch_bounds__(TPB) void k_fill_sbsum(Dev Dv) {
-  const Dev D = dev_view(Dv);
-  if (blockIdx.x == 0 && threadIdx.x == 0) D.cnt->epoch = 1u;
-  for (uint64_t b = (uint64_t)blockIdx.x * TPB + threadIdx.x; b < D.n_bricks;
-       b += (uint64_t)gridDim.x * TPB)
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_fill_sbsum(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (V.b == 0 && threadIdx.x == 0) D.cnt->epoch = 1u;
+  for (uint64_t b = (uint64_t)V.b * TPB + threadIdx.x; b < D.n_bricks;
+       b += (uint64_t)V.G * TPB)
     D.sbsum[b] = make_uint2(NIL, 0u);
 }
 
 // New records A[first, first+count): those marked stopped, and (with box
 // exit) those outside the box, move to the stopped store.
-__global__ __launch_bounds__(TPB) void k_classify_new(Dev Dv, uint32_t first, uint32_t count) {
-  const Dev D = dev_view(Dv);
-  for (uint32_t k0 = blockIdx.x * TPB; k0 < count; k0 += gridDim.x * TPB) {
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_classify_new(Bind Bd, uint32_t first, uint32_t count) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  for (uint32_t k0 = V.b * TPB; k0 < count; k0 += V.G * TPB) {
     const uint32_t k = k0 + threadIdx.x;
     bool out = false;
     uint4 r = make_uint4(0u, 0u, 0u, 0u);
@@ -1642,12 +1752,15 @@ __global__ __launch_bounds__(TPB) void k_classify_new(Dev Dv, uint32_t first, ui
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_claim_ball(Dev Dv, uint32_t g, int32_t r) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_claim_ball(Bind Bd, uint32_t g, int32_t r) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const int32_t w = 2 * r + 1;
   const uint64_t total = (uint64_t)w * w * w;
-  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
-       v += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total;
+       v += (uint64_t)V.G * TPB) {
     const int x = (int)(v % w) - r;
     const int y = (int)((v / w) % w) - r;
     const int z = (int)(v / ((uint64_t)w * w)) - r;
@@ -1655,10 +1768,13 @@ __global__ __launch_bounds__(TPB) void k_claim_ball(Dev Dv, uint32_t g, int32_t 
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_claim_list(Dev Dv, const int32_t* grain, const int32_t* site,
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_claim_list(Bind Bd, const int32_t* grain, const int32_t* site,
                                                     const uint8_t* flags, uint32_t n) {
-  const Dev D = dev_view(Dv);
-  for (uint32_t k = blockIdx.x * TPB + threadIdx.x; k < n; k += gridDim.x * TPB) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  for (uint32_t k = V.b * TPB + threadIdx.x; k < n; k += V.G * TPB) {
     const uint32_t g = (uint32_t)grain[k];
     const int x = site[3 * k], y = site[3 * k + 1], z = site[3 * k + 2];
     uint32_t m = 0;
@@ -1714,11 +1830,14 @@ __device__ __forceinline__ bool in_window(const Window& w, P3 p) {
                    p.z >= w.lo[2] && p.z < w.hi[2]);
 }
 
-__global__ __launch_bounds__(TPB) void k_export_particles(Dev Dv, uint32_t* counter, PartOut* out,
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_export_particles(Bind Bd, uint32_t* counter, PartOut* out,
                                                           uint32_t cap_out, Window win) {
-  const Dev D = dev_view(Dv);
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint32_t na = D.cnt->n_active, ns = min(D.cnt->n_stopped, D.cap_s);
-  for (uint32_t k0 = blockIdx.x * TPB; k0 < na + ns; k0 += gridDim.x * TPB) {
+  for (uint32_t k0 = V.b * TPB; k0 < na + ns; k0 += V.G * TPB) {
     const uint32_t k = k0 + threadIdx.x;
     bool take = false;
     uint4 r = make_uint4(0u, 0u, 0u, 0u);
@@ -1744,12 +1863,15 @@ struct ClaimOut {
 };
 static_assert(sizeof(ClaimOut) == 20, "claim record layout");
 
-__global__ __launch_bounds__(TPB) void k_export_claims(Dev Dv, uint32_t* counter, ClaimOut* out,
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_export_claims(Bind Bd, uint32_t* counter, ClaimOut* out,
                                                        uint32_t cap_out, Window win) {
-  const Dev D = dev_view(Dv);
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint64_t slots = D.cmask + 1;
-  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < slots * 8;
-       v += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < slots * 8;
+       v += (uint64_t)V.G * TPB) {
     const uint64_t slot = v >> 3;
     const uint32_t w = (uint32_t)(v & 7u);
     const unsigned long long key = D.ckeys[slot];
@@ -1796,15 +1918,18 @@ __global__ __launch_bounds__(TPB) void k_export_claims(Dev Dv, uint32_t* counter
 
 // Grain map: voxel centre y takes the grain whose reached site is y's rounded
 // lattice position; nearest such site wins, then the lower grain.
-__global__ __launch_bounds__(TPB) void k_grain_map(Dev Dv, int32_t n0, int32_t n1, int32_t n2,
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_grain_map(Bind Bd, int32_t n0, int32_t n1, int32_t n2,
                                                    float o0, float o1, float o2, float s0, float s1,
                                                    float s2, uint32_t* out) {
-  const Dev D = dev_view(Dv);
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint64_t total = (uint64_t)n0 * n1 * n2;
   const uint32_t ng = D.cnt->n_grains;
   const float inv_l = 1.0f / D.lambda0;
-  for (uint64_t v = (uint64_t)blockIdx.x * TPB + threadIdx.x; v < total;
-       v += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total;
+       v += (uint64_t)V.G * TPB) {
     const uint64_t i = v % (uint64_t)n0, j = (v / (uint64_t)n0) % (uint64_t)n1,
                    k = v / ((uint64_t)n0 * n1);
     const P3 y = {o0 + ((float)i + 0.5f) * s0, o1 + ((float)j + 0.5f) * s1,
@@ -1894,9 +2019,12 @@ __device__ __forceinline__ P3 field_grad(const Dev& D, P3 p) {
 
 // Tracked set: the records of the active store at the start of the
 // recorded run, tag i = storage index i.
-__global__ __launch_bounds__(TPB) void k_adj_init(Dev Dv, uint32_t n, int32_t n_steps) {
-  const Dev D = dev_view(Dv);
-  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_adj_init(Bind Bd, uint32_t n, int32_t n_steps) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  for (uint32_t i = V.b * TPB + threadIdx.x; i < n; i += V.G * TPB) {
     const uint4 r = D.A[i];
     D.adj_rec[i] = r;
     D.tagA[i] = i;
@@ -1907,10 +2035,13 @@ __global__ __launch_bounds__(TPB) void k_adj_init(Dev Dv, uint32_t n, int32_t n_
 }
 
 // After the last recorded step: travel of the tracked particles still active.
-__global__ __launch_bounds__(TPB) void k_adj_final(Dev Dv) {
-  const Dev D = dev_view(Dv);
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_adj_final(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   const uint32_t n = D.cnt->n_active;
-  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+  for (uint32_t i = V.b * TPB + threadIdx.x; i < n; i += V.G * TPB) {
     const uint32_t t = D.tagA[i];
     const uint4 r = D.A[i];
     if (t != NIL && (rec_fl(r) & 3u) == ST_ACTIVE) D.adj_sfin[t] = rec_s(r);
@@ -1918,9 +2049,12 @@ __global__ __launch_bounds__(TPB) void k_adj_final(Dev Dv) {
 }
 
 // Final positions of the tracked particles, [n][3].
-__global__ __launch_bounds__(TPB) void k_adj_positions(Dev Dv, uint32_t n, float* xN) {
-  const Dev D = dev_view(Dv);
-  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_adj_positions(Bind Bd, uint32_t n, float* xN) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  for (uint32_t i = V.b * TPB + threadIdx.x; i < n; i += V.G * TPB) {
     const uint4 r = D.adj_rec[i];
     const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
     const P3 x = lattice_pos(G, rec_sx(r), rec_sy(r), rec_sz(r), rec_dir(r), D.adj_sfin[i]);
@@ -1934,15 +2068,18 @@ __global__ __launch_bounds__(TPB) void k_adj_positions(Dev Dv, uint32_t n, float
 // of K steps is recomputed from its checkpoint into seg[j][i] (step-major,
 // coalesced) with the forward's own arithmetic, then walked backwards.
 // Per-block FP64 partial sums go to part[block][3].
-__global__ __launch_bounds__(TPB) void k_adj_backward(Dev Dv, uint32_t n, int32_t n_steps,
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_adj_backward(Bind Bd, uint32_t n, int32_t n_steps,
                                                       int32_t K, const float* linc, float dt,
                                                       const float* dLdx, float* seg,
                                                       double* part, uint32_t* mismatch) {
-  const Dev D = dev_view(Dv);
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
   __shared__ double s_red[3][TPB / 64];
   double ga0 = 0.0, ga1 = 0.0, gth = 0.0;
   uint32_t bad = 0;
-  for (uint32_t i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+  for (uint32_t i = V.b * TPB + threadIdx.x; i < n; i += V.G * TPB) {
     const uint4 r = D.adj_rec[i];
     const int32_t nact = D.adj_nact[i];
     if (nact <= 0) continue;
@@ -2002,7 +2139,7 @@ __global__ __launch_bounds__(TPB) void k_adj_backward(Dev Dv, uint32_t n, int32_
   if (threadIdx.x < 3) {
     double x = 0.0;
     for (int w = 0; w < TPB / 64; ++w) x += s_red[threadIdx.x][w];
-    part[(size_t)blockIdx.x * 3 + threadIdx.x] = x;
+    part[(size_t)V.b * 3 + threadIdx.x] = x;
   }
 }
 
@@ -2047,75 +2184,76 @@ hipError_t resident_grids(Dev& d) {
     grid = g >= 8u ? g / 8u * 8u : g;
     return hipSuccess;
   };
-  const void* ks[TK_N] = {(const void*)k_advance, (const void*)k_mark_now, (const void*)k_branch,
-                          (const void*)k_cellscan, (const void*)k_scatter,
-                          (const void*)k_scatter_children, (const void*)k_dirty,
-                          (const void*)k_contain, (const void*)k_stoplink};
+  const void* ks[TK_N] = {(const void*)k_advance<Plain>, (const void*)k_mark_now<Plain>,
+                          (const void*)k_branch<Plain>, (const void*)k_cellscan<Plain>,
+                          (const void*)k_scatter<Plain>, (const void*)k_scatter_children<Plain>,
+                          (const void*)k_dirty<Plain>, (const void*)k_contain<Plain>,
+                          (const void*)k_stoplink<Plain>};
   for (int t = 0; t < TK_N && e == hipSuccess; ++t) e = family({ks[t]}, d.sched[t]);
   return e;
 }
 
 void launch_advance(const Dev& d, float dt, hipStream_t s) {
-  k_advance<<<d.sched[TK_ADVANCE], TPB, 0, s>>>(d, dt);
-  k_spawn_scan<<<1, 1024, 0, s>>>(d);
+  k_advance<<<d.sched[TK_ADVANCE], TPB, 0, s>>>(Plain{d}, dt);
+  k_spawn_scan<<<1, 1024, 0, s>>>(Plain{d});
 }
 void launch_mark_now(const Dev& d, hipStream_t s) {
-  k_mark_now<<<d.sched[TK_MARKNOW], TPB, 0, s>>>(d);
+  k_mark_now<<<d.sched[TK_MARKNOW], TPB, 0, s>>>(Plain{d});
 }
-void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.sched[TK_BRANCH], TPB, 0, s>>>(d); }
+void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.sched[TK_BRANCH], TPB, 0, s>>>(Plain{d}); }
 static void scan_bricks(const Dev& d, int mode, hipStream_t s) {
   const uint32_t ntiles = (uint32_t)((d.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
-  k_scan_reduce<<<ntiles, TPB, 0, s>>>(d, mode);
-  k_scan_top<<<1, TPB, 0, s>>>(d, ntiles, mode);
-  k_scan_write<<<ntiles, TPB, 0, s>>>(d, mode);
-  k_cellscan<<<mode == 0 ? d.sched[TK_CELLSCAN] : (uint32_t)STREAM_GRID, TPB, 0, s>>>(d, mode);
+  k_scan_reduce<<<ntiles, TPB, 0, s>>>(Plain{d}, mode);
+  k_scan_top<<<1, TPB, 0, s>>>(Plain{d}, mode);
+  k_scan_write<<<ntiles, TPB, 0, s>>>(Plain{d}, mode);
+  k_cellscan<<<mode == 0 ? d.sched[TK_CELLSCAN] : (uint32_t)STREAM_GRID, TPB, 0, s>>>(Plain{d}, mode);
 }
 void launch_scan(const Dev& d, hipStream_t s) { scan_bricks(d, 0, s); }
-void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<d.sched[TK_SCATTER], TPB, 0, s>>>(d); }
+void launch_scatter(const Dev& d, hipStream_t s) { k_scatter<<<d.sched[TK_SCATTER], TPB, 0, s>>>(Plain{d}); }
 void launch_scatter_children(const Dev& d, hipStream_t s) {
-  k_scatter_children<<<d.sched[TK_CHILDREN], TPB, 0, s>>>(d);
+  k_scatter_children<<<d.sched[TK_CHILDREN], TPB, 0, s>>>(Plain{d});
 }
 void launch_dirty(const Dev& d, hipStream_t s) {
-  k_dirty<<<d.sched[TK_DIRTY], TPB, 0, s>>>(d);
+  k_dirty<<<d.sched[TK_DIRTY], TPB, 0, s>>>(Plain{d});
 }
 void launch_contain(const Dev& d, hipStream_t s) {
-  k_contain<<<d.sched[TK_CONTAIN], TPB, 0, s>>>(d);
+  k_contain<<<d.sched[TK_CONTAIN], TPB, 0, s>>>(Plain{d});
 }
 void launch_stoplink(const Dev& d, hipStream_t s) {
-  k_stoplink<<<d.sched[TK_STOPLINK], TPB, 0, s>>>(d);
+  k_stoplink<<<d.sched[TK_STOPLINK], TPB, 0, s>>>(Plain{d});
 }
 void launch_nucleate(const Dev& d, hipStream_t s) {
   if (d.n_sites == 0) return;
-  k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(d);
-  k_nuc_fire<<<1, TPB, 0, s>>>(d);
+  k_nuc_test<<<grid_for(d.n_sites, 1024), TPB, 0, s>>>(Plain{d});
+  k_nuc_fire<<<1, TPB, 0, s>>>(Plain{d});
 }
-void launch_finish(const Dev& d, double dt, hipStream_t s) { k_finish<<<1, 1, 0, s>>>(d, dt); }
-void launch_reset_stats(const Dev& d, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(d); }
+void launch_finish(const Dev& d, double dt, hipStream_t s) { k_finish<<<1, 1, 0, s>>>(Plain{d}, dt); }
+void launch_reset_stats(const Dev& d, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(Plain{d}); }
 void launch_stopped_rebuild(const Dev& d, hipStream_t s) {
-  k_srb_count<<<STREAM_GRID, TPB, 0, s>>>(d);
+  k_srb_count<<<STREAM_GRID, TPB, 0, s>>>(Plain{d});
   scan_bricks(d, 1, s);
-  k_srb_scatter<<<STREAM_GRID, TPB, 0, s>>>(d);
-  k_srb_finish<<<1, 1, 0, s>>>(d);
+  k_srb_scatter<<<STREAM_GRID, TPB, 0, s>>>(Plain{d});
+  k_srb_finish<<<1, 1, 0, s>>>(Plain{d});
 }
 void launch_resample(const Dev& d, hipStream_t s) {
   const uint64_t total = (uint64_t)d.fn[0] * d.fn[1] * d.fn[2];
-  k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(d);
+  k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(Plain{d});
 }
 void launch_init_workspace(const Dev& d, hipStream_t s) {
-  k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(d);
+  k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});
 }
 void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s) {
   if (count == 0) return;
-  k_classify_new<<<grid_for(count, 4096), TPB, 0, s>>>(d, first, count);
+  k_classify_new<<<grid_for(count, 4096), TPB, 0, s>>>(Plain{d}, first, count);
 }
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s) {
   const uint64_t w = 2ull * (uint64_t)r + 1ull;
-  k_claim_ball<<<grid_for(w * w * w, 8192), TPB, 0, s>>>(d, grain, r);
+  k_claim_ball<<<grid_for(w * w * w, 8192), TPB, 0, s>>>(Plain{d}, grain, r);
 }
 void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
                        const uint8_t* flags, uint32_t n, hipStream_t s) {
   if (n == 0) return;
-  k_claim_list<<<grid_for(n, 8192), TPB, 0, s>>>(d, grain, site, flags, n);
+  k_claim_list<<<grid_for(n, 8192), TPB, 0, s>>>(Plain{d}, grain, site, flags, n);
 }
 static Window make_window(const float* win) {
   Window w;
@@ -2128,31 +2266,75 @@ static Window make_window(const float* win) {
 }
 void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                              const float* win, hipStream_t s) {
-  k_export_particles<<<1024, TPB, 0, s>>>(d, counter, (PartOut*)out, cap_out, make_window(win));
+  k_export_particles<<<1024, TPB, 0, s>>>(Plain{d}, counter, (PartOut*)out, cap_out, make_window(win));
 }
 void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                           const float* win, hipStream_t s) {
-  k_export_claims<<<4096, TPB, 0, s>>>(d, counter, (ClaimOut*)out, cap_out, make_window(win));
+  k_export_claims<<<4096, TPB, 0, s>>>(Plain{d}, counter, (ClaimOut*)out, cap_out, make_window(win));
 }
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s) {
   const uint64_t total = (uint64_t)n[0] * n[1] * n[2];
-  k_grain_map<<<grid_for(total, 8192), TPB, 0, s>>>(d, n[0], n[1], n[2], origin[0], origin[1],
+  k_grain_map<<<grid_for(total, 8192), TPB, 0, s>>>(Plain{d}, n[0], n[1], n[2], origin[0], origin[1],
                                                     origin[2], spacing[0], spacing[1], spacing[2],
                                                     out);
 }
 void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s) {
-  if (n) k_adj_init<<<grid_for(n, 4096), TPB, 0, s>>>(d, n, n_steps);
+  if (n) k_adj_init<<<grid_for(n, 4096), TPB, 0, s>>>(Plain{d}, n, n_steps);
 }
-void launch_adj_final(const Dev& d, hipStream_t s) { k_adj_final<<<4096, TPB, 0, s>>>(d); }
+void launch_adj_final(const Dev& d, hipStream_t s) { k_adj_final<<<4096, TPB, 0, s>>>(Plain{d}); }
 void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s) {
-  if (n) k_adj_positions<<<grid_for(n, 4096), TPB, 0, s>>>(d, n, xN);
+  if (n) k_adj_positions<<<grid_for(n, 4096), TPB, 0, s>>>(Plain{d}, n, xN);
 }
 void launch_adj_backward(const Dev& d, uint32_t n, int32_t n_steps, int32_t K, const float* linc,
                          float dt, const float* dLdx, float* seg, double* part, double* grad_out,
                          uint32_t* mismatch, hipStream_t s) {
-  k_adj_backward<<<ADJ_BLOCKS, TPB, 0, s>>>(d, n, n_steps, K, linc, dt, dLdx, seg, part, mismatch);
+  k_adj_backward<<<ADJ_BLOCKS, TPB, 0, s>>>(Plain{d}, n, n_steps, K, linc, dt, dLdx, seg, part, mismatch);
   k_adj_reduce<<<1, 192, 0, s>>>(part, ADJ_BLOCKS, grad_out);
+}
+
+
+// ------------------------------------------------------ batched launches --
+static inline Batch bind_of(const BatchLaunch& L, int site) {
+  return Batch{L.tab, L.base, L.site[site].map, L.site[site].gsz};
+}
+
+void launch_batch_reset_stats(const BatchLaunch& L, hipStream_t s) {
+  k_reset_stats<<<L.site[BS_ONE].total, 1, 0, s>>>(bind_of(L, BS_ONE));
+}
+
+// One step of every context of the batch: the launches of a plain step, each
+// covering all contexts.  The re-sort kernels run every step; each context's
+// device step count decides whether its stopped store is re-sorted.
+void launch_batch_step(const BatchLaunch& L, double dt, hipStream_t s) {
+  const uint32_t one = L.site[BS_ONE].total, tiles = L.site[BS_TILES].total;
+  if (L.site[BS_RESAMPLE].total)
+    k_resample<<<L.site[BS_RESAMPLE].total, TPB, 0, s>>>(bind_of(L, BS_RESAMPLE));
+  k_advance<<<L.site[BS_ADVANCE].total, TPB, 0, s>>>(bind_of(L, BS_ADVANCE), (float)dt);
+  k_spawn_scan<<<one, 1024, 0, s>>>(bind_of(L, BS_ONE));
+  k_mark_now<<<L.site[BS_MARKNOW].total, TPB, 0, s>>>(bind_of(L, BS_MARKNOW));
+  k_branch<<<L.site[BS_BRANCH].total, TPB, 0, s>>>(bind_of(L, BS_BRANCH));
+  k_scan_reduce<<<tiles, TPB, 0, s>>>(bind_of(L, BS_TILES), 0);
+  k_scan_top<<<one, TPB, 0, s>>>(bind_of(L, BS_ONE), 0);
+  k_scan_write<<<tiles, TPB, 0, s>>>(bind_of(L, BS_TILES), 0);
+  k_cellscan<<<L.site[BS_CELLSCAN].total, TPB, 0, s>>>(bind_of(L, BS_CELLSCAN), 0);
+  k_scatter<<<L.site[BS_SCATTER].total, TPB, 0, s>>>(bind_of(L, BS_SCATTER));
+  k_scatter_children<<<L.site[BS_CHILDREN].total, TPB, 0, s>>>(bind_of(L, BS_CHILDREN));
+  k_dirty<<<L.site[BS_DIRTY].total, TPB, 0, s>>>(bind_of(L, BS_DIRTY));
+  k_contain<<<L.site[BS_CONTAIN].total, TPB, 0, s>>>(bind_of(L, BS_CONTAIN));
+  k_stoplink<<<L.site[BS_STOPLINK].total, TPB, 0, s>>>(bind_of(L, BS_STOPLINK));
+  if (L.site[BS_NUCTEST].total) {
+    k_nuc_test<<<L.site[BS_NUCTEST].total, TPB, 0, s>>>(bind_of(L, BS_NUCTEST));
+    k_nuc_fire<<<L.site[BS_NUCFIRE].total, TPB, 0, s>>>(bind_of(L, BS_NUCFIRE));
+  }
+  k_finish<<<one, 1, 0, s>>>(bind_of(L, BS_ONE), dt);
+  k_srb_count<<<L.site[BS_RESORT].total, TPB, 0, s>>>(bind_of(L, BS_RESORT));
+  k_scan_reduce<<<tiles, TPB, 0, s>>>(bind_of(L, BS_TILES), 1);
+  k_scan_top<<<one, TPB, 0, s>>>(bind_of(L, BS_ONE), 1);
+  k_scan_write<<<tiles, TPB, 0, s>>>(bind_of(L, BS_TILES), 1);
+  k_cellscan<<<L.site[BS_RESORT].total, TPB, 0, s>>>(bind_of(L, BS_RESORT), 1);
+  k_srb_scatter<<<L.site[BS_RESORT].total, TPB, 0, s>>>(bind_of(L, BS_RESORT));
+  k_srb_finish<<<one, 1, 0, s>>>(bind_of(L, BS_ONE));
 }
 
 }  // namespace ge

@@ -1259,3 +1259,396 @@ ge_status ge_adjoint_backward(ge_ctx* c, const float* dLdx, int32_t on_device, d
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- batches ---
+// Many contexts advanced by one launch per phase: each launch gives every
+// context a share of its blocks.  The contexts live in one workspace so that
+// their tables can hold offsets from its base.
+struct ge_batch {
+  std::vector<ge_ctx*> mem;
+  std::vector<size_t> mem_off;
+  char* base = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  uint32_t cap[ge::BS_N] = {0};      // map entries per site
+  uint32_t T[ge::BS_N] = {0};        // blocks of the shared sites (0: fixed sites)
+  size_t off_tab = 0, off_map[ge::BS_N] = {0}, off_gsz[ge::BS_N] = {0};
+  ge::BatchLaunch L{};
+  std::vector<Dev> htab;
+  std::vector<uint32_t> hmap, hgsz;
+  bool use_graphs = true;
+  hipGraphExec_t gexec = nullptr;
+  bool gvalid = false;
+  double gdt = 0.0;
+  uint32_t gtotal[ge::BS_N] = {0};
+  hipStream_t cap_stream = nullptr;
+  int32_t R = 16;
+  std::string err;
+};
+
+namespace {
+
+constexpr uint32_t BATCH_MAX_BLOCKS = 65536;  // blocks of one shared launch
+
+// Tunable kernel of each shared site (-1: fixed site).
+const int SITE_TK[ge::BS_N] = {-1, ge::TK_ADVANCE, -1, ge::TK_MARKNOW, ge::TK_BRANCH, -1,
+                               ge::TK_CELLSCAN, ge::TK_SCATTER, ge::TK_CHILDREN, ge::TK_DIRTY,
+                               ge::TK_CONTAIN, ge::TK_STOPLINK, -1, -1, -1};
+
+uint32_t tiles_of(const Dev& d) {
+  return (uint32_t)((d.n_bricks + ge::SCAN_TILE_HOST - 1) / ge::SCAN_TILE_HOST);
+}
+uint32_t grid_cap(uint64_t n, uint32_t cap) {
+  uint64_t g = (n + 255) / 256;
+  g = std::max<uint64_t>(g, 1);
+  return (uint32_t)std::min<uint64_t>(g, cap);
+}
+
+struct BatchLayout {
+  std::vector<size_t> mem_off, mem_size;
+  size_t off_tab, off_map[ge::BS_N], off_gsz[ge::BS_N], total;
+  uint32_t cap[ge::BS_N];
+};
+
+const char* batch_layout(int32_t n, const ge_params* params, BatchLayout& B) {
+  if (n < 1 || (uint32_t)n > ge::BATCH_MAX || !params) return "bad batch size";
+  size_t off = 0;
+  uint64_t tiles = 0, resample = 0, nuc = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    size_t sz = 0;
+    if (ge_workspace_size(&params[i], &sz) != GE_OK) return "invalid member parameters";
+    B.mem_off.push_back(off);
+    B.mem_size.push_back(sz);
+    off += align_up(sz);
+    const Geometry g = geometry(&params[i]);
+    tiles += (g.n_bricks + ge::SCAN_TILE_HOST - 1) / ge::SCAN_TILE_HOST;
+    const uint64_t nodes = (uint64_t)params[i].field_n[0] * params[i].field_n[1] * params[i].field_n[2];
+    if (nodes) resample += grid_cap(nodes, 8192);
+    if (params[i].cap_sites > 0) nuc += grid_cap((uint64_t)params[i].cap_sites, 1024);
+  }
+  // A shared launch has max(T, 8 n) blocks, T <= BATCH_MAX_BLOCKS.
+  const uint32_t share = std::max<uint32_t>(BATCH_MAX_BLOCKS, 8u * (uint32_t)n);
+  for (int k = 0; k < ge::BS_N; ++k) B.cap[k] = share;
+  B.cap[ge::BS_ONE] = (uint32_t)n;
+  B.cap[ge::BS_NUCFIRE] = (uint32_t)n;
+  B.cap[ge::BS_TILES] = (uint32_t)tiles;
+  B.cap[ge::BS_RESAMPLE] = (uint32_t)std::max<uint64_t>(resample, 1);
+  B.cap[ge::BS_NUCTEST] = (uint32_t)std::max<uint64_t>(nuc, 1);
+  B.off_tab = off;
+  off += align_up(sizeof(Dev) * (size_t)n);
+  for (int k = 0; k < ge::BS_N; ++k) {  // the maps, contiguous
+    B.off_map[k] = off;
+    off += align_up(4 * (size_t)B.cap[k]);
+  }
+  for (int k = 0; k < ge::BS_N; ++k) B.off_gsz[k] = off + 4 * (size_t)k * (size_t)n;
+  off += align_up(4 * (size_t)ge::BS_N * (size_t)n);  // then the per-context block counts
+  B.total = off;
+  return nullptr;
+}
+
+ge_status bfail(ge_batch* b, ge_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  return s;
+}
+
+// Per-context blocks of every site for the current particle counts, the
+// tables (pointers as offsets, writer grids of the shared per-block lists set
+// to the contexts' shares) and their upload.
+ge_status batch_bind(ge_batch* b) {
+  const uint32_t n = (uint32_t)b->mem.size();
+  std::vector<double> w(n);
+  double wsum = 0;
+  for (uint32_t m = 0; m < n; ++m) {
+    ge_ctx* c = b->mem[m];
+    if (c->dead) return bfail(b, GE_ESTATE, "a member context is unusable after an earlier error");
+    ge_status st = read_counters(c);
+    if (st != GE_OK) return bfail(b, st, c->err);
+    w[m] = (double)c->host_cnt->n_active + 64.0;
+    wsum += w[m];
+  }
+  std::vector<uint32_t> g(n);
+  for (int k = 0; k < ge::BS_N; ++k) {
+    for (uint32_t m = 0; m < n; ++m) {
+      const Dev& d = b->mem[m]->d;
+      uint32_t v = 0;
+      switch (k) {
+        case ge::BS_ONE: v = 1; break;
+        case ge::BS_TILES: v = tiles_of(d); break;
+        case ge::BS_RESAMPLE:
+          v = b->mem[m]->field.kind == GE_FIELD_ROSENTHAL
+                  ? grid_cap((uint64_t)d.fn[0] * d.fn[1] * d.fn[2], 8192) : 0;
+          break;
+        case ge::BS_NUCTEST: v = d.n_sites ? grid_cap(d.n_sites, 1024) : 0; break;
+        case ge::BS_NUCFIRE: v = d.n_sites ? 1 : 0; break;
+        default: break;
+      }
+      g[m] = v;
+    }
+    if (SITE_TK[k] >= 0 || k == ge::BS_RESORT) {
+      // Shared site: 8 blocks per context, the rest in units of 8 by weight
+      // (largest remainders), T blocks in all (at least 8 per context).
+      const uint32_t units = std::max<uint32_t>(b->T[k] / 8u, n);
+      const uint32_t extra = units - n;
+      std::vector<std::pair<double, uint32_t>> frac(n);
+      uint32_t given = 0;
+      for (uint32_t m = 0; m < n; ++m) {
+        const double q = extra * w[m] / wsum;
+        const uint32_t u = (uint32_t)q;
+        g[m] = 8u * (1u + u);
+        given += u;
+        frac[m] = {q - u, m};
+      }
+      std::sort(frac.begin(), frac.end(), [](auto& x, auto& y) {
+        return x.first != y.first ? x.first > y.first : x.second < y.second;
+      });
+      for (uint32_t r = 0; given < extra; ++r, ++given) g[frac[r % n].second] += 8u;
+      // Per-block lists hold at most STREAM_GRID regions per context.
+      for (uint32_t m = 0; m < n; ++m) g[m] = std::min<uint32_t>(g[m], ge::STREAM_GRID);
+    }
+    uint32_t total = 0;
+    for (uint32_t m = 0; m < n; ++m) {
+      if ((uint64_t)total + g[m] > b->cap[k]) return bfail(b, GE_EINVAL, "batch site capacity");
+      for (uint32_t v = 0; v < g[m]; ++v) b->hmap[(b->off_map[k] - b->off_map[0]) / 4 + total + v] = m | (v << 12);
+      b->hgsz[(size_t)k * n + m] = g[m];
+      total += g[m];
+    }
+    b->L.site[k].total = total;
+    if (SITE_TK[k] == ge::TK_ADVANCE || SITE_TK[k] == ge::TK_CONTAIN)
+      for (uint32_t m = 0; m < n; ++m) b->htab[m].sched[SITE_TK[k]] = g[m];
+  }
+  for (uint32_t m = 0; m < n; ++m) {
+    const Dev& d = b->mem[m]->d;
+    Dev& t = b->htab[m];
+    const uint32_t sa = t.sched[ge::TK_ADVANCE], sc = t.sched[ge::TK_CONTAIN];
+    t = d;
+    t.sched[ge::TK_ADVANCE] = sa;
+    t.sched[ge::TK_CONTAIN] = sc;
+    if (t.tagA || t.tagB) return bfail(b, GE_ESTATE, "a member is recording an adjoint run");
+#define GE_TO_OFFSET(f) \
+    t.f = t.f ? (decltype(t.f))((uintptr_t)((char*)t.f - b->base)) : (decltype(t.f))ge::NULL_OFFSET;
+    GE_DEV_POINTERS(GE_TO_OFFSET)
+#undef GE_TO_OFFSET
+  }
+  hipStream_t s = b->stream;
+  char* w0 = b->base;
+  if (hipMemcpyAsync(w0 + b->off_tab, b->htab.data(), sizeof(Dev) * n, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(w0 + b->off_map[0], b->hmap.data(), 4 * b->hmap.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(w0 + b->off_gsz[0], b->hgsz.data(), 4 * b->hgsz.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bfail(b, GE_EDEVICE, "batch table upload failed");
+  return GE_OK;
+}
+
+ge_status batch_graph(ge_batch* b, double dt) {
+  bool same = b->gvalid && b->gdt == dt;
+  for (int k = 0; k < ge::BS_N && same; ++k) same = b->gtotal[k] == b->L.site[k].total;
+  if (same) return GE_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->gvalid = false;
+  if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return bfail(b, GE_EDEVICE, "capture stream");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int32_t k = 0; k < b->R; ++k) ge::launch_batch_step(b->L, dt, b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &g);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return bfail(b, GE_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+  b->gvalid = true;
+  b->gdt = dt;
+  for (int k = 0; k < ge::BS_N; ++k) b->gtotal[k] = b->L.site[k].total;
+  return GE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ge_status ge_batch_workspace_size(int32_t n, const ge_params* params, size_t* bytes) {
+  if (!bytes) return GE_EINVAL;
+  BatchLayout B;
+  if (batch_layout(n, params, B)) return GE_EINVAL;
+  *bytes = B.total;
+  return GE_OK;
+}
+
+ge_status ge_batch_create(int32_t n, const ge_params* params, void* workspace, size_t bytes,
+                          void* stream, ge_batch** out) {
+  if (!out || !workspace) return GE_EINVAL;
+  *out = nullptr;
+  BatchLayout B;
+  if (batch_layout(n, params, B)) return GE_EINVAL;
+  if (bytes < B.total || ((uintptr_t)workspace) % ALIGN) return GE_EINVAL;
+  ge_batch* b = new ge_batch();
+  b->base = (char*)workspace;
+  b->bytes = bytes;
+  b->stream = (hipStream_t)stream;
+  for (int32_t i = 0; i < n; ++i) {
+    ge_ctx* c = nullptr;
+    const ge_status st = ge_create(&params[i], b->base + B.mem_off[i], B.mem_size[i], stream, &c);
+    if (st != GE_OK) {
+      ge_batch_destroy(b);
+      return st;
+    }
+    b->mem.push_back(c);
+    b->mem_off.push_back(B.mem_off[i]);
+  }
+  b->off_tab = B.off_tab;
+  for (int k = 0; k < ge::BS_N; ++k) {
+    b->off_map[k] = B.off_map[k];
+    b->off_gsz[k] = B.off_gsz[k];
+    b->cap[k] = B.cap[k];
+    const int tk = SITE_TK[k];
+    b->T[k] = tk >= 0 ? b->mem[0]->d.sched[tk] : (k == ge::BS_RESORT ? ge::STREAM_GRID : 0);
+  }
+  // One host staging array for all maps, in the workspace's order.
+  b->hmap.assign((b->off_map[ge::BS_N - 1] - b->off_map[0]) / 4 + b->cap[ge::BS_N - 1], 0u);
+  b->hgsz.assign((size_t)ge::BS_N * n, 0u);
+  b->htab.resize(n);
+  b->L.tab = (const Dev*)(b->base + b->off_tab);
+  b->L.base = b->base;
+  for (int k = 0; k < ge::BS_N; ++k) {
+    b->L.site[k].map = (const uint32_t*)(b->base + b->off_map[k]);
+    b->L.site[k].gsz = (const uint32_t*)(b->base + b->off_gsz[0]) + (size_t)k * n;
+  }
+  b->R = b->mem[0]->resort_every;
+  *out = b;
+  return GE_OK;
+}
+
+ge_status ge_batch_destroy(ge_batch* b) {
+  if (!b) return GE_EINVAL;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (ge_ctx* c : b->mem) ge_destroy(c);
+  delete b;
+  return GE_OK;
+}
+
+ge_status ge_batch_member(ge_batch* b, int32_t i, ge_ctx** out) {
+  if (!b || !out || i < 0 || (size_t)i >= b->mem.size()) return GE_EINVAL;
+  *out = b->mem[(size_t)i];
+  return GE_OK;
+}
+
+const char* ge_batch_last_error(const ge_batch* b) { return b ? b->err.c_str() : ""; }
+
+ge_status ge_batch_use_graphs(ge_batch* b, int32_t on) {
+  if (!b) return GE_EINVAL;
+  b->use_graphs = on != 0;
+  return GE_OK;
+}
+
+ge_status ge_batch_step(ge_batch* b, double dt, int32_t n_steps, ge_step_stats* stats) {
+  if (!b) return GE_EINVAL;
+  if (!(std::isfinite(dt) && dt > 0) || n_steps < 0) return bfail(b, GE_EINVAL, "bad dt or n_steps");
+  ge_status st = batch_bind(b);
+  if (st != GE_OK) return st;
+  hipStream_t s = b->stream;
+  ge::launch_batch_reset_stats(b->L, s);
+  int32_t k = 0;
+  if (b->use_graphs && n_steps >= 2 * b->R) {
+    if ((st = batch_graph(b, dt)) != GE_OK) return st;
+    const int32_t reps = n_steps / b->R;
+    for (int32_t r = 0; r < reps; ++r)
+      if (hipGraphLaunch(b->gexec, s) != hipSuccess) return bfail(b, GE_EDEVICE, "graph launch");
+    k = reps * b->R;
+  }
+  for (; k < n_steps; ++k) ge::launch_batch_step(b->L, dt, s);
+  if (hipGetLastError() != hipSuccess) return bfail(b, GE_EDEVICE, "batch launch");
+  ge_status worst = GE_OK;
+  for (size_t m = 0; m < b->mem.size(); ++m) {
+    ge_ctx* c = b->mem[m];
+    st = read_counters(c);
+    if (st != GE_OK) return bfail(b, st, c->err);
+    c->hstep = c->host_cnt->step;
+    if (stats) fill_stats(c, &stats[m]);
+    st = error_status(c, c->host_cnt->err);
+    if (st != GE_OK && worst == GE_OK) {
+      worst = st;
+      b->err = "member " + std::to_string(m) + ": " + c->err;
+    }
+  }
+  return worst;
+}
+
+ge_status ge_batch_get_blocks(ge_batch* b, int32_t* blocks) {
+  if (!b || !blocks) return GE_EINVAL;
+  for (int t = 0; t < GE_N_TUNABLE; ++t) blocks[t] = 0;
+  for (int k = 0; k < ge::BS_N; ++k)
+    if (SITE_TK[k] >= 0) blocks[SITE_TK[k]] = (int32_t)b->T[k];
+  return GE_OK;
+}
+
+ge_status ge_batch_set_blocks(ge_batch* b, const int32_t* blocks) {
+  if (!b || !blocks) return GE_EINVAL;
+  for (int t = 0; t < GE_N_TUNABLE; ++t)
+    if (blocks[t] < 0 || blocks[t] > (int32_t)BATCH_MAX_BLOCKS) return bfail(b, GE_EINVAL, "blocks out of range");
+  for (int k = 0; k < ge::BS_N; ++k)
+    if (SITE_TK[k] >= 0 && blocks[SITE_TK[k]] > 0) b->T[k] = (uint32_t)blocks[SITE_TK[k]];
+  return GE_OK;
+}
+
+ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial, int32_t* blocks_out) {
+  if (!b || steps_per_trial < 1) return GE_EINVAL;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return bfail(b, GE_EDEVICE, "device query");
+  const uint32_t n = (uint32_t)b->mem.size();
+  std::vector<uint32_t> cand;
+  for (int per = 1; per <= 8; ++per) {
+    uint32_t g = (uint32_t)std::max(per * std::max(cus, 1), (int)(8 * n));
+    g = g / 8u * 8u;
+    if (cand.empty() || cand.back() != g) cand.push_back(g);
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return bfail(b, GE_EDEVICE, "events");
+  ge_status st = GE_OK;
+  for (int k = 0; k < ge::BS_N && st == GE_OK; ++k) {
+    if (SITE_TK[k] < 0) continue;
+    uint32_t best = b->T[k];
+    double best_cost = INFINITY;
+    for (uint32_t g : cand) {
+      b->T[k] = g;
+      if ((st = batch_bind(b)) != GE_OK) break;
+      (void)hipEventRecord(e0, b->stream);
+      for (int32_t r = 0; r < steps_per_trial; ++r) ge::launch_batch_step(b->L, dt, b->stream);
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = bfail(b, GE_EDEVICE, "autotune step");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      uint64_t adv = 0;
+      for (ge_ctx* c : b->mem) {
+        if ((st = read_counters(c)) != GE_OK) break;
+        adv += c->host_cnt->n_active;
+      }
+      if (st != GE_OK) break;
+      const double cost = ms / (double)std::max<uint64_t>(adv, 1);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = g;
+      }
+    }
+    b->T[k] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (ge_ctx* c : b->mem)
+    if (read_counters(c) == GE_OK) c->hstep = c->host_cnt->step;
+  if (st != GE_OK) return st;
+  return blocks_out ? ge_batch_get_blocks(b, blocks_out) : GE_OK;
+}
+
+}  // extern "C"

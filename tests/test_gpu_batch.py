@@ -1,0 +1,89 @@
+"""Batched launches: contexts of different sizes and kinds advanced together
+give, call after call, bitwise the states and counters of the same contexts
+stepped alone."""
+import numpy as np
+import pytest
+
+from paper_2504_12858_amd import binding as B
+from paper_2504_12858_amd import workloads as W
+from tests.gpu_helpers import context_for, gpu_claims, gpu_parts, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+CAPS = dict(cap_particles=1 << 20, cap_stopped=1 << 20, cap_claim_bricks=1 << 16)
+DT = 5e-4
+
+
+def _workloads():
+    return [
+        W.directional(seed=11, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0, h=10e-6),
+        W.directional(seed=12, n_grains=3, size=(0.2e-3, 0.2e-3, 0.3e-3), dT0=9.0),
+        W.cet(seed=5, size=(0.4e-3, 0.2e-3, 0.1e-3), lambda0=4e-6, grid_n=24, dT0=6.0, rate=2.0,
+              bulk_density=2e12, face_density=2e8, U=0.005, q=0.004),
+        W.single_grain(shell_r=6),
+        W.directional(seed=13, n_grains=16, size=(0.4e-3, 0.4e-3, 0.4e-3), dT0=10.0),
+    ]
+
+
+def _state(ctx):
+    p, _ = gpu_parts(ctx)
+    c, _ = gpu_claims(ctx)
+    return p.tobytes(), c.tobytes()
+
+
+def _stats(st):
+    st = dict(st)
+    st.pop("pair_tests")  # depends on the order within a cell
+    return st
+
+
+def test_batch_equals_plain_contexts():
+    require_gpu()
+    ws = _workloads()
+    batch = B.Batch([B.params_from_workload(w, **CAPS) for w in ws])
+    for m, w in zip(batch.members, ws):
+        m.init_from_workload(w)
+    refs = [context_for(w, **CAPS) for w in ws]
+    for n in (40, 7, 33, 48):
+        print(f"batch step {n}", flush=True)
+        got = batch.step(DT, n)
+        for i, (r, w) in enumerate(zip(refs, ws)):
+            want = r.step(DT, n)
+            assert _stats(got[i]) == _stats(want), (i, n)
+            assert _state(batch.members[i]) == _state(r), (i, n)
+    # A member stepped alone between batched steps, then the batch again.
+    batch.members[2].step(DT, 5)
+    refs[2].step(DT, 5)
+    batch.step(DT, 16)
+    for r in refs:
+        r.step(DT, 16)
+    for i, r in enumerate(refs):
+        assert _state(batch.members[i]) == _state(r), i
+        r.close()
+    batch.close()
+
+
+def test_batch_schedule_and_graphs_keep_results():
+    """Odd block totals, the autotuner and graphs off change only speed."""
+    require_gpu()
+    ws = _workloads()[:3]
+    outs = []
+    for mode in range(3):
+        batch = B.Batch([B.params_from_workload(w, **CAPS) for w in ws])
+        for m, w in zip(batch.members, ws):
+            m.init_from_workload(w)
+        if mode == 1:
+            batch.set_blocks({"advance": 24, "branch": 8, "contain": 4096, "dirty": 40,
+                              "scatter": 16, "children": 64, "marknow": 24, "stoplink": 8,
+                              "cellscan": 512})
+            batch.use_graphs(False)
+        if mode == 2:
+            batch.step(DT, 3)
+            best = batch.autotune(DT, 1)
+            assert all(v > 0 for v in best.values())
+        steps = [m.counts()["step"] for m in batch.members]
+        assert len(set(steps)) == 1 and steps[0] < 160
+        batch.step(DT, 160 - steps[0])
+        outs.append([_state(m) for m in batch.members])
+        batch.close()
+    assert outs[0] == outs[1] == outs[2]
