@@ -232,6 +232,78 @@ def adjoint_leg():
             "grad_a0_a1_theta": [float(v) for v in grad]}
 
 
+BATCH_MEMBERS = 128
+BATCH_STEPS = 200
+
+
+def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
+    """Batched against sequential plain stepping of the same contexts:
+    directional growth (2 x 2 x 4 mm, 64 grains, lambda0 = 5 um, cells of
+    10 um), member m with seed 1000 + m and a target of N_m ~ U{50k..1M}
+    stored particles (seed 4).  Two identical batches are advanced to the
+    snapshot (each member held once it reaches its target, checked every 32
+    steps); then batch A takes `steps` batched steps and batch B steps its
+    members one after the other with plain ge_step calls.  The states must
+    agree bit for bit (order-independent digests)."""
+    import numpy as np
+    import torch
+    from paper_2504_12858_amd import workloads as W
+    from paper_2504_12858_amd import binding as B
+    targets = W.rng(4).integers(50_000, 1_000_001, size=members)
+    ws = [W.directional(seed=1000 + m, h=10e-6) for m in range(members)]
+    dt = ws[0].dt
+
+    def params(m):
+        c = int(1.5 * targets[m]) + (1 << 18)
+        return B.params_from_workload(ws[m], cap_particles=c, cap_stopped=c,
+                                      cap_claim_bricks=1 << 17)
+
+    def snapshot():
+        b = B.Batch([params(m) for m in range(members)])
+        for m, w in zip(b.members, ws):
+            m.init_from_workload(w)
+        held = np.zeros(members, bool)
+        k = 0
+        while not held.all() and k < 6000:
+            st = b.step(dt, 32)
+            k += 32
+            for m in range(members):
+                if not held[m] and st[m]["n_active"] + st[m]["n_stopped"] >= targets[m]:
+                    b.members[m].hold(True)
+                    held[m] = True
+        for m in b.members:
+            m.hold(False)
+        return b, k
+
+    t0 = time.perf_counter()
+    a, ka = snapshot()
+    b, kb = snapshot()
+    log(f"[batch] snapshots in {time.perf_counter() - t0:.1f} s ({ka} batched steps)")
+    stored = sum(m.counts()["n_active"] + m.counts()["n_stopped"] for m in a.members)
+    for m in b.members:
+        m.prepare_step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sa = a.step(dt, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sb = [m.step(dt, steps) for m in b.members]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    equal = all(x.digest() == y.digest() for x, y in zip(a.members, b.members))
+    upd_a = sum(s["advanced"] for s in sa)
+    upd_b = sum(s["advanced"] for s in sb)
+    a.close()
+    b.close()
+    return {"workload": f"directional-{members}-members-50k-1M", "members": members,
+            "stored_at_snapshot": int(stored), "steps": steps,
+            "batched_s": round(t_batch, 4), "plain_sequential_s": round(t_plain, 4),
+            "speedup": round(t_plain / t_batch, 3),
+            "batched_updates_per_s": upd_a / t_batch, "plain_updates_per_s": upd_b / t_plain,
+            "bitwise_equal": bool(equal and upd_a == upd_b)}
+
+
 def cpu_baseline(ctx, w, budget_s=15.0, max_steps=8):
     """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot."""
     import numpy as np
@@ -280,6 +352,7 @@ def main():
     ap.add_argument("--target", type=int, default=TARGET_ACTIVE)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -363,9 +436,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
     ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
         log(f"[adjoint] {out['adjoint']}")
+    if not args.no_batch:
+        out["batched"] = batch_leg()
+        log(f"[batch] {out['batched']}")
     print(json.dumps(out), flush=True)
 
 

@@ -146,6 +146,9 @@ typedef struct ge_step_stats {
 #define GE_QUERY_CLAIMS 3    /* out: ge_claim_rec[...] */
 #define GE_QUERY_SITES 4     /* out: int32 site states [n_sites] */
 #define GE_QUERY_GRAINS 5    /* out: float [n_grains][24]: centre, pad, R (row-major), lambda0 R */
+#define GE_QUERY_DIGEST 6    /* out: uint64 [3]: order-independent digests of the active
+                                particles, the stopped particles and the claims (equal
+                                states give equal digests) */
 
 /* Exported particle: position computed on the device, binning cell. */
 typedef struct ge_particle_rec {
@@ -282,6 +285,14 @@ const char* ge_phase_name(int32_t phase);
    arguments (schedule, model, field, sites, time step).  Phase profiling
    (ge_profile) runs plain steps.  ge_use_graphs(ctx, 0) turns it off. */
 ge_status ge_use_graphs(ge_ctx* ctx, int32_t on);
+/* Records the step sequence for time step dt now, so that the next ge_step
+   call with that dt starts replaying at once. */
+ge_status ge_prepare_step(ge_ctx* ctx, double dt);
+
+/* Holds (on = 1) or releases (on = 0) a context: while held, its steps
+   change nothing (time and step count included); a held context is not in
+   error.  Used to freeze some contexts of a batch while the others go on. */
+ge_status ge_hold(ge_ctx* ctx, int32_t on);
 
 /* Launch schedule: the number of thread blocks (256 threads each) of every
    tunable kernel of ge_step.  Kernels: advance, reached-site marks, branch,

@@ -19,7 +19,8 @@ GE_OK, GE_EINVAL, GE_ECAPACITY, GE_ENUMERIC, GE_ECFL, GE_EDEVICE, GE_ESTATE = 0,
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "ENUMERIC", -4: "ECFL",
                 -5: "EDEVICE", -6: "ESTATE"}
 FIELD_UNIFORM, FIELD_LINEAR, FIELD_GRID, FIELD_ROSENTHAL = 0, 1, 2, 3
-QUERY_COUNTS, QUERY_PARTICLES, QUERY_GRAIN_MAP, QUERY_CLAIMS, QUERY_SITES, QUERY_GRAINS = range(6)
+(QUERY_COUNTS, QUERY_PARTICLES, QUERY_GRAIN_MAP, QUERY_CLAIMS, QUERY_SITES, QUERY_GRAINS,
+ QUERY_DIGEST) = range(7)
 ACTIVE, STOPPED, RETIRED = 0, 1, 2
 
 PARTICLE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("s", "<f4"),
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH):
         "ge_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
         "ge_tunable_name": ([C.c_int32], C.c_char_p),
         "ge_use_graphs": ([vp, C.c_int32], C.c_int32),
+        "ge_prepare_step": ([vp, C.c_double], C.c_int32),
+        "ge_hold": ([vp, C.c_int32], C.c_int32),
         "ge_batch_workspace_size": ([C.c_int32, P(ge_params), P(C.c_size_t)], C.c_int32),
         "ge_batch_create": ([C.c_int32, P(ge_params), vp, C.c_size_t, vp, P(vp)], C.c_int32),
         "ge_batch_destroy": ([vp], C.c_int32),
@@ -147,7 +150,7 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
             "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward",
-            "ge_use_graphs", "ge_batch_workspace_size", "ge_batch_create", "ge_batch_destroy",
+            "ge_use_graphs", "ge_prepare_step", "ge_hold", "ge_batch_workspace_size", "ge_batch_create", "ge_batch_destroy",
             "ge_batch_member", "ge_batch_last_error", "ge_batch_step", "ge_batch_use_graphs",
             "ge_batch_get_blocks", "ge_batch_set_blocks", "ge_batch_autotune")
 N_PHASES = 13
@@ -383,6 +386,18 @@ class Context:
 
     def use_graphs(self, on):
         self._check(self.lib.ge_use_graphs(self.ctx, int(bool(on))), "ge_use_graphs")
+
+    def prepare_step(self, dt):
+        self._check(self.lib.ge_prepare_step(self.ctx, float(dt)), "ge_prepare_step")
+
+    def hold(self, on):
+        self._check(self.lib.ge_hold(self.ctx, int(bool(on))), "ge_hold")
+
+    def digest(self):
+        """(active, stopped, claims) order-independent state digests."""
+        out = np.zeros(3, np.uint64)
+        self.query_envelope(QUERY_DIGEST, out)
+        return tuple(int(v) for v in out)
 
     def set_model(self, a, b, theta, branching):
         av = (C.c_double * 2)(*[float(v) for v in a])

@@ -23,6 +23,8 @@ enum : uint32_t { SITE_DORMANT = 0, SITE_FIRED = 1, SITE_ENGULFED = 2 };
 
 // Error bits of the sticky error word.
 enum : uint32_t { ERR_CAPACITY = 1, ERR_NUMERIC = 2, ERR_CFL = 4 };
+// Held context (not an error): every kernel of a step returns at once.
+constexpr uint32_t HOLD = 0x100u;
 
 // Grain table row: 24 floats.
 //   [0..2] centre, [3] spare (site tables: nucleation undercooling),
@@ -245,6 +247,7 @@ void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
                       const float spacing[3], uint32_t* out, hipStream_t s);
 void launch_batch_reset_stats(const BatchLaunch& L, hipStream_t s);
 void launch_batch_step(const BatchLaunch& L, double dt, hipStream_t s);
+void launch_digest(const Dev& d, unsigned long long* out /*[3], zeroed*/, hipStream_t s);
 void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s);
 void launch_adj_final(const Dev& d, hipStream_t s);
 void launch_adj_positions(const Dev& d, uint32_t n, float* xN, hipStream_t s);

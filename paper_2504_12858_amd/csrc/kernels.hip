@@ -395,9 +395,10 @@ __device__ __forceinline__ Chunk regions_of(const VGrid& V, uint32_t G_w) {
   return c;
 }
 
+// A context whose state must not change: a capacity error, or held.
 __device__ __forceinline__ bool dead(const Dev& D) {
   return (__hip_atomic_load(&D.cnt->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-          ERR_CAPACITY) != 0u;
+          (ERR_CAPACITY | HOLD)) != 0u;
 }
 
 // The context as seen by a kernel of the current step: the launch argument
@@ -1559,7 +1560,7 @@ __global__ void k_finish(Bind Bd, double dt) {
   VGrid V;
   Bd.bind(D, V);
   Counters* c = D.cnt;
-  if (c->err & ERR_CAPACITY) return;
+  if (c->err & (ERR_CAPACITY | HOLD)) return;
   // The step's sorted output becomes the next step's input; the step ends.
   c->par ^= 1u;
   c->t = c->t + dt;
@@ -1656,7 +1657,7 @@ __global__ void k_srb_finish(Bind Bd) {
   Dev D;
   VGrid V;
   Bd.bind(D, V);
-  if ((D.cnt->err & ERR_CAPACITY) || !resort_due(D)) return;
+  if ((D.cnt->err & (ERR_CAPACITY | HOLD)) || !resort_due(D)) return;
   D.cnt->n_sorted = min(D.cnt->n_stopped, D.cap_s);
   D.cnt->spar ^= 1u;  // the re-sorted copy becomes the stopped store
 }
@@ -2154,6 +2155,40 @@ __global__ void k_adj_reduce(const double* part, uint32_t nblocks, double* out) 
   if (l == 0) out[q] = x;
 }
 
+
+// Order-independent digest of the state: wrap-around sums of a hash of each
+// active record, each stopped record (flags other than the state cleared)
+// and each occupied claim slot (claimed and reached masks).
+__device__ __forceinline__ unsigned long long rec_digest(uint4 r) {
+  const unsigned long long lo = ((unsigned long long)r.y << 32) | r.x;
+  const unsigned long long hi = ((unsigned long long)(r.w & 0x3FFFFu) << 32) | r.z;
+  return mix64(lo ^ mix64(hi + 0x9e3779b97f4a7c15ull));
+}
+
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_digest(Bind Bd, unsigned long long* out) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  const uint32_t na = D.cnt->n_active, ns = min(D.cnt->n_stopped, D.cap_s);
+  unsigned long long a = 0, b = 0, c = 0;
+  for (uint32_t i = V.b * TPB + threadIdx.x; i < na; i += V.G * TPB) {
+    const uint4 r = D.A[i];
+    if ((rec_fl(r) & 3u) == ST_ACTIVE) a += rec_digest(r);
+  }
+  for (uint32_t j = V.b * TPB + threadIdx.x; j < ns; j += V.G * TPB) b += rec_digest(D.S[j]);
+  for (uint64_t k = (uint64_t)V.b * TPB + threadIdx.x; k <= D.cmask; k += (uint64_t)V.G * TPB) {
+    const unsigned long long key = D.ckeys[k];
+    if (key == CLAIM_EMPTY) continue;
+    unsigned long long h = mix64(key);
+    for (int w = 0; w < 16; ++w) h = mix64(h ^ D.cbits[k * 24 + w]);
+    c += h;
+  }
+  if (a) atomicAdd(&out[0], a);
+  if (b) atomicAdd(&out[1], b);
+  if (c) atomicAdd(&out[2], c);
+}
+
 // ============================================================ launchers ===
 static inline unsigned grid_for(uint64_t n, unsigned cap = 65535u) {
   uint64_t g = (n + TPB - 1) / TPB;
@@ -2278,6 +2313,9 @@ void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],
   k_grain_map<<<grid_for(total, 8192), TPB, 0, s>>>(Plain{d}, n[0], n[1], n[2], origin[0], origin[1],
                                                     origin[2], spacing[0], spacing[1], spacing[2],
                                                     out);
+}
+void launch_digest(const Dev& d, unsigned long long* out, hipStream_t s) {
+  k_digest<<<2048, TPB, 0, s>>>(Plain{d}, out);
 }
 void launch_adj_init(const Dev& d, uint32_t n, int32_t n_steps, hipStream_t s) {
   if (n) k_adj_init<<<grid_for(n, 4096), TPB, 0, s>>>(Plain{d}, n, n_steps);

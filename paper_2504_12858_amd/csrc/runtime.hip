@@ -34,7 +34,7 @@ struct Geometry {
 struct Layout {
   size_t A, B, P, spawn, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
       bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
-      stab, sstate, cand, fgrid, cnt, total;
+      stab, sstate, cand, fgrid, cnt, dig, total;
 };
 
 uint64_t next_pow2(uint64_t v) {
@@ -143,6 +143,7 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.cand = put(4 * (uint64_t)std::max(p->cap_sites, 1));
   L.fgrid = put(4 * std::max<uint64_t>(g.field_nodes, 8));
   L.cnt = put(sizeof(ge::Counters));
+  L.dig = put(64);
   L.total = off;
   return L;
 }
@@ -286,6 +287,7 @@ static ge_status write_counters(ge_ctx* c) {
 }
 
 static ge_status error_status(ge_ctx* c, uint32_t err) {
+  err &= ~ge::HOLD;  // a held context is not in error
   if (err == 0) return GE_OK;
   c->dead = true;
   if (err & ge::ERR_CAPACITY) return fail(c, GE_ECAPACITY, "capacity exceeded on the device");
@@ -864,6 +866,16 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
       if (!out || out_bytes < need || need == 0) return GE_OK;
       return deliver(c, c->d.sstate, out, need);
     }
+    case GE_QUERY_DIGEST: {
+      need = 3 * sizeof(unsigned long long);
+      if (needed) *needed = need;
+      if (!out || out_bytes < need) return GE_OK;
+      char* dig = c->ws + c->lay.dig;
+      HIPCHK(c, hipMemsetAsync(dig, 0, need, c->stream));
+      ge::launch_digest(c->d, (unsigned long long*)dig, c->stream);
+      HIPCHK(c, hipGetLastError());
+      return deliver(c, dig, out, need);
+    }
     case GE_QUERY_GRAINS: {
       need = (size_t)H.n_grains * ge::GT_STRIDE * 4;
       if (needed) *needed = need;
@@ -911,6 +923,24 @@ static const int TUNABLE_PHASE[GE_N_TUNABLE] = {1, 2, 3, 4, 5, 6, 7, 8, 9};
 
 const char* ge_tunable_name(int32_t k) {
   return (k >= 0 && k < GE_N_TUNABLE) ? TUNABLE_NAMES[k] : "";
+}
+
+ge_status ge_hold(ge_ctx* c, int32_t on) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  ge::Counters& H = *c->host_cnt;
+  H.err = on ? (H.err | ge::HOLD) : (H.err & ~ge::HOLD);
+  c->hstep = H.step;
+  return write_counters(c);
+}
+
+ge_status ge_prepare_step(ge_ctx* c, double dt) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(c, GE_EINVAL, "bad dt");
+  return c->use_graphs ? ensure_graph(c, dt) : GE_OK;
 }
 
 ge_status ge_use_graphs(ge_ctx* c, int32_t on) {

@@ -87,3 +87,35 @@ def test_batch_schedule_and_graphs_keep_results():
         outs.append([_state(m) for m in batch.members])
         batch.close()
     assert outs[0] == outs[1] == outs[2]
+
+
+def test_hold_and_digest():
+    """A held context does not change (digest, step count); released, it
+    continues exactly like a context that was never held.  Equal states have
+    equal digests, different states different ones."""
+    require_gpu()
+    ws = _workloads()[:2]
+    batch = B.Batch([B.params_from_workload(w, **CAPS) for w in ws])
+    for m, w in zip(batch.members, ws):
+        m.init_from_workload(w)
+    refs = [context_for(w, **CAPS) for w in ws]
+    batch.step(DT, 20)
+    for r in refs:
+        r.step(DT, 20)
+    d0 = batch.members[0].digest()
+    assert d0 == refs[0].digest() and d0 != refs[1].digest()
+    batch.members[0].hold(True)
+    st = batch.step(DT, 40)
+    assert st[0]["advanced"] == 0 and st[0]["step"] == 20
+    assert batch.members[0].digest() == d0
+    refs[1].step(DT, 40)
+    assert batch.members[1].digest() == refs[1].digest()
+    batch.members[0].hold(False)
+    batch.step(DT, 33)
+    refs[0].step(DT, 33)
+    refs[1].step(DT, 33)
+    for m, r in zip(batch.members, refs):
+        assert m.digest() == r.digest()
+        assert _state(m) == _state(r)
+        r.close()
+    batch.close()
