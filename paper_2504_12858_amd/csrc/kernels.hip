@@ -567,6 +567,62 @@ __device__ __forceinline__ bool cached_test(const Dev& D, SlotCache& c, uint32_t
   return (v & m) != 0;
 }
 
+// Claim words of the reached site S's slot around S: the z-layers
+// (S.z & 7) - 2 .. + 1.  Every target S + e and every same-step competitor
+// T - e' of a target T lies in them or in another slot.  The bits k_branch
+// tests do not change during the kernel (targets are claimed only by their
+// winner, reached sites carry this step's mark already), so they are read
+// once: one probe and twelve independent loads.
+struct SlotWin {
+  int bx, by, bz, z0;
+  unsigned long long a0, a1, a2, a3;  // claimed | reached | this step's marks
+  unsigned long long n0, n1, n2, n3;  // this step's marks
+};
+
+__device__ __forceinline__ SlotWin load_win(const Dev& D, uint32_t g, int sx, int sy, int sz) {
+  SlotWin w;
+  w.bx = sx >> 3;
+  w.by = sy >> 3;
+  w.bz = sz >> 3;
+  w.z0 = (sz & 7) - 2;
+  const int64_t slot = claim_find(D, claim_key(g, sx, sy, sz));
+  const unsigned long long* q = D.cbits + (size_t)(slot < 0 ? 0 : slot) * 24;
+  auto layer = [&](int z, unsigned long long& any, unsigned long long& now) {
+    unsigned long long c = 0, r = 0, m = 0;
+    if (slot >= 0 && z >= 0 && z < 8) {
+      c = load_relaxed(q + CB_CLAIMED + z);
+      r = load_relaxed(q + CB_REACHED + z);
+      m = load_relaxed(q + CB_NOW + z);
+    }
+    any = c | r | m;
+    now = m;
+  };
+  layer(w.z0, w.a0, w.n0);
+  layer(w.z0 + 1, w.a1, w.n1);
+  layer(w.z0 + 2, w.a2, w.n2);
+  layer(w.z0 + 3, w.a3, w.n3);
+  return w;
+}
+
+// Bit of a site in the window (false: the site is outside it).
+__device__ __forceinline__ bool win_bit(const SlotWin& w, int sx, int sy, int sz, bool now_only,
+                                        bool& hit) {
+  if ((sx >> 3) != w.bx || (sy >> 3) != w.by || (sz >> 3) != w.bz) return false;
+  const int j = (sz & 7) - w.z0;
+  if (j < 0 || j > 3) return false;
+  // Word j by masks (a select chain would be turned into an indexed table
+  // in scratch memory).
+  const unsigned long long m0 = 0ull - (unsigned long long)(j == 0);
+  const unsigned long long m1 = 0ull - (unsigned long long)(j == 1);
+  const unsigned long long m2 = 0ull - (unsigned long long)(j == 2);
+  const unsigned long long m3 = 0ull - (unsigned long long)(j == 3);
+  const unsigned long long v =
+      now_only ? ((w.n0 & m0) | (w.n1 & m1) | (w.n2 & m2) | (w.n3 & m3))
+               : ((w.a0 & m0) | (w.a1 & m1) | (w.a2 & m2) | (w.a3 & m3));
+  hit = ((v >> ((sx & 7) | ((sy & 7) << 3))) & 1ull) != 0ull;
+  return true;
+}
+
 // claim_or through a one-entry find-or-insert cache.
 __device__ __forceinline__ void cached_or(const Dev& D, SlotCache& c, uint32_t g, int sx, int sy,
                                           int sz, uint32_t which) {
@@ -829,25 +885,33 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     const uint32_t g = rec_grain(r);
     const int d = rec_dir(r);
     const float s2 = rec_s(r);
-    int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
-    S[d >> 1] += (d & 1) ? -1 : 1;
+    // Reached site S = departure site + one step in direction d.
+    const int dstep = (d & 1) ? -1 : 1;
+    const int S[3] = {rec_sx(r) + ((d >> 1) == 0 ? dstep : 0), rec_sy(r) + ((d >> 1) == 1 ? dstep : 0),
+                      rec_sz(r) + ((d >> 1) == 2 ? dstep : 0)};
     SlotCache sc{~0ull, -1};
+    const SlotWin win = load_win(D, g, S[0], S[1], S[2]);
     uint32_t mask = 0;
     for (int dd = 0; dd < 6; ++dd) {
       const int a = dd >> 1;
       const int sg = (dd & 1) ? -1 : 1;
-      if (sg * S[a] < 0) continue;  // octant rule: only outer directions
-      int T[3] = {S[0], S[1], S[2]};
-      T[a] += sg;
-      if (cached_test(D, sc, g, T[0], T[1], T[2], M_CLAIMED | M_REACHED | M_NOW)) continue;
+      if (sg * (a == 0 ? S[0] : a == 1 ? S[1] : S[2]) < 0) continue;  // octant rule: outer only
+      const int tx = S[0] + (a == 0 ? sg : 0), ty = S[1] + (a == 1 ? sg : 0),
+                tz = S[2] + (a == 2 ? sg : 0);
+      bool taken;
+      if (!win_bit(win, tx, ty, tz, false, taken))
+        taken = cached_test(D, sc, g, tx, ty, tz, M_CLAIMED | M_REACHED | M_NOW);
+      if (taken) continue;
       bool lose = false;
       for (int d2 = 0; d2 < dd && !lose; ++d2) {
         const int a2 = d2 >> 1;
         const int sg2 = (d2 & 1) ? -1 : 1;
-        int S2[3] = {T[0], T[1], T[2]};
-        S2[a2] -= sg2;
-        if (sg2 * S2[a2] < 0) continue;
-        if (cached_test(D, sc, g, S2[0], S2[1], S2[2], M_NOW)) lose = true;
+        const int ux = tx - (a2 == 0 ? sg2 : 0), uy = ty - (a2 == 1 ? sg2 : 0),
+                  uz = tz - (a2 == 2 ? sg2 : 0);
+        if (sg2 * (a2 == 0 ? ux : a2 == 1 ? uy : uz) < 0) continue;
+        bool rival;
+        if (!win_bit(win, ux, uy, uz, true, rival)) rival = cached_test(D, sc, g, ux, uy, uz, M_NOW);
+        if (rival) lose = true;
       }
       if (!lose) mask |= 1u << dd;
     }
@@ -864,10 +928,11 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       const uint32_t ci = cell_index(D, c.x, c.y, c.z);
       atomicAdd(&D.ccnt[ci], 1u);
       atomicAdd(&D.bcnt[ci / (uint32_t)BRICK_CELLS], 1u);
-      int T[3] = {S[0], S[1], S[2]};
-      T[dd >> 1] += (dd & 1) ? -1 : 1;
-      cached_or(D, wc, g, T[0], T[1], T[2], M_CLAIMED);
-      bbox_add(D, g, T[0], T[1], T[2]);
+      const int ta = dd >> 1, ts = (dd & 1) ? -1 : 1;
+      const int tx = S[0] + (ta == 0 ? ts : 0), ty = S[1] + (ta == 1 ? ts : 0),
+                tz = S[2] + (ta == 2 ? ts : 0);
+      cached_or(D, wc, g, tx, ty, tz, M_CLAIMED);
+      bbox_add(D, g, tx, ty, tz);
       nch += 1;
     }
     cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
@@ -1005,9 +1070,19 @@ __global__ __launch_bounds__(TPB) void k_cellscan(Bind Bd, int mode) {
 }
 
 // ------------------------------------------------------------- scatter ----
+// Grain range of a brick (one update per run of equal (brick, grain) lanes).
 __device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g) {
   atomicMin(&D.binfo[b].z, g);
   atomicMax(&D.binfo[b].w, g);
+}
+// The same for children, which arrive in no order: a relaxed read first, an
+// atomic only when the range grows (most children join a grain already
+// noted in their brick).
+__device__ __forceinline__ void note_grain_checked(const Dev& D, uint32_t b, uint32_t g) {
+  uint32_t* lo = &D.binfo[b].z;
+  uint32_t* hi = &D.binfo[b].w;
+  if (g < __hip_atomic_load(lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(lo, g);
+  if (g > __hip_atomic_load(hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(hi, g);
 }
 
 template <class Bind>
@@ -1090,7 +1165,7 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
         D.P[dst] = pos4(xc, gs);
         if (D.tagA) D.tagB[dst] = NIL;
       }
-      note_grain(D, ci / (uint32_t)BRICK_CELLS, gs);
+      note_grain_checked(D, ci / (uint32_t)BRICK_CELLS, gs);
     }
   }
 }
