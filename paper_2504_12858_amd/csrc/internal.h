@@ -151,6 +151,8 @@ struct Dev {
   uint32_t* dlist;     // [bricks] dirty bricks, per-block regions of the occupied list
   uint32_t* dlist_cnt; // [STREAM_GRID]
   uint32_t* dpart;     // [cap_p] particles of dirty bricks (indices into B, P)
+  unsigned long long* dmask;  // [bricks] per listed brick: cells whose particles need the test
+  uint32_t* doff;      // [bricks] per listed brick: offset in the block's stretch of dpart
   uint2* bown;         // [bricks] {step, owner word of the active particles: the grain of a
                        //  single-grain brick, or BOWN_CELLS for a dirty brick}
   uint2* cown;         // [cells] {owner word of the active particles (dirty bricks, this
@@ -192,7 +194,8 @@ struct Dev {
 #define GE_DEV_POINTERS(X)                                                                   \
   X(fgrid) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spawn_cnt) X(spawn_off) X(newstop)      \
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
-  X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(bown)        \
+  X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
+  X(doff) X(bown)                                                                             \
   X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(stab) X(sstate) X(cand) X(cnt) X(tagA)      \
   X(tagB) X(adj_rec) X(adj_nact) X(adj_sfin) X(adj_ck) X(adj_linc)
 constexpr uintptr_t NULL_OFFSET = ~(uintptr_t)0;

@@ -1170,13 +1170,16 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
   }
 }
 
-// One wave per occupied brick: the brick is "dirty" when it holds particles
-// of several grains or one of its 27 neighbourhood bricks (itself included)
-// holds a particle of another grain, active this step or stopped.  A
-// particle's contact stencil lies inside its brick's neighbourhood, so
-// particles of clean bricks cannot meet another grain.  Each block takes a
-// contiguous chunk of the occupied-brick list and lists its dirty bricks in
-// its own region of `dlist`.
+// One wave per occupied brick.  The brick is "dirty" when it holds
+// particles of several grains or one of its 27 neighbourhood bricks (itself
+// included) holds a particle of another grain, active this step or stopped.
+// A particle's contact stencil lies inside the 3x3x3 cells around its cell,
+// so it can meet another grain only if those cells reach a flagged brick:
+// every cell of a brick flagged itself, and otherwise the cells on the faces,
+// edges and corners that border a flagged neighbour.  Dirty bricks get the
+// owner words of their cells (read by the containment of their neighbours);
+// the particles of the cells that need the test go to one contiguous stretch
+// of the global list `dpart` per block.
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
   Dev D;
@@ -1194,6 +1197,18 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
   const Chunk ch = chunk_of(V, nocc, TPB / 64);
   const int lane = lane_id();
   const int nbx = D.nb[0], nby = D.nb[1], nbz = D.nb[2];
+  // Neighbour bricks the 3x3x3 cells around this lane's cell reach: bit
+  // (ox + 1) + 3 (oy + 1) + 9 (oz + 1).
+  const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+  uint32_t reach = 0;
+#pragma unroll
+  for (int t = 0; t < 27; ++t) {
+    const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+    const bool rx = ox == 0 || (ox < 0 ? lx == 0 : lx == 3);
+    const bool ry = oy == 0 || (oy < 0 ? ly == 0 : ly == 3);
+    const bool rz = oz == 0 || (oz < 0 ? lz == 0 : lz == 3);
+    if (rx && ry && rz) reach |= 1u << t;
+  }
   for (uint32_t k = ch.begin + (threadIdx.x >> 6); k < ch.end; k += TPB / 64) {
     const uint32_t b = D.occ[k];
     const uint4 own = D.binfo[b];
@@ -1205,21 +1220,18 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
       const int bz = (int)(b / ((uint32_t)nbx * (uint32_t)nby)) + lane / 9 - 1;
       if (bx >= 0 && by >= 0 && bz >= 0 && bx < nbx && by < nby && bz < nbz) {
         const uint32_t nb = ((uint32_t)bz * (uint32_t)nby + (uint32_t)by) * (uint32_t)nbx + (uint32_t)bx;
-        if (D.bepoch[nb] == epoch) {
-          const uint4 inf = D.binfo[nb];
-          if (!(inf.z == g && inf.w == g)) foreign = true;
-        }
+        const uint32_t be = D.bepoch[nb];
+        const uint4 inf = D.binfo[nb];
         const uint2 sb = D.sbsum[nb];
+        if (be == epoch && !(inf.z == g && inf.w == g)) foreign = true;
         if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) foreign = true;
       }
     }
-    const bool dirty = (own.z != own.w) || (__ballot(foreign) != 0ull);
+    // Flagged bricks; the brick itself (bit 13) when it holds several grains.
+    const uint32_t flags = (uint32_t)__ballot(foreign) | (own.z != own.w ? (1u << 13) : 0u);
+    const bool dirty = flags != 0u;
     if (lane == 0) D.bown[b] = make_uint2(epoch, dirty ? BOWN_CELLS : g);
     if (!dirty) continue;
-    if (lane == 0) {
-      D.dlist[ch.begin + atomicAdd(&s_n, 1u)] = b;
-      atomicAdd(&s_np, own.y);
-    }
     // Owner grain of the active particles of each of the brick's 64 cells
     // (one lane per cell).
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
@@ -1228,23 +1240,38 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     uint32_t owner = NIL;
     for (uint32_t j = st; j < en; ++j) owner = owner_merge(owner, grain_of(D.P[j]));
     D.cown[ci].x = owner;
+    const bool need = (flags & (1u << 13)) != 0u || (flags & reach) != 0u;
+    const uint32_t cnt = need ? en - st : 0u;
+    const unsigned long long mask = __ballot(cnt > 0u);
+    if (!mask) continue;
+    uint32_t tot;
+    (void)wave_excl_scan(cnt, tot);
+    if (lane == 0) {
+      const uint32_t slot = atomicAdd(&s_n, 1u);
+      D.dlist[ch.begin + slot] = b;
+      D.dmask[ch.begin + slot] = mask;
+      D.doff[ch.begin + slot] = atomicAdd(&s_np, tot);
+    }
   }
   __syncthreads();
-  // The particles of the block's dirty bricks go to one contiguous stretch
-  // of the global dirty-particle list.
-  if (threadIdx.x == 0) {
-    D.dlist_cnt[logical_block(V)] = s_n;
-    s_base = s_np ? atomicAdd(&D.cnt->n_dpart, s_np) : 0u;
-    s_np = 0;
-  }
+  if (threadIdx.x == 0) s_base = s_np ? atomicAdd(&D.cnt->n_dpart, s_np) : 0u;
   __syncthreads();
   const uint32_t nd = s_n, base = s_base;
   for (uint32_t k = threadIdx.x >> 6; k < nd; k += TPB / 64) {
-    const uint4 own = D.binfo[D.dlist[ch.begin + k]];
-    uint32_t off = 0;
-    if (lane == 0) off = atomicAdd(&s_np, own.y);
-    off = __shfl(off, 0);
-    for (uint32_t i = (uint32_t)lane; i < own.y; i += 64u) D.dpart[base + off + i] = own.x + i;
+    const uint32_t b = D.dlist[ch.begin + k];
+    const unsigned long long mask = D.dmask[ch.begin + k];
+    const uint32_t off = D.doff[ch.begin + k];
+    const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
+    uint32_t st = 0, cnt = 0;
+    if ((mask >> lane) & 1ull) {
+      const uint4 inf = D.binfo[b];
+      st = D.cstart[ci];
+      const uint32_t en = lane + 1 < BRICK_CELLS ? D.cstart[ci + 1] : inf.x + inf.y;
+      cnt = en - st;
+    }
+    uint32_t tot;
+    const uint32_t ex = wave_excl_scan(cnt, tot);
+    for (uint32_t j = 0; j < cnt; ++j) D.dpart[base + off + ex + j] = st + j;
   }
 }
 

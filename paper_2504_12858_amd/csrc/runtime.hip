@@ -33,7 +33,7 @@ struct Geometry {
 
 struct Layout {
   size_t A, B, P, spawn, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
-      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
+      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
       stab, sstate, cand, fgrid, cnt, dig, total;
 };
 
@@ -131,6 +131,8 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.dlist_cnt = put(4 * ge::STREAM_GRID);
   L.dpart = put(4 * cp);
   L.bown = put(8 * g.n_bricks);
+  L.dmask = put(8 * g.n_bricks);
+  L.doff = put(4 * g.n_bricks);
   L.cown = put(8 * g.n_cells);
   L.occ = put(4 * g.n_bricks);
   L.scan_tmp = put(8 * ntiles);
@@ -428,6 +430,8 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.dlist_cnt = (uint32_t*)(w + L.dlist_cnt);
   d.dpart = (uint32_t*)(w + L.dpart);
   d.bown = (uint2*)(w + L.bown);
+  d.dmask = (unsigned long long*)(w + L.dmask);
+  d.doff = (uint32_t*)(w + L.doff);
   d.cown = (uint2*)(w + L.cown);
   d.occ = (uint32_t*)(w + L.occ);
   d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
