@@ -242,8 +242,9 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
     10 um), member m with seed 1000 + m and a target of N_m ~ U{50k..1M}
     stored particles (seed 4).  Two identical batches are advanced to the
     snapshot (each member held once it reaches its target, checked every 32
-    steps); then batch A takes `steps` batched steps and batch B steps its
-    members one after the other with plain ge_step calls.  The states must
+    steps); batch A's shared launches are autotuned from the snapshot (which
+    is restored), then batch A takes `steps` batched steps and batch B steps
+    its members one after the other with plain ge_step calls.  The states must
     agree bit for bit (order-independent digests)."""
     import numpy as np
     import torch
@@ -280,6 +281,10 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
     b, kb = snapshot()
     log(f"[batch] snapshots in {time.perf_counter() - t0:.1f} s ({ka} batched steps)")
     stored = sum(m.counts()["n_active"] + m.counts()["n_stopped"] for m in a.members)
+    t0 = time.perf_counter()
+    blocks = a.autotune(dt, 2)
+    t_tune = time.perf_counter() - t0
+    log(f"[batch] autotuned {blocks} in {t_tune:.1f} s")
     for m in b.members:
         m.prepare_step(dt)
     torch.cuda.synchronize()
@@ -299,12 +304,13 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
     return {"workload": f"directional-{members}-members-50k-1M", "members": members,
             "stored_at_snapshot": int(stored), "steps": steps,
             "batched_s": round(t_batch, 4), "plain_sequential_s": round(t_plain, 4),
-            "speedup": round(t_plain / t_batch, 3),
+            "speedup": round(t_plain / t_batch, 3), "blocks": blocks,
+            "autotune_s": round(t_tune, 2),
             "batched_updates_per_s": upd_a / t_batch, "plain_updates_per_s": upd_b / t_plain,
             "bitwise_equal": bool(equal and upd_a == upd_b)}
 
 
-def cpu_baseline(ctx, w, budget_s=15.0, max_steps=8):
+def cpu_baseline(ctx, w, budget_s=15.0, max_steps=400):
     """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot."""
     import numpy as np
     from oracle import Oracle
@@ -354,9 +360,13 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
-    ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
+    ap.add_argument("--autotune", type=int, default=3, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
-                         "trial before the warm-up (0: default schedule)")
+                         "trial before the warm-up; every trial starts from the snapshot, "
+                         "which is restored (0: the default schedule)")
+    ap.add_argument("--schedule", default="", metavar="KERNEL=BLOCKS,...",
+                    help="blocks per launch of the named tunable kernels (others keep the "
+                         "default from the occupancy of the kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -372,6 +382,9 @@ def main():
     ctx = make_context(w)
     snap_steps, st = advance_to_snapshot(ctx, w, args.target)
     log(f"[snapshot] reached in {time.perf_counter() - t_build:.1f} s")
+    if args.schedule:
+        ctx.set_schedule({k: int(v) for k, v in
+                          (item.split("=") for item in args.schedule.split(","))})
     if args.autotune:
         t_tune = time.perf_counter()
         best = ctx.autotune(w.dt, args.autotune)
@@ -428,7 +441,8 @@ def main():
                    "active_at_snapshot": st["n_active"], "stopped_at_snapshot": st["n_stopped"],
                    "active_after": stats["n_active"], "stopped_after": stats["n_stopped"],
                    "timed_from_step": int(stats["step"]) - args.steps,
-                   "schedule": ctx.schedule(), "autotuned": bool(args.autotune)},
+                   "schedule": ctx.schedule(), "autotuned": bool(args.autotune),
+                   "schedule_set": args.schedule or None},
         "phases_ms_per_step": {k: round(v / max(n_prof, 1), 4) for k, v in phases.items()},
         "roofline": roofline,
         "step_roofline": step_roofline,

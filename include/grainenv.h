@@ -96,8 +96,9 @@ typedef struct ge_params {
   int64_t cap_stopped;   /* capacity of the stopped particle store */
   int32_t cap_grains;    /* maximum number of grains (< 2^28 - 1) */
   int32_t cap_sites;     /* maximum number of nucleation sites */
-  int64_t cap_claim_bricks; /* slots of the claim hash (rounded up to a power of two);
-                               each slot holds 8^3 lattice sites of one grain */
+  int64_t cap_claim_bricks; /* slots of the claim hash (rounded up to a power of two,
+                               at most 2^31); each slot holds 8^3 lattice sites of
+                               one grain */
   int32_t field_n[3];    /* largest field grid the context will hold (nodes per axis) */
   int32_t resort_every;  /* steps between re-sorts of the stopped store by cell (0: 16) */
 } ge_params;
@@ -303,17 +304,23 @@ ge_status ge_hold(ge_ctx* ctx, int32_t on);
    ge_get_schedule writes the current schedule.  ge_set_schedule takes a new
    one; an entry of 0 keeps the current value; EINVAL for an entry outside
    [1, GE_MAX_BLOCKS].
-   ge_autotune searches the schedule kernel by kernel: for each candidate it
-   runs steps_per_trial real steps timed with the phase profiler (1 to 8
-   blocks per compute unit: the state advances by at most
-   8 * GE_N_TUNABLE * steps_per_trial steps in all), scores each by its
-   phase time per particle update and keeps the best.  It leaves the best schedule set, writes it to blocks_out
-   (nullable), and leaves phase profiling off. */
+   ge_autotune searches the schedule kernel by kernel: for each candidate
+   (1 to 8 blocks per compute unit) it runs steps_per_trial real steps timed
+   with the phase profiler, scores each by its phase time per particle
+   update and keeps the best.  With a snapshot buffer (device memory of at
+   least ge_workspace_size bytes, owned by the caller, used only during the
+   call; EINVAL if smaller) the context's device state is copied to it
+   first, every trial starts from that state and the state is restored at
+   the end, so the call changes nothing but the schedule.  With snapshot =
+   NULL the trials advance the state (by at most 8 * GE_N_TUNABLE *
+   steps_per_trial steps in all).  It leaves the best schedule set, writes
+   it to blocks_out (nullable), and leaves phase profiling off. */
 #define GE_N_TUNABLE 9
 #define GE_MAX_BLOCKS 2048
 ge_status ge_get_schedule(ge_ctx* ctx, int32_t* blocks /*[GE_N_TUNABLE]*/);
 ge_status ge_set_schedule(ge_ctx* ctx, const int32_t* blocks /*[GE_N_TUNABLE]*/);
-ge_status ge_autotune(ge_ctx* ctx, double dt, int32_t steps_per_trial,
+ge_status ge_autotune(ge_ctx* ctx, double dt, int32_t steps_per_trial, void* snapshot,
+                      size_t snapshot_bytes,
                       int32_t* blocks_out /*[GE_N_TUNABLE], nullable*/);
 const char* ge_tunable_name(int32_t k);
 
@@ -407,7 +414,10 @@ ge_status ge_adjoint_backward(ge_ctx* ctx, const float* dLdx, int32_t on_device,
    shared launch: 0; at most 65536 each; a context gets at most 2048 blocks of
    a launch).  ge_batch_autotune: coordinate search of those totals
    (1 to 8 blocks per compute unit) scored by batched step time per active
-   particle; its trials run real steps (steps_per_trial per candidate).
+   particle; its trials run real steps (steps_per_trial per candidate), from
+   a snapshot of the whole batch workspace restored at the end when
+   `snapshot` (at least ge_batch_workspace_size bytes of device memory) is
+   given, else advancing every context.
    ge_batch_use_graphs: replays on (default) or off. */
 typedef struct ge_batch ge_batch;
 ge_status ge_batch_workspace_size(int32_t n, const ge_params* params /*[n]*/, size_t* bytes);
@@ -420,7 +430,8 @@ ge_status ge_batch_step(ge_batch* b, double dt, int32_t n_steps, ge_step_stats* 
 ge_status ge_batch_use_graphs(ge_batch* b, int32_t on);
 ge_status ge_batch_get_blocks(ge_batch* b, int32_t* blocks /*[GE_N_TUNABLE]*/);
 ge_status ge_batch_set_blocks(ge_batch* b, const int32_t* blocks /*[GE_N_TUNABLE]*/);
-ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial,
+ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial, void* snapshot,
+                            size_t snapshot_bytes,
                             int32_t* blocks_out /*[GE_N_TUNABLE], nullable*/);
 
 #ifdef __cplusplus

@@ -113,7 +113,7 @@ def load_library(path: str = LIB_PATH):
         "ge_phase_name": ([C.c_int32], C.c_char_p),
         "ge_get_schedule": ([vp, P(C.c_int32)], C.c_int32),
         "ge_set_schedule": ([vp, P(C.c_int32)], C.c_int32),
-        "ge_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
+        "ge_autotune": ([vp, C.c_double, C.c_int32, vp, C.c_size_t, P(C.c_int32)], C.c_int32),
         "ge_tunable_name": ([C.c_int32], C.c_char_p),
         "ge_use_graphs": ([vp, C.c_int32], C.c_int32),
         "ge_prepare_step": ([vp, C.c_double], C.c_int32),
@@ -127,7 +127,8 @@ def load_library(path: str = LIB_PATH):
         "ge_batch_use_graphs": ([vp, C.c_int32], C.c_int32),
         "ge_batch_get_blocks": ([vp, P(C.c_int32)], C.c_int32),
         "ge_batch_set_blocks": ([vp, P(C.c_int32)], C.c_int32),
-        "ge_batch_autotune": ([vp, C.c_double, C.c_int32, P(C.c_int32)], C.c_int32),
+        "ge_batch_autotune": ([vp, C.c_double, C.c_int32, vp, C.c_size_t, P(C.c_int32)],
+                              C.c_int32),
         "ge_set_model": ([vp, P(C.c_double), P(C.c_double), C.c_double, C.c_int32], C.c_int32),
         "ge_adjoint_workspace_size": ([vp, C.c_int32, C.c_int32, P(C.c_size_t)], C.c_int32),
         "ge_adjoint_forward": ([vp, C.c_double, C.c_int32, C.c_int32, vp, C.c_size_t,
@@ -453,10 +454,19 @@ class Context:
         self._check(rc, "ge_adjoint_backward")
         return tuple(g)
 
-    def autotune(self, dt, steps_per_trial=2):
+    def autotune(self, dt, steps_per_trial=2, restore=True):
+        """Autotunes the launch schedule; with restore, every trial starts from
+        the current state and the state is left unchanged (a device snapshot
+        of the workspace's size is held during the call)."""
         b = (C.c_int32 * N_TUNABLE)()
-        self._check(self.lib.ge_autotune(self.ctx, float(dt), int(steps_per_trial), b),
-                    "ge_autotune")
+        snap, ptr, n = None, None, 0
+        if restore:
+            n = workspace_size(self.params)
+            snap = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+            ptr = C.c_void_p(snap.data_ptr())
+        rc = self.lib.ge_autotune(self.ctx, float(dt), int(steps_per_trial), ptr, n, b)
+        del snap
+        self._check(rc, "ge_autotune")
         names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
         return dict(zip(names, list(b)))
 
@@ -575,10 +585,18 @@ class Batch:
         b = (C.c_int32 * N_TUNABLE)(*[int(blocks.get(n, 0)) for n in names])
         self._check(self.lib.ge_batch_set_blocks(self.b, b), "ge_batch_set_blocks")
 
-    def autotune(self, dt, steps_per_trial=1):
+    def autotune(self, dt, steps_per_trial=1, restore=True):
+        """Autotunes the shared launches; with restore, from a snapshot of the
+        batch workspace that is restored at the end."""
         b = (C.c_int32 * N_TUNABLE)()
-        self._check(self.lib.ge_batch_autotune(self.b, float(dt), int(steps_per_trial), b),
-                    "ge_batch_autotune")
+        snap, ptr, n = None, None, 0
+        if restore:
+            n = self.workspace.numel()
+            snap = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+            ptr = C.c_void_p(snap.data_ptr())
+        rc = self.lib.ge_batch_autotune(self.b, float(dt), int(steps_per_trial), ptr, n, b)
+        del snap
+        self._check(rc, "ge_batch_autotune")
         names = [self.lib.ge_tunable_name(k).decode() for k in range(N_TUNABLE)]
         return dict(zip(names, list(b)))
 

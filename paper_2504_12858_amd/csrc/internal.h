@@ -126,6 +126,8 @@ struct Dev {
   float4* P;
   uint32_t cap_p;
   uint32_t* spawn;        // [cap_p], per-block regions
+  uint32_t* spslot;       // [cap_p] claim slot of each spawner's reached site, by
+                          //  position in the step's spawner list
   uint32_t* spawn_cnt;    // [STREAM_GRID]
   uint32_t* spawn_off;    // [STREAM_GRID + 1] exclusive prefix of spawn_cnt
   uint32_t* newstop;      // [cap_p], per-block regions
@@ -192,7 +194,7 @@ struct Dev {
 // Every pointer member of Dev (a batched launch stores them as offsets from
 // the batch workspace and rebuilds them on the device).
 #define GE_DEV_POINTERS(X)                                                                   \
-  X(fgrid) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spawn_cnt) X(spawn_off) X(newstop)      \
+  X(fgrid) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \

@@ -271,13 +271,6 @@ __device__ __forceinline__ void claim_or(const Dev& D, uint32_t g, int sx, int s
   if (which & M_NOW) atomicOr(w + CB_NOW, m);
 }
 
-__device__ __forceinline__ void claim_clear_now(const Dev& D, uint32_t g, int sx, int sy, int sz) {
-  int64_t slot = claim_find(D, claim_key(g, sx, sy, sz));
-  if (slot < 0) return;
-  const uint32_t b = site_bit(sx, sy, sz);
-  atomicAnd(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), ~(1ull << (b & 63)));
-}
-
 // True if the site is in any of the masks selected by `which`.
 __device__ __forceinline__ bool claim_test(const Dev& D, uint32_t g, int sx, int sy, int sz,
                                            uint32_t which) {
@@ -579,17 +572,16 @@ struct SlotWin {
   unsigned long long n0, n1, n2, n3;  // this step's marks
 };
 
-__device__ __forceinline__ SlotWin load_win(const Dev& D, uint32_t g, int sx, int sy, int sz) {
+__device__ __forceinline__ SlotWin load_win(const Dev& D, uint32_t slot, int sx, int sy, int sz) {
   SlotWin w;
   w.bx = sx >> 3;
   w.by = sy >> 3;
   w.bz = sz >> 3;
   w.z0 = (sz & 7) - 2;
-  const int64_t slot = claim_find(D, claim_key(g, sx, sy, sz));
-  const unsigned long long* q = D.cbits + (size_t)(slot < 0 ? 0 : slot) * 24;
+  const unsigned long long* q = D.cbits + (size_t)(slot == NIL ? 0u : slot) * 24;
   auto layer = [&](int z, unsigned long long& any, unsigned long long& now) {
     unsigned long long c = 0, r = 0, m = 0;
-    if (slot >= 0 && z >= 0 && z < 8) {
+    if (slot != NIL && z >= 0 && z < 8) {
       c = load_relaxed(q + CB_CLAIMED + z);
       r = load_relaxed(q + CB_REACHED + z);
       m = load_relaxed(q + CB_NOW + z);
@@ -844,7 +836,9 @@ __device__ __forceinline__ uint32_t spawn_item(const Dev& D, const SpawnView& v,
   return D.spawn[chunk_at(v.n, TPB, v.G, lo).begin + (i - s_off[lo])];
 }
 
-// Marks the site each spawner has reached as reached during this step.
+// Marks the site each spawner has reached as reached during this step and
+// keeps the claim slot of that site for the branching and the clearing of
+// the mark.
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_mark_now(Bind Bd) {
   Dev D;
@@ -859,7 +853,11 @@ __global__ __launch_bounds__(TPB) void k_mark_now(Bind Bd) {
     const int d = rec_dir(r);
     int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
     S[d >> 1] += (d & 1) ? -1 : 1;
-    claim_or(D, rec_grain(r), S[0], S[1], S[2], M_NOW);
+    const int64_t slot = claim_get(D, claim_key(rec_grain(r), S[0], S[1], S[2]));
+    D.spslot[i] = slot < 0 ? NIL : (uint32_t)slot;
+    if (slot < 0) continue;
+    const uint32_t b = site_bit(S[0], S[1], S[2]);
+    atomicOr(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), 1ull << (b & 63));
   }
 }
 
@@ -890,7 +888,8 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     const int S[3] = {rec_sx(r) + ((d >> 1) == 0 ? dstep : 0), rec_sy(r) + ((d >> 1) == 1 ? dstep : 0),
                       rec_sz(r) + ((d >> 1) == 2 ? dstep : 0)};
     SlotCache sc{~0ull, -1};
-    const SlotWin win = load_win(D, g, S[0], S[1], S[2]);
+    const uint32_t slot = D.spslot[k];
+    const SlotWin win = load_win(D, slot, S[0], S[1], S[2]);
     uint32_t mask = 0;
     for (int dd = 0; dd < 6; ++dd) {
       const int a = dd >> 1;
@@ -920,7 +919,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
     const float* G = D.gtab + (size_t)g * GT_STRIDE;
     const float sc2 = s2 - D.lambda0;
-    SlotCache wc{~0ull, -1};
+    SlotCache wc{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
     for (int dd = 0; dd < 6; ++dd) {
       if (!(mask & (1u << dd))) continue;
       const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc2);
@@ -1148,7 +1147,11 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
     const int d = rec_dir(r);
     int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
     S[d >> 1] += (d & 1) ? -1 : 1;
-    claim_clear_now(D, gs, S[0], S[1], S[2]);
+    const uint32_t slot = D.spslot[k];
+    if (slot != NIL) {
+      const uint32_t b = site_bit(S[0], S[1], S[2]);
+      atomicAnd(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), ~(1ull << (b & 63)));
+    }
     const uint32_t mask = (fl >> 8) & 63u;
     if (!mask) continue;
     const float* G = D.gtab + (size_t)gs * GT_STRIDE;
@@ -1237,8 +1240,15 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
     const uint32_t st = D.cstart[ci];
     const uint32_t en = lane + 1 < BRICK_CELLS ? D.cstart[ci + 1] : own.x + own.y;
+    // Four independent loads per round (the tail round repeats the last
+    // particle, which leaves the owner unchanged).
     uint32_t owner = NIL;
-    for (uint32_t j = st; j < en; ++j) owner = owner_merge(owner, grain_of(D.P[j]));
+    for (uint32_t j = st; j < en; j += 4u) {
+      const uint32_t l = en - 1u;
+      const uint32_t g0 = grain_of(D.P[j]), g1 = grain_of(D.P[min(j + 1u, l)]);
+      const uint32_t g2 = grain_of(D.P[min(j + 2u, l)]), g3 = grain_of(D.P[min(j + 3u, l)]);
+      owner = owner_merge(owner_merge(owner_merge(owner_merge(owner, g0), g1), g2), g3);
+    }
     D.cown[ci].x = owner;
     const bool need = (flags & (1u << 13)) != 0u || (flags & reach) != 0u;
     const uint32_t cnt = need ? en - st : 0u;

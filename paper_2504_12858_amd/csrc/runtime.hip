@@ -32,7 +32,7 @@ struct Geometry {
 };
 
 struct Layout {
-  size_t A, B, P, spawn, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
+  size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
       bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
       stab, sstate, cand, fgrid, cnt, dig, total;
 };
@@ -61,7 +61,7 @@ const char* check_params(const ge_params* p) {
   if (p->cap_stopped < 1 || p->cap_stopped > (1ll << 31)) return "cap_stopped out of range";
   if (p->cap_grains < 1 || p->cap_grains > (1 << 28) - 2) return "cap_grains out of range";
   if (p->cap_sites < 0) return "cap_sites out of range";
-  if (p->cap_claim_bricks < 1 || p->cap_claim_bricks > (1ll << 32)) return "cap_claim_bricks out of range";
+  if (p->cap_claim_bricks < 1 || p->cap_claim_bricks > (1ll << 31)) return "cap_claim_bricks out of range";
   double diag = 0;
   double nb_total = 1;
   for (int a = 0; a < 3; ++a) {
@@ -109,6 +109,7 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.B = put(16 * cp);
   L.P = put(16 * cp);
   L.spawn = put(4 * cp);
+  L.spslot = put(4 * cp);
   L.spawn_cnt = put(4 * ge::STREAM_GRID);
   L.spawn_off = put(4 * (ge::STREAM_GRID + 1));
   L.newstop = put(4 * cp);
@@ -407,6 +408,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.P = (float4*)(w + L.P);
   d.cap_p = (uint32_t)p->cap_particles;
   d.spawn = (uint32_t*)(w + L.spawn);
+  d.spslot = (uint32_t*)(w + L.spslot);
   d.spawn_cnt = (uint32_t*)(w + L.spawn_cnt);
   d.spawn_off = (uint32_t*)(w + L.spawn_off);
   d.newstop = (uint32_t*)(w + L.newstop);
@@ -968,10 +970,13 @@ ge_status ge_set_schedule(ge_ctx* c, const int32_t* blocks) {
   return sync_dev(c);
 }
 
-ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* blocks_out) {
+ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, void* snapshot,
+                      size_t snapshot_bytes, int32_t* blocks_out) {
   if (!c) return GE_EINVAL;
   if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
   if (steps_per_trial < 1) return fail(c, GE_EINVAL, "steps_per_trial must be >= 1");
+  if (snapshot && snapshot_bytes < c->lay.total)
+    return fail(c, GE_EINVAL, "snapshot smaller than the context's workspace");
   int dev = 0, cus = 0;
   ge_status st = hip_check(c, hipGetDevice(&dev), "autotune");
   if (st == GE_OK)
@@ -985,12 +990,25 @@ ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* bl
     g = g >= 8u ? g / 8u * 8u : g;
     if (cand.empty() || cand.back() != g) cand.push_back(g);
   }
+  // With a snapshot every trial starts from the state of the call, which is
+  // restored at the end.
+  const uint64_t hstep0 = c->hstep;
+  auto restore = [&]() -> ge_status {
+    c->hstep = hstep0;
+    return hip_check(c, hipMemcpyAsync(c->ws, snapshot, c->lay.total, hipMemcpyDeviceToDevice,
+                                       c->stream), "autotune snapshot");
+  };
+  if (snapshot &&
+      (st = hip_check(c, hipMemcpyAsync(snapshot, c->ws, c->lay.total, hipMemcpyDeviceToDevice,
+                                        c->stream), "autotune snapshot")) != GE_OK)
+    return st;
   for (int k = 0; k < GE_N_TUNABLE; ++k) {
     uint32_t best = c->d.sched[k];
     double best_cost = INFINITY;
     for (uint32_t g : cand) {
       c->d.sched[k] = g;
       if ((st = sync_dev(c)) != GE_OK) return st;
+      if (snapshot && (st = restore()) != GE_OK) return st;
       ge_profile(c, 1);
       ge_step_stats s{};
       st = ge_step(c, dt, steps_per_trial, &s);
@@ -1008,6 +1026,9 @@ ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, int32_t* bl
     c->d.sched[k] = best;
   }
   if ((st = sync_dev(c)) != GE_OK) return st;
+  if (snapshot) {
+    if ((st = restore()) != GE_OK || (st = read_counters(c)) != GE_OK) return st;
+  }
   if (blocks_out) return ge_get_schedule(c, blocks_out);
   return GE_OK;
 }
@@ -1630,8 +1651,11 @@ ge_status ge_batch_set_blocks(ge_batch* b, const int32_t* blocks) {
   return GE_OK;
 }
 
-ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial, int32_t* blocks_out) {
+ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial, void* snapshot,
+                            size_t snapshot_bytes, int32_t* blocks_out) {
   if (!b || steps_per_trial < 1) return GE_EINVAL;
+  if (snapshot && snapshot_bytes < b->bytes)
+    return bfail(b, GE_EINVAL, "snapshot smaller than the batch workspace");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1647,12 +1671,23 @@ ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial, int
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return bfail(b, GE_EDEVICE, "events");
   ge_status st = GE_OK;
+  std::vector<uint64_t> hstep0;
+  for (ge_ctx* c : b->mem) hstep0.push_back(c->hstep);
+  auto copy = [&](void* dst, const void* src) -> ge_status {
+    return hipMemcpyAsync(dst, src, b->bytes, hipMemcpyDeviceToDevice, b->stream) == hipSuccess
+               ? GE_OK
+               : bfail(b, GE_EDEVICE, "autotune snapshot");
+  };
+  // The snapshot covers the launch tables of the batch too: a restore comes
+  // before batch_bind, which writes the tables of the trial's totals.
+  if (snapshot) st = copy(snapshot, b->base);
   for (int k = 0; k < ge::BS_N && st == GE_OK; ++k) {
     if (SITE_TK[k] < 0) continue;
     uint32_t best = b->T[k];
     double best_cost = INFINITY;
     for (uint32_t g : cand) {
       b->T[k] = g;
+      if (snapshot && (st = copy(b->base, snapshot)) != GE_OK) break;
       if ((st = batch_bind(b)) != GE_OK) break;
       (void)hipEventRecord(e0, b->stream);
       for (int32_t r = 0; r < steps_per_trial; ++r) ge::launch_batch_step(b->L, dt, b->stream);
@@ -1679,6 +1714,11 @@ ge_status ge_batch_autotune(ge_batch* b, double dt, int32_t steps_per_trial, int
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (snapshot && st == GE_OK) {
+    st = copy(b->base, snapshot);
+    for (size_t i = 0; i < b->mem.size(); ++i) b->mem[i]->hstep = hstep0[i];
+    if (st == GE_OK) st = batch_bind(b);
+  }
   for (ge_ctx* c : b->mem)
     if (read_counters(c) == GE_OK) c->hstep = c->host_cnt->step;
   if (st != GE_OK) return st;

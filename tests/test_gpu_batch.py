@@ -79,8 +79,11 @@ def test_batch_schedule_and_graphs_keep_results():
             batch.use_graphs(False)
         if mode == 2:
             batch.step(DT, 3)
-            best = batch.autotune(DT, 1)
+            before = [_state(m) for m in batch.members]
+            best = batch.autotune(DT, 2)
             assert all(v > 0 for v in best.values())
+            assert [_state(m) for m in batch.members] == before
+            best = batch.autotune(DT, 1, restore=False)
         steps = [m.counts()["step"] for m in batch.members]
         assert len(set(steps)) == 1 and steps[0] < 160
         batch.step(DT, 160 - steps[0])

@@ -212,21 +212,31 @@ def test_schedule_validation():
 
 
 def test_autotune_keeps_results():
-    """The autotuner runs real steps; the state after it equals a plain run
+    """With a snapshot the autotuner leaves the state as it found it; without
+    one its trials are real steps, and the state after it equals a plain run
     of the same number of steps."""
     require_gpu()
     w = _scaled_directional(seed=8)
+    ref = context_for(w)
+    ref.step(w.dt, 40)
+    want = _state_bytes(ref)
     ctx = context_for(w)
     ctx.step(w.dt, 40)
-    best = ctx.autotune(w.dt, steps_per_trial=1)
+    best = ctx.autotune(w.dt, steps_per_trial=2, restore=True)
     assert all(1 <= v <= B.MAX_BLOCKS for v in best.values())
     assert ctx.schedule() == best
+    assert ctx.counts()["step"] == 40
+    assert _state_bytes(ctx) == want
+    # The next steps continue exactly like the reference's.
+    ctx.step(w.dt, 20)
+    ref.step(w.dt, 20)
+    assert _state_bytes(ctx) == _state_bytes(ref)
+    ctx.autotune(w.dt, steps_per_trial=1, restore=False)
     n = ctx.counts()["step"]
-    assert 40 < n <= 40 + 8 * B.N_TUNABLE
+    assert 60 < n <= 60 + 8 * B.N_TUNABLE
     got = _state_bytes(ctx)
     ctx.close()
-    ref = context_for(w)
-    ref.step(w.dt, n)
+    ref.step(w.dt, n - 60)
     assert _state_bytes(ref) == got
     ref.close()
 
