@@ -1423,58 +1423,187 @@ __device__ __forceinline__ bool walk_recent(const Dev& D, uint32_t j, P3 p, uint
   return false;
 }
 
-// Containment test of one particle of grain g.  The owner words of all
-// stencil cells are read first (one memory round trip), then the candidate
-// ranges of the cells that hold another grain (a second one), then the
-// candidates.  A clamped axis repeats its cell; the repeat is skipped.
-__device__ bool contact(const Dev& D, uint32_t epoch, P3 p, uint32_t g, uint32_t& tests) {
+// ----------------------------------------------- wave-shared candidates ---
+// The candidates of a particle are very uneven (from none to long cell lists),
+// and a wave waits for its slowest lane.  The containment therefore lists,
+// for the wave's 64 particles, every candidate source of every stencil cell
+// that holds another grain (a range of the cell-sorted active store, a range
+// of the cell-sorted stopped store, the head of a recent-stop list) in shared
+// memory, and the lanes take the sources in turn, whichever particle they
+// belong to.  Entry: {first index or list head, length, kind << 6 | lane of
+// the particle}.
+constexpr int CE_MAX = 384;  // entries per wave and round
+constexpr uint32_t CE_ACTIVE = 0u, CE_STOPPED = 1u, CE_RECENT = 2u;
+
+// Cell k of the stencil: S8 (2 x 2 x 2 cells, k < 8) or 3 x 3 x 3 (k < 27).
+// False for a cell outside the clamped stencil (or the repeat of a clamped
+// axis in the 2 x 2 x 2 case).
+struct Stencil {
   int x0, x1, y0, y1, z0, z1;
-  stencil_axis(D, p.x, 0, x0, x1);
-  stencil_axis(D, p.y, 1, y0, y1);
-  stencil_axis(D, p.z, 2, z0, z1);
-  const float rc2 = D.rc2;
-  if (D.stencil8) {
-    CellOwners o[8];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int x = (k & 1) ? x1 : x0, y = (k & 2) ? y1 : y0, z = (k & 4) ? z1 : z0;
-      o[k] = cell_owners(D, epoch, x, y, z, g);
-      const bool dup = ((k & 1) && x1 == x0) || ((k & 2) && y1 == y0) || ((k & 4) && z1 == z0);
-      if (dup) o[k].act = o[k].stp = false;
-      any |= o[k].act | o[k].stp;
-    }
-    if (!any) return false;
-    CellRanges r[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) r[k] = cell_ranges(D, o[k]);
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (scan_range(D.P, r[k].ast, r[k].aen, p, g, rc2, tests) ||
-          scan_range(D.PS, r[k].sst, r[k].sen, p, g, rc2, tests))
-        return true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (walk_recent(D, r[k].hd, p, g, tests)) return true;
-    return false;
+};
+template <bool S8>
+__device__ __forceinline__ bool stencil_cell(const Stencil& s, int k, int& x, int& y, int& z) {
+  if (S8) {
+    x = (k & 1) ? s.x1 : s.x0;
+    y = (k & 2) ? s.y1 : s.y0;
+    z = (k & 4) ? s.z1 : s.z0;
+    return !(((k & 1) && s.x1 == s.x0) || ((k & 2) && s.y1 == s.y0) || ((k & 4) && s.z1 == s.z0));
   }
-  for (int z = z0; z <= z1; ++z)
-    for (int y = y0; y <= y1; ++y)
-      for (int x = x0; x <= x1; ++x) {
-        const CellOwners o = cell_owners(D, epoch, x, y, z, g);
-        if (!(o.act || o.stp)) continue;
-        const CellRanges r = cell_ranges(D, o);
-        if (scan_range(D.P, r.ast, r.aen, p, g, rc2, tests) ||
-            scan_range(D.PS, r.sst, r.sen, p, g, rc2, tests) || walk_recent(D, r.hd, p, g, tests))
-          return true;
-      }
-  return false;
+  x = s.x0 + k % 3;
+  y = s.y0 + (k / 3) % 3;
+  z = s.z0 + k / 9;
+  return x <= s.x1 && y <= s.y1 && z <= s.z1;
 }
 
-// Containment (Sec. 2.4): one wave per dirty brick of the block's chunk of
-// the occupied list, one lane per particle.  Particles of clean bricks cannot
-// meet another grain and are not visited.  Hits go to the block's region of
-// the stop list.
+// Foreign-owner bits of the stencil cells (bit k: cell k holds active,
+// resp. stopped particles of another grain).  Owner words are loaded one
+// z-layer of the stencil at a time, all cells of a layer together.
+template <bool S8>
+__device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, const Stencil& st,
+                                               uint32_t g, uint32_t& act, uint32_t& stp) {
+  constexpr int NL = S8 ? 2 : 3, PL = S8 ? 4 : 9;
+  act = 0u;
+  stp = 0u;
+  for (int l = 0; l < NL; ++l) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int k = l * PL + u;
+      int x, y, z;
+      if (!stencil_cell<S8>(st, k, x, y, z)) continue;
+      const CellOwners o = cell_owners(D, epoch, x, y, z, g);
+      act |= (uint32_t)o.act << k;
+      stp |= (uint32_t)o.stp << k;
+    }
+  }
+}
+
+// Writes the entries of the cells with bits in act / stp to e[0 ..).
+template <bool S8>
+__device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st, uint32_t act,
+                                                uint32_t stp, uint32_t lane, uint3* e) {
+  uint32_t n = 0;
+  auto cell = [&](int k) {
+    if (!(((act | stp) >> k) & 1u)) return;
+    int x, y, z;
+    (void)stencil_cell<S8>(st, k, x, y, z);
+    CellOwners o;
+    o.b = brick_index(D, x, y, z);
+    o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
+    o.act = (act >> k) & 1u;
+    o.stp = (stp >> k) & 1u;
+    const CellRanges r = cell_ranges(D, o);
+    if (o.act) e[n++] = make_uint3(r.ast, r.aen - r.ast, (CE_ACTIVE << 6) | lane);
+    if (o.stp) {
+      e[n++] = make_uint3(r.sst, r.sen - r.sst, (CE_STOPPED << 6) | lane);
+      e[n++] = make_uint3(r.hd, 0u, (CE_RECENT << 6) | lane);
+    }
+  };
+  if constexpr (S8) {
+#pragma unroll 4
+    for (int k = 0; k < 8; ++k) cell(k);
+  } else {
+    for (int k = 0; k < 27; ++k) cell(k);
+  }
+}
+
+struct ContainShared {
+  uint32_t n, tests;
+  float4 pos[TPB];
+  uint32_t hit[TPB];
+  uint3 ent[TPB / 64][CE_MAX];
+};
+
+// Containment (Sec. 2.4) of the particles listed in dpart (those of the
+// cells of dirty bricks that can reach another grain), 64 per wave: owner
+// words of the stencil cells per particle, then the wave's candidate sources
+// shared out among its lanes, in rounds of at most CE_MAX entries (a lane's
+// sources stay in one round).  Hits go to the block's region of the stop
+// list.
+template <bool S8>
+__device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint32_t epoch,
+                                             ContainShared& S) {
+  if (threadIdx.x == 0) {
+    S.n = 0;
+    S.tests = 0;
+  }
+  __syncthreads();
+  const uint32_t lb = logical_block(V);
+  const uint32_t nd = D.cnt->n_dpart;
+  const Chunk ch = chunk_of(V, nd, TPB);
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t w = threadIdx.x >> 6;
+  uint3* ent = S.ent[w];
+  const float rc2 = D.rc2;
+  uint32_t tests = 0;
+  for (uint32_t k0 = ch.begin; k0 < ch.end; k0 += TPB) {
+    const uint32_t k = k0 + threadIdx.x;
+    uint32_t i = 0, act = 0u, stp = 0u;
+    Stencil st = {0, 0, 0, 0, 0, 0};
+    if (k < ch.end) {
+      i = D.dpart[k];
+      const float4 q = D.P[i];
+      S.pos[threadIdx.x] = q;
+      const P3 p = p3_of(q);
+      stencil_axis(D, p.x, 0, st.x0, st.x1);
+      stencil_axis(D, p.y, 1, st.y0, st.y1);
+      stencil_axis(D, p.z, 2, st.z0, st.z1);
+      stencil_owners<S8>(D, epoch, st, grain_of(q), act, stp);
+    }
+    S.hit[threadIdx.x] = 0u;
+    // Rounds: the lanes whose sources fit after those of the lanes before
+    // them (at most 3 per stencil cell, so every round takes one lane at
+    // least).  The loop bounds are the same for the block's four waves.
+    uint32_t ne = (uint32_t)__popc(act) + 2u * (uint32_t)__popc(stp);
+    for (;;) {
+      uint32_t tot;
+      const uint32_t e0 = wave_excl_scan(ne, tot);
+      const bool take = ne > 0u && e0 + ne <= (uint32_t)CE_MAX;
+      uint32_t used;
+      (void)wave_excl_scan(take ? ne : 0u, used);
+      if (take) {
+        stencil_entries<S8>(D, st, act, stp, lane, ent + e0);
+        ne = 0u;
+      }
+      __syncthreads();
+      for (uint32_t t = lane; t < used; t += 64u) {
+        const uint3 en = ent[t];
+        const uint32_t L = w * 64u + (en.z & 63u);
+        if (S.hit[L]) continue;
+        const float4 pq = S.pos[L];
+        const uint32_t kind = en.z >> 6;
+        bool h;
+        if (kind == CE_RECENT)
+          h = walk_recent(D, en.x, p3_of(pq), grain_of(pq), tests);
+        else
+          h = scan_range(kind == CE_ACTIVE ? D.P : D.PS, en.x, en.x + en.y, p3_of(pq),
+                         grain_of(pq), rc2, tests);
+        if (h) S.hit[L] = 1u;
+      }
+      __syncthreads();
+      if (__syncthreads_or(ne > 0u) == 0) break;
+    }
+    const bool hit = k < ch.end && S.hit[threadIdx.x] != 0u;
+    const unsigned long long m = __ballot(hit);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      uint32_t wb = 0;
+      if ((int)lane == leader) wb = atomicAdd(&S.n, (uint32_t)__popcll(m));
+      wb = __shfl(wb, leader);
+      if (hit) D.newstop[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
+  }
+  // Pair tests: one shared-memory add per wave, one global add per block.
+  uint32_t wtests;
+  (void)wave_excl_scan(tests, wtests);
+  if (lane == 0u && wtests) atomicAdd(&S.tests, wtests);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    D.newstop_cnt[lb] = S.n;
+    if (S.tests) atomicAdd(&D.cnt->pair_tests, (unsigned long long)S.tests);
+    if (lb == 0) atomicAdd(&D.cnt->dirty_tests, (unsigned long long)nd);
+  }
+}
+
 template <class Bind>
 __global__ __launch_bounds__(TPB, 6) void k_contain(Bind Bd) {
   Dev D;
@@ -1482,38 +1611,9 @@ __global__ __launch_bounds__(TPB, 6) void k_contain(Bind Bd) {
   Bd.bind(D, V);
   const uint32_t epoch = step_epoch(D);
   if (dead(D)) return;
-  __shared__ uint32_t s_n;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  const uint32_t lb = logical_block(V);
-  const uint32_t nd = D.cnt->n_dpart;
-  const Chunk ch = chunk_of(V, nd, TPB);
-  const int lane = lane_id();
-  uint32_t tests = 0;
-  for (uint32_t k0 = ch.begin; k0 < ch.end; k0 += TPB) {
-    const uint32_t k = k0 + threadIdx.x;
-    uint32_t i = 0;
-    bool hit = false;
-    if (k < ch.end) {
-      i = D.dpart[k];
-      const float4 q = D.P[i];
-      hit = contact(D, epoch, p3_of(q), grain_of(q), tests);
-    }
-    const unsigned long long m = __ballot(hit);
-    if (m) {
-      const int leader = __ffsll((long long)m) - 1;
-      uint32_t wb = 0;
-      if (lane == leader) wb = atomicAdd(&s_n, (uint32_t)__popcll(m));
-      wb = __shfl(wb, leader);
-      if (hit) D.newstop[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
-    }
-  }
-  if (tests) atomicAdd(&D.cnt->pair_tests, (unsigned long long)tests);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    D.newstop_cnt[lb] = s_n;
-    if (lb == 0) atomicAdd(&D.cnt->dirty_tests, (unsigned long long)nd);
-  }
+  __shared__ ContainShared S;
+  if (D.stencil8) contain_body<true>(D, V, epoch, S);
+  else contain_body<false>(D, V, epoch, S);
 }
 
 template <class Bind>
