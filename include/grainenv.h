@@ -135,9 +135,13 @@ typedef struct ge_step_stats {
   double max_step;    /* largest v dt of the call [m] */
   double t;           /* time after the call [s] */
   int64_t step;       /* steps taken since creation or the last state load */
-  int64_t pair_tests; /* candidate particles examined by the containment test (up to the
-                         first hit: depends on the order within a cell, not reproducible) */
-  int64_t dirty_tests;/* active particles whose brick neighbourhood holds another grain */
+  int64_t pair_tests; /* candidate particles examined by the containment test (a particle's
+                         candidates are examined until it is found to meet another grain:
+                         the count depends on timing and on the order within a cell, and
+                         is not reproducible) */
+  int64_t dirty_tests;/* active particles given the containment test: those of the cells
+                         of dirty bricks whose 3x3x3 cell neighbourhood reaches a brick
+                         that holds another grain */
 } ge_step_stats;
 
 /* Query kinds of ge_query_envelope. */
