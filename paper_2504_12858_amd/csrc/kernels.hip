@@ -1212,8 +1212,11 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     const bool rz = oz == 0 || (oz < 0 ? lz == 0 : lz == 3);
     if (rx && ry && rz) reach |= 1u << t;
   }
+  // The next brick of the wave is fetched during this one.
+  uint32_t b1 = ch.begin + (threadIdx.x >> 6) < ch.end ? D.occ[ch.begin + (threadIdx.x >> 6)] : 0u;
   for (uint32_t k = ch.begin + (threadIdx.x >> 6); k < ch.end; k += TPB / 64) {
-    const uint32_t b = D.occ[k];
+    const uint32_t b = b1;
+    if (k + TPB / 64 < ch.end) b1 = D.occ[k + TPB / 64];
     const uint4 own = D.binfo[b];
     const uint32_t g = own.z;
     bool foreign = false;
@@ -1535,13 +1538,27 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
   uint3* ent = S.ent[w];
   const float rc2 = D.rc2;
   uint32_t tests = 0;
+  // The particle of the next group is fetched during this one (its list
+  // entry two groups ahead), off the critical path.
+  uint32_t i1 = 0, i2 = 0;
+  float4 q1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (ch.begin + threadIdx.x < ch.end) {
+    i1 = D.dpart[ch.begin + threadIdx.x];
+    q1 = D.P[i1];
+  }
+  if (ch.begin + TPB + threadIdx.x < ch.end) i2 = D.dpart[ch.begin + TPB + threadIdx.x];
   for (uint32_t k0 = ch.begin; k0 < ch.end; k0 += TPB) {
     const uint32_t k = k0 + threadIdx.x;
-    uint32_t i = 0, act = 0u, stp = 0u;
+    const uint32_t i = i1;
+    const float4 q = q1;
+    if (k + TPB < ch.end) {
+      i1 = i2;
+      q1 = D.P[i1];
+    }
+    if (k + 2u * TPB < ch.end) i2 = D.dpart[k + 2u * TPB];
+    uint32_t act = 0u, stp = 0u;
     Stencil st = {0, 0, 0, 0, 0, 0};
     if (k < ch.end) {
-      i = D.dpart[k];
-      const float4 q = D.P[i];
       S.pos[threadIdx.x] = q;
       const P3 p = p3_of(q);
       stencil_axis(D, p.x, 0, st.x0, st.x1);
