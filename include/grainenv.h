@@ -57,6 +57,9 @@ typedef int32_t ge_status;
 #define GE_FIELD_GRID 2      /* trilinear interpolation of node values */
 #define GE_FIELD_ROSENTHAL 3 /* LINEAR background minus a moving point source,
                                 resampled onto the node grid every step */
+#define GE_FIELD_SOLUTE 4    /* temperature and solute node values: the local
+                                undercooling is taken with respect to the local
+                                liquidus, dT = liq_T + liq_m w - T (Sec. 3.4) */
 
 /* Particle states in exported records. */
 #define GE_ACTIVE 0
@@ -118,6 +121,16 @@ typedef struct ge_field {
      direction; the source rasters back and forth along x between x_start
      and x_end at speed U, at (y, z) = (ys, zs); dT is floored at dT_min. */
   double q, U, alpha, x_start, x_end, ys, zs, r_min, dT_min;
+  /* SOLUTE: temperature T [K] and solute concentration w of every node of the
+     grid (n, origin, spacing), FP64, index (k*ny + j)*nx + i, host or device
+     memory (data_on_device); liquidus T_L(w) = liq_T + liq_m w [K, K per unit
+     of w].  The node undercooling T_L(w) - T is formed in FP64 and stored in
+     FP32; the liquidus being linear in w, its trilinear interpolant is the
+     liquidus of the interpolated concentration minus the interpolated
+     temperature. */
+  const double* T;
+  const double* w;
+  double liq_T, liq_m;
 } ge_field;
 
 /* Counters of a ge_step call (sums over its steps) and the state after it. */
@@ -238,7 +251,13 @@ ge_status ge_init_grains(ge_ctx* ctx, int32_t n, const double* centre /*[n][3]*/
                          uint32_t* first_id);
 
 /* Sets the thermal field used from the next step on (undercooling values).
-   ENUMERIC on non-finite scalars; EINVAL on a grid larger than field_n. */
+   ENUMERIC on non-finite scalars; EINVAL on a grid larger than field_n or
+   missing node arrays.  Host node arrays are copied before return; device
+   node arrays are read in stream order (the caller keeps them until the
+   stream has passed this call).  A new field of the same kind and geometry
+   (new node values, or new scalars of the same kind) keeps the recorded step
+   sequence of ge_step valid, so a coupled solver can hand over a field every
+   step at the cost of one copy. */
 ge_status ge_set_thermal_field(ge_ctx* ctx, const ge_field* f);
 
 /* Registers n dormant nucleation sites (Sec. 2.1.1): position, nucleation

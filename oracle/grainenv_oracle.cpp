@@ -64,7 +64,7 @@ namespace {
 enum : int32_t { P_ACTIVE = 0, P_STOPPED = 1, P_RETIRED = 2 };
 enum : int32_t { S_DORMANT = 0, S_FIRED = 1 };
 enum : uint8_t { C_CLAIMED = 1, C_REACHED = 2 };
-enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3 };
+enum : int32_t { F_UNIFORM = 0, F_LINEAR = 1, F_GRID = 2, F_ROSENTHAL = 3, F_SOLUTE = 4 };
 enum : int32_t { E_OK = 0, E_INVAL = -1, E_CAPACITY = -2, E_NUMERIC = -3, E_CFL = -4 };
 
 struct Params {
@@ -102,6 +102,11 @@ struct Field {
   int32_t n[3] = {0, 0, 0};
   double o[3] = {0, 0, 0}, sp[3] = {0, 0, 0};
   std::vector<double> data;  // node values, index (k*ny + j)*nx + i
+  // SOLUTE: node temperature and solute concentration, liquidus
+  // T_L(w) = liq_T + liq_m w (Sec. 3.4: undercooling taken with respect to
+  // the local solute concentration)
+  std::vector<double> Tn, wn;
+  double liq_T = 0, liq_m = 0;
   double q = 0, U = 0, alpha = 0, x_start = 0, x_end = 0, ys = 0, zs = 0, r_min = 0,
          dT_min = -1000;
   double sampled_t = NAN;  // time at which a Rosenthal grid was last sampled
@@ -208,10 +213,12 @@ void sample_rosenthal(Field& f, double t) {
   f.sampled_t = t;
 }
 
-// Trilinear interpolation on a node-centred grid; cell index clamped to
-// [0, n-2], fraction clamped to [0, 1].  Optionally returns the gradient of
-// the interpolant (zero along an axis whose fraction was clamped).
-double trilinear(const Field& f, const double x[3], double grad[3]) {
+// Trilinear interpolation of node values `data` on the field's node-centred
+// grid; cell index clamped to [0, n-2], fraction clamped to [0, 1].
+// Optionally returns the gradient of the interpolant (zero along an axis
+// whose fraction was clamped).
+double trilinear(const Field& f, const std::vector<double>& data, const double x[3],
+                 double grad[3]) {
   int i0[3];
   double fr[3];
   bool clamped[3];
@@ -230,7 +237,7 @@ double trilinear(const Field& f, const double x[3], double grad[3]) {
   }
   const int nx = f.n[0], ny = f.n[1];
   auto at = [&](int di, int dj, int dk) {
-    return f.data[((size_t)(i0[2] + dk) * ny + (i0[1] + dj)) * nx + (i0[0] + di)];
+    return data[((size_t)(i0[2] + dk) * ny + (i0[1] + dj)) * nx + (i0[0] + di)];
   };
   double v = 0;
   double g[3] = {0, 0, 0};
@@ -263,7 +270,17 @@ double field_value(const Field& f, const double x[3], double t, double grad[3] =
       return f.dT0 + f.grad[0] * x[0] + f.grad[1] * x[1] + f.grad[2] * x[2] + f.rate * t;
     case F_GRID:
     case F_ROSENTHAL:
-      return trilinear(f, x, grad);
+      return trilinear(f, f.data, x, grad);
+    case F_SOLUTE: {
+      // Liquidus of the interpolated concentration minus the interpolated
+      // temperature.
+      double gT[3], gw[3];
+      const double T = trilinear(f, f.Tn, x, grad ? gT : nullptr);
+      const double w = trilinear(f, f.wn, x, grad ? gw : nullptr);
+      if (grad)
+        for (int a = 0; a < 3; ++a) grad[a] = f.liq_m * gw[a] - gT[a];
+      return (f.liq_T + f.liq_m * w) - T;
+    }
   }
   return NAN;
 }
@@ -608,6 +625,9 @@ struct orc_field {
   double origin[3], spacing[3];
   const float* data;  // GRID node values (host, FP32), (k*ny + j)*nx + i
   double q, U, alpha, x_start, x_end, ys, zs, r_min, dT_min;
+  const double* T;    // SOLUTE node temperatures and concentrations (host, FP64)
+  const double* w;
+  double liq_T, liq_m;
 };
 
 void* orc_create(const orc_params* pp) {
@@ -654,17 +674,32 @@ int32_t orc_set_field(void* h, const orc_field* fs) {
   f.q = fs->q; f.U = fs->U; f.alpha = fs->alpha;
   f.x_start = fs->x_start; f.x_end = fs->x_end;
   f.ys = fs->ys; f.zs = fs->zs; f.r_min = fs->r_min; f.dT_min = fs->dT_min;
-  if (f.kind == F_GRID || f.kind == F_ROSENTHAL) {
+  if (f.kind == F_GRID || f.kind == F_ROSENTHAL || f.kind == F_SOLUTE) {
     for (int a = 0; a < 3; ++a)
       if (f.n[a] < 2 || !(f.sp[a] > 0)) return E_INVAL;
   }
+  const size_t m = (size_t)f.n[0] * f.n[1] * f.n[2];
   if (f.kind == F_GRID) {
-    size_t m = (size_t)f.n[0] * f.n[1] * f.n[2];
     f.data.resize(m);
     for (size_t i = 0; i < m; ++i) f.data[i] = (double)fs->data[i];
   }
+  if (f.kind == F_SOLUTE) {
+    if (!fs->T || !fs->w) return E_INVAL;
+    f.Tn.assign(fs->T, fs->T + m);
+    f.wn.assign(fs->w, fs->w + m);
+    f.liq_T = fs->liq_T;
+    f.liq_m = fs->liq_m;
+  }
   o.f = std::move(f);
   return E_OK;
+}
+
+// Undercooling field (without theta) and its gradient at n points, time t
+// (a ROSENTHAL field is sampled at t first).
+void orc_field_value(void* h, int64_t n, const double* x, double t, double* out, double* grad) {
+  Oracle& o = *(Oracle*)h;
+  if (o.f.kind == F_ROSENTHAL) sample_rosenthal(o.f, t);
+  for (int64_t k = 0; k < n; ++k) out[k] = field_value(o.f, x + 3 * k, t, grad ? grad + 3 * k : nullptr);
 }
 
 // Appends grains.  shell_r[i] = 0: a 6-particle nucleus at the centre with

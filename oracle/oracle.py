@@ -26,7 +26,8 @@ class _Field(C.Structure):
                 ("data", C.POINTER(C.c_float)), ("q", C.c_double), ("U", C.c_double),
                 ("alpha", C.c_double), ("x_start", C.c_double), ("x_end", C.c_double),
                 ("ys", C.c_double), ("zs", C.c_double), ("r_min", C.c_double),
-                ("dT_min", C.c_double)]
+                ("dT_min", C.c_double), ("T", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("liq_T", C.c_double), ("liq_m", C.c_double)]
 
 
 _lib = None
@@ -56,6 +57,8 @@ def _load():
     lib.orc_set_branching.argtypes = [vp, C.c_int32]
     lib.orc_set_field.argtypes = [vp, C.POINTER(_Field)]
     lib.orc_set_field.restype = C.c_int32
+    lib.orc_field_value.argtypes = [vp, C.c_int64, P(np.float64), C.c_double, P(np.float64),
+                                    P(np.float64)]
     lib.orc_init_grains.argtypes = [vp, C.c_int32, P(np.float64), P(np.float64), P(np.int32)]
     lib.orc_init_grains.restype = C.c_int32
     lib.orc_nucleate.argtypes = [vp, C.c_int32, P(np.float64), P(np.float64), P(np.float64)]
@@ -160,9 +163,23 @@ class Oracle:
             fs.data = arr.ctypes.data_as(C.POINTER(C.c_float))
         for k in ("q", "U", "alpha", "x_start", "x_end", "ys", "zs", "r_min", "dT_min"):
             setattr(fs, k, getattr(f, k))
+        if getattr(f, "T", None) is not None:
+            for k in ("T", "w"):
+                arr = np.ascontiguousarray(getattr(f, k), dtype=np.float64)
+                self._keep.append(arr)
+                setattr(fs, k, arr.ctypes.data_as(C.POINTER(C.c_double)))
+            fs.liq_T, fs.liq_m = f.liq_T, f.liq_m
         rc = self.lib.orc_set_field(self.h, C.byref(fs))
         if rc != 0:
             raise ValueError(f"orc_set_field failed: {rc}")
+
+    def field_value(self, x, t=0.0):
+        """Undercooling field (without theta) and its gradient at points x [n, 3]."""
+        x = _f64(x).reshape(-1, 3)
+        out = np.zeros(len(x))
+        grad = np.zeros((len(x), 3))
+        self.lib.orc_field_value(self.h, len(x), x, float(t), out, grad)
+        return out, grad
 
     def set_theta(self, theta):
         self.lib.orc_set_theta(self.h, float(theta))

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgrainenv.so")
 GE_OK, GE_EINVAL, GE_ECAPACITY, GE_ENUMERIC, GE_ECFL, GE_EDEVICE, GE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "ENUMERIC", -4: "ECFL",
                 -5: "EDEVICE", -6: "ESTATE"}
-FIELD_UNIFORM, FIELD_LINEAR, FIELD_GRID, FIELD_ROSENTHAL = 0, 1, 2, 3
+FIELD_UNIFORM, FIELD_LINEAR, FIELD_GRID, FIELD_ROSENTHAL, FIELD_SOLUTE = 0, 1, 2, 3, 4
 (QUERY_COUNTS, QUERY_PARTICLES, QUERY_GRAIN_MAP, QUERY_CLAIMS, QUERY_SITES, QUERY_GRAINS,
  QUERY_DIGEST) = range(7)
 ACTIVE, STOPPED, RETIRED = 0, 1, 2
@@ -55,7 +55,8 @@ class ge_field(C.Structure):
                 ("data", C.c_void_p), ("data_on_device", C.c_int32), ("q", C.c_double),
                 ("U", C.c_double), ("alpha", C.c_double), ("x_start", C.c_double),
                 ("x_end", C.c_double), ("ys", C.c_double), ("zs", C.c_double),
-                ("r_min", C.c_double), ("dT_min", C.c_double)]
+                ("r_min", C.c_double), ("dT_min", C.c_double), ("T", C.c_void_p),
+                ("w", C.c_void_p), ("liq_T", C.c_double), ("liq_m", C.c_double)]
 
 
 class ge_step_stats(C.Structure):
@@ -180,7 +181,8 @@ def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1
 
 
 def params_from_workload(w, **caps) -> ge_params:
-    fn = tuple(w.field.n) if w.field.kind in (FIELD_GRID, FIELD_ROSENTHAL) else (0, 0, 0)
+    fn = (tuple(w.field.n) if w.field.kind in (FIELD_GRID, FIELD_ROSENTHAL, FIELD_SOLUTE)
+          else (0, 0, 0))
     caps.setdefault("field_n", fn)
     caps.setdefault("cap_sites", max(len(w.site_dTn), 1))
     return make_params(w.lo, w.hi, w.lambda0, w.h, w.rc, w.a, w.b, w.theta, w.branching,
@@ -291,16 +293,38 @@ class Context:
         fs.n[:] = list(f.n)
         fs.origin[:] = list(f.origin)
         fs.spacing[:] = list(f.spacing)
-        keep = None
+        keep = []
+
+        n_nodes = int(np.prod(list(f.n)))
+
+        def nodes(a, dtype):
+            """Pointer to node values (numpy: host; torch: host or device);
+            a missing array passes NULL, which the library rejects."""
+            if a is None:
+                return None, 0
+            if hasattr(a, "data_ptr"):
+                t = a.contiguous()
+                if t.element_size() != np.dtype(dtype).itemsize or not t.is_floating_point():
+                    raise ValueError(f"node values must be {np.dtype(dtype).name}")
+                if t.numel() != n_nodes:
+                    raise ValueError(f"{t.numel()} node values for a grid of {n_nodes} nodes")
+                keep.append(t)
+                return t.data_ptr(), 1 if t.is_cuda else 0
+            arr = np.ascontiguousarray(a, dtype)
+            if arr.size != n_nodes:
+                raise ValueError(f"{arr.size} node values for a grid of {n_nodes} nodes")
+            keep.append(arr)
+            return arr.ctypes.data, 0
+
         if f.kind == FIELD_GRID:
-            if hasattr(f.data, "data_ptr"):
-                keep = f.data.contiguous()
-                fs.data = keep.data_ptr()
-                fs.data_on_device = 1 if keep.is_cuda else 0
-            else:
-                keep = np.ascontiguousarray(f.data, np.float32)
-                fs.data = keep.ctypes.data
-                fs.data_on_device = 0
+            fs.data, fs.data_on_device = nodes(f.data, np.float32)
+        elif f.kind == FIELD_SOLUTE:
+            fs.T, on_t = nodes(f.T, np.float64)
+            fs.w, on_w = nodes(f.w, np.float64)
+            if on_t != on_w:
+                raise ValueError("SOLUTE: T and w must both be host or both device arrays")
+            fs.data_on_device = on_t
+            fs.liq_T, fs.liq_m = float(f.liq_T), float(f.liq_m)
         for k in ("q", "U", "alpha", "x_start", "x_end", "ys", "zs", "r_min", "dT_min"):
             setattr(fs, k, float(getattr(f, k)))
         self._check(self.lib.ge_set_thermal_field(self.ctx, C.byref(fs)), "ge_set_thermal_field")

@@ -239,6 +239,9 @@ void launch_finish(const Dev& d, double dt, hipStream_t s);
 void launch_reset_stats(const Dev& d, hipStream_t s);
 void launch_stopped_rebuild(const Dev& d, hipStream_t s);  // S -> S2 (caller swaps)
 void launch_resample(const Dev& d, hipStream_t s);
+// Node undercooling liq_T + liq_m w - T of a SOLUTE field (FP64 in, FP32 out).
+void launch_solute_nodes(const double* T, const double* w, double liq_T, double liq_m,
+                         uint64_t n, float* out, hipStream_t s);
 void launch_init_workspace(const Dev& d, hipStream_t s);
 void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s);
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);

@@ -2186,6 +2186,18 @@ __global__ __launch_bounds__(TPB) void k_grain_map(Bind Bd, int32_t n0, int32_t 
   }
 }
 
+// Node undercooling of a temperature-and-solute field (Sec. 3.4: the local
+// undercooling is taken with respect to the liquidus of the local solute
+// concentration), formed in FP64 and stored in FP32.
+__global__ __launch_bounds__(TPB) void k_solute_nodes(const double* __restrict__ T,
+                                                      const double* __restrict__ w, double liq_T,
+                                                      double liq_m, uint64_t n,
+                                                      float* __restrict__ out) {
+  for (uint64_t k = (uint64_t)blockIdx.x * TPB + threadIdx.x; k < n;
+       k += (uint64_t)gridDim.x * TPB)
+    out[k] = (float)((liq_T + liq_m * w[k]) - T[k]);
+}
+
 // ============================================================== adjoint ===
 // Gradients of the final positions of the tracked particles with respect to
 // the kinetic coefficients a0, a1 and the undercooling offset theta, with
@@ -2502,6 +2514,10 @@ void launch_stopped_rebuild(const Dev& d, hipStream_t s) {
 void launch_resample(const Dev& d, hipStream_t s) {
   const uint64_t total = (uint64_t)d.fn[0] * d.fn[1] * d.fn[2];
   k_resample<<<grid_for(total, 8192), TPB, 0, s>>>(Plain{d});
+}
+void launch_solute_nodes(const double* T, const double* w, double liq_T, double liq_m,
+                         uint64_t n, float* out, hipStream_t s) {
+  k_solute_nodes<<<grid_for(n, 8192), TPB, 0, s>>>(T, w, liq_T, liq_m, n, out);
 }
 void launch_init_workspace(const Dev& d, hipStream_t s) {
   k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});

@@ -559,6 +559,7 @@ ge_status ge_set_thermal_field(ge_ctx* c, const ge_field* f) {
         return fail(c, GE_ENUMERIC, "non-finite field");
       break;
     case GE_FIELD_GRID:
+    case GE_FIELD_SOLUTE:
     case GE_FIELD_ROSENTHAL: {
       uint64_t nodes = 1;
       for (int a = 0; a < 3; ++a) {
@@ -572,7 +573,24 @@ ge_status ge_set_thermal_field(ge_ctx* c, const ge_field* f) {
         HIPCHK(c, hipMemcpyAsync(d.fgrid, f->data, nodes * 4,
                                  f->data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                  c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (!f->data_on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+      } else if (f->kind == GE_FIELD_SOLUTE) {
+        if (!f->T || !f->w) return fail(c, GE_EINVAL, "SOLUTE needs T and w");
+        if (!fin(f->liq_T) || !fin(f->liq_m)) return fail(c, GE_ENUMERIC, "non-finite liquidus");
+        if (f->data_on_device) {
+          ge::launch_solute_nodes(f->T, f->w, f->liq_T, f->liq_m, nodes, d.fgrid, c->stream);
+          HIPCHK(c, hipGetLastError());
+        } else {
+          // Node undercooling in FP64, stored in FP32.
+          std::vector<float> u(nodes);
+          for (uint64_t k = 0; k < nodes; ++k) {
+            const double v = (f->liq_T + f->liq_m * f->w[k]) - f->T[k];
+            if (!fin(v)) return fail(c, GE_ENUMERIC, "non-finite node value");
+            u[k] = (float)v;
+          }
+          HIPCHK(c, hipMemcpyAsync(d.fgrid, u.data(), nodes * 4, hipMemcpyHostToDevice, c->stream));
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
       } else {
         const double v[] = {f->dT0, f->rate, f->q, f->U, f->alpha, f->x_start, f->x_end, f->ys,
                             f->zs, f->r_min, f->dT_min, f->grad[0], f->grad[1], f->grad[2]};
@@ -587,7 +605,10 @@ ge_status ge_set_thermal_field(ge_ctx* c, const ge_field* f) {
   }
   c->field = *f;
   c->field.data = nullptr;
-  d.fkind = f->kind;
+  c->field.T = c->field.w = nullptr;
+  const Dev before = d;
+  // The device interpolates a SOLUTE field's node undercooling like a GRID.
+  d.fkind = f->kind == GE_FIELD_SOLUTE ? GE_FIELD_GRID : f->kind;
   d.fdT = (float)f->dT;
   for (int a = 0; a < 3; ++a) {
     d.fgrad[a] = (float)f->grad[a];
@@ -614,6 +635,9 @@ ge_status ge_set_thermal_field(ge_ctx* c, const ge_field* f) {
     r.o[a] = f->origin[a];
     r.sp[a] = f->spacing[a];
   }
+  // Launch arguments unchanged (same kind and geometry, new node values):
+  // the recorded step sequence stays valid.
+  if (std::memcmp(&before, &d, sizeof(Dev)) == 0) return GE_OK;
   return sync_dev(c);
 }
 

@@ -42,6 +42,7 @@ FIELD_UNIFORM = 0
 FIELD_LINEAR = 1
 FIELD_GRID = 2
 FIELD_ROSENTHAL = 3
+FIELD_SOLUTE = 4
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -135,6 +136,12 @@ class Field:
     zs: float = 0.0
     r_min: float = 0.0                   # distance floor [m]
     dT_min: float = -1000.0              # undercooling floor [K]
+    # SOLUTE: node temperature [K] and solute concentration, float64, shape
+    # (nz, ny, nx); liquidus T_L(w) = liq_T + liq_m w
+    T: Optional[np.ndarray] = None
+    w: Optional[np.ndarray] = None
+    liq_T: float = 0.0
+    liq_m: float = 0.0
 
 
 @dataclass
@@ -166,7 +173,7 @@ class Workload:
         return max(h - l for l, h in zip(self.lo, self.hi))
 
 
-# Kinetics of the BASELINE workloads: v = 1e-5 dT^2 + 1e-6 dT^3 (Eq. 2 with
+# Kinetics of the benchmark workloads: v = 1e-5 dT^2 + 1e-6 dT^3 (Eq. 2 with
 # exponents 2 and 3).
 KIN_A = (1e-5, 1e-6)
 KIN_B = (2.0, 3.0)
@@ -213,6 +220,59 @@ def directional(seed: int = 2, n_grains: int = 64, size=(2e-3, 2e-3, 4e-3),
         grain_centre=centre, grain_quat=quat,
         grain_shell=np.zeros(n_grains, np.int32),
         notes=f"seed={seed}")
+
+
+# Binary alloy of the solute-coupled workloads (Al-Cu-like): melting point of
+# the pure solvent [K] and liquidus slope [K per wt%].
+LIQ_T, LIQ_M = 933.5, -3.4
+
+
+@dataclass
+class SoluteSpec:
+    """Temperature and solute node values of a solute-coupled field: an
+    imposed temperature T = T_L(w0) - dT0 + G z - rate t and a static lateral
+    segregation pattern w = w0 + amp sin(2 pi x / period) sin(2 pi y / period)
+    (the local undercooling is taken with respect to the local liquidus,
+    Sec. 3.4)."""
+    n: tuple
+    origin: tuple
+    spacing: tuple
+    dT0: float
+    G: float
+    rate: float
+    w0: float
+    amp: float
+    period: float
+
+    def field(self, t: float) -> Field:
+        nx, ny, nz = self.n
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        x = self.origin[0] + i * self.spacing[0]
+        y = self.origin[1] + j * self.spacing[1]
+        z = self.origin[2] + k * self.spacing[2]
+        T = (LIQ_T + LIQ_M * self.w0) - self.dT0 + self.G * z - self.rate * t
+        w = self.w0 + self.amp * np.sin(2 * np.pi * x / self.period) * np.sin(2 * np.pi * y / self.period)
+        return Field(FIELD_SOLUTE, n=tuple(self.n), origin=tuple(self.origin),
+                     spacing=tuple(self.spacing), T=np.ascontiguousarray(T, np.float64),
+                     w=np.ascontiguousarray(w, np.float64), liq_T=LIQ_T, liq_m=LIQ_M)
+
+
+def directional_solute(seed: int = 2, n_grains: int = 8, size=(0.3e-3, 0.3e-3, 0.6e-3),
+                       lambda0: float = 5e-6, dT0: float = 10.0, G: float = 1e4,
+                       rate: float = 10.0, w0: float = 3.0, amp: float = 0.3,
+                       period: float = 1e-4, grid=(16, 16, 32), dt: float = 5e-4,
+                       n_steps: int = 240, h: Optional[float] = None):
+    """Directional growth (grains on the bottom face) under a temperature and
+    solute field on a node grid spanning the box; returns the workload (field
+    at t = 0) and the spec that gives the field at any time."""
+    w = directional(seed=seed, n_grains=n_grains, size=size, lambda0=lambda0, dT0=dT0, G=G,
+                    rate=rate, dt=dt, n_steps=n_steps, h=h)
+    spacing = tuple(s / (m - 1) for s, m in zip(size, grid))
+    spec = SoluteSpec(n=tuple(grid), origin=(0.0, 0.0, 0.0), spacing=spacing, dT0=dT0, G=G,
+                      rate=rate, w0=w0, amp=amp, period=period)
+    w.field = spec.field(0.0)
+    w.name = "directional_solute"
+    return w, spec
 
 
 def cet(seed: int = 3, size=(4e-3, 2e-3, 1e-3), lambda0: float = 2e-6,
