@@ -28,6 +28,7 @@ import ctypes
 import glob
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -310,6 +311,79 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
             "bitwise_equal": bool(equal and upd_a == upd_b)}
 
 
+SOLUTE_STEPS = 20
+
+
+def solute_leg(ctx, w, steps=SOLUTE_STEPS):
+    """Coupled stepping at the 20M snapshot: a temperature-and-solute field on
+    the 256^3 node grid of the box, handed over from device arrays (FP64)
+    before a step, as a coupled solver would (the undercooling is taken with
+    respect to the liquidus of the local concentration, Sec. 3.4).  A
+    stand-in solver (torch, outside the timed spans) gives the node
+    temperatures T = T_L(w0) - dT_R(x, t), dT_R being the moving-source
+    undercooling of the workload, and a static segregation pattern w around
+    w0, so the undercooling is the workload's plus liq_m (w - w0).  Steps
+    alternate between a hand-over before the step and the field kept; HIP
+    events time the hand-over (node conversion included) and the step."""
+    import torch
+    from paper_2504_12858_amd import workloads as W
+    fd = w.field
+    n = tuple(fd.n)
+    dev = torch.device("cuda")
+    k, j, i = torch.meshgrid(*(torch.arange(m, dtype=torch.float64, device=dev)
+                               for m in (n[2], n[1], n[0])), indexing="ij")
+    X = fd.origin[0] + i * fd.spacing[0]
+    Y = fd.origin[1] + j * fd.spacing[1]
+    Z = fd.origin[2] + k * fd.spacing[2]
+    del i, j, k
+    w0, amp, period = 3.0, 0.3, 1e-4
+    wn = (w0 + amp * torch.sin(2 * math.pi * X / period) *
+          torch.sin(2 * math.pi * Y / period)).contiguous()
+    T_L0 = W.LIQ_T + W.LIQ_M * w0
+
+    def temperature(t):
+        L = fd.x_end - fd.x_start
+        phase = math.fmod(fd.U * t, 2 * L)
+        xs, sg = (fd.x_start + phase, 1.0) if phase < L else (fd.x_start + 2 * L - phase, -1.0)
+        xi = sg * (X - xs)
+        r = torch.sqrt(xi * xi + (Y - fd.ys) ** 2 + (Z - fd.zs) ** 2).clamp_min(fd.r_min)
+        rise = fd.q / (2 * math.pi) / r * torch.exp(-fd.U / (2 * fd.alpha) * (xi + r))
+        dT = (fd.dT0 + fd.rate * t + fd.grad[0] * X + fd.grad[1] * Y + fd.grad[2] * Z - rise)
+        return (T_L0 - dT.clamp_min(fd.dT_min)).contiguous()
+
+    def field(t):
+        return W.Field(W.FIELD_SOLUTE, n=n, origin=tuple(fd.origin), spacing=tuple(fd.spacing),
+                       T=temperature(t), w=wn, liq_T=W.LIQ_T, liq_m=W.LIQ_M)
+
+    ctx.set_thermal_field(field(float(ctx.counts()["t"])))
+    ctx.step(w.dt, 2, stats=False)
+    s = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for it in range(steps):
+        coupled = it % 2 == 0
+        f = field(float(ctx.counts()["t"])) if coupled else None
+        e = ev[it]
+        e[0].record(s)
+        if coupled:
+            ctx.set_thermal_field(f)
+        e[1].record(s)
+        ctx.step(w.dt, 1, stats=False)
+        e[2].record(s)
+    torch.cuda.synchronize()
+    hand = [ev[i][0].elapsed_time(ev[i][1]) for i in range(0, steps, 2)]
+    step_c = [ev[i][1].elapsed_time(ev[i][2]) for i in range(0, steps, 2)]
+    step_p = [ev[i][1].elapsed_time(ev[i][2]) for i in range(1, steps, 2)]
+    st = ctx.counts()
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
+    return {"workload": "cet-moving-source-20M snapshot, temperature-and-solute field "
+                        f"{n[0]}x{n[1]}x{n[2]} nodes (FP64 T and w on the device)",
+            "steps": steps, "n_active": int(st["n_active"]),
+            "handover_ms": round(mean(hand), 4),
+            "step_after_handover_ms": round(mean(step_c), 4),
+            "step_field_kept_ms": round(mean(step_p), 4),
+            "coupled_updates_per_s": st["n_active"] / ((mean(hand) + mean(step_c)) * 1e-3)}
+
+
 def cpu_baseline(ctx, w, budget_s=15.0, max_steps=400):
     """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot."""
     import numpy as np
@@ -359,6 +433,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-solute", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=3, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -449,6 +524,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
+    if not args.no_solute:
+        out["solute"] = solute_leg(ctx, w)
+        log(f"[solute] {out['solute']}")
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
