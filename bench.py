@@ -311,6 +311,54 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
             "bitwise_equal": bool(equal and upd_a == upd_b)}
 
 
+MUSHY_STEPS = 32
+
+
+def mushy_leg(ctx, w, steps=MUSHY_STEPS):
+    """Mushy-zone deposition at the 20M snapshot on the 256^3 node grid of
+    the field: the full count of every reached site when the grid is set,
+    then blocks of `steps` steps (recorded sequences) with the deposition on
+    and off, alternated twice, timed with HIP events; the g^m query."""
+    import numpy as np
+    import torch
+    fd = w.field
+    n = tuple(fd.n)
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    on_ms, off_ms = [], []
+    recount_ms = 0.0
+    for rep in range(2):
+        ctx.set_deposition_grid(None)
+        ctx.prepare_step(w.dt)
+        off_ms.append(timed(lambda: ctx.step(w.dt, steps, stats=False)) / steps)
+        recount_ms = timed(lambda: ctx.set_deposition_grid(n, fd.origin, fd.spacing))
+        ctx.prepare_step(w.dt)
+        on_ms.append(timed(lambda: ctx.step(w.dt, steps, stats=False)) / steps)
+    t = time.perf_counter()
+    gm = ctx.mushy_fraction()
+    query_ms = 1e3 * (time.perf_counter() - t)
+    cnt = ctx.mushy_counts()
+    ctx.set_deposition_grid(None)
+    on, off = sum(on_ms) / len(on_ms), sum(off_ms) / len(off_ms)
+    return {"workload": f"cet-moving-source-20M snapshot, deposition on the {n[0]}x{n[1]}x{n[2]} "
+                        "node grid of the field",
+            "steps_per_block": steps, "recount_ms": round(recount_ms, 3),
+            "step_ms_deposition_on": round(on, 4), "step_ms_deposition_off": round(off, 4),
+            "overhead_ms_per_step": round(on - off, 4),
+            "reached_sites": int(cnt.sum(dtype=np.int64)),
+            "cells_mushy_full": int((gm >= 1.0).sum()), "cells_mushy_partial": int(((gm > 0) & (gm < 1)).sum()),
+            "fraction_query_to_host_ms": round(query_ms, 2)}
+
+
 SOLUTE_STEPS = 20
 
 
@@ -434,6 +482,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-solute", action="store_true")
+    ap.add_argument("--no-mushy", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=3, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -524,6 +573,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
+    if not args.no_mushy:
+        out["mushy"] = mushy_leg(ctx, w)
+        log(f"[mushy] {out['mushy']}")
     if not args.no_solute:
         out["solute"] = solute_leg(ctx, w)
         log(f"[solute] {out['solute']}")

@@ -167,6 +167,10 @@ typedef struct ge_step_stats {
 #define GE_QUERY_DIGEST 6    /* out: uint64 [3]: order-independent digests of the active
                                 particles, the stopped particles and the claims (equal
                                 states give equal digests) */
+#define GE_QUERY_MUSHY_COUNTS 7 /* out: uint32 [n2][n1][n0]: reached lattice sites per cell
+                                   of the deposition grid (EINVAL if none is set) */
+#define GE_QUERY_MUSHY 8     /* out: float [n2][n1][n0]: mushy-zone fraction per cell,
+                                g^m = min(1, count lambda0^3 / cell volume) */
 
 /* Exported particle: position computed on the device, binning cell. */
 typedef struct ge_particle_rec {
@@ -249,6 +253,24 @@ const char* ge_last_error(const ge_ctx* ctx);
 ge_status ge_init_grains(ge_ctx* ctx, int32_t n, const double* centre /*[n][3]*/,
                          const double* quat /*[n][4]*/, const int32_t* shell_r /*[n]*/,
                          uint32_t* first_id);
+
+/* Mushy-zone deposition (Sec. 2.2: the mushy zone is the volume inside the
+   grain envelopes, and its fraction g^m per volume element is what the
+   coupled solver needs from the envelopes, Eqs. (4)-(5)).  The inside of a
+   grain's envelope is taken as the lattice sites it has reached, each
+   standing for its crystal-frame cube of edge lambda0.  A reached site counts
+   in the cell of the deposition grid that holds its centre; cell (i, j, k) is
+   the box of half-width spacing / 2 around node origin + (i, j, k) spacing
+   (index floor((x - origin) / spacing + 1/2) per axis in FP32; sites outside
+   every cell are not counted).  g^m = min(1, count lambda0^3 / cell volume)
+   (GE_QUERY_MUSHY; GE_QUERY_MUSHY_COUNTS gives the counts).
+   ge_set_deposition_grid sets the grid (at most field_n nodes per axis,
+   EINVAL otherwise) and counts every site reached so far; from then on each
+   step adds the sites it reaches (branching, nucleation, new grains), and
+   ge_load_state counts the loaded claims again.  n = NULL or a zero entry
+   turns the deposition off. */
+ge_status ge_set_deposition_grid(ge_ctx* ctx, const int32_t* n /*[3]*/, const double* origin /*[3]*/,
+                                 const double* spacing /*[3]*/);
 
 /* Sets the thermal field used from the next step on (undercooling values).
    ENUMERIC on non-finite scalars; EINVAL on a grid larger than field_n or

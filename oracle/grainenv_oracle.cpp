@@ -951,6 +951,67 @@ void orc_grain_map(void* h, const int32_t n[3], const double origin[3], const do
 // ------------------------------------------------- FP32 checker ----------
 // Single-rounded FP32 binning: cell = (int)floorf((x - lo) * inv_h), one FP32
 // subtract and one FP32 multiply, clamped to [0, n-1].
+// Mushy-zone deposition (reading R14).  The inside of a grain's envelope is
+// the set of lattice sites the grain has reached, each standing for its
+// crystal-frame cube of edge lambda0 (the mushy zone of Sec. 2.2 is the
+// volume inside the envelopes).  A reached site counts in the node-centred
+// cell of the grid (n, origin, spacing) that holds its centre,
+// index floor((x - origin) / spacing + 1/2) per axis; sites outside every
+// cell are not counted.  FP64.
+void orc_deposit_counts(void* h, const int32_t n[3], const double origin[3],
+                        const double spacing[3], uint32_t* out) {
+  Oracle& o = *(Oracle*)h;
+  std::fill(out, out + (size_t)n[0] * n[1] * n[2], 0u);
+  const uint64_t m21 = (1u << 21) - 1;
+  const int32_t off = 1 << 20;
+  for (size_t g = 0; g < o.claims.size(); ++g) {
+    const Grain& G = o.grains[g];
+    for (auto& kv : o.claims[g]) {
+      if (!(kv.second & C_REACHED)) continue;
+      const double S[3] = {(double)((int32_t)((kv.first >> 42) & m21) - off),
+                           (double)((int32_t)((kv.first >> 21) & m21) - off),
+                           (double)((int32_t)(kv.first & m21) - off)};
+      int64_t idx[3];
+      bool in = true;
+      for (int a = 0; a < 3; ++a) {
+        const double x = G.c[a] + o.p.lambda0 * (G.R[a][0] * S[0] + G.R[a][1] * S[1] + G.R[a][2] * S[2]);
+        const double f = std::floor((x - origin[a]) / spacing[a] + 0.5);
+        if (!(f >= 0 && f < n[a])) in = false;
+        idx[a] = (int64_t)f;
+      }
+      if (in) ++out[((size_t)idx[2] * n[1] + idx[1]) * n[0] + idx[0]];
+    }
+  }
+}
+
+// FP32 checker of the deposition: the site centre computed from FP32 grain
+// rows (centre at [0..2], lambda0 R row-major at [13..21]) as a chain of
+// single-rounded fused multiply-adds, x = c + (lR)_{a0} S0 + (lR)_{a1} S1 +
+// (lR)_{a2} S2 taken from the S2 term outwards, and the index
+// floor((x - origin) * inv_spacing + 1/2) with each operation rounded to FP32.
+void orc_f32_deposit(int64_t m, const int32_t* grain, const int32_t* site, const float* gtab,
+                     const int32_t n[3], const float origin[3], const float inv_sp[3],
+                     uint32_t* out) {
+  std::fill(out, out + (size_t)n[0] * n[1] * n[2], 0u);
+  for (int64_t k = 0; k < m; ++k) {
+    const float* G = gtab + (size_t)grain[k] * 24;
+    const float f0 = (float)site[3 * k], f1 = (float)site[3 * k + 1], f2 = (float)site[3 * k + 2];
+    int64_t idx[3];
+    bool in = true;
+    for (int a = 0; a < 3; ++a) {
+      const float* row = G + 13 + 3 * a;
+      const float x = fmaf(row[0], f0, fmaf(row[1], f1, fmaf(row[2], f2, G[a])));
+      volatile float d = x - origin[a];
+      volatile float u = d * inv_sp[a];
+      volatile float v = u + 0.5f;
+      const float f = floorf(v);
+      if (!(f >= 0.0f && f < (float)n[a])) in = false;
+      idx[a] = (int64_t)f;
+    }
+    if (in) ++out[((size_t)idx[2] * n[1] + idx[1]) * n[0] + idx[0]];
+  }
+}
+
 void orc_f32_cells(int64_t n, const float* xyz, const float lo[3], float inv_h,
                    const int32_t ncell[3], int32_t* out) {
   for (int64_t i = 0; i < n; ++i)

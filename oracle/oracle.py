@@ -86,6 +86,10 @@ def _load():
                                    C.c_int32, P(np.int32), C.c_double, C.c_int64]
     lib.orc_load_state.restype = C.c_int32
     lib.orc_grain_map.argtypes = [vp, P(np.int32), P(np.float64), P(np.float64), P(np.uint32)]
+    lib.orc_deposit_counts.argtypes = [vp, P(np.int32), P(np.float64), P(np.float64),
+                                       P(np.uint32)]
+    lib.orc_f32_deposit.argtypes = [C.c_int64, P(np.int32), P(np.int32), P(np.float32),
+                                    P(np.int32), P(np.float32), P(np.float32), P(np.uint32)]
     lib.orc_f32_cells.argtypes = [C.c_int64, P(np.float32), P(np.float32), C.c_float,
                                   P(np.int32), P(np.int32)]
     lib.orc_f32_contain.argtypes = [C.c_int64, P(np.float32), P(np.int32), P(np.uint8),
@@ -282,6 +286,13 @@ class Oracle:
         self.lib.orc_contain_decisions(self.h, int(method), out)
         return out
 
+    def deposit_counts(self, n, origin, spacing):
+        """Reached lattice sites per node-centred cell, shape (n2, n1, n0) (FP64)."""
+        n = _i32(n)
+        out = np.zeros(int(np.prod(n)), np.uint32)
+        self.lib.orc_deposit_counts(self.h, n, _f64(origin), _f64(spacing), out)
+        return out.reshape(n[2], n[1], n[0])
+
     def grain_map(self, n, origin, spacing):
         n = _i32(n)
         out = np.zeros(int(np.prod(n)), np.uint32)
@@ -329,6 +340,21 @@ def f32_cells(xyz, lo, inv_h, ncell):
     lib.orc_f32_cells(xyz.size // 3, xyz, np.ascontiguousarray(lo, np.float32),
                       np.float32(inv_h), _i32(ncell), out)
     return out.reshape(-1, 3)
+
+
+def f32_deposit(grain, site, gtab, n, origin, inv_spacing):
+    """FP32 checker of the deposition counts of reached sites (grain, site)
+    from FP32 grain rows gtab [n_grains, 24]."""
+    lib = _load()
+    grain = _i32(grain)
+    site = _i32(site).reshape(-1)
+    n = _i32(n)
+    out = np.zeros(int(np.prod(n)), np.uint32)
+    lib.orc_f32_deposit(len(grain), grain, site,
+                        np.ascontiguousarray(gtab, np.float32).reshape(-1), n,
+                        np.ascontiguousarray(origin, np.float32),
+                        np.ascontiguousarray(inv_spacing, np.float32), out)
+    return out.reshape(n[2], n[1], n[0])
 
 
 def f32_contain(xyz, grain, role, rc2):

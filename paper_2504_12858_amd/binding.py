@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "ENUMERIC", -4: "ECF
                 -5: "EDEVICE", -6: "ESTATE"}
 FIELD_UNIFORM, FIELD_LINEAR, FIELD_GRID, FIELD_ROSENTHAL, FIELD_SOLUTE = 0, 1, 2, 3, 4
 (QUERY_COUNTS, QUERY_PARTICLES, QUERY_GRAIN_MAP, QUERY_CLAIMS, QUERY_SITES, QUERY_GRAINS,
- QUERY_DIGEST) = range(7)
+ QUERY_DIGEST, QUERY_MUSHY_COUNTS, QUERY_MUSHY) = range(9)
 ACTIVE, STOPPED, RETIRED = 0, 1, 2
 
 PARTICLE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("s", "<f4"),
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "ge_last_error": ([vp], C.c_char_p),
         "ge_init_grains": ([vp, C.c_int32, vp, vp, vp, P(C.c_uint32)], C.c_int32),
         "ge_set_thermal_field": ([vp, P(ge_field)], C.c_int32),
+        "ge_set_deposition_grid": ([vp, vp, vp, vp], C.c_int32),
         "ge_nucleate": ([vp, C.c_int32, vp, vp, vp], C.c_int32),
         "ge_step": ([vp, C.c_double, C.c_int32, P(ge_step_stats)], C.c_int32),
         "ge_query_envelope": ([vp, C.c_int32, P(ge_query_args), vp, C.c_size_t,
@@ -147,7 +148,8 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy",
-            "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_nucleate", "ge_step",
+            "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_set_deposition_grid",
+            "ge_nucleate", "ge_step",
             "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
@@ -329,6 +331,34 @@ class Context:
             setattr(fs, k, float(getattr(f, k)))
         self._check(self.lib.ge_set_thermal_field(self.ctx, C.byref(fs)), "ge_set_thermal_field")
         del keep
+
+    def set_deposition_grid(self, n, origin=None, spacing=None):
+        """Mushy-zone deposition grid (node-centred cells); n = None: off."""
+        if n is None:
+            self._check(self.lib.ge_set_deposition_grid(self.ctx, None, None, None),
+                        "ge_set_deposition_grid")
+            self.dep_n = None
+            return
+        nn = np.ascontiguousarray(n, np.int32)
+        o = np.ascontiguousarray(origin, np.float64)
+        sp = np.ascontiguousarray(spacing, np.float64)
+        self._check(self.lib.ge_set_deposition_grid(self.ctx, _ptr(nn), _ptr(o), _ptr(sp)),
+                    "ge_set_deposition_grid")
+        self.dep_n = tuple(int(v) for v in nn)
+
+    def mushy_counts(self) -> np.ndarray:
+        """Reached lattice sites per deposition cell, shape (n2, n1, n0)."""
+        n0, n1, n2 = self.dep_n
+        out = np.zeros((n2, n1, n0), np.uint32)
+        self.query_envelope(QUERY_MUSHY_COUNTS, out)
+        return out
+
+    def mushy_fraction(self) -> np.ndarray:
+        """Mushy-zone fraction g^m per deposition cell, shape (n2, n1, n0)."""
+        n0, n1, n2 = self.dep_n
+        out = np.zeros((n2, n1, n0), np.float32)
+        self.query_envelope(QUERY_MUSHY, out)
+        return out
 
     def nucleate(self, xyz, dT_nuc, quat):
         xyz = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)

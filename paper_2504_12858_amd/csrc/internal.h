@@ -115,6 +115,11 @@ struct Dev {
   int32_t fn[3];
   float fo[3], finv[3];
   float* fgrid;
+  // mushy-zone deposition grid (gcnt null: off): reached sites per
+  // node-centred cell
+  uint32_t* gcnt;
+  int32_t gn[3];
+  float go[3], ginv[3];
   // grains
   float* gtab;     // [cap_grains][GT_STRIDE]
   int32_t* gbox;   // [cap_grains][6] lattice bbox of claims: lo xyz, hi xyz
@@ -194,7 +199,7 @@ struct Dev {
 // Every pointer member of Dev (a batched launch stores them as offsets from
 // the batch workspace and rebuilds them on the device).
 #define GE_DEV_POINTERS(X)                                                                   \
-  X(fgrid) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
+  X(fgrid) X(gcnt) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \
@@ -239,6 +244,11 @@ void launch_finish(const Dev& d, double dt, hipStream_t s);
 void launch_reset_stats(const Dev& d, hipStream_t s);
 void launch_stopped_rebuild(const Dev& d, hipStream_t s);  // S -> S2 (caller swaps)
 void launch_resample(const Dev& d, hipStream_t s);
+// Mushy-zone deposition: counts of every reached site (counts cleared
+// first), and g^m = min(1, count lambda0^3 / cell volume) per cell.
+void launch_deposit_all(const Dev& d, hipStream_t s);
+void launch_mushy_fraction(const uint32_t* cnt, uint64_t n, double site_over_cell, float* out,
+                           hipStream_t s);
 // Node undercooling liq_T + liq_m w - T of a SOLUTE field (FP64 in, FP32 out).
 void launch_solute_nodes(const double* T, const double* w, double liq_T, double liq_m,
                          uint64_t n, float* out, hipStream_t s);

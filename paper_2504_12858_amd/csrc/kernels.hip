@@ -301,6 +301,24 @@ __device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int s
   }
 }
 
+// Mushy-zone deposition: a lattice site that a grain has reached adds its
+// crystal-frame cube (lambda0^3) to the deposition cell holding its centre;
+// cell (i, j, k) is the node-centred box of node (i, j, k) of the deposition
+// grid.  FP32, single-rounded: i = floor((x - origin) * inv_spacing + 1/2).
+__device__ __forceinline__ void deposit_site(const Dev& D, const float* __restrict__ G, int sx,
+                                             int sy, int sz) {
+  const P3 x = lattice_pos(G, sx, sy, sz, 0, 0.0f);
+  const float xs[3] = {x.x, x.y, x.z};
+  uint32_t idx[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float f = floorf((xs[a] - D.go[a]) * D.ginv[a] + 0.5f);
+    if (!(f >= 0.0f && f < (float)D.gn[a])) return;
+    idx[a] = (uint32_t)f;
+  }
+  atomicAdd(&D.gcnt[((size_t)idx[2] * (uint32_t)D.gn[1] + idx[1]) * (uint32_t)D.gn[0] + idx[0]], 1u);
+}
+
 // Rounded lattice position of world point y in grain G (crystal frame).
 __device__ __forceinline__ void lattice_round(const float* __restrict__ G, float inv_lambda, P3 y,
                                               int out[3]) {
@@ -936,6 +954,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     }
     cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
     bbox_add(D, g, S[0], S[1], S[2]);
+    if (D.gcnt) deposit_site(D, G, S[0], S[1], S[2]);
     nsp += 1;
   }
   if (nsp) atomicAdd(&s_sp, nsp);
@@ -1765,6 +1784,7 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Bind Bd) {
           int32_t* bb = D.gbox + (size_t)g * 6;
           for (int k = 0; k < 6; ++k) bb[k] = 0;
           claim_or(D, g, 0, 0, 0, M_CLAIMED | M_REACHED);
+          if (D.gcnt) deposit_site(D, T, 0, 0, 0);
           for (int d = 0; d < 6; ++d) {
             D.B[n_out + 6 * nf + d] = make_rec(0.0f, g, d, 0, 0, 0, ST_ACTIVE);
             if (D.tagA) D.tagB[n_out + 6 * nf + d] = NIL;
@@ -1994,7 +2014,10 @@ __global__ __launch_bounds__(TPB) void k_claim_ball(Bind Bd, uint32_t g, int32_t
     const int x = (int)(v % w) - r;
     const int y = (int)((v / w) % w) - r;
     const int z = (int)(v / ((uint64_t)w * w)) - r;
-    if (abs(x) + abs(y) + abs(z) <= r) claim_or(D, g, x, y, z, M_CLAIMED | M_REACHED);
+    if (abs(x) + abs(y) + abs(z) <= r) {
+      claim_or(D, g, x, y, z, M_CLAIMED | M_REACHED);
+      if (D.gcnt) deposit_site(D, D.gtab + (size_t)g * GT_STRIDE, x, y, z);
+    }
   }
 }
 
@@ -2196,6 +2219,44 @@ __global__ __launch_bounds__(TPB) void k_solute_nodes(const double* __restrict__
   for (uint64_t k = (uint64_t)blockIdx.x * TPB + threadIdx.x; k < n;
        k += (uint64_t)gridDim.x * TPB)
     out[k] = (float)((liq_T + liq_m * w[k]) - T[k]);
+}
+
+// Deposition counts from the whole claim hash (every reached site), after
+// the counts were cleared: one lane per (slot, z-layer) word.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_deposit_all(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  const uint64_t slots = D.cmask + 1;
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < slots * 8;
+       v += (uint64_t)V.G * TPB) {
+    const uint64_t slot = v >> 3;
+    const uint32_t w = (uint32_t)(v & 7u);
+    const unsigned long long key = D.ckeys[slot];
+    if (key == CLAIM_EMPTY) continue;
+    unsigned long long rm = D.cbits[slot * 24 + CB_REACHED + w];
+    if (!rm) continue;
+    const uint32_t g = (uint32_t)(key >> 36);
+    const int bx = (int)((key >> 24) & 0xFFFull) - 2048;
+    const int by = (int)((key >> 12) & 0xFFFull) - 2048;
+    const int bz = (int)(key & 0xFFFull) - 2048;
+    const float* G = D.gtab + (size_t)g * GT_STRIDE;
+    while (rm) {
+      const int bit = __ffsll((long long)rm) - 1;
+      rm &= rm - 1ull;
+      deposit_site(D, G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + (int)w);
+    }
+  }
+}
+
+// Mushy-zone fraction of every deposition cell: min(1, count lambda0^3 / V).
+__global__ __launch_bounds__(TPB) void k_mushy_fraction(const uint32_t* __restrict__ cnt,
+                                                        uint64_t n, double site_over_cell,
+                                                        float* __restrict__ out) {
+  for (uint64_t k = (uint64_t)blockIdx.x * TPB + threadIdx.x; k < n;
+       k += (uint64_t)gridDim.x * TPB)
+    out[k] = (float)fmin(1.0, (double)cnt[k] * site_over_cell);
 }
 
 // ============================================================== adjoint ===
@@ -2518,6 +2579,13 @@ void launch_resample(const Dev& d, hipStream_t s) {
 void launch_solute_nodes(const double* T, const double* w, double liq_T, double liq_m,
                          uint64_t n, float* out, hipStream_t s) {
   k_solute_nodes<<<grid_for(n, 8192), TPB, 0, s>>>(T, w, liq_T, liq_m, n, out);
+}
+void launch_deposit_all(const Dev& d, hipStream_t s) {
+  k_deposit_all<<<grid_for((d.cmask + 1) * 8, 16384), TPB, 0, s>>>(Plain{d});
+}
+void launch_mushy_fraction(const uint32_t* cnt, uint64_t n, double site_over_cell, float* out,
+                           hipStream_t s) {
+  k_mushy_fraction<<<grid_for(n, 8192), TPB, 0, s>>>(cnt, n, site_over_cell, out);
 }
 void launch_init_workspace(const Dev& d, hipStream_t s) {
   k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});

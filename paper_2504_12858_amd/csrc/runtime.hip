@@ -34,7 +34,7 @@ struct Geometry {
 struct Layout {
   size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
       bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
-      stab, sstate, cand, fgrid, cnt, dig, total;
+      stab, sstate, cand, fgrid, gcnt, cnt, dig, total;
 };
 
 uint64_t next_pow2(uint64_t v) {
@@ -145,6 +145,7 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.sstate = put(4 * (uint64_t)std::max(p->cap_sites, 1));
   L.cand = put(4 * (uint64_t)std::max(p->cap_sites, 1));
   L.fgrid = put(4 * std::max<uint64_t>(g.field_nodes, 8));
+  L.gcnt = put(4 * std::max<uint64_t>(g.field_nodes, 8));
   L.cnt = put(sizeof(ge::Counters));
   L.dig = put(64);
   L.total = off;
@@ -200,6 +201,9 @@ struct ge_ctx {
   uint64_t gversion = 0;
   double gdt = 0.0;
   hipStream_t cap_stream = nullptr;  // capture stream (the context's stream may be the null stream)
+  // mushy-zone deposition grid (nodes 0: off) and the volume of its cells
+  uint64_t dep_nodes = 0;
+  double dep_cell_volume = 0.0;
   bool dead;
   std::string err;
   // phase timing
@@ -912,6 +916,24 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
       if (!out || out_bytes < need || need == 0) return GE_OK;
       return deliver(c, c->d.gtab, out, need);
     }
+    case GE_QUERY_MUSHY_COUNTS:
+    case GE_QUERY_MUSHY: {
+      if (!c->d.gcnt) return fail(c, GE_EINVAL, "no deposition grid set");
+      need = (size_t)c->dep_nodes * 4;
+      if (needed) *needed = need;
+      if (!out || out_bytes < need) return GE_OK;
+      if (kind == GE_QUERY_MUSHY_COUNTS) return deliver(c, c->d.gcnt, out, need);
+      // g^m on the device, then to the caller.
+      const double site_over_cell =
+          (double)c->p.lambda0 * c->p.lambda0 * c->p.lambda0 / c->dep_cell_volume;
+      float* tmp = nullptr;
+      HIPCHK(c, hipMalloc((void**)&tmp, need));
+      ge::launch_mushy_fraction(c->d.gcnt, c->dep_nodes, site_over_cell, tmp, c->stream);
+      const ge_status st2 = deliver(c, tmp, out, need);
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(tmp);
+      return st2;
+    }
     default:
       return fail(c, GE_EINVAL, "unknown query kind");
   }
@@ -1146,10 +1168,47 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
     HIPCHK(c, hipStreamSynchronize(s));
     (void)hipFree(buf);
   }
+  if (c->d.gcnt) {
+    // Deposition counts of the loaded claims.
+    HIPCHK(c, hipMemsetAsync(c->d.gcnt, 0, 4 * c->dep_nodes, s));
+    ge::launch_deposit_all(c->d, s);
+  }
   HIPCHK(c, hipGetLastError());
   st = read_counters(c);
   if (st != GE_OK) return st;
   return error_status(c, c->host_cnt->err);
+}
+
+ge_status ge_set_deposition_grid(ge_ctx* c, const int32_t n[3], const double origin[3],
+                                 const double spacing[3]) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  Dev& d = c->d;
+  if (!n || n[0] == 0 || n[1] == 0 || n[2] == 0) {
+    d.gcnt = nullptr;
+    c->dep_nodes = 0;
+    return sync_dev(c);
+  }
+  if (!origin || !spacing) return fail(c, GE_EINVAL, "missing grid geometry");
+  uint64_t nodes = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1 || n[a] > c->p.field_n[a]) return fail(c, GE_EINVAL, "deposition grid larger than field_n");
+    if (!std::isfinite(origin[a]) || !(spacing[a] > 0) || !std::isfinite(spacing[a]))
+      return fail(c, GE_EINVAL, "bad deposition grid geometry");
+    nodes *= (uint64_t)n[a];
+  }
+  d.gcnt = (uint32_t*)(c->ws + c->lay.gcnt);
+  for (int a = 0; a < 3; ++a) {
+    d.gn[a] = n[a];
+    d.go[a] = (float)origin[a];
+    d.ginv[a] = (float)(1.0 / spacing[a]);
+  }
+  c->dep_nodes = nodes;
+  c->dep_cell_volume = spacing[0] * spacing[1] * spacing[2];
+  HIPCHK(c, hipMemsetAsync(d.gcnt, 0, 4 * nodes, c->stream));
+  ge::launch_deposit_all(d, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return sync_dev(c);
 }
 
 // ------------------------------------------------------------- model ----
