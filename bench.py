@@ -317,9 +317,11 @@ MUSHY_STEPS = 32
 def mushy_leg(ctx, w, steps=MUSHY_STEPS):
     """Mushy-zone deposition at the 20M snapshot on the 256^3 node grid of
     the field: the full count of every reached site when the grid is set,
-    then blocks of `steps` steps (recorded sequences) with the deposition on
-    and off, alternated twice, each after 16 untimed steps, timed with HIP
-    events; the g^m query."""
+    then blocks of `steps` steps (recorded sequences) with the deposition
+    off, on, on, off (the state grows between blocks: the order cancels the
+    trend), each after 16 untimed steps, timed with HIP events; the branch
+    phase (where reached sites are deposited) with the deposition on and
+    off; the g^m query."""
     import numpy as np
     import torch
     fd = w.field
@@ -337,15 +339,21 @@ def mushy_leg(ctx, w, steps=MUSHY_STEPS):
 
     on_ms, off_ms = [], []
     recount_ms = 0.0
-    for rep in range(2):
-        ctx.set_deposition_grid(None)
+    branch_ms = {}
+    for on in (False, True, True, False):
+        if on:
+            recount_ms = timed(lambda: ctx.set_deposition_grid(n, fd.origin, fd.spacing))
+        else:
+            ctx.set_deposition_grid(None)
         ctx.step(w.dt, 16, stats=False)
         ctx.prepare_step(w.dt)
-        off_ms.append(timed(lambda: ctx.step(w.dt, steps, stats=False)) / steps)
-        recount_ms = timed(lambda: ctx.set_deposition_grid(n, fd.origin, fd.spacing))
-        ctx.step(w.dt, 16, stats=False)
-        ctx.prepare_step(w.dt)
-        on_ms.append(timed(lambda: ctx.step(w.dt, steps, stats=False)) / steps)
+        (on_ms if on else off_ms).append(timed(lambda: ctx.step(w.dt, steps, stats=False)) / steps)
+        if on not in branch_ms:
+            ctx.profile(1)
+            ctx.step(w.dt, 4, stats=False)
+            ph, k = ctx.profile_read()
+            ctx.profile(0)
+            branch_ms[on] = ph["branch"] / max(k, 1)
     t = time.perf_counter()
     gm = ctx.mushy_fraction()
     query_ms = 1e3 * (time.perf_counter() - t)
@@ -357,6 +365,8 @@ def mushy_leg(ctx, w, steps=MUSHY_STEPS):
             "steps_per_block": steps, "recount_ms": round(recount_ms, 3),
             "step_ms_deposition_on": round(on, 4), "step_ms_deposition_off": round(off, 4),
             "overhead_ms_per_step": round(on - off, 4),
+            "branch_ms_deposition_on": round(branch_ms[True], 4),
+            "branch_ms_deposition_off": round(branch_ms[False], 4),
             "reached_sites": int(cnt.sum(dtype=np.int64)),
             "cells_mushy_full": int((gm >= 1.0).sum()), "cells_mushy_partial": int(((gm > 0) & (gm < 1)).sum()),
             "fraction_query_to_host_ms": round(query_ms, 2)}

@@ -305,18 +305,24 @@ __device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int s
 // crystal-frame cube (lambda0^3) to the deposition cell holding its centre;
 // cell (i, j, k) is the node-centred box of node (i, j, k) of the deposition
 // grid.  FP32, single-rounded: i = floor((x - origin) * inv_spacing + 1/2).
-__device__ __forceinline__ void deposit_site(const Dev& D, const float* __restrict__ G, int sx,
-                                             int sy, int sz) {
+// Deposition cell of a site, or NIL outside the grid.
+__device__ __forceinline__ uint32_t deposit_cell(const Dev& D, const float* __restrict__ G, int sx,
+                                                 int sy, int sz) {
   const P3 x = lattice_pos(G, sx, sy, sz, 0, 0.0f);
   const float xs[3] = {x.x, x.y, x.z};
   uint32_t idx[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float f = floorf((xs[a] - D.go[a]) * D.ginv[a] + 0.5f);
-    if (!(f >= 0.0f && f < (float)D.gn[a])) return;
+    if (!(f >= 0.0f && f < (float)D.gn[a])) return NIL;
     idx[a] = (uint32_t)f;
   }
-  atomicAdd(&D.gcnt[((size_t)idx[2] * (uint32_t)D.gn[1] + idx[1]) * (uint32_t)D.gn[0] + idx[0]], 1u);
+  return (idx[2] * (uint32_t)D.gn[1] + idx[1]) * (uint32_t)D.gn[0] + idx[0];
+}
+__device__ __forceinline__ void deposit_site(const Dev& D, const float* __restrict__ G, int sx,
+                                             int sy, int sz) {
+  const uint32_t c = deposit_cell(D, G, sx, sy, sz);
+  if (c != NIL) atomicAdd(&D.gcnt[c], 1u);
 }
 
 // Rounded lattice position of world point y in grain G (crystal frame).
@@ -895,67 +901,77 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
   const SpawnView v = spawn_view(D, s_off);
   const Chunk it = chunk_of(V, v.total, 1u);
   uint32_t nsp = 0, nch = 0;
-  for (uint32_t k = it.begin + threadIdx.x; k < it.end; k += TPB) {
-    const uint32_t i = spawn_item(D, v, s_off, k);
-    const uint4 r = D.A[i];
-    const uint32_t g = rec_grain(r);
-    const int d = rec_dir(r);
-    const float s2 = rec_s(r);
-    // Reached site S = departure site + one step in direction d.
-    const int dstep = (d & 1) ? -1 : 1;
-    const int S[3] = {rec_sx(r) + ((d >> 1) == 0 ? dstep : 0), rec_sy(r) + ((d >> 1) == 1 ? dstep : 0),
-                      rec_sz(r) + ((d >> 1) == 2 ? dstep : 0)};
-    SlotCache sc{~0ull, -1};
-    const uint32_t slot = D.spslot[k];
-    const SlotWin win = load_win(D, slot, S[0], S[1], S[2]);
-    uint32_t mask = 0;
-    for (int dd = 0; dd < 6; ++dd) {
-      const int a = dd >> 1;
-      const int sg = (dd & 1) ? -1 : 1;
-      if (sg * (a == 0 ? S[0] : a == 1 ? S[1] : S[2]) < 0) continue;  // octant rule: outer only
-      const int tx = S[0] + (a == 0 ? sg : 0), ty = S[1] + (a == 1 ? sg : 0),
-                tz = S[2] + (a == 2 ? sg : 0);
-      bool taken;
-      if (!win_bit(win, tx, ty, tz, false, taken))
-        taken = cached_test(D, sc, g, tx, ty, tz, M_CLAIMED | M_REACHED | M_NOW);
-      if (taken) continue;
-      bool lose = false;
-      for (int d2 = 0; d2 < dd && !lose; ++d2) {
-        const int a2 = d2 >> 1;
-        const int sg2 = (d2 & 1) ? -1 : 1;
-        const int ux = tx - (a2 == 0 ? sg2 : 0), uy = ty - (a2 == 1 ? sg2 : 0),
-                  uz = tz - (a2 == 2 ? sg2 : 0);
-        if (sg2 * (a2 == 0 ? ux : a2 == 1 ? uy : uz) < 0) continue;
-        bool rival;
-        if (!win_bit(win, ux, uy, uz, true, rival)) rival = cached_test(D, sc, g, ux, uy, uz, M_NOW);
-        if (rival) lose = true;
+  // The trip count is the same for the block's waves, so the deposition of
+  // the reached sites can be added once per run of equal cells of a wave.
+  for (uint32_t k0 = it.begin; k0 < it.end; k0 += TPB) {
+    const uint32_t k = k0 + threadIdx.x;
+    uint32_t dep = NIL;
+    if (k < it.end) {
+      const uint32_t i = spawn_item(D, v, s_off, k);
+      const uint4 r = D.A[i];
+      const uint32_t g = rec_grain(r);
+      const int d = rec_dir(r);
+      const float s2 = rec_s(r);
+      // Reached site S = departure site + one step in direction d.
+      const int dstep = (d & 1) ? -1 : 1;
+      const int S[3] = {rec_sx(r) + ((d >> 1) == 0 ? dstep : 0), rec_sy(r) + ((d >> 1) == 1 ? dstep : 0),
+                        rec_sz(r) + ((d >> 1) == 2 ? dstep : 0)};
+      SlotCache sc{~0ull, -1};
+      const uint32_t slot = D.spslot[k];
+      const SlotWin win = load_win(D, slot, S[0], S[1], S[2]);
+      uint32_t mask = 0;
+      for (int dd = 0; dd < 6; ++dd) {
+        const int a = dd >> 1;
+        const int sg = (dd & 1) ? -1 : 1;
+        if (sg * (a == 0 ? S[0] : a == 1 ? S[1] : S[2]) < 0) continue;  // octant rule: outer only
+        const int tx = S[0] + (a == 0 ? sg : 0), ty = S[1] + (a == 1 ? sg : 0),
+                  tz = S[2] + (a == 2 ? sg : 0);
+        bool taken;
+        if (!win_bit(win, tx, ty, tz, false, taken))
+          taken = cached_test(D, sc, g, tx, ty, tz, M_CLAIMED | M_REACHED | M_NOW);
+        if (taken) continue;
+        bool lose = false;
+        for (int d2 = 0; d2 < dd && !lose; ++d2) {
+          const int a2 = d2 >> 1;
+          const int sg2 = (d2 & 1) ? -1 : 1;
+          const int ux = tx - (a2 == 0 ? sg2 : 0), uy = ty - (a2 == 1 ? sg2 : 0),
+                    uz = tz - (a2 == 2 ? sg2 : 0);
+          if (sg2 * (a2 == 0 ? ux : a2 == 1 ? uy : uz) < 0) continue;
+          bool rival;
+          if (!win_bit(win, ux, uy, uz, true, rival)) rival = cached_test(D, sc, g, ux, uy, uz, M_NOW);
+          if (rival) lose = true;
+        }
+        if (!lose) mask |= 1u << dd;
       }
-      if (!lose) mask |= 1u << dd;
+      // The parent retires whether or not a child survives: without one, every
+      // outer neighbour of S already belongs to the grain (interior point).
+      D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
+      const float* G = D.gtab + (size_t)g * GT_STRIDE;
+      const float sc2 = s2 - D.lambda0;
+      SlotCache wc{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!(mask & (1u << dd))) continue;
+        const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc2);
+        const C3 c = cell_of(D, xc);
+        const uint32_t ci = cell_index(D, c.x, c.y, c.z);
+        atomicAdd(&D.ccnt[ci], 1u);
+        atomicAdd(&D.bcnt[ci / (uint32_t)BRICK_CELLS], 1u);
+        const int ta = dd >> 1, ts = (dd & 1) ? -1 : 1;
+        const int tx = S[0] + (ta == 0 ? ts : 0), ty = S[1] + (ta == 1 ? ts : 0),
+                  tz = S[2] + (ta == 2 ? ts : 0);
+        cached_or(D, wc, g, tx, ty, tz, M_CLAIMED);
+        bbox_add(D, g, tx, ty, tz);
+        nch += 1;
+      }
+      cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
+      bbox_add(D, g, S[0], S[1], S[2]);
+      if (D.gcnt) dep = deposit_cell(D, G, S[0], S[1], S[2]);
+      nsp += 1;
     }
-    // The parent retires whether or not a child survives: without one, every
-    // outer neighbour of S already belongs to the grain (interior point).
-    D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
-    const float* G = D.gtab + (size_t)g * GT_STRIDE;
-    const float sc2 = s2 - D.lambda0;
-    SlotCache wc{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
-    for (int dd = 0; dd < 6; ++dd) {
-      if (!(mask & (1u << dd))) continue;
-      const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc2);
-      const C3 c = cell_of(D, xc);
-      const uint32_t ci = cell_index(D, c.x, c.y, c.z);
-      atomicAdd(&D.ccnt[ci], 1u);
-      atomicAdd(&D.bcnt[ci / (uint32_t)BRICK_CELLS], 1u);
-      const int ta = dd >> 1, ts = (dd & 1) ? -1 : 1;
-      const int tx = S[0] + (ta == 0 ? ts : 0), ty = S[1] + (ta == 1 ? ts : 0),
-                tz = S[2] + (ta == 2 ? ts : 0);
-      cached_or(D, wc, g, tx, ty, tz, M_CLAIMED);
-      bbox_add(D, g, tx, ty, tz);
-      nch += 1;
+    if (D.gcnt) {
+      const Run run = wave_run(dep);
+      if (dep != NIL && run.off == 0) atomicAdd(&D.gcnt[dep], (uint32_t)run.len);
     }
-    cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
-    bbox_add(D, g, S[0], S[1], S[2]);
-    if (D.gcnt) deposit_site(D, G, S[0], S[1], S[2]);
-    nsp += 1;
   }
   if (nsp) atomicAdd(&s_sp, nsp);
   if (nch) atomicAdd(&s_ch, nch);
