@@ -354,6 +354,7 @@ def mushy_leg(ctx, w, steps=MUSHY_STEPS):
             ph, k = ctx.profile_read()
             ctx.profile(0)
             branch_ms[on] = ph["branch"] / max(k, 1)
+    ctx.set_deposition_grid(n, fd.origin, fd.spacing)
     t = time.perf_counter()
     gm = ctx.mushy_fraction()
     query_ms = 1e3 * (time.perf_counter() - t)
