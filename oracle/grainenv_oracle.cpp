@@ -115,6 +115,7 @@ struct Field {
 struct Stats {
   int64_t advanced = 0, exited = 0, spawners = 0, children = 0, contained = 0,
           nucleated = 0;
+  int64_t melted = 0, removed = 0, reactivated = 0, grains_melted = 0;
   double max_step = 0;
 };
 
@@ -131,6 +132,8 @@ struct Oracle {
   int64_t step = 0;
   int32_t err = E_OK;
   Stats last;
+  bool melting = false;
+  std::vector<int32_t> grain_site;  // nucleation site of each grain, -1 for initial grains
 };
 
 inline int axis_of(int d) { return d >> 1; }
@@ -526,12 +529,103 @@ void phase_contain(Oracle& o) {
   o.last.contained = n;
 }
 
-void add_grain(Oracle& o, const double c[3], const double q[4]) {
+void add_grain(Oracle& o, const double c[3], const double q[4], int32_t site = -1) {
   Grain g{};
   for (int a = 0; a < 3; ++a) g.c[a] = c[a];
   rotation_from_quat(q, g.R);
   o.grains.push_back(g);
   o.claims.emplace_back();
+  o.grain_site.push_back(site);
+}
+
+inline void site_of_key(uint64_t key, int32_t s[3]) {
+  const uint64_t m21 = (1u << 21) - 1;
+  const int32_t off = 1 << 20;
+  s[0] = (int32_t)((key >> 42) & m21) - off;
+  s[1] = (int32_t)((key >> 21) & m21) - off;
+  s[2] = (int32_t)(key & m21) - off;
+}
+
+// Melting by walk-back (Sec. 2.1.3; reading R15), with the field at t_n:
+//   1. a reached site S whose undercooling is negative, dT(x_S) < 0, melts:
+//      it is no longer claimed or reached;
+//   2. a particle (active or stopped) whose departure site melted is
+//      removed, and an active one's target is no longer claimed;
+//   3. walk-back: for each site T melted in this step, the first direction d
+//      (0..5) for which S = T - e_d is still a reached site of the grain gives
+//      an active particle at S moving towards T (travel 0), and T is claimed
+//      as its target (the re-activated points are the solid sites next to
+//      the melt, within lambda0 of the dT = 0 iso-surface);
+//   4. a grain left without reached sites has melted entirely; its
+//      nucleation site, if it has one, is dormant again and may fire anew.
+void phase_melt(Oracle& o) {
+  const Params& p = o.p;
+  if (!o.melting) return;
+  if (o.f.kind == F_ROSENTHAL) sample_rosenthal(o.f, o.t);
+  std::vector<std::vector<uint64_t>> melted(o.grains.size());
+  for (size_t g = 0; g < o.grains.size(); ++g) {
+    for (auto& kv : o.claims[g]) {
+      if (!(kv.second & C_REACHED)) continue;
+      int32_t S[3];
+      site_of_key(kv.first, S);
+      double x[3];
+      lattice_position(p, o.grains[g], S, 0, 0.0, x);
+      if (field_value(o.f, x, o.t) - p.theta < 0) melted[g].push_back(kv.first);
+    }
+    std::sort(melted[g].begin(), melted[g].end());
+    for (uint64_t k : melted[g]) o.claims[g].erase(k);
+    o.last.melted += (int64_t)melted[g].size();
+  }
+  // Particles of melted departure sites.
+  for (Particle& q : o.parts) {
+    if (q.state == P_RETIRED) continue;
+    const auto& mg = melted[q.g];
+    if (!std::binary_search(mg.begin(), mg.end(), site_key(q.site[0], q.site[1], q.site[2])))
+      continue;
+    if (q.state == P_ACTIVE) {
+      int32_t T[3] = {q.site[0], q.site[1], q.site[2]};
+      T[axis_of(q.dir)] += sign_of(q.dir);
+      auto it = o.claims[q.g].find(site_key(T[0], T[1], T[2]));
+      if (it != o.claims[q.g].end() && it->second == C_CLAIMED) o.claims[q.g].erase(it);
+    }
+    q.state = P_RETIRED;
+    o.last.removed += 1;
+  }
+  // Walk-back.
+  for (size_t g = 0; g < o.grains.size(); ++g) {
+    for (uint64_t k : melted[g]) {
+      int32_t T[3];
+      site_of_key(k, T);
+      for (int d = 0; d < 6; ++d) {
+        int32_t S[3] = {T[0], T[1], T[2]};
+        S[axis_of(d)] -= sign_of(d);
+        auto it = o.claims[g].find(site_key(S[0], S[1], S[2]));
+        if (it == o.claims[g].end() || !(it->second & C_REACHED)) continue;
+        Particle ch{};
+        ch.g = (int32_t)g;
+        for (int a = 0; a < 3; ++a) ch.site[a] = S[a];
+        ch.dir = d;
+        ch.s = 0;
+        lattice_position(p, o.grains[g], ch.site, ch.dir, 0.0, ch.x);
+        ch.state = P_ACTIVE;
+        o.parts.push_back(ch);
+        add_claim(o.claims[g], T, C_CLAIMED);
+        o.last.reactivated += 1;
+        break;
+      }
+    }
+    // A grain without reached sites has melted entirely.
+    if (!melted[g].empty()) {
+      bool any = false;
+      for (auto& kv : o.claims[g])
+        if (kv.second & C_REACHED) { any = true; break; }
+      if (!any) {
+        o.claims[g].clear();
+        o.last.grains_melted += 1;
+        if (o.grain_site[g] >= 0) o.sites[o.grain_site[g]].state = S_DORMANT;
+      }
+    }
+  }
 }
 
 void phase_nucleate(Oracle& o) {
@@ -572,7 +666,7 @@ void phase_nucleate(Oracle& o) {
     if (!liquid) continue;
     // Fire: new grain with centre y, 6 particles at the centre.
     st.state = S_FIRED;
-    add_grain(o, st.y, st.q);
+    add_grain(o, st.y, st.q, (int32_t)(&st - o.sites.data()));
     int32_t g = (int32_t)o.grains.size() - 1;
     int32_t zero[3] = {0, 0, 0};
     add_claim(o.claims[g], zero, C_CLAIMED | C_REACHED);
@@ -595,6 +689,7 @@ void phase_nucleate(Oracle& o) {
 
 void do_step(Oracle& o, double dt) {
   o.last = Stats{};
+  phase_melt(o);
   phase_advance(o, dt);
   phase_box_exit(o);
   phase_branch(o);
@@ -657,6 +752,18 @@ void orc_set_kinetics(void* h, const double a[2]) {
 }
 
 void orc_set_branching(void* h, int32_t on) { ((Oracle*)h)->p.branching = on; }
+
+void orc_set_melting(void* h, int32_t on) { ((Oracle*)h)->melting = on != 0; }
+
+// Melting counters of the last step: sites melted, particles removed,
+// particles re-activated, grains melted entirely.
+void orc_melt_stats(void* h, int64_t out[4]) {
+  const Stats& s = ((Oracle*)h)->last;
+  out[0] = s.melted;
+  out[1] = s.removed;
+  out[2] = s.reactivated;
+  out[3] = s.grains_melted;
+}
 
 int32_t orc_set_field(void* h, const orc_field* fs) {
   Oracle& o = *(Oracle*)h;
@@ -787,6 +894,7 @@ int32_t orc_phase(void* h, int32_t phase, double dt) {
     case 3: phase_contain(o); break;
     case 4: phase_nucleate(o); break;
     case 5: o.t += dt; o.step += 1; break;
+    case 6: phase_melt(o); break;
     default: return E_INVAL;
   }
   return o.err;
@@ -895,7 +1003,16 @@ int32_t orc_load_state(void* h, int32_t n_grains, const double* centre, const do
   o.grains.clear();
   o.claims.clear();
   o.parts.clear();
-  for (int32_t g = 0; g < n_grains; ++g) add_grain(o, centre + 3 * g, quat + 4 * g);
+  o.grain_site.clear();
+  // A grain whose centre is a fired site's position came from that site.
+  for (int32_t g = 0; g < n_grains; ++g) {
+    int32_t from = -1;
+    for (size_t i = 0; i < o.sites.size() && i < (size_t)n_sites && from < 0; ++i)
+      if (site_state[i] == S_FIRED && o.sites[i].y[0] == centre[3 * g] &&
+          o.sites[i].y[1] == centre[3 * g + 1] && o.sites[i].y[2] == centre[3 * g + 2])
+        from = (int32_t)i;
+    add_grain(o, centre + 3 * g, quat + 4 * g, from);
+  }
   o.parts.resize(n_parts);
   for (int64_t i = 0; i < n_parts; ++i) {
     Particle& q = o.parts[i];

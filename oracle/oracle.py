@@ -55,6 +55,8 @@ def _load():
     lib.orc_set_theta.argtypes = [vp, C.c_double]
     lib.orc_set_kinetics.argtypes = [vp, P(np.float64)]
     lib.orc_set_branching.argtypes = [vp, C.c_int32]
+    lib.orc_set_melting.argtypes = [vp, C.c_int32]
+    lib.orc_melt_stats.argtypes = [vp, P(np.int64)]
     lib.orc_set_field.argtypes = [vp, C.POINTER(_Field)]
     lib.orc_set_field.restype = C.c_int32
     lib.orc_field_value.argtypes = [vp, C.c_int64, P(np.float64), C.c_double, P(np.float64),
@@ -193,6 +195,14 @@ class Oracle:
 
     def set_branching(self, on):
         self.lib.orc_set_branching(self.h, int(on))
+
+    def set_melting(self, on):
+        self.lib.orc_set_melting(self.h, int(on))
+
+    def melt_stats(self):
+        out = np.zeros(4, np.int64)
+        self.lib.orc_melt_stats(self.h, out)
+        return dict(zip(("melted", "removed", "reactivated", "grains_melted"), out.tolist()))
 
     def init_grains(self, centre, quat, shell_r):
         centre, quat, shell_r = _f64(centre).reshape(-1, 3), _f64(quat).reshape(-1, 4), _i32(shell_r)
