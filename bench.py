@@ -373,6 +373,43 @@ def mushy_leg(ctx, w, steps=MUSHY_STEPS):
             "fraction_query_to_host_ms": round(query_ms, 2)}
 
 
+MELT_STEPS = 32
+
+
+def melt_leg(ctx, w, steps=MELT_STEPS):
+    """Melting by walk-back at the 20M snapshot under the moving source (its
+    melt pool): blocks of `steps` steps with melting off, on, on, off, each
+    after 16 untimed steps, timed with HIP events, and the melting counts."""
+    import torch
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        out = fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    on_ms, off_ms, counts = [], [], {}
+    for on in (False, True, True, False):
+        ctx.set_melting(on)
+        ctx.step(w.dt, 16, stats=False)
+        ctx.prepare_step(w.dt)
+        ms, st = timed(lambda: ctx.step(w.dt, steps))
+        (on_ms if on else off_ms).append(ms / steps)
+        if on:
+            for k in ("melted", "removed", "reactivated", "grains_melted"):
+                counts[k] = counts.get(k, 0) + int(st[k])
+    ctx.set_melting(False)
+    on, off = sum(on_ms) / len(on_ms), sum(off_ms) / len(off_ms)
+    return {"workload": "cet-moving-source-20M snapshot, melting under the moving source",
+            "steps_per_block": steps, "step_ms_melting_on": round(on, 4),
+            "step_ms_melting_off": round(off, 4), "overhead_ms_per_step": round(on - off, 4),
+            "per_step_on": {k: round(v / (2 * steps), 1) for k, v in counts.items()}}
+
+
 SOLUTE_STEPS = 20
 
 
@@ -497,6 +534,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-solute", action="store_true")
     ap.add_argument("--no-mushy", action="store_true")
+    ap.add_argument("--no-melt", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=3, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -587,6 +625,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
+    if not args.no_melt:
+        out["melting"] = melt_leg(ctx, w)
+        log(f"[melt] {out['melting']}")
     if not args.no_mushy:
         out["mushy"] = mushy_leg(ctx, w)
         log(f"[mushy] {out['mushy']}")

@@ -155,6 +155,10 @@ typedef struct ge_step_stats {
   int64_t dirty_tests;/* active particles given the containment test: those of the cells
                          of dirty bricks whose 3x3x3 cell neighbourhood reaches a brick
                          that holds another grain */
+  int64_t melted;     /* melting: reached sites melted */
+  int64_t removed;    /* melting: particles removed with their melted departure sites */
+  int64_t reactivated;/* melting: particles re-activated next to melted sites (walk-back) */
+  int64_t grains_melted; /* melting: grains melted entirely */
 } ge_step_stats;
 
 /* Query kinds of ge_query_envelope. */
@@ -271,6 +275,24 @@ ge_status ge_init_grains(ge_ctx* ctx, int32_t n, const double* centre /*[n][3]*/
    turns the deposition off. */
 ge_status ge_set_deposition_grid(ge_ctx* ctx, const int32_t* n /*[3]*/, const double* origin /*[3]*/,
                                  const double* spacing /*[3]*/);
+
+/* Melting by walk-back (Sec. 2.1.3), off by default.  With melting on,
+   every step starts, with the field of that step (dT = field - theta), by:
+     1. a reached lattice site S of a grain with dT(x_S) < 0 melts: it is no
+        longer claimed or reached;
+     2. a particle, active or stopped, whose departure site melted is
+        removed, and an active one's target is released;
+     3. walk-back: for each site T melted in this step, the first direction
+        d (0..5) for which S = T - e_d is a reached site of the grain gives
+        an active particle at S moving towards T (travel 0), and T is claimed
+        as its target: the solid sites next to the melt are re-activated;
+     4. a grain left without reached sites has melted entirely, and its
+        nucleation site, if it has one, is dormant again and may fire anew
+        (as a new grain) once its nucleation undercooling is reached.
+   Sites inside claims are then tested again every step.  The counts of a
+   step call are in ge_step_stats.  Not available with an adjoint recording
+   or in batched steps (EINVAL there). */
+ge_status ge_set_melting(ge_ctx* ctx, int32_t on);
 
 /* Sets the thermal field used from the next step on (undercooling values).
    ENUMERIC on non-finite scalars; EINVAL on a grid larger than field_n or

@@ -64,7 +64,9 @@ class ge_step_stats(C.Structure):
                 ("n_claim_bricks", C.c_int64), ("advanced", C.c_int64), ("exited", C.c_int64),
                 ("spawners", C.c_int64), ("children", C.c_int64), ("contained", C.c_int64),
                 ("nucleated", C.c_int64), ("max_step", C.c_double), ("t", C.c_double),
-                ("step", C.c_int64), ("pair_tests", C.c_int64), ("dirty_tests", C.c_int64)]
+                ("step", C.c_int64), ("pair_tests", C.c_int64), ("dirty_tests", C.c_int64),
+                ("melted", C.c_int64), ("removed", C.c_int64), ("reactivated", C.c_int64),
+                ("grains_melted", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "ge_init_grains": ([vp, C.c_int32, vp, vp, vp, P(C.c_uint32)], C.c_int32),
         "ge_set_thermal_field": ([vp, P(ge_field)], C.c_int32),
         "ge_set_deposition_grid": ([vp, vp, vp, vp], C.c_int32),
+        "ge_set_melting": ([vp, C.c_int32], C.c_int32),
         "ge_nucleate": ([vp, C.c_int32, vp, vp, vp], C.c_int32),
         "ge_step": ([vp, C.c_double, C.c_int32, P(ge_step_stats)], C.c_int32),
         "ge_query_envelope": ([vp, C.c_int32, P(ge_query_args), vp, C.c_size_t,
@@ -149,6 +152,7 @@ def load_library(path: str = LIB_PATH):
 
 EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy",
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_set_deposition_grid",
+            "ge_set_melting",
             "ge_nucleate", "ge_step",
             "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
@@ -331,6 +335,10 @@ class Context:
             setattr(fs, k, float(getattr(f, k)))
         self._check(self.lib.ge_set_thermal_field(self.ctx, C.byref(fs)), "ge_set_thermal_field")
         del keep
+
+    def set_melting(self, on):
+        """Melting by walk-back at the start of every step (off by default)."""
+        self._check(self.lib.ge_set_melting(self.ctx, int(bool(on))), "ge_set_melting")
 
     def set_deposition_grid(self, n, origin=None, spacing=None):
         """Mushy-zone deposition grid (node-centred cells); n = None: off."""

@@ -74,6 +74,11 @@ struct Counters {
   unsigned long long advanced, exited, spawners, children, contained, nucleated;
   unsigned long long pair_tests;  // candidate particles examined by containment
   unsigned long long dirty_tests; // active particles in dirty bricks
+  // melting (walk-back): sites melted, particles removed, particles
+  // re-activated, grains melted entirely
+  unsigned long long melted, removed, reactivated, grains_melted;
+  uint32_t n_melt_slots;  // claim slots with sites melted this step
+  uint32_t n_resorted;    // live records counted by the stopped-store re-sort
   // step state, advanced on the device by k_finish (so that a captured
   // sequence of steps replays without host involvement)
   uint32_t par;        // 1: the active-store roles of A and B (and their tags) are swapped
@@ -120,6 +125,13 @@ struct Dev {
   uint32_t* gcnt;
   int32_t gn[3];
   float go[3], ginv[3];
+  // melting (walk-back; melting = 0: off)
+  int32_t melting;
+  float* fcmin;        // [field cells] least node value of each cell of a node grid
+  uint32_t* mslots;    // [claim slots] slots with sites melted this step
+  uint32_t* greach;    // [cap_grains] reached sites of each grain (kept while melting)
+  int32_t* gsite;      // [cap_grains] nucleation site of each grain, -1: none
+  uint32_t* gdead;     // [cap_grains] 1: the grain has melted entirely
   // grains
   float* gtab;     // [cap_grains][GT_STRIDE]
   int32_t* gbox;   // [cap_grains][6] lattice bbox of claims: lo xyz, hi xyz
@@ -199,7 +211,7 @@ struct Dev {
 // Every pointer member of Dev (a batched launch stores them as offsets from
 // the batch workspace and rebuilds them on the device).
 #define GE_DEV_POINTERS(X)                                                                   \
-  X(fgrid) X(gcnt) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
+  X(fgrid) X(gcnt) X(fcmin) X(mslots) X(greach) X(gsite) X(gdead) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \
@@ -244,6 +256,12 @@ void launch_finish(const Dev& d, double dt, hipStream_t s);
 void launch_reset_stats(const Dev& d, hipStream_t s);
 void launch_stopped_rebuild(const Dev& d, hipStream_t s);  // S -> S2 (caller swaps)
 void launch_resample(const Dev& d, hipStream_t s);
+// Melting by walk-back, run at the start of a step when enabled: least node
+// value per field cell, melted sites, walk-back particles, melted grains,
+// stopped particles of melted sites.  launch_count_reached recounts the
+// reached sites of every grain (grains with none are marked melted).
+void launch_melt(const Dev& d, hipStream_t s);
+void launch_count_reached(const Dev& d, hipStream_t s);
 // Mushy-zone deposition: counts of every reached site (counts cleared
 // first), and g^m = min(1, count lambda0^3 / cell volume) per cell.
 void launch_deposit_all(const Dev& d, hipStream_t s);

@@ -325,6 +325,45 @@ __device__ __forceinline__ void deposit_site(const Dev& D, const float* __restri
   if (c != NIL) atomicAdd(&D.gcnt[c], 1u);
 }
 
+// Lower bound of the undercooling field (without theta) over the box
+// [lo, hi], with a margin for the rounding of the evaluation.
+__device__ float field_lower(const Dev& D, P3 lo, P3 hi, float lin_c) {
+  if (D.fkind == F_UNIFORM) return D.fdT;
+  if (D.fkind == F_LINEAR) {
+    const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+    float v = lin_c, mag = fabsf(lin_c);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      v += fminf(D.fgrad[a] * l[a], D.fgrad[a] * h[a]);
+      mag += fmaxf(fabsf(D.fgrad[a] * l[a]), fabsf(D.fgrad[a] * h[a]));
+    }
+    return v - 1e-5f * mag - 1e-6f;
+  }
+  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+  int c0[3], c1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float top = (float)(D.fn[a] - 2);
+    c0[a] = (int)fminf(fmaxf(floorf((l[a] - D.fo[a]) * D.finv[a]), 0.0f), top);
+    c1[a] = (int)fminf(fmaxf(floorf((h[a] - D.fo[a]) * D.finv[a]), 0.0f), top);
+  }
+  const size_t cx = (size_t)D.fn[0] - 1, cy = (size_t)D.fn[1] - 1;
+  float m = INFINITY;
+  for (int k = c0[2]; k <= c1[2]; ++k)
+    for (int j = c0[1]; j <= c1[1]; ++j)
+      for (int i = c0[0]; i <= c1[0]; ++i) m = fminf(m, D.fcmin[((size_t)k * cy + j) * cx + i]);
+  return m - 1e-5f * fabsf(m) - 1e-6f;
+}
+
+// Undercooling at the departure site of a record is negative (the site
+// melted), tested first against the bound of its cell neighbourhood.
+__device__ __forceinline__ bool departure_melted(const Dev& D, const float* __restrict__ G,
+                                                 int sx, int sy, int sz, float lin_c) {
+  const P3 x = lattice_pos(G, sx, sy, sz, 0, 0.0f);
+  if (field_lower(D, x, x, lin_c) - D.theta >= 0.0f) return false;
+  return field_at(D, x, lin_c) - D.theta < 0.0f;
+}
+
 // Rounded lattice position of world point y in grain G (crystal frame).
 __device__ __forceinline__ void lattice_round(const float* __restrict__ G, float inv_lambda, P3 y,
                                               int out[3]) {
@@ -717,7 +756,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
   const Chunk ch = chunk_of(V, n, TPB);
   const int lane = lane_id();
   float max_step = 0.0f;
-  uint32_t nadv = 0, nexit = 0, bad = 0;
+  uint32_t nadv = 0, nexit = 0, bad = 0, nrm = 0;
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t i = base + threadIdx.x;
     const bool valid = i < ch.end;
@@ -727,7 +766,28 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
     bool spawn = false, exited = false;
     P3 x2 = {0.0f, 0.0f, 0.0f};
     uint32_t tag = NIL;
-    if (act) {
+    bool gone = false;
+    if (act && D.melting) {
+      // Melting: a particle whose departure site melted this step goes, and
+      // its target is released.
+      const uint32_t g = rec_grain(r);
+      const float* G = D.gtab + (size_t)g * GT_STRIDE;
+      gone = departure_melted(D, G, rec_sx(r), rec_sy(r), rec_sz(r), lin_c);
+      if (gone) {
+        const int d = rec_dir(r);
+        int T[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
+        T[d >> 1] += (d & 1) ? -1 : 1;
+        const int64_t slot = claim_find(D, claim_key(g, T[0], T[1], T[2]));
+        if (slot >= 0) {
+          const uint32_t b = site_bit(T[0], T[1], T[2]);
+          atomicAnd(D.cbits + (size_t)slot * 24 + CB_CLAIMED + (b >> 6), ~(1ull << (b & 63)));
+        }
+        r = with_fl(r, ST_RETIRED);
+        D.A[i] = r;
+        nrm += 1;
+      }
+    }
+    if (act && !gone) {
       const uint32_t g = rec_grain(r);
       const int d = rec_dir(r);
       const int sx = rec_sx(r), sy = rec_sy(r), sz = rec_sz(r);
@@ -796,6 +856,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
   }
   if (nadv) atomicAdd(&s_adv, nadv);
   if (nexit) atomicAdd(&s_exit, nexit);
+  if (nrm) atomicAdd(&D.cnt->removed, (unsigned long long)nrm);
   if (bad) atomicOr(&s_bad, bad);
   if (max_step > 0.0f) atomicMax(&s_max, __float_as_uint(max_step));
   __syncthreads();
@@ -905,7 +966,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
   // the reached sites can be added once per run of equal cells of a wave.
   for (uint32_t k0 = it.begin; k0 < it.end; k0 += TPB) {
     const uint32_t k = k0 + threadIdx.x;
-    uint32_t dep = NIL;
+    uint32_t dep = NIL, rg = NIL;
     if (k < it.end) {
       const uint32_t i = spawn_item(D, v, s_off, k);
       const uint4 r = D.A[i];
@@ -966,11 +1027,16 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
       bbox_add(D, g, S[0], S[1], S[2]);
       if (D.gcnt) dep = deposit_cell(D, G, S[0], S[1], S[2]);
+      if (D.melting) rg = g;
       nsp += 1;
     }
     if (D.gcnt) {
       const Run run = wave_run(dep);
       if (dep != NIL && run.off == 0) atomicAdd(&D.gcnt[dep], (uint32_t)run.len);
+    }
+    if (D.melting) {
+      const Run run = wave_run(rg);
+      if (rg != NIL && run.off == 0) atomicAdd(&D.greach[rg], (uint32_t)run.len);
     }
   }
   if (nsp) atomicAdd(&s_sp, nsp);
@@ -1038,6 +1104,7 @@ __global__ __launch_bounds__(TPB) void k_scan_top(Bind Bd, int mode) {
       if (n_out > D.cap_p) atomicOr(&D.cnt->err, ERR_CAPACITY);
     } else {
       D.cnt->n_socc = n_occ;
+      D.cnt->n_resorted = n_out;
     }
   }
 }
@@ -1732,7 +1799,8 @@ __global__ __launch_bounds__(TPB) void k_nuc_test(Bind Bd) {
       claimed = claim_test(D, g, l[0], l[1], l[2], M_CLAIMED | M_REACHED);
     }
     if (claimed) {
-      D.sstate[i] = SITE_ENGULFED;  // claims never shrink: permanent
+      // Without melting claims never shrink: the site can never fire.
+      if (!D.melting) D.sstate[i] = SITE_ENGULFED;
       continue;
     }
     uint32_t tests = 0;
@@ -1801,6 +1869,9 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Bind Bd) {
           for (int k = 0; k < 6; ++k) bb[k] = 0;
           claim_or(D, g, 0, 0, 0, M_CLAIMED | M_REACHED);
           if (D.gcnt) deposit_site(D, T, 0, 0, 0);
+          D.greach[g] = 1u;
+          D.gdead[g] = 0u;
+          D.gsite[g] = (int32_t)si;
           for (int d = 0; d < 6; ++d) {
             D.B[n_out + 6 * nf + d] = make_rec(0.0f, g, d, 0, 0, 0, ST_ACTIVE);
             if (D.tagA) D.tagB[n_out + 6 * nf + d] = NIL;
@@ -1856,6 +1927,10 @@ __global__ void k_reset_stats(Bind Bd) {
   c->max_step = 0;
   c->pair_tests = 0;
   c->dirty_tests = 0;
+  c->melted = 0;
+  c->removed = 0;
+  c->reactivated = 0;
+  c->grains_melted = 0;
 }
 
 // ------------------------------------------------ stopped-store re-sort ---
@@ -1874,9 +1949,14 @@ __global__ __launch_bounds__(TPB) void k_srb_count(Bind Bd) {
     const uint32_t j = base + threadIdx.x;
     uint32_t ckey = NIL;
     if (j < ch.end) {
-      const C3 c = cell_of(D, p3_of(D.PS[j]));
+      // A record removed by melting (NaN position) is dropped; the list head
+      // of its cell is cleared all the same.
+      const float4 q = D.PS[j];
+      const bool gone = isnan(q.x);
+      const C3 c = cell_of(D, gone ? rec_pos(D, D.S[j]) : p3_of(q));
       ckey = cell_index(D, c.x, c.y, c.z);
       if (j >= ns) D.shead[ckey] = NIL;
+      if (gone) ckey = NIL;
     }
     const Run rc = wave_run(ckey);
     if (ckey != NIL && rc.off == 0) atomicAdd(&D.ccnt[ckey], (uint32_t)rc.len);
@@ -1900,8 +1980,10 @@ __global__ __launch_bounds__(TPB) void k_srb_scatter(Bind Bd) {
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     if (j < ch.end) {
       q = D.PS[j];
-      const C3 c = cell_of(D, p3_of(q));
-      ckey = cell_index(D, c.x, c.y, c.z);
+      if (!isnan(q.x)) {
+        const C3 c = cell_of(D, p3_of(q));
+        ckey = cell_index(D, c.x, c.y, c.z);
+      }
     }
     const Run run = wave_run(ckey);
     uint32_t rbase = 0;
@@ -1923,8 +2005,11 @@ __global__ void k_srb_finish(Bind Bd) {
   VGrid V;
   Bd.bind(D, V);
   if ((D.cnt->err & (ERR_CAPACITY | HOLD)) || !resort_due(D)) return;
-  D.cnt->n_sorted = min(D.cnt->n_stopped, D.cap_s);
-  D.cnt->spar ^= 1u;  // the re-sorted copy becomes the stopped store
+  // The re-sorted copy (the records not removed by melting) becomes the
+  // stopped store.
+  D.cnt->n_sorted = D.cnt->n_resorted;
+  D.cnt->n_stopped = D.cnt->n_resorted;
+  D.cnt->spar ^= 1u;
 }
 
 // ------------------------------------------------------------- resample ---
@@ -1968,6 +2053,266 @@ __global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
     if (dT < a.dT_min) dT = a.dT_min;
     D.fgrid[v] = (float)dT;
   }
+}
+
+// -------------------------------------------------------------- melting ---
+// Melting by walk-back (Sec. 2.1.3), at the start of a step when enabled,
+// with the field of the step (the undercooling dT = field - theta):
+//   1. a reached site S of a grain with dT(x_S) < 0 melts: it is no longer
+//      claimed or reached (k_melt_sites; the melted sites are marked in the
+//      slot's this-step words, which are clear at the start of a step);
+//   2. a particle whose departure site melted is removed, an active one's
+//      target released (k_advance for active particles, k_melt_stopped for
+//      stopped ones); departure sites are reached sites, so the test is
+//      dT(x_D) < 0 with the same arithmetic as in 1;
+//   3. walk-back: each melted site T whose first direction d (0..5) with
+//      S = T - e_d a reached site of the grain gives an active particle at S
+//      moving towards T (travel 0), and T is claimed as its target
+//      (k_walkback);
+//   4. a grain left without reached sites has melted entirely; its
+//      nucleation site is dormant again (k_melt_grains).
+// Work is confined by lower bounds of the field over boxes: a box whose
+// bound is not negative holds no melting site.
+
+// Least node value of each cell of a node grid.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_field_cellmin(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (dead(D) || !(D.fkind == F_GRID || D.fkind == F_ROSENTHAL)) return;
+  const uint32_t cx = (uint32_t)D.fn[0] - 1u, cy = (uint32_t)D.fn[1] - 1u, cz = (uint32_t)D.fn[2] - 1u;
+  const uint64_t total = (uint64_t)cx * cy * cz;
+  const size_t sy = (size_t)D.fn[0], sz = (size_t)D.fn[0] * (size_t)D.fn[1];
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total; v += (uint64_t)V.G * TPB) {
+    const uint64_t i = v % cx, j = (v / cx) % cy, k = v / ((uint64_t)cx * cy);
+    const size_t b = k * sz + j * sy + i;
+    const float* g = D.fgrid;
+    float m = fminf(fminf(g[b], g[b + 1]), fminf(g[b + sy], g[b + sy + 1]));
+    m = fminf(m, fminf(fminf(g[b + sz], g[b + sz + 1]), fminf(g[b + sz + sy], g[b + sz + sy + 1])));
+    D.fcmin[v] = m;
+  }
+}
+
+// One lane per claim slot: the reached sites below zero undercooling melt,
+// layer by layer (a layer whose bound is not negative is skipped); a slot
+// with melted sites goes to the walk-back list.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_melt_sites(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (dead(D)) return;
+  const float lin_c = lin_const(D);
+  __shared__ uint32_t s_melted;
+  if (threadIdx.x == 0) s_melted = 0;
+  __syncthreads();
+  uint32_t melted = 0;
+  const uint64_t slots = D.cmask + 1;
+  for (uint64_t slot = (uint64_t)V.b * TPB + threadIdx.x; slot < slots; slot += (uint64_t)V.G * TPB) {
+    const unsigned long long key = D.ckeys[slot];
+    if (key == CLAIM_EMPTY) continue;
+    const uint32_t g = (uint32_t)(key >> 36);
+    const int bx = (int)((key >> 24) & 0xFFFull) - 2048;
+    const int by = (int)((key >> 12) & 0xFFFull) - 2048;
+    const int bz = (int)(key & 0xFFFull) - 2048;
+    const float* G = D.gtab + (size_t)g * GT_STRIDE;
+    // Half-extents of a layer of 8 x 8 sites around its centre site (3, 3)
+    // (at most 4 sites away along x and y, none along z).
+    const float ex = 4.0f * (fabsf(G[13]) + fabsf(G[14]));
+    const float ey = 4.0f * (fabsf(G[16]) + fabsf(G[17]));
+    const float ez = 4.0f * (fabsf(G[19]) + fabsf(G[20]));
+    unsigned long long* q = D.cbits + slot * 24;
+    uint32_t n = 0;
+    for (int w = 0; w < 8; ++w) {
+      const unsigned long long rm = q[CB_REACHED + w];
+      if (!rm) continue;
+      const P3 c = lattice_pos(G, bx * 8 + 3, by * 8 + 3, bz * 8 + w, 0, 0.0f);
+      if (field_lower(D, P3{c.x - ex, c.y - ey, c.z - ez}, P3{c.x + ex, c.y + ey, c.z + ez},
+                      lin_c) - D.theta >= 0.0f)
+        continue;
+      unsigned long long mask = 0, m = rm;
+      while (m) {
+        const int bit = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const P3 x = lattice_pos(G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + w, 0,
+                                 0.0f);
+        if (field_at(D, x, lin_c) - D.theta < 0.0f) mask |= 1ull << bit;
+      }
+      if (!mask) continue;
+      atomicAnd(q + CB_CLAIMED + w, ~mask);
+      atomicAnd(q + CB_REACHED + w, ~mask);
+      atomicOr(q + CB_NOW + w, mask);
+      n += (uint32_t)__popcll(mask);
+      if (D.gcnt) {
+        unsigned long long mm = mask;
+        while (mm) {
+          const int bit = __ffsll((long long)mm) - 1;
+          mm &= mm - 1ull;
+          const uint32_t cell =
+              deposit_cell(D, G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + w);
+          if (cell != NIL) atomicSub(&D.gcnt[cell], 1u);
+        }
+      }
+    }
+    if (!n) continue;
+    atomicSub(&D.greach[g], n);
+    melted += n;
+    D.mslots[atomicAdd(&D.cnt->n_melt_slots, 1u)] = (uint32_t)slot;
+  }
+  if (melted) atomicAdd(&s_melted, melted);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_melted) atomicAdd(&D.cnt->melted, (unsigned long long)s_melted);
+}
+
+// Reached bit of site (sx, sy, sz) of grain g: from the given slot's words
+// when the site is in that slot's brick, else through the hash.
+__device__ __forceinline__ bool reached_at(const Dev& D, uint32_t g, uint64_t own_key,
+                                           const unsigned long long* own, int sx, int sy, int sz) {
+  const uint64_t key = claim_key(g, sx, sy, sz);
+  const unsigned long long* q = own;
+  if (key != own_key) {
+    const int64_t slot = claim_find(D, key);
+    if (slot < 0) return false;
+    q = D.cbits + (size_t)slot * 24;
+  }
+  const uint32_t b = site_bit(sx, sy, sz);
+  return (load_relaxed(q + CB_REACHED + (b >> 6)) >> (b & 63)) & 1ull;
+}
+
+// One lane per listed slot: each site melted in this step is re-approached
+// from its first reached neighbour; the slot's marks are cleared.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_walkback(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (dead(D)) return;
+  __shared__ uint32_t s_new;
+  if (threadIdx.x == 0) s_new = 0;
+  __syncthreads();
+  uint32_t made = 0;
+  const uint32_t n = D.cnt->n_melt_slots;
+  for (uint32_t k = V.b * TPB + threadIdx.x; k < n; k += V.G * TPB) {
+    const uint64_t slot = D.mslots[k];
+    const unsigned long long key = D.ckeys[slot];
+    unsigned long long* q = D.cbits + slot * 24;
+    const uint32_t g = (uint32_t)(key >> 36);
+    const int bx = (int)((key >> 24) & 0xFFFull) - 2048;
+    const int by = (int)((key >> 12) & 0xFFFull) - 2048;
+    const int bz = (int)(key & 0xFFFull) - 2048;
+    for (int w = 0; w < 8; ++w) {
+      const unsigned long long mm = load_relaxed(q + CB_NOW + w);
+      if (!mm) continue;
+      unsigned long long m = mm, claim = 0;
+      while (m) {
+        const int bit = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const int T[3] = {bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + w};
+        for (int d = 0; d < 6; ++d) {
+          const int a = d >> 1, sg = (d & 1) ? -1 : 1;
+          const int sx = T[0] - (a == 0 ? sg : 0), sy = T[1] - (a == 1 ? sg : 0),
+                    sz = T[2] - (a == 2 ? sg : 0);
+          if (!reached_at(D, g, key, q, sx, sy, sz)) continue;
+          const uint32_t j = atomicAdd(&D.cnt->n_active, 1u);
+          if (j >= D.cap_p) {
+            // No room: the count is taken back (it bounds every reader of A).
+            atomicSub(&D.cnt->n_active, 1u);
+            atomicOr(&D.cnt->err, ERR_CAPACITY);
+          } else {
+            D.A[j] = make_rec(0.0f, g, d, sx, sy, sz, ST_ACTIVE);
+            if (D.tagA) D.tagA[j] = NIL;
+            atomicAdd(&D.cnt->n_live, 1u);
+            claim |= 1ull << bit;
+            made += 1;
+          }
+          break;
+        }
+      }
+      if (claim) atomicOr(q + CB_CLAIMED + w, claim);
+      atomicAnd(q + CB_NOW + w, ~mm);
+    }
+  }
+  if (made) atomicAdd(&s_new, made);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_new) atomicAdd(&D.cnt->reactivated, (unsigned long long)s_new);
+}
+
+// Grains left without reached sites have melted entirely: their nucleation
+// sites are dormant again.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_melt_grains(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (dead(D)) return;
+  const uint32_t ng = D.cnt->n_grains;
+  for (uint32_t g = V.b * TPB + threadIdx.x; g < ng; g += V.G * TPB) {
+    if (D.gdead[g] || D.greach[g] != 0u) continue;
+    D.gdead[g] = 1u;
+    atomicAdd(&D.cnt->grains_melted, 1ull);
+    const int32_t si = D.gsite[g];
+    if (si >= 0) D.sstate[si] = SITE_DORMANT;
+  }
+  if (V.b == 0 && threadIdx.x == 0) D.cnt->n_melt_slots = 0;
+}
+
+// Stopped particles whose departure site melted are removed: the record is
+// retired and its position made NaN, so that no test meets it; the re-sort
+// drops it.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_melt_stopped(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (dead(D)) return;
+  const float lin_c = lin_const(D);
+  __shared__ uint32_t s_rm;
+  if (threadIdx.x == 0) s_rm = 0;
+  __syncthreads();
+  uint32_t rm = 0;
+  const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
+  for (uint32_t j = V.b * TPB + threadIdx.x; j < n; j += V.G * TPB) {
+    const uint4 r = D.S[j];
+    if ((rec_fl(r) & 3u) == ST_RETIRED) continue;
+    const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
+    if (!departure_melted(D, G, rec_sx(r), rec_sy(r), rec_sz(r), lin_c)) continue;
+    D.S[j] = with_fl(r, ST_RETIRED);
+    const float nan = __uint_as_float(0x7FC00000u);
+    D.PS[j] = make_float4(nan, nan, nan, __uint_as_float(rec_grain(r)));
+    rm += 1;
+  }
+  if (rm) atomicAdd(&s_rm, rm);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_rm) atomicAdd(&D.cnt->removed, (unsigned long long)s_rm);
+}
+
+// Reached sites of every grain from the claim hash; grains with none are
+// marked melted, and with melting on every engulfed site is tested again.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_count_reached(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  const uint64_t slots = D.cmask + 1;
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < slots; v += (uint64_t)V.G * TPB) {
+    const unsigned long long key = D.ckeys[v];
+    if (key == CLAIM_EMPTY) continue;
+    uint32_t n = 0;
+    for (int w = 0; w < 8; ++w) n += (uint32_t)__popcll(D.cbits[v * 24 + CB_REACHED + w]);
+    if (n) atomicAdd(&D.greach[(uint32_t)(key >> 36)], n);
+  }
+}
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_count_finish(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  const uint32_t ng = D.cnt->n_grains;
+  for (uint32_t g = V.b * TPB + threadIdx.x; g < ng; g += V.G * TPB) D.gdead[g] = D.greach[g] == 0u;
+  if (D.melting)
+    for (uint32_t i = V.b * TPB + threadIdx.x; i < D.n_sites; i += V.G * TPB)
+      if (D.sstate[i] == SITE_ENGULFED) D.sstate[i] = SITE_DORMANT;
 }
 
 // --------------------------------------------------------- init / load ----
@@ -2032,6 +2377,7 @@ __global__ __launch_bounds__(TPB) void k_claim_ball(Bind Bd, uint32_t g, int32_t
     const int z = (int)(v / ((uint64_t)w * w)) - r;
     if (abs(x) + abs(y) + abs(z) <= r) {
       claim_or(D, g, x, y, z, M_CLAIMED | M_REACHED);
+      atomicAdd(&D.greach[g], 1u);
       if (D.gcnt) deposit_site(D, D.gtab + (size_t)g * GT_STRIDE, x, y, z);
     }
   }
@@ -2116,7 +2462,7 @@ __global__ __launch_bounds__(TPB) void k_export_particles(Bind Bd, uint32_t* cou
       take = (rec_fl(r) & 3u) == ST_ACTIVE;
     } else if (k < na + ns) {
       r = D.S[k - na];
-      take = true;
+      take = (rec_fl(r) & 3u) != ST_RETIRED;  // removed by melting
       st = ST_STOPPED;
     }
     if (take && win.on) take = in_window(win, rec_pos(D, r));
@@ -2494,7 +2840,10 @@ __global__ __launch_bounds__(TPB) void k_digest(Bind Bd, unsigned long long* out
     const uint4 r = D.A[i];
     if ((rec_fl(r) & 3u) == ST_ACTIVE) a += rec_digest(r);
   }
-  for (uint32_t j = V.b * TPB + threadIdx.x; j < ns; j += V.G * TPB) b += rec_digest(D.S[j]);
+  for (uint32_t j = V.b * TPB + threadIdx.x; j < ns; j += V.G * TPB) {
+    const uint4 r = D.S[j];
+    if ((rec_fl(r) & 3u) != ST_RETIRED) b += rec_digest(r);
+  }
   for (uint64_t k = (uint64_t)V.b * TPB + threadIdx.x; k <= D.cmask; k += (uint64_t)V.G * TPB) {
     const unsigned long long key = D.ckeys[k];
     if (key == CLAIM_EMPTY) continue;
@@ -2602,6 +2951,20 @@ void launch_deposit_all(const Dev& d, hipStream_t s) {
 void launch_mushy_fraction(const uint32_t* cnt, uint64_t n, double site_over_cell, float* out,
                            hipStream_t s) {
   k_mushy_fraction<<<grid_for(n, 8192), TPB, 0, s>>>(cnt, n, site_over_cell, out);
+}
+void launch_melt(const Dev& d, hipStream_t s) {
+  if (d.fkind == F_GRID || d.fkind == F_ROSENTHAL)
+    k_field_cellmin<<<grid_for((uint64_t)(d.fn[0] - 1) * (d.fn[1] - 1) * (d.fn[2] - 1), 8192), TPB, 0,
+                      s>>>(Plain{d});
+  k_melt_sites<<<grid_for(d.cmask + 1, 16384), TPB, 0, s>>>(Plain{d});
+  k_walkback<<<1024, TPB, 0, s>>>(Plain{d});
+  k_melt_grains<<<grid_for(d.cap_grains, 256), TPB, 0, s>>>(Plain{d});
+  k_melt_stopped<<<STREAM_GRID, TPB, 0, s>>>(Plain{d});
+}
+void launch_count_reached(const Dev& d, hipStream_t s) {
+  (void)hipMemsetAsync(d.greach, 0, 4 * (size_t)d.cap_grains, s);
+  k_count_reached<<<grid_for(d.cmask + 1, 16384), TPB, 0, s>>>(Plain{d});
+  k_count_finish<<<grid_for(std::max<uint64_t>(d.cap_grains, d.n_sites), 256), TPB, 0, s>>>(Plain{d});
 }
 void launch_init_workspace(const Dev& d, hipStream_t s) {
   k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});

@@ -34,7 +34,7 @@ struct Geometry {
 struct Layout {
   size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
       bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
-      stab, sstate, cand, fgrid, gcnt, cnt, dig, total;
+      stab, sstate, cand, fgrid, gcnt, fcmin, mslots, greach, gsite, gdead, cnt, dig, total;
 };
 
 uint64_t next_pow2(uint64_t v) {
@@ -146,6 +146,11 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.cand = put(4 * (uint64_t)std::max(p->cap_sites, 1));
   L.fgrid = put(4 * std::max<uint64_t>(g.field_nodes, 8));
   L.gcnt = put(4 * std::max<uint64_t>(g.field_nodes, 8));
+  L.fcmin = put(4 * std::max<uint64_t>(g.field_nodes, 8));
+  L.mslots = put(4 * g.slots);
+  L.greach = put(4 * (uint64_t)p->cap_grains);
+  L.gsite = put(4 * (uint64_t)p->cap_grains);
+  L.gdead = put(4 * (uint64_t)p->cap_grains);
   L.cnt = put(sizeof(ge::Counters));
   L.dig = put(64);
   L.total = off;
@@ -204,6 +209,7 @@ struct ge_ctx {
   // mushy-zone deposition grid (nodes 0: off) and the volume of its cells
   uint64_t dep_nodes = 0;
   double dep_cell_volume = 0.0;
+  std::vector<double> site_xyz;  // registered nucleation sites (grain-to-site link of loaded states)
   bool dead;
   std::string err;
   // phase timing
@@ -322,6 +328,9 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.cbits, 0, 192 * g.slots, s));
   HIPCHK(c, hipMemsetAsync(w + L.cnt, 0, sizeof(ge::Counters), s));
   HIPCHK(c, hipMemsetAsync(w + L.cand, 0, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
+  HIPCHK(c, hipMemsetAsync(w + L.greach, 0, 4 * (uint64_t)c->p.cap_grains, s));
+  HIPCHK(c, hipMemsetAsync(w + L.gsite, 0xFF, 4 * (uint64_t)c->p.cap_grains, s));
+  HIPCHK(c, hipMemsetAsync(w + L.gdead, 0, 4 * (uint64_t)c->p.cap_grains, s));
   ge::launch_init_workspace(c->d, s);  // also starts the step stamps at 1
   HIPCHK(c, hipGetLastError());
   return GE_OK;
@@ -404,6 +413,11 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.fkind = ge::F_UNIFORM;
   d.fdT = 0.0f;
   d.fgrid = (float*)(w + L.fgrid);
+  d.fcmin = (float*)(w + L.fcmin);
+  d.mslots = (uint32_t*)(w + L.mslots);
+  d.greach = (uint32_t*)(w + L.greach);
+  d.gsite = (int32_t*)(w + L.gsite);
+  d.gdead = (uint32_t*)(w + L.gdead);
   d.gtab = (float*)(w + L.gtab);
   d.gbox = (int32_t*)(w + L.gbox);
   d.cap_grains = (uint32_t)p->cap_grains;
@@ -665,6 +679,7 @@ ge_status ge_nucleate(ge_ctx* c, int32_t n, const double* xyz, const double* dT_
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->n_sites += (uint32_t)n;
   c->d.n_sites = c->n_sites;
+  c->site_xyz.insert(c->site_xyz.end(), xyz, xyz + 3 * (size_t)n);
   ge_status st = sync_dev(c);
   if (st != GE_OK) return st;
   return GE_OK;
@@ -690,6 +705,10 @@ static void fill_stats(ge_ctx* c, ge_step_stats* st) {
   st->step = (int64_t)H.step;
   st->pair_tests = (int64_t)H.pair_tests;
   st->dirty_tests = (int64_t)H.dirty_tests;
+  st->melted = (int64_t)H.melted;
+  st->removed = (int64_t)H.removed;
+  st->reactivated = (int64_t)H.reactivated;
+  st->grains_melted = (int64_t)H.grains_melted;
 }
 
 ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
@@ -734,6 +753,8 @@ static void step_once(ge_ctx* c, double dt) {
   if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
   prof_mark(c, -1);
   if (c->field.kind == GE_FIELD_ROSENTHAL) ge::launch_resample(d, s);
+  // Melting uses the field of this step.
+  if (d.melting) ge::launch_melt(d, s);
   prof_mark(c, 0);
   ge::launch_advance(d, (float)dt, s);
   prof_mark(c, 1);
@@ -1131,8 +1152,17 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
                             S.site[3 * i + 2],
                             S.state[i] == GE_STOPPED ? ge::ST_STOPPED : ge::ST_ACTIVE));
   }
+  // A grain whose centre is the position of a fired site came from that
+  // site (it returns to it if it melts entirely).
+  std::vector<int32_t> gsite((size_t)S.n_grains, -1);
+  for (int32_t g = 0; g < S.n_grains; ++g)
+    for (uint32_t i = 0; i < c->n_sites && gsite[g] < 0; ++i)
+      if (S.site_state[i] == GE_SITE_FIRED && c->site_xyz[3 * i] == S.centre[3 * g] &&
+          c->site_xyz[3 * i + 1] == S.centre[3 * g + 1] && c->site_xyz[3 * i + 2] == S.centre[3 * g + 2])
+        gsite[g] = (int32_t)i;
   if (!rows.empty()) {
     HIPCHK(c, hipMemcpyAsync(c->d.gtab, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d.gsite, gsite.data(), gsite.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->d.gbox, boxes.data(), boxes.size() * 4, hipMemcpyHostToDevice, s));
   }
   if (!recs.empty())
@@ -1173,10 +1203,25 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
     HIPCHK(c, hipMemsetAsync(c->d.gcnt, 0, 4 * c->dep_nodes, s));
     ge::launch_deposit_all(c->d, s);
   }
+  // Reached sites per grain of the loaded claims.
+  ge::launch_count_reached(c->d, s);
   HIPCHK(c, hipGetLastError());
   st = read_counters(c);
   if (st != GE_OK) return st;
   return error_status(c, c->host_cnt->err);
+}
+
+ge_status ge_set_melting(ge_ctx* c, int32_t on) {
+  if (!c) return GE_EINVAL;
+  if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
+  if (on && c->adj.valid && c->d.tagA) return fail(c, GE_ESTATE, "an adjoint run is being recorded");
+  c->d.melting = on ? 1 : 0;
+  // Reached sites per grain (kept step by step while melting is on).
+  if (on) {
+    ge::launch_count_reached(c->d, c->stream);
+    HIPCHK(c, hipGetLastError());
+  }
+  return sync_dev(c);
 }
 
 ge_status ge_set_deposition_grid(ge_ctx* c, const int32_t n[3], const double origin[3],
@@ -1279,6 +1324,7 @@ ge_status ge_adjoint_forward(ge_ctx* c, double dt, int32_t n_steps, int32_t ckpt
     return fail(c, GE_EINVAL, "bad adjoint arguments");
   if (((uintptr_t)workspace) % ALIGN) return fail(c, GE_EINVAL, "adjoint workspace not 256-byte aligned");
   if (c->d.branching) return fail(c, GE_EINVAL, "the recorded run needs branching off");
+  if (c->d.melting) return fail(c, GE_EINVAL, "the recorded run needs melting off");
   if (c->field.kind == GE_FIELD_ROSENTHAL)
     return fail(c, GE_EINVAL, "the recorded run needs a field that is fixed in time (not ROSENTHAL)");
   ge_ctx::Adj A;
@@ -1562,6 +1608,7 @@ ge_status batch_bind(ge_batch* b) {
     t.sched[ge::TK_ADVANCE] = sa;
     t.sched[ge::TK_CONTAIN] = sc;
     if (t.tagA || t.tagB) return bfail(b, GE_ESTATE, "a member is recording an adjoint run");
+    if (t.melting) return bfail(b, GE_EINVAL, "melting is not available in batched steps");
 #define GE_TO_OFFSET(f) \
     t.f = t.f ? (decltype(t.f))((uintptr_t)((char*)t.f - b->base)) : (decltype(t.f))ge::NULL_OFFSET;
     GE_DEV_POINTERS(GE_TO_OFFSET)

@@ -58,7 +58,7 @@ int main(void) {
   F(ge_params, field_n) F(ge_params, resort_every)
   F(ge_field, data) F(ge_field, data_on_device) F(ge_field, q) F(ge_field, dT_min)
   F(ge_field, T) F(ge_field, w) F(ge_field, liq_T) F(ge_field, liq_m)
-  F(ge_step_stats, max_step) F(ge_step_stats, dirty_tests)
+  F(ge_step_stats, max_step) F(ge_step_stats, dirty_tests) F(ge_step_stats, grains_melted)
   F(ge_particle_rec, grain) F(ge_particle_rec, dir) F(ge_particle_rec, cell)
   F(ge_state_in, n_particles) F(ge_state_in, c_flags) F(ge_state_in, step)
   return 0;

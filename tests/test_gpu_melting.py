@@ -1,0 +1,172 @@
+"""Melting by walk-back on the GPU (Sec. 2.1.3): a lattice ball cut by a
+plane against the FP64 oracle (claims and particles as sets, exactly), a
+grain melted entirely, a site that fires, melts and fires again, a CET run
+under the moving source with melting on against the oracle's run, recorded
+sequences against plain steps, and the paths where melting is refused."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2504_12858_amd import binding as B
+from paper_2504_12858_amd import workloads as W
+from tests.gpu_helpers import (context_for, gpu_claims, gpu_parts, orc_claims, orc_parts,
+                               require_gpu)
+
+pytestmark = pytest.mark.gpu
+
+LAM = 5e-6
+C = np.array([5e-4, 5e-4, 5e-4])
+BOX = ((0.0, 0.0, 0.0), (1e-3, 1e-3, 1e-3))
+
+
+def _ctx(field, **kw):
+    p = B.make_params(BOX[0], BOX[1], LAM, LAM, LAM, W.KIN_A, W.KIN_B, cap_particles=1 << 18,
+                      cap_stopped=1 << 18, cap_claim_bricks=1 << 14, **kw)
+    ctx = B.Context(p)
+    ctx.set_thermal_field(field)
+    return ctx
+
+
+def _orc(field):
+    o = Oracle(BOX[0], BOX[1], LAM, LAM, LAM, W.KIN_A, W.KIN_B)
+    o.set_field(field)
+    return o
+
+
+def _claim_set(c):
+    return {(int(g), tuple(s), int(f)) for g, s, f in zip(c["grain"], np.asarray(c["site"]).tolist(),
+                                                         c["flags"])}
+
+
+def _part_set(p):
+    keep = np.asarray(p["state"]) != 2
+    return {(int(g), tuple(s), int(d), int(st)) for g, s, d, st in
+            zip(np.asarray(p["grain"])[keep], np.asarray(p["site"])[keep].tolist(),
+                np.asarray(p["dir"])[keep], np.asarray(p["state"])[keep])}
+
+
+def test_plane_cut_matches_the_oracle():
+    require_gpu()
+    r, cut, G = 8, 3, 1e4
+    x_cut = C[0] + (cut + 0.5) * LAM
+    f = W.Field(W.FIELD_LINEAR, dT0=G * x_cut, grad=(-G, 0.0, 0.0), rate=0.0)
+    q = np.array([[1.0, 0, 0, 0]])
+    ctx = _ctx(f)
+    ctx.init_grains(C[None, :], q, np.array([r], np.int32))
+    ctx.set_melting(True)
+    st = ctx.step(1e-4, 1)
+    o = _orc(f)
+    o.init_grains(C[None, :], q, np.array([r], np.int32))
+    o.set_melting(True)
+    o.step(1e-4, 1)
+    ms = o.melt_stats()
+    print(f"melted {st['melted']} removed {st['removed']} reactivated {st['reactivated']} "
+          f"oracle {ms}", flush=True)
+    assert (st["melted"], st["removed"], st["reactivated"], st["grains_melted"]) == \
+        (ms["melted"], ms["removed"], ms["reactivated"], ms["grains_melted"])
+    assert ms["melted"] > 50 and ms["reactivated"] > 10
+    gc, _ = gpu_claims(ctx)
+    oc, _ = orc_claims(o)
+    assert _claim_set(gc) == _claim_set(oc)
+    gp, _ = gpu_parts(ctx)
+    op, _ = orc_parts(o)
+    assert _part_set(gp) == _part_set(op)
+    ctx.close()
+
+
+def test_uniform_superheat_melts_the_grain():
+    require_gpu()
+    ctx = _ctx(W.Field(W.FIELD_UNIFORM, dT=-1.0))
+    ctx.init_grains(C[None, :], np.array([[1.0, 0, 0, 0]]), np.array([5], np.int32))
+    ctx.set_melting(True)
+    st = ctx.step(1e-4, 1)
+    ball = 11 * (2 * 25 + 10 + 3) // 3
+    assert st["melted"] == ball and st["grains_melted"] == 1 and st["reactivated"] == 0
+    assert st["n_active"] == 0
+    assert len(ctx.claims()) == 0
+    ctx.close()
+
+
+def test_melted_site_fires_again():
+    require_gpu()
+    ctx = _ctx(W.Field(W.FIELD_UNIFORM, dT=5.0), cap_sites=4)
+    ctx.nucleate(C[None, :], np.array([1.0]), np.array([[1.0, 0, 0, 0]]))
+    ctx.set_melting(True)
+    ctx.step(1e-4, 1)
+    assert list(ctx.site_states()) == [1]
+    ctx.set_thermal_field(W.Field(W.FIELD_UNIFORM, dT=-1.0))
+    st = ctx.step(1e-4, 1)
+    assert st["grains_melted"] == 1
+    assert list(ctx.site_states()) == [0]
+    ctx.set_thermal_field(W.Field(W.FIELD_UNIFORM, dT=5.0))
+    st = ctx.step(1e-4, 1)
+    assert list(ctx.site_states()) == [1]
+    assert st["n_grains"] == 2 and st["n_active"] == 6
+    assert set(ctx.claims()["grain"].tolist()) == {1}
+    ctx.close()
+
+
+def _cet():
+    return W.cet(seed=3, size=(0.4e-3, 0.2e-3, 0.1e-3), lambda0=4e-6, grid_n=24, dT0=6.0,
+                 rate=2.0, bulk_density=2e12, face_density=2e8, dt=1.5e-3, n_steps=300,
+                 U=0.005, q=0.004)
+
+
+def test_cet_with_melting_matches_the_oracle():
+    """The moving source melts what grew under it; the grain maps of the HIP
+    path and the oracle agree."""
+    require_gpu()
+    w = _cet()
+    ctx = context_for(w)
+    ctx.set_melting(True)
+    st = ctx.step(w.dt, w.n_steps)
+    o = Oracle.from_workload(w)
+    o.set_melting(True)
+    melted = 0
+    for _ in range(w.n_steps):
+        o.step(w.dt, 1)
+        melted += o.melt_stats()["melted"]
+    assert o.error == 0
+    print(f"gpu melted {st['melted']} removed {st['removed']} reactivated {st['reactivated']} "
+          f"grains {st['grains_melted']}; oracle melted {melted}", flush=True)
+    assert st["melted"] > 1000
+    assert abs(st["melted"] - melted) <= 0.01 * melted
+    vox = 4e-6
+    n = [int(round((h - l) / vox)) for l, h in zip(w.lo, w.hi)]
+    gm = ctx.grain_map(n, w.lo, [vox] * 3)
+    om = o.grain_map(np.array(n, np.int32), np.array(w.lo), np.array([vox] * 3))
+    agree = (gm == om).mean()
+    print(f"map agreement {agree:.6f} solid {(om > 0).mean():.3f}", flush=True)
+    assert agree >= 0.999
+    ctx.close()
+
+
+def test_melting_replays_equal_plain_steps():
+    require_gpu()
+    w = _cet()
+    a, b = context_for(w), context_for(w)
+    b.use_graphs(False)
+    for c in (a, b):
+        c.set_melting(True)
+    for n in (40, 33, 64):
+        sa, sb = a.step(w.dt, n), b.step(w.dt, n)
+        sa.pop("pair_tests")
+        sb.pop("pair_tests")
+        assert sa == sb
+    pa, _ = gpu_parts(a)
+    pb, _ = gpu_parts(b)
+    assert pa.tobytes() == pb.tobytes()
+    a.close()
+    b.close()
+
+
+def test_melting_refused_where_unsupported():
+    require_gpu()
+    w = _cet()
+    batch = B.Batch([B.params_from_workload(w, cap_particles=1 << 20, cap_stopped=1 << 20,
+                                            cap_claim_bricks=1 << 16)])
+    batch.members[0].init_from_workload(w)
+    batch.members[0].set_melting(True)
+    with pytest.raises(B.GrainEnvError):
+        batch.step(w.dt, 2)
+    batch.close()
