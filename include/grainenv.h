@@ -213,7 +213,7 @@ typedef struct ge_state_in {
   const int32_t* grain;    /* [n] */
   const int32_t* site;     /* [n][3] */
   const int32_t* dir;      /* [n] */
-  const float* s;          /* [n] */
+  const float* s;          /* [n] travel, finite, 0 <= s < 2 lambda0 (EINVAL otherwise) */
   const int32_t* state;    /* [n] GE_ACTIVE / GE_STOPPED (GE_RETIRED entries are dropped) */
   int64_t n_claims;
   const int32_t* c_grain;  /* [m] */

@@ -128,6 +128,7 @@ struct Dev {
   // melting (walk-back; melting = 0: off)
   int32_t melting;
   float* fcmin;        // [field cells] least node value of each cell of a node grid
+  float* fcoarse;      // [coarse cells] least of fcmin over blocks of 4 x 4 x 4 cells
   uint32_t* mslots;    // [claim slots] slots with sites melted this step
   uint32_t* greach;    // [cap_grains] reached sites of each grain (kept while melting)
   int32_t* gsite;      // [cap_grains] nucleation site of each grain, -1: none
@@ -181,12 +182,16 @@ struct Dev {
   // claims
   unsigned long long* ckeys;   // [slots]
   unsigned long long* cbits;   // [slots][3][8]: claimed, reached, now
+  unsigned long long* clist;   // [slots] keys of the occupied slots in insertion order
+                               //  (claim_used of them)
   uint64_t cmask;              // slots - 1
   uint32_t claim_limit;        // occupancy limit of the hash
   // sites
   float* stab;         // [cap_sites][GT_STRIDE], [3] = nucleation undercooling
   uint32_t* sstate;    // [cap_sites]
   uint32_t* cand;      // [cap_sites]
+  uint32_t* sgrain;    // [cap_sites] with melting: grain whose claims covered the site at its
+                       //  last test (a hint; NIL or stale values only cost the full search)
   uint32_t n_sites;
   // counters
   Counters* cnt;
@@ -211,11 +216,11 @@ struct Dev {
 // Every pointer member of Dev (a batched launch stores them as offsets from
 // the batch workspace and rebuilds them on the device).
 #define GE_DEV_POINTERS(X)                                                                   \
-  X(fgrid) X(gcnt) X(fcmin) X(mslots) X(greach) X(gsite) X(gdead) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
+  X(fgrid) X(gcnt) X(fcmin) X(fcoarse) X(mslots) X(greach) X(gsite) X(gdead) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \
-  X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(stab) X(sstate) X(cand) X(cnt) X(tagA)      \
+  X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(clist) X(stab) X(sstate) X(cand) X(sgrain) X(cnt) X(tagA)      \
   X(tagB) X(adj_rec) X(adj_nact) X(adj_sfin) X(adj_ck) X(adj_linc)
 constexpr uintptr_t NULL_OFFSET = ~(uintptr_t)0;
 

@@ -249,7 +249,8 @@ __device__ int64_t claim_get(const Dev& D, uint64_t key) {
       }
       unsigned long long prev = atomicCAS(&D.ckeys[idx], CLAIM_EMPTY, (unsigned long long)key);
       if (prev == CLAIM_EMPTY) {
-        atomicAdd(&D.cnt->claim_used, 1u);
+        // One count per slot taken, so the list index stays below the slots.
+        D.clist[atomicAdd(&D.cnt->claim_used, 1u)] = key;
         return (int64_t)idx;
       }
       if (prev == key) return (int64_t)idx;
@@ -325,21 +326,27 @@ __device__ __forceinline__ void deposit_site(const Dev& D, const float* __restri
   if (c != NIL) atomicAdd(&D.gcnt[c], 1u);
 }
 
-// Lower bound of the undercooling field (without theta) over the box
-// [lo, hi], with a margin for the rounding of the evaluation.
-__device__ float field_lower(const Dev& D, P3 lo, P3 hi, float lin_c) {
-  if (D.fkind == F_UNIFORM) return D.fdT;
+// Whether the undercooling field minus theta can be negative somewhere in
+// the box [lo, hi]: false only when a lower bound of the field over the box
+// (with a margin for the rounding of the evaluation) is at least theta.  For
+// a node grid the bound is the least node value of the cells the box meets
+// (a trilinear interpolant lies between the least and the greatest node of
+// its cell), taken first over blocks of 4 x 4 x 4 cells from a table small
+// enough to stay in cache, then cell by cell.  Clamped coordinates and boxes
+// reaching beyond the grid are handled as the interpolation handles them.
+__device__ __forceinline__ float bound_margin(float m) { return m - 1e-5f * fabsf(m) - 1e-6f; }
+__device__ bool may_melt(const Dev& D, P3 lo, P3 hi, float lin_c) {
+  if (D.fkind == F_UNIFORM) return D.fdT - D.theta < 0.0f;
+  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
   if (D.fkind == F_LINEAR) {
-    const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
     float v = lin_c, mag = fabsf(lin_c);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       v += fminf(D.fgrad[a] * l[a], D.fgrad[a] * h[a]);
       mag += fmaxf(fabsf(D.fgrad[a] * l[a]), fabsf(D.fgrad[a] * h[a]));
     }
-    return v - 1e-5f * mag - 1e-6f;
+    return v - 1e-5f * mag - 1e-6f - D.theta < 0.0f;
   }
-  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
   int c0[3], c1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -348,11 +355,18 @@ __device__ float field_lower(const Dev& D, P3 lo, P3 hi, float lin_c) {
     c1[a] = (int)fminf(fmaxf(floorf((h[a] - D.fo[a]) * D.finv[a]), 0.0f), top);
   }
   const size_t cx = (size_t)D.fn[0] - 1, cy = (size_t)D.fn[1] - 1;
+  const size_t kx = (cx + 3) >> 2, ky = (cy + 3) >> 2;
   float m = INFINITY;
+  for (int k = c0[2] >> 2; k <= c1[2] >> 2; ++k)
+    for (int j = c0[1] >> 2; j <= c1[1] >> 2; ++j)
+      for (int i = c0[0] >> 2; i <= c1[0] >> 2; ++i)
+        m = fminf(m, D.fcoarse[((size_t)k * ky + j) * kx + i]);
+  if (bound_margin(m) - D.theta >= 0.0f) return false;
+  m = INFINITY;
   for (int k = c0[2]; k <= c1[2]; ++k)
     for (int j = c0[1]; j <= c1[1]; ++j)
       for (int i = c0[0]; i <= c1[0]; ++i) m = fminf(m, D.fcmin[((size_t)k * cy + j) * cx + i]);
-  return m - 1e-5f * fabsf(m) - 1e-6f;
+  return bound_margin(m) - D.theta < 0.0f;
 }
 
 // Undercooling at the departure site of a record is negative (the site
@@ -360,8 +374,7 @@ __device__ float field_lower(const Dev& D, P3 lo, P3 hi, float lin_c) {
 __device__ __forceinline__ bool departure_melted(const Dev& D, const float* __restrict__ G,
                                                  int sx, int sy, int sz, float lin_c) {
   const P3 x = lattice_pos(G, sx, sy, sz, 0, 0.0f);
-  if (field_lower(D, x, x, lin_c) - D.theta >= 0.0f) return false;
-  return field_at(D, x, lin_c) - D.theta < 0.0f;
+  return may_melt(D, x, x, lin_c) && field_at(D, x, lin_c) - D.theta < 0.0f;
 }
 
 // Rounded lattice position of world point y in grain G (crystal frame).
@@ -1772,6 +1785,16 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Bind Bd) {
 }
 
 // ----------------------------------------------------------- nucleation ---
+// Site position y lies on a claimed or reached lattice site of grain g.
+__device__ __forceinline__ bool covers(const Dev& D, uint32_t g, P3 y, float inv_l) {
+  int l[3];
+  lattice_round(D.gtab + (size_t)g * GT_STRIDE, inv_l, y, l);
+  const int32_t* bb = D.gbox + (size_t)g * 6;
+  if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] || l[2] > bb[5])
+    return false;
+  return claim_test(D, g, l[0], l[1], l[2], M_CLAIMED | M_REACHED);
+}
+
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_nuc_test(Bind Bd) {
   Dev D;
@@ -1788,19 +1811,21 @@ __global__ __launch_bounds__(TPB) void k_nuc_test(Bind Bd) {
     const P3 y = {T[0], T[1], T[2]};
     const float dT = field_at(D, y, lin_c) - D.theta;
     if (!(dT >= T[3])) continue;
+    // With melting claims shrink, so an engulfed site is tested again every
+    // step, first against the grain that covered it at its last test.
+    const uint32_t hint = D.melting ? D.sgrain[i] : NIL;
+    if (hint < ng && covers(D, hint, y, inv_l)) continue;
     bool claimed = false;
-    for (uint32_t g = 0; g < ng && !claimed; ++g) {
-      int l[3];
-      lattice_round(D.gtab + (size_t)g * GT_STRIDE, inv_l, y, l);
-      const int32_t* bb = D.gbox + (size_t)g * 6;
-      if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] ||
-          l[2] > bb[5])
-        continue;
-      claimed = claim_test(D, g, l[0], l[1], l[2], M_CLAIMED | M_REACHED);
-    }
+    uint32_t g = 0;
+    for (; g < ng; ++g)
+      if (g != hint && covers(D, g, y, inv_l)) {
+        claimed = true;
+        break;
+      }
     if (claimed) {
       // Without melting claims never shrink: the site can never fire.
       if (!D.melting) D.sstate[i] = SITE_ENGULFED;
+      else D.sgrain[i] = g;
       continue;
     }
     uint32_t tests = 0;
@@ -2094,9 +2119,49 @@ __global__ __launch_bounds__(TPB) void k_field_cellmin(Bind Bd) {
   }
 }
 
-// One lane per claim slot: the reached sites below zero undercooling melt,
-// layer by layer (a layer whose bound is not negative is skipped); a slot
-// with melted sites goes to the walk-back list.
+// Least of the cell minima over each block of 4 x 4 x 4 cells (clipped at
+// the grid's end).
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_field_coarsemin(Bind Bd) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  if (dead(D) || !(D.fkind == F_GRID || D.fkind == F_ROSENTHAL)) return;
+  const uint32_t cx = (uint32_t)D.fn[0] - 1u, cy = (uint32_t)D.fn[1] - 1u, cz = (uint32_t)D.fn[2] - 1u;
+  const uint32_t kx = (cx + 3u) >> 2, ky = (cy + 3u) >> 2, kz = (cz + 3u) >> 2;
+  const uint64_t total = (uint64_t)kx * ky * kz;
+  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total; v += (uint64_t)V.G * TPB) {
+    const uint32_t i = (uint32_t)(v % kx), j = (uint32_t)((v / kx) % ky),
+                   k = (uint32_t)(v / ((uint64_t)kx * ky));
+    float m = INFINITY;
+    for (uint32_t c = 4u * k; c < min(4u * k + 4u, cz); ++c)
+      for (uint32_t b = 4u * j; b < min(4u * j + 4u, cy); ++b)
+        for (uint32_t a = 4u * i; a < min(4u * i + 4u, cx); ++a)
+          m = fminf(m, D.fcmin[((size_t)c * cy + b) * cx + a]);
+    D.fcoarse[v] = m;
+  }
+}
+
+// Box of world positions holding every site of a brick (sites 0..7 of each
+// axis lie at most 4 lattice steps from site 3) or of one z layer of it
+// (half_z = 0), padded by half a lattice step against the rounding of the
+// site positions.
+__device__ __forceinline__ void brick_box(const float* __restrict__ G, int bx, int by, int bz,
+                                          int w, float half_z, P3& lo, P3& hi) {
+  const P3 c = lattice_pos(G, bx * 8 + 3, by * 8 + 3, bz * 8 + w, 0, 0.0f);
+  const float ex = 4.5f * (fabsf(G[13]) + fabsf(G[14])) + half_z * fabsf(G[15]);
+  const float ey = 4.5f * (fabsf(G[16]) + fabsf(G[17])) + half_z * fabsf(G[18]);
+  const float ez = 4.5f * (fabsf(G[19]) + fabsf(G[20])) + half_z * fabsf(G[21]);
+  lo = P3{c.x - ex, c.y - ey, c.z - ez};
+  hi = P3{c.x + ex, c.y + ey, c.z + ez};
+}
+
+// Occupied claim slots, from the list of their keys, in groups of 64 per
+// wave: each lane bounds the field over the brick of its key; the bricks
+// whose bound is negative are then taken one at a time by the whole wave, a
+// z layer of 64 sites per pass, one site per lane (the bit of a site in its
+// layer word is its lane).  The reached sites below zero undercooling melt;
+// a slot with melted sites goes to the walk-back list.
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_melt_sites(Bind Bd) {
   Dev D;
@@ -2104,61 +2169,71 @@ __global__ __launch_bounds__(TPB) void k_melt_sites(Bind Bd) {
   Bd.bind(D, V);
   if (dead(D)) return;
   const float lin_c = lin_const(D);
+  const int lane = lane_id();
   __shared__ uint32_t s_melted;
   if (threadIdx.x == 0) s_melted = 0;
   __syncthreads();
   uint32_t melted = 0;
-  const uint64_t slots = D.cmask + 1;
-  for (uint64_t slot = (uint64_t)V.b * TPB + threadIdx.x; slot < slots; slot += (uint64_t)V.G * TPB) {
-    const unsigned long long key = D.ckeys[slot];
-    if (key == CLAIM_EMPTY) continue;
-    const uint32_t g = (uint32_t)(key >> 36);
-    const int bx = (int)((key >> 24) & 0xFFFull) - 2048;
-    const int by = (int)((key >> 12) & 0xFFFull) - 2048;
-    const int bz = (int)(key & 0xFFFull) - 2048;
-    const float* G = D.gtab + (size_t)g * GT_STRIDE;
-    // Half-extents of a layer of 8 x 8 sites around its centre site (3, 3)
-    // (at most 4 sites away along x and y, none along z).
-    const float ex = 4.0f * (fabsf(G[13]) + fabsf(G[14]));
-    const float ey = 4.0f * (fabsf(G[16]) + fabsf(G[17]));
-    const float ez = 4.0f * (fabsf(G[19]) + fabsf(G[20]));
-    unsigned long long* q = D.cbits + slot * 24;
-    uint32_t n = 0;
-    for (int w = 0; w < 8; ++w) {
-      const unsigned long long rm = q[CB_REACHED + w];
-      if (!rm) continue;
-      const P3 c = lattice_pos(G, bx * 8 + 3, by * 8 + 3, bz * 8 + w, 0, 0.0f);
-      if (field_lower(D, P3{c.x - ex, c.y - ey, c.z - ez}, P3{c.x + ex, c.y + ey, c.z + ez},
-                      lin_c) - D.theta >= 0.0f)
-        continue;
-      unsigned long long mask = 0, m = rm;
-      while (m) {
-        const int bit = __ffsll((long long)m) - 1;
-        m &= m - 1ull;
-        const P3 x = lattice_pos(G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + w, 0,
-                                 0.0f);
-        if (field_at(D, x, lin_c) - D.theta < 0.0f) mask |= 1ull << bit;
-      }
-      if (!mask) continue;
-      atomicAnd(q + CB_CLAIMED + w, ~mask);
-      atomicAnd(q + CB_REACHED + w, ~mask);
-      atomicOr(q + CB_NOW + w, mask);
-      n += (uint32_t)__popcll(mask);
-      if (D.gcnt) {
-        unsigned long long mm = mask;
-        while (mm) {
-          const int bit = __ffsll((long long)mm) - 1;
-          mm &= mm - 1ull;
-          const uint32_t cell =
-              deposit_cell(D, G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + w);
+  const uint64_t used = min((uint64_t)D.cnt->claim_used, D.cmask + 1);
+  const uint64_t waves = (uint64_t)V.G * (TPB / 64);
+  for (uint64_t base = ((uint64_t)V.b * (TPB / 64) + (threadIdx.x >> 6)) * 64; base < used;
+       base += waves * 64) {
+    bool cand = false;
+    unsigned long long key = CLAIM_EMPTY;
+    if (base + lane < used) {
+      key = D.clist[base + lane];
+      const float* G = D.gtab + (size_t)(key >> 36) * GT_STRIDE;
+      P3 lo, hi;
+      brick_box(G, (int)((key >> 24) & 0xFFFull) - 2048, (int)((key >> 12) & 0xFFFull) - 2048,
+                (int)(key & 0xFFFull) - 2048, 3, 4.5f, lo, hi);
+      cand = may_melt(D, lo, hi, lin_c);
+    }
+    unsigned long long todo = __ballot(cand);
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const unsigned long long key_c =
+          ((unsigned long long)__shfl((uint32_t)(key >> 32), src) << 32) |
+          (unsigned long long)__shfl((uint32_t)key, src);
+      const int64_t found = claim_find(D, key_c);
+      if (found < 0) continue;  // listed keys are in the hash: never taken
+      const uint64_t slot = (uint64_t)found;
+      const uint32_t g = (uint32_t)(key_c >> 36);
+      const int bx = (int)((key_c >> 24) & 0xFFFull) - 2048;
+      const int by = (int)((key_c >> 12) & 0xFFFull) - 2048;
+      const int bz = (int)(key_c & 0xFFFull) - 2048;
+      const float* G = D.gtab + (size_t)g * GT_STRIDE;
+      unsigned long long* q = D.cbits + slot * 24;
+      uint32_t n = 0;
+      for (int w = 0; w < 8; ++w) {
+        const unsigned long long rm = q[CB_REACHED + w];
+        if (!rm) continue;
+        P3 lo, hi;
+        brick_box(G, bx, by, bz, w, 0.0f, lo, hi);
+        if (!may_melt(D, lo, hi, lin_c)) continue;
+        const int sx = bx * 8 + (lane & 7), sy = by * 8 + (lane >> 3), sz = bz * 8 + w;
+        bool melt = false;
+        if ((rm >> lane) & 1ull)
+          melt = field_at(D, lattice_pos(G, sx, sy, sz, 0, 0.0f), lin_c) - D.theta < 0.0f;
+        const unsigned long long mask = __ballot(melt);
+        if (!mask) continue;
+        if (lane == 0) {
+          atomicAnd(q + CB_CLAIMED + w, ~mask);
+          atomicAnd(q + CB_REACHED + w, ~mask);
+          atomicOr(q + CB_NOW + w, mask);
+        }
+        n += (uint32_t)__popcll(mask);
+        if (melt && D.gcnt) {
+          const uint32_t cell = deposit_cell(D, G, sx, sy, sz);
           if (cell != NIL) atomicSub(&D.gcnt[cell], 1u);
         }
       }
+      if (n && lane == 0) {
+        atomicSub(&D.greach[g], n);
+        melted += n;
+        D.mslots[atomicAdd(&D.cnt->n_melt_slots, 1u)] = (uint32_t)slot;
+      }
     }
-    if (!n) continue;
-    atomicSub(&D.greach[g], n);
-    melted += n;
-    D.mslots[atomicAdd(&D.cnt->n_melt_slots, 1u)] = (uint32_t)slot;
   }
   if (melted) atomicAdd(&s_melted, melted);
   __syncthreads();
@@ -2259,7 +2334,23 @@ __global__ __launch_bounds__(TPB) void k_melt_grains(Bind Bd) {
 
 // Stopped particles whose departure site melted are removed: the record is
 // retired and its position made NaN, so that no test meets it; the re-sort
-// drops it.
+// drops it.  The cell-sorted prefix of the store is taken brick by brick:
+// lanes bound the field over their bricks (padded by the reach of a stopped
+// particle from its departure site, under 2 lambda0; bricks on the faces of
+// the grid, which also hold the particles beyond it, reach out without
+// limit), and the records of the bricks whose bound is negative are tested
+// by the whole wave; the unsorted tail is tested record by record.
+__device__ __forceinline__ uint32_t melt_stopped_rec(const Dev& D, uint32_t j, float lin_c) {
+  const uint4 r = D.S[j];
+  if ((rec_fl(r) & 3u) == ST_RETIRED) return 0u;
+  const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
+  if (!departure_melted(D, G, rec_sx(r), rec_sy(r), rec_sz(r), lin_c)) return 0u;
+  D.S[j] = with_fl(r, ST_RETIRED);
+  const float nan = __uint_as_float(0x7FC00000u);
+  D.PS[j] = make_float4(nan, nan, nan, __uint_as_float(rec_grain(r)));
+  return 1u;
+}
+
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_melt_stopped(Bind Bd) {
   Dev D;
@@ -2267,21 +2358,49 @@ __global__ __launch_bounds__(TPB) void k_melt_stopped(Bind Bd) {
   Bd.bind(D, V);
   if (dead(D)) return;
   const float lin_c = lin_const(D);
+  const int lane = lane_id();
   __shared__ uint32_t s_rm;
   if (threadIdx.x == 0) s_rm = 0;
   __syncthreads();
   uint32_t rm = 0;
   const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
-  for (uint32_t j = V.b * TPB + threadIdx.x; j < n; j += V.G * TPB) {
-    const uint4 r = D.S[j];
-    if ((rec_fl(r) & 3u) == ST_RETIRED) continue;
-    const float* G = D.gtab + (size_t)rec_grain(r) * GT_STRIDE;
-    if (!departure_melted(D, G, rec_sx(r), rec_sy(r), rec_sz(r), lin_c)) continue;
-    D.S[j] = with_fl(r, ST_RETIRED);
-    const float nan = __uint_as_float(0x7FC00000u);
-    D.PS[j] = make_float4(nan, nan, nan, __uint_as_float(rec_grain(r)));
-    rm += 1;
+  const uint32_t ns = min(D.cnt->n_sorted, n);
+  const uint32_t nb = D.n_bricks;
+  const float h = 1.0f / D.inv_h;
+  const float pad = 2.01f * D.lambda0 + 0.01f * h;
+  constexpr float FAR = 1e30f;
+  const uint64_t waves = (uint64_t)V.G * (TPB / 64);
+  for (uint64_t base = ((uint64_t)V.b * (TPB / 64) + (threadIdx.x >> 6)) * 64; base < nb;
+       base += waves * 64) {
+    bool cand = false;
+    uint2 bs = make_uint2(0u, 0u);
+    if (base + lane < nb) {
+      const uint32_t b = (uint32_t)(base + lane);
+      bs = D.bsinfo[b];
+      if (bs.y && bs.x < ns) {
+        const int i[3] = {(int)(b % (uint32_t)D.nb[0]),
+                          (int)((b / (uint32_t)D.nb[0]) % (uint32_t)D.nb[1]),
+                          (int)(b / ((uint32_t)D.nb[0] * (uint32_t)D.nb[1]))};
+        float l[3], u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          // Cells clamp positions beyond the grid into its outer cells.
+          l[a] = i[a] == 0 ? -FAR : D.lo[a] + (float)(4 * i[a]) * h - pad;
+          u[a] = 4 * i[a] + 4 >= D.n[a] ? FAR : D.lo[a] + (float)(4 * i[a] + 4) * h + pad;
+        }
+        cand = may_melt(D, P3{l[0], l[1], l[2]}, P3{u[0], u[1], u[2]}, lin_c);
+      }
+    }
+    unsigned long long todo = __ballot(cand);
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const uint32_t start = __shfl(bs.x, src);
+      const uint32_t end = min(start + __shfl(bs.y, src), ns);
+      for (uint32_t j = start + (uint32_t)lane; j < end; j += 64u) rm += melt_stopped_rec(D, j, lin_c);
+    }
   }
+  for (uint32_t j = ns + V.b * TPB + threadIdx.x; j < n; j += V.G * TPB) rm += melt_stopped_rec(D, j, lin_c);
   if (rm) atomicAdd(&s_rm, rm);
   __syncthreads();
   if (threadIdx.x == 0 && s_rm) atomicAdd(&D.cnt->removed, (unsigned long long)s_rm);
@@ -2953,9 +3072,12 @@ void launch_mushy_fraction(const uint32_t* cnt, uint64_t n, double site_over_cel
   k_mushy_fraction<<<grid_for(n, 8192), TPB, 0, s>>>(cnt, n, site_over_cell, out);
 }
 void launch_melt(const Dev& d, hipStream_t s) {
-  if (d.fkind == F_GRID || d.fkind == F_ROSENTHAL)
-    k_field_cellmin<<<grid_for((uint64_t)(d.fn[0] - 1) * (d.fn[1] - 1) * (d.fn[2] - 1), 8192), TPB, 0,
-                      s>>>(Plain{d});
+  if (d.fkind == F_GRID || d.fkind == F_ROSENTHAL) {
+    const uint64_t c[3] = {(uint64_t)d.fn[0] - 1, (uint64_t)d.fn[1] - 1, (uint64_t)d.fn[2] - 1};
+    k_field_cellmin<<<grid_for(c[0] * c[1] * c[2], 8192), TPB, 0, s>>>(Plain{d});
+    k_field_coarsemin<<<grid_for(((c[0] + 3) >> 2) * ((c[1] + 3) >> 2) * ((c[2] + 3) >> 2), 2048),
+                        TPB, 0, s>>>(Plain{d});
+  }
   k_melt_sites<<<grid_for(d.cmask + 1, 16384), TPB, 0, s>>>(Plain{d});
   k_walkback<<<1024, TPB, 0, s>>>(Plain{d});
   k_melt_grains<<<grid_for(d.cap_grains, 256), TPB, 0, s>>>(Plain{d});

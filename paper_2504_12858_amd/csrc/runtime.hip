@@ -33,8 +33,8 @@ struct Geometry {
 
 struct Layout {
   size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
-      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, gtab, gbox,
-      stab, sstate, cand, fgrid, gcnt, fcmin, mslots, greach, gsite, gdead, cnt, dig, total;
+      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, clist, gtab, gbox,
+      stab, sstate, cand, sgrain, fgrid, gcnt, fcmin, fcoarse, mslots, greach, gsite, gdead, cnt, dig, total;
 };
 
 uint64_t next_pow2(uint64_t v) {
@@ -139,14 +139,19 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.scan_tmp = put(8 * ntiles);
   L.ckeys = put(8 * g.slots);
   L.cbits = put(192 * g.slots);
+  L.clist = put(8 * g.slots);
   L.gtab = put(4 * ge::GT_STRIDE * (uint64_t)p->cap_grains);
   L.gbox = put(24 * (uint64_t)p->cap_grains);
   L.stab = put(4 * ge::GT_STRIDE * (uint64_t)std::max(p->cap_sites, 1));
   L.sstate = put(4 * (uint64_t)std::max(p->cap_sites, 1));
   L.cand = put(4 * (uint64_t)std::max(p->cap_sites, 1));
+  L.sgrain = put(4 * (uint64_t)std::max(p->cap_sites, 1));
   L.fgrid = put(4 * std::max<uint64_t>(g.field_nodes, 8));
   L.gcnt = put(4 * std::max<uint64_t>(g.field_nodes, 8));
   L.fcmin = put(4 * std::max<uint64_t>(g.field_nodes, 8));
+  // ceil((n - 1) / 4) <= n / 2 for every n >= 2 nodes per axis, so the
+  // coarse cells number at most a eighth of the nodes.
+  L.fcoarse = put(4 * std::max<uint64_t>(g.field_nodes / 8 + 1, 8));
   L.mslots = put(4 * g.slots);
   L.greach = put(4 * (uint64_t)p->cap_grains);
   L.gsite = put(4 * (uint64_t)p->cap_grains);
@@ -328,6 +333,7 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.cbits, 0, 192 * g.slots, s));
   HIPCHK(c, hipMemsetAsync(w + L.cnt, 0, sizeof(ge::Counters), s));
   HIPCHK(c, hipMemsetAsync(w + L.cand, 0, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
+  HIPCHK(c, hipMemsetAsync(w + L.sgrain, 0xFF, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
   HIPCHK(c, hipMemsetAsync(w + L.greach, 0, 4 * (uint64_t)c->p.cap_grains, s));
   HIPCHK(c, hipMemsetAsync(w + L.gsite, 0xFF, 4 * (uint64_t)c->p.cap_grains, s));
   HIPCHK(c, hipMemsetAsync(w + L.gdead, 0, 4 * (uint64_t)c->p.cap_grains, s));
@@ -414,6 +420,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.fdT = 0.0f;
   d.fgrid = (float*)(w + L.fgrid);
   d.fcmin = (float*)(w + L.fcmin);
+  d.fcoarse = (float*)(w + L.fcoarse);
   d.mslots = (uint32_t*)(w + L.mslots);
   d.greach = (uint32_t*)(w + L.greach);
   d.gsite = (int32_t*)(w + L.gsite);
@@ -456,12 +463,14 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.occ = (uint32_t*)(w + L.occ);
   d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
   d.ckeys = (unsigned long long*)(w + L.ckeys);
+  d.clist = (unsigned long long*)(w + L.clist);
   d.cbits = (unsigned long long*)(w + L.cbits);
   d.cmask = g.slots - 1;
   d.claim_limit = (uint32_t)std::min<uint64_t>(g.slots - g.slots / 4, 0xFFFFFFFFull);
   d.stab = (float*)(w + L.stab);
   d.sstate = (uint32_t*)(w + L.sstate);
   d.cand = (uint32_t*)(w + L.cand);
+  d.sgrain = (uint32_t*)(w + L.sgrain);
   d.n_sites = 0;
   d.cnt = (ge::Counters*)(w + L.cnt);
   d.resort_every = c->resort_every;
@@ -1118,6 +1127,10 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
     if (S.state[i] != GE_ACTIVE && S.state[i] != GE_STOPPED) return fail(c, GE_EINVAL, "bad particle state");
     if (S.grain[i] < 0 || S.grain[i] >= S.n_grains || S.dir[i] < 0 || S.dir[i] > 5)
       return fail(c, GE_EINVAL, "bad particle");
+    // The travel of a live particle stays below 2 lambda0 (the CFL error
+    // stops a step before it); kernels rely on that bound.
+    if (!(S.s[i] >= 0.0f && S.s[i] < (float)(2.0 * c->p.lambda0)))
+      return fail(c, GE_EINVAL, "particle travel outside [0, 2 lambda0)");
     for (int a = 0; a < 3; ++a)
       if (std::abs(S.site[3 * i + a]) > MAX_SITE_RANGE) return fail(c, GE_EINVAL, "site out of range");
     ++n_keep;

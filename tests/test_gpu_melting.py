@@ -74,6 +74,59 @@ def test_plane_cut_matches_the_oracle():
     ctx.close()
 
 
+def _plane_field(kind, x_cut, G):
+    if kind == "linear":
+        return W.Field(W.FIELD_LINEAR, dT0=G * x_cut, grad=(-G, 0.0, 0.0), rate=0.0)
+    n, sp = (41, 41, 41), 2.5e-5
+    x = np.arange(n[0]) * sp
+    data = np.broadcast_to((G * (x_cut - x)).astype(np.float32), (n[2], n[1], n[0]))
+    return W.Field(W.FIELD_GRID, n=n, origin=(0.0, 0.0, 0.0), spacing=(sp,) * 3,
+                   data=np.ascontiguousarray(data))
+
+
+@pytest.mark.parametrize("kind", ["linear", "grid"])
+def test_plane_cut_at_the_box_face_matches_the_oracle(kind):
+    """A grain whose shell reaches through the face x = hi: the shell
+    particles beyond the face start stopped (their cells are the clamped
+    outer cells of the grid).  Steps at zero undercooling (nothing moves) run
+    until the stopped store has been sorted by cell; then the plane cut
+    melts everything past the lattice plane S_x = 0 and removes those
+    stopped particles with the rest, as in the oracle (sets compared
+    exactly)."""
+    require_gpu()
+    r, cut, G = 8, 0, 1e4
+    c = np.array([1e-3 - 3 * LAM, 5e-4, 5e-4])
+    x_cut = c[0] + (cut + 0.5) * LAM
+    f = _plane_field(kind, x_cut, G)
+    q = np.array([[1.0, 0, 0, 0]])
+    still = W.Field(W.FIELD_UNIFORM, dT=0.0)
+    ctx = _ctx(still, field_n=(41, 41, 41))
+    ctx.init_grains(c[None, :], q, np.array([r], np.int32))
+    gp0, _ = gpu_parts(ctx)
+    assert (np.asarray(gp0["state"]) == 1).sum() > 20
+    ctx.step(1e-4, 32)
+    ctx.set_thermal_field(f)
+    ctx.set_melting(True)
+    st = ctx.step(1e-4, 1)
+    o = _orc(f)
+    o.init_grains(c[None, :], q, np.array([r], np.int32))
+    o.set_melting(True)
+    o.step(1e-4, 1)
+    ms = o.melt_stats()
+    print(f"{kind}: melted {st['melted']} removed {st['removed']} reactivated {st['reactivated']} "
+          f"oracle {ms}", flush=True)
+    assert (st["melted"], st["removed"], st["reactivated"]) == \
+        (ms["melted"], ms["removed"], ms["reactivated"])
+    assert ms["removed"] > 40
+    gc, _ = gpu_claims(ctx)
+    oc, _ = orc_claims(o)
+    assert _claim_set(gc) == _claim_set(oc)
+    gp, _ = gpu_parts(ctx)
+    op, _ = orc_parts(o)
+    assert _part_set(gp) == _part_set(op)
+    ctx.close()
+
+
 def test_uniform_superheat_melts_the_grain():
     require_gpu()
     ctx = _ctx(W.Field(W.FIELD_UNIFORM, dT=-1.0))
@@ -122,15 +175,18 @@ def test_cet_with_melting_matches_the_oracle():
     st = ctx.step(w.dt, w.n_steps)
     o = Oracle.from_workload(w)
     o.set_melting(True)
-    melted = 0
+    tot = {"melted": 0, "removed": 0, "reactivated": 0}
     for _ in range(w.n_steps):
         o.step(w.dt, 1)
-        melted += o.melt_stats()["melted"]
+        ms = o.melt_stats()
+        for k in tot:
+            tot[k] += ms[k]
     assert o.error == 0
     print(f"gpu melted {st['melted']} removed {st['removed']} reactivated {st['reactivated']} "
-          f"grains {st['grains_melted']}; oracle melted {melted}", flush=True)
+          f"grains {st['grains_melted']}; oracle {tot}", flush=True)
     assert st["melted"] > 1000
-    assert abs(st["melted"] - melted) <= 0.01 * melted
+    for k in tot:
+        assert abs(st[k] - tot[k]) <= 0.01 * tot[k], k
     vox = 4e-6
     n = [int(round((h - l) / vox)) for l, h in zip(w.lo, w.hi)]
     gm = ctx.grain_map(n, w.lo, [vox] * 3)

@@ -164,6 +164,14 @@ def test_host_validation_errors():
     with pytest.raises(B.GrainEnvError) as e:
         ctx.step(-1.0, 1)
     assert e.value.status == B.GE_EINVAL
+    # A loaded particle's travel must lie in [0, 2 lambda0).
+    none = {"grain": np.zeros(0), "site": np.zeros((0, 3)), "flags": np.zeros(0)}
+    for s in (2.0 * w.lambda0, -1e-9, float("nan")):
+        parts = {"grain": [0], "site": [[0, 0, 0]], "dir": [0], "s": [s], "state": [0]}
+        with pytest.raises(B.GrainEnvError) as e:
+            ctx.load_state(np.array([w.grain_centre[0]]), np.array([[1.0, 0, 0, 0]]), parts, none,
+                           ctx.site_states(), 0.0, 0)
+        assert e.value.status == B.GE_EINVAL
 
 
 def _state_bytes(ctx):
