@@ -2255,20 +2255,23 @@ __device__ __forceinline__ bool reached_at(const Dev& D, uint32_t g, uint64_t ow
   return (load_relaxed(q + CB_REACHED + (b >> 6)) >> (b & 63)) & 1ull;
 }
 
-// One lane per listed slot: each site melted in this step is re-approached
-// from its first reached neighbour; the slot's marks are cleared.
+// One wave per listed slot, a z layer of 64 sites per pass, one site per
+// lane: each site melted in this step is re-approached from its first
+// reached neighbour; the slot's marks are cleared.
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_walkback(Bind Bd) {
   Dev D;
   VGrid V;
   Bd.bind(D, V);
   if (dead(D)) return;
+  const int lane = lane_id();
   __shared__ uint32_t s_new;
   if (threadIdx.x == 0) s_new = 0;
   __syncthreads();
   uint32_t made = 0;
   const uint32_t n = D.cnt->n_melt_slots;
-  for (uint32_t k = V.b * TPB + threadIdx.x; k < n; k += V.G * TPB) {
+  const uint32_t waves = V.G * (TPB / 64);
+  for (uint32_t k = V.b * (TPB / 64) + (threadIdx.x >> 6); k < n; k += waves) {
     const uint64_t slot = D.mslots[k];
     const unsigned long long key = D.ckeys[slot];
     unsigned long long* q = D.cbits + slot * 24;
@@ -2279,11 +2282,9 @@ __global__ __launch_bounds__(TPB) void k_walkback(Bind Bd) {
     for (int w = 0; w < 8; ++w) {
       const unsigned long long mm = load_relaxed(q + CB_NOW + w);
       if (!mm) continue;
-      unsigned long long m = mm, claim = 0;
-      while (m) {
-        const int bit = __ffsll((long long)m) - 1;
-        m &= m - 1ull;
-        const int T[3] = {bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + w};
+      bool claim = false;
+      if ((mm >> lane) & 1ull) {
+        const int T[3] = {bx * 8 + (lane & 7), by * 8 + (lane >> 3), bz * 8 + w};
         for (int d = 0; d < 6; ++d) {
           const int a = d >> 1, sg = (d & 1) ? -1 : 1;
           const int sx = T[0] - (a == 0 ? sg : 0), sy = T[1] - (a == 1 ? sg : 0),
@@ -2298,14 +2299,17 @@ __global__ __launch_bounds__(TPB) void k_walkback(Bind Bd) {
             D.A[j] = make_rec(0.0f, g, d, sx, sy, sz, ST_ACTIVE);
             if (D.tagA) D.tagA[j] = NIL;
             atomicAdd(&D.cnt->n_live, 1u);
-            claim |= 1ull << bit;
+            claim = true;
             made += 1;
           }
           break;
         }
       }
-      if (claim) atomicOr(q + CB_CLAIMED + w, claim);
-      atomicAnd(q + CB_NOW + w, ~mm);
+      const unsigned long long cm = __ballot(claim);
+      if (lane == 0) {
+        if (cm) atomicOr(q + CB_CLAIMED + w, cm);
+        atomicAnd(q + CB_NOW + w, ~mm);
+      }
     }
   }
   if (made) atomicAdd(&s_new, made);
