@@ -73,6 +73,7 @@ struct Params {
   double a[2], b[2];
   double theta;
   int32_t branching, box_exit;
+  int32_t periodic;  // bit a: axis a is periodic with period hi[a] - lo[a]
 };
 
 struct Grain {
@@ -307,6 +308,55 @@ void lattice_round(const Params& p, const Grain& g, const double y[3], int32_t o
   }
 }
 
+// ------------------------------------------------ periodic boundaries ----
+// Periodic axes (reading R16; Sec. 3.4 applies periodic conditions on the
+// faces normal to x and y): the domain repeats with period L = hi - lo.
+// Positions stay lattice-anchored and unwrapped; the field, the cell of a
+// particle, the deposition cell and the grain map take the position wrapped
+// into the box, and distances are taken between nearest periodic images.
+inline bool periodic_axis(const Params& p, int a) { return ((p.periodic >> a) & 1) != 0; }
+
+void wrap_pos(const Params& p, const double x[3], double w[3]) {
+  for (int a = 0; a < 3; ++a) {
+    w[a] = x[a];
+    if (!periodic_axis(p, a)) continue;
+    const double L = p.hi[a] - p.lo[a];
+    w[a] = x[a] - L * std::floor((x[a] - p.lo[a]) / L);
+  }
+}
+
+// Displacement from b to a between nearest images; returns whether that
+// image is not b itself (some periodic shift is non-zero).
+bool min_image(const Params& p, const double a[3], const double b[3], double d[3]) {
+  bool shifted = false;
+  for (int a_ = 0; a_ < 3; ++a_) {
+    d[a_] = a[a_] - b[a_];
+    if (!periodic_axis(p, a_)) continue;
+    const double L = p.hi[a_] - p.lo[a_];
+    const double k = std::nearbyint(d[a_] / L);
+    d[a_] -= k * L;
+    if (k != 0) shifted = true;
+  }
+  return shifted;
+}
+
+// Two particles touch (R4): within rc of each other's nearest image, and of
+// different grains or, for one grain, through a periodic image (a grain
+// that has grown around the period meets itself).
+bool touch(const Params& p, const Particle& a, const Particle& b, double rc2) {
+  double d[3];
+  const bool shifted = min_image(p, a.x, b.x, d);
+  if (a.g == b.g && !shifted) return false;
+  return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rc2;
+}
+
+// Cell index along axis a, wrapped on periodic axes (-1 if outside).
+inline int32_t stencil_index(const Params& p, const int32_t n[3], int a, int32_t i) {
+  if (i >= 0 && i < n[a]) return i;
+  if (!periodic_axis(p, a)) return -1;
+  return i < 0 ? i + n[a] : i - n[a];
+}
+
 // ---------------------------------------------------------------- cells ----
 
 struct CellIndex {
@@ -314,7 +364,9 @@ struct CellIndex {
   std::unordered_map<int64_t, std::vector<int32_t>> cells;
 };
 
-void cell_of(const Params& p, const int32_t n[3], const double x[3], int32_t c[3]) {
+void cell_of(const Params& p, const int32_t n[3], const double x_in[3], int32_t c[3]) {
+  double x[3];
+  wrap_pos(p, x_in, x);
   for (int a = 0; a < 3; ++a) {
     double u = std::floor((x[a] - p.lo[a]) / p.h);
     int64_t i = (int64_t)u;
@@ -370,15 +422,14 @@ void contain_decisions_cells(const Oracle& o, std::vector<uint8_t>& stop) {
     for (int dk = -1; dk <= 1 && !hit; ++dk)
       for (int dj = -1; dj <= 1 && !hit; ++dj)
         for (int di = -1; di <= 1 && !hit; ++di) {
-          int32_t ii = c[0] + di, jj = c[1] + dj, kk = c[2] + dk;
-          if (ii < 0 || jj < 0 || kk < 0 || ii >= ci.n[0] || jj >= ci.n[1] || kk >= ci.n[2]) continue;
+          int32_t ii = stencil_index(o.p, ci.n, 0, c[0] + di);
+          int32_t jj = stencil_index(o.p, ci.n, 1, c[1] + dj);
+          int32_t kk = stencil_index(o.p, ci.n, 2, c[2] + dk);
+          if (ii < 0 || jj < 0 || kk < 0) continue;
           auto it = ci.cells.find(cell_key(ci.n, ii, jj, kk));
           if (it == ci.cells.end()) continue;
-          for (int32_t j : it->second) {
-            const Particle& b = o.parts[j];
-            if (b.g == a.g) continue;
-            if (dist2(a.x, b.x) < rc2) { hit = true; break; }
-          }
+          for (int32_t j : it->second)
+            if (touch(o.p, a, o.parts[j], rc2)) { hit = true; break; }
         }
     stop[i] = hit ? 1 : 0;
   }
@@ -393,10 +444,23 @@ void contain_decisions_brute(const Oracle& o, std::vector<uint8_t>& stop) {
   for (int64_t i = 0; i < np; ++i) {
     const Particle& a = o.parts[i];
     if (a.state != P_ACTIVE) continue;
-    for (int64_t j = 0; j < np; ++j) {
+    // Every periodic image of every other particle (shift k L per periodic
+    // axis, |k| <= 2: unwrapped positions lie within one period of the
+    // box); a particle's own grain counts through images only.
+    int kmax[3];
+    for (int c = 0; c < 3; ++c) kmax[c] = ((o.p.periodic >> c) & 1) ? 2 : 0;
+    for (int64_t j = 0; j < np && !stop[i]; ++j) {
       const Particle& b = o.parts[j];
-      if (b.state == P_RETIRED || b.g == a.g) continue;
-      if (dist2(a.x, b.x) < rc2) { stop[i] = 1; break; }
+      if (b.state == P_RETIRED) continue;
+      for (int kz = -kmax[2]; kz <= kmax[2]; ++kz)
+        for (int ky = -kmax[1]; ky <= kmax[1]; ++ky)
+          for (int kx = -kmax[0]; kx <= kmax[0]; ++kx) {
+            if (b.g == a.g && kx == 0 && ky == 0 && kz == 0) continue;
+            const double img[3] = {b.x[0] + kx * (o.p.hi[0] - o.p.lo[0]),
+                                   b.x[1] + ky * (o.p.hi[1] - o.p.lo[1]),
+                                   b.x[2] + kz * (o.p.hi[2] - o.p.lo[2])};
+            if (dist2(a.x, img) < rc2) stop[i] = 1;
+          }
     }
   }
 }
@@ -415,7 +479,9 @@ void phase_advance(Oracle& o, double dt) {
     Particle& q = o.parts[i];
     if (q.state != P_ACTIVE) continue;
     const Grain& g = o.grains[q.g];
-    double dT = field_value(o.f, q.x, o.t) - p.theta;
+    double xw[3];
+    wrap_pos(p, q.x, xw);
+    double dT = field_value(o.f, xw, o.t) - p.theta;
     double v = velocity(p, dT);
     double d = v * dt;
     if (!std::isfinite(d)) {
@@ -444,7 +510,7 @@ void phase_box_exit(Oracle& o) {
     if (q.state != P_ACTIVE) continue;
     bool inside = true;
     for (int a = 0; a < 3; ++a)
-      if (!(q.x[a] >= p.lo[a] && q.x[a] < p.hi[a])) inside = false;
+      if (!periodic_axis(p, a) && !(q.x[a] >= p.lo[a] && q.x[a] < p.hi[a])) inside = false;
     if (!inside) { q.state = P_STOPPED; ++n; }
   }
   o.last.exited = n;
@@ -568,9 +634,10 @@ void phase_melt(Oracle& o) {
       if (!(kv.second & C_REACHED)) continue;
       int32_t S[3];
       site_of_key(kv.first, S);
-      double x[3];
+      double x[3], xw[3];
       lattice_position(p, o.grains[g], S, 0, 0.0, x);
-      if (field_value(o.f, x, o.t) - p.theta < 0) melted[g].push_back(kv.first);
+      wrap_pos(p, x, xw);
+      if (field_value(o.f, xw, o.t) - p.theta < 0) melted[g].push_back(kv.first);
     }
     std::sort(melted[g].begin(), melted[g].end());
     for (uint64_t k : melted[g]) o.claims[g].erase(k);
@@ -639,15 +706,28 @@ void phase_nucleate(Oracle& o) {
   CellIndex ci = build_cells(o);
   for (NucSite& st : o.sites) {
     if (st.state != S_DORMANT) continue;
-    double dT = field_value(o.f, st.y, o.t) - p.theta;
+    double yw[3];
+    wrap_pos(p, st.y, yw);
+    double dT = field_value(o.f, yw, o.t) - p.theta;
     if (!(dT >= st.dTn)) continue;
     // Liquid test, claims part: any grain (including grains nucleated earlier
-    // in this step) whose claims contain the rounded lattice position.
+    // in this step) whose claims contain the rounded lattice position of the
+    // site or, on periodic axes, of one of its images.
     bool liquid = true;
     for (size_t g = 0; g < o.grains.size() && liquid; ++g) {
-      int32_t s[3];
-      lattice_round(p, o.grains[g], st.y, s);
-      if (claimed(o.claims[g], s)) liquid = false;
+      for (int k = 0; k < 27 && liquid; ++k) {
+        const int sh[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+        bool ok = true;
+        double y[3];
+        for (int a = 0; a < 3; ++a) {
+          if (sh[a] != 0 && !periodic_axis(p, a)) ok = false;
+          y[a] = st.y[a] + sh[a] * (p.hi[a] - p.lo[a]);
+        }
+        if (!ok) continue;
+        int32_t s[3];
+        lattice_round(p, o.grains[g], y, s);
+        if (claimed(o.claims[g], s)) liquid = false;
+      }
     }
     if (!liquid) continue;
     // Liquid test, particles part: no non-retired particle within rc.
@@ -656,12 +736,18 @@ void phase_nucleate(Oracle& o) {
     for (int dk = -1; dk <= 1 && liquid; ++dk)
       for (int dj = -1; dj <= 1 && liquid; ++dj)
         for (int di = -1; di <= 1 && liquid; ++di) {
-          int32_t ii = c[0] + di, jj = c[1] + dj, kk = c[2] + dk;
-          if (ii < 0 || jj < 0 || kk < 0 || ii >= ci.n[0] || jj >= ci.n[1] || kk >= ci.n[2]) continue;
+          int32_t ii = stencil_index(p, ci.n, 0, c[0] + di);
+          int32_t jj = stencil_index(p, ci.n, 1, c[1] + dj);
+          int32_t kk = stencil_index(p, ci.n, 2, c[2] + dk);
+          if (ii < 0 || jj < 0 || kk < 0) continue;
           auto it = ci.cells.find(cell_key(ci.n, ii, jj, kk));
           if (it == ci.cells.end()) continue;
-          for (int32_t j : it->second)
-            if (o.parts[j].state != P_RETIRED && dist2(o.parts[j].x, st.y) < rc2) { liquid = false; break; }
+          for (int32_t j : it->second) {
+            if (o.parts[j].state == P_RETIRED) continue;
+            double d[3];
+            min_image(p, o.parts[j].x, st.y, d);
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rc2) { liquid = false; break; }
+          }
         }
     if (!liquid) continue;
     // Fire: new grain with centre y, 6 particles at the centre.
@@ -711,6 +797,7 @@ struct orc_params {
   double a[2], b[2];
   double theta;
   int32_t branching, box_exit;
+  int32_t periodic;  // bit a: axis a periodic
 };
 
 struct orc_field {
@@ -737,6 +824,7 @@ void* orc_create(const orc_params* pp) {
   o->p.theta = pp->theta;
   o->p.branching = pp->branching;
   o->p.box_exit = pp->box_exit;
+  o->p.periodic = pp->periodic;
   return o;
 }
 
@@ -852,7 +940,7 @@ int32_t orc_init_grains(void* h, int32_t n, const double* centre, const double* 
             lattice_position(o.p, G, q.site, q.dir, 0.0, q.x);
             bool inside = true;
             for (int k = 0; k < 3; ++k)
-              if (!(q.x[k] >= o.p.lo[k] && q.x[k] < o.p.hi[k])) inside = false;
+              if (!periodic_axis(o.p, k) && !(q.x[k] >= o.p.lo[k] && q.x[k] < o.p.hi[k])) inside = false;
             q.state = (inside || !o.p.box_exit) ? P_ACTIVE : P_STOPPED;
             o.parts.push_back(q);
           }
@@ -1051,16 +1139,26 @@ void orc_grain_map(void* h, const int32_t n[3], const double origin[3], const do
                    origin[2] + (k + 0.5) * spacing[2]};
     uint32_t best = 0;
     double bd = INFINITY;
-    for (size_t g = 0; g < o.grains.size(); ++g) {
-      int32_t s[3];
-      lattice_round(o.p, o.grains[g], y, s);
-      auto it = o.claims[g].find(site_key(s[0], s[1], s[2]));
-      if (it == o.claims[g].end() || !(it->second & C_REACHED)) continue;
-      double ps[3];
-      lattice_position(o.p, o.grains[g], s, 0, 0.0, ps);
-      double d = dist2(y, ps);
-      if (d < bd) { bd = d; best = (uint32_t)g + 1; }
-    }
+    for (size_t g = 0; g < o.grains.size(); ++g)
+      for (int k = 0; k < 27; ++k) {
+        // The voxel centre and, on periodic axes, its images.
+        const int sh[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+        bool ok = true;
+        double yi[3];
+        for (int a = 0; a < 3; ++a) {
+          if (sh[a] != 0 && !periodic_axis(o.p, a)) ok = false;
+          yi[a] = y[a] + sh[a] * (o.p.hi[a] - o.p.lo[a]);
+        }
+        if (!ok) continue;
+        int32_t s[3];
+        lattice_round(o.p, o.grains[g], yi, s);
+        auto it = o.claims[g].find(site_key(s[0], s[1], s[2]));
+        if (it == o.claims[g].end() || !(it->second & C_REACHED)) continue;
+        double ps[3];
+        lattice_position(o.p, o.grains[g], s, 0, 0.0, ps);
+        double d = dist2(yi, ps);
+        if (d < bd) { bd = d; best = (uint32_t)g + 1; }
+      }
     out[v] = best;
   }
 }
@@ -1090,9 +1188,12 @@ void orc_deposit_counts(void* h, const int32_t n[3], const double origin[3],
                            (double)((int32_t)(kv.first & m21) - off)};
       int64_t idx[3];
       bool in = true;
+      double x[3], xw[3];
+      for (int a = 0; a < 3; ++a)
+        x[a] = G.c[a] + o.p.lambda0 * (G.R[a][0] * S[0] + G.R[a][1] * S[1] + G.R[a][2] * S[2]);
+      wrap_pos(o.p, x, xw);
       for (int a = 0; a < 3; ++a) {
-        const double x = G.c[a] + o.p.lambda0 * (G.R[a][0] * S[0] + G.R[a][1] * S[1] + G.R[a][2] * S[2]);
-        const double f = std::floor((x - origin[a]) / spacing[a] + 0.5);
+        const double f = std::floor((xw[a] - origin[a]) / spacing[a] + 0.5);
         if (!(f >= 0 && f < n[a])) in = false;
         idx[a] = (int64_t)f;
       }
@@ -1215,9 +1316,10 @@ static double replay_one(const Oracle& o, const Params& p, const Grain& g, const
   if (trace) trace[0] = s;
   for (int32_t k = 0; k < n_steps; ++k) {
     if (k < nact) {
-      double x[3];
+      double x[3], xw[3];
       lattice_position(p, g, site, d, s, x);
-      double dT = field_value(o.f, x, t0 + k * dt) - p.theta;
+      wrap_pos(p, x, xw);
+      double dT = field_value(o.f, xw, t0 + k * dt) - p.theta;
       s += velocity(p, dT) * dt;
     }
     if (trace) trace[k + 1] = s;
@@ -1267,9 +1369,10 @@ int32_t orc_adjoint_grad(void* h, int64_t n, const int32_t* grain, const int32_t
     double lam = dLdx[3 * i] * u[0] + dLdx[3 * i + 1] * u[1] + dLdx[3 * i + 2] * u[2];
     for (int32_t k = n_steps - 1; k >= 0; --k) {
       if (k >= nact[i]) continue;
-      double x[3], gF[3];
+      double x[3], xw[3], gF[3];
       lattice_position(p, g, site + 3 * i, dir[i], tr[k], x);
-      double dT = field_value(o.f, x, t0 + k * dt, gF) - p.theta;
+      wrap_pos(p, x, xw);
+      double dT = field_value(o.f, xw, t0 + k * dt, gF) - p.theta;
       double vp = velocity_slope(p, dT);
       if (dT > 0) {
         G0 += lam * dt * std::pow(dT, p.b[0]);

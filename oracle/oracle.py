@@ -16,7 +16,7 @@ class _Params(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("lambda0", C.c_double),
                 ("h", C.c_double), ("rc", C.c_double), ("a", C.c_double * 2),
                 ("b", C.c_double * 2), ("theta", C.c_double), ("branching", C.c_int32),
-                ("box_exit", C.c_int32)]
+                ("box_exit", C.c_int32), ("periodic", C.c_int32)]
 
 
 class _Field(C.Structure):
@@ -121,7 +121,8 @@ def _f64(a):
 class Oracle:
     """One oracle simulation state."""
 
-    def __init__(self, lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1):
+    def __init__(self, lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,
+                 periodic=0):
         self.lib = _load()
         p = _Params()
         p.lo[:] = list(lo)
@@ -132,13 +133,15 @@ class Oracle:
         p.theta = theta
         p.branching = int(branching)
         p.box_exit = int(box_exit)
+        p.periodic = int(periodic)
         self.params = p
         self.h = self.lib.orc_create(C.byref(p))
         self._keep = []
 
     @classmethod
     def from_workload(cls, w, init=True):
-        o = cls(w.lo, w.hi, w.lambda0, w.h, w.rc, w.a, w.b, w.theta, w.branching, w.box_exit)
+        o = cls(w.lo, w.hi, w.lambda0, w.h, w.rc, w.a, w.b, w.theta, w.branching, w.box_exit,
+                w.periodic)
         o.set_field(w.field)
         if init:
             if len(w.grain_centre):

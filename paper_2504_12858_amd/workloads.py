@@ -160,6 +160,7 @@ class Workload:
     field: Field
     branching: int = 1
     box_exit: int = 1
+    periodic: int = 0       # bit a: axis a periodic with period hi - lo (Sec. 3.4)
     grain_centre: np.ndarray = dc_field(default_factory=lambda: np.zeros((0, 3)))
     grain_quat: np.ndarray = dc_field(default_factory=lambda: np.zeros((0, 4)))
     grain_shell: np.ndarray = dc_field(default_factory=lambda: np.zeros((0,), np.int32))
