@@ -83,8 +83,23 @@ typedef int32_t ge_status;
  * contact radius rc must satisfy rc <= h and rc <= lambda0; with rc <= h/2
  * the containment test visits 2^3 cells per particle, otherwise 3^3.
  * Lattice sites must stay within +-16000 of a grain's centre:
- * (box diagonal) / lambda0 < 16000.  Dense per-cell tables take 24 bytes per
- * cell (padded to whole bricks).
+ * (box diagonal) / lambda0 < 16000, the extent of a periodic axis counted
+ * twice.  Dense per-cell tables take 24 bytes per cell (padded to whole
+ * bricks).
+ *
+ * Periodic axes (Sec. 3.4 imposes periodic conditions on the faces normal
+ * to x and y): bit a of `periodic` makes axis a repeat with period
+ * L = hi - lo, which must be a whole number (at least 3) of cells h.
+ * Particles never leave through such faces (box_exit concerns the other
+ * axes); positions stay lattice-anchored (unwrapped: a grain grows on
+ * across the face), and the field, the cell of a particle, the deposition
+ * cell and the grain map take the position wrapped into the box.  Two
+ * particles meet when their nearest periodic images are closer than rc and
+ * they belong to different grains, or to one grain through a non-zero
+ * period shift (a grain that has grown around the period meets itself).  A
+ * nucleation site is inside a grain when one of its periodic images is.
+ * cap_grains must then stay below 2^26 - 8 (the image of a position is kept
+ * in the upper bits of its grain word).
  */
 typedef struct ge_params {
   double lo[3], hi[3];   /* box [m] */
@@ -104,6 +119,7 @@ typedef struct ge_params {
                                one grain */
   int32_t field_n[3];    /* largest field grid the context will hold (nodes per axis) */
   int32_t resort_every;  /* steps between re-sorts of the stopped store by cell (0: 16) */
+  int32_t periodic;      /* bit a (a = 0, 1, 2 for x, y, z): axis a is periodic */
 } ge_params;
 
 /* Thermal field (Sec. 2.3 interpolation; Sec. 3.1 / 3.4 imposed fields). */

@@ -45,7 +45,7 @@ class ge_params(C.Structure):
                 ("box_exit", C.c_int32), ("cap_particles", C.c_int64),
                 ("cap_stopped", C.c_int64), ("cap_grains", C.c_int32), ("cap_sites", C.c_int32),
                 ("cap_claim_bricks", C.c_int64), ("field_n", C.c_int32 * 3),
-                ("resort_every", C.c_int32)]
+                ("resort_every", C.c_int32), ("periodic", C.c_int32)]
 
 
 class ge_field(C.Structure):
@@ -169,7 +169,7 @@ MAX_BLOCKS = 2048
 def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1,
                 cap_particles=1 << 20, cap_stopped=1 << 20, cap_grains=1 << 12,
                 cap_sites=1 << 12, cap_claim_bricks=1 << 16, field_n=(0, 0, 0),
-                resort_every=0) -> ge_params:
+                resort_every=0, periodic=0) -> ge_params:
     p = ge_params()
     p.lo[:] = [float(v) for v in lo]
     p.hi[:] = [float(v) for v in hi]
@@ -183,6 +183,7 @@ def make_params(lo, hi, lambda0, h, rc, a, b, theta=0.0, branching=1, box_exit=1
     p.cap_claim_bricks = int(cap_claim_bricks)
     p.field_n[:] = [int(v) for v in field_n]
     p.resort_every = int(resort_every)
+    p.periodic = int(periodic)
     return p
 
 
@@ -191,6 +192,7 @@ def params_from_workload(w, **caps) -> ge_params:
           else (0, 0, 0))
     caps.setdefault("field_n", fn)
     caps.setdefault("cap_sites", max(len(w.site_dTn), 1))
+    caps.setdefault("periodic", w.periodic)
     return make_params(w.lo, w.hi, w.lambda0, w.h, w.rc, w.a, w.b, w.theta, w.branching,
                        w.box_exit, **caps)
 

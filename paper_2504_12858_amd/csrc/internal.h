@@ -47,6 +47,11 @@ constexpr uint64_t CLAIM_EMPTY = ~0ull;
 constexpr uint32_t NIL = 0xFFFFFFFFu;
 constexpr uint32_t MIXED = 0xFFFFFFFEu;  // owner word: particles of several grains
 constexpr uint32_t BOWN_CELLS = 0xFFFFFFFDu;  // brick owner word: see the cells' words
+// Owner word of a particle with periodic axes: grain | image code << 26, the
+// code holding the period index of the unwrapped position, two bits per
+// axis (two's complement); without periodic axes the code is zero.
+constexpr uint32_t OWNER_SHIFT = 26;
+constexpr uint32_t GRAIN_MASK = (1u << OWNER_SHIFT) - 1u;
 
 // Tunable kernels (index into Dev::sched).
 enum : int { TK_ADVANCE = 0, TK_MARKNOW, TK_BRANCH, TK_CELLSCAN, TK_SCATTER, TK_CHILDREN, TK_DIRTY,
@@ -107,6 +112,8 @@ struct Dev {
   int32_t nb[3];     // bricks per axis
   uint32_t n_bricks;
   int32_t stencil8;  // rc <= h/2: 2x2x2 cell stencil, else 3x3x3
+  int32_t periodic;  // bit a: axis a periodic with period L[a] = hi[a] - lo[a]
+  float L[3], invL[3];
   float lambda0, rc2, rc_half;
   float ka[2], kb[2];
   int32_t kin_poly;
@@ -243,6 +250,7 @@ struct BatchLaunch {
   const Dev* tab;  // per context: Dev with pointers stored as offsets from base
   char* base;
   BatchSite site[BS_N];
+  int32_t any_periodic;  // some context has periodic axes
 };
 
 // -------------------------------------------------- host-side launchers --

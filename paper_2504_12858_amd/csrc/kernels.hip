@@ -104,6 +104,73 @@ __device__ __forceinline__ C3 cell_of(const Dev& D, P3 p) {
   return c;
 }
 
+// ------------------------------------------------ periodic boundaries ---
+// On a periodic axis (period L = hi - lo) positions stay lattice-anchored
+// and unwrapped; the cell, the field and the contact tests take the position
+// wrapped into [lo, hi) together with its period index k (x = wrapped + k L).
+// A position already inside the box is returned unchanged, so wrapping is
+// idempotent.
+struct Placed {
+  P3 p;
+  uint32_t code;  // period index per periodic axis, two bits each (two's complement)
+};
+__device__ __forceinline__ float wrap_axis(float x, float lo, float hi, float L, float invL,
+                                          int& k) {
+  k = 0;
+  if (x >= lo && x < hi) return x;
+  float f = floorf((x - lo) * invL);
+  float y = fmaf(-f, L, x);
+  if (!(y >= lo)) {
+    y = lo;
+  } else if (!(y < hi)) {
+    y = lo;
+    f += 1.0f;
+  }
+  k = (int)f;
+  return y;
+}
+__device__ __forceinline__ Placed place(const Dev& D, P3 x) {
+  Placed o = {x, 0u};
+  if (!D.periodic) return o;
+  int k;
+  if (D.periodic & 1) {
+    o.p.x = wrap_axis(x.x, D.lo[0], D.hi[0], D.L[0], D.invL[0], k);
+    o.code |= (uint32_t)k & 3u;
+  }
+  if (D.periodic & 2) {
+    o.p.y = wrap_axis(x.y, D.lo[1], D.hi[1], D.L[1], D.invL[1], k);
+    o.code |= ((uint32_t)k & 3u) << 2;
+  }
+  if (D.periodic & 4) {
+    o.p.z = wrap_axis(x.z, D.lo[2], D.hi[2], D.L[2], D.invL[2], k);
+    o.code |= ((uint32_t)k & 3u) << 4;
+  }
+  return o;
+}
+__device__ __forceinline__ uint32_t owner_id(uint32_t g, uint32_t code) {
+  return g | (code << OWNER_SHIFT);
+}
+// Period index of axis a in an owner word.
+__device__ __forceinline__ int owner_image(uint32_t own, int a) {
+  const int v = (int)((own >> (OWNER_SHIFT + 2 * a)) & 3u);
+  return v >= 2 ? v - 4 : v;
+}
+// Inside the box along every axis that is not periodic.
+template <int PM = 2>
+__device__ __forceinline__ bool in_box(const Dev& D, P3 x) {
+  const int per = PM == 0 ? 0 : D.periodic;
+  return ((per & 1) || (x.x >= D.lo[0] && x.x < D.hi[0])) &&
+         ((per & 2) || (x.y >= D.lo[1] && x.y < D.hi[1])) &&
+         ((per & 4) || (x.z >= D.lo[2] && x.z < D.hi[2]));
+}
+// Wrapped position and owner word of a particle of grain g at x.
+__device__ __forceinline__ float4 placed4(const Dev& D, P3 x, uint32_t g) {
+  const Placed pl = place(D, x);
+  return make_float4(pl.p.x, pl.p.y, pl.p.z, __uint_as_float(owner_id(g, pl.code)));
+}
+// Cell index along a periodic axis, wrapped (stencil cells past a face).
+__device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
 __device__ __forceinline__ uint32_t brick_index(const Dev& D, int cx, int cy, int cz) {
   return ((uint32_t)(cz >> 2) * (uint32_t)D.nb[1] + (uint32_t)(cy >> 2)) * (uint32_t)D.nb[0] +
          (uint32_t)(cx >> 2);
@@ -145,6 +212,8 @@ __device__ __forceinline__ void stencil_axis(const Dev& D, float x, int a, int& 
     c0 = c - 1;
     c1 = c + 1;
   }
+  // On a periodic axis the stencil runs past the face (its cells wrap).
+  if ((D.periodic >> a) & 1) return;
   c0 = max(c0, 0);
   c1 = min(c1, n - 1);
 }
@@ -180,8 +249,13 @@ __device__ __forceinline__ float trilinear(const Dev& D, P3 p) {
 }
 
 // Undercooling at p (without theta).  lin_c = dT0 + rate t for LINEAR.
+// PM (periodic mode): 0 for a context without periodic axes, 1 with them,
+// 2 as the context has them; kernels on the hot path are instantiated for 0
+// and 1 so that the plain case carries no periodic code.
+template <int PM = 2>
 __device__ __forceinline__ float field_at(const Dev& D, P3 p, float lin_c) {
   if (D.fkind == F_UNIFORM) return D.fdT;
+  if constexpr (PM != 0) p = place(D, p).p;
   if (D.fkind == F_LINEAR)
     return ((lin_c + D.fgrad[0] * p.x) + D.fgrad[1] * p.y) + D.fgrad[2] * p.z;
   return trilinear(D, p);
@@ -309,7 +383,7 @@ __device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int s
 // Deposition cell of a site, or NIL outside the grid.
 __device__ __forceinline__ uint32_t deposit_cell(const Dev& D, const float* __restrict__ G, int sx,
                                                  int sy, int sz) {
-  const P3 x = lattice_pos(G, sx, sy, sz, 0, 0.0f);
+  const P3 x = place(D, lattice_pos(G, sx, sy, sz, 0, 0.0f)).p;
   const float xs[3] = {x.x, x.y, x.z};
   uint32_t idx[3];
 #pragma unroll
@@ -335,9 +409,28 @@ __device__ __forceinline__ void deposit_site(const Dev& D, const float* __restri
 // enough to stay in cache, then cell by cell.  Clamped coordinates and boxes
 // reaching beyond the grid are handled as the interpolation handles them.
 __device__ __forceinline__ float bound_margin(float m) { return m - 1e-5f * fabsf(m) - 1e-6f; }
+template <int PM = 2>
 __device__ bool may_melt(const Dev& D, P3 lo, P3 hi, float lin_c) {
   if (D.fkind == F_UNIFORM) return D.fdT - D.theta < 0.0f;
-  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+  float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+  // On a periodic axis the box is moved into the period of its low end
+  // (with a margin for the rounding of the move); a box that then reaches
+  // past the face, or spans a period, takes the whole axis.
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (PM == 0 || !((D.periodic >> a) & 1)) continue;
+    int k;
+    const float ln = wrap_axis(l[a], D.lo[a], D.hi[a], D.L[a], D.invL[a], k);
+    const float m = 1e-6f * D.L[a];
+    const float hn = fmaf(-(float)k, D.L[a], h[a]) + m;
+    if (!(h[a] - l[a] < D.L[a]) || !(hn < D.hi[a])) {
+      l[a] = D.lo[a];
+      h[a] = D.hi[a];
+    } else {
+      l[a] = ln - m;
+      h[a] = hn;
+    }
+  }
   if (D.fkind == F_LINEAR) {
     float v = lin_c, mag = fabsf(lin_c);
 #pragma unroll
@@ -371,10 +464,11 @@ __device__ bool may_melt(const Dev& D, P3 lo, P3 hi, float lin_c) {
 
 // Undercooling at the departure site of a record is negative (the site
 // melted), tested first against the bound of its cell neighbourhood.
+template <int PM = 2>
 __device__ __forceinline__ bool departure_melted(const Dev& D, const float* __restrict__ G,
                                                  int sx, int sy, int sz, float lin_c) {
   const P3 x = lattice_pos(G, sx, sy, sz, 0, 0.0f);
-  return may_melt(D, x, x, lin_c) && field_at(D, x, lin_c) - D.theta < 0.0f;
+  return may_melt<PM>(D, x, x, lin_c) && field_at<PM>(D, x, lin_c) - D.theta < 0.0f;
 }
 
 // Rounded lattice position of world point y in grain G (crystal frame).
@@ -714,18 +808,19 @@ __device__ __forceinline__ uint32_t owner_merge(uint32_t own, uint32_t g) {
 }
 
 // ------------------------------------------------------- stopped store ----
-// Writes record r (state STOPPED) and its position at slot j of the stopped
-// store and links it into the cell list of recently stopped particles.
-// Callers run in kernels that never read those lists.
-__device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P3 p) {
+// Writes record r (state STOPPED) and its placed position pw (wrapped
+// position, owner word) at slot j of the stopped store and links it into the
+// cell list of recently stopped particles.  Callers run in kernels that
+// never read those lists.
+__device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, float4 pw) {
   if (j >= D.cap_s) {
     atomicOr(&D.cnt->err, ERR_CAPACITY);
     return;
   }
-  const uint32_t g = rec_grain(r);
+  const uint32_t g = grain_of(pw);
   D.S[j] = r;
-  D.PS[j] = pos4(p, g);
-  const C3 c = cell_of(D, p);
+  D.PS[j] = pw;
+  const C3 c = cell_of(D, p3_of(pw));
   const uint32_t ci = cell_index(D, c.x, c.y, c.z);
   const uint32_t old = atomicExch(&D.shead[ci], j);
   D.snext[j] = old;
@@ -746,7 +841,7 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, P
 }
 
 // ==================================================================== step
-template <class Bind>
+template <class Bind, int PM>
 __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
   Dev D;
   VGrid V;
@@ -785,7 +880,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
       // its target is released.
       const uint32_t g = rec_grain(r);
       const float* G = D.gtab + (size_t)g * GT_STRIDE;
-      gone = departure_melted(D, G, rec_sx(r), rec_sy(r), rec_sz(r), lin_c);
+      gone = departure_melted<PM>(D, G, rec_sx(r), rec_sy(r), rec_sz(r), lin_c);
       if (gone) {
         const int d = rec_dir(r);
         int T[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
@@ -812,7 +907,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
       }
       const float* G = D.gtab + (size_t)g * GT_STRIDE;
       const P3 x = lattice_pos(G, sx, sy, sz, d, s);
-      const float dT = field_at(D, x, lin_c) - D.theta;
+      const float dT = field_at<PM>(D, x, lin_c) - D.theta;
       float delta = velocity(D, dT) * dt;
       if (!isfinite(delta)) {
         bad |= ERR_NUMERIC;
@@ -823,8 +918,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
       const float s2 = s + delta;
       x2 = lattice_pos(G, sx, sy, sz, d, s2);
       nadv += 1;
-      const bool inside = x2.x >= D.lo[0] && x2.x < D.hi[0] && x2.y >= D.lo[1] &&
-                          x2.y < D.hi[1] && x2.z >= D.lo[2] && x2.z < D.hi[2];
+      const bool inside = in_box<PM>(D, x2);
       uint32_t fl;
       if (D.box_exit && !inside) {
         exited = true;
@@ -836,7 +930,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
         if (s2 >= 2.0f * D.lambda0) bad |= ERR_CFL;
       } else {
         fl = ST_ACTIVE | FL_KEEP;
-        const C3 c = cell_of(D, x2);
+        const C3 c = cell_of(D, PM == 0 ? x2 : place(D, x2).p);
         ckey = cell_index(D, c.x, c.y, c.z);
         bkey = ckey / (uint32_t)BRICK_CELLS;
       }
@@ -860,7 +954,7 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
     }
     const uint32_t sj = wave_append(exited, &D.cnt->n_stopped);
     if (exited) {
-      stopped_put(D, sj, r, x2);
+      stopped_put(D, sj, r, PM == 0 ? pos4(x2, rec_grain(r)) : placed4(D, x2, rec_grain(r)));
       if (tag != NIL) {
         D.adj_nact[tag] = adj_k + 1;
         D.adj_sfin[tag] = rec_s(r);
@@ -1025,7 +1119,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       SlotCache wc{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
       for (int dd = 0; dd < 6; ++dd) {
         if (!(mask & (1u << dd))) continue;
-        const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc2);
+        const P3 xc = place(D, lattice_pos(G, S[0], S[1], S[2], dd, sc2)).p;
         const C3 c = cell_of(D, xc);
         const uint32_t ci = cell_index(D, c.x, c.y, c.z);
         atomicAdd(&D.ccnt[ci], 1u);
@@ -1216,8 +1310,9 @@ __global__ __launch_bounds__(TPB) void k_scatter(Bind Bd) {
     uint32_t g = NIL;
     P3 p = {0.0f, 0.0f, 0.0f};
     if (fl & FL_KEEP) {
-      g = rec_grain(r);
-      p = rec_pos(D, r);
+      const Placed pl = place(D, rec_pos(D, r));
+      g = owner_id(rec_grain(r), pl.code);
+      p = pl.p;
       const C3 c = cell_of(D, p);
       ckey = cell_index(D, c.x, c.y, c.z);
     }
@@ -1273,17 +1368,17 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
     const float sc = rec_s(r) - D.lambda0;
     for (int dd = 0; dd < 6; ++dd) {
       if (!(mask & (1u << dd))) continue;
-      const P3 xc = lattice_pos(G, S[0], S[1], S[2], dd, sc);
-      const C3 c = cell_of(D, xc);
+      const float4 xc = placed4(D, lattice_pos(G, S[0], S[1], S[2], dd, sc), gs);
+      const C3 c = cell_of(D, p3_of(xc));
       const uint32_t ci = cell_index(D, c.x, c.y, c.z);
       const uint32_t rank = atomicSub(&D.ccnt[ci], 1u) - 1u;
       const uint32_t dst = D.cstart[ci] + rank;
       if (dst < D.cap_p) {
         D.B[dst] = make_rec(sc, gs, dd, S[0], S[1], S[2], ST_ACTIVE);
-        D.P[dst] = pos4(xc, gs);
+        D.P[dst] = xc;
         if (D.tagA) D.tagB[dst] = NIL;
       }
-      note_grain_checked(D, ci / (uint32_t)BRICK_CELLS, gs);
+      note_grain_checked(D, ci / (uint32_t)BRICK_CELLS, grain_of(xc));
     }
   }
 }
@@ -1348,8 +1443,19 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
         if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) foreign = true;
       }
     }
-    // Flagged bricks; the brick itself (bit 13) when it holds several grains.
-    const uint32_t flags = (uint32_t)__ballot(foreign) | (own.z != own.w ? (1u << 13) : 0u);
+    // Flagged bricks; the brick itself (bit 13) when it holds several grains
+    // or lies on a periodic face (its cells' stencils wrap, and owner words
+    // do not tell the periods apart).
+    bool face = false;
+    if (D.periodic) {
+      const int cx = (int)(b % (uint32_t)nbx), cy = (int)((b / (uint32_t)nbx) % (uint32_t)nby),
+                cz = (int)(b / ((uint32_t)nbx * (uint32_t)nby));
+      face = ((D.periodic & 1) && (cx == 0 || cx == nbx - 1)) ||
+             ((D.periodic & 2) && (cy == 0 || cy == nby - 1)) ||
+             ((D.periodic & 4) && (cz == 0 || cz == nbz - 1));
+    }
+    const uint32_t flags =
+        (uint32_t)__ballot(foreign) | (own.z != own.w || face ? (1u << 13) : 0u);
     const bool dirty = flags != 0u;
     if (lane == 0) D.bown[b] = make_uint2(epoch, dirty ? BOWN_CELLS : g);
     if (!dirty) continue;
@@ -1404,6 +1510,43 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
 }
 
 // ---------------------------------------------------------- containment ---
+// Contact of a particle at p with owner word g and a candidate q (position,
+// owner word).  Without periodic axes: another grain within rc.  With them:
+// the nearest images within rc, and another grain or the same grain through
+// a non-zero period shift (the candidate's period index minus the
+// particle's, plus the shift to the nearest image).  g = NIL: any particle.
+__device__ __forceinline__ bool meets_periodic(const Dev& D, float4 q, P3 p, uint32_t g,
+                                               float rc2) {
+  const uint32_t h = grain_of(q);
+  float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+  int shift = 0;
+  if (D.periodic & 1) {
+    const float k = rintf(dx * D.invL[0]);
+    dx = fmaf(-k, D.L[0], dx);
+    shift |= (int)k + owner_image(g, 0) - owner_image(h, 0);
+  }
+  if (D.periodic & 2) {
+    const float k = rintf(dy * D.invL[1]);
+    dy = fmaf(-k, D.L[1], dy);
+    shift |= (int)k + owner_image(g, 1) - owner_image(h, 1);
+  }
+  if (D.periodic & 4) {
+    const float k = rintf(dz * D.invL[2]);
+    dz = fmaf(-k, D.L[2], dz);
+    shift |= (int)k + owner_image(g, 2) - owner_image(h, 2);
+  }
+  if (g != NIL && ((g ^ h) & GRAIN_MASK) == 0u && shift == 0) return false;
+  return (dx * dx + dy * dy) + dz * dz < rc2;
+}
+template <bool PER>
+__device__ __forceinline__ bool meets(const Dev& D, float4 q, P3 p, uint32_t g, float rc2) {
+  if constexpr (PER) return meets_periodic(D, q, p, g, rc2);
+  return grain_of(q) != g && dist2(p, p3_of(q)) < rc2;
+}
+__device__ __forceinline__ bool meets_any(const Dev& D, float4 q, P3 p, uint32_t g, float rc2) {
+  return D.periodic ? meets_periodic(D, q, p, g, rc2) : meets<false>(D, q, p, g, rc2);
+}
+
 // True if a particle of a grain other than g (g = NIL: of any grain) lies
 // within rc of p, among this step's active particles and the stopped ones.
 // `tests` counts the candidate particles examined (diagnostics).
@@ -1412,9 +1555,11 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
   stencil_axis(D, p.x, 0, x0, x1);
   stencil_axis(D, p.y, 1, y0, y1);
   stencil_axis(D, p.z, 2, z0, z1);
-  for (int z = z0; z <= z1; ++z)
-    for (int y = y0; y <= y1; ++y)
-      for (int x = x0; x <= x1; ++x) {
+  for (int zs = z0; zs <= z1; ++zs)
+    for (int ys = y0; ys <= y1; ++ys)
+      for (int xs = x0; xs <= x1; ++xs) {
+        const int x = wrap_cell(xs, D.n[0]), y = wrap_cell(ys, D.n[1]), z = wrap_cell(zs, D.n[2]);
+        const bool cross = x != xs || y != ys || z != zs;
         const uint32_t b = brick_index(D, x, y, z);
         const uint32_t loc = local_index(x, y, z);
         const uint32_t ci = b * (uint32_t)BRICK_CELLS + loc;
@@ -1422,19 +1567,19 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
         // nothing) cannot hold a foreign particle.
         if (D.bepoch[b] == epoch) {
           const uint4 inf = D.binfo[b];
-          if (!(inf.z == g && inf.w == g)) {
+          if (cross || !(inf.z == g && inf.w == g)) {
             const uint32_t st = D.cstart[ci];
             const uint32_t en =
                 (loc + 1u < (uint32_t)BRICK_CELLS) ? D.cstart[ci + 1] : inf.x + inf.y;
             for (uint32_t j = st; j < en; ++j) {
               const float4 q = D.P[j];
               ++tests;
-              if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+              if (meets_any(D, q, p, g, D.rc2)) return true;
             }
           }
         }
         const uint2 sb = D.sbsum[b];
-        if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) {
+        if (sb.x <= sb.y && (cross || !(sb.x == g && sb.y == g))) {
           const uint2 bs = D.bsinfo[b];
           if (bs.y > 0u) {
             const uint32_t st = D.sstart[ci];
@@ -1443,13 +1588,13 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
             for (uint32_t j = st; j < en; ++j) {
               const float4 q = D.PS[j];
               ++tests;
-              if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+              if (meets_any(D, q, p, g, D.rc2)) return true;
             }
           }
           for (uint32_t j = D.shead[ci]; j != NIL; j = D.snext[j]) {
             const float4 q = D.PS[j];
             ++tests;
-            if (grain_of(q) != g && dist2(p, p3_of(q)) < D.rc2) return true;
+            if (meets_any(D, q, p, g, D.rc2)) return true;
           }
         }
       }
@@ -1466,26 +1611,35 @@ struct CellOwners {
   bool act, stp;
 };
 
+// With periodic axes a stencil cell past a face wraps, and every particle
+// there is a candidate: the owner word cannot tell a particle's own period
+// from the next one.
+template <bool PER>
 __device__ __forceinline__ CellOwners cell_owners(const Dev& D, uint32_t epoch, int x, int y,
                                                   int z, uint32_t g) {
+  bool cross = false;
+  if constexpr (PER) {
+    const int xw = wrap_cell(x, D.n[0]), yw = wrap_cell(y, D.n[1]), zw = wrap_cell(z, D.n[2]);
+    cross = xw != x || yw != y || zw != z;
+    x = xw;
+    y = yw;
+    z = zw;
+  }
   CellOwners o;
   o.b = brick_index(D, x, y, z);
   o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
   const uint2 bw = D.bown[o.b];
   const uint2 cw = D.cown[o.ci];
   const uint32_t aown = bw.x != epoch ? NIL : (bw.y == BOWN_CELLS ? cw.x : bw.y);
-  o.act = aown != NIL && aown != g;
-  o.stp = cw.y != NIL && cw.y != g;
+  o.act = aown != NIL && (cross || aown != g);
+  o.stp = cw.y != NIL && (cross || cw.y != g);
   return o;
-}
-
-__device__ __forceinline__ bool meets(float4 q, P3 p, uint32_t g, float rc2) {
-  return grain_of(q) != g && dist2(p, p3_of(q)) < rc2;
 }
 
 // Candidates Q[st, en) in groups of four independent loads (the tail group
 // repeats its last candidate, which does not change the outcome).
-__device__ __forceinline__ bool scan_range(const float4* __restrict__ Q, uint32_t st,
+template <bool PER>
+__device__ __forceinline__ bool scan_range(const Dev& D, const float4* __restrict__ Q, uint32_t st,
                                            uint32_t en, P3 p, uint32_t g, float rc2,
                                            uint32_t& tests) {
   for (uint32_t j = st; j < en; j += 4u) {
@@ -1495,8 +1649,8 @@ __device__ __forceinline__ bool scan_range(const float4* __restrict__ Q, uint32_
     const float4 q2 = Q[min(j + 2u, l)];
     const float4 q3 = Q[min(j + 3u, l)];
     tests += min(en - j, 4u);
-    const int m = (int)meets(q0, p, g, rc2) | (int)meets(q1, p, g, rc2) |
-                  (int)meets(q2, p, g, rc2) | (int)meets(q3, p, g, rc2);
+    const int m = (int)meets<PER>(D, q0, p, g, rc2) | (int)meets<PER>(D, q1, p, g, rc2) |
+                  (int)meets<PER>(D, q2, p, g, rc2) | (int)meets<PER>(D, q3, p, g, rc2);
     if (m) return true;
   }
   return false;
@@ -1532,11 +1686,12 @@ __device__ __forceinline__ CellRanges cell_ranges(const Dev& D, const CellOwners
   return r;
 }
 
+template <bool PER>
 __device__ __forceinline__ bool walk_recent(const Dev& D, uint32_t j, P3 p, uint32_t g,
                                             uint32_t& tests) {
   for (; j != NIL; j = D.snext[j]) {
     ++tests;
-    if (meets(D.PS[j], p, g, D.rc2)) return true;
+    if (meets<PER>(D, D.PS[j], p, g, D.rc2)) return true;
   }
   return false;
 }
@@ -1576,7 +1731,7 @@ __device__ __forceinline__ bool stencil_cell(const Stencil& s, int k, int& x, in
 // Foreign-owner bits of the stencil cells (bit k: cell k holds active,
 // resp. stopped particles of another grain).  Owner words are loaded one
 // z-layer of the stencil at a time, all cells of a layer together.
-template <bool S8>
+template <bool S8, bool PER>
 __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, const Stencil& st,
                                                uint32_t g, uint32_t& act, uint32_t& stp) {
   constexpr int NL = S8 ? 2 : 3, PL = S8 ? 4 : 9;
@@ -1588,7 +1743,7 @@ __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, con
       const int k = l * PL + u;
       int x, y, z;
       if (!stencil_cell<S8>(st, k, x, y, z)) continue;
-      const CellOwners o = cell_owners(D, epoch, x, y, z, g);
+      const CellOwners o = cell_owners<PER>(D, epoch, x, y, z, g);
       act |= (uint32_t)o.act << k;
       stp |= (uint32_t)o.stp << k;
     }
@@ -1596,7 +1751,7 @@ __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, con
 }
 
 // Writes the entries of the cells with bits in act / stp to e[0 ..).
-template <bool S8>
+template <bool S8, bool PER>
 __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st, uint32_t act,
                                                 uint32_t stp, uint32_t lane, uint3* e) {
   uint32_t n = 0;
@@ -1604,6 +1759,11 @@ __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st,
     if (!(((act | stp) >> k) & 1u)) return;
     int x, y, z;
     (void)stencil_cell<S8>(st, k, x, y, z);
+    if constexpr (PER) {
+      x = wrap_cell(x, D.n[0]);
+      y = wrap_cell(y, D.n[1]);
+      z = wrap_cell(z, D.n[2]);
+    }
     CellOwners o;
     o.b = brick_index(D, x, y, z);
     o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
@@ -1637,7 +1797,7 @@ struct ContainShared {
 // shared out among its lanes, in rounds of at most CE_MAX entries (a lane's
 // sources stay in one round).  Hits go to the block's region of the stop
 // list.
-template <bool S8>
+template <bool S8, bool PER>
 __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint32_t epoch,
                                              ContainShared& S) {
   if (threadIdx.x == 0) {
@@ -1679,7 +1839,7 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
       stencil_axis(D, p.x, 0, st.x0, st.x1);
       stencil_axis(D, p.y, 1, st.y0, st.y1);
       stencil_axis(D, p.z, 2, st.z0, st.z1);
-      stencil_owners<S8>(D, epoch, st, grain_of(q), act, stp);
+      stencil_owners<S8, PER>(D, epoch, st, grain_of(q), act, stp);
     }
     S.hit[threadIdx.x] = 0u;
     // Rounds: the lanes whose sources fit after those of the lanes before
@@ -1693,7 +1853,7 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
       uint32_t used;
       (void)wave_excl_scan(take ? ne : 0u, used);
       if (take) {
-        stencil_entries<S8>(D, st, act, stp, lane, ent + e0);
+        stencil_entries<S8, PER>(D, st, act, stp, lane, ent + e0);
         ne = 0u;
       }
       __syncthreads();
@@ -1705,10 +1865,10 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
         const uint32_t kind = en.z >> 6;
         bool h;
         if (kind == CE_RECENT)
-          h = walk_recent(D, en.x, p3_of(pq), grain_of(pq), tests);
+          h = walk_recent<PER>(D, en.x, p3_of(pq), grain_of(pq), tests);
         else
-          h = scan_range(kind == CE_ACTIVE ? D.P : D.PS, en.x, en.x + en.y, p3_of(pq),
-                         grain_of(pq), rc2, tests);
+          h = scan_range<PER>(D, kind == CE_ACTIVE ? D.P : D.PS, en.x, en.x + en.y, p3_of(pq),
+                              grain_of(pq), rc2, tests);
         if (h) S.hit[L] = 1u;
       }
       __syncthreads();
@@ -1736,7 +1896,10 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
   }
 }
 
-template <class Bind>
+// PM: 0 without periodic axes, 1 with them, 2 as each context has them (a
+// batched launch); separate instantiations keep the plain case free of the
+// periodic code.
+template <class Bind, int PM>
 __global__ __launch_bounds__(TPB, 6) void k_contain(Bind Bd) {
   Dev D;
   VGrid V;
@@ -1744,8 +1907,18 @@ __global__ __launch_bounds__(TPB, 6) void k_contain(Bind Bd) {
   const uint32_t epoch = step_epoch(D);
   if (dead(D)) return;
   __shared__ ContainShared S;
-  if (D.stencil8) contain_body<true>(D, V, epoch, S);
-  else contain_body<false>(D, V, epoch, S);
+  const bool per = PM == 1 || (PM == 2 && D.periodic != 0);
+  if constexpr (PM != 1) {
+    if (!per) {
+      if (D.stencil8) contain_body<true, false>(D, V, epoch, S);
+      else contain_body<false, false>(D, V, epoch, S);
+      return;
+    }
+  }
+  if constexpr (PM != 0) {
+    if (D.stencil8) contain_body<true, true>(D, V, epoch, S);
+    else contain_body<false, true>(D, V, epoch, S);
+  }
 }
 
 template <class Bind>
@@ -1772,7 +1945,7 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Bind Bd) {
       const uint32_t i = D.newstop[beg + k];
       const uint4 r = with_fl(D.B[i], ST_STOPPED);
       D.B[i] = r;
-      stopped_put(D, base + k, r, p3_of(D.P[i]));
+      stopped_put(D, base + k, r, D.P[i]);
       if (D.tagA) {
         const uint32_t tag = D.tagB[i];
         if (tag != NIL) {
@@ -1785,14 +1958,33 @@ __global__ __launch_bounds__(TPB) void k_stoplink(Bind Bd) {
 }
 
 // ----------------------------------------------------------- nucleation ---
-// Site position y lies on a claimed or reached lattice site of grain g.
-__device__ __forceinline__ bool covers(const Dev& D, uint32_t g, P3 y, float inv_l) {
+// Image k (0..26) of y: y shifted by one period or none along each periodic
+// axis; false for a shift along an axis that is not periodic.
+__device__ __forceinline__ bool image_of(const Dev& D, P3 y, int k, P3& out) {
+  const int sx = k % 3 - 1, sy = (k / 3) % 3 - 1, sz = k / 9 - 1;
+  if ((sx && !(D.periodic & 1)) || (sy && !(D.periodic & 2)) || (sz && !(D.periodic & 4)))
+    return false;
+  out = P3{fmaf((float)sx, D.L[0], y.x), fmaf((float)sy, D.L[1], y.y), fmaf((float)sz, D.L[2], y.z)};
+  return true;
+}
+
+// Site position y (or, with periodic axes, one of its images) lies on a
+// claimed or reached lattice site of grain g.
+__device__ __forceinline__ bool covers_at(const Dev& D, uint32_t g, P3 y, float inv_l) {
   int l[3];
   lattice_round(D.gtab + (size_t)g * GT_STRIDE, inv_l, y, l);
   const int32_t* bb = D.gbox + (size_t)g * 6;
   if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] || l[2] > bb[5])
     return false;
   return claim_test(D, g, l[0], l[1], l[2], M_CLAIMED | M_REACHED);
+}
+__device__ __forceinline__ bool covers(const Dev& D, uint32_t g, P3 y, float inv_l) {
+  if (!D.periodic) return covers_at(D, g, y, inv_l);
+  for (int k = 0; k < 27; ++k) {
+    P3 yi;
+    if (image_of(D, y, k, yi) && covers_at(D, g, yi, inv_l)) return true;
+  }
+  return false;
 }
 
 template <class Bind>
@@ -1876,10 +2068,15 @@ __global__ __launch_bounds__(TPB) void k_nuc_fire(Bind Bd) {
       for (uint32_t g = ng0 + threadIdx.x; g < ng0 + nf; g += TPB) {
         const float* G = D.gtab + (size_t)g * GT_STRIDE;
         const P3 cg = {G[0], G[1], G[2]};
-        int l[3];
-        lattice_round(G, inv_l, y, l);
-        if (dist2(y, cg) < D.rc2 || (l[0] == 0 && l[1] == 0 && l[2] == 0))
-          atomicOr(&s_blocked, 1u);
+        bool blocked = false;
+        for (int k = 0; k < (D.periodic ? 27 : 1); ++k) {
+          P3 yi = y;
+          if (D.periodic && !image_of(D, y, k, yi)) continue;
+          int l[3];
+          lattice_round(G, inv_l, yi, l);
+          blocked |= dist2(yi, cg) < D.rc2 || (l[0] == 0 && l[1] == 0 && l[2] == 0);
+        }
+        if (blocked) atomicOr(&s_blocked, 1u);
       }
       __syncthreads();
       if (threadIdx.x == 0 && s_blocked == 0u) {
@@ -1978,7 +2175,7 @@ __global__ __launch_bounds__(TPB) void k_srb_count(Bind Bd) {
       // of its cell is cleared all the same.
       const float4 q = D.PS[j];
       const bool gone = isnan(q.x);
-      const C3 c = cell_of(D, gone ? rec_pos(D, D.S[j]) : p3_of(q));
+      const C3 c = cell_of(D, gone ? place(D, rec_pos(D, D.S[j])).p : p3_of(q));
       ckey = cell_index(D, c.x, c.y, c.z);
       if (j >= ns) D.shead[ckey] = NIL;
       if (gone) ckey = NIL;
@@ -2471,9 +2668,7 @@ __global__ __launch_bounds__(TPB) void k_classify_new(Bind Bd, uint32_t first, u
       if ((rec_fl(r) & 3u) == ST_STOPPED) {
         out = true;
       } else if (D.box_exit) {
-        const bool inside = x.x >= D.lo[0] && x.x < D.hi[0] && x.y >= D.lo[1] &&
-                            x.y < D.hi[1] && x.z >= D.lo[2] && x.z < D.hi[2];
-        out = !inside;
+        out = !in_box(D, x);
       }
       if (out) {
         r = with_fl(r, ST_STOPPED);
@@ -2482,7 +2677,7 @@ __global__ __launch_bounds__(TPB) void k_classify_new(Bind Bd, uint32_t first, u
       }
     }
     const uint32_t j = wave_append(out, &D.cnt->n_stopped);
-    if (out) stopped_put(D, j, r, x);
+    if (out) stopped_put(D, j, r, placed4(D, x, rec_grain(r)));
   }
 }
 
@@ -2539,7 +2734,7 @@ static_assert(sizeof(PartOut) == 48, "particle record layout");
 
 __device__ __forceinline__ void put_particle(const Dev& D, uint4 r, uint32_t state, PartOut* o) {
   const P3 p = rec_pos(D, r);
-  const C3 c = cell_of(D, p);
+  const C3 c = cell_of(D, place(D, p).p);
   PartOut v;
   v.x = p.x;
   v.y = p.y;
@@ -2588,7 +2783,7 @@ __global__ __launch_bounds__(TPB) void k_export_particles(Bind Bd, uint32_t* cou
       take = (rec_fl(r) & 3u) != ST_RETIRED;  // removed by melting
       st = ST_STOPPED;
     }
-    if (take && win.on) take = in_window(win, rec_pos(D, r));
+    if (take && win.on) take = in_window(win, place(D, rec_pos(D, r)).p);
     const uint32_t j = wave_append(take, counter);
     if (take && j < cap_out) put_particle(D, r, st, out + j);
   }
@@ -2631,7 +2826,7 @@ __global__ __launch_bounds__(TPB) void k_export_claims(Bind Bd, uint32_t* counte
         m &= m - 1ull;
         const P3 p = lattice_pos(G, bx * 8 + (bit & 7), by * 8 + ((bit >> 3) & 7), bz * 8 + (int)w,
                                  0, 0.0f);
-        if (in_window(win, p)) keep |= 1ull << bit;
+        if (in_window(win, place(D, p).p)) keep |= 1ull << bit;
       }
       any = keep;
       if (!any) continue;
@@ -2676,18 +2871,23 @@ __global__ __launch_bounds__(TPB) void k_grain_map(Bind Bd, int32_t n0, int32_t 
     float bd = INFINITY;
     for (uint32_t g = 0; g < ng; ++g) {
       const float* G = D.gtab + (size_t)g * GT_STRIDE;
-      int l[3];
-      lattice_round(G, inv_l, y, l);
-      const int32_t* bb = D.gbox + (size_t)g * 6;
-      if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] ||
-          l[2] > bb[5])
-        continue;
-      if (!claim_test(D, g, l[0], l[1], l[2], M_REACHED)) continue;
-      const P3 ps = lattice_pos(G, l[0], l[1], l[2], 0, 0.0f);
-      const float d = dist2(y, ps);
-      if (d < bd) {
-        bd = d;
-        best = g + 1;
+      // The voxel centre and, with periodic axes, its images.
+      for (int k = 0; k < (D.periodic ? 27 : 1); ++k) {
+        P3 yi = y;
+        if (D.periodic && !image_of(D, y, k, yi)) continue;
+        int l[3];
+        lattice_round(G, inv_l, yi, l);
+        const int32_t* bb = D.gbox + (size_t)g * 6;
+        if (l[0] < bb[0] || l[1] < bb[1] || l[2] < bb[2] || l[0] > bb[3] || l[1] > bb[4] ||
+            l[2] > bb[5])
+          continue;
+        if (!claim_test(D, g, l[0], l[1], l[2], M_REACHED)) continue;
+        const P3 ps = lattice_pos(G, l[0], l[1], l[2], 0, 0.0f);
+        const float d = dist2(yi, ps);
+        if (d < bd) {
+          bd = d;
+          best = g + 1;
+        }
       }
     }
     out[v] = best;
@@ -2773,6 +2973,7 @@ __device__ __forceinline__ float velocity_slope(const Dev& D, float dT) {
 __device__ __forceinline__ P3 field_grad(const Dev& D, P3 p) {
   if (D.fkind == F_UNIFORM) return P3{0.0f, 0.0f, 0.0f};
   if (D.fkind == F_LINEAR) return P3{D.fgrad[0], D.fgrad[1], D.fgrad[2]};
+  p = place(D, p).p;
   float u[3] = {(p.x - D.fo[0]) * D.finv[0], (p.y - D.fo[1]) * D.finv[1],
                 (p.z - D.fo[2]) * D.finv[2]};
   int i0[3];
@@ -3009,17 +3210,18 @@ hipError_t resident_grids(Dev& d) {
     grid = g >= 8u ? g / 8u * 8u : g;
     return hipSuccess;
   };
-  const void* ks[TK_N] = {(const void*)k_advance<Plain>, (const void*)k_mark_now<Plain>,
+  const void* ks[TK_N] = {(const void*)k_advance<Plain, 0>, (const void*)k_mark_now<Plain>,
                           (const void*)k_branch<Plain>, (const void*)k_cellscan<Plain>,
                           (const void*)k_scatter<Plain>, (const void*)k_scatter_children<Plain>,
-                          (const void*)k_dirty<Plain>, (const void*)k_contain<Plain>,
+                          (const void*)k_dirty<Plain>, (const void*)k_contain<Plain, 0>,
                           (const void*)k_stoplink<Plain>};
   for (int t = 0; t < TK_N && e == hipSuccess; ++t) e = family({ks[t]}, d.sched[t]);
   return e;
 }
 
 void launch_advance(const Dev& d, float dt, hipStream_t s) {
-  k_advance<<<d.sched[TK_ADVANCE], TPB, 0, s>>>(Plain{d}, dt);
+  if (d.periodic) k_advance<Plain, 1><<<d.sched[TK_ADVANCE], TPB, 0, s>>>(Plain{d}, dt);
+  else k_advance<Plain, 0><<<d.sched[TK_ADVANCE], TPB, 0, s>>>(Plain{d}, dt);
   k_spawn_scan<<<1, 1024, 0, s>>>(Plain{d});
 }
 void launch_mark_now(const Dev& d, hipStream_t s) {
@@ -3042,7 +3244,8 @@ void launch_dirty(const Dev& d, hipStream_t s) {
   k_dirty<<<d.sched[TK_DIRTY], TPB, 0, s>>>(Plain{d});
 }
 void launch_contain(const Dev& d, hipStream_t s) {
-  k_contain<<<d.sched[TK_CONTAIN], TPB, 0, s>>>(Plain{d});
+  if (d.periodic) k_contain<Plain, 1><<<d.sched[TK_CONTAIN], TPB, 0, s>>>(Plain{d});
+  else k_contain<Plain, 0><<<d.sched[TK_CONTAIN], TPB, 0, s>>>(Plain{d});
 }
 void launch_stoplink(const Dev& d, hipStream_t s) {
   k_stoplink<<<d.sched[TK_STOPLINK], TPB, 0, s>>>(Plain{d});
@@ -3166,7 +3369,10 @@ void launch_batch_step(const BatchLaunch& L, double dt, hipStream_t s) {
   const uint32_t one = L.site[BS_ONE].total, tiles = L.site[BS_TILES].total;
   if (L.site[BS_RESAMPLE].total)
     k_resample<<<L.site[BS_RESAMPLE].total, TPB, 0, s>>>(bind_of(L, BS_RESAMPLE));
-  k_advance<<<L.site[BS_ADVANCE].total, TPB, 0, s>>>(bind_of(L, BS_ADVANCE), (float)dt);
+  if (L.any_periodic)
+    k_advance<Batch, 2><<<L.site[BS_ADVANCE].total, TPB, 0, s>>>(bind_of(L, BS_ADVANCE), (float)dt);
+  else
+    k_advance<Batch, 0><<<L.site[BS_ADVANCE].total, TPB, 0, s>>>(bind_of(L, BS_ADVANCE), (float)dt);
   k_spawn_scan<<<one, 1024, 0, s>>>(bind_of(L, BS_ONE));
   k_mark_now<<<L.site[BS_MARKNOW].total, TPB, 0, s>>>(bind_of(L, BS_MARKNOW));
   k_branch<<<L.site[BS_BRANCH].total, TPB, 0, s>>>(bind_of(L, BS_BRANCH));
@@ -3177,7 +3383,8 @@ void launch_batch_step(const BatchLaunch& L, double dt, hipStream_t s) {
   k_scatter<<<L.site[BS_SCATTER].total, TPB, 0, s>>>(bind_of(L, BS_SCATTER));
   k_scatter_children<<<L.site[BS_CHILDREN].total, TPB, 0, s>>>(bind_of(L, BS_CHILDREN));
   k_dirty<<<L.site[BS_DIRTY].total, TPB, 0, s>>>(bind_of(L, BS_DIRTY));
-  k_contain<<<L.site[BS_CONTAIN].total, TPB, 0, s>>>(bind_of(L, BS_CONTAIN));
+  if (L.any_periodic) k_contain<Batch, 2><<<L.site[BS_CONTAIN].total, TPB, 0, s>>>(bind_of(L, BS_CONTAIN));
+  else k_contain<Batch, 0><<<L.site[BS_CONTAIN].total, TPB, 0, s>>>(bind_of(L, BS_CONTAIN));
   k_stoplink<<<L.site[BS_STOPLINK].total, TPB, 0, s>>>(bind_of(L, BS_STOPLINK));
   if (L.site[BS_NUCTEST].total) {
     k_nuc_test<<<L.site[BS_NUCTEST].total, TPB, 0, s>>>(bind_of(L, BS_NUCTEST));

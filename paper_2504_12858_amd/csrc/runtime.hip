@@ -43,6 +43,12 @@ uint64_t next_pow2(uint64_t v) {
   return p;
 }
 
+// Cells along axis a: ceil(L / h), or L / h exactly on a periodic axis.
+static double cells_along(const ge_params* p, int a) {
+  const double m = (p->hi[a] - p->lo[a]) / p->h;
+  return ((p->periodic >> a) & 1) ? std::nearbyint(m) : std::ceil(m);
+}
+
 const char* check_params(const ge_params* p) {
   if (!p) return "null params";
   for (int a = 0; a < 3; ++a) {
@@ -66,8 +72,10 @@ const char* check_params(const ge_params* p) {
   double nb_total = 1;
   for (int a = 0; a < 3; ++a) {
     double L = p->hi[a] - p->lo[a];
-    diag += L * L;
-    double nc = std::ceil(L / p->h);
+    // A grain grows across a periodic face by up to one period.
+    const double ext = ((p->periodic >> a) & 1) ? 2.0 * L : L;
+    diag += ext * ext;
+    double nc = cells_along(p, a);
     if (nc > (1 << 20)) return "too many cells along an axis";
     nb_total *= std::ceil(nc / ge::BRICK);
     if (p->field_n[a] < 0 || p->field_n[a] == 1) return "field_n must be 0 or >= 2";
@@ -75,6 +83,16 @@ const char* check_params(const ge_params* p) {
   if (std::sqrt(diag) / p->lambda0 > MAX_SITE_RANGE) return "box too large for lambda0 (site range)";
   if (nb_total * ge::BRICK_CELLS > 4294967295.0) return "too many cells (2^32)";
   if (p->resort_every < 0) return "resort_every must be >= 0";
+  if (p->periodic < 0 || p->periodic > 7) return "periodic must be a mask of axes (0..7)";
+  if (p->periodic) {
+    if (p->cap_grains > (1 << 26) - 8) return "cap_grains out of range for periodic axes";
+    for (int a = 0; a < 3; ++a) {
+      if (!((p->periodic >> a) & 1)) continue;
+      const double m = (p->hi[a] - p->lo[a]) / p->h;
+      if (std::fabs(m - std::nearbyint(m)) > 1e-6 * m || std::nearbyint(m) < 3)
+        return "a periodic axis must be a whole number (>= 3) of cells h";
+    }
+  }
   return nullptr;
 }
 
@@ -83,7 +101,7 @@ Geometry geometry(const ge_params* p) {
   g.n_cells = 1;
   g.n_bricks = 1;
   for (int a = 0; a < 3; ++a) {
-    g.n[a] = (int32_t)std::max(1.0, std::ceil((p->hi[a] - p->lo[a]) / p->h));
+    g.n[a] = (int32_t)std::max(1.0, cells_along(p, a));
     g.nb[a] = (g.n[a] + ge::BRICK - 1) / ge::BRICK;
     g.n_bricks *= (uint64_t)g.nb[a];
   }
@@ -405,6 +423,12 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.inv_h = (float)(1.0 / p->h);
   d.n_bricks = (uint32_t)g.n_bricks;
   d.stencil8 = (2.0 * p->rc <= p->h) ? 1 : 0;
+  d.periodic = p->periodic;
+  for (int a = 0; a < 3; ++a) {
+    const double L = p->hi[a] - p->lo[a];
+    d.L[a] = (float)L;
+    d.invL[a] = (float)(1.0 / L);
+  }
   d.lambda0 = (float)p->lambda0;
   d.rc2 = (float)(p->rc * p->rc);
   d.rc_half = (float)(0.5 * p->rc);
@@ -1716,6 +1740,8 @@ ge_status ge_batch_create(int32_t n, const ge_params* params, void* workspace, s
     b->L.site[k].gsz = (const uint32_t*)(b->base + b->off_gsz[0]) + (size_t)k * n;
   }
   b->R = b->mem[0]->resort_every;
+  b->L.any_periodic = 0;
+  for (ge_ctx* m : b->mem) b->L.any_periodic |= m->d.periodic != 0 ? 1 : 0;
   *out = b;
   return GE_OK;
 }

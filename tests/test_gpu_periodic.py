@@ -1,0 +1,213 @@
+"""Periodic lateral boundaries on the GPU (Sec. 3.4; reading R16) against
+the FP64 oracle: a grain meeting its own image and two grains meeting
+across a face at the closed-form steps, a site inside a grain through a
+face, grain maps and deposition through a face, a plane cut that melts a
+ball straddling a face (claims and particles as sets, exactly), a periodic
+directional run with grains growing through the faces (grain maps agree),
+recorded sequences against plain steps, and the parameter checks."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2504_12858_amd import binding as B
+from paper_2504_12858_amd import workloads as W
+from tests.gpu_helpers import (context_for, gpu_claims, gpu_parts, orc_claims, orc_parts,
+                               require_gpu)
+
+pytestmark = pytest.mark.gpu
+
+LAM = 5e-6
+Q0 = np.array([[1.0, 0.0, 0.0, 0.0]])
+VDT = (W.KIN_A[0] * 5.0 ** 2 + W.KIN_A[1] * 5.0 ** 3) * 1e-4
+HI = (20 * LAM, 26 * LAM, 60 * LAM)
+
+
+def _pair(periodic, branching=1, field=None, **kw):
+    f = field or W.Field(W.FIELD_UNIFORM, dT=5.0)
+    p = B.make_params((0, 0, 0), HI, LAM, LAM, LAM, W.KIN_A, W.KIN_B, branching=branching,
+                      periodic=periodic, cap_particles=1 << 16, cap_stopped=1 << 16,
+                      cap_claim_bricks=1 << 12, **kw)
+    ctx = B.Context(p)
+    ctx.set_thermal_field(f)
+    o = Oracle((0, 0, 0), HI, LAM, LAM, LAM, W.KIN_A, W.KIN_B, periodic=periodic)
+    o.set_field(f)
+    o.set_branching(branching)
+    return ctx, o
+
+
+def _first_step(gap0, rc):
+    s, n = 0.0, 0
+    while True:
+        n += 1
+        s += VDT
+        if gap0 - 2.0 * s < rc:
+            return n
+
+
+def _states_by_dir(parts):
+    return {(int(g), int(d)): int(s) for g, d, s in zip(parts["grain"], parts["dir"], parts["state"])}
+
+
+def test_grain_meets_its_own_image():
+    """+-x particles of one nucleus (branching off) stop at the step where
+    L_x - 2 s drops below rc, +-y at L_y; as in the oracle."""
+    require_gpu()
+    nx, ny = _first_step(HI[0], LAM), _first_step(HI[1], LAM)
+    c = np.array([[0.3 * LAM, 25.6 * LAM, 30 * LAM]])
+    ctx, o = _pair(3, branching=0)
+    ctx.init_grains(c, Q0, np.array([0], np.int32))
+    o.init_grains(c, Q0, np.array([0], np.int32))
+    ctx.step(1e-4, nx - 1)
+    assert set(_states_by_dir(ctx.particles()).values()) == {0}
+    ctx.step(1e-4, 1)
+    st = _states_by_dir(ctx.particles())
+    assert [st[(0, d)] for d in range(6)] == [1, 1, 0, 0, 0, 0]
+    ctx.step(1e-4, ny - nx - 1)
+    assert [_states_by_dir(ctx.particles())[(0, d)] for d in (2, 3)] == [0, 0]
+    ctx.step(1e-4, 1)
+    assert [_states_by_dir(ctx.particles())[(0, d)] for d in range(6)] == [1, 1, 1, 1, 0, 0]
+    o.step(1e-4, ny)
+    op, _ = orc_parts(o)
+    assert _states_by_dir(op) == _states_by_dir(ctx.particles())
+    ctx.close()
+
+
+def test_two_grains_meet_across_a_face():
+    require_gpu()
+    n = _first_step(5 * LAM, LAM)
+    c = np.array([[2 * LAM, 13 * LAM, 30 * LAM], [HI[0] - 3 * LAM, 13 * LAM, 30 * LAM]])
+    ctx, o = _pair(1, branching=0)
+    ctx.init_grains(c, np.repeat(Q0, 2, 0), np.array([0, 0], np.int32))
+    ctx.step(1e-4, n - 1)
+    assert set(_states_by_dir(ctx.particles()).values()) == {0}
+    st = ctx.step(1e-4, 1)
+    assert st["contained"] == 2 and st["exited"] == 0
+    stopped = {k for k, v in _states_by_dir(ctx.particles()).items() if v == 1}
+    assert stopped == {(0, 1), (1, 0)}
+    ctx.close()
+
+
+def test_site_inside_a_grain_through_the_face():
+    require_gpu()
+    c = np.array([[HI[0] - 3 * LAM, 13 * LAM, 30 * LAM]])
+    site = np.array([[2 * LAM, 13 * LAM, 30 * LAM]])
+    for periodic, fired in ((1, 0), (0, 1)):
+        ctx, _ = _pair(periodic)
+        ctx.init_grains(c, Q0, np.array([10], np.int32))
+        ctx.nucleate(site, np.array([1.0]), Q0)
+        ctx.step(1e-9, 1)
+        # 1: fired; a site inside a grain stays unfired (dormant or engulfed).
+        assert (int(ctx.site_states()[0]) == 1) == bool(fired)
+        ctx.close()
+
+
+def test_grain_map_and_deposition_through_the_face():
+    require_gpu()
+    face = np.array([[18.5 * LAM, 10.5 * LAM, 30.5 * LAM]])
+    n = np.array([20, 26, 60], np.int32)
+    ctx, o = _pair(1, field_n=(11, 14, 31))
+    ctx.init_grains(face, Q0, np.array([6], np.int32))
+    o.init_grains(face, Q0, np.array([6], np.int32))
+    gm = ctx.grain_map(n, np.zeros(3), np.array([LAM] * 3))
+    om = o.grain_map(n, np.zeros(3), np.array([LAM] * 3))
+    np.testing.assert_array_equal(gm, om)
+    ball = (2 * 6 + 1) * (2 * 36 + 12 + 3) // 3
+    assert (gm > 0).sum() == ball and (gm[:, :, :5] > 0).any()
+    sp = np.array([2 * LAM] * 3)
+    ctx.set_deposition_grid((10, 13, 30), sp / 2, sp)
+    got = ctx.mushy_counts()
+    np.testing.assert_array_equal(got, o.deposit_counts((10, 13, 30), sp / 2, sp))
+    assert got.sum() == ball
+    ctx.close()
+
+
+def test_plane_cut_of_a_ball_straddling_a_face():
+    """dT = G (z_cut - z) cuts a ball that reaches through the face x = L:
+    melted sites, removed and re-activated particles equal the oracle's, as
+    sets."""
+    require_gpu()
+    c = np.array([[HI[0] - 2 * LAM, 13 * LAM, 30 * LAM]])
+    z_cut = c[0, 2] + 2.5 * LAM
+    f = W.Field(W.FIELD_LINEAR, dT0=1e4 * z_cut, grad=(0.0, 0.0, -1e4), rate=0.0)
+    ctx, o = _pair(1, field=f)
+    for m in (ctx, o):
+        m.init_grains(c, Q0, np.array([8], np.int32))
+        m.set_melting(True)
+    st = ctx.step(1e-4, 1)
+    o.step(1e-4, 1)
+    ms = o.melt_stats()
+    assert (st["melted"], st["removed"], st["reactivated"]) == \
+        (ms["melted"], ms["removed"], ms["reactivated"])
+    assert ms["melted"] > 50
+    gc, _ = gpu_claims(ctx)
+    oc, _ = orc_claims(o)
+    assert {(int(g), tuple(s), int(fl)) for g, s, fl in zip(gc["grain"], gc["site"].tolist(), gc["flags"])} == \
+        {(int(g), tuple(s), int(fl)) for g, s, fl in zip(oc["grain"], oc["site"].tolist(), oc["flags"])}
+    gp, _ = gpu_parts(ctx)
+    op, _ = orc_parts(o)
+    key = lambda p: {(int(g), tuple(s), int(d), int(t)) for g, s, d, t in
+                     zip(p["grain"], np.asarray(p["site"]).tolist(), p["dir"], p["state"])}
+    assert key(gp) == key(op)
+    ctx.close()
+
+
+def _directional():
+    w = W.directional(seed=5, n_grains=10, size=(0.2e-3, 0.2e-3, 0.3e-3), lambda0=5e-6,
+                      dT0=6.0, G=2e4, rate=0.0, dt=2e-3, n_steps=300)
+    w.periodic = 3
+    return w
+
+
+def test_periodic_directional_run_matches_the_oracle():
+    """Grains on the bottom face of a box periodic in x and y grow through
+    the lateral faces and compete across them; the grain maps of the HIP
+    path and the oracle agree."""
+    require_gpu()
+    w = _directional()
+    ctx = context_for(w)
+    st = ctx.step(w.dt, w.n_steps)
+    o = Oracle.from_workload(w)
+    o.step(w.dt, w.n_steps)
+    assert o.error == 0
+    p = ctx.particles()
+    outside = ((p["x"] < w.lo[0]) | (p["x"] >= w.hi[0]) | (p["y"] < w.lo[1]) | (p["y"] >= w.hi[1]))
+    print(f"active {st['n_active']} stopped {st['n_stopped']} contained {st['contained']} "
+          f"beyond the lateral faces {outside.sum()}", flush=True)
+    assert outside.sum() > 100
+    vox = 4e-6
+    n = np.array([int(round((h - l) / vox)) for l, h in zip(w.lo, w.hi)], np.int32)
+    gm = ctx.grain_map(n, np.array(w.lo), np.array([vox] * 3))
+    om = o.grain_map(n, np.array(w.lo), np.array([vox] * 3))
+    agree = (gm == om).mean()
+    print(f"map agreement {agree:.6f} solid {(om > 0).mean():.3f}", flush=True)
+    assert (om > 0).mean() > 0.2
+    assert agree >= 0.999
+    ctx.close()
+
+
+def test_periodic_replays_equal_plain_steps():
+    require_gpu()
+    w = _directional()
+    a, b = context_for(w), context_for(w)
+    b.use_graphs(False)
+    for n in (40, 33, 64):
+        sa, sb = a.step(w.dt, n), b.step(w.dt, n)
+        sa.pop("pair_tests")
+        sb.pop("pair_tests")
+        assert sa == sb
+    pa, _ = gpu_parts(a)
+    pb, _ = gpu_parts(b)
+    assert pa.tobytes() == pb.tobytes()
+    a.close()
+    b.close()
+
+
+def test_periodic_parameter_checks():
+    require_gpu()
+    for hi, h in (((20.5 * LAM, 26 * LAM, 60 * LAM), LAM), ((2 * LAM, 26 * LAM, 60 * LAM), LAM)):
+        p = B.make_params((0, 0, 0), hi, LAM, h, LAM, W.KIN_A, W.KIN_B, periodic=1)
+        with pytest.raises(B.GrainEnvError):
+            B.Context(p)
+    p = B.make_params((0, 0, 0), HI, LAM, LAM, LAM, W.KIN_A, W.KIN_B, periodic=8)
+    with pytest.raises(B.GrainEnvError):
+        B.Context(p)
