@@ -1074,20 +1074,27 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
   for (uint32_t k0 = it.begin; k0 < it.end; k0 += TPB) {
     const uint32_t k = k0 + threadIdx.x;
     uint32_t dep = NIL, rg = NIL;
+    // Children of this lane's spawner (mask 0 past the range), placed after
+    // the tests so that the cell and brick counts of a direction are added
+    // once per run of equal keys of the wave.
+    uint32_t mask = 0, g = 0;
+    int S[3] = {0, 0, 0};
+    float sc2 = 0.0f;
+    SlotCache wc{~0ull, -1};
     if (k < it.end) {
       const uint32_t i = spawn_item(D, v, s_off, k);
       const uint4 r = D.A[i];
-      const uint32_t g = rec_grain(r);
+      g = rec_grain(r);
       const int d = rec_dir(r);
       const float s2 = rec_s(r);
       // Reached site S = departure site + one step in direction d.
       const int dstep = (d & 1) ? -1 : 1;
-      const int S[3] = {rec_sx(r) + ((d >> 1) == 0 ? dstep : 0), rec_sy(r) + ((d >> 1) == 1 ? dstep : 0),
-                        rec_sz(r) + ((d >> 1) == 2 ? dstep : 0)};
+      S[0] = rec_sx(r) + ((d >> 1) == 0 ? dstep : 0);
+      S[1] = rec_sy(r) + ((d >> 1) == 1 ? dstep : 0);
+      S[2] = rec_sz(r) + ((d >> 1) == 2 ? dstep : 0);
       SlotCache sc{~0ull, -1};
       const uint32_t slot = D.spslot[k];
       const SlotWin win = load_win(D, slot, S[0], S[1], S[2]);
-      uint32_t mask = 0;
       for (int dd = 0; dd < 6; ++dd) {
         const int a = dd >> 1;
         const int sg = (dd & 1) ? -1 : 1;
@@ -1114,16 +1121,21 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       // The parent retires whether or not a child survives: without one, every
       // outer neighbour of S already belongs to the grain (interior point).
       D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
-      const float* G = D.gtab + (size_t)g * GT_STRIDE;
-      const float sc2 = s2 - D.lambda0;
-      SlotCache wc{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
-      for (int dd = 0; dd < 6; ++dd) {
-        if (!(mask & (1u << dd))) continue;
-        const P3 xc = place(D, lattice_pos(G, S[0], S[1], S[2], dd, sc2)).p;
+      sc2 = s2 - D.lambda0;
+      wc = SlotCache{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
+      cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
+      bbox_add(D, g, S[0], S[1], S[2]);
+      if (D.gcnt) dep = deposit_cell(D, D.gtab + (size_t)g * GT_STRIDE, S[0], S[1], S[2]);
+      if (D.melting) rg = g;
+      nsp += 1;
+    }
+    for (int dd = 0; dd < 6; ++dd) {
+      uint32_t ci = NIL;
+      if ((mask >> dd) & 1u) {
+        const P3 xc =
+            place(D, lattice_pos(D.gtab + (size_t)g * GT_STRIDE, S[0], S[1], S[2], dd, sc2)).p;
         const C3 c = cell_of(D, xc);
-        const uint32_t ci = cell_index(D, c.x, c.y, c.z);
-        atomicAdd(&D.ccnt[ci], 1u);
-        atomicAdd(&D.bcnt[ci / (uint32_t)BRICK_CELLS], 1u);
+        ci = cell_index(D, c.x, c.y, c.z);
         const int ta = dd >> 1, ts = (dd & 1) ? -1 : 1;
         const int tx = S[0] + (ta == 0 ? ts : 0), ty = S[1] + (ta == 1 ? ts : 0),
                   tz = S[2] + (ta == 2 ? ts : 0);
@@ -1131,11 +1143,11 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
         bbox_add(D, g, tx, ty, tz);
         nch += 1;
       }
-      cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
-      bbox_add(D, g, S[0], S[1], S[2]);
-      if (D.gcnt) dep = deposit_cell(D, G, S[0], S[1], S[2]);
-      if (D.melting) rg = g;
-      nsp += 1;
+      const Run rc = wave_run(ci);
+      if (ci != NIL && rc.off == 0) atomicAdd(&D.ccnt[ci], (uint32_t)rc.len);
+      const uint32_t bk = ci == NIL ? NIL : ci / (uint32_t)BRICK_CELLS;
+      const Run rb = wave_run(bk);
+      if (bk != NIL && rb.off == 0) atomicAdd(&D.bcnt[bk], (uint32_t)rb.len);
     }
     if (D.gcnt) {
       const Run run = wave_run(dep);
