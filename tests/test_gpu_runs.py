@@ -154,6 +154,26 @@ def test_cfl_error():
     assert e.value.status == B.GE_ECFL
 
 
+def test_empty_context_steps():
+    """No grains, no particles: steps (plain and recorded), the queries, the
+    grain map, deposition and melting all work on the empty state."""
+    require_gpu()
+    p = B.make_params((0, 0, 0), (1e-3,) * 3, 5e-6, 5e-6, 5e-6, W.KIN_A, W.KIN_B,
+                      cap_particles=1 << 12, cap_stopped=1 << 12, cap_claim_bricks=1 << 10,
+                      field_n=(8, 8, 8))
+    ctx = B.Context(p)
+    ctx.set_thermal_field(W.Field(W.FIELD_UNIFORM, dT=5.0))
+    ctx.set_deposition_grid((8, 8, 8), (0.0, 0.0, 0.0), (1.25e-4,) * 3)
+    ctx.set_melting(True)
+    for n in (1, 40):
+        st = ctx.step(1e-4, n)
+        assert (st["n_active"], st["n_stopped"], st["n_grains"], st["advanced"]) == (0, 0, 0, 0)
+    assert len(ctx.particles()) == 0 and len(ctx.claims()) == 0
+    assert not ctx.grain_map(np.array([4, 4, 4], np.int32), np.zeros(3), np.array([2.5e-4] * 3)).any()
+    assert ctx.mushy_counts().sum() == 0
+    ctx.close()
+
+
 def test_host_validation_errors():
     require_gpu()
     w = W.nucleus_uniform()
