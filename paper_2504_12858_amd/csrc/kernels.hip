@@ -1434,27 +1434,52 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     const bool rz = oz == 0 || (oz < 0 ? lz == 0 : lz == 3);
     if (rx && ry && rz) reach |= 1u << t;
   }
-  // The next brick of the wave is fetched during this one.
-  uint32_t b1 = ch.begin + (threadIdx.x >> 6) < ch.end ? D.occ[ch.begin + (threadIdx.x >> 6)] : 0u;
-  for (uint32_t k = ch.begin + (threadIdx.x >> 6); k < ch.end; k += TPB / 64) {
-    const uint32_t b = b1;
-    if (k + TPB / 64 < ch.end) b1 = D.occ[k + TPB / 64];
-    const uint4 own = D.binfo[b];
-    const uint32_t g = own.z;
-    bool foreign = false;
+  // Neighbour words of one brick, one neighbour per lane (lanes < 27).
+  struct Nb {
+    uint32_t be, gz, gw;
+    uint2 sb;
+  };
+  auto fetch = [&](uint32_t b, Nb& n) {
+    n = Nb{0u, 0u, 0u, make_uint2(1u, 0u)};
     if (lane < 27) {
       const int bx = (int)(b % (uint32_t)nbx) + lane % 3 - 1;
       const int by = (int)((b / (uint32_t)nbx) % (uint32_t)nby) + (lane / 3) % 3 - 1;
       const int bz = (int)(b / ((uint32_t)nbx * (uint32_t)nby)) + lane / 9 - 1;
       if (bx >= 0 && by >= 0 && bz >= 0 && bx < nbx && by < nby && bz < nbz) {
         const uint32_t nb = ((uint32_t)bz * (uint32_t)nby + (uint32_t)by) * (uint32_t)nbx + (uint32_t)bx;
-        const uint32_t be = D.bepoch[nb];
+        n.be = D.bepoch[nb];
         const uint4 inf = D.binfo[nb];
-        const uint2 sb = D.sbsum[nb];
-        if (be == epoch && !(inf.z == g && inf.w == g)) foreign = true;
-        if (sb.x <= sb.y && !(sb.x == g && sb.y == g)) foreign = true;
+        n.gz = inf.z;
+        n.gw = inf.w;
+        n.sb = D.sbsum[nb];
       }
     }
+  };
+  // Software pipeline: the words of the next brick of the wave are loaded
+  // during this one, and its index one brick earlier.
+  const uint32_t W = TPB / 64;
+  const uint32_t k0 = ch.begin + (threadIdx.x >> 6);
+  uint32_t b1 = k0 < ch.end ? D.occ[k0] : 0u;
+  uint32_t b2 = k0 + W < ch.end ? D.occ[k0 + W] : 0u;
+  uint4 own1 = make_uint4(0u, 0u, 0u, 0u);
+  Nb n1{0u, 0u, 0u, make_uint2(1u, 0u)};
+  if (k0 < ch.end) {
+    own1 = D.binfo[b1];
+    fetch(b1, n1);
+  }
+  for (uint32_t k = k0; k < ch.end; k += W) {
+    const uint32_t b = b1;
+    const uint4 own = own1;
+    const Nb nn = n1;
+    if (k + W < ch.end) {
+      b1 = b2;
+      own1 = D.binfo[b1];
+      fetch(b1, n1);
+    }
+    if (k + 2u * W < ch.end) b2 = D.occ[k + 2u * W];
+    const uint32_t g = own.z;
+    const bool foreign = (nn.be == epoch && !(nn.gz == g && nn.gw == g)) ||
+                         (nn.sb.x <= nn.sb.y && !(nn.sb.x == g && nn.sb.y == g));
     // Flagged bricks; the brick itself (bit 13) when it holds several grains
     // or lies on a periodic face (its cells' stencils wrap, and owner words
     // do not tell the periods apart).
