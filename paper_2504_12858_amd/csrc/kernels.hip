@@ -2,6 +2,8 @@
 //
 // One step (Sec. 2.1.2 growth and branching, Sec. 2.3 cell partitioning and
 // collision detection, Sec. 2.1.1 nucleation) runs as:
+//   k_resample   moving point-source field sampled onto the node grid
+//   k_melt_*, k_walkback   melting by walk-back, when enabled (Sec. 2.1.3)
 //   k_advance    undercooling at each active particle, kinetic law Eq. (2),
 //                advance along R e_d, box exit, spawner list, per-cell and
 //                per-brick counts of the particles that stay active
@@ -13,6 +15,8 @@
 //   k_cellscan   one wave per occupied brick, one lane per cell: cell starts
 //   k_scatter    records and positions -> cell-sorted arrays (ranks from
 //                wave-aggregated decrements of the cell counts)
+//   k_dirty      bricks whose particles can meet another grain; their cells'
+//                owner words and the list of particles to test
 //   k_contain    cell-stencil test against other grains' particles
 //   k_stoplink   moves newly stopped particles to the stopped store
 //   k_nuc_test / k_nuc_fire   nucleation of liquid sites past threshold
@@ -24,7 +28,9 @@
 //
 // Particle positions are recomputed from the record (grain, departure site,
 // direction, travel) with one function everywhere, so binning, containment
-// and export see identical FP32 values.
+// and export see identical FP32 values.  With periodic axes (Sec. 3.4) the
+// binned and stored position is that one wrapped into the box, its period
+// index kept in the owner word.
 #include "internal.h"
 
 #include <math.h>
