@@ -410,6 +410,43 @@ def melt_leg(ctx, w, steps=MELT_STEPS):
             "per_step_on": {k: round(v / (2 * steps), 1) for k, v in counts.items()}}
 
 
+PERIODIC_STEPS = 100
+
+
+def periodic_leg(schedule, plain_value, steps=PERIODIC_STEPS):
+    """Periodic lateral boundaries (Sec. 3.4 imposes periodic conditions on
+    the faces normal to x and y) at the bench's scale: the CET workload with
+    x and y periodic (periods of 2000 and 1000 cells; the moving-source field
+    wraps with the positions), advanced to the same 20M-active snapshot
+    target, then `steps` steps timed with HIP events on the context's stream
+    (recorded sequences) in the launch schedule of the plain run."""
+    import torch
+    s = torch.cuda.current_stream()
+    w = cet_workload()
+    w.periodic = 3
+    ctx = make_context(w)
+    snap, st0 = advance_to_snapshot(ctx, w, TARGET_ACTIVE)
+    ctx.set_schedule(schedule)
+    ctx.step(w.dt, 5, stats=False)
+    ctx.prepare_step(w.dt)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    st = ctx.step(w.dt, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = st["advanced"] / (ms * 1e-3)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return {"workload": "cet-moving-source-20M with x and y periodic", "snapshot_step": snap,
+            "active_at_snapshot": st0["n_active"], "steps": steps,
+            "ms_per_step": round(ms / steps, 4), "updates_per_s": value,
+            "vs_walls_updates_per_s": round(value / plain_value, 4),
+            "active_after": st["n_active"], "stopped_after": st["n_stopped"]}
+
+
 SOLUTE_STEPS = 20
 
 
@@ -535,6 +572,7 @@ def main():
     ap.add_argument("--no-solute", action="store_true")
     ap.add_argument("--no-mushy", action="store_true")
     ap.add_argument("--no-melt", action="store_true")
+    ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=3, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -637,6 +675,9 @@ def main():
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
+    if not args.no_periodic:
+        out["periodic"] = periodic_leg(out["config"]["schedule"], value)
+        log(f"[periodic] {out['periodic']}")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
         log(f"[adjoint] {out['adjoint']}")
