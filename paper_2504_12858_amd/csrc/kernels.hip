@@ -370,16 +370,21 @@ __device__ __forceinline__ bool claim_test(const Dev& D, uint32_t g, int sx, int
 // Grows grain g's lattice bounding box to include the site.  Plain reads
 // first: the box changes only at its extremes, and skipping the atomics in
 // the common case keeps thousands of spawners of one grain off six hot words.
-__device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int sy, int sz) {
+// Grows grain g's lattice bounding box to hold the box [lo, hi] of sites.
+__device__ __forceinline__ void bbox_add_box(const Dev& D, uint32_t g, const int lo[3],
+                                             const int hi[3]) {
   int32_t* b = D.gbox + (size_t)g * 6;
-  const int s[3] = {sx, sy, sz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (s[a] < __hip_atomic_load(b + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMin(b + a, s[a]);
-    if (s[a] > __hip_atomic_load(b + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMax(b + 3 + a, s[a]);
+    if (lo[a] < __hip_atomic_load(b + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(b + a, lo[a]);
+    if (hi[a] > __hip_atomic_load(b + 3 + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(b + 3 + a, hi[a]);
   }
+}
+__device__ __forceinline__ void bbox_add(const Dev& D, uint32_t g, int sx, int sy, int sz) {
+  const int s[3] = {sx, sy, sz};
+  bbox_add_box(D, g, s, s);
 }
 
 // Mushy-zone deposition: a lattice site that a grain has reached adds its
@@ -1130,7 +1135,17 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       sc2 = s2 - D.lambda0;
       wc = SlotCache{claim_key(g, S[0], S[1], S[2]), slot == NIL ? -1 : (int64_t)slot};
       cached_or(D, wc, g, S[0], S[1], S[2], M_REACHED);
-      bbox_add(D, g, S[0], S[1], S[2]);
+      // One bounding-box update for the reached site and the targets of its
+      // children (each one step from S).
+      int blo[3] = {S[0], S[1], S[2]}, bhi[3] = {S[0], S[1], S[2]};
+#pragma unroll
+      for (int dd = 0; dd < 6; ++dd) {
+        if (!((mask >> dd) & 1u)) continue;
+        const int a = dd >> 1;
+        if (dd & 1) blo[a] = S[a] - 1;
+        else bhi[a] = S[a] + 1;
+      }
+      bbox_add_box(D, g, blo, bhi);
       if (D.gcnt) dep = deposit_cell(D, D.gtab + (size_t)g * GT_STRIDE, S[0], S[1], S[2]);
       if (D.melting) rg = g;
       nsp += 1;
@@ -1146,7 +1161,6 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
         const int tx = S[0] + (ta == 0 ? ts : 0), ty = S[1] + (ta == 1 ? ts : 0),
                   tz = S[2] + (ta == 2 ? ts : 0);
         cached_or(D, wc, g, tx, ty, tz, M_CLAIMED);
-        bbox_add(D, g, tx, ty, tz);
         nch += 1;
       }
       const Run rc = wave_run(ci);
