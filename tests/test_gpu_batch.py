@@ -63,6 +63,32 @@ def test_batch_equals_plain_contexts():
     batch.close()
 
 
+def test_batch_with_periodic_members_equals_plain_contexts():
+    """Members with periodic lateral boundaries and members without share the
+    batched launches (which then decide per member); each equals its plain
+    context bit for bit."""
+    require_gpu()
+    ws = _workloads()[:2]
+    per = W.directional(seed=11, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0, h=10e-6)
+    per.periodic = 3
+    ws = [per] + ws
+    batch = B.Batch([B.params_from_workload(w, **CAPS) for w in ws])
+    for m, w in zip(batch.members, ws):
+        m.init_from_workload(w)
+    refs = [context_for(w, **CAPS) for w in ws]
+    for n in (40, 33, 64):
+        got = batch.step(DT, n)
+        for i, r in enumerate(refs):
+            want = r.step(DT, n)
+            assert _stats(got[i]) == _stats(want), (i, n)
+            assert _state(batch.members[i]) == _state(r), (i, n)
+    p = batch.members[0].particles()
+    assert ((p["x"] < 0) | (p["x"] >= 0.3e-3) | (p["y"] < 0) | (p["y"] >= 0.3e-3)).any()
+    for r in refs:
+        r.close()
+    batch.close()
+
+
 def test_batch_schedule_and_graphs_keep_results():
     """Odd block totals, the autotuner and graphs off change only speed."""
     require_gpu()
