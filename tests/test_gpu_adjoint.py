@@ -113,6 +113,54 @@ def test_gradient_matches_oracle_on_gpu_masks(ckpt_every):
     ctx.close()
 
 
+def test_gradient_through_a_periodic_face():
+    """x periodic, a node field periodic in x (dT = 5 + 2 sin(2 pi x / L)),
+    two grains whose particles cross the face x = L during the run and meet
+    across it: on the GPU's masks the replay and the gradient match the
+    oracle's, which take the field at the wrapped positions."""
+    require_gpu()
+    L = BOX[1][0]
+    n = (41, 5, 5)
+    x = np.arange(n[0]) * (L / 40)
+    data = np.broadcast_to((5.0 + 2.0 * np.sin(2 * np.pi * x / L)).astype(np.float32),
+                           (n[2], n[1], n[0]))
+    f = W.Field(W.FIELD_GRID, n=n, origin=(0.0, 0.0, 0.0), spacing=(L / 40, 0.25e-3, 0.25e-3),
+                data=np.ascontiguousarray(data))
+    centre = np.array([[L - 2 * LAM, 5e-4, 5e-4], [3 * LAM, 5.01e-4, 4.99e-4]])
+    q = W.shoemake_quaternions(W.rng(9), 2)
+    shells = np.array([3, 2], np.int32)
+    dt, N = 1e-3, 60
+    p = B.make_params(BOX[0], BOX[1], LAM, LAM, LAM, W.KIN_A, W.KIN_B, branching=0, periodic=1,
+                      cap_particles=1 << 16, cap_stopped=1 << 16, cap_claim_bricks=1 << 12,
+                      field_n=n)
+    ctx = B.Context(p)
+    ctx.set_thermal_field(f)
+    ctx.init_grains(centre, q, shells)
+    ctx.adjoint_forward(dt, N, ckpt_every=7)
+    tr = ctx.adjoint_tracked()
+    assert (tr["nact"] < N).any() and (tr["nact"] == N).any()
+    xg = ctx.adjoint_positions().cpu().numpy().astype(np.float64)
+    assert ((xg[:, 0] >= L) | (xg[:, 0] < 0)).any()   # some crossed the face
+    o = Oracle(BOX[0], BOX[1], LAM, LAM, LAM, W.KIN_A, W.KIN_B, branching=0, periodic=1)
+    o.set_field(f)
+    o.init_grains(centre, q, shells)
+    op = o.particles()
+    onact = o.adjoint_record(dt, N)
+    okey = ident(op["grain"], op["site"], op["dir"])[: len(onact)]
+    m = dict(zip(okey.tolist(), onact.tolist()))
+    same = np.array([m.get(k) == v for k, v in zip(ident(tr["grain"], tr["site"], tr["dir"]).tolist(),
+                                                   tr["nact"].tolist())])
+    assert same.mean() >= 0.99, same.mean()
+    parts = _tracked_parts(tr)
+    xo = o.adjoint_replay(np.array(W.KIN_A), 0.0, parts, tr["nact"], 0.0, dt, N)
+    np.testing.assert_allclose(xg, xo, rtol=0, atol=1e-5 * 1e-3)
+    dLdx = 2.0 * (xg - (xo + W.rng(4).normal(scale=1e-6, size=xo.shape)))
+    g = np.array(ctx.adjoint_backward(dLdx.astype(np.float32)))
+    go = o.adjoint_grad(parts, tr["nact"], 0.0, dt, N, dLdx.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(g, go, rtol=2e-4)
+    ctx.close()
+
+
 def test_envelope_run_autograd():
     """torch.autograd through EnvelopeRun: loss = sum |x_N - xhat|^2; the
     parameter gradient equals the adjoint call on dL/dx = 2 (x_N - xhat)
