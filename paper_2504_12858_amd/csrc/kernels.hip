@@ -1671,9 +1671,11 @@ struct CellOwners {
 // With periodic axes a stencil cell past a face wraps, and every particle
 // there is a candidate: the owner word cannot tell a particle's own period
 // from the next one.
+// The brick word of the previous cell is reused when the cell lies in the
+// same brick (the cells of a stencil mostly do): brick cb, its word cbw.
 template <bool PER>
 __device__ __forceinline__ CellOwners cell_owners(const Dev& D, uint32_t epoch, int x, int y,
-                                                  int z, uint32_t g) {
+                                                  int z, uint32_t g, uint32_t& cb, uint2& cbw) {
   bool cross = false;
   if constexpr (PER) {
     const int xw = wrap_cell(x, D.n[0]), yw = wrap_cell(y, D.n[1]), zw = wrap_cell(z, D.n[2]);
@@ -1685,7 +1687,11 @@ __device__ __forceinline__ CellOwners cell_owners(const Dev& D, uint32_t epoch, 
   CellOwners o;
   o.b = brick_index(D, x, y, z);
   o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
-  const uint2 bw = D.bown[o.b];
+  if (o.b != cb) {
+    cb = o.b;
+    cbw = D.bown[o.b];
+  }
+  const uint2 bw = cbw;
   const uint2 cw = D.cown[o.ci];
   const uint32_t aown = bw.x != epoch ? NIL : (bw.y == BOWN_CELLS ? cw.x : bw.y);
   o.act = aown != NIL && (cross || aown != g);
@@ -1794,13 +1800,15 @@ __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, con
   constexpr int NL = S8 ? 2 : 3, PL = S8 ? 4 : 9;
   act = 0u;
   stp = 0u;
+  uint32_t cb = NIL;
+  uint2 cbw = make_uint2(0u, 0u);
   for (int l = 0; l < NL; ++l) {
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
       const int k = l * PL + u;
       int x, y, z;
       if (!stencil_cell<S8>(st, k, x, y, z)) continue;
-      const CellOwners o = cell_owners<PER>(D, epoch, x, y, z, g);
+      const CellOwners o = cell_owners<PER>(D, epoch, x, y, z, g, cb, cbw);
       act |= (uint32_t)o.act << k;
       stp |= (uint32_t)o.stp << k;
     }
