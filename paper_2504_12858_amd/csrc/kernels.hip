@@ -1725,18 +1725,28 @@ struct CellRanges {
   uint32_t ast, aen, sst, sen, hd;
 };
 
-__device__ __forceinline__ CellRanges cell_ranges(const Dev& D, const CellOwners& o) {
+// The brick's end of the active store is read only for its last cell; its
+// stopped-store word is reused from the previous cell of the same brick
+// (brick sb, word sbw).
+__device__ __forceinline__ CellRanges cell_ranges(const Dev& D, const CellOwners& o, uint32_t& sb,
+                                                  uint2& sbw) {
   CellRanges r = {0u, 0u, 0u, 0u, NIL};
   const bool last = (o.ci & (uint32_t)(BRICK_CELLS - 1)) == (uint32_t)(BRICK_CELLS - 1);
   if (o.act) {
-    const uint4 inf = D.binfo[o.b];
-    const uint32_t c0 = D.cstart[o.ci];
-    const uint32_t c1 = last ? 0u : D.cstart[o.ci + 1];
-    r.ast = c0;
-    r.aen = last ? inf.x + inf.y : c1;
+    r.ast = D.cstart[o.ci];
+    if (last) {
+      const uint4 inf = D.binfo[o.b];
+      r.aen = inf.x + inf.y;
+    } else {
+      r.aen = D.cstart[o.ci + 1];
+    }
   }
   if (o.stp) {
-    const uint2 bs = D.bsinfo[o.b];
+    if (o.b != sb) {
+      sb = o.b;
+      sbw = D.bsinfo[o.b];
+    }
+    const uint2 bs = sbw;
     const uint32_t t0 = D.sstart[o.ci];
     const uint32_t t1 = last ? 0u : D.sstart[o.ci + 1];
     const uint32_t hd = D.shead[o.ci];
@@ -1820,6 +1830,8 @@ template <bool S8, bool PER>
 __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st, uint32_t act,
                                                 uint32_t stp, uint32_t lane, uint3* e) {
   uint32_t n = 0;
+  uint32_t sb = NIL;
+  uint2 sbw = make_uint2(0u, 0u);
   auto cell = [&](int k) {
     if (!(((act | stp) >> k) & 1u)) return;
     int x, y, z;
@@ -1834,7 +1846,7 @@ __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st,
     o.ci = o.b * (uint32_t)BRICK_CELLS + local_index(x, y, z);
     o.act = (act >> k) & 1u;
     o.stp = (stp >> k) & 1u;
-    const CellRanges r = cell_ranges(D, o);
+    const CellRanges r = cell_ranges(D, o, sb, sbw);
     if (o.act) e[n++] = make_uint3(r.ast, r.aen - r.ast, (CE_ACTIVE << 6) | lane);
     if (o.stp) {
       e[n++] = make_uint3(r.sst, r.sen - r.sst, (CE_STOPPED << 6) | lane);
