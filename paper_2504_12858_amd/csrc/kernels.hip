@@ -1468,9 +1468,10 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
       if (bx >= 0 && by >= 0 && bz >= 0 && bx < nbx && by < nby && bz < nbz) {
         const uint32_t nb = ((uint32_t)bz * (uint32_t)nby + (uint32_t)by) * (uint32_t)nbx + (uint32_t)bx;
         n.be = D.bepoch[nb];
-        const uint4 inf = D.binfo[nb];
-        n.gz = inf.z;
-        n.gw = inf.w;
+        // Grain range only: the upper half of the brick's info word.
+        const uint2 gr = reinterpret_cast<const uint2*>(D.binfo + nb)[1];
+        n.gz = gr.x;
+        n.gw = gr.y;
         n.sb = D.sbsum[nb];
       }
     }
