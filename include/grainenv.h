@@ -194,7 +194,7 @@ typedef struct ge_step_stats {
 
 /* Exported particle: position computed on the device, binning cell. */
 typedef struct ge_particle_rec {
-  float x, y, z;
+  float x, y, z;     /* position [m]; on periodic axes unwrapped (lattice-anchored) */
   float s;           /* travel since the departure site [m] */
   int32_t site[3];   /* departure lattice site (crystal frame) */
   uint32_t grain;
@@ -338,8 +338,9 @@ ge_status ge_step(ge_ctx* ctx, double dt, int32_t n_steps, ge_step_stats* stats)
    With out == NULL (or out_bytes too small) only *needed is set.  The call
    synchronises when out is host memory.  For PARTICLES and CLAIMS, non-null
    args select a window: only particles (claimed sites) whose world position
-   lies in [origin, origin + n * spacing) are exported; with args == NULL
-   everything is.  GRAIN_MAP requires args. */
+   (wrapped into the box on periodic axes) lies in [origin, origin + n *
+   spacing) are exported; with args == NULL everything is.  GRAIN_MAP
+   requires args. */
 ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args, void* out,
                             size_t out_bytes, size_t* needed);
 
