@@ -380,9 +380,12 @@ inline int64_t cell_key(const int32_t n[3], int32_t i, int32_t j, int32_t k) {
   return ((int64_t)k * n[1] + j) * n[0] + i;
 }
 
+// Cells per axis: ceil(L / h); on a periodic axis the period is a whole
+// number of cells, L / h rounded (so that the last cell borders the first).
 void grid_dims(const Params& p, int32_t n[3]) {
   for (int a = 0; a < 3; ++a) {
-    double m = std::ceil((p.hi[a] - p.lo[a]) / p.h);
+    const double r = (p.hi[a] - p.lo[a]) / p.h;
+    double m = periodic_axis(p, a) ? std::nearbyint(r) : std::ceil(r);
     n[a] = (int32_t)std::max(1.0, m);
   }
 }

@@ -67,6 +67,29 @@ def test_periodic_cells_equal_brute_force_over_images(periodic, seed):
     assert own.sum() > 0
 
 
+def test_period_that_does_not_divide_exactly_in_fp64():
+    """A period of 50 cells of 4 um: (0.2 mm) / (4 um) is 50.00000000000001 in
+    FP64, and the grid must still have exactly 50 cells along the periodic
+    axis (the last cell borders the first), else contacts across the face
+    are missed."""
+    lam = 4e-6
+    L = 0.2e-3
+    assert (L / lam) != 50.0 and round(L / lam) == 50
+    g = W.rng(3)
+    centre = g.random((3, 3)) * L
+    quat = W.shoemake_quaternions(g, 3)
+    grain = np.repeat(np.arange(3, dtype=np.int32), 1500)
+    site = g.integers(-30, 31, size=(grain.size, 3)).astype(np.int32)
+    parts = dict(grain=grain, site=site, dir=g.integers(0, 6, grain.size).astype(np.int32),
+                 s=g.random(grain.size) * lam, state=np.zeros(grain.size, np.int32))
+    o = Oracle((0, 0, 0), (L,) * 3, lam, lam, lam, W.KIN_A, W.KIN_B, box_exit=0, periodic=7)
+    o.set_field(W.Field(W.FIELD_UNIFORM, dT=0.0))
+    o.load_state(centre, quat, parts, _EMPTY, np.zeros(0, np.int32), 0.0, 0)
+    cells = o.contain_decisions(0)
+    np.testing.assert_array_equal(cells, o.contain_decisions(1))
+    assert cells.sum() > 0
+
+
 def _first_step(gap0, rate, rc):
     """First step n with gap0 - rate * s_n < rc, s_n the FP64 running sum of
     v dt; also the margin to the threshold at the steps around it."""
