@@ -185,6 +185,42 @@ def test_periodic_directional_run_matches_the_oracle():
     ctx.close()
 
 
+def test_periodic_cet_with_melting_matches_the_oracle():
+    """A scaled CET run (moving source, bulk and face nucleation) periodic in
+    x and y with melting on: melted, removed and re-activated totals within
+    1 % of the oracle's run, grain maps equal on >= 99.9 % of voxels."""
+    require_gpu()
+    w = W.cet(seed=3, size=(0.4e-3, 0.2e-3, 0.1e-3), lambda0=4e-6, grid_n=24, dT0=6.0,
+              rate=2.0, bulk_density=2e12, face_density=2e8, dt=1.5e-3, n_steps=300,
+              U=0.005, q=0.004)
+    w.periodic = 3
+    ctx = context_for(w)
+    ctx.set_melting(True)
+    st = ctx.step(w.dt, w.n_steps)
+    o = Oracle.from_workload(w)
+    o.set_melting(True)
+    tot = {"melted": 0, "removed": 0, "reactivated": 0}
+    for _ in range(w.n_steps):
+        o.step(w.dt, 1)
+        for k, v in o.melt_stats().items():
+            if k in tot:
+                tot[k] += v
+    assert o.error == 0
+    print(f"gpu melted {st['melted']} removed {st['removed']} reactivated {st['reactivated']}; "
+          f"oracle {tot}", flush=True)
+    assert st["melted"] > 1000
+    for k in tot:
+        assert abs(st[k] - tot[k]) <= 0.01 * tot[k], k
+    vox = 4e-6
+    n = np.array([int(round((h - l) / vox)) for l, h in zip(w.lo, w.hi)], np.int32)
+    gm = ctx.grain_map(n, np.array(w.lo), np.array([vox] * 3))
+    om = o.grain_map(n, np.array(w.lo), np.array([vox] * 3))
+    agree = (gm == om).mean()
+    print(f"map agreement {agree:.6f} solid {(om > 0).mean():.3f}", flush=True)
+    assert agree >= 0.999
+    ctx.close()
+
+
 def test_periodic_replays_equal_plain_steps():
     require_gpu()
     w = _directional()
