@@ -35,12 +35,14 @@ def _state(ctx):
     return p.tobytes(), c.tobytes()
 
 
-def test_solute_directional_matches_oracle():
+@pytest.mark.parametrize("periodic", [0, 3])
+def test_solute_directional_matches_oracle(periodic):
     """Eight grains grow from the bottom face through a lateral segregation
-    pattern; the grain maps of the HIP path and the oracle agree on >= 99.9 %
-    of the voxels."""
+    pattern (with walls, or periodic in x and y); the grain maps of the HIP
+    path and the oracle agree on >= 99.9 % of the voxels."""
     require_gpu()
     w, spec = W.directional_solute()
+    w.periodic = periodic
     print(f"directional solute: {w.n_steps} steps, field every {EVERY}", flush=True)
     ctx = context_for(w)
     st = _run_gpu(ctx, w, spec, w.n_steps)
