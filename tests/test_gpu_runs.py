@@ -51,11 +51,13 @@ def test_directional_scaled_grain_map_parity(h):
     assert abs(st["n_active"] - o.n_active()) <= 0.01 * o.n_active()
 
 
-@pytest.mark.parametrize("h", [None, 8e-6])
-def test_cet_scaled_grain_map_parity(h):
-    """Moving Rosenthal source resampled each step, bulk and face nuclei."""
+@pytest.mark.parametrize("h,periodic", [(None, 0), (8e-6, 0), (8e-6, 3)])
+def test_cet_scaled_grain_map_parity(h, periodic):
+    """Moving Rosenthal source resampled each step, bulk and face nuclei
+    (with walls, or periodic in x and y)."""
     require_gpu()
     w = _scaled_cet(h=h)
+    w.periodic = periodic
     print(f"cet scaled: {len(w.site_dTn)} sites, {w.n_steps} steps", flush=True)
     ctx = context_for(w)
     st = ctx.step(w.dt, w.n_steps)
