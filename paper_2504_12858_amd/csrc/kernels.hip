@@ -1862,6 +1862,14 @@ __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st,
   }
 }
 
+// Orders the LDS accesses of this wave's lanes: every access before it
+// (by any lane of the wave) is complete and visible to every access after it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct ContainShared {
   uint32_t n, tests;
   float4 pos[TPB];
@@ -1922,7 +1930,9 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
     S.hit[threadIdx.x] = 0u;
     // Rounds: the lanes whose sources fit after those of the lanes before
     // them (at most 3 per stencil cell, so every round takes one lane at
-    // least).  The loop bounds are the same for the block's four waves.
+    // least).  Entries, positions and hit flags are the wave's own, so the
+    // rounds order LDS within the wave only and the block's waves run
+    // independently.
     uint32_t ne = (uint32_t)__popc(act) + 2u * (uint32_t)__popc(stp);
     for (;;) {
       uint32_t tot;
@@ -1934,7 +1944,7 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
         stencil_entries<S8, PER>(D, st, act, stp, lane, ent + e0);
         ne = 0u;
       }
-      __syncthreads();
+      wave_lds_sync();
       for (uint32_t t = lane; t < used; t += 64u) {
         const uint3 en = ent[t];
         const uint32_t L = w * 64u + (en.z & 63u);
@@ -1949,8 +1959,8 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
                               grain_of(pq), rc2, tests);
         if (h) S.hit[L] = 1u;
       }
-      __syncthreads();
-      if (__syncthreads_or(ne > 0u) == 0) break;
+      wave_lds_sync();
+      if (!__any(ne > 0u)) break;
     }
     const bool hit = k < ch.end && S.hit[threadIdx.x] != 0u;
     const unsigned long long m = __ballot(hit);
