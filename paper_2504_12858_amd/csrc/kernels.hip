@@ -1080,10 +1080,27 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
   const SpawnView v = spawn_view(D, s_off);
   const Chunk it = chunk_of(V, v.total, 1u);
   uint32_t nsp = 0, nch = 0;
+  // The next round's spawner (index, record, claim slot) is loaded during
+  // this round, off the chain of dependent loads.  Each record is read and
+  // written only in its own spawner's round.
+  uint32_t ni = 0, nslot = NIL;
+  uint4 nr = make_uint4(0u, 0u, 0u, 0u);
+  if (it.begin + threadIdx.x < it.end) {
+    ni = spawn_item(D, v, s_off, it.begin + threadIdx.x);
+    nr = D.A[ni];
+    nslot = D.spslot[it.begin + threadIdx.x];
+  }
   // The trip count is the same for the block's waves, so the deposition of
   // the reached sites can be added once per run of equal cells of a wave.
   for (uint32_t k0 = it.begin; k0 < it.end; k0 += TPB) {
     const uint32_t k = k0 + threadIdx.x;
+    const uint32_t i = ni, slot = nslot;
+    const uint4 r = nr;
+    if (k + TPB < it.end) {
+      ni = spawn_item(D, v, s_off, k + TPB);
+      nr = D.A[ni];
+      nslot = D.spslot[k + TPB];
+    }
     uint32_t dep = NIL, rg = NIL;
     // Children of this lane's spawner (mask 0 past the range), placed after
     // the tests so that the cell and brick counts of a direction are added
@@ -1093,8 +1110,6 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     float sc2 = 0.0f;
     SlotCache wc{~0ull, -1};
     if (k < it.end) {
-      const uint32_t i = spawn_item(D, v, s_off, k);
-      const uint4 r = D.A[i];
       g = rec_grain(r);
       const int d = rec_dir(r);
       const float s2 = rec_s(r);
@@ -1104,7 +1119,6 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       S[1] = rec_sy(r) + ((d >> 1) == 1 ? dstep : 0);
       S[2] = rec_sz(r) + ((d >> 1) == 2 ? dstep : 0);
       SlotCache sc{~0ull, -1};
-      const uint32_t slot = D.spslot[k];
       const SlotWin win = load_win(D, slot, S[0], S[1], S[2]);
       for (int dd = 0; dd < 6; ++dd) {
         const int a = dd >> 1;
