@@ -574,7 +574,7 @@ def main():
     ap.add_argument("--no-melt", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
-    ap.add_argument("--autotune", type=int, default=3, metavar="STEPS",
+    ap.add_argument("--autotune", type=int, default=6, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
                          "trial before the warm-up; every trial starts from the snapshot, "
                          "which is restored (0: the default schedule)")
