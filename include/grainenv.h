@@ -347,6 +347,84 @@ ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args
 /* Replaces grains, particles, claims, site states, time and step. */
 ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
 
+/* ------------------------------------------------------ saved states ---
+   Checkpoint and resume of the whole state of the method (Sec. 2.1: grains
+   with their orientation, the tracking particles, the lattice sites each
+   grain has claimed or reached, the nucleation sites, the time), as one
+   versioned, self-checking blob in host memory.  A context restored from a
+   blob steps exactly like the context that saved it: the same particles,
+   claims, grain rows (formed again from the FP64 centres and quaternions)
+   and site states, so equal inputs give bitwise equal states afterwards.
+   The usual use: save, re-create the context with larger capacities after a
+   capacity error, restore.
+
+   Layout (little-endian; every section starts on an 8-byte boundary):
+     ge_state_header
+     grains     n_grains    x ge_state_grain     (FP64 centre and quaternion)
+     sites      n_sites     x ge_state_site      (FP64 position, threshold,
+                                                  quaternion; state)
+     particles  n_particles x ge_state_particle  (active and stopped)
+     claims     n_claim_bricks x ge_state_claims (the claimed and reached
+                masks of one grain's brick of 8 x 8 x 8 lattice sites)
+   checksum: 64-bit FNV-1a over everything after the header, taken as
+   little-endian 64-bit words (h = (h ^ word) * 0x100000001b3, starting from
+   0xcbf29ce484222325).
+
+   ge_save_state (synchronises): writes the blob to host memory `out`.  With
+   out == NULL or out_bytes too small only *needed is set (GE_OK).  The
+   sticky device error of a context in error is returned instead (a state
+   taken after an error is not a state of the method).
+   ge_state_check (no device needed): validates a blob (magic, version,
+   sizes, section counts, checksum) and copies its header to hdr
+   (nullable).  GE_EINVAL on any mismatch.
+   ge_restore_state: checks the blob, then replaces the context's state like
+   ge_load_state.  The blob must come from a context with the same lambda0
+   and box (GE_EINVAL otherwise).  Its nucleation sites are registered when
+   the context has none; otherwise the registered sites must equal the
+   blob's (GE_EINVAL).  GE_ECAPACITY when a capacity of the context is too
+   small for the blob. */
+#define GE_STATE_MAGIC 0x54534547u /* "GEST" */
+#define GE_STATE_VERSION 1u
+typedef struct ge_state_header {
+  uint32_t magic;          /* GE_STATE_MAGIC */
+  uint32_t version;        /* GE_STATE_VERSION */
+  uint64_t bytes;          /* size of the whole blob */
+  uint64_t checksum;       /* of the sections after the header */
+  double lambda0;          /* of the context that saved the state [m] */
+  double lo[3], hi[3];     /* its box [m] */
+  double t;                /* time [s] */
+  int64_t step;            /* steps taken */
+  int64_t n_grains, n_sites, n_particles, n_claim_bricks;
+} ge_state_header;         /* 128 bytes */
+typedef struct ge_state_grain {
+  double centre[3];
+  double quat[4];          /* (w, x, y, z), crystal -> world */
+} ge_state_grain;          /* 56 bytes */
+typedef struct ge_state_site {
+  double xyz[3];
+  double dT_nuc;
+  double quat[4];
+  int32_t state;           /* GE_SITE_DORMANT / FIRED / ENGULFED */
+  int32_t pad;
+} ge_state_site;           /* 72 bytes */
+typedef struct ge_state_particle {
+  float s;                 /* travel since the departure site [m] */
+  uint32_t grain;
+  int32_t site[3];         /* departure lattice site */
+  uint8_t dir;             /* 0..5 */
+  uint8_t state;           /* GE_ACTIVE / GE_STOPPED */
+  uint16_t pad;
+} ge_state_particle;       /* 24 bytes */
+typedef struct ge_state_claims {
+  uint32_t grain;
+  int32_t brick[3];        /* sites 8 brick .. 8 brick + 7 along each axis */
+  uint64_t claimed[8];     /* word z & 7, bit (x & 7) | (y & 7) << 3 */
+  uint64_t reached[8];
+} ge_state_claims;         /* 144 bytes */
+ge_status ge_save_state(ge_ctx* ctx, void* out, size_t out_bytes, size_t* needed);
+ge_status ge_state_check(const void* blob, size_t bytes, ge_state_header* hdr);
+ge_status ge_restore_state(ge_ctx* ctx, const void* blob, size_t bytes);
+
 /* Phase timing of ge_step with HIP events recorded on the context's stream
    between the phases of every step.
    ge_profile(ctx, 1) starts recording and clears the totals; ge_profile(ctx, 0)

@@ -85,6 +85,17 @@ class ge_state_in(C.Structure):
                 ("t", C.c_double), ("step", C.c_int64)]
 
 
+class ge_state_header(C.Structure):
+    _fields_ = [("magic", C.c_uint32), ("version", C.c_uint32), ("bytes", C.c_uint64),
+                ("checksum", C.c_uint64), ("lambda0", C.c_double), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("t", C.c_double), ("step", C.c_int64),
+                ("n_grains", C.c_int64), ("n_sites", C.c_int64), ("n_particles", C.c_int64),
+                ("n_claim_bricks", C.c_int64)]
+
+
+STATE_MAGIC, STATE_VERSION = 0x54534547, 1
+assert C.sizeof(ge_state_header) == 128
+
 _lib = None
 
 
@@ -113,6 +124,9 @@ def load_library(path: str = LIB_PATH):
         "ge_query_envelope": ([vp, C.c_int32, P(ge_query_args), vp, C.c_size_t,
                                P(C.c_size_t)], C.c_int32),
         "ge_load_state": ([vp, P(ge_state_in)], C.c_int32),
+        "ge_save_state": ([vp, vp, C.c_size_t, P(C.c_size_t)], C.c_int32),
+        "ge_state_check": ([vp, C.c_size_t, P(ge_state_header)], C.c_int32),
+        "ge_restore_state": ([vp, vp, C.c_size_t], C.c_int32),
         "ge_profile": ([vp, C.c_int32], C.c_int32),
         "ge_profile_read": ([vp, P(C.c_double), P(C.c_int64)], C.c_int32),
         "ge_phase_name": ([C.c_int32], C.c_char_p),
@@ -154,7 +168,8 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_set_deposition_grid",
             "ge_set_melting",
             "ge_nucleate", "ge_step",
-            "ge_query_envelope", "ge_load_state", "ge_profile", "ge_profile_read",
+            "ge_query_envelope", "ge_load_state", "ge_save_state", "ge_state_check",
+            "ge_restore_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
             "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward",
@@ -208,6 +223,18 @@ def workspace_size(p: ge_params) -> int:
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def state_check(blob) -> dict:
+    """Header of a saved state after checking the blob (no device needed);
+    raises GrainEnvError(EINVAL) for a blob that is not a valid saved state."""
+    lib = load_library()
+    blob = np.ascontiguousarray(blob, np.uint8)
+    h = ge_state_header()
+    rc = lib.ge_state_check(_ptr(blob), blob.nbytes, C.byref(h))
+    if rc != GE_OK:
+        raise GrainEnvError(rc, "not a valid saved state")
+    return {k: (list(getattr(h, k)) if k in ("lo", "hi") else getattr(h, k)) for k, _ in h._fields_}
 
 
 class Context:
@@ -422,6 +449,21 @@ class Context:
         st.site_state = _ptr(ss)
         st.t, st.step = float(t), int(step)
         self._check(self.lib.ge_load_state(self.ctx, C.byref(st)), "ge_load_state")
+
+    def save_state(self) -> np.ndarray:
+        """The whole state as a versioned blob (uint8 array in host memory)."""
+        need = C.c_size_t()
+        self._check(self.lib.ge_save_state(self.ctx, None, 0, C.byref(need)), "ge_save_state")
+        out = np.zeros(need.value, np.uint8)
+        self._check(self.lib.ge_save_state(self.ctx, _ptr(out), out.nbytes, C.byref(need)),
+                    "ge_save_state")
+        return out
+
+    def restore_state(self, blob: np.ndarray):
+        blob = np.ascontiguousarray(blob, np.uint8)
+        self._check(self.lib.ge_restore_state(self.ctx, _ptr(blob), blob.nbytes),
+                    "ge_restore_state")
+        self.n_sites = state_check(blob)["n_sites"]
 
     def profile(self, on):
         self._check(self.lib.ge_profile(self.ctx, int(on)), "ge_profile")

@@ -288,6 +288,12 @@ void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);
 void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
                        const uint8_t* flags, uint32_t n, hipStream_t s);
+// Claim bricks of a saved state (144-byte records, see k_export_slots):
+// into the claim hash, and out of it (every slot with a claimed or reached
+// site; counter: device uint32, zeroed by the caller).
+void launch_claim_slots(const Dev& d, const void* slots, uint32_t n, hipStream_t s);
+void launch_export_slots(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
+                         hipStream_t s);
 void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                              const float* window /* lo xyz, hi xyz or null */, hipStream_t s);
 void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,

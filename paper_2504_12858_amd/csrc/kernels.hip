@@ -2951,6 +2951,90 @@ __global__ __launch_bounds__(TPB) void k_export_claims(Bind Bd, uint32_t* counte
   }
 }
 
+// Claim bricks for a saved state: each occupied slot with a claimed or
+// reached site as {grain, brick xyz, claimed[8], reached[8]} (144 bytes).
+struct SlotOut {
+  uint32_t grain;
+  int32_t brick[3];
+  unsigned long long claimed[8], reached[8];
+};
+static_assert(sizeof(SlotOut) == 144, "claim brick record layout");
+
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_export_slots(Bind Bd, uint32_t* counter, SlotOut* out,
+                                                      uint32_t cap_out) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  const uint64_t slots = D.cmask + 1;
+  for (uint64_t k0 = (uint64_t)V.b * TPB; k0 < slots; k0 += (uint64_t)V.G * TPB) {
+    const uint64_t slot = k0 + threadIdx.x;
+    bool take = false;
+    unsigned long long key = CLAIM_EMPTY;
+    if (slot < slots) {
+      key = D.ckeys[slot];
+      if (key != CLAIM_EMPTY) {
+        unsigned long long any = 0;
+        for (int w = 0; w < 16; ++w) any |= D.cbits[slot * 24 + w];
+        take = any != 0ull;
+      }
+    }
+    const uint32_t j = wave_append(take, counter);
+    if (!take || j >= cap_out) continue;
+    SlotOut o;
+    o.grain = (uint32_t)(key >> 36);
+    o.brick[0] = (int)((key >> 24) & 0xFFFull) - 2048;
+    o.brick[1] = (int)((key >> 12) & 0xFFFull) - 2048;
+    o.brick[2] = (int)(key & 0xFFFull) - 2048;
+    for (int w = 0; w < 8; ++w) {
+      o.claimed[w] = D.cbits[slot * 24 + CB_CLAIMED + w];
+      o.reached[w] = D.cbits[slot * 24 + CB_REACHED + w];
+    }
+    out[j] = o;
+  }
+}
+
+// Claim bricks of a saved state into the claim hash, with the grains'
+// bounding boxes grown to the occupied sites of each brick.
+template <class Bind>
+__global__ __launch_bounds__(TPB) void k_claim_slots(Bind Bd, const SlotOut* in, uint32_t n) {
+  Dev D;
+  VGrid V;
+  Bd.bind(D, V);
+  for (uint32_t k = V.b * TPB + threadIdx.x; k < n; k += V.G * TPB) {
+    const SlotOut r = in[k];
+    unsigned long long occ = 0;  // sites of the brick's 8 x 8 columns
+    int z0 = 8, z1 = -1;
+    for (int w = 0; w < 8; ++w) {
+      const unsigned long long m = r.claimed[w] | r.reached[w];
+      occ |= m;
+      if (m) {
+        z0 = min(z0, w);
+        z1 = w;
+      }
+    }
+    if (!occ) continue;
+    const int sx = r.brick[0] * 8, sy = r.brick[1] * 8, sz = r.brick[2] * 8;
+    const int64_t slot = claim_get(D, claim_key(r.grain, sx, sy, sz));
+    if (slot < 0) continue;
+    unsigned long long* w8 = D.cbits + (size_t)slot * 24;
+    for (int w = 0; w < 8; ++w) {
+      if (r.claimed[w]) atomicOr(w8 + CB_CLAIMED + w, r.claimed[w]);
+      if (r.reached[w]) atomicOr(w8 + CB_REACHED + w, r.reached[w]);
+    }
+    // Occupied rows (y) and columns (x) of the brick.
+    uint32_t rows = 0, cols = 0;
+    for (int y = 0; y < 8; ++y) {
+      const uint32_t b = (uint32_t)((occ >> (8 * y)) & 0xFFull);
+      if (b) rows |= 1u << y;
+      cols |= b;
+    }
+    const int lo[3] = {sx + __ffs(cols) - 1, sy + __ffs(rows) - 1, sz + z0};
+    const int hi[3] = {sx + 31 - __clz(cols), sy + 31 - __clz(rows), sz + z1};
+    bbox_add_box(D, r.grain, lo, hi);
+  }
+}
+
 // Grain map: voxel centre y takes the grain whose reached site is y's rounded
 // lattice position; nearest such site wins, then the lower grain.
 template <class Bind>
@@ -3412,6 +3496,15 @@ void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
                        const uint8_t* flags, uint32_t n, hipStream_t s) {
   if (n == 0) return;
   k_claim_list<<<grid_for(n, 8192), TPB, 0, s>>>(Plain{d}, grain, site, flags, n);
+}
+void launch_claim_slots(const Dev& d, const void* slots, uint32_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_claim_slots<<<grid_for(n, 8192), TPB, 0, s>>>(Plain{d}, (const SlotOut*)slots, n);
+}
+void launch_export_slots(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
+                         hipStream_t s) {
+  k_export_slots<<<grid_for(d.cmask + 1, 16384), TPB, 0, s>>>(Plain{d}, counter, (SlotOut*)out,
+                                                               cap_out);
 }
 static Window make_window(const float* win) {
   Window w;

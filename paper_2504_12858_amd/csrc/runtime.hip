@@ -233,6 +233,13 @@ struct ge_ctx {
   uint64_t dep_nodes = 0;
   double dep_cell_volume = 0.0;
   std::vector<double> site_xyz;  // registered nucleation sites (grain-to-site link of loaded states)
+  // FP64 definitions kept for saved states: the nucleation sites (threshold
+  // and quaternion beside site_xyz) and the grains defined on the host
+  // (ge_init_grains, loaded states), by grain id; nucleated grains take
+  // their site's.
+  std::vector<double> site_dT64, site_q64;
+  std::vector<double> grain_c64, grain_q64;
+  std::vector<uint8_t> grain_host;
   bool dead;
   std::string err;
   // phase timing
@@ -524,6 +531,24 @@ ge_status ge_destroy(ge_ctx* c) {
 
 const char* ge_last_error(const ge_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+// Keeps the FP64 centre and quaternion of grains g0 .. g0 + n - 1 defined on
+// the host (for saved states).
+static void remember_grains(ge_ctx* c, uint32_t g0, int32_t n, const double* centre,
+                            const double* quat) {
+  const size_t end = (size_t)g0 + (size_t)n;
+  if (c->grain_host.size() < end) {
+    c->grain_host.resize(end, 0);
+    c->grain_c64.resize(3 * end, 0.0);
+    c->grain_q64.resize(4 * end, 0.0);
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    const size_t g = (size_t)g0 + (size_t)i;
+    c->grain_host[g] = 1;
+    std::memcpy(&c->grain_c64[3 * g], centre + 3 * i, 3 * sizeof(double));
+    std::memcpy(&c->grain_q64[4 * g], quat + 4 * i, 4 * sizeof(double));
+  }
+}
+
 ge_status ge_init_grains(ge_ctx* c, int32_t n, const double* centre, const double* quat,
                          const int32_t* shell_r, uint32_t* first_id) {
   if (!c) return GE_EINVAL;
@@ -592,6 +617,7 @@ ge_status ge_init_grains(ge_ctx* c, int32_t n, const double* centre, const doubl
   st = read_counters(c);
   if (st != GE_OK) return st;
   if (c->host_cnt->err) return error_status(c, c->host_cnt->err);
+  remember_grains(c, g0, n, centre, quat);
   if (first_id) *first_id = g0;
   return GE_OK;
 }
@@ -713,6 +739,8 @@ ge_status ge_nucleate(ge_ctx* c, int32_t n, const double* xyz, const double* dT_
   c->n_sites += (uint32_t)n;
   c->d.n_sites = c->n_sites;
   c->site_xyz.insert(c->site_xyz.end(), xyz, xyz + 3 * (size_t)n);
+  c->site_dT64.insert(c->site_dT64.end(), dT_nuc, dT_nuc + (size_t)n);
+  c->site_q64.insert(c->site_q64.end(), quat, quat + 4 * (size_t)n);
   ge_status st = sync_dev(c);
   if (st != GE_OK) return st;
   return GE_OK;
@@ -1133,11 +1161,14 @@ ge_status ge_autotune(ge_ctx* c, double dt, int32_t steps_per_trial, void* snaps
   return GE_OK;
 }
 
-ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
-  if (!c || !st_in) return GE_EINVAL;
-  const ge_state_in& S = *st_in;
+// Loads a state: grains, particles, site states and time from S; the claims
+// from S's per-site arrays, or (slots non-null) from n_slots claim-brick
+// records of a saved state (host memory).
+static ge_status load_state(ge_ctx* c, const ge_state_in& S, const void* slots, int64_t n_slots) {
   if (S.n_grains < 0 || S.n_grains > c->p.cap_grains) return fail(c, GE_ECAPACITY, "cap_grains exceeded");
-  if (S.n_particles < 0 || S.n_claims < 0) return fail(c, GE_EINVAL, "negative counts");
+  if (S.n_particles < 0 || S.n_claims < 0 || n_slots < 0) return fail(c, GE_EINVAL, "negative counts");
+  if (n_slots > 0 && (uint64_t)n_slots > c->d.claim_limit)
+    return fail(c, GE_ECAPACITY, "cap_claim_bricks too small for the saved claims");
   if ((uint32_t)S.n_sites != c->n_sites) return fail(c, GE_EINVAL, "site count differs from registered sites");
   // Every argument is checked before the device state is touched.
   if ((S.n_grains > 0 && (!S.centre || !S.quat)) ||
@@ -1235,6 +1266,19 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
     HIPCHK(c, hipStreamSynchronize(s));
     (void)hipFree(buf);
   }
+  if (n_slots > 0) {
+    // In chunks of at most 1M claim bricks (144 MB of staging).
+    const size_t rec = sizeof(ge_state_claims), chunk = std::min<size_t>((size_t)n_slots, 1u << 20);
+    char* buf = nullptr;
+    HIPCHK(c, hipMalloc((void**)&buf, chunk * rec));
+    for (size_t k = 0; k < (size_t)n_slots; k += chunk) {
+      const size_t m = std::min(chunk, (size_t)n_slots - k);
+      HIPCHK(c, hipMemcpyAsync(buf, (const char*)slots + k * rec, m * rec, hipMemcpyHostToDevice, s));
+      ge::launch_claim_slots(c->d, buf, (uint32_t)m, s);
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
+    (void)hipFree(buf);
+  }
   if (c->d.gcnt) {
     // Deposition counts of the loaded claims.
     HIPCHK(c, hipMemsetAsync(c->d.gcnt, 0, 4 * c->dep_nodes, s));
@@ -1245,7 +1289,261 @@ ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
   HIPCHK(c, hipGetLastError());
   st = read_counters(c);
   if (st != GE_OK) return st;
+  c->grain_host.clear();
+  c->grain_c64.clear();
+  c->grain_q64.clear();
+  remember_grains(c, 0, S.n_grains, S.centre, S.quat);
   return error_status(c, c->host_cnt->err);
+}
+
+ge_status ge_load_state(ge_ctx* c, const ge_state_in* st_in) {
+  if (!c || !st_in) return GE_EINVAL;
+  return load_state(c, *st_in, nullptr, 0);
+}
+
+// ------------------------------------------------------ saved states ---
+static_assert(sizeof(ge_state_header) == 128, "state header layout");
+static_assert(sizeof(ge_state_grain) == 56 && sizeof(ge_state_site) == 72, "state record layout");
+static_assert(sizeof(ge_state_particle) == 24 && sizeof(ge_state_claims) == 144,
+              "state record layout");
+
+namespace {
+
+// 64-bit FNV-1a over little-endian 64-bit words.
+uint64_t blob_checksum(const char* p, size_t bytes) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t k = 0; k + 8 <= bytes; k += 8) {
+    uint64_t w;
+    std::memcpy(&w, p + k, 8);
+    h = (h ^ w) * 0x100000001b3ull;
+  }
+  return h;
+}
+
+size_t pad8(size_t v) { return (v + 7) / 8 * 8; }
+
+// Section offsets of a blob with the header's counts; 0 when a count is
+// negative or the sizes overflow.
+struct BlobLayout {
+  size_t grains, sites, particles, claims, total;
+};
+BlobLayout blob_layout(const ge_state_header& h) {
+  BlobLayout L{};
+  const int64_t n[4] = {h.n_grains, h.n_sites, h.n_particles, h.n_claim_bricks};
+  const size_t rec[4] = {sizeof(ge_state_grain), sizeof(ge_state_site), sizeof(ge_state_particle),
+                         sizeof(ge_state_claims)};
+  size_t off = sizeof(ge_state_header), at[4];
+  for (int k = 0; k < 4; ++k) {
+    if (n[k] < 0 || (uint64_t)n[k] > (1ull << 40)) return BlobLayout{};
+    at[k] = off;
+    off = pad8(off + (size_t)n[k] * rec[k]);
+  }
+  L.grains = at[0];
+  L.sites = at[1];
+  L.particles = at[2];
+  L.claims = at[3];
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+ge_status ge_state_check(const void* blob, size_t bytes, ge_state_header* hdr) {
+  if (!blob || bytes < sizeof(ge_state_header)) return GE_EINVAL;
+  ge_state_header h;
+  std::memcpy(&h, blob, sizeof(h));
+  if (h.magic != GE_STATE_MAGIC || h.version != GE_STATE_VERSION) return GE_EINVAL;
+  if (h.bytes != bytes) return GE_EINVAL;
+  const BlobLayout L = blob_layout(h);
+  if (L.total == 0 || L.total != bytes) return GE_EINVAL;
+  if (h.n_grains > INT32_MAX || h.n_sites > INT32_MAX || h.n_particles > UINT32_MAX ||
+      h.n_claim_bricks > UINT32_MAX)
+    return GE_EINVAL;
+  if (blob_checksum((const char*)blob + sizeof(h), bytes - sizeof(h)) != h.checksum)
+    return GE_EINVAL;
+  if (hdr) *hdr = h;
+  return GE_OK;
+}
+
+ge_status ge_save_state(ge_ctx* c, void* out, size_t out_bytes, size_t* needed) {
+  if (!c) return GE_EINVAL;
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  if (c->host_cnt->err) return error_status(c, c->host_cnt->err);
+  hipStream_t s = c->stream;
+  const ge::Counters H = *c->host_cnt;
+  // Particles and claim bricks are counted first (the size of the blob).
+  uint32_t* counter = nullptr;
+  HIPCHK(c, hipMalloc((void**)&counter, 8));
+  HIPCHK(c, hipMemsetAsync(counter, 0, 8, s));
+  ge::launch_export_particles(c->d, counter, nullptr, 0, nullptr, s);
+  ge::launch_export_slots(c->d, counter + 1, nullptr, 0, s);
+  uint32_t cnt[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(cnt, counter, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  ge_state_header h{};
+  h.magic = GE_STATE_MAGIC;
+  h.version = GE_STATE_VERSION;
+  h.lambda0 = c->p.lambda0;
+  for (int a = 0; a < 3; ++a) {
+    h.lo[a] = c->p.lo[a];
+    h.hi[a] = c->p.hi[a];
+  }
+  h.t = H.t;
+  h.step = (int64_t)H.step;
+  h.n_grains = H.n_grains;
+  h.n_sites = c->n_sites;
+  h.n_particles = cnt[0];
+  h.n_claim_bricks = cnt[1];
+  const BlobLayout L = blob_layout(h);
+  h.bytes = L.total;
+  if (needed) *needed = L.total;
+  if (!out || out_bytes < L.total) {
+    (void)hipFree(counter);
+    return GE_OK;
+  }
+  char* o = (char*)out;
+  std::memset(o, 0, L.total);
+  // Grains: FP64 definitions from the host, or from the site a grain was
+  // nucleated at.
+  std::vector<int32_t> gsite(H.n_grains);
+  if (H.n_grains)
+    HIPCHK(c, hipMemcpyAsync(gsite.data(), c->d.gsite, 4 * (size_t)H.n_grains,
+                             hipMemcpyDeviceToHost, s));
+  std::vector<uint32_t> sst(c->n_sites);
+  if (c->n_sites)
+    HIPCHK(c, hipMemcpyAsync(sst.data(), c->d.sstate, 4 * (size_t)c->n_sites,
+                             hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (uint32_t g = 0; g < H.n_grains; ++g) {
+    ge_state_grain r{};
+    if (g < c->grain_host.size() && c->grain_host[g]) {
+      std::memcpy(r.centre, &c->grain_c64[3 * (size_t)g], sizeof(r.centre));
+      std::memcpy(r.quat, &c->grain_q64[4 * (size_t)g], sizeof(r.quat));
+    } else if (gsite[g] >= 0 && (uint32_t)gsite[g] < c->n_sites) {
+      const size_t i = (size_t)gsite[g];
+      std::memcpy(r.centre, &c->site_xyz[3 * i], sizeof(r.centre));
+      std::memcpy(r.quat, &c->site_q64[4 * i], sizeof(r.quat));
+    } else {
+      (void)hipFree(counter);
+      return fail(c, GE_ESTATE, "grain without a known definition");
+    }
+    std::memcpy(o + L.grains + g * sizeof(r), &r, sizeof(r));
+  }
+  for (uint32_t i = 0; i < c->n_sites; ++i) {
+    ge_state_site r{};
+    std::memcpy(r.xyz, &c->site_xyz[3 * (size_t)i], sizeof(r.xyz));
+    r.dT_nuc = c->site_dT64[i];
+    std::memcpy(r.quat, &c->site_q64[4 * (size_t)i], sizeof(r.quat));
+    r.state = (int32_t)sst[i];
+    std::memcpy(o + L.sites + i * sizeof(r), &r, sizeof(r));
+  }
+  // Particles (export records, then the saved form) and claim bricks
+  // (written by the device in their saved form), staged on the device.
+  const size_t pbytes = (size_t)cnt[0] * sizeof(ge_particle_rec);
+  const size_t cbytes = (size_t)cnt[1] * sizeof(ge_state_claims);
+  char* stage = nullptr;
+  HIPCHK(c, hipMalloc((void**)&stage, std::max<size_t>(std::max(pbytes, cbytes), 64)));
+  std::vector<ge_particle_rec> prec(cnt[0]);
+  if (cnt[0]) {
+    HIPCHK(c, hipMemsetAsync(counter, 0, 4, s));
+    ge::launch_export_particles(c->d, counter, stage, cnt[0], nullptr, s);
+    HIPCHK(c, hipMemcpyAsync(prec.data(), stage, pbytes, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (cnt[1]) {
+    HIPCHK(c, hipMemsetAsync(counter, 0, 4, s));
+    ge::launch_export_slots(c->d, counter, stage, cnt[1], s);
+    HIPCHK(c, hipMemcpyAsync(o + L.claims, stage, cbytes, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  (void)hipFree(stage);
+  (void)hipFree(counter);
+  for (uint32_t k = 0; k < cnt[0]; ++k) {
+    const ge_particle_rec& q = prec[k];
+    ge_state_particle r{};
+    r.s = q.s;
+    r.grain = q.grain;
+    std::memcpy(r.site, q.site, sizeof(r.site));
+    r.dir = q.dir;
+    r.state = q.state;
+    std::memcpy(o + L.particles + (size_t)k * sizeof(r), &r, sizeof(r));
+  }
+  h.checksum = blob_checksum(o + sizeof(h), L.total - sizeof(h));
+  std::memcpy(o, &h, sizeof(h));
+  return GE_OK;
+}
+
+ge_status ge_restore_state(ge_ctx* c, const void* blob, size_t bytes) {
+  if (!c) return GE_EINVAL;
+  ge_state_header h;
+  if (ge_state_check(blob, bytes, &h) != GE_OK) return fail(c, GE_EINVAL, "not a valid saved state");
+  if (h.lambda0 != c->p.lambda0) return fail(c, GE_EINVAL, "saved with another lambda0");
+  for (int a = 0; a < 3; ++a)
+    if (h.lo[a] != c->p.lo[a] || h.hi[a] != c->p.hi[a]) return fail(c, GE_EINVAL, "saved with another box");
+  const BlobLayout L = blob_layout(h);
+  const char* b = (const char*)blob;
+  // Nucleation sites: registered from the blob, or equal to it.
+  std::vector<double> xyz(3 * (size_t)h.n_sites), dTn((size_t)h.n_sites), q(4 * (size_t)h.n_sites);
+  std::vector<int32_t> sst((size_t)h.n_sites);
+  for (int64_t i = 0; i < h.n_sites; ++i) {
+    ge_state_site r;
+    std::memcpy(&r, b + L.sites + (size_t)i * sizeof(r), sizeof(r));
+    std::memcpy(&xyz[3 * i], r.xyz, sizeof(r.xyz));
+    dTn[i] = r.dT_nuc;
+    std::memcpy(&q[4 * i], r.quat, sizeof(r.quat));
+    sst[i] = r.state;
+    if (r.state < GE_SITE_DORMANT || r.state > GE_SITE_ENGULFED) return fail(c, GE_EINVAL, "bad site state");
+  }
+  if (c->n_sites == 0 && h.n_sites > 0) {
+    const ge_status st = ge_nucleate(c, (int32_t)h.n_sites, xyz.data(), dTn.data(), q.data());
+    if (st != GE_OK) return st;
+  } else if ((int64_t)c->n_sites != h.n_sites || c->site_xyz != xyz || c->site_dT64 != dTn ||
+             c->site_q64 != q) {
+    return fail(c, GE_EINVAL, "registered sites differ from the saved ones");
+  }
+  std::vector<double> gc(3 * (size_t)h.n_grains), gq(4 * (size_t)h.n_grains);
+  for (int64_t g = 0; g < h.n_grains; ++g) {
+    ge_state_grain r;
+    std::memcpy(&r, b + L.grains + (size_t)g * sizeof(r), sizeof(r));
+    std::memcpy(&gc[3 * g], r.centre, sizeof(r.centre));
+    std::memcpy(&gq[4 * g], r.quat, sizeof(r.quat));
+  }
+  const size_t np = (size_t)h.n_particles;
+  std::vector<int32_t> pg(np), ps(3 * np), pd(np), pst(np);
+  std::vector<float> pss(np);
+  for (size_t k = 0; k < np; ++k) {
+    ge_state_particle r;
+    std::memcpy(&r, b + L.particles + k * sizeof(r), sizeof(r));
+    pg[k] = (int32_t)r.grain;
+    std::memcpy(&ps[3 * k], r.site, sizeof(r.site));
+    pd[k] = r.dir;
+    pss[k] = r.s;
+    pst[k] = r.state;
+  }
+  for (int64_t k = 0; k < h.n_claim_bricks; ++k) {
+    ge_state_claims r;
+    std::memcpy(&r, b + L.claims + (size_t)k * sizeof(r), sizeof(r));
+    if (r.grain >= (uint64_t)h.n_grains) return fail(c, GE_EINVAL, "bad claim grain");
+    for (int a = 0; a < 3; ++a)
+      if (std::abs((int64_t)r.brick[a]) * 8 > MAX_SITE_RANGE + 8) return fail(c, GE_EINVAL, "claim site out of range");
+  }
+  ge_state_in S{};
+  S.n_grains = (int32_t)h.n_grains;
+  S.centre = gc.data();
+  S.quat = gq.data();
+  S.n_particles = (int64_t)np;
+  S.grain = pg.data();
+  S.site = ps.data();
+  S.dir = pd.data();
+  S.s = pss.data();
+  S.state = pst.data();
+  S.n_claims = 0;
+  S.n_sites = (int32_t)h.n_sites;
+  S.site_state = sst.data();
+  S.t = h.t;
+  S.step = h.step;
+  return load_state(c, S, b + L.claims, h.n_claim_bricks);
 }
 
 ge_status ge_set_melting(ge_ctx* c, int32_t on) {

@@ -51,9 +51,10 @@ LAYOUT_PROBE = r"""
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
   printf("ge_params %zu\nge_field %zu\nge_step_stats %zu\nge_particle_rec %zu\n"
-         "ge_claim_rec %zu\nge_query_args %zu\nge_state_in %zu\n",
+         "ge_claim_rec %zu\nge_query_args %zu\nge_state_in %zu\nge_state_header %zu\n",
          sizeof(ge_params), sizeof(ge_field), sizeof(ge_step_stats), sizeof(ge_particle_rec),
-         sizeof(ge_claim_rec), sizeof(ge_query_args), sizeof(ge_state_in));
+         sizeof(ge_claim_rec), sizeof(ge_query_args), sizeof(ge_state_in),
+         sizeof(ge_state_header));
   F(ge_params, lambda0) F(ge_params, cap_particles) F(ge_params, cap_claim_bricks)
   F(ge_params, field_n) F(ge_params, resort_every)
   F(ge_field, data) F(ge_field, data_on_device) F(ge_field, q) F(ge_field, dT_min)
@@ -61,6 +62,8 @@ int main(void) {
   F(ge_step_stats, max_step) F(ge_step_stats, dirty_tests) F(ge_step_stats, grains_melted)
   F(ge_particle_rec, grain) F(ge_particle_rec, dir) F(ge_particle_rec, cell)
   F(ge_state_in, n_particles) F(ge_state_in, c_flags) F(ge_state_in, step)
+  F(ge_state_header, checksum) F(ge_state_header, lo) F(ge_state_header, t)
+  F(ge_state_header, n_claim_bricks)
   return 0;
 }
 """
@@ -76,7 +79,7 @@ def test_ctypes_mirrors_match_the_c_layout(tmp_path):
         [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
     types = {"ge_params": B.ge_params, "ge_field": B.ge_field,
              "ge_step_stats": B.ge_step_stats, "ge_query_args": B.ge_query_args,
-             "ge_state_in": B.ge_state_in}
+             "ge_state_in": B.ge_state_in, "ge_state_header": B.ge_state_header}
     records = {"ge_particle_rec": B.PARTICLE_DTYPE, "ge_claim_rec": B.CLAIM_DTYPE}
     for key, val in c_side.items():
         t, _, m = key.partition(".")

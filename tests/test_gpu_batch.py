@@ -148,3 +148,54 @@ def test_hold_and_digest():
         assert _state(m) == _state(r)
         r.close()
     batch.close()
+
+
+def test_batch_members_against_the_oracle():
+    """Batched members against the FP64 oracle, each run as its own oracle
+    simulation: two directional realisations (different seeds: positions and
+    orientations of the grains) and a scaled CET member (moving source,
+    nucleation) agree on >= 99.9 % of grain-map voxels; a single grain keeps
+    the oracle's particle identities, with positions within 1e-5 of the box."""
+    require_gpu()
+    from oracle import Oracle
+    from tests.gpu_helpers import orc_parts
+    n_steps = 240
+    sg = W.single_grain(shell_r=6)
+    sg.field = W.Field(W.FIELD_UNIFORM, dT=4.7)  # no travel total on a multiple of lambda0
+    ws = [W.directional(seed=2, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0),
+          W.directional(seed=21, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0),
+          W.cet(seed=3, size=(0.4e-3, 0.2e-3, 0.1e-3), lambda0=4e-6, grid_n=24, dT0=6.0,
+                rate=6.0, bulk_density=2e12, face_density=2e8, U=0.005, q=0.004),
+          sg]
+    batch = B.Batch([B.params_from_workload(w, **CAPS) for w in ws])
+    for m, w in zip(batch.members, ws):
+        m.init_from_workload(w)
+    print(f"batch of {len(ws)} members: {n_steps} steps", flush=True)
+    batch.step(DT, n_steps)
+    for i, (m, w) in enumerate(zip(batch.members, ws)):
+        o = Oracle.from_workload(w)
+        o.step(DT, n_steps)
+        assert o.error == 0
+        if w.name == "single_grain":
+            p, key = gpu_parts(m)
+            q, okey = orc_parts(o)
+            np.testing.assert_array_equal(key, okey)
+            xyz = np.stack([p["x"], p["y"], p["z"]], 1).astype(np.float64)
+            err = np.abs(xyz - q["x"]).max()
+            print(f"member {i} single grain: {len(p)} particles, max |dx| {err:.3e} m",
+                  flush=True)
+            assert err <= 1e-5 * w.box_size
+            continue
+        vox = 5e-6 if w.name == "directional" else 4e-6
+        n = [int(round((h - l) / vox)) for l, h in zip(w.lo, w.hi)]
+        gm = m.grain_map(n, w.lo, [vox] * 3)
+        om = o.grain_map(np.array(n, np.int32), np.array(w.lo), np.array([vox] * 3))
+        agree, solid = (gm == om).mean(), (om > 0).mean()
+        print(f"member {i} {w.name}: map agreement {agree:.6f}, solid {solid:.3f}", flush=True)
+        assert solid > 0.02
+        assert agree >= 0.999
+        if len(w.site_dTn):
+            fired_gpu, fired_orc = m.site_states() == 1, o.site_states() == 1
+            assert fired_gpu.sum() > 5
+            assert (fired_gpu != fired_orc).sum() <= max(1, 0.01 * fired_orc.sum())
+    batch.close()
