@@ -189,7 +189,7 @@ def adjoint_leg():
         if st["n_active"] + st["n_stopped"] >= ADJ_STORED:
             break
     log(f"[adjoint] snapshot at step {steps}: {st['n_active']} active, {st['n_stopped']} stopped")
-    run = AdjointRun.capture(ctx, w.grain_centre, w.grain_quat, w.b, w.dt, ADJ_STEPS, ADJ_CKPT)
+    run = AdjointRun.capture(ctx, w.b, w.dt, ADJ_STEPS, ADJ_CKPT)
     a = tuple(w.a)
 
     def restore(a0, a1, th):
@@ -222,6 +222,7 @@ def adjoint_leg():
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     loss = float(((x.double() - xhat.double()) ** 2).sum())
+    acc = adjoint_accuracy(ctx, run, w, a, xhat, dLdx, grad)
     ctx.close()
     return {"workload": "directional-16-grains-512k-500-steps", "tracked": int(n),
             "snapshot_step": steps, "steps": ADJ_STEPS, "ckpt_every": ADJ_CKPT,
@@ -229,8 +230,72 @@ def adjoint_leg():
             "recorded_forward_ms": round(1e3 * (t1 - t0), 3),
             "backward_ms": round(1e3 * (t2 - t1), 3),
             "ratio_vs_plain": round((t2 - t0) / t_plain, 4),
-            "plain_updates": int(plain["advanced"]), "loss": loss,
-            "grad_a0_a1_theta": [float(v) for v in grad]}
+            "plain_updates": int(plain["advanced"]),
+            "active_per_step": round(plain["advanced"] / ADJ_STEPS),
+            "loss": loss, "grad_a0_a1_theta": [float(v) for v in grad], "accuracy": acc}
+
+
+ADJ_SAMPLE = 20_000
+ADJ_FD_H = 1e-4
+
+
+def adjoint_accuracy(ctx, run, w, a, xhat, dLdx, grad):
+    """Gradient errors of the adjoint leg.
+    (1) Central differences of L = sum |x_N - xhat|^2 on the HIP path: six
+        more recorded forwards at a0 (1 +- h), a1 (1 +- h) (h = 1e-4
+        relative) and theta = +-1e-4 K (absolute: theta = 0 at the point).
+        These runs take their own masks, as the target run does.
+    (2) The FP64 oracle's adjoint on the GPU's masks for a seeded sample of
+        20k tracked particles (dL/dx zero outside the sample), and the
+        oracle's FP64 replay of their final positions."""
+    import numpy as np
+    import torch
+    from oracle import Oracle
+    from paper_2504_12858_amd import binding as B
+    from paper_2504_12858_amd import workloads as W
+    t0 = B.state_check(run.blob)["t"]
+    base = (a[0], a[1], 0.0)
+    steps = (ADJ_FD_H * a[0], ADJ_FD_H * a[1], ADJ_FD_H)
+    fd = []
+    for k in range(3):
+        Ls = []
+        for sg in (1.0, -1.0):
+            p = list(base)
+            p[k] += sg * steps[k]
+            xp = run.forward(*p)
+            Ls.append(float(((xp.double() - xhat.double()) ** 2).sum()))
+        fd.append((Ls[0] - Ls[1]) / (2 * steps[k]))
+    fd = np.array(fd)
+    g = np.array(grad, np.float64)
+    rel_fd = np.abs(g - fd) / np.abs(fd)
+    # The base recorded run again (the FD runs replaced the recording).
+    run.forward(*base)
+    tr = ctx.adjoint_tracked()
+    n = len(tr)
+    idx = np.sort(W.rng(7).choice(n, size=min(ADJ_SAMPLE, n), replace=False))
+    d_all = dLdx.detach().float().cpu().numpy()
+    d_s = np.zeros_like(d_all)
+    d_s[idx] = d_all[idx]
+    g_s = np.array(ctx.adjoint_backward(torch.from_numpy(d_s).cuda()))
+    o = Oracle(w.lo, w.hi, w.lambda0, w.h, w.rc, w.a, w.b, w.theta, 0, w.box_exit, w.periodic)
+    o.set_field(w.field)
+    o.init_grains(w.grain_centre, w.grain_quat, np.zeros(len(w.grain_centre), np.int32))
+    parts = dict(grain=tr["grain"][idx].astype(np.int32), site=tr["site"][idx].astype(np.int32),
+                 dir=tr["dir"][idx].astype(np.int32), s=tr["s0"][idx].astype(np.float64))
+    go = o.adjoint_grad(parts, tr["nact"][idx], t0, w.dt, ADJ_STEPS,
+                        d_s[idx].astype(np.float64))
+    xo = o.adjoint_replay(np.array(w.a), 0.0, parts, tr["nact"][idx], t0, w.dt, ADJ_STEPS)
+    xg = ctx.adjoint_positions().cpu().numpy()[idx].astype(np.float64)
+    box = max(h - l for l, h in zip(w.lo, w.hi))
+    rel_o = np.abs(g_s - go) / np.abs(go)
+    return {"fd_h_relative": ADJ_FD_H, "fd_theta_step_K": ADJ_FD_H,
+            "fd_grad": [float(v) for v in fd],
+            "rel_err_vs_central_differences": [float(v) for v in rel_fd],
+            "oracle_sample": int(len(idx)),
+            "oracle_grad_sample": [float(v) for v in go],
+            "gpu_grad_sample": [float(v) for v in g_s],
+            "rel_err_vs_oracle_adjoint": [float(v) for v in rel_o],
+            "replay_max_abs_dx_over_box": float(np.abs(xg - xo).max() / box)}
 
 
 BATCH_MEMBERS = 128
@@ -392,6 +457,17 @@ def melt_leg(ctx, w, steps=MELT_STEPS):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), out
 
+    # Advance with melting on until the source melts solid sites step after
+    # step (the melt pool has to reach grown solid; the first block after
+    # melting is turned on only melts what the field had already melted), so
+    # that the timed blocks melt.
+    ctx.set_melting(True)
+    pre, melted_pre, streak = 0, 0, 0
+    while pre < 2400 and streak < 3:
+        melted_pre = int(ctx.step(w.dt, 16)["melted"])
+        pre += 16
+        streak = streak + 1 if (melted_pre > 0 and pre > 16) else 0
+    ctx.set_melting(False)
     on_ms, off_ms, counts = [], [], {}
     for on in (False, True, True, False):
         ctx.set_melting(on)
@@ -407,6 +483,8 @@ def melt_leg(ctx, w, steps=MELT_STEPS):
     return {"workload": "cet-moving-source-20M snapshot, melting under the moving source",
             "steps_per_block": steps, "step_ms_melting_on": round(on, 4),
             "step_ms_melting_off": round(off, 4), "overhead_ms_per_step": round(on - off, 4),
+            "preroll_steps_until_melting": pre, "melted_in_last_preroll_block": melted_pre,
+            "timed_from_step": int(ctx.counts()["step"]) - 4 * (16 + steps),
             "per_step_on": {k: round(v / (2 * steps), 1) for k, v in counts.items()}}
 
 

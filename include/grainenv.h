@@ -344,7 +344,9 @@ ge_status ge_step(ge_ctx* ctx, double dt, int32_t n_steps, ge_step_stats* stats)
 ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args, void* out,
                             size_t out_bytes, size_t* needed);
 
-/* Replaces grains, particles, claims, site states, time and step. */
+/* Replaces grains, particles, claims, site states, time and step.  Particles
+   keep the states they are given (an active particle outside the box stays
+   active until its next advance, as in the step that produced it). */
 ge_status ge_load_state(ge_ctx* ctx, const ge_state_in* st);
 
 /* ------------------------------------------------------ saved states ---

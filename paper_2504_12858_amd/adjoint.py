@@ -20,38 +20,22 @@ from . import binding as B
 
 @dataclass
 class AdjointRun:
-    """A saved state of a context plus the recorded-run settings."""
+    """A saved state of a context (ge_save_state blob) plus the recorded-run
+    settings."""
     ctx: "B.Context"
-    grain_centre: np.ndarray
-    grain_quat: np.ndarray
-    parts: dict
-    claims: dict
-    site_state: np.ndarray
-    t0: float
-    step0: int
+    blob: np.ndarray
     b: tuple
     dt: float
     n_steps: int
     ckpt_every: int = 50
 
     @classmethod
-    def capture(cls, ctx, grain_centre, grain_quat, b, dt, n_steps, ckpt_every=50):
-        """Saves the context's current state (particles, claims, sites, time)."""
-        p = ctx.particles()
-        c = ctx.claims()
-        st = ctx.counts()
-        parts = dict(grain=p["grain"].astype(np.int32), site=p["site"].astype(np.int32),
-                     dir=p["dir"].astype(np.int32), s=p["s"].astype(np.float64),
-                     state=p["state"].astype(np.int32))
-        claims = dict(grain=c["grain"].astype(np.int32), site=c["site"].astype(np.int32),
-                      flags=c["flags"].astype(np.uint8))
-        return cls(ctx, np.asarray(grain_centre, np.float64), np.asarray(grain_quat, np.float64),
-                   parts, claims, ctx.site_states(), float(st["t"]), int(st["step"]), tuple(b),
-                   float(dt), int(n_steps), int(ckpt_every))
+    def capture(cls, ctx, b, dt, n_steps, ckpt_every=50):
+        """Saves the context's current state (grains, particles, claims, sites, time)."""
+        return cls(ctx, ctx.save_state(), tuple(b), float(dt), int(n_steps), int(ckpt_every))
 
     def restore(self):
-        self.ctx.load_state(self.grain_centre, self.grain_quat, self.parts, self.claims,
-                            self.site_state, self.t0, self.step0)
+        self.ctx.restore_state(self.blob)
 
     def forward(self, a0, a1, theta):
         """Recorded run from the saved state; returns x_N (torch, device)."""

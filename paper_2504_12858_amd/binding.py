@@ -168,7 +168,8 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_set_deposition_grid",
             "ge_set_melting",
             "ge_nucleate", "ge_step",
-            "ge_query_envelope", "ge_load_state", "ge_save_state", "ge_state_check",
+            "ge_query_envelope", "ge_load_state",
+            "ge_save_state", "ge_state_check",
             "ge_restore_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",

@@ -284,7 +284,10 @@ void launch_mushy_fraction(const uint32_t* cnt, uint64_t n, double site_over_cel
 void launch_solute_nodes(const double* T, const double* w, double liq_T, double liq_m,
                          uint64_t n, float* out, hipStream_t s);
 void launch_init_workspace(const Dev& d, hipStream_t s);
-void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s);
+// exit_rule: particles outside the box (box exit on) start stopped (new
+// envelopes); off for loaded states, whose particles keep their states.
+void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, bool exit_rule,
+                         hipStream_t s);
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s);
 void launch_claim_list(const Dev& d, const int32_t* grain, const int32_t* site,
                        const uint8_t* flags, uint32_t n, hipStream_t s);

@@ -1891,7 +1891,8 @@ struct ContainShared {
   uint3 ent[TPB / 64][CE_MAX];
 };
 
-// Containment (Sec. 2.4) of the particles listed in dpart (those of the
+// Containment (particles of two grains that meet stop, Sec. 2.1.2; the
+// neighbour search, Sec. 2.3) of the particles listed in dpart (those of the
 // cells of dirty bricks that can reach another grain), 64 per wave: owner
 // words of the stencil cells per particle, then the wave's candidate sources
 // shared out among its lanes, in rounds of at most CE_MAX entries (a lane's
@@ -2752,9 +2753,11 @@ __global__ __launch_bounds__(TPB) void k_fill_sbsum(Bind Bd) {
 }
 
 // New records A[first, first+count): those marked stopped, and (with box
-// exit) those outside the box, move to the stopped store.
+// exit, when exit_rule is set: new envelopes) those outside the box, move to
+// the stopped store.  A loaded state keeps the states it was given.
 template <class Bind>
-__global__ __launch_bounds__(TPB) void k_classify_new(Bind Bd, uint32_t first, uint32_t count) {
+__global__ __launch_bounds__(TPB) void k_classify_new(Bind Bd, uint32_t first, uint32_t count,
+                                                      int32_t exit_rule) {
   Dev D;
   VGrid V;
   Bd.bind(D, V);
@@ -2769,7 +2772,7 @@ __global__ __launch_bounds__(TPB) void k_classify_new(Bind Bd, uint32_t first, u
       x = rec_pos(D, r);
       if ((rec_fl(r) & 3u) == ST_STOPPED) {
         out = true;
-      } else if (D.box_exit) {
+      } else if (D.box_exit && exit_rule) {
         out = !in_box(D, x);
       }
       if (out) {
@@ -3484,9 +3487,10 @@ void launch_count_reached(const Dev& d, hipStream_t s) {
 void launch_init_workspace(const Dev& d, hipStream_t s) {
   k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});
 }
-void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, hipStream_t s) {
+void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, bool exit_rule,
+                         hipStream_t s) {
   if (count == 0) return;
-  k_classify_new<<<grid_for(count, 4096), TPB, 0, s>>>(Plain{d}, first, count);
+  k_classify_new<<<grid_for(count, 4096), TPB, 0, s>>>(Plain{d}, first, count, exit_rule ? 1 : 0);
 }
 void launch_claim_ball(const Dev& d, uint32_t grain, int32_t r, hipStream_t s) {
   const uint64_t w = 2ull * (uint64_t)r + 1ull;

@@ -608,7 +608,7 @@ ge_status ge_init_grains(ge_ctx* c, int32_t n, const double* centre, const doubl
   H.n_live += (uint32_t)recs.size();
   st = write_counters(c);
   if (st != GE_OK) return st;
-  ge::launch_classify_new(c->d, na, (uint32_t)recs.size(), s);
+  ge::launch_classify_new(c->d, na, (uint32_t)recs.size(), true, s);
   for (int32_t i = 0; i < n; ++i) {
     if (shell_r[i] == 0) ge::launch_claim_ball(c->d, g0 + (uint32_t)i, 0, s);
     else ge::launch_claim_ball(c->d, g0 + (uint32_t)i, shell_r[i], s);
@@ -1251,7 +1251,7 @@ static ge_status load_state(ge_ctx* c, const ge_state_in& S, const void* slots, 
   c->hstep = (uint64_t)S.step;
   st = write_counters(c);
   if (st != GE_OK) return st;
-  ge::launch_classify_new(c->d, 0, (uint32_t)recs.size(), s);
+  ge::launch_classify_new(c->d, 0, (uint32_t)recs.size(), false, s);
   if (S.n_claims > 0) {
     const size_t m = (size_t)S.n_claims;
     char* buf = nullptr;

@@ -170,7 +170,7 @@ def test_envelope_run_autograd():
     q = W.shoemake_quaternions(W.rng(5), 3)
     f, dt, N = CASE["field"], CASE["dt"], CASE["N"]
     ctx = _ctx(f, CASE["centre"], q, CASE["shells"])
-    run = AdjointRun.capture(ctx, CASE["centre"], q, W.KIN_B, dt, N, ckpt_every=50)
+    run = AdjointRun.capture(ctx, W.KIN_B, dt, N, ckpt_every=50)
     # Targets: a run with a +5 % and theta = +2 K (its own masks).
     with torch.no_grad():
         xhat = envelope_run(torch.tensor([W.KIN_A[0] * 1.05, W.KIN_A[1] * 1.05, 2.0],

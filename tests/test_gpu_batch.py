@@ -159,7 +159,7 @@ def test_batch_members_against_the_oracle():
     require_gpu()
     from oracle import Oracle
     from tests.gpu_helpers import orc_parts
-    n_steps = 240
+    n_steps = 480
     sg = W.single_grain(shell_r=6)
     sg.field = W.Field(W.FIELD_UNIFORM, dT=4.7)  # no travel total on a multiple of lambda0
     ws = [W.directional(seed=2, n_grains=8, size=(0.3e-3, 0.3e-3, 0.6e-3), dT0=10.0),
