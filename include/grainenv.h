@@ -344,6 +344,23 @@ ge_status ge_step(ge_ctx* ctx, double dt, int32_t n_steps, ge_step_stats* stats)
 ge_status ge_query_envelope(ge_ctx* ctx, int32_t kind, const ge_query_args* args, void* out,
                             size_t out_bytes, size_t* needed);
 
+/* Allocation-free variant of ge_query_envelope(GE_QUERY_PARTICLES), for
+   callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): it calls no
+   hipMalloc or hipFree.  The particles of the window `args` (NULL: all) are
+   exported into a static scratch array of the library (one per device, kept
+   until the process ends: a 256-byte counter and staging for at most
+   1,048,576 records of 48 bytes, about 48 MiB), then copied to `out` (host
+   or device memory, at least *needed bytes; out == NULL or out_bytes too
+   small: only *needed is set).  Records are those of GE_QUERY_PARTICLES, in
+   no particular order.  A window holding more than 1,048,576 particles is
+   refused with GE_ECAPACITY (*needed still set).  Every call on one device
+   shares that device's scratch: calls that overlap on one GPU (contexts on
+   different streams or threads) race and must be serialised by the caller.
+   Synchronises the context's stream. */
+ge_status ge_query_particles_noalloc(ge_ctx* ctx, const ge_query_args* args, void* out,
+                                     size_t out_bytes, size_t* needed);
+
 /* Replaces grains, particles, claims, site states, time and step.  Particles
    keep the states they are given (an active particle outside the box stays
    active until its next advance, as in the step that produced it). */

@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "ge_query_envelope": ([vp, C.c_int32, P(ge_query_args), vp, C.c_size_t,
                                P(C.c_size_t)], C.c_int32),
         "ge_load_state": ([vp, P(ge_state_in)], C.c_int32),
+        "ge_query_particles_noalloc": ([vp, P(ge_query_args), vp, C.c_size_t, P(C.c_size_t)],
+                                       C.c_int32),
         "ge_save_state": ([vp, vp, C.c_size_t, P(C.c_size_t)], C.c_int32),
         "ge_state_check": ([vp, C.c_size_t, P(ge_state_header)], C.c_int32),
         "ge_restore_state": ([vp, vp, C.c_size_t], C.c_int32),
@@ -168,7 +170,7 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_last_error", "ge_init_grains", "ge_set_thermal_field", "ge_set_deposition_grid",
             "ge_set_melting",
             "ge_nucleate", "ge_step",
-            "ge_query_envelope", "ge_load_state",
+            "ge_query_envelope", "ge_query_particles_noalloc", "ge_load_state",
             "ge_save_state", "ge_state_check",
             "ge_restore_state", "ge_profile", "ge_profile_read",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
@@ -604,6 +606,28 @@ class Context:
         if need:
             self.query_envelope(QUERY_PARTICLES, out, args=a)
         return out
+
+    def particles_noalloc(self, window=None, out=None):
+        """Particles of a window through the allocation-free entry point
+        (the library's static staging).  out: a host numpy array or a device
+        tensor of PARTICLE_DTYPE records (uint8 bytes for a tensor), or None
+        for a new host array."""
+        a = self._window(window)
+        need = C.c_size_t()
+        self._check(self.lib.ge_query_particles_noalloc(
+            self.ctx, C.byref(a) if a is not None else None, None, 0, C.byref(need)),
+            "ge_query_particles_noalloc")
+        n = need.value // PARTICLE_DTYPE.itemsize
+        if out is None:
+            out = np.zeros(n, PARTICLE_DTYPE)
+        if isinstance(out, np.ndarray):
+            ptr, nbytes = _ptr(out), out.nbytes
+        else:
+            ptr, nbytes = C.c_void_p(out.data_ptr()), out.numel() * out.element_size()
+        self._check(self.lib.ge_query_particles_noalloc(
+            self.ctx, C.byref(a) if a is not None else None, ptr, nbytes, C.byref(need)),
+            "ge_query_particles_noalloc")
+        return out, n
 
     def claims(self, window=None) -> np.ndarray:
         a = self._window(window)

@@ -299,6 +299,15 @@ void launch_export_slots(const Dev& d, uint32_t* counter, void* out, uint32_t ca
                          hipStream_t s);
 void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                              const float* window /* lo xyz, hi xyz or null */, hipStream_t s);
+// Allocation-free particle export: records staged in a static device array
+// of NOALLOC_RECORDS records (48 bytes each) after a 256-byte header whose
+// first word counts the records the window holds.  noalloc_scratch gives the
+// array's address on the current device (looked up once per device).
+constexpr size_t NOALLOC_RECORDS = 1u << 20;
+constexpr size_t NOALLOC_RECORDS_OFFSET = 256;
+hipError_t noalloc_scratch(void** out);
+void launch_export_particles_staged(const Dev& d, void* scratch_ptr, const float* window,
+                                    hipStream_t s);
 void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                           const float* window, hipStream_t s);
 void launch_grain_map(const Dev& d, const int32_t n[3], const float origin[3],

@@ -37,6 +37,7 @@
 
 #include <algorithm>
 #include <initializer_list>
+#include <mutex>
 
 namespace ge {
 
@@ -3522,6 +3523,45 @@ static Window make_window(const float* win) {
 void launch_export_particles(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                              const float* win, hipStream_t s) {
   k_export_particles<<<1024, TPB, 0, s>>>(Plain{d}, counter, (PartOut*)out, cap_out, make_window(win));
+}
+// ------------------------------------------- allocation-free particle query --
+// Scratch of ge_query_particles_noalloc: a 256-byte header (the append
+// counter of the export) and staging for NOALLOC_RECORDS exported particles,
+// in a static device array (each device holds its own copy until the process
+// ends).  Host code reaches it only through the address that
+// hipGetSymbolAddress gives on each device.
+constexpr size_t NOALLOC_HEADER = NOALLOC_RECORDS_OFFSET;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_HEADER + NOALLOC_RECORDS * sizeof(PartOut)];
+
+__global__ void k_zero_word(uint32_t* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
+hipError_t noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+void launch_export_particles_staged(const Dev& d, void* scratch_ptr, const float* win,
+                                    hipStream_t s) {
+  uint32_t* counter = (uint32_t*)scratch_ptr;
+  k_zero_word<<<1, 64, 0, s>>>(counter);
+  k_export_particles<<<1024, TPB, 0, s>>>(Plain{d}, counter,
+                                          (PartOut*)((char*)scratch_ptr + NOALLOC_HEADER),
+                                          (uint32_t)NOALLOC_RECORDS, make_window(win));
 }
 void launch_export_claims(const Dev& d, uint32_t* counter, void* out, uint32_t cap_out,
                           const float* win, hipStream_t s) {

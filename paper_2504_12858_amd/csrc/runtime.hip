@@ -215,6 +215,8 @@ struct ge_ctx {
   char* ws;
   Dev d;
   ge::Counters* host_cnt;  // pinned
+  uint32_t* host_word;     // pinned: record count of the allocation-free query
+  void* noalloc = nullptr; // this device's scratch of the allocation-free query
   ge_field field;
   std::vector<float> grid_copy;
   int32_t resort_every;
@@ -416,6 +418,19 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
     return GE_EDEVICE;
   }
   std::memset(c->host_cnt, 0, sizeof(ge::Counters));
+  if (hipHostMalloc((void**)&c->host_word, 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipHostFree(c->host_cnt);
+    delete c;
+    return GE_EDEVICE;
+  }
+  // The static scratch of the allocation-free query, on the current device.
+  if (ge::noalloc_scratch(&c->noalloc) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(c->host_word);
+    (void)hipHostFree(c->host_cnt);
+    delete c;
+    return GE_EDEVICE;
+  }
   const Layout& L = c->lay;
   const Geometry& g = c->geo;
   char* w = c->ws;
@@ -525,6 +540,7 @@ ge_status ge_destroy(ge_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   (void)hipHostFree(c->host_cnt);
+  (void)hipHostFree(c->host_word);
   delete c;
   return GE_OK;
 }
@@ -1019,6 +1035,36 @@ ge_status ge_query_envelope(ge_ctx* c, int32_t kind, const ge_query_args* args, 
     default:
       return fail(c, GE_EINVAL, "unknown query kind");
   }
+}
+
+ge_status ge_query_particles_noalloc(ge_ctx* c, const ge_query_args* args, void* out,
+                                     size_t out_bytes, size_t* needed) {
+  if (!c) return GE_EINVAL;
+  ge_status st = read_counters(c);
+  if (st != GE_OK) return st;
+  float winbuf[6];
+  const float* win = nullptr;
+  if (args) {
+    for (int a = 0; a < 3; ++a) {
+      if (args->n[a] < 1 || !(args->spacing[a] > 0)) return fail(c, GE_EINVAL, "bad window");
+      winbuf[a] = (float)args->origin[a];
+      winbuf[3 + a] = (float)(args->origin[a] + args->n[a] * args->spacing[a]);
+    }
+    win = winbuf;
+  }
+  hipStream_t s = c->stream;
+  ge::launch_export_particles_staged(c->d, c->noalloc, win, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->host_word, c->noalloc, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const uint32_t count = *c->host_word;
+  const size_t need = (size_t)count * sizeof(ge_particle_rec);
+  if (needed) *needed = need;
+  if (count > ge::NOALLOC_RECORDS)
+    return fail(c, GE_ECAPACITY, "the window holds more particles than the static staging of "
+                                 "the allocation-free query (1048576)");
+  if (!out || out_bytes < need || count == 0) return GE_OK;
+  return deliver(c, (const char*)c->noalloc + ge::NOALLOC_RECORDS_OFFSET, out, need);
 }
 
 ge_status ge_profile(ge_ctx* c, int32_t on) {
