@@ -99,16 +99,36 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from a committed counter summary
-    (profiles/*hbm_traffic*.md), or None when there is none for this kernel or
-    the kernel sources changed since the counters were taken."""
+def _traffic_fields():
+    """Machine-read fields of the committed counter summaries
+    (profiles/*hbm_traffic*.md) taken on the current kernel sources."""
     sha = kernel_sources_sha()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*hbm_traffic*.md"))):
         text = open(path).read()
-        fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
-        if fields.get("kernel") == kernel and fields.get("kernel_sources_sha256") == sha:
-            return float(fields["traffic_bytes_per_launch"])
+        fields = dict(re.findall(r"^- ([\w\[\]]+): `([^`]*)`", text, flags=re.M))
+        if fields.get("kernel_sources_sha256") == sha:
+            yield fields
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the counters (FETCH_SIZE +
+    WRITE_SIZE, calibrated), or None when no summary was taken on the current
+    kernel sources."""
+    for f in _traffic_fields():
+        v = f.get(f"traffic_bytes_per_launch[{kernel}]")
+        if v is not None:
+            return float(v)
+        if f.get("kernel") == kernel:
+            return float(f["traffic_bytes_per_launch"])
+    return None
+
+
+def measured_step_traffic():
+    """HBM bytes per step of every kernel of the step, from the counters, or
+    None (see measured_traffic)."""
+    for f in _traffic_fields():
+        if "traffic_bytes_per_step" in f:
+            return float(f["traffic_bytes_per_step"])
     return None
 
 
@@ -443,8 +463,10 @@ MELT_STEPS = 32
 
 def melt_leg(ctx, w, steps=MELT_STEPS):
     """Melting by walk-back at the 20M snapshot under the moving source (its
-    melt pool): blocks of `steps` steps with melting off, on, on, off, each
-    after 16 untimed steps, timed with HIP events, and the melting counts."""
+    melt pool): after a pre-roll with melting on until three blocks of 16
+    steps in a row melt solid sites, blocks of `steps` steps with melting on,
+    off, off, on, each after 16 untimed steps, timed with HIP events, and the
+    melting counts of the timed blocks."""
     import torch
     s = torch.cuda.current_stream()
 
@@ -467,9 +489,10 @@ def melt_leg(ctx, w, steps=MELT_STEPS):
         melted_pre = int(ctx.step(w.dt, 16)["melted"])
         pre += 16
         streak = streak + 1 if (melted_pre > 0 and pre > 16) else 0
-    ctx.set_melting(False)
     on_ms, off_ms, counts = [], [], {}
-    for on in (False, True, True, False):
+    # Melting stays on from the pre-roll into the first block (steady melting);
+    # on, off, off, on cancels the growth of the state between blocks.
+    for on in (True, False, False, True):
         ctx.set_melting(on)
         ctx.step(w.dt, 16, stats=False)
         ctx.prepare_step(w.dt)
@@ -483,7 +506,8 @@ def melt_leg(ctx, w, steps=MELT_STEPS):
     return {"workload": "cet-moving-source-20M snapshot, melting under the moving source",
             "steps_per_block": steps, "step_ms_melting_on": round(on, 4),
             "step_ms_melting_off": round(off, 4), "overhead_ms_per_step": round(on - off, 4),
-            "preroll_steps_until_melting": pre, "melted_in_last_preroll_block": melted_pre,
+            "preroll_steps_until_melting": pre,
+            "melted_per_step_last_preroll_block": round(melted_pre / 16, 1),
             "timed_from_step": int(ctx.counts()["step"]) - 4 * (16 + steps),
             "per_step_on": {k: round(v / (2 * steps), 1) for k, v in counts.items()}}
 
@@ -721,6 +745,14 @@ def main():
     step_roofline = {"bound": "hbm", "bytes_per_update": STEP_BYTES_PER_UPDATE,
                      "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+    step_bytes = measured_step_traffic()
+    step_traffic = None
+    if step_bytes is not None:
+        tb = step_bytes / (ms_step * 1e-3) / 1e9
+        step_traffic = {"bytes_per_step": step_bytes, "achieved": round(tb, 2),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(tb / HBM_PEAK_GBS, 4),
+                        "vs_algorithmic": round(step_bytes / (STEP_BYTES_PER_UPDATE * stats["advanced"]
+                                                              / args.steps), 3)}
     out = {
         "metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -738,6 +770,7 @@ def main():
         "phases_ms_per_step": {k: round(v / max(n_prof, 1), 4) for k, v in phases.items()},
         "roofline": roofline,
         "step_roofline": step_roofline,
+        "step_traffic": step_traffic,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
