@@ -168,13 +168,15 @@ struct Dev {
   uint32_t* shead;     // [cells]
   uint32_t* sstart;    // [cells]
   uint2* bsinfo;       // [bricks] start, count of the sorted stopped particles
-  uint2* sbsum;        // [bricks] grain min / max of all stopped particles
   // per-step cell list of the active particles
   uint32_t* ccnt;      // [cells] counts, back to zero after the scatter
   uint32_t* cstart;    // [cells]
   uint32_t* bcnt;      // [bricks] counts, reset by the scan
-  uint4* binfo;        // [bricks] start, count, grain min, grain max
-  uint32_t* bepoch;    // [bricks] step at which binfo was written
+  uint2* binfo;        // [bricks] start, count of the step's active particles
+  uint4* bmeta;        // [bricks] {step at which the brick was last occupied by active
+                       //  particles, their least and greatest owner word that step,
+                       //  owner word of the stopped particles}: what the neighbour
+                       //  tests read, in one 16-byte load
   uint32_t* dlist;     // [bricks] dirty bricks, per-block regions of the occupied list
   uint32_t* dlist_cnt; // [STREAM_GRID]
   uint32_t* dpart;     // [cap_p] particles of dirty bricks (indices into B, P)
@@ -224,8 +226,8 @@ struct Dev {
 // the batch workspace and rebuilds them on the device).
 #define GE_DEV_POINTERS(X)                                                                   \
   X(fgrid) X(gcnt) X(fcmin) X(fcoarse) X(mslots) X(greach) X(gsite) X(gdead) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
-  X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo) X(sbsum)      \
-  X(ccnt) X(cstart) X(bcnt) X(binfo) X(bepoch) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
+  X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo)      \
+  X(ccnt) X(cstart) X(bcnt) X(binfo) X(bmeta) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \
   X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(clist) X(stab) X(sstate) X(cand) X(sgrain) X(cnt) X(tagA)      \
   X(tagB) X(adj_rec) X(adj_nact) X(adj_sfin) X(adj_ck) X(adj_linc)

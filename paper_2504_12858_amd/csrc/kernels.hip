@@ -847,9 +847,16 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, f
     if (prev == own) break;
     own = prev;
   }
-  const uint32_t b = ci / (uint32_t)BRICK_CELLS;
-  atomicMin(&D.sbsum[b].x, g);
-  atomicMax(&D.sbsum[b].y, g);
+  // The same for the brick's stopped owner word.
+  uint32_t* bown_s = &D.bmeta[ci / (uint32_t)BRICK_CELLS].w;
+  own = *bown_s;
+  for (;;) {
+    const uint32_t nw = owner_merge(own, g);
+    if (nw == own) break;
+    const uint32_t prev = atomicCAS(bown_s, own, nw);
+    if (prev == own) break;
+    own = prev;
+  }
 }
 
 // ==================================================================== step
@@ -1291,8 +1298,12 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Bind Bd, int mode) {
       if (mode == 1) D.bsinfo[b] = make_uint2(start, c[k]);
       if (c[k] > 0u) {
         if (mode == 0) {
-          D.binfo[b] = make_uint4(start, c[k], NIL, 0u);
-          D.bepoch[b] = epoch;
+          D.binfo[b] = make_uint2(start, c[k]);
+          // Step stamp and an empty owner range; the stopped owner word (.w)
+          // is kept.
+          uint4* m = D.bmeta + b;
+          *reinterpret_cast<uint2*>(m) = make_uint2(epoch, NIL);
+          reinterpret_cast<uint32_t*>(m)[2] = 0u;
         }
         D.occ[occ] = (uint32_t)b;
         D.bcnt[b] = 0u;
@@ -1327,15 +1338,15 @@ __global__ __launch_bounds__(TPB) void k_cellscan(Bind Bd, int mode) {
 // ------------------------------------------------------------- scatter ----
 // Grain range of a brick (one update per run of equal (brick, grain) lanes).
 __device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g) {
-  atomicMin(&D.binfo[b].z, g);
-  atomicMax(&D.binfo[b].w, g);
+  atomicMin(&D.bmeta[b].y, g);
+  atomicMax(&D.bmeta[b].z, g);
 }
 // The same for children, which arrive in no order: a relaxed read first, an
 // atomic only when the range grows (most children join a grain already
 // noted in their brick).
 __device__ __forceinline__ void note_grain_checked(const Dev& D, uint32_t b, uint32_t g) {
-  uint32_t* lo = &D.binfo[b].z;
-  uint32_t* hi = &D.binfo[b].w;
+  uint32_t* lo = &D.bmeta[b].y;
+  uint32_t* hi = &D.bmeta[b].z;
   if (g < __hip_atomic_load(lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(lo, g);
   if (g > __hip_atomic_load(hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(hi, g);
 }
@@ -1469,25 +1480,18 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     const bool rz = oz == 0 || (oz < 0 ? lz == 0 : lz == 3);
     if (rx && ry && rz) reach |= 1u << t;
   }
-  // Neighbour words of one brick, one neighbour per lane (lanes < 27).
-  struct Nb {
-    uint32_t be, gz, gw;
-    uint2 sb;
-  };
-  auto fetch = [&](uint32_t b, Nb& n) {
-    n = Nb{0u, 0u, 0u, make_uint2(1u, 0u)};
+  // Summary of one neighbour brick per lane (lanes < 27; lane 13 is the
+  // brick itself): {step stamp, owner range of the step's active particles,
+  // stopped owner word}, one 16-byte load.
+  auto fetch = [&](uint32_t b, uint4& n) {
+    n = make_uint4(0u, 0u, 0u, NIL);
     if (lane < 27) {
       const int bx = (int)(b % (uint32_t)nbx) + lane % 3 - 1;
       const int by = (int)((b / (uint32_t)nbx) % (uint32_t)nby) + (lane / 3) % 3 - 1;
       const int bz = (int)(b / ((uint32_t)nbx * (uint32_t)nby)) + lane / 9 - 1;
       if (bx >= 0 && by >= 0 && bz >= 0 && bx < nbx && by < nby && bz < nbz) {
         const uint32_t nb = ((uint32_t)bz * (uint32_t)nby + (uint32_t)by) * (uint32_t)nbx + (uint32_t)bx;
-        n.be = D.bepoch[nb];
-        // Grain range only: the upper half of the brick's info word.
-        const uint2 gr = reinterpret_cast<const uint2*>(D.binfo + nb)[1];
-        n.gz = gr.x;
-        n.gw = gr.y;
-        n.sb = D.sbsum[nb];
+        n = D.bmeta[nb];
       }
     }
   };
@@ -1497,25 +1501,27 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
   const uint32_t k0 = ch.begin + (threadIdx.x >> 6);
   uint32_t b1 = k0 < ch.end ? D.occ[k0] : 0u;
   uint32_t b2 = k0 + W < ch.end ? D.occ[k0 + W] : 0u;
-  uint4 own1 = make_uint4(0u, 0u, 0u, 0u);
-  Nb n1{0u, 0u, 0u, make_uint2(1u, 0u)};
+  uint2 own1 = make_uint2(0u, 0u);
+  uint4 n1 = make_uint4(0u, 0u, 0u, NIL);
   if (k0 < ch.end) {
     own1 = D.binfo[b1];
     fetch(b1, n1);
   }
   for (uint32_t k = k0; k < ch.end; k += W) {
     const uint32_t b = b1;
-    const uint4 own = own1;
-    const Nb nn = n1;
+    const uint2 own = own1;
+    const uint4 nn = n1;
     if (k + W < ch.end) {
       b1 = b2;
       own1 = D.binfo[b1];
       fetch(b1, n1);
     }
     if (k + 2u * W < ch.end) b2 = D.occ[k + 2u * W];
-    const uint32_t g = own.z;
-    const bool foreign = (nn.be == epoch && !(nn.gz == g && nn.gw == g)) ||
-                         (nn.sb.x <= nn.sb.y && !(nn.sb.x == g && nn.sb.y == g));
+    // The brick's own owner range (lane 13).
+    const uint32_t g = (uint32_t)__shfl((int)nn.y, 13);
+    const uint32_t gmax = (uint32_t)__shfl((int)nn.z, 13);
+    const bool foreign = (nn.x == epoch && !(nn.y == g && nn.z == g)) ||
+                         (nn.w != NIL && nn.w != g);
     // Flagged bricks; the brick itself (bit 13) when it holds several grains
     // or lies on a periodic face (its cells' stencils wrap, and owner words
     // do not tell the periods apart).
@@ -1528,7 +1534,7 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
              ((D.periodic & 4) && (cz == 0 || cz == nbz - 1));
     }
     const uint32_t flags =
-        (uint32_t)__ballot(foreign) | (own.z != own.w || face ? (1u << 13) : 0u);
+        (uint32_t)__ballot(foreign) | (g != gmax || face ? (1u << 13) : 0u);
     const bool dirty = flags != 0u;
     if (lane == 0) D.bown[b] = make_uint2(epoch, dirty ? BOWN_CELLS : g);
     if (!dirty) continue;
@@ -1571,7 +1577,7 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
     uint32_t st = 0, cnt = 0;
     if ((mask >> lane) & 1ull) {
-      const uint4 inf = D.binfo[b];
+      const uint2 inf = D.binfo[b];
       st = D.cstart[ci];
       const uint32_t en = lane + 1 < BRICK_CELLS ? D.cstart[ci + 1] : inf.x + inf.y;
       cnt = en - st;
@@ -1638,9 +1644,10 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
         const uint32_t ci = b * (uint32_t)BRICK_CELLS + loc;
         // Brick summaries: a source whose brick holds grain g only (or
         // nothing) cannot hold a foreign particle.
-        if (D.bepoch[b] == epoch) {
-          const uint4 inf = D.binfo[b];
-          if (cross || !(inf.z == g && inf.w == g)) {
+        const uint4 meta = D.bmeta[b];
+        if (meta.x == epoch) {
+          if (cross || !(meta.y == g && meta.z == g)) {
+            const uint2 inf = D.binfo[b];
             const uint32_t st = D.cstart[ci];
             const uint32_t en =
                 (loc + 1u < (uint32_t)BRICK_CELLS) ? D.cstart[ci + 1] : inf.x + inf.y;
@@ -1651,8 +1658,7 @@ __device__ bool foreign_within(const Dev& D, uint32_t epoch, P3 p, uint32_t g, u
             }
           }
         }
-        const uint2 sb = D.sbsum[b];
-        if (sb.x <= sb.y && (cross || !(sb.x == g && sb.y == g))) {
+        if (meta.w != NIL && (cross || meta.w != g)) {
           const uint2 bs = D.bsinfo[b];
           if (bs.y > 0u) {
             const uint32_t st = D.sstart[ci];
@@ -1751,7 +1757,7 @@ __device__ __forceinline__ CellRanges cell_ranges(const Dev& D, const CellOwners
   if (o.act) {
     r.ast = D.cstart[o.ci];
     if (last) {
-      const uint4 inf = D.binfo[o.b];
+      const uint2 inf = D.binfo[o.b];
       r.aen = inf.x + inf.y;
     } else {
       r.aen = D.cstart[o.ci + 1];
@@ -2740,17 +2746,17 @@ __global__ __launch_bounds__(TPB) void k_count_finish(Bind Bd) {
 }
 
 // --------------------------------------------------------- init / load ----
-// Empty stopped-grain ranges; the step stamps start at 1 (0 marks bricks
-// never occupied).
+// Empty brick summaries (no step stamp, no owner); the step stamps start
+// at 1 (0 marks bricks never occupied).
 template <class Bind>
-__global__ __launch_bounds__(TPB) void k_fill_sbsum(Bind Bd) {
+__global__ __launch_bounds__(TPB) void k_fill_bmeta(Bind Bd) {
   Dev D;
   VGrid V;
   Bd.bind(D, V);
   if (V.b == 0 && threadIdx.x == 0) D.cnt->epoch = 1u;
   for (uint64_t b = (uint64_t)V.b * TPB + threadIdx.x; b < D.n_bricks;
        b += (uint64_t)V.G * TPB)
-    D.sbsum[b] = make_uint2(NIL, 0u);
+    D.bmeta[b] = make_uint4(0u, NIL, 0u, NIL);
 }
 
 // New records A[first, first+count): those marked stopped, and (with box
@@ -3486,7 +3492,7 @@ void launch_count_reached(const Dev& d, hipStream_t s) {
   k_count_finish<<<grid_for(std::max<uint64_t>(d.cap_grains, d.n_sites), 256), TPB, 0, s>>>(Plain{d});
 }
 void launch_init_workspace(const Dev& d, hipStream_t s) {
-  k_fill_sbsum<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});
+  k_fill_bmeta<<<grid_for(d.n_bricks, 8192), TPB, 0, s>>>(Plain{d});
 }
 void launch_classify_new(const Dev& d, uint32_t first, uint32_t count, bool exit_rule,
                          hipStream_t s) {

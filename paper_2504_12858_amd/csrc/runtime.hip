@@ -33,7 +33,7 @@ struct Geometry {
 
 struct Layout {
   size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
-      bsinfo, sbsum, ccnt, cstart, bcnt, binfo, bepoch, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, clist, gtab, gbox,
+      bsinfo, ccnt, cstart, bcnt, binfo, bmeta, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, clist, gtab, gbox,
       stab, sstate, cand, sgrain, fgrid, gcnt, fcmin, fcoarse, mslots, greach, gsite, gdead, cnt, dig, total;
 };
 
@@ -140,12 +140,11 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.shead = put(4 * g.n_cells);
   L.sstart = put(4 * g.n_cells);
   L.bsinfo = put(8 * g.n_bricks);
-  L.sbsum = put(8 * g.n_bricks);
   L.ccnt = put(4 * g.n_cells);
   L.cstart = put(4 * g.n_cells);
   L.bcnt = put(4 * g.n_bricks);
-  L.binfo = put(16 * g.n_bricks);
-  L.bepoch = put(4 * g.n_bricks);
+  L.binfo = put(8 * g.n_bricks);
+  L.bmeta = put(16 * g.n_bricks);
   L.dlist = put(4 * g.n_bricks);
   L.dlist_cnt = put(4 * ge::STREAM_GRID);
   L.dpart = put(4 * cp);
@@ -349,7 +348,6 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.shead, 0xFF, 4 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.ccnt, 0, 4 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.bcnt, 0, 4 * g.n_bricks, s));
-  HIPCHK(c, hipMemsetAsync(w + L.bepoch, 0, 4 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.dlist_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.bown, 0, 8 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.cown, 0xFF, 8 * g.n_cells, s));
@@ -364,7 +362,7 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.greach, 0, 4 * (uint64_t)c->p.cap_grains, s));
   HIPCHK(c, hipMemsetAsync(w + L.gsite, 0xFF, 4 * (uint64_t)c->p.cap_grains, s));
   HIPCHK(c, hipMemsetAsync(w + L.gdead, 0, 4 * (uint64_t)c->p.cap_grains, s));
-  ge::launch_init_workspace(c->d, s);  // also starts the step stamps at 1
+  ge::launch_init_workspace(c->d, s);  // brick summaries; the step stamps start at 1
   HIPCHK(c, hipGetLastError());
   return GE_OK;
 }
@@ -493,12 +491,11 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.shead = (uint32_t*)(w + L.shead);
   d.sstart = (uint32_t*)(w + L.sstart);
   d.bsinfo = (uint2*)(w + L.bsinfo);
-  d.sbsum = (uint2*)(w + L.sbsum);
   d.ccnt = (uint32_t*)(w + L.ccnt);
   d.cstart = (uint32_t*)(w + L.cstart);
   d.bcnt = (uint32_t*)(w + L.bcnt);
-  d.binfo = (uint4*)(w + L.binfo);
-  d.bepoch = (uint32_t*)(w + L.bepoch);
+  d.binfo = (uint2*)(w + L.binfo);
+  d.bmeta = (uint4*)(w + L.bmeta);
   d.dlist = (uint32_t*)(w + L.dlist);
   d.dlist_cnt = (uint32_t*)(w + L.dlist_cnt);
   d.dpart = (uint32_t*)(w + L.dpart);
