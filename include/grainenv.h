@@ -259,7 +259,8 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
 /* Destroys the context (host memory only; the workspace stays the caller's). */
 ge_status ge_destroy(ge_ctx* ctx);
 
-/* Text of the last error of the context ("" if none). */
+/* Text of the last error of the context ("" if none).  With ctx == NULL: why
+   the last ge_create of the calling thread failed ("" if it did not). */
 const char* ge_last_error(const ge_ctx* ctx);
 
 /* Appends n grains (Sec. 2.1.2).  shell_r[i] = 0: a nucleus of six particles
@@ -312,7 +313,10 @@ ge_status ge_set_melting(ge_ctx* ctx, int32_t on);
 
 /* Sets the thermal field used from the next step on (undercooling values).
    ENUMERIC on non-finite scalars; EINVAL on a grid larger than field_n or
-   missing node arrays.  Host node arrays are copied before return; device
+   missing node arrays.  GRID node values are copied as given: a non-finite
+   node is found by the step that interpolates an undercooling from it (at an
+   active particle or a dormant nucleation site), which then fails with
+   ENUMERIC.  Host node arrays are copied before return; device
    node arrays are read in stream order (the caller keeps them until the
    stream has passed this call).  A new field of the same kind and geometry
    (new node values, or new scalars of the same kind) keeps the recorded step
@@ -331,7 +335,9 @@ ge_status ge_nucleate(ge_ctx* ctx, int32_t n, const double* xyz /*[n][3]*/,
 
 /* Advances n_steps steps of dt seconds on the context's stream.  Returns at
    once unless stats is non-null; then it synchronises, fills stats and
-   returns any sticky device error. */
+   returns any sticky device error: ECAPACITY, ENUMERIC (a non-finite
+   undercooling at an active particle or a dormant site, or a non-finite
+   travel), ECFL.  After one the context refuses further steps (ESTATE). */
 ge_status ge_step(ge_ctx* ctx, double dt, int32_t n_steps, ge_step_stats* stats);
 
 /* Exports part of the state into a caller-owned buffer (host or device).

@@ -107,6 +107,10 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
                            "(there is no fallback path)")
+    # torch's HIP runtime is loaded before the library's: loaded the other way
+    # round, the library's runtime finds no device in a process that then
+    # imports torch.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, P = C.c_void_p, C.POINTER
     sig = {
@@ -259,7 +263,8 @@ class Context:
         rc = self.lib.ge_create(C.byref(params), C.c_void_p(self.workspace.data_ptr()),
                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         if rc != GE_OK:
-            raise GrainEnvError(rc, "ge_create failed")
+            msg = self.lib.ge_last_error(None)
+            raise GrainEnvError(rc, f"ge_create failed: {msg.decode() if msg else ''}")
         self.ctx = ctx
         self.n_sites = 0
 

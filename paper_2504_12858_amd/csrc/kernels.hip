@@ -928,7 +928,8 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
       const P3 x = lattice_pos(G, sx, sy, sz, d, s);
       const float dT = field_at<PM>(D, x, lin_c) - D.theta;
       float delta = velocity(D, dT) * dt;
-      if (!isfinite(delta)) {
+      // velocity() maps a NaN undercooling to rest: test both.
+      if (!isfinite(dT) || !isfinite(delta)) {
         bad |= ERR_NUMERIC;
         delta = 0.0f;
       }
@@ -2112,6 +2113,10 @@ __global__ __launch_bounds__(TPB) void k_nuc_test(Bind Bd) {
     const float* T = D.stab + (size_t)i * GT_STRIDE;
     const P3 y = {T[0], T[1], T[2]};
     const float dT = field_at(D, y, lin_c) - D.theta;
+    if (!isfinite(dT)) {
+      atomicOr(&D.cnt->err, ERR_NUMERIC);
+      continue;
+    }
     if (!(dT >= T[3])) continue;
     // With melting claims shrink, so an engulfed site is tested again every
     // step, first against the grain that covered it at its last test.

@@ -389,8 +389,12 @@ ge_status ge_workspace_size(const ge_params* p, size_t* bytes) {
   return GE_OK;
 }
 
+// Why the last ge_create on this thread failed (ge_last_error(NULL)).
+static thread_local std::string g_create_err;
+
 ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* stream,
                     ge_ctx** out) {
+  g_create_err.clear();
   if (!out || !workspace) return GE_EINVAL;
   *out = nullptr;
   if (check_params(p)) return GE_EINVAL;
@@ -412,17 +416,20 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   c->field.kind = GE_FIELD_UNIFORM;
   if (hipHostMalloc((void**)&c->host_cnt, sizeof(ge::Counters), hipHostMallocDefault) !=
       hipSuccess) {
+    g_create_err = "pinned counters: " + std::string(hipGetErrorString(hipGetLastError()));
     delete c;
     return GE_EDEVICE;
   }
   std::memset(c->host_cnt, 0, sizeof(ge::Counters));
   if (hipHostMalloc((void**)&c->host_word, 64, hipHostMallocDefault) != hipSuccess) {
+    g_create_err = "pinned word: " + std::string(hipGetErrorString(hipGetLastError()));
     (void)hipHostFree(c->host_cnt);
     delete c;
     return GE_EDEVICE;
   }
   // The static scratch of the allocation-free query, on the current device.
-  if (ge::noalloc_scratch(&c->noalloc) != hipSuccess) {
+  if (const hipError_t e = ge::noalloc_scratch(&c->noalloc); e != hipSuccess) {
+    g_create_err = "static scratch: " + std::string(hipGetErrorString(e));
     (void)hipGetLastError();
     (void)hipHostFree(c->host_word);
     (void)hipHostFree(c->host_cnt);
@@ -522,7 +529,9 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   if (st == GE_OK) st = reset_device(c);
   if (st == GE_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "create");
   if (st != GE_OK) {
+    g_create_err = c->err;
     (void)hipHostFree(c->host_cnt);
+    (void)hipHostFree(c->host_word);
     delete c;
     return st;
   }
@@ -542,7 +551,7 @@ ge_status ge_destroy(ge_ctx* c) {
   return GE_OK;
 }
 
-const char* ge_last_error(const ge_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* ge_last_error(const ge_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 // Keeps the FP64 centre and quaternion of grains g0 .. g0 + n - 1 defined on
 // the host (for saved states).

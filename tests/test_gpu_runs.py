@@ -156,6 +156,39 @@ def test_cfl_error():
     assert e.value.status == B.GE_ECFL
 
 
+def _nan_node_context(node):
+    """A nucleus at the centre of the 1 mm cube under a GRID field of 9^3 nodes
+    (spacing 125 um), 5 K everywhere but a NaN at `node` (i, j, k)."""
+    import dataclasses
+    w = W.nucleus_uniform(lambda0=5e-6, dT=5.0)
+    data = np.full((9, 9, 9), 5.0, np.float32)
+    data[node[2], node[1], node[0]] = np.nan
+    w = dataclasses.replace(w, field=W.Field(W.FIELD_GRID, n=(9, 9, 9), origin=(0.0, 0.0, 0.0),
+                                             spacing=(1.25e-4,) * 3, data=data))
+    return w, context_for(w)
+
+
+def test_non_finite_grid_node_is_a_numeric_error_on_the_device():
+    """A GRID field is copied as given; a NaN node is found where a particle's
+    undercooling is interpolated from it (the advance's finiteness check), the
+    step fails with ENUMERIC and the context refuses further steps."""
+    require_gpu()
+    # A NaN in the corner node: the nucleus at the centre never samples it.
+    w, ctx = _nan_node_context((0, 0, 0))
+    st = ctx.step(w.dt, 5)
+    assert st["n_active"] > 0
+    ctx.close()
+    # A NaN in the node at the nucleus: the first step reads it.
+    w, ctx = _nan_node_context((4, 4, 4))
+    with pytest.raises(B.GrainEnvError) as e:
+        ctx.step(w.dt, 1)
+    assert e.value.status == B.GE_ENUMERIC
+    with pytest.raises(B.GrainEnvError) as e2:
+        ctx.step(w.dt, 1)
+    assert e2.value.status == B.GE_ESTATE
+    ctx.close()
+
+
 def test_empty_context_steps():
     """No grains, no particles: steps (plain and recorded), the queries, the
     grain map, deposition and melting all work on the empty state."""
