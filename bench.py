@@ -16,8 +16,9 @@ step_roofline = value x the method's algorithmic bytes per update of the whole
 cpu_baseline = the FP64 oracle stepping a spatial window of the same snapshot
             on the host cores
 
-The timed region is bracketed by roctxProfilerResume / roctxProfilerPause, so
-`rocprofv3 --selected-regions` records exactly the timed launches.
+The timed region (and the batched leg's timed steps) is bracketed by
+roctxProfilerResume / roctxProfilerPause, so `rocprofv3 --selected-regions`
+records exactly the timed launches.
 `--copy-probe MB` instead runs a plain device copy of MB megabytes inside such
 a region (the calibration of the HBM byte counters) and exits.
 
@@ -318,6 +319,40 @@ def adjoint_accuracy(ctx, run, w, a, xhat, dLdx, grad):
             "replay_max_abs_dx_over_box": float(np.abs(xg - xo).max() / box)}
 
 
+DIRECTIONAL_STEPS = 2000
+DIRECTIONAL_TIMED = 100
+
+
+def directional_leg(steps=DIRECTIONAL_STEPS, timed=DIRECTIONAL_TIMED):
+    """The directional-growth workload at its stated size (2 x 2 x 4 mm, 64
+    grains on the cold face, linear field, lambda0 = h = rc = 5 um, dt =
+    5e-5 s): `steps` steps untimed (about 2M stored particles), then `timed`
+    more steps timed with HIP events on the context's stream (recorded
+    sequences, default schedule)."""
+    import torch
+    from paper_2504_12858_amd import workloads as W
+    from paper_2504_12858_amd import binding as B
+    w = W.directional(seed=2)
+    ctx = B.Context.from_workload(w, cap_particles=1 << 22, cap_stopped=1 << 22,
+                                  cap_claim_bricks=1 << 20)
+    st0 = ctx.step(w.dt, steps)
+    ctx.prepare_step(w.dt)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    st = ctx.step(w.dt, timed)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ctx.close()
+    return {"workload": "directional-2x2x4mm-64-grains", "steps_before": steps,
+            "active_at_start": st0["n_active"], "stored_at_start": st0["n_active"] + st0["n_stopped"],
+            "steps": timed, "ms_per_step": round(ms / timed, 4),
+            "updates_per_s": st["advanced"] / (ms * 1e-3),
+            "active_after": st["n_active"], "stopped_after": st["n_stopped"]}
+
+
 BATCH_MEMBERS = 128
 BATCH_STEPS = 200
 
@@ -331,7 +366,10 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
     steps); batch A's shared launches are autotuned from the snapshot (which
     is restored), then batch A takes `steps` batched steps and batch B steps
     its members one after the other with plain ge_step calls.  The states must
-    agree bit for bit (order-independent digests)."""
+    agree bit for bit (order-independent digests).  Last, batch A takes the
+    same steps again with every member held: the launch floor of the recorded
+    per-phase sequence (launch, dispatch and retire of every block, no
+    work)."""
     import numpy as np
     import torch
     from paper_2504_12858_amd import workloads as W
@@ -374,10 +412,12 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
     for m in b.members:
         m.prepare_step(dt)
     torch.cuda.synchronize()
+    REGION.resume()
     t0 = time.perf_counter()
     sa = a.step(dt, steps)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    REGION.pause()
     t0 = time.perf_counter()
     sb = [m.step(dt, steps) for m in b.members]
     torch.cuda.synchronize()
@@ -385,6 +425,15 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
     equal = all(x.digest() == y.digest() for x, y in zip(a.members, b.members))
     upd_a = sum(s["advanced"] for s in sa)
     upd_b = sum(s["advanced"] for s in sb)
+    # Launch floor: the same recorded sequences and block shares with every
+    # member held, so every block of every launch returns at once.
+    for m in a.members:
+        m.hold(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.step(dt, steps)
+    torch.cuda.synchronize()
+    t_floor = time.perf_counter() - t0
     a.close()
     b.close()
     return {"workload": f"directional-{members}-members-50k-1M", "members": members,
@@ -392,6 +441,7 @@ def batch_leg(members=BATCH_MEMBERS, steps=BATCH_STEPS):
             "batched_s": round(t_batch, 4), "plain_sequential_s": round(t_plain, 4),
             "speedup": round(t_plain / t_batch, 3), "blocks": blocks,
             "autotune_s": round(t_tune, 2),
+            "launch_floor_s": round(t_floor, 4), "launch_floor_frac": round(t_floor / t_batch, 4),
             "batched_updates_per_s": upd_a / t_batch, "plain_updates_per_s": upd_b / t_plain,
             "bitwise_equal": bool(equal and upd_a == upd_b)}
 
@@ -675,6 +725,7 @@ def main():
     ap.add_argument("--no-mushy", action="store_true")
     ap.add_argument("--no-melt", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
+    ap.add_argument("--no-directional", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=6, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -789,6 +840,9 @@ def main():
     if not args.no_periodic:
         out["periodic"] = periodic_leg(out["config"]["schedule"], value)
         log(f"[periodic] {out['periodic']}")
+    if not args.no_directional:
+        out["directional"] = directional_leg()
+        log(f"[directional] {out['directional']}")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
         log(f"[adjoint] {out['adjoint']}")
