@@ -58,7 +58,7 @@ KERNEL_SOURCES = ("paper_2504_12858_amd/csrc/kernels.hip", "paper_2504_12858_amd
 #   resort   : read and write record and position of each stopped particle
 #   resample : write one FP32 node value
 PHASE_BYTES = {"advance": 32, "scatter": 48, "contain": 16, "branch": 32, "resample": 4,
-               "children": 48, "dirty": 16, "marknow": 16}
+               "children": 48, "dirty": 16}
 
 
 def log(*a):
@@ -672,8 +672,48 @@ def solute_leg(ctx, w, steps=SOLUTE_STEPS):
             "coupled_updates_per_s": st["n_active"] / ((mean(hand) + mean(step_c)) * 1e-3)}
 
 
-def cpu_baseline(ctx, w, budget_s=15.0, max_steps=400):
-    """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot."""
+def cell_change(ctx, w):
+    """Of the particles active before and after one step (neither branched
+    nor stopped in it), the fraction whose cell changed: particle queries
+    before and after the step, matched by identity (grain, departure site,
+    direction)."""
+    import numpy as np
+
+    def active():
+        p = ctx.particles()
+        p = p[p["state"] == 0]
+        s = p["site"].astype(np.int64) + (1 << 15)
+        key = ((p["grain"].astype(np.int64) << 51) | (s[:, 0] << 35) | (s[:, 1] << 19)
+               | (s[:, 2] << 3) | p["dir"].astype(np.int64))
+        cell = ((p["cell"][:, 2].astype(np.int64) << 42) | (p["cell"][:, 1].astype(np.int64) << 21)
+                | p["cell"][:, 0].astype(np.int64))
+        o = np.argsort(key)
+        return key[o], cell[o]
+
+    k0, c0 = active()
+    ctx.step(w.dt, 1)
+    k1, c1 = active()
+    both, i0, i1 = np.intersect1d(k0, k1, assume_unique=True, return_indices=True)
+    moved = int(np.count_nonzero(c0[i0] != c1[i1]))
+    return {"active_before": int(len(k0)), "active_after": int(len(k1)), "kept": int(len(both)),
+            "changed_cell": moved, "fraction": round(moved / max(len(both), 1), 4),
+            "fraction_of_active": round(moved / max(len(k0), 1), 4)}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(ctx, w, budget_s=15.0, max_steps=400, one_thread_s=5.0):
+    """The FP64 oracle steps a 0.25 x 0.25 x 1 mm column of the snapshot on
+    every host core, then a few more steps of the same column on one thread."""
     import numpy as np
     from oracle import Oracle
     from oracle import oracle as orc
@@ -703,9 +743,24 @@ def cpu_baseline(ctx, w, budget_s=15.0, max_steps=400):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    log(f"[cpu] {k} oracle steps in {dt:.2f} s")
-    return {"value": updates / dt, "unit": "particle-updates/s", "cores": orc.threads(),
-            "kind": "oracle",
+    cores = orc.threads()
+    log(f"[cpu] {k} oracle steps in {dt:.2f} s on {cores} threads")
+    # The same column, continued, on one thread.
+    orc.set_threads(1)
+    u1, k1 = 0, 0
+    t1 = time.perf_counter()
+    while k1 < max_steps:
+        o.step(w.dt, 1)
+        u1 += o.last_stats()["advanced"]
+        k1 += 1
+        if time.perf_counter() - t1 > one_thread_s:
+            break
+    d1 = time.perf_counter() - t1
+    orc.set_threads(cores)
+    log(f"[cpu] {k1} oracle steps in {d1:.2f} s on one thread")
+    return {"value": updates / dt, "unit": "particle-updates/s", "cores": cores,
+            "kind": "oracle", "value_one_thread": u1 / d1, "steps_one_thread": k1,
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
             "sample": f"FP64 oracle, {k} steps of the 0.25x0.25x1 mm column "
                       f"x in [1.875,2.125] mm, y in [0.875,1.125] mm of the same snapshot "
                       f"({n_act} active particles, {len(parts) - n_act} stopped, "
@@ -726,6 +781,9 @@ def main():
     ap.add_argument("--no-melt", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--no-directional", action="store_true")
+    ap.add_argument("--cell-change", action="store_true",
+                    help="after the timed steps, measure the fraction of the kept particles "
+                         "that change cell in one step (particle queries; slow)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=6, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -825,6 +883,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, w)
+    if args.cell_change:
+        out["cell_change"] = cell_change(ctx, w)
+        log(f"[cell change] {out['cell_change']}")
     if not args.no_melt:
         out["melting"] = melt_leg(ctx, w)
         log(f"[melt] {out['melting']}")

@@ -455,10 +455,10 @@ ge_status ge_restore_state(ge_ctx* ctx, const void* blob, size_t bytes);
    ge_profile(ctx, 1) starts recording and clears the totals; ge_profile(ctx, 0)
    stops.  ge_profile_read synchronises and returns, per phase, the summed
    GPU time in milliseconds and the number of steps recorded.  Phases: field
-   resample, advance, reached-site marks, branch, brick and cell scan,
-   scatter, child scatter, dirty-brick pass, containment, stop linking,
+   resample, advance (with the reached-site marks), branch, brick and cell
+   scan, scatter, child scatter, dirty-brick pass, containment, stop linking,
    nucleation, finish, stopped-store re-sort. */
-#define GE_N_PHASES 13
+#define GE_N_PHASES 12
 ge_status ge_profile(ge_ctx* ctx, int32_t on);
 ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);
 const char* ge_phase_name(int32_t phase);
@@ -483,9 +483,8 @@ ge_status ge_prepare_step(ge_ctx* ctx, double dt);
 ge_status ge_hold(ge_ctx* ctx, int32_t on);
 
 /* Launch schedule: the number of thread blocks (256 threads each) of every
-   tunable kernel of ge_step.  Kernels: advance, reached-site marks, branch,
-   cell scan, scatter, child scatter, dirty-brick pass, containment, stop
-   linking.  The schedule changes only speed, never results.  The default,
+   tunable kernel of ge_step.  Kernels: advance, branch, cell scan, scatter,
+   child scatter, dirty-brick pass, containment, stop linking.  The schedule changes only speed, never results.  The default,
    set by ge_create, is the number of blocks the device keeps resident at
    once for each kernel.
    ge_get_schedule writes the current schedule.  ge_set_schedule takes a new
@@ -502,7 +501,7 @@ ge_status ge_hold(ge_ctx* ctx, int32_t on);
    NULL the trials advance the state (by at most 8 * GE_N_TUNABLE *
    steps_per_trial steps in all).  It leaves the best schedule set, writes
    it to blocks_out (nullable), and leaves phase profiling off. */
-#define GE_N_TUNABLE 9
+#define GE_N_TUNABLE 8
 #define GE_MAX_BLOCKS 2048
 ge_status ge_get_schedule(ge_ctx* ctx, int32_t* blocks /*[GE_N_TUNABLE]*/);
 ge_status ge_set_schedule(ge_ctx* ctx, const int32_t* blocks /*[GE_N_TUNABLE]*/);

@@ -1038,6 +1038,15 @@ int32_t orc_threads() {
 #endif
 }
 
+// Threads of the parallel loops from now on (n <= 0: one per processor).
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
+
 void orc_get_particles(void* h, int32_t* grain, int32_t* site, int32_t* dir, double* s, double* x,
                        int32_t* state) {
   Oracle& o = *(Oracle*)h;

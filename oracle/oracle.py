@@ -75,6 +75,8 @@ def _load():
     lib.orc_last_stats.argtypes = [vp, P(np.int64), C.POINTER(C.c_double)]
     lib.orc_threads.argtypes = []
     lib.orc_threads.restype = C.c_int32
+    lib.orc_set_threads.argtypes = [C.c_int32]
+    lib.orc_set_threads.restype = None
     lib.orc_time.argtypes = [vp]
     lib.orc_time.restype = C.c_double
     lib.orc_get_particles.argtypes = [vp, P(np.int32), P(np.int32), P(np.int32), P(np.float64),
@@ -344,6 +346,11 @@ class Oracle:
 
 def threads():
     return _load().orc_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on (0: one per processor)."""
+    _load().orc_set_threads(int(n))
 
 
 def f32_cells(xyz, lo, inv_h, ncell):

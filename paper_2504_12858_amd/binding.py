@@ -183,8 +183,8 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_use_graphs", "ge_prepare_step", "ge_hold", "ge_batch_workspace_size", "ge_batch_create", "ge_batch_destroy",
             "ge_batch_member", "ge_batch_last_error", "ge_batch_step", "ge_batch_use_graphs",
             "ge_batch_get_blocks", "ge_batch_set_blocks", "ge_batch_autotune")
-N_PHASES = 13
-N_TUNABLE = 9
+N_PHASES = 12
+N_TUNABLE = 8
 MAX_BLOCKS = 2048
 
 

@@ -54,7 +54,7 @@ constexpr uint32_t OWNER_SHIFT = 26;
 constexpr uint32_t GRAIN_MASK = (1u << OWNER_SHIFT) - 1u;
 
 // Tunable kernels (index into Dev::sched).
-enum : int { TK_ADVANCE = 0, TK_MARKNOW, TK_BRANCH, TK_CELLSCAN, TK_SCATTER, TK_CHILDREN, TK_DIRTY,
+enum : int { TK_ADVANCE = 0, TK_BRANCH, TK_CELLSCAN, TK_SCATTER, TK_CHILDREN, TK_DIRTY,
              TK_CONTAIN, TK_STOPLINK, TK_N };
 
 // Field kinds.
@@ -237,7 +237,7 @@ constexpr uintptr_t NULL_OFFSET = ~(uintptr_t)0;
 // (map: per block, context | virtual block << 12; gsz: per context, its
 // blocks; total: blocks of the launch).
 enum : int {
-  BS_RESAMPLE = 0, BS_ADVANCE, BS_ONE, BS_MARKNOW, BS_BRANCH, BS_TILES, BS_CELLSCAN,
+  BS_RESAMPLE = 0, BS_ADVANCE, BS_ONE, BS_BRANCH, BS_TILES, BS_CELLSCAN,
   BS_SCATTER, BS_CHILDREN, BS_DIRTY, BS_CONTAIN, BS_STOPLINK, BS_NUCTEST, BS_NUCFIRE,
   BS_RESORT, BS_N
 };
@@ -258,7 +258,6 @@ struct BatchLaunch {
 // -------------------------------------------------- host-side launchers --
 hipError_t resident_grids(Dev& d);  // default schedule for the current device
 void launch_advance(const Dev& d, float dt, hipStream_t s);
-void launch_mark_now(const Dev& d, hipStream_t s);
 void launch_branch(const Dev& d, hipStream_t s);
 void launch_scan(const Dev& d, hipStream_t s);
 void launch_scatter(const Dev& d, hipStream_t s);

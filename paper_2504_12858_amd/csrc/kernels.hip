@@ -6,8 +6,8 @@
 //   k_melt_*, k_walkback   melting by walk-back, when enabled (Sec. 2.1.3)
 //   k_advance    undercooling at each active particle, kinetic law Eq. (2),
 //                advance along R e_d, box exit, spawner list, per-cell and
-//                per-brick counts of the particles that stay active
-//   k_mark_now   marks each spawner's reached site for this step
+//                per-brick counts of the particles that stay active; marks
+//                each spawner's reached site as reached this step
 //   k_branch     outer directions of each spawner against the grain's claims;
 //                same-step competitors for one target resolved by lowest
 //                direction; counts of the children
@@ -987,6 +987,22 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
   if (bad) atomicOr(&s_bad, bad);
   if (max_step > 0.0f) atomicMax(&s_max, __float_as_uint(max_step));
   __syncthreads();
+  // The reached sites of the block's spawners, marked as reached this step
+  // (the mark the same-step competition of the branching reads), with the
+  // claim slot of each kept next to the spawner's index.  The records were
+  // written by this block before the barrier.
+  for (uint32_t k = threadIdx.x; k < s_nsp; k += TPB) {
+    const uint32_t pos = ch.begin + k;
+    const uint4 r = D.A[D.spawn[pos]];
+    const int d = rec_dir(r), a = d >> 1, e = (d & 1) ? -1 : 1;
+    const int sx = rec_sx(r) + (a == 0 ? e : 0), sy = rec_sy(r) + (a == 1 ? e : 0),
+              sz = rec_sz(r) + (a == 2 ? e : 0);
+    const int64_t slot = claim_get(D, claim_key(rec_grain(r), sx, sy, sz));
+    D.spslot[pos] = slot < 0 ? NIL : (uint32_t)slot;
+    if (slot < 0) continue;
+    const uint32_t b = site_bit(sx, sy, sz);
+    atomicOr(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), 1ull << (b & 63));
+  }
   if (threadIdx.x == 0) {
     D.spawn_cnt[logical_block(V)] = s_nsp;
     if (s_adv) atomicAdd(&D.cnt->advanced, (unsigned long long)s_adv);
@@ -1037,40 +1053,17 @@ __device__ __forceinline__ SpawnView spawn_view(const Dev& D, uint32_t* s_off) {
   v.total = s_off[v.G];
   return v;
 }
-__device__ __forceinline__ uint32_t spawn_item(const Dev& D, const SpawnView& v,
-                                               const uint32_t* s_off, uint32_t i) {
+// Position of spawner i of the step in the per-block regions of the
+// spawner list (where the advance wrote its index and its claim slot).
+__device__ __forceinline__ uint32_t spawn_pos(const SpawnView& v, const uint32_t* s_off,
+                                              uint32_t i) {
   uint32_t lo = 0, hi = v.G;  // s_off[lo] <= i < s_off[hi]
   while (hi - lo > 1u) {
     const uint32_t mid = (lo + hi) >> 1;
     if (s_off[mid] <= i) lo = mid;
     else hi = mid;
   }
-  return D.spawn[chunk_at(v.n, TPB, v.G, lo).begin + (i - s_off[lo])];
-}
-
-// Marks the site each spawner has reached as reached during this step and
-// keeps the claim slot of that site for the branching and the clearing of
-// the mark.
-template <class Bind>
-__global__ __launch_bounds__(TPB) void k_mark_now(Bind Bd) {
-  Dev D;
-  VGrid V;
-  Bd.bind(D, V);
-  if (dead(D)) return;
-  __shared__ uint32_t s_off[STREAM_GRID + 1];
-  const SpawnView v = spawn_view(D, s_off);
-  const Chunk it = chunk_of(V, v.total, 1u);
-  for (uint32_t i = it.begin + threadIdx.x; i < it.end; i += TPB) {
-    const uint4 r = D.A[spawn_item(D, v, s_off, i)];
-    const int d = rec_dir(r);
-    int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
-    S[d >> 1] += (d & 1) ? -1 : 1;
-    const int64_t slot = claim_get(D, claim_key(rec_grain(r), S[0], S[1], S[2]));
-    D.spslot[i] = slot < 0 ? NIL : (uint32_t)slot;
-    if (slot < 0) continue;
-    const uint32_t b = site_bit(S[0], S[1], S[2]);
-    atomicOr(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), 1ull << (b & 63));
-  }
+  return chunk_at(v.n, TPB, v.G, lo).begin + (i - s_off[lo]);
 }
 
 template <class Bind>
@@ -1095,9 +1088,10 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
   uint32_t ni = 0, nslot = NIL;
   uint4 nr = make_uint4(0u, 0u, 0u, 0u);
   if (it.begin + threadIdx.x < it.end) {
-    ni = spawn_item(D, v, s_off, it.begin + threadIdx.x);
+    const uint32_t np = spawn_pos(v, s_off, it.begin + threadIdx.x);
+    ni = D.spawn[np];
     nr = D.A[ni];
-    nslot = D.spslot[it.begin + threadIdx.x];
+    nslot = D.spslot[np];
   }
   // The trip count is the same for the block's waves, so the deposition of
   // the reached sites can be added once per run of equal cells of a wave.
@@ -1106,9 +1100,10 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     const uint32_t i = ni, slot = nslot;
     const uint4 r = nr;
     if (k + TPB < it.end) {
-      ni = spawn_item(D, v, s_off, k + TPB);
+      const uint32_t np = spawn_pos(v, s_off, k + TPB);
+      ni = D.spawn[np];
       nr = D.A[ni];
-      nslot = D.spslot[k + TPB];
+      nslot = D.spslot[np];
     }
     uint32_t dep = NIL, rg = NIL;
     // Children of this lane's spawner (mask 0 past the range), placed after
@@ -1410,13 +1405,14 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
   const SpawnView v = spawn_view(D, s_off);
   const Chunk it = chunk_of(V, v.total, 1u);
   for (uint32_t k = it.begin + threadIdx.x; k < it.end; k += TPB) {
-    const uint4 r = D.A[spawn_item(D, v, s_off, k)];
+    const uint32_t kp = spawn_pos(v, s_off, k);
+    const uint4 r = D.A[D.spawn[kp]];
     const uint32_t fl = rec_fl(r);
     const uint32_t gs = rec_grain(r);
     const int d = rec_dir(r);
     int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
     S[d >> 1] += (d & 1) ? -1 : 1;
-    const uint32_t slot = D.spslot[k];
+    const uint32_t slot = D.spslot[kp];
     if (slot != NIL) {
       const uint32_t b = site_bit(S[0], S[1], S[2]);
       atomicAnd(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), ~(1ull << (b & 63)));
@@ -3411,8 +3407,7 @@ hipError_t resident_grids(Dev& d) {
     grid = g >= 8u ? g / 8u * 8u : g;
     return hipSuccess;
   };
-  const void* ks[TK_N] = {(const void*)k_advance<Plain, 0>, (const void*)k_mark_now<Plain>,
-                          (const void*)k_branch<Plain>, (const void*)k_cellscan<Plain>,
+  const void* ks[TK_N] = {(const void*)k_advance<Plain, 0>, (const void*)k_branch<Plain>, (const void*)k_cellscan<Plain>,
                           (const void*)k_scatter<Plain>, (const void*)k_scatter_children<Plain>,
                           (const void*)k_dirty<Plain>, (const void*)k_contain<Plain, 0>,
                           (const void*)k_stoplink<Plain>};
@@ -3424,9 +3419,6 @@ void launch_advance(const Dev& d, float dt, hipStream_t s) {
   if (d.periodic) k_advance<Plain, 1><<<d.sched[TK_ADVANCE], TPB, 0, s>>>(Plain{d}, dt);
   else k_advance<Plain, 0><<<d.sched[TK_ADVANCE], TPB, 0, s>>>(Plain{d}, dt);
   k_spawn_scan<<<1, 1024, 0, s>>>(Plain{d});
-}
-void launch_mark_now(const Dev& d, hipStream_t s) {
-  k_mark_now<<<d.sched[TK_MARKNOW], TPB, 0, s>>>(Plain{d});
 }
 void launch_branch(const Dev& d, hipStream_t s) { k_branch<<<d.sched[TK_BRANCH], TPB, 0, s>>>(Plain{d}); }
 static void scan_bricks(const Dev& d, int mode, hipStream_t s) {
@@ -3624,7 +3616,6 @@ void launch_batch_step(const BatchLaunch& L, double dt, hipStream_t s) {
   else
     k_advance<Batch, 0><<<L.site[BS_ADVANCE].total, TPB, 0, s>>>(bind_of(L, BS_ADVANCE), (float)dt);
   k_spawn_scan<<<one, 1024, 0, s>>>(bind_of(L, BS_ONE));
-  k_mark_now<<<L.site[BS_MARKNOW].total, TPB, 0, s>>>(bind_of(L, BS_MARKNOW));
   k_branch<<<L.site[BS_BRANCH].total, TPB, 0, s>>>(bind_of(L, BS_BRANCH));
   k_scan_reduce<<<tiles, TPB, 0, s>>>(bind_of(L, BS_TILES), 0);
   k_scan_top<<<one, TPB, 0, s>>>(bind_of(L, BS_ONE), 0);

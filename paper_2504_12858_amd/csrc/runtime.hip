@@ -261,7 +261,7 @@ struct ge_ctx {
 };
 
 static const char* PHASE_NAMES[GE_N_PHASES] = {
-    "resample", "advance", "marknow",  "branch",   "scan",   "scatter", "children",
+    "resample", "advance",  "branch",   "scan",   "scatter", "children",
     "dirty",    "contain", "stoplink", "nucleate", "finish", "resort"};
 
 // Records the event that closes phase `k` of the current step (k = -1 opens
@@ -841,32 +841,30 @@ static void step_once(ge_ctx* c, double dt) {
   prof_mark(c, 0);
   ge::launch_advance(d, (float)dt, s);
   prof_mark(c, 1);
-  ge::launch_mark_now(d, s);
-  prof_mark(c, 2);
   ge::launch_branch(d, s);
-  prof_mark(c, 3);
+  prof_mark(c, 2);
   ge::launch_scan(d, s);
-  prof_mark(c, 4);
+  prof_mark(c, 3);
   ge::launch_scatter(d, s);
-  prof_mark(c, 5);
+  prof_mark(c, 4);
   ge::launch_scatter_children(d, s);
-  prof_mark(c, 6);
+  prof_mark(c, 5);
   ge::launch_dirty(d, s);
-  prof_mark(c, 7);
+  prof_mark(c, 6);
   ge::launch_contain(d, s);
-  prof_mark(c, 8);
+  prof_mark(c, 7);
   ge::launch_stoplink(d, s);
-  prof_mark(c, 9);
+  prof_mark(c, 8);
   ge::launch_nucleate(d, s);
-  prof_mark(c, 10);
+  prof_mark(c, 9);
   // Counts the step, advances time, swaps the roles of the active stores.
   ge::launch_finish(d, dt, s);
-  prof_mark(c, 11);
+  prof_mark(c, 10);
   // Re-sort of the stopped store after every resort_every-th step (the
   // kernels check the device step count as well).
   c->hstep += 1;
   if (c->hstep % (uint64_t)c->resort_every == 0) ge::launch_stopped_rebuild(d, s);
-  prof_mark(c, 12);
+  prof_mark(c, 11);
 }
 
 // Records resort_every steps from a step count that is a multiple of
@@ -1101,11 +1099,10 @@ const char* ge_phase_name(int32_t k) {
 
 static_assert(GE_N_TUNABLE == ge::TK_N, "tunable kernel count");
 static_assert(GE_MAX_BLOCKS == ge::STREAM_GRID, "per-block list capacity");
-static const char* TUNABLE_NAMES[GE_N_TUNABLE] = {"advance", "marknow", "branch", "cellscan",
-                                                   "scatter", "children", "dirty", "contain",
-                                                   "stoplink"};
+static const char* TUNABLE_NAMES[GE_N_TUNABLE] = {"advance", "branch", "cellscan", "scatter",
+                                                   "children", "dirty", "contain", "stoplink"};
 // Phase (profiler index) whose time each tunable kernel dominates.
-static const int TUNABLE_PHASE[GE_N_TUNABLE] = {1, 2, 3, 4, 5, 6, 7, 8, 9};
+static const int TUNABLE_PHASE[GE_N_TUNABLE] = {1, 2, 3, 4, 5, 6, 7, 8};
 
 const char* ge_tunable_name(int32_t k) {
   return (k >= 0 && k < GE_N_TUNABLE) ? TUNABLE_NAMES[k] : "";
@@ -1862,7 +1859,7 @@ namespace {
 constexpr uint32_t BATCH_MAX_BLOCKS = 65536;  // blocks of one shared launch
 
 // Tunable kernel of each shared site (-1: fixed site).
-const int SITE_TK[ge::BS_N] = {-1, ge::TK_ADVANCE, -1, ge::TK_MARKNOW, ge::TK_BRANCH, -1,
+const int SITE_TK[ge::BS_N] = {-1, ge::TK_ADVANCE, -1, ge::TK_BRANCH, -1,
                                ge::TK_CELLSCAN, ge::TK_SCATTER, ge::TK_CHILDREN, ge::TK_DIRTY,
                                ge::TK_CONTAIN, ge::TK_STOPLINK, -1, -1, -1};
 

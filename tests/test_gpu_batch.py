@@ -100,7 +100,7 @@ def test_batch_schedule_and_graphs_keep_results():
             m.init_from_workload(w)
         if mode == 1:
             batch.set_blocks({"advance": 24, "branch": 8, "contain": 4096, "dirty": 40,
-                              "scatter": 16, "children": 64, "marknow": 24, "stoplink": 8,
+                              "scatter": 16, "children": 64, "stoplink": 8,
                               "cellscan": 512})
             batch.use_graphs(False)
         if mode == 2:

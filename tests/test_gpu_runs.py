@@ -246,9 +246,9 @@ def test_launch_schedule_does_not_change_results():
     ref.step(w.dt, 150)
     want = _state_bytes(ref)
     ref.close()
-    for sched in ({"advance": 8, "marknow": 1, "branch": 24, "children": 2048, "contain": 16,
+    for sched in ({"advance": 8, "branch": 24, "children": 2048, "contain": 16,
                    "stoplink": 1, "dirty": 1, "scatter": 40, "cellscan": 8},
-                  {"advance": 2048, "marknow": 512, "branch": 1, "children": 8, "contain": 2048,
+                  {"advance": 2048, "branch": 1, "children": 8, "contain": 2048,
                    "stoplink": 2048, "dirty": 2048, "scatter": 1, "cellscan": 2048}):
         print(f"schedule {sched}", flush=True)
         ctx = context_for(w)
