@@ -157,8 +157,11 @@ def cet_workload():
 
 def make_context(w):
     from paper_2504_12858_amd import binding as B
-    return B.Context.from_workload(w, cap_particles=1 << 26, cap_stopped=1 << 27,
-                                   cap_claim_bricks=1 << 24, cap_grains=4096)
+    # Room for the legs that run on after the timed steps (melting,
+    # deposition, solute: about 600 more steps, to about 30M active and more
+    # than 130M stopped particles).
+    return B.Context.from_workload(w, cap_particles=1 << 26, cap_stopped=1 << 28,
+                                   cap_claim_bricks=1 << 25, cap_grains=4096)
 
 
 def advance_to_snapshot(ctx, w, target, max_steps=6000, chunk=50):
@@ -265,7 +268,12 @@ def adjoint_accuracy(ctx, run, w, a, xhat, dLdx, grad):
     (1) Central differences of L = sum |x_N - xhat|^2 on the HIP path: six
         more recorded forwards at a0 (1 +- h), a1 (1 +- h) (h = 1e-4
         relative) and theta = +-1e-4 K (absolute: theta = 0 at the point).
-        These runs take their own masks, as the target run does.
+        These runs take their own masks, as the target run does, so a
+        particle that stops one step earlier or later in a perturbed run
+        adds a jump the frozen-mask gradient does not see.  Hence also the
+        same differences over the particles that advance the same number of
+        steps in the three runs of each parameter, against the adjoint
+        gradient of that part of L.
     (2) The FP64 oracle's adjoint on the GPU's masks for a seeded sample of
         20k tracked particles (dL/dx zero outside the sample), and the
         oracle's FP64 replay of their final positions."""
@@ -277,20 +285,38 @@ def adjoint_accuracy(ctx, run, w, a, xhat, dLdx, grad):
     t0 = B.state_check(run.blob)["t"]
     base = (a[0], a[1], 0.0)
     steps = (ADJ_FD_H * a[0], ADJ_FD_H * a[1], ADJ_FD_H)
-    fd = []
+    run.forward(*base)
+    nact0 = ctx.adjoint_tracked()["nact"].copy()
+    xh = xhat.double()
+    fd, fd_same, same = [], [], []
     for k in range(3):
-        Ls = []
+        Ls, Ls_same, nacts = [], [], []
+        r2 = []
         for sg in (1.0, -1.0):
             p = list(base)
             p[k] += sg * steps[k]
             xp = run.forward(*p)
-            Ls.append(float(((xp.double() - xhat.double()) ** 2).sum()))
+            nacts.append(ctx.adjoint_tracked()["nact"].copy())
+            r2.append(((xp.double() - xh) ** 2).sum(dim=1))
+        keep = (nacts[0] == nact0) & (nacts[1] == nact0)
+        m = torch.from_numpy(keep).to(xh.device)
+        Ls = [float(v.sum()) for v in r2]
+        Ls_same = [float((v * m).sum()) for v in r2]
         fd.append((Ls[0] - Ls[1]) / (2 * steps[k]))
-    fd = np.array(fd)
+        fd_same.append((Ls_same[0] - Ls_same[1]) / (2 * steps[k]))
+        same.append(keep)
+    fd, fd_same = np.array(fd), np.array(fd_same)
     g = np.array(grad, np.float64)
     rel_fd = np.abs(g - fd) / np.abs(fd)
     # The base recorded run again (the FD runs replaced the recording).
     run.forward(*base)
+    g_same = []
+    for k in range(3):
+        d_k = dLdx.detach().clone()
+        d_k[torch.from_numpy(~same[k]).to(d_k.device)] = 0.0
+        g_same.append(float(ctx.adjoint_backward(d_k)[k]))
+    g_same = np.array(g_same)
+    rel_fd_same = np.abs(g_same - fd_same) / np.abs(fd_same)
     tr = ctx.adjoint_tracked()
     n = len(tr)
     idx = np.sort(W.rng(7).choice(n, size=min(ADJ_SAMPLE, n), replace=False))
@@ -312,6 +338,10 @@ def adjoint_accuracy(ctx, run, w, a, xhat, dLdx, grad):
     return {"fd_h_relative": ADJ_FD_H, "fd_theta_step_K": ADJ_FD_H,
             "fd_grad": [float(v) for v in fd],
             "rel_err_vs_central_differences": [float(v) for v in rel_fd],
+            "same_masks_fraction": [float(v.mean()) for v in same],
+            "fd_grad_same_masks": [float(v) for v in fd_same],
+            "grad_same_masks": [float(v) for v in g_same],
+            "rel_err_vs_central_differences_same_masks": [float(v) for v in rel_fd_same],
             "oracle_sample": int(len(idx)),
             "oracle_grad_sample": [float(v) for v in go],
             "gpu_grad_sample": [float(v) for v in g_s],
@@ -887,12 +917,15 @@ def main():
         out["cell_change"] = cell_change(ctx, w)
         log(f"[cell change] {out['cell_change']}")
     if not args.no_melt:
+        log(f"[melt] start: {ctx.counts()}")
         out["melting"] = melt_leg(ctx, w)
         log(f"[melt] {out['melting']}")
     if not args.no_mushy:
+        log(f"[mushy] start: {ctx.counts()}")
         out["mushy"] = mushy_leg(ctx, w)
         log(f"[mushy] {out['mushy']}")
     if not args.no_solute:
+        log(f"[solute] start: {ctx.counts()}")
         out["solute"] = solute_leg(ctx, w)
         log(f"[solute] {out['solute']}")
     ctx.close()
