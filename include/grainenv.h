@@ -333,12 +333,8 @@ ge_status ge_set_thermal_field(ge_ctx* ctx, const ge_field* f);
 ge_status ge_nucleate(ge_ctx* ctx, int32_t n, const double* xyz /*[n][3]*/,
                       const double* dT_nuc /*[n]*/, const double* quat /*[n][4]*/);
 
-/* Advances n_steps steps of dt seconds on the context's stream.  Part of
-   each step (the child scatter) runs on a second stream of the library's
-   own, made on the first call, forked from and joined back to the
-   context's stream with events within the step, so the work stays ordered
-   on the context's stream as seen by the caller.  Returns at once unless
-   stats is non-null; then it synchronises, fills stats and
+/* Advances n_steps steps of dt seconds on the context's stream.  Returns at
+   once unless stats is non-null; then it synchronises, fills stats and
    returns any sticky device error: ECAPACITY, ENUMERIC (a non-finite
    undercooling at an active particle or a dormant site, or a non-finite
    travel), ECFL.  After one the context refuses further steps (ESTATE). */
