@@ -230,10 +230,6 @@ struct ge_ctx {
   uint64_t gversion = 0;
   double gdt = 0.0;
   hipStream_t cap_stream = nullptr;  // capture stream (the context's stream may be the null stream)
-  // The child scatter runs beside the scatter on a second stream (default
-  // priority), forked from and joined to the context's stream by events.
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // mushy-zone deposition grid (nodes 0: off) and the volume of its cells
   uint64_t dep_nodes = 0;
   double dep_cell_volume = 0.0;
@@ -381,7 +377,6 @@ static ge_status sync_dev(ge_ctx* c) {
 static void step_once(ge_ctx* c, double dt);
 static ge_status sync_dev(ge_ctx* c);
 static ge_status ensure_graph(ge_ctx* c, double dt);
-static ge_status ensure_side(ge_ctx* c);
 
 extern "C" {
 
@@ -549,12 +544,6 @@ ge_status ge_destroy(ge_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  if (c->side) {
-    (void)hipStreamSynchronize(c->side);
-    (void)hipStreamDestroy(c->side);
-  }
-  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   (void)hipHostFree(c->host_cnt);
   (void)hipHostFree(c->host_word);
@@ -809,9 +798,6 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
   if (!c) return GE_EINVAL;
   if (c->dead) return fail(c, GE_ESTATE, "context unusable after an earlier error");
   if (!(std::isfinite(dt) && dt > 0) || n_steps < 0) return fail(c, GE_EINVAL, "bad dt or n_steps");
-  if (n_steps > 0) {
-    if (const ge_status st = ensure_side(c); st != GE_OK) return st;
-  }
   ge::launch_reset_stats(c->d, c->stream);
   int32_t k = 0;
   const int32_t R = c->resort_every;
@@ -859,21 +845,10 @@ static void step_once(ge_ctx* c, double dt) {
   prof_mark(c, 2);
   ge::launch_scan(d, s);
   prof_mark(c, 3);
-  if (c->prof_on || !c->side) {
-    ge::launch_scatter(d, s);
-    prof_mark(c, 4);
-    ge::launch_scatter_children(d, s);
-    prof_mark(c, 5);
-  } else {
-    // The two scatters write disjoint slots (ranks from the cell counts) and
-    // touch no common state otherwise, so they run side by side.
-    (void)hipEventRecord(c->ev_fork, s);
-    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    ge::launch_scatter_children(d, c->side);
-    (void)hipEventRecord(c->ev_join, c->side);
-    ge::launch_scatter(d, s);
-    (void)hipStreamWaitEvent(s, c->ev_join, 0);
-  }
+  ge::launch_scatter(d, s);
+  prof_mark(c, 4);
+  ge::launch_scatter_children(d, s);
+  prof_mark(c, 5);
   ge::launch_dirty(d, s);
   prof_mark(c, 6);
   ge::launch_contain(d, s);
@@ -892,18 +867,6 @@ static void step_once(ge_ctx* c, double dt) {
   prof_mark(c, 11);
 }
 
-// The side stream of the child scatter and its two events, made on the
-// context's first step (contexts of a batch that only step together never
-// make them).
-static ge_status ensure_side(ge_ctx* c) {
-  if (c->side) return GE_OK;
-  hipError_t e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-  if (e != hipSuccess) c->side = nullptr;
-  return hip_check(c, e, "side stream");
-}
-
 // Records resort_every steps from a step count that is a multiple of
 // resort_every (nothing runs during the recording) and instantiates them.
 static ge_status ensure_graph(ge_ctx* c, double dt) {
@@ -914,7 +877,6 @@ static ge_status ensure_graph(ge_ctx* c, double dt) {
   }
   c->graph_valid = false;
   if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  if (const ge_status st = ensure_side(c); st != GE_OK) return st;
   const uint64_t h0 = c->hstep;
   hipStream_t user = c->stream;
   c->stream = c->cap_stream;
