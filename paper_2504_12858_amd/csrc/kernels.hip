@@ -703,6 +703,14 @@ __device__ __forceinline__ unsigned long long block_excl_scan64(unsigned long lo
   return off + incl - v;
 }
 
+// Orders the LDS accesses of this wave's lanes: every access before it
+// (by any lane of the wave) is complete and visible to every access after it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive scan over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
   const int lane = lane_id();
@@ -1243,14 +1251,20 @@ __global__ __launch_bounds__(TPB) void k_scan_top(Bind Bd, int mode) {
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
   const uint32_t ntiles = (uint32_t)((D.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   __shared__ unsigned long long wsum[TPB / 64];
-  unsigned long long carry = 0;
-  for (uint32_t base = 0; base < ntiles; base += TPB) {
-    const uint32_t t = base + threadIdx.x;
-    const unsigned long long v = t < ntiles ? D.scan_tmp[t] : 0ull;
-    unsigned long long total;
-    const unsigned long long ex = block_excl_scan64(v, wsum, total);
-    if (t < ntiles) D.scan_tmp[t] = carry + ex;
-    carry += total;
+  // Each thread takes a run of consecutive tiles: their sum, one block scan
+  // of the sums, then the run's exclusive prefixes.
+  const uint32_t per = (ntiles + TPB - 1u) / TPB;
+  const uint32_t t0 = threadIdx.x * per;
+  unsigned long long sum = 0;
+  for (uint32_t q = 0; q < per; ++q)
+    if (t0 + q < ntiles) sum += D.scan_tmp[t0 + q];
+  unsigned long long carry;
+  unsigned long long run = block_excl_scan64(sum, wsum, carry);
+  for (uint32_t q = 0; q < per; ++q) {
+    if (t0 + q >= ntiles) break;
+    const unsigned long long v = D.scan_tmp[t0 + q];
+    D.scan_tmp[t0 + q] = run;
+    run += v;
   }
   if (threadIdx.x == 0) {
     const uint32_t n_out = (uint32_t)(carry & 0xFFFFFFFFull);
@@ -1320,12 +1334,27 @@ __global__ __launch_bounds__(TPB) void k_cellscan(Bind Bd, int mode) {
   const uint32_t nocc = mode == 0 ? D.cnt->n_occ : D.cnt->n_socc;
   const uint32_t waves = V.G * (TPB / 64);
   const uint32_t lane = (uint32_t)lane_id();
-  for (uint32_t k = V.b * (TPB / 64) + (threadIdx.x >> 6); k < nocc; k += waves) {
-    const uint32_t b = D.occ[k];
-    const uint32_t start = mode == 0 ? D.binfo[b].x : D.bsinfo[b].x;
+  // Software pipeline: the next brick's start and counts are loaded during
+  // this one, and its index one brick earlier.
+  uint32_t k = V.b * (TPB / 64) + (threadIdx.x >> 6);
+  uint32_t b1 = k < nocc ? D.occ[k] : 0u;
+  uint32_t b2 = k + waves < nocc ? D.occ[k + waves] : 0u;
+  uint32_t start1 = 0u, cnt1 = 0u;
+  if (k < nocc) {
+    start1 = mode == 0 ? D.binfo[b1].x : D.bsinfo[b1].x;
+    cnt1 = D.ccnt[b1 * (uint32_t)BRICK_CELLS + lane];
+  }
+  for (; k < nocc; k += waves) {
+    const uint32_t b = b1, start = start1, cnt = cnt1;
+    if (k + waves < nocc) {
+      b1 = b2;
+      start1 = mode == 0 ? D.binfo[b1].x : D.bsinfo[b1].x;
+      cnt1 = D.ccnt[b1 * (uint32_t)BRICK_CELLS + lane];
+    }
+    if (k + 2u * waves < nocc) b2 = D.occ[k + 2u * waves];
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + lane;
     uint32_t tot;
-    const uint32_t ex = wave_excl_scan(D.ccnt[ci], tot);
+    const uint32_t ex = wave_excl_scan(cnt, tot);
     if (mode == 0) D.cstart[ci] = start + ex;
     else D.sstart[ci] = start + ex;
   }
@@ -1567,10 +1596,23 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
   if (threadIdx.x == 0) s_base = s_np ? atomicAdd(&D.cnt->n_dpart, s_np) : 0u;
   __syncthreads();
   const uint32_t nd = s_n, base = s_base;
-  for (uint32_t k = threadIdx.x >> 6; k < nd; k += TPB / 64) {
-    const uint32_t b = D.dlist[ch.begin + k];
-    const unsigned long long mask = D.dmask[ch.begin + k];
-    const uint32_t off = D.doff[ch.begin + k];
+  // The next dirty brick's list entry is loaded during this one.
+  uint32_t k = threadIdx.x >> 6;
+  uint32_t nb = 0, noff = 0;
+  unsigned long long nmask = 0;
+  if (k < nd) {
+    nb = D.dlist[ch.begin + k];
+    nmask = D.dmask[ch.begin + k];
+    noff = D.doff[ch.begin + k];
+  }
+  for (; k < nd; k += TPB / 64) {
+    const uint32_t b = nb, off = noff;
+    const unsigned long long mask = nmask;
+    if (k + TPB / 64 < nd) {
+      nb = D.dlist[ch.begin + k + TPB / 64];
+      nmask = D.dmask[ch.begin + k + TPB / 64];
+      noff = D.doff[ch.begin + k + TPB / 64];
+    }
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
     uint32_t st = 0, cnt = 0;
     if ((mask >> lane) & 1ull) {
@@ -1880,13 +1922,6 @@ __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st,
   }
 }
 
-// Orders the LDS accesses of this wave's lanes: every access before it
-// (by any lane of the wave) is complete and visible to every access after it.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 struct ContainShared {
   uint32_t n, tests;
