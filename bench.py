@@ -155,13 +155,17 @@ def cet_workload():
     return W.cet(**CET_KNOBS)
 
 
+RESORT_EVERY = 16
+
+
 def make_context(w):
     from paper_2504_12858_amd import binding as B
     # Room for the legs that run on after the timed steps (melting,
     # deposition, solute: about 600 more steps, to about 30M active and more
     # than 130M stopped particles).
     return B.Context.from_workload(w, cap_particles=1 << 26, cap_stopped=1 << 28,
-                                   cap_claim_bricks=1 << 25, cap_grains=4096)
+                                   cap_claim_bricks=1 << 25, cap_grains=4096,
+                                   resort_every=RESORT_EVERY)
 
 
 def advance_to_snapshot(ctx, w, target, max_steps=6000, chunk=50):
@@ -798,6 +802,7 @@ def cpu_baseline(ctx, w, budget_s=15.0, max_steps=400, one_thread_s=5.0):
 
 
 def main():
+    global RESORT_EVERY
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
@@ -814,6 +819,8 @@ def main():
     ap.add_argument("--cell-change", action="store_true",
                     help="after the timed steps, measure the fraction of the kept particles "
                          "that change cell in one step (particle queries; slow)")
+    ap.add_argument("--resort-every", type=int, default=RESORT_EVERY, metavar="STEPS",
+                    help="steps between re-sorts of the stopped store of the 20M contexts")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MB")
     ap.add_argument("--autotune", type=int, default=6, metavar="STEPS",
                     help="autotune the launch schedule at the snapshot with STEPS steps per "
@@ -823,6 +830,7 @@ def main():
                     help="blocks per launch of the named tunable kernels (others keep the "
                          "default from the occupancy of the kernel)")
     args = ap.parse_args()
+    RESORT_EVERY = args.resort_every
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "slab decomposition is a design, not part of this build.", file=sys.stderr)
