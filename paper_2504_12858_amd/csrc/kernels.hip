@@ -84,6 +84,51 @@ __device__ __forceinline__ P3 lattice_pos(const float* __restrict__ G, int sx, i
   return p;
 }
 
+
+// A grain's table row held in registers (six 16-byte loads), for kernels
+// that place several positions of one grain around atomics: a wave's memory
+// operations retire in order, so a load issued after an atomic waits for
+// the atomic's round trip.
+struct GRow {
+  float v[24];
+};
+__device__ __forceinline__ GRow load_grow(const float* G) {
+  GRow g;
+  const float4* q = reinterpret_cast<const float4*>(G);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float4 t = q[k];
+    g.v[4 * k] = t.x;
+    g.v[4 * k + 1] = t.y;
+    g.v[4 * k + 2] = t.z;
+    g.v[4 * k + 3] = t.w;
+  }
+  return g;
+}
+// Site S of a grain as lattice_pos builds it: the site's position
+// c + lambda0 R S and the columns of R, from which the positions at travel s
+// along each direction follow with the same FMAs (hence the same bits).
+struct SiteFrame {
+  P3 o;
+  float e[9];  // R e_a for a = 0, 1, 2: x components, then y, then z
+};
+__device__ __forceinline__ SiteFrame site_frame(const GRow& G, int sx, int sy, int sz) {
+  const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+  SiteFrame f;
+  f.o.x = fmaf(G.v[13], fx, fmaf(G.v[14], fy, fmaf(G.v[15], fz, G.v[0])));
+  f.o.y = fmaf(G.v[16], fx, fmaf(G.v[17], fy, fmaf(G.v[18], fz, G.v[1])));
+  f.o.z = fmaf(G.v[19], fx, fmaf(G.v[20], fy, fmaf(G.v[21], fz, G.v[2])));
+#pragma unroll
+  for (int k = 0; k < 9; ++k) f.e[k] = G.v[4 + k];
+  return f;
+}
+// lattice_pos(G, S, d, s) from the frame of S.
+__device__ __forceinline__ P3 frame_pos(const SiteFrame& f, int d, float s) {
+  const int a = d >> 1;
+  const float ss = (d & 1) ? -s : s;
+  return {fmaf(ss, f.e[a], f.o.x), fmaf(ss, f.e[3 + a], f.o.y), fmaf(ss, f.e[6 + a], f.o.z)};
+}
+
 __device__ __forceinline__ P3 rec_pos(const Dev& D, uint4 r) {
   return lattice_pos(D.gtab + (size_t)rec_grain(r) * GT_STRIDE, rec_sx(r), rec_sy(r), rec_sz(r),
                      rec_dir(r), rec_s(r));
@@ -1123,6 +1168,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     int S[3] = {0, 0, 0};
     float sc2 = 0.0f;
     SlotCache wc{~0ull, -1};
+    SiteFrame F{};
     if (k < it.end) {
       g = rec_grain(r);
       const int d = rec_dir(r);
@@ -1157,6 +1203,9 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
         }
         if (!lose) mask |= 1u << dd;
       }
+      // The grain row for the children's positions, loaded before the
+      // round's atomics.
+      if (mask) F = site_frame(load_grow(D.gtab + (size_t)g * GT_STRIDE), S[0], S[1], S[2]);
       // The parent retires whether or not a child survives: without one, every
       // outer neighbour of S already belongs to the grain (interior point).
       D.A[i] = with_fl(r, ST_RETIRED | FL_SPAWN | (mask << 8));
@@ -1181,8 +1230,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
     for (int dd = 0; dd < 6; ++dd) {
       uint32_t ci = NIL;
       if ((mask >> dd) & 1u) {
-        const P3 xc =
-            place(D, lattice_pos(D.gtab + (size_t)g * GT_STRIDE, S[0], S[1], S[2], dd, sc2)).p;
+        const P3 xc = place(D, frame_pos(F, dd, sc2)).p;
         const C3 c = cell_of(D, xc);
         ci = cell_index(D, c.x, c.y, c.z);
         const int ta = dd >> 1, ts = (dd & 1) ? -1 : 1;
@@ -1447,17 +1495,19 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
     int S[3] = {rec_sx(r), rec_sy(r), rec_sz(r)};
     S[d >> 1] += (d & 1) ? -1 : 1;
     const uint32_t slot = D.spslot[kp];
+    const uint32_t mask = (fl >> 8) & 63u;
+    // The grain row for the children's positions, loaded before the atomics.
+    SiteFrame F{};
+    if (mask) F = site_frame(load_grow(D.gtab + (size_t)gs * GT_STRIDE), S[0], S[1], S[2]);
     if (slot != NIL) {
       const uint32_t b = site_bit(S[0], S[1], S[2]);
       atomicAnd(D.cbits + (size_t)slot * 24 + CB_NOW + (b >> 6), ~(1ull << (b & 63)));
     }
-    const uint32_t mask = (fl >> 8) & 63u;
     if (!mask) continue;
-    const float* G = D.gtab + (size_t)gs * GT_STRIDE;
     const float sc = rec_s(r) - D.lambda0;
     for (int dd = 0; dd < 6; ++dd) {
       if (!(mask & (1u << dd))) continue;
-      const float4 xc = placed4(D, lattice_pos(G, S[0], S[1], S[2], dd, sc), gs);
+      const float4 xc = placed4(D, frame_pos(F, dd, sc), gs);
       const C3 c = cell_of(D, p3_of(xc));
       const uint32_t ci = cell_index(D, c.x, c.y, c.z);
       const uint32_t rank = atomicSub(&D.ccnt[ci], 1u) - 1u;
