@@ -153,8 +153,6 @@ struct Dev {
   uint32_t* spawn;        // [cap_p], per-block regions
   uint32_t* spslot;       // [cap_p] claim slot of each spawner's reached site, at
                           //  the spawner's position in the per-block regions
-  uint32_t* akey;         // [cap_p] cell of each particle of the active store that
-                          //  stays active through the advance (NIL otherwise)
   uint32_t* spawn_cnt;    // [STREAM_GRID]
   uint32_t* spawn_off;    // [STREAM_GRID + 1] exclusive prefix of spawn_cnt
   uint32_t* newstop;      // [cap_p], per-block regions
@@ -227,7 +225,7 @@ struct Dev {
 // Every pointer member of Dev (a batched launch stores them as offsets from
 // the batch workspace and rebuilds them on the device).
 #define GE_DEV_POINTERS(X)                                                                   \
-  X(fgrid) X(gcnt) X(fcmin) X(fcoarse) X(mslots) X(greach) X(gsite) X(gdead) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(akey) X(spawn_cnt) X(spawn_off) X(newstop)      \
+  X(fgrid) X(gcnt) X(fcmin) X(fcoarse) X(mslots) X(greach) X(gsite) X(gdead) X(gtab) X(gbox) X(A) X(B) X(P) X(spawn) X(spslot) X(spawn_cnt) X(spawn_off) X(newstop)      \
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bmeta) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \

@@ -1010,8 +1010,6 @@ __global__ __launch_bounds__(TPB, 8) void k_advance(Bind Bd, float dt) {
       r = make_rec(s2, g, d, sx, sy, sz, fl);
       D.A[i] = r;
     }
-    // The cell of each kept particle for the scatter (its first load).
-    if (valid) D.akey[i] = ckey;
     // Cell and brick counts of the particles that stay active: one atomic
     // per run of equal keys in consecutive lanes (the input is cell-sorted).
     const Run rc = wave_run(ckey);
@@ -1438,25 +1436,22 @@ __global__ __launch_bounds__(TPB) void k_scatter(Bind Bd) {
     const uint32_t i = base + threadIdx.x;
     const bool valid = i < ch.end;
     const uint4 r = valid ? D.A[i] : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t kk = valid ? D.akey[i] : NIL;
     const uint32_t fl = valid ? rec_fl(r) : 0u;
-    // The cell comes from the advance (the same position function gives the
-    // same cell), so the rank atomic and the cell start are issued before
-    // the position is recomputed.
-    const uint32_t ckey = (fl & FL_KEEP) ? kk : NIL;
-    // Ranks within the cell: one decrement per run of equal cells; the cell
-    // counts return to zero once every particle has been placed.
-    const Run run = wave_run(ckey);
-    uint32_t rbase = 0;
-    if (ckey != NIL && run.off == 0) rbase = atomicSub(&D.ccnt[ckey], (uint32_t)run.len);
-    const uint32_t cs = ckey != NIL ? D.cstart[ckey] : 0u;
+    uint32_t ckey = NIL;
     uint32_t g = NIL;
     P3 p = {0.0f, 0.0f, 0.0f};
     if (fl & FL_KEEP) {
       const Placed pl = place(D, rec_pos(D, r));
       g = owner_id(rec_grain(r), pl.code);
       p = pl.p;
+      const C3 c = cell_of(D, p);
+      ckey = cell_index(D, c.x, c.y, c.z);
     }
+    // Ranks within the cell: one decrement per run of equal cells; the cell
+    // counts return to zero once every particle has been placed.
+    const Run run = wave_run(ckey);
+    uint32_t rbase = 0;
+    if (ckey != NIL && run.off == 0) rbase = atomicSub(&D.ccnt[ckey], (uint32_t)run.len);
     rbase = __shfl(rbase, run.head);
     // Grain range per brick: one update per run of equal (brick, grain).
     const uint32_t bkey = ckey == NIL ? NIL : ckey / (uint32_t)BRICK_CELLS;
@@ -1464,7 +1459,7 @@ __global__ __launch_bounds__(TPB) void k_scatter(Bind Bd) {
     const bool head = lane_id() == 0 || pb != bkey || pg != g;
     if (ckey != NIL) {
       const uint32_t rank = rbase - (uint32_t)run.len + (uint32_t)run.off;
-      const uint32_t dst = cs + rank;
+      const uint32_t dst = D.cstart[ckey] + rank;
       if (dst < D.cap_p) {
         D.B[dst] = with_fl(r, ST_ACTIVE);
         D.P[dst] = pos4(p, g);

@@ -32,7 +32,7 @@ struct Geometry {
 };
 
 struct Layout {
-  size_t A, B, P, spawn, spslot, akey, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
+  size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
       bsinfo, ccnt, cstart, bcnt, binfo, bmeta, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, clist, gtab, gbox,
       stab, sstate, cand, sgrain, fgrid, gcnt, fcmin, fcoarse, mslots, greach, gsite, gdead, cnt, dig, total;
 };
@@ -128,7 +128,6 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.P = put(16 * cp);
   L.spawn = put(4 * cp);
   L.spslot = put(4 * cp);
-  L.akey = put(4 * cp);
   L.spawn_cnt = put(4 * ge::STREAM_GRID);
   L.spawn_off = put(4 * (ge::STREAM_GRID + 1));
   L.newstop = put(4 * cp);
@@ -486,7 +485,6 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.cap_p = (uint32_t)p->cap_particles;
   d.spawn = (uint32_t*)(w + L.spawn);
   d.spslot = (uint32_t*)(w + L.spslot);
-  d.akey = (uint32_t*)(w + L.akey);
   d.spawn_cnt = (uint32_t*)(w + L.spawn_cnt);
   d.spawn_off = (uint32_t*)(w + L.spawn_off);
   d.newstop = (uint32_t*)(w + L.newstop);
