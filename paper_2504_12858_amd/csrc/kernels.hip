@@ -347,6 +347,13 @@ constexpr uint32_t MAX_PROBE = 4096;
 __device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A plain load, which the L2 of the reading chiplet may serve.  Each kernel
+// starts with the caches invalidated, so it returns the word as it was at the
+// kernel's start or a later value; the readers below take it for words whose
+// updates during the kernel do not change their outcome.
+__device__ __forceinline__ unsigned long long load_cached(const unsigned long long* p) {
+  return *p;
+}
 
 // Read-only probe: slot or -1.
 __device__ int64_t claim_find(const Dev& D, uint64_t key) {
@@ -360,12 +367,27 @@ __device__ int64_t claim_find(const Dev& D, uint64_t key) {
   return -1;
 }
 
-// Find or insert: slot or -1 (capacity error raised).
+// Read-only probe through the cache: a key inserted during the kernel may
+// be missed.
+__device__ int64_t claim_find_cached(const Dev& D, uint64_t key) {
+  uint64_t h = mix64(key) & D.cmask;
+  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
+    uint64_t idx = (h + p) & D.cmask;
+    uint64_t k = load_cached(&D.ckeys[idx]);
+    if (k == key) return (int64_t)idx;
+    if (k == CLAIM_EMPTY) return -1;
+  }
+  return -1;
+}
+
+// Find or insert: slot or -1 (capacity error raised).  A key never changes
+// once inserted, so the probes read through the cache: a stale empty entry
+// only sends the insertion to the compare-and-swap, whose result decides.
 __device__ int64_t claim_get(const Dev& D, uint64_t key) {
   uint64_t h = mix64(key) & D.cmask;
   for (uint32_t p = 0; p < MAX_PROBE; ++p) {
     uint64_t idx = (h + p) & D.cmask;
-    unsigned long long k = load_relaxed(&D.ckeys[idx]);
+    unsigned long long k = load_cached(&D.ckeys[idx]);
     if (k == key) return (int64_t)idx;
     if (k == CLAIM_EMPTY) {
       if (__hip_atomic_load(&D.cnt->claim_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
@@ -782,25 +804,26 @@ __device__ __forceinline__ bool cached_test(const Dev& D, SlotCache& c, uint32_t
   const uint64_t key = claim_key(g, sx, sy, sz);
   if (key != c.key) {
     c.key = key;
-    c.slot = claim_find(D, key);
+    c.slot = claim_find_cached(D, key);
   }
   if (c.slot < 0) return false;
   const uint32_t b = site_bit(sx, sy, sz);
   const unsigned long long m = 1ull << (b & 63);
   const unsigned long long* w = D.cbits + (size_t)c.slot * 24 + (b >> 6);
   unsigned long long v = 0;
-  if (which & M_CLAIMED) v |= load_relaxed(w + CB_CLAIMED);
-  if (which & M_REACHED) v |= load_relaxed(w + CB_REACHED);
-  if (which & M_NOW) v |= load_relaxed(w + CB_NOW);
+  if (which & M_CLAIMED) v |= load_cached(w + CB_CLAIMED);
+  if (which & M_REACHED) v |= load_cached(w + CB_REACHED);
+  if (which & M_NOW) v |= load_cached(w + CB_NOW);
   return (v & m) != 0;
 }
 
 // Claim words of the reached site S's slot around S: the z-layers
 // (S.z & 7) - 2 .. + 1.  Every target S + e and every same-step competitor
-// T - e' of a target T lies in them or in another slot.  The bits k_branch
-// tests do not change during the kernel (targets are claimed only by their
-// winner, reached sites carry this step's mark already), so they are read
-// once: one probe and twelve independent loads.
+// T - e' of a target T lies in them or in another slot.  No update made
+// during k_branch changes the outcome of its tests (a target is claimed only
+// by its winner, after that spawner's own test, and this step's marks do not
+// change), so the words are read once, through the cache: one probe and
+// twelve independent loads.  The same holds for the tests outside the window.
 struct SlotWin {
   int bx, by, bz, z0;
   unsigned long long a0, a1, a2, a3;  // claimed | reached | this step's marks
@@ -817,9 +840,9 @@ __device__ __forceinline__ SlotWin load_win(const Dev& D, uint32_t slot, int sx,
   auto layer = [&](int z, unsigned long long& any, unsigned long long& now) {
     unsigned long long c = 0, r = 0, m = 0;
     if (slot != NIL && z >= 0 && z < 8) {
-      c = load_relaxed(q + CB_CLAIMED + z);
-      r = load_relaxed(q + CB_REACHED + z);
-      m = load_relaxed(q + CB_NOW + z);
+      c = load_cached(q + CB_CLAIMED + z);
+      r = load_cached(q + CB_REACHED + z);
+      m = load_cached(q + CB_NOW + z);
     }
     any = c | r | m;
     now = m;
