@@ -1638,14 +1638,14 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     if (lane == 0) D.bown[b] = make_uint2(epoch, dirty ? BOWN_CELLS : g);
     if (!dirty) continue;
     // Owner grain of the active particles of each of the brick's 64 cells
-    // (one lane per cell).
+    // (one lane per cell): the brick's one grain, unless it holds several.
     const uint32_t ci = b * (uint32_t)BRICK_CELLS + (uint32_t)lane;
     const uint32_t st = D.cstart[ci];
     const uint32_t en = lane + 1 < BRICK_CELLS ? D.cstart[ci + 1] : own.x + own.y;
     // Four independent loads per round (the tail round repeats the last
     // particle, which leaves the owner unchanged).
-    uint32_t owner = NIL;
-    for (uint32_t j = st; j < en; j += 4u) {
+    uint32_t owner = g == gmax && en > st ? g : NIL;
+    for (uint32_t j = st; g != gmax && j < en; j += 4u) {
       const uint32_t l = en - 1u;
       const uint32_t g0 = grain_of(D.P[j]), g1 = grain_of(D.P[min(j + 1u, l)]);
       const uint32_t g2 = grain_of(D.P[min(j + 2u, l)]), g3 = grain_of(D.P[min(j + 3u, l)]);
