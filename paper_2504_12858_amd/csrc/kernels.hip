@@ -1291,6 +1291,28 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
 static_assert(SCAN_TILE == (int)SCAN_TILE_HOST, "brick-scan tile of the host launchers");
+static_assert(SCAN_ITEMS == 8, "two 16-byte loads per thread");
+
+// The counts of bricks b0 .. b0 + 7 (zero past the last brick): two 16-byte
+// loads when all eight exist (b0 is a multiple of eight and the count array
+// 256-byte aligned).
+__device__ __forceinline__ void load_counts8(const Dev& D, uint64_t b0, uint32_t c[8]) {
+  if (b0 + 8u <= D.n_bricks) {
+    const uint4 lo = *reinterpret_cast<const uint4*>(D.bcnt + b0);
+    const uint4 hi = *reinterpret_cast<const uint4*>(D.bcnt + b0 + 4);
+    c[0] = lo.x;
+    c[1] = lo.y;
+    c[2] = lo.z;
+    c[3] = lo.w;
+    c[4] = hi.x;
+    c[5] = hi.y;
+    c[6] = hi.z;
+    c[7] = hi.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = b0 + k < D.n_bricks ? D.bcnt[b0 + k] : 0u;
+  }
+}
 
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_scan_reduce(Bind Bd, int mode) {
@@ -1299,16 +1321,13 @@ __global__ __launch_bounds__(TPB) void k_scan_reduce(Bind Bd, int mode) {
   Bd.bind(D, V);
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
   __shared__ unsigned long long wsum[TPB / 64];
-  const uint64_t tile0 = (uint64_t)V.b * SCAN_TILE;
+  const uint64_t b0 = (uint64_t)V.b * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t c[SCAN_ITEMS];
+  load_counts8(D, b0, c);
   unsigned long long v = 0;
 #pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
-    if (b < D.n_bricks) {
-      const uint32_t c = D.bcnt[b];
-      v += (unsigned long long)c | ((unsigned long long)(c > 0u) << 32);
-    }
-  }
+  for (int k = 0; k < SCAN_ITEMS; ++k)
+    v += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
   unsigned long long total;
   block_excl_scan64(v, wsum, total);
   if (threadIdx.x == 0) D.scan_tmp[V.b] = total;
@@ -1359,20 +1378,27 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Bind Bd, int mode) {
   if (dead(D) || (mode == 1 && !resort_due(D))) return;
   const uint32_t epoch = step_epoch(D);
   __shared__ unsigned long long wsum[TPB / 64];
-  const uint64_t tile0 = (uint64_t)V.b * SCAN_TILE;
+  const uint64_t b0 = (uint64_t)V.b * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
   uint32_t c[SCAN_ITEMS];
+  load_counts8(D, b0, c);
   unsigned long long v = 0;
+  uint32_t any = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
-    c[k] = b < D.n_bricks ? D.bcnt[b] : 0u;
     v += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
+    any |= c[k];
   }
   unsigned long long total;
   unsigned long long ex = block_excl_scan64(v, wsum, total) + D.scan_tmp[V.b];
+  // Counts back to zero: the eight at once when they all exist.
+  const bool whole = b0 + 8u <= D.n_bricks;
+  if (whole && any) {
+    *reinterpret_cast<uint4*>(D.bcnt + b0) = make_uint4(0u, 0u, 0u, 0u);
+    *reinterpret_cast<uint4*>(D.bcnt + b0 + 4) = make_uint4(0u, 0u, 0u, 0u);
+  }
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const uint64_t b = tile0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+    const uint64_t b = b0 + k;
     if (b < D.n_bricks) {
       const uint32_t start = (uint32_t)(ex & 0xFFFFFFFFull);
       const uint32_t occ = (uint32_t)(ex >> 32);
@@ -1387,7 +1413,7 @@ __global__ __launch_bounds__(TPB) void k_scan_write(Bind Bd, int mode) {
           reinterpret_cast<uint32_t*>(m)[2] = 0u;
         }
         D.occ[occ] = (uint32_t)b;
-        D.bcnt[b] = 0u;
+        if (!whole) D.bcnt[b] = 0u;
       }
       ex += (unsigned long long)c[k] | ((unsigned long long)(c[k] > 0u) << 32);
     }
