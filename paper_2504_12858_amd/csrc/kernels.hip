@@ -1961,12 +1961,48 @@ __device__ __forceinline__ bool stencil_cell(const Stencil& s, int k, int& x, in
   return x <= s.x1 && y <= s.y1 && z <= s.z1;
 }
 
+// For the 2 x 2 x 2 stencil: the particle's own cell and, per axis, its
+// squared distance (in cells) to the neighbouring layer of the stencil.  A
+// stencil cell whose box lies farther than rc from the particle holds no
+// contact; the test keeps a margin of 0.01 cells (20 nm at 2 um cells),
+// far above the FP32 rounding of cell coordinates and distances, so a
+// skipped cell can never hold a particle that the distance test accepts.
+struct Near {
+  int c[3];
+  float d2[3];
+  float lim2;
+};
+__device__ __forceinline__ Near near_of(const Dev& D, P3 p) {
+  Near n;
+  const float x[3] = {p.x, p.y, p.z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float u = (x[a] - D.lo[a]) * D.inv_h;
+    const float fl = floorf(u);
+    n.c[a] = (int)fminf(fmaxf(fl, 0.0f), (float)(D.n[a] - 1));
+    const float f = u - fl;
+    const float d = f >= 0.5f ? 1.0f - f : f;
+    n.d2[a] = d * d;
+  }
+  const float lim = sqrtf(D.rc2) * D.inv_h + 0.01f;
+  n.lim2 = lim * lim;
+  return n;
+}
+__device__ __forceinline__ bool near_skips(const Near& n, int x, int y, int z) {
+  const float d2 = (x != n.c[0] ? n.d2[0] : 0.0f) + (y != n.c[1] ? n.d2[1] : 0.0f) +
+                   (z != n.c[2] ? n.d2[2] : 0.0f);
+  return d2 > n.lim2;
+}
+
 // Foreign-owner bits of the stencil cells (bit k: cell k holds active,
 // resp. stopped particles of another grain).  Owner words are loaded one
-// z-layer of the stencil at a time, all cells of a layer together.
+// z-layer of the stencil at a time, all cells of a layer together.  With
+// the 2 x 2 x 2 stencil and no periodic axis, cells out of reach
+// (near_skips) are left out.
 template <bool S8, bool PER>
 __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, const Stencil& st,
-                                               uint32_t g, uint32_t& act, uint32_t& stp) {
+                                               const Near& nr, uint32_t g, uint32_t& act,
+                                               uint32_t& stp) {
   constexpr int NL = S8 ? 2 : 3, PL = S8 ? 4 : 9;
   act = 0u;
   stp = 0u;
@@ -1978,6 +2014,7 @@ __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, con
       const int k = l * PL + u;
       int x, y, z;
       if (!stencil_cell<S8>(st, k, x, y, z)) continue;
+      if (S8 && !PER && near_skips(nr, x, y, z)) continue;
       const CellOwners o = cell_owners<PER>(D, epoch, x, y, z, g, cb, cbw);
       act |= (uint32_t)o.act << k;
       stp |= (uint32_t)o.stp << k;
@@ -2078,7 +2115,9 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
       stencil_axis(D, p.x, 0, st.x0, st.x1);
       stencil_axis(D, p.y, 1, st.y0, st.y1);
       stencil_axis(D, p.z, 2, st.z0, st.z1);
-      stencil_owners<S8, PER>(D, epoch, st, grain_of(q), act, stp);
+      Near nr{};
+      if (S8 && !PER) nr = near_of(D, p);
+      stencil_owners<S8, PER>(D, epoch, st, nr, grain_of(q), act, stp);
     }
     S.hit[threadIdx.x] = 0u;
     // Rounds: the lanes whose sources fit after those of the lanes before
