@@ -1463,14 +1463,17 @@ __device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g)
   atomicMin(&D.bmeta[b].y, g);
   atomicMax(&D.bmeta[b].z, g);
 }
-// The same for children, which arrive in no order: a relaxed read first, an
-// atomic only when the range grows (most children join a grain already
-// noted in their brick).
+// The same for children, which arrive in no order: a read first, an atomic
+// only when the range grows (most children join a grain already noted in
+// their brick).  The range only grows, so a read served by the cache (the
+// range as it was at the kernel's start, or wider) can only cost an atomic
+// that changes nothing.
 __device__ __forceinline__ void note_grain_checked(const Dev& D, uint32_t b, uint32_t g) {
   uint32_t* lo = &D.bmeta[b].y;
   uint32_t* hi = &D.bmeta[b].z;
-  if (g < __hip_atomic_load(lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(lo, g);
-  if (g > __hip_atomic_load(hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(hi, g);
+  const uint32_t clo = *lo, chi = *hi;
+  if (g < clo) atomicMin(lo, g);
+  if (g > chi) atomicMax(hi, g);
 }
 
 template <class Bind>
