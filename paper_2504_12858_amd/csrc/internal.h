@@ -89,7 +89,7 @@ struct Counters {
   uint32_t par;        // 1: the active-store roles of A and B (and their tags) are swapped
   uint32_t spar;       // 1: the roles of S, PS and S2, PS2 are swapped
   uint32_t epoch;      // step stamp of occupied bricks (starts at 1)
-  uint32_t pad0;
+  uint32_t dir_used;   // occupied entries of the claim-block directory
   double t;            // time
   unsigned long long step;  // steps taken
 };
@@ -188,13 +188,17 @@ struct Dev {
                        //  step), owner word of the stopped particles}
   uint32_t* occ;       // [bricks] occupied-brick list
   uint64_t* scan_tmp;  // block partial sums of the brick scan
-  // claims
-  unsigned long long* ckeys;   // [slots]
+  // claims: the slot bricks of a grain in blocks of 2 x 2 x 2, eight
+  // consecutive slots per block; a hash directory of the blocks
+  unsigned long long* ckeys;   // [slots] key of each taken slot, else CLAIM_EMPTY
   unsigned long long* cbits;   // [slots][3][8]: claimed, reached, now
   unsigned long long* clist;   // [slots] keys of the occupied slots in insertion order
                                //  (claim_used of them)
+  unsigned long long* dirkeys; // [blocks] block key of each directory entry
   uint64_t cmask;              // slots - 1
-  uint32_t claim_limit;        // occupancy limit of the hash
+  uint64_t dirmask;            // blocks - 1 (slots = 8 blocks)
+  uint32_t claim_limit;        // slots that can be taken
+  uint32_t dir_limit;          // occupancy limit of the directory
   // sites
   float* stab;         // [cap_sites][GT_STRIDE], [3] = nucleation undercooling
   uint32_t* sstate;    // [cap_sites]
@@ -229,7 +233,7 @@ struct Dev {
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bmeta) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \
-  X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(clist) X(stab) X(sstate) X(cand) X(sgrain) X(cnt) X(tagA)      \
+  X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(clist) X(dirkeys) X(stab) X(sstate) X(cand) X(sgrain) X(cnt) X(tagA)      \
   X(tagB) X(adj_rec) X(adj_nact) X(adj_sfin) X(adj_ck) X(adj_linc)
 constexpr uintptr_t NULL_OFFSET = ~(uintptr_t)0;
 

@@ -355,57 +355,75 @@ __device__ __forceinline__ unsigned long long load_cached(const unsigned long lo
   return *p;
 }
 
+// Claim slots.  The slot bricks of a grain are grouped 2 x 2 x 2 into
+// blocks of eight consecutive slots, so that the claim words of nearby sites
+// lie close together in memory (few pages, hence few address translations,
+// per wave).  A hash directory (open addressing, linear probing) places the
+// blocks: slot = 8 * (directory entry of the block) + position in the block.
+__device__ __forceinline__ uint64_t claim_block_key(uint64_t key) {
+  return key & ~((1ull << 24) | (1ull << 12) | 1ull);
+}
+__device__ __forceinline__ uint64_t claim_fine(uint64_t key) {
+  return ((key >> 24) & 1ull) | (((key >> 12) & 1ull) << 1) | ((key & 1ull) << 2);
+}
+
+// Directory entry of a block, or -1; through the cache or not.
+template <bool CACHED>
+__device__ __forceinline__ int64_t block_find(const Dev& D, uint64_t bkey) {
+  const uint64_t h = mix64(bkey) & D.dirmask;
+  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
+    const uint64_t idx = (h + p) & D.dirmask;
+    const uint64_t k = CACHED ? load_cached(&D.dirkeys[idx]) : load_relaxed(&D.dirkeys[idx]);
+    if (k == bkey) return (int64_t)idx;
+    if (k == CLAIM_EMPTY) return -1;
+  }
+  return -1;
+}
+
 // Read-only probe: slot or -1.
 __device__ int64_t claim_find(const Dev& D, uint64_t key) {
-  uint64_t h = mix64(key) & D.cmask;
-  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
-    uint64_t idx = (h + p) & D.cmask;
-    uint64_t k = load_relaxed(&D.ckeys[idx]);
-    if (k == key) return (int64_t)idx;
-    if (k == CLAIM_EMPTY) return -1;
-  }
-  return -1;
+  const int64_t b = block_find<false>(D, claim_block_key(key));
+  if (b < 0) return -1;
+  const uint64_t slot = (uint64_t)b * 8u + claim_fine(key);
+  return load_relaxed(&D.ckeys[slot]) == key ? (int64_t)slot : -1;
 }
 
-// Read-only probe through the cache: a key inserted during the kernel may
-// be missed.
-__device__ int64_t claim_find_cached(const Dev& D, uint64_t key) {
-  uint64_t h = mix64(key) & D.cmask;
-  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
-    uint64_t idx = (h + p) & D.cmask;
-    uint64_t k = load_cached(&D.ckeys[idx]);
-    if (k == key) return (int64_t)idx;
-    if (k == CLAIM_EMPTY) return -1;
-  }
-  return -1;
-}
-
-// Find or insert: slot or -1 (capacity error raised).  A key never changes
+// Find or insert: slot or -1 (capacity error raised).  Keys never change
 // once inserted, so the probes read through the cache: a stale empty entry
 // only sends the insertion to the compare-and-swap, whose result decides.
+// A slot can only ever hold its own key.
 __device__ int64_t claim_get(const Dev& D, uint64_t key) {
-  uint64_t h = mix64(key) & D.cmask;
-  for (uint32_t p = 0; p < MAX_PROBE; ++p) {
-    uint64_t idx = (h + p) & D.cmask;
-    unsigned long long k = load_cached(&D.ckeys[idx]);
-    if (k == key) return (int64_t)idx;
-    if (k == CLAIM_EMPTY) {
-      if (__hip_atomic_load(&D.cnt->claim_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-          D.claim_limit) {
+  const uint64_t bkey = claim_block_key(key);
+  const uint64_t h = mix64(bkey) & D.dirmask;
+  int64_t blk = -1;
+  for (uint32_t p = 0; p < MAX_PROBE && blk < 0; ++p) {
+    const uint64_t idx = (h + p) & D.dirmask;
+    const unsigned long long k = load_cached(&D.dirkeys[idx]);
+    if (k == bkey) {
+      blk = (int64_t)idx;
+    } else if (k == CLAIM_EMPTY) {
+      if (__hip_atomic_load(&D.cnt->dir_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+          D.dir_limit) {
         atomicOr(&D.cnt->err, ERR_CAPACITY);
         return -1;
       }
-      unsigned long long prev = atomicCAS(&D.ckeys[idx], CLAIM_EMPTY, (unsigned long long)key);
-      if (prev == CLAIM_EMPTY) {
-        // One count per slot taken, so the list index stays below the slots.
-        D.clist[atomicAdd(&D.cnt->claim_used, 1u)] = key;
-        return (int64_t)idx;
-      }
-      if (prev == key) return (int64_t)idx;
+      const unsigned long long prev =
+          atomicCAS(&D.dirkeys[idx], CLAIM_EMPTY, (unsigned long long)bkey);
+      if (prev == CLAIM_EMPTY) atomicAdd(&D.cnt->dir_used, 1u);
+      if (prev == CLAIM_EMPTY || prev == bkey) blk = (int64_t)idx;
     }
   }
-  atomicOr(&D.cnt->err, ERR_CAPACITY);
-  return -1;
+  if (blk < 0) {
+    atomicOr(&D.cnt->err, ERR_CAPACITY);
+    return -1;
+  }
+  const uint64_t slot = (uint64_t)blk * 8u + claim_fine(key);
+  if (load_cached(&D.ckeys[slot]) != key &&
+      atomicCAS(&D.ckeys[slot], CLAIM_EMPTY, (unsigned long long)key) == CLAIM_EMPTY) {
+    // One count per slot taken, so the list index stays below the slots.
+    D.clist[atomicAdd(&D.cnt->claim_used, 1u)] = key;
+  }
+  return (int64_t)slot;
 }
 
 __device__ __forceinline__ void claim_or(const Dev& D, uint32_t g, int sx, int sy, int sz,
@@ -792,24 +810,34 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) 
 }
 
 
-// One-entry cache of claim-hash slots: the sites a spawner tests lie within
-// two lattice steps of its reached site, mostly in the same 8^3 slot brick.
+// One-entry cache of claim slots: the sites a spawner claims lie within one
+// lattice step of its reached site, mostly in the same 8^3 slot brick.
 struct SlotCache {
   uint64_t key;
   int64_t slot;
 };
+// One-entry cache of claim blocks for the tests: the sites a spawner tests
+// lie within two lattice steps of its reached site, mostly in the same
+// block of 2 x 2 x 2 slot bricks.  A slot of a known block that was never
+// taken has all its words zero, so the tests read it without checking.
+struct BlockCache {
+  uint64_t bkey;
+  int64_t blk;
+};
 
-__device__ __forceinline__ bool cached_test(const Dev& D, SlotCache& c, uint32_t g, int sx, int sy,
-                                            int sz, uint32_t which) {
+__device__ __forceinline__ bool cached_test(const Dev& D, BlockCache& c, uint32_t g, int sx,
+                                            int sy, int sz, uint32_t which) {
   const uint64_t key = claim_key(g, sx, sy, sz);
-  if (key != c.key) {
-    c.key = key;
-    c.slot = claim_find_cached(D, key);
+  const uint64_t bkey = claim_block_key(key);
+  if (bkey != c.bkey) {
+    c.bkey = bkey;
+    c.blk = block_find<true>(D, bkey);
   }
-  if (c.slot < 0) return false;
+  if (c.blk < 0) return false;
+  const uint64_t slot = (uint64_t)c.blk * 8u + claim_fine(key);
   const uint32_t b = site_bit(sx, sy, sz);
   const unsigned long long m = 1ull << (b & 63);
-  const unsigned long long* w = D.cbits + (size_t)c.slot * 24 + (b >> 6);
+  const unsigned long long* w = D.cbits + (size_t)slot * 24 + (b >> 6);
   unsigned long long v = 0;
   if (which & M_CLAIMED) v |= load_cached(w + CB_CLAIMED);
   if (which & M_REACHED) v |= load_cached(w + CB_REACHED);
@@ -1199,7 +1227,7 @@ __global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
       S[0] = rec_sx(r) + ((d >> 1) == 0 ? dstep : 0);
       S[1] = rec_sy(r) + ((d >> 1) == 1 ? dstep : 0);
       S[2] = rec_sz(r) + ((d >> 1) == 2 ? dstep : 0);
-      SlotCache sc{~0ull, -1};
+      BlockCache sc{~0ull, -1};
       const SlotWin win = load_win(D, slot, S[0], S[1], S[2]);
       for (int dd = 0; dd < 6; ++dd) {
         const int a = dd >> 1;
