@@ -44,6 +44,12 @@ constexpr int STREAM_GRID = 2048;
 // Claim hash: 8^3 lattice sites per slot, three 512-bit masks per slot
 // (claimed as target, reached, reached during the current step).
 constexpr uint64_t CLAIM_EMPTY = ~0ull;
+// Claim slot bricks per block along each axis: 2^CLAIM_BLOCK_BITS.
+constexpr int CLAIM_BLOCK_BITS = 1;
+constexpr uint64_t CLAIM_BLOCK_SLOTS = 1ull << (3 * CLAIM_BLOCK_BITS);
+// Slots in the pool per slot brick asked for (blocks at the fringe of a
+// grain are partly used).
+constexpr uint64_t CLAIM_POOL_FACTOR = 2;
 constexpr uint32_t NIL = 0xFFFFFFFFu;
 constexpr uint32_t MIXED = 0xFFFFFFFEu;  // owner word: particles of several grains
 constexpr uint32_t BOWN_CELLS = 0xFFFFFFFDu;  // brick owner word: see the cells' words
@@ -188,15 +194,15 @@ struct Dev {
                        //  step), owner word of the stopped particles}
   uint32_t* occ;       // [bricks] occupied-brick list
   uint64_t* scan_tmp;  // block partial sums of the brick scan
-  // claims: the slot bricks of a grain in blocks of 2 x 2 x 2, eight
-  // consecutive slots per block; a hash directory of the blocks
+  // claims: the slot bricks of a grain in cubic blocks of CLAIM_BLOCK_SLOTS
+  // consecutive slots; a hash directory of the blocks
   unsigned long long* ckeys;   // [slots] key of each taken slot, else CLAIM_EMPTY
   unsigned long long* cbits;   // [slots][3][8]: claimed, reached, now
   unsigned long long* clist;   // [slots] keys of the occupied slots in insertion order
                                //  (claim_used of them)
   unsigned long long* dirkeys; // [blocks] block key of each directory entry
   uint64_t cmask;              // slots - 1
-  uint64_t dirmask;            // blocks - 1 (slots = 8 blocks)
+  uint64_t dirmask;            // blocks - 1 (slots = CLAIM_BLOCK_SLOTS blocks)
   uint32_t claim_limit;        // slots that can be taken
   uint32_t dir_limit;          // occupancy limit of the directory
   // sites

@@ -355,16 +355,19 @@ __device__ __forceinline__ unsigned long long load_cached(const unsigned long lo
   return *p;
 }
 
-// Claim slots.  The slot bricks of a grain are grouped 2 x 2 x 2 into
-// blocks of eight consecutive slots, so that the claim words of nearby sites
-// lie close together in memory (few pages, hence few address translations,
-// per wave).  A hash directory (open addressing, linear probing) places the
-// blocks: slot = 8 * (directory entry of the block) + position in the block.
+// Claim slots.  The slot bricks of a grain are grouped into cubic blocks
+// (2^CLAIM_BLOCK_BITS slot bricks per axis) of consecutive slots, so that the
+// claim words of nearby sites lie close together in memory (few pages, hence
+// few address translations, per wave).  A hash directory (open addressing,
+// linear probing) places the blocks: slot = CLAIM_BLOCK_SLOTS * (directory
+// entry of the block) + position in the block.
+constexpr uint64_t CB_LOW = (1ull << CLAIM_BLOCK_BITS) - 1ull;
 __device__ __forceinline__ uint64_t claim_block_key(uint64_t key) {
-  return key & ~((1ull << 24) | (1ull << 12) | 1ull);
+  return key & ~((CB_LOW << 24) | (CB_LOW << 12) | CB_LOW);
 }
 __device__ __forceinline__ uint64_t claim_fine(uint64_t key) {
-  return ((key >> 24) & 1ull) | (((key >> 12) & 1ull) << 1) | ((key & 1ull) << 2);
+  return ((key >> 24) & CB_LOW) | (((key >> 12) & CB_LOW) << CLAIM_BLOCK_BITS) |
+         ((key & CB_LOW) << (2 * CLAIM_BLOCK_BITS));
 }
 
 // Directory entry of a block, or -1; through the cache or not.
@@ -384,7 +387,7 @@ __device__ __forceinline__ int64_t block_find(const Dev& D, uint64_t bkey) {
 __device__ int64_t claim_find(const Dev& D, uint64_t key) {
   const int64_t b = block_find<false>(D, claim_block_key(key));
   if (b < 0) return -1;
-  const uint64_t slot = (uint64_t)b * 8u + claim_fine(key);
+  const uint64_t slot = (uint64_t)b * CLAIM_BLOCK_SLOTS + claim_fine(key);
   return load_relaxed(&D.ckeys[slot]) == key ? (int64_t)slot : -1;
 }
 
@@ -417,7 +420,7 @@ __device__ int64_t claim_get(const Dev& D, uint64_t key) {
     atomicOr(&D.cnt->err, ERR_CAPACITY);
     return -1;
   }
-  const uint64_t slot = (uint64_t)blk * 8u + claim_fine(key);
+  const uint64_t slot = (uint64_t)blk * CLAIM_BLOCK_SLOTS + claim_fine(key);
   if (load_cached(&D.ckeys[slot]) != key &&
       atomicCAS(&D.ckeys[slot], CLAIM_EMPTY, (unsigned long long)key) == CLAIM_EMPTY) {
     // One count per slot taken, so the list index stays below the slots.
@@ -818,7 +821,7 @@ struct SlotCache {
 };
 // One-entry cache of claim blocks for the tests: the sites a spawner tests
 // lie within two lattice steps of its reached site, mostly in the same
-// block of 2 x 2 x 2 slot bricks.  A slot of a known block that was never
+// block of slot bricks.  A slot of a known block that was never
 // taken has all its words zero, so the tests read it without checking.
 struct BlockCache {
   uint64_t bkey;
@@ -834,7 +837,7 @@ __device__ __forceinline__ bool cached_test(const Dev& D, BlockCache& c, uint32_
     c.blk = block_find<true>(D, bkey);
   }
   if (c.blk < 0) return false;
-  const uint64_t slot = (uint64_t)c.blk * 8u + claim_fine(key);
+  const uint64_t slot = (uint64_t)c.blk * CLAIM_BLOCK_SLOTS + claim_fine(key);
   const uint32_t b = site_bit(sx, sy, sz);
   const unsigned long long m = 1ull << (b & 63);
   const unsigned long long* w = D.cbits + (size_t)slot * 24 + (b >> 6);

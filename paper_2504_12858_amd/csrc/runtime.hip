@@ -106,9 +106,7 @@ Geometry geometry(const ge_params* p) {
     g.n_bricks *= (uint64_t)g.nb[a];
   }
   g.n_cells = g.n_bricks * ge::BRICK_CELLS;  // brick-major, padded to whole bricks
-  // Twice the slot bricks asked for: blocks at the fringe of a grain are
-  // partly used.
-  g.slots = 2 * next_pow2((uint64_t)std::max<int64_t>(p->cap_claim_bricks, 1024));
+  g.slots = ge::CLAIM_POOL_FACTOR * next_pow2((uint64_t)std::max<int64_t>(p->cap_claim_bricks, 1024));
   g.field_nodes = 1;
   for (int a = 0; a < 3; ++a) g.field_nodes *= (uint64_t)std::max(p->field_n[a], 0);
   if (p->field_n[0] == 0) g.field_nodes = 0;
@@ -159,7 +157,7 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.ckeys = put(8 * g.slots);
   L.cbits = put(192 * g.slots);
   L.clist = put(8 * g.slots);
-  L.dirkeys = put(8 * (g.slots / 8));
+  L.dirkeys = put(8 * (g.slots / ge::CLAIM_BLOCK_SLOTS));
   L.gtab = put(4 * ge::GT_STRIDE * (uint64_t)p->cap_grains);
   L.gbox = put(24 * (uint64_t)p->cap_grains);
   L.stab = put(4 * ge::GT_STRIDE * (uint64_t)std::max(p->cap_sites, 1));
@@ -358,7 +356,7 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.spawn_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.newstop_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.ckeys, 0xFF, 8 * g.slots, s));
-  HIPCHK(c, hipMemsetAsync(w + L.dirkeys, 0xFF, g.slots, s));
+  HIPCHK(c, hipMemsetAsync(w + L.dirkeys, 0xFF, 8 * (g.slots / ge::CLAIM_BLOCK_SLOTS), s));
   HIPCHK(c, hipMemsetAsync(w + L.cbits, 0, 192 * g.slots, s));
   HIPCHK(c, hipMemsetAsync(w + L.cnt, 0, sizeof(ge::Counters), s));
   HIPCHK(c, hipMemsetAsync(w + L.cand, 0, 4 * (uint64_t)std::max(c->p.cap_sites, 1), s));
@@ -521,9 +519,10 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.cbits = (unsigned long long*)(w + L.cbits);
   d.dirkeys = (unsigned long long*)(w + L.dirkeys);
   d.cmask = g.slots - 1;
-  d.dirmask = g.slots / 8 - 1;
+  d.dirmask = g.slots / ge::CLAIM_BLOCK_SLOTS - 1;
   d.claim_limit = (uint32_t)std::min<uint64_t>(g.slots, 0xFFFFFFFFull);
-  d.dir_limit = (uint32_t)std::min<uint64_t>(g.slots / 8 - g.slots / 32, 0xFFFFFFFFull);
+  const uint64_t blocks = g.slots / ge::CLAIM_BLOCK_SLOTS;
+  d.dir_limit = (uint32_t)std::min<uint64_t>(blocks - blocks / 4, 0xFFFFFFFFull);
   d.stab = (float*)(w + L.stab);
   d.sstate = (uint32_t*)(w + L.sstate);
   d.cand = (uint32_t*)(w + L.cand);
