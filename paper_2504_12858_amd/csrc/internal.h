@@ -192,6 +192,8 @@ struct Dev {
                        //  single-grain brick, or BOWN_CELLS for a dirty brick}
   uint2* cown;         // [cells] {owner word of the active particles (dirty bricks, this
                        //  step), owner word of the stopped particles}
+  uint32_t* smask;     // [cells] slabs (eighths of the cell per axis, 8 bits per axis)
+                       //  that hold stopped particles
   uint32_t* occ;       // [bricks] occupied-brick list
   uint64_t* scan_tmp;  // block partial sums of the brick scan
   // claims: the slot bricks of a grain in cubic blocks of CLAIM_BLOCK_SLOTS
@@ -239,7 +241,7 @@ struct Dev {
   X(newstop_cnt) X(S) X(PS) X(S2) X(PS2) X(snext) X(shead) X(sstart) X(bsinfo)      \
   X(ccnt) X(cstart) X(bcnt) X(binfo) X(bmeta) X(dlist) X(dlist_cnt) X(dpart) X(dmask)       \
   X(doff) X(bown)                                                                             \
-  X(cown) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(clist) X(dirkeys) X(stab) X(sstate) X(cand) X(sgrain) X(cnt) X(tagA)      \
+  X(cown) X(smask) X(occ) X(scan_tmp) X(ckeys) X(cbits) X(clist) X(dirkeys) X(stab) X(sstate) X(cand) X(sgrain) X(cnt) X(tagA)      \
   X(tagB) X(adj_rec) X(adj_nact) X(adj_sfin) X(adj_ck) X(adj_linc)
 constexpr uintptr_t NULL_OFFSET = ~(uintptr_t)0;
 

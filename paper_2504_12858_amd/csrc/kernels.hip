@@ -927,6 +927,22 @@ __device__ __forceinline__ uint32_t owner_merge(uint32_t own, uint32_t g) {
 }
 
 // ------------------------------------------------------- stopped store ----
+// Slab bits of a position in its cell: bit 8 a + k for the k-th eighth of
+// the cell along axis a (the cell coordinate as in cell_of).
+__device__ __forceinline__ uint32_t slab_bits(const Dev& D, P3 p) {
+  const float x[3] = {p.x, p.y, p.z};
+  uint32_t bits = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float u = (x[a] - D.lo[a]) * D.inv_h;
+    const float f = u - floorf(u);
+    const bool inside = u >= 0.0f && u < (float)D.n[a];
+    const uint32_t k = min((uint32_t)(f * 8.0f), 7u);
+    bits |= (inside ? (1u << k) : 0xFFu) << (8 * a);
+  }
+  return bits;
+}
+
 // Writes record r (state STOPPED) and its placed position pw (wrapped
 // position, owner word) at slot j of the stopped store and links it into the
 // cell list of recently stopped particles.  Callers run in kernels that
@@ -943,6 +959,10 @@ __device__ __forceinline__ void stopped_put(const Dev& D, uint32_t j, uint4 r, f
   const uint32_t ci = cell_index(D, c.x, c.y, c.z);
   const uint32_t old = atomicExch(&D.shead[ci], j);
   D.snext[j] = old;
+  // The slab of each axis that holds the particle (all eight of an axis
+  // whose position lies outside the grid, clamped into its outer cell).
+  const uint32_t bits = slab_bits(D, p3_of(pw));
+  if ((D.smask[ci] & bits) != bits) atomicOr(&D.smask[ci], bits);
   // Owner word of the cell's stopped particles; it only moves from NIL to a
   // grain to MIXED, so a stale read costs one failed compare-and-swap.
   uint32_t* sown = &D.cown[ci].y;
@@ -2003,6 +2023,7 @@ __device__ __forceinline__ bool stencil_cell(const Stencil& s, int k, int& x, in
 // skipped cell can never hold a particle that the distance test accepts.
 struct Near {
   int c[3];
+  float u[3];  // cell coordinates of the particle
   float d2[3];
   float lim2;
 };
@@ -2013,6 +2034,7 @@ __device__ __forceinline__ Near near_of(const Dev& D, P3 p) {
   for (int a = 0; a < 3; ++a) {
     const float u = (x[a] - D.lo[a]) * D.inv_h;
     const float fl = floorf(u);
+    n.u[a] = u;
     n.c[a] = (int)fminf(fmaxf(fl, 0.0f), (float)(D.n[a] - 1));
     const float f = u - fl;
     const float d = f >= 0.5f ? 1.0f - f : f;
@@ -2021,6 +2043,22 @@ __device__ __forceinline__ Near near_of(const Dev& D, P3 p) {
   const float lim = sqrtf(D.rc2) * D.inv_h + 0.01f;
   n.lim2 = lim * lim;
   return n;
+}
+// The stopped particles of stencil cell (x, y, z), within the slabs of
+// mask m, all lie farther than rc from the particle (same margin).
+__device__ __forceinline__ bool slabs_far(const Near& n, uint32_t m, int x, int y, int z) {
+  const int cc[3] = {x, y, z};
+  float d2 = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const uint32_t s = (m >> (8 * a)) & 0xFFu;
+    if (!s) return false;
+    const float lo = (float)cc[a] + 0.125f * (float)(__ffs((int)s) - 1);
+    const float hi = (float)cc[a] + 0.125f * (float)(32 - __clz((int)s));
+    const float d = fmaxf(fmaxf(lo - n.u[a], n.u[a] - hi), 0.0f);
+    d2 += d * d;
+  }
+  return d2 > n.lim2;
 }
 __device__ __forceinline__ bool near_skips(const Near& n, int x, int y, int z) {
   const float d2 = (x != n.c[0] ? n.d2[0] : 0.0f) + (y != n.c[1] ? n.d2[1] : 0.0f) +
@@ -2032,7 +2070,8 @@ __device__ __forceinline__ bool near_skips(const Near& n, int x, int y, int z) {
 // resp. stopped particles of another grain).  Owner words are loaded one
 // z-layer of the stencil at a time, all cells of a layer together.  With
 // the 2 x 2 x 2 stencil and no periodic axis, cells out of reach
-// (near_skips) are left out.
+// (near_skips) are left out, and so are stopped particles whose slabs in
+// their cell lie out of reach (slabs_far).
 template <bool S8, bool PER>
 __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, const Stencil& st,
                                                const Near& nr, uint32_t g, uint32_t& act,
@@ -2050,8 +2089,15 @@ __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, con
       if (!stencil_cell<S8>(st, k, x, y, z)) continue;
       if (S8 && !PER && near_skips(nr, x, y, z)) continue;
       const CellOwners o = cell_owners<PER>(D, epoch, x, y, z, g, cb, cbw);
+      bool ostp = o.stp;
+      if (S8 && !PER) {
+        // The slab mask, loaded with the owner words: stopped particles out
+        // of reach are no sources.
+        const uint32_t m = D.smask[o.ci];
+        ostp = ostp && !slabs_far(nr, m, x, y, z);
+      }
       act |= (uint32_t)o.act << k;
-      stp |= (uint32_t)o.stp << k;
+      stp |= (uint32_t)ostp << k;
     }
   }
 }

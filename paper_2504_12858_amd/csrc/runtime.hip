@@ -33,7 +33,7 @@ struct Geometry {
 
 struct Layout {
   size_t A, B, P, spawn, spslot, spawn_cnt, spawn_off, newstop, newstop_cnt, S, PS, S2, PS2, snext, shead, sstart,
-      bsinfo, ccnt, cstart, bcnt, binfo, bmeta, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, occ, scan_tmp, ckeys, cbits, clist, dirkeys, gtab, gbox,
+      bsinfo, ccnt, cstart, bcnt, binfo, bmeta, dlist, dlist_cnt, dpart, dmask, doff, bown, cown, smask, occ, scan_tmp, ckeys, cbits, clist, dirkeys, gtab, gbox,
       stab, sstate, cand, sgrain, fgrid, gcnt, fcmin, fcoarse, mslots, greach, gsite, gdead, cnt, dig, total;
 };
 
@@ -152,6 +152,7 @@ Layout layout(const ge_params* p, const Geometry& g) {
   L.dmask = put(8 * g.n_bricks);
   L.doff = put(4 * g.n_bricks);
   L.cown = put(8 * g.n_cells);
+  L.smask = put(4 * g.n_cells);
   L.occ = put(4 * g.n_bricks);
   L.scan_tmp = put(8 * ntiles);
   L.ckeys = put(8 * g.slots);
@@ -352,6 +353,7 @@ static ge_status reset_device(ge_ctx* c) {
   HIPCHK(c, hipMemsetAsync(w + L.dlist_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.bown, 0, 8 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.cown, 0xFF, 8 * g.n_cells, s));
+  HIPCHK(c, hipMemsetAsync(w + L.smask, 0, 4 * g.n_cells, s));
   HIPCHK(c, hipMemsetAsync(w + L.bsinfo, 0, 8 * g.n_bricks, s));
   HIPCHK(c, hipMemsetAsync(w + L.spawn_cnt, 0, 4 * ge::STREAM_GRID, s));
   HIPCHK(c, hipMemsetAsync(w + L.newstop_cnt, 0, 4 * ge::STREAM_GRID, s));
@@ -512,6 +514,7 @@ ge_status ge_create(const ge_params* p, void* workspace, size_t bytes, void* str
   d.dmask = (unsigned long long*)(w + L.dmask);
   d.doff = (uint32_t*)(w + L.doff);
   d.cown = (uint2*)(w + L.cown);
+  d.smask = (uint32_t*)(w + L.smask);
   d.occ = (uint32_t*)(w + L.occ);
   d.scan_tmp = (uint64_t*)(w + L.scan_tmp);
   d.ckeys = (unsigned long long*)(w + L.ckeys);
