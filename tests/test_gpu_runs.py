@@ -147,6 +147,31 @@ def test_capacity_error_is_reported_and_sticky():
     assert e2.value.status == B.GE_ESTATE
 
 
+def test_claim_capacity_error_is_reported_and_sticky():
+    """Claim slot bricks are grouped in blocks of a hash directory, which
+    holds three quarters of (2 x cap_claim_bricks) / 8 blocks: 192 for
+    cap_claim_bricks = 1024.  Three hundred grains far apart need a block
+    each, so the claims run out (GE_ECAPACITY), and the context then refuses
+    further steps."""
+    require_gpu()
+    p = B.make_params((0, 0, 0), (1e-3,) * 3, 5e-6, 5e-6, 5e-6, W.KIN_A, W.KIN_B,
+                      cap_particles=1 << 14, cap_stopped=1 << 14, cap_grains=512,
+                      cap_claim_bricks=1024)
+    ctx = B.Context(p)
+    ctx.set_thermal_field(W.Field(W.FIELD_UNIFORM, dT=5.0))
+    g = W.rng(11)
+    n = 300
+    centres = 1e-4 + 8e-4 * g.random((n, 3))
+    with pytest.raises(B.GrainEnvError) as e:
+        ctx.init_grains(centres, W.shoemake_quaternions(g, n), np.zeros(n, np.int32))
+        ctx.step(1e-4, 2)
+    assert e.value.status == B.GE_ECAPACITY
+    with pytest.raises(B.GrainEnvError) as e2:
+        ctx.step(1e-4, 1)
+    assert e2.value.status == B.GE_ESTATE
+    ctx.close()
+
+
 def test_cfl_error():
     require_gpu()
     w = W.nucleus_uniform(lambda0=5e-6, dT=5.0)
