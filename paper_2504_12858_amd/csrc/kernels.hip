@@ -2069,9 +2069,12 @@ __device__ __forceinline__ bool near_skips(const Near& n, int x, int y, int z) {
 // Foreign-owner bits of the stencil cells (bit k: cell k holds active,
 // resp. stopped particles of another grain).  Owner words are loaded one
 // z-layer of the stencil at a time, all cells of a layer together.  With
-// the 2 x 2 x 2 stencil and no periodic axis, cells out of reach
-// (near_skips) are left out, and so are stopped particles whose slabs in
-// their cell lie out of reach (slabs_far).
+// the 2 x 2 x 2 stencil, cells out of reach (near_skips) are left out, and
+// so are stopped particles whose slabs in their cell lie out of reach
+// (slabs_far).  Both take the stencil cells unwrapped: on a periodic axis
+// a cell past a face is the image of the cell it wraps to, at the distance
+// of that image, and with r_c <= h/2 only the images through the stencil's
+// own side can come within r_c.
 template <bool S8, bool PER>
 __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, const Stencil& st,
                                                const Near& nr, uint32_t g, uint32_t& act,
@@ -2087,10 +2090,10 @@ __device__ __forceinline__ void stencil_owners(const Dev& D, uint32_t epoch, con
       const int k = l * PL + u;
       int x, y, z;
       if (!stencil_cell<S8>(st, k, x, y, z)) continue;
-      if (S8 && !PER && near_skips(nr, x, y, z)) continue;
+      if (S8 && near_skips(nr, x, y, z)) continue;
       const CellOwners o = cell_owners<PER>(D, epoch, x, y, z, g, cb, cbw);
       bool ostp = o.stp;
-      if (S8 && !PER) {
+      if (S8) {
         // The slab mask, loaded with the owner words: stopped particles out
         // of reach are no sources.
         const uint32_t m = D.smask[o.ci];
@@ -2196,7 +2199,7 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
       stencil_axis(D, p.y, 1, st.y0, st.y1);
       stencil_axis(D, p.z, 2, st.z0, st.z1);
       Near nr{};
-      if (S8 && !PER) nr = near_of(D, p);
+      if (S8) nr = near_of(D, p);
       stencil_owners<S8, PER>(D, epoch, st, nr, grain_of(q), act, stp);
     }
     S.hit[threadIdx.x] = 0u;
