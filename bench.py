@@ -155,7 +155,9 @@ def cet_workload():
     return W.cet(**CET_KNOBS)
 
 
-RESORT_EVERY = 16
+# Steps between re-sorts of the stopped store for the CET workload (the
+# containment's recent-stop lists grow with it, the re-sort's share falls).
+RESORT_EVERY = 24
 
 
 def make_context(w):
