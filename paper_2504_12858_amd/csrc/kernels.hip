@@ -1193,8 +1193,10 @@ __device__ __forceinline__ uint32_t spawn_pos(const SpawnView& v, const uint32_t
   return chunk_at(v.n, TPB, v.G, lo).begin + (i - s_off[lo]);
 }
 
+// At most 80 registers, for six waves per SIMD: more waves in flight hide
+// more of the latency of the branching's loads and atomics.
 template <class Bind>
-__global__ __launch_bounds__(TPB) void k_branch(Bind Bd) {
+__global__ __launch_bounds__(TPB, 6) void k_branch(Bind Bd) {
   Dev D;
   VGrid V;
   Bd.bind(D, V);
