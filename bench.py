@@ -5,12 +5,15 @@ Workload: columnar-to-equiaxed transition under a moving Rosenthal source
 (4 x 2 x 1 mm box, 256^3 FP32 undercooling grid resampled every step, 800
 face and 800 bulk nuclei, lambda0 = rc = 1 um, cells of h = 2 um, dT0 = 12 K), advanced
 untimed from t = 0 to the first step with >= 20M active particles.  Then W
-warm-up steps and K timed steps, bracketed by stream synchronisations.
+warm-up steps (an event between every two phases: the dominant phase) and K
+timed steps with two events per step around the dominant phase alone,
+bracketed by stream synchronisations; then one re-sort interval of steps with
+an event between every two phases gives the phase table.
 
 value     = particle updates (active particles advanced) over the K steps / s
 roofline  = the dominant phase's algorithmic bytes per launch / its average
-            launch duration (HIP events on the context's stream over the
-            timed region), against the 8 TB/s HBM peak
+            launch duration (HIP events around it on the context's stream in
+            every timed step), against the 8 TB/s HBM peak
 step_roofline = value x the method's algorithmic bytes per update of the whole
             step (83 B at this workload) against the same peak
 cpu_baseline = the FP64 oracle stepping a spatial window of the same snapshot
@@ -854,10 +857,19 @@ def main():
         t_tune = time.perf_counter()
         best = ctx.autotune(w.dt, args.autotune)
         log(f"[autotune] {best} in {time.perf_counter() - t_tune:.1f} s")
+    # The warm-up steps run with an event between every two phases (plain
+    # launches): the phase table, and the phase that takes longest.
+    phases, n_prof = {}, 0
     if args.warmup:
+        ctx.profile(1)
         ctx.step(w.dt, args.warmup)
-    torch.cuda.synchronize()
-    ctx.profile(1)
+        phases, n_prof = ctx.profile_read()
+        ctx.profile(0)
+    dom = (max((k for k in phases if k in PHASE_BYTES), key=lambda k: phases[k])
+           if n_prof else "contain")
+    # The timed steps carry two events per step around that phase alone (an
+    # event between every two phases costs the step about 1 %).
+    ctx.profile_phase(dom)
     torch.cuda.synchronize()
     REGION.resume()
     t0 = time.perf_counter()
@@ -865,8 +877,17 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     REGION.pause()
-    phases, n_prof = ctx.profile_read()
+    dom_ms, n_dom = ctx.profile_read()
     ctx.profile(0)
+    if n_dom != args.steps or not dom_ms[dom] > 0:
+        raise RuntimeError(f"phase timer: {n_dom} steps, {dom_ms[dom]} ms for {dom}")
+    # The phase table: one re-sort interval after the timed steps, an event
+    # between every two phases.
+    if args.steps:
+        ctx.profile(1)
+        ctx.step(w.dt, RESORT_EVERY)
+        phases, n_prof = ctx.profile_read()
+        ctx.profile(0)
     elapsed = t1 - t0
     value = stats["advanced"] / elapsed
     ms_step = 1e3 * elapsed / args.steps
@@ -875,9 +896,9 @@ def main():
         f"{stats['spawners']} children {stats['children']} contained {stats['contained']} "
         f"pair tests {stats['pair_tests']} dirty {stats['dirty_tests']}")
     for k, v in sorted(phases.items(), key=lambda kv: -kv[1]):
-        log(f"[phase] {k:9s} {v / max(n_prof, 1):8.3f} ms/step")
-    dom = max((k for k in phases if k in PHASE_BYTES), key=lambda k: phases[k])
-    avg_ms = phases[dom] / max(n_prof, 1)
+        log(f"[phase] {k:9s} {v / max(n_prof, 1):8.3f} ms/step (after the timed steps)")
+    avg_ms = dom_ms[dom] / n_dom
+    log(f"[timed phase] {dom} {avg_ms:.4f} ms/step over the timed steps")
     units = stats["advanced"] / args.steps
     if dom == "resample":
         units = float(w.field.n[0] * w.field.n[1] * w.field.n[2])
@@ -917,6 +938,7 @@ def main():
                    "schedule": ctx.schedule(), "autotuned": bool(args.autotune),
                    "schedule_set": args.schedule or None},
         "phases_ms_per_step": {k: round(v / max(n_prof, 1), 4) for k, v in phases.items()},
+        "phases_window": f"{n_prof} steps after the timed ones, an event between every two phases",
         "roofline": roofline,
         "step_roofline": step_roofline,
         "step_traffic": step_traffic,

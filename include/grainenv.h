@@ -462,6 +462,13 @@ ge_status ge_restore_state(ge_ctx* ctx, const void* blob, size_t bytes);
 ge_status ge_profile(ge_ctx* ctx, int32_t on);
 ge_status ge_profile_read(ge_ctx* ctx, double* ms /*[GE_N_PHASES]*/, int64_t* steps);
 const char* ge_phase_name(int32_t phase);
+/* Times one phase alone (0 <= phase < GE_N_PHASES; -1 stops), with two HIP
+   events per step around it on the context's stream, instead of one between
+   every two phases: the rest of the step runs without events in between.
+   Steps run plain while it is on (HIP does not time events recorded inside a
+   graph).  Clears the totals, which ge_profile_read returns (zero for the
+   other phases); ge_profile ends it.  GE_EINVAL for a phase out of range. */
+ge_status ge_profile_phase(ge_ctx* ctx, int32_t phase);
 
 /* Recorded step sequences.  With graphs on (the default), a ge_step call of
    at least 2 resort_every steps runs plain steps up to a step count that is
@@ -471,7 +478,8 @@ const char* ge_phase_name(int32_t phase);
    state lives in device memory), so replays give the same results as plain
    steps.  The recording is made again after any change of the launch
    arguments (schedule, model, field, sites, time step).  Phase profiling
-   (ge_profile) runs plain steps.  ge_use_graphs(ctx, 0) turns it off. */
+   (ge_profile, ge_profile_phase) runs plain steps.  ge_use_graphs(ctx, 0)
+   turns it off. */
 ge_status ge_use_graphs(ge_ctx* ctx, int32_t on);
 /* Records the step sequence for time step dt now, so that the next ge_step
    call with that dt starts replaying at once. */

@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
         "ge_restore_state": ([vp, vp, C.c_size_t], C.c_int32),
         "ge_profile": ([vp, C.c_int32], C.c_int32),
         "ge_profile_read": ([vp, P(C.c_double), P(C.c_int64)], C.c_int32),
+        "ge_profile_phase": ([vp, C.c_int32], C.c_int32),
         "ge_phase_name": ([C.c_int32], C.c_char_p),
         "ge_get_schedule": ([vp, P(C.c_int32)], C.c_int32),
         "ge_set_schedule": ([vp, P(C.c_int32)], C.c_int32),
@@ -176,7 +177,7 @@ EXPORTED = ("ge_workspace_size", "ge_validate_params", "ge_create", "ge_destroy"
             "ge_nucleate", "ge_step",
             "ge_query_envelope", "ge_query_particles_noalloc", "ge_load_state",
             "ge_save_state", "ge_state_check",
-            "ge_restore_state", "ge_profile", "ge_profile_read",
+            "ge_restore_state", "ge_profile", "ge_profile_read", "ge_profile_phase",
             "ge_phase_name", "ge_get_schedule", "ge_set_schedule", "ge_autotune",
             "ge_tunable_name", "ge_set_model", "ge_adjoint_workspace_size", "ge_adjoint_forward",
             "ge_adjoint_positions", "ge_adjoint_tracked", "ge_adjoint_backward",
@@ -475,6 +476,18 @@ class Context:
 
     def profile(self, on):
         self._check(self.lib.ge_profile(self.ctx, int(on)), "ge_profile")
+
+    def profile_phase(self, phase):
+        """Times one phase (by name or index; None stops) in every step,
+        recorded step sequences included."""
+        if phase is None:
+            k = -1
+        elif isinstance(phase, str):
+            names = [self.lib.ge_phase_name(i).decode() for i in range(N_PHASES)]
+            k = names.index(phase)
+        else:
+            k = int(phase)
+        self._check(self.lib.ge_profile_phase(self.ctx, k), "ge_profile_phase")
 
     def profile_read(self):
         ms = (C.c_double * N_PHASES)()

@@ -247,7 +247,9 @@ struct ge_ctx {
   std::string err;
   // phase timing
   bool prof_on = false;
-  std::vector<hipEvent_t> ev_pool;   // GE_N_PHASES + 1 events per recorded step
+  bool capturing = false;            // a step sequence is being recorded
+  int prof_one = -1;                 // phase timed alone (ge_profile_phase), -1: none
+  std::vector<hipEvent_t> ev_pool;   // GE_N_PHASES + 1 (or 2) events per recorded step
   size_t ev_used = 0;                // events recorded since the last read
   double prof_ms[GE_N_PHASES] = {0};
   int64_t prof_steps = 0;
@@ -266,25 +268,50 @@ static const char* PHASE_NAMES[GE_N_PHASES] = {
     "resample", "advance",  "branch",   "scan",   "scatter", "children",
     "dirty",    "contain", "stoplink", "nucleate", "finish", "resort"};
 
-// Records the event that closes phase `k` of the current step (k = -1 opens
-// the step).
-static void prof_mark(ge_ctx* c, int k) {
-  if (!c->prof_on) return;
-  (void)k;
+// The next event of the pool (null if none can be created).
+static hipEvent_t pool_event(ge_ctx* c) {
   if (c->ev_used == c->ev_pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) {
-      c->prof_on = false;
-      return;
-    }
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
     c->ev_pool.push_back(e);
   }
-  (void)hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
+  return c->ev_pool[c->ev_used++];
+}
+
+// Records the event that closes phase `k` of the current step (k = -1 opens
+// the step).  The single-phase timer records only the two events around its
+// phase.  Neither records while a step sequence is being recorded.
+static void prof_mark(ge_ctx* c, int k) {
+  if (c->capturing) return;
+  if (c->prof_one >= 0) {
+    if (k != c->prof_one - 1 && k != c->prof_one) return;
+    const hipEvent_t e = pool_event(c);
+    if (e) (void)hipEventRecord(e, c->stream);
+    return;
+  }
+  if (!c->prof_on) return;
+  const hipEvent_t e = pool_event(c);
+  if (!e) {
+    c->prof_on = false;
+    return;
+  }
+  (void)hipEventRecord(e, c->stream);
 }
 
 static void prof_collect(ge_ctx* c) {
   if (c->ev_used == 0) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->prof_one >= 0) {
+    const size_t steps = c->ev_used / 2;
+    for (size_t st = 0; st < steps; ++st) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, c->ev_pool[2 * st], c->ev_pool[2 * st + 1]) == hipSuccess)
+        c->prof_ms[c->prof_one] += ms;
+    }
+    c->prof_steps += (int64_t)steps;
+    c->ev_used = 0;
+    return;
+  }
   const size_t per = GE_N_PHASES + 1;
   const size_t steps = c->ev_used / per;
   for (size_t st = 0; st < steps; ++st)
@@ -810,7 +837,7 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
   ge::launch_reset_stats(c->d, c->stream);
   int32_t k = 0;
   const int32_t R = c->resort_every;
-  if (c->use_graphs && !c->prof_on && n_steps >= 2 * R) {
+  if (c->use_graphs && !c->prof_on && c->prof_one < 0 && n_steps >= 2 * R) {
     // Plain steps up to a multiple of resort_every, then whole recorded
     // sequences of resort_every steps, then the rest plain.
     while (k < n_steps && c->hstep % (uint64_t)R != 0) {
@@ -842,7 +869,8 @@ ge_status ge_step(ge_ctx* c, double dt, int32_t n_steps, ge_step_stats* stats) {
 static void step_once(ge_ctx* c, double dt) {
   hipStream_t s = c->stream;
   const Dev& d = c->d;
-  if (c->prof_on && c->ev_used + GE_N_PHASES + 1 > 4096) prof_collect(c);
+  if ((c->prof_on || c->prof_one >= 0) && !c->capturing && c->ev_used + GE_N_PHASES + 1 > 4096)
+    prof_collect(c);
   prof_mark(c, -1);
   if (c->field.kind == GE_FIELD_ROSENTHAL) ge::launch_resample(d, s);
   // Melting uses the field of this step.
@@ -892,7 +920,9 @@ static ge_status ensure_graph(ge_ctx* c, double dt) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+    c->capturing = true;
     for (int32_t k = 0; k < c->resort_every; ++k) step_once(c, dt);
+    c->capturing = false;
     e = hipStreamEndCapture(c->cap_stream, &g);
   }
   c->stream = user;
@@ -1082,15 +1112,26 @@ ge_status ge_query_particles_noalloc(ge_ctx* c, const ge_query_args* args, void*
 
 ge_status ge_profile(ge_ctx* c, int32_t on) {
   if (!c) return GE_EINVAL;
+  prof_collect(c);
+  c->prof_one = -1;
   if (on) {
-    prof_collect(c);
     for (double& v : c->prof_ms) v = 0;
     c->prof_steps = 0;
     c->prof_on = true;
   } else {
-    prof_collect(c);
     c->prof_on = false;
   }
+  return GE_OK;
+}
+
+ge_status ge_profile_phase(ge_ctx* c, int32_t phase) {
+  if (!c) return GE_EINVAL;
+  if (phase < -1 || phase >= GE_N_PHASES) return fail(c, GE_EINVAL, "phase out of range");
+  prof_collect(c);
+  c->prof_on = false;
+  c->prof_one = phase;
+  for (double& v : c->prof_ms) v = 0;
+  c->prof_steps = 0;
   return GE_OK;
 }
 

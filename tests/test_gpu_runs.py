@@ -329,6 +329,32 @@ def test_autotune_keeps_results():
     ref.close()
 
 
+def test_phase_timer_times_one_phase():
+    """ge_profile_phase times one phase with two events per step: every step
+    is counted, only that phase gets time, and the state equals that of a
+    context stepped with graph replays and no timer."""
+    require_gpu()
+    w = _scaled_cet(seed=4)
+    a, b = context_for(w), context_for(w)
+    for phase, n in (("advance", 40), ("contain", 33), ("contain", 64)):
+        a.profile_phase(phase)
+        sa, sb = a.step(w.dt, n), b.step(w.dt, n)
+        ms, steps = a.profile_read()
+        assert steps == n
+        assert ms[phase] > 0.0
+        assert all(v == 0.0 for k, v in ms.items() if k != phase)
+        sa.pop("pair_tests")
+        sb.pop("pair_tests")
+        assert sa == sb
+        assert _state_bytes(a) == _state_bytes(b)
+    a.profile(0)
+    with pytest.raises(B.GrainEnvError) as e:
+        a.profile_phase(B.N_PHASES)
+    assert e.value.status == B.GE_EINVAL
+    a.close()
+    b.close()
+
+
 def test_graph_replays_equal_plain_steps():
     """ge_step replays a recorded graph of resort_every steps; every call
     (with host work and synchronisation in between) leaves the same state as
