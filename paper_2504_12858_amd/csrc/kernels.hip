@@ -2628,11 +2628,14 @@ __global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
   const double base_t = a.dT0 + a.rate * t;
   const double k2 = -a.U / (2.0 * a.alpha);
   const double qn = a.q / (2.0 * M_PI);
-  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total;
-       v += (uint64_t)V.G * TPB) {
-    const uint64_t i = v % (uint64_t)D.fn[0];
-    const uint64_t j = (v / (uint64_t)D.fn[0]) % (uint64_t)D.fn[1];
-    const uint64_t k = v / ((uint64_t)D.fn[0] * D.fn[1]);
+  // Node indices (i, j, k) of v, carried from one grid-stride step to the
+  // next (the stride split the same way once), so that no step divides.
+  const uint64_t n0 = (uint64_t)D.fn[0], n1 = (uint64_t)D.fn[1];
+  const uint64_t stride = (uint64_t)V.G * TPB;
+  const uint64_t s0 = stride % n0, s1 = (stride / n0) % n1, s2 = stride / (n0 * n1);
+  uint64_t v = (uint64_t)V.b * TPB + threadIdx.x;
+  uint64_t i = v % n0, j = (v / n0) % n1, k = v / (n0 * n1);
+  for (; v < total; v += stride) {
     const double X = a.o[0] + (double)i * a.sp[0];
     const double Y = a.o[1] + (double)j * a.sp[1];
     const double Z = a.o[2] + (double)k * a.sp[2];
@@ -2643,6 +2646,13 @@ __global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
     double dT = base_t + a.grad[0] * X + a.grad[1] * Y + a.grad[2] * Z - rise;
     if (dT < a.dT_min) dT = a.dT_min;
     D.fgrid[v] = (float)dT;
+    i += s0;
+    const uint64_t ci = i >= n0 ? 1u : 0u;
+    i -= ci * n0;
+    j += s1 + ci;
+    const uint64_t cj = j >= n1 ? 1u : 0u;
+    j -= cj * n1;
+    k += s2 + cj;
   }
 }
 
