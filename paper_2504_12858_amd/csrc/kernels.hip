@@ -2607,6 +2607,33 @@ __global__ void k_srb_finish(Bind Bd) {
 
 // Rosenthal moving point source on a linear background, evaluated in FP64
 // at every node and stored as FP32 undercooling.
+// Grid-stride walk over the points of an n0 x n1 x n2 grid: the indices
+// (i, j, k) of the point v are carried from one step to the next (the stride
+// split the same way once), so that no step divides.
+struct GridWalk {
+  uint64_t n0, n1, s0, s1, s2, v, stride, i, j, k;
+  __device__ GridWalk(uint64_t n0_, uint64_t n1_, uint64_t v0, uint64_t stride_)
+      : n0(n0_), n1(n1_), v(v0), stride(stride_) {
+    s0 = stride % n0;
+    s1 = (stride / n0) % n1;
+    s2 = stride / (n0 * n1);
+    i = v % n0;
+    j = (v / n0) % n1;
+    k = v / (n0 * n1);
+  }
+  __device__ uint64_t next() {
+    i += s0;
+    const uint64_t ci = i >= n0 ? 1u : 0u;
+    i -= ci * n0;
+    j += s1 + ci;
+    const uint64_t cj = j >= n1 ? 1u : 0u;
+    j -= cj * n1;
+    k += s2 + cj;
+    v += stride;
+    return v;
+  }
+};
+
 template <class Bind>
 __global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
   Dev D;
@@ -2628,17 +2655,12 @@ __global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
   const double base_t = a.dT0 + a.rate * t;
   const double k2 = -a.U / (2.0 * a.alpha);
   const double qn = a.q / (2.0 * M_PI);
-  // Node indices (i, j, k) of v, carried from one grid-stride step to the
-  // next (the stride split the same way once), so that no step divides.
-  const uint64_t n0 = (uint64_t)D.fn[0], n1 = (uint64_t)D.fn[1];
-  const uint64_t stride = (uint64_t)V.G * TPB;
-  const uint64_t s0 = stride % n0, s1 = (stride / n0) % n1, s2 = stride / (n0 * n1);
-  uint64_t v = (uint64_t)V.b * TPB + threadIdx.x;
-  uint64_t i = v % n0, j = (v / n0) % n1, k = v / (n0 * n1);
-  for (; v < total; v += stride) {
-    const double X = a.o[0] + (double)i * a.sp[0];
-    const double Y = a.o[1] + (double)j * a.sp[1];
-    const double Z = a.o[2] + (double)k * a.sp[2];
+  GridWalk gw((uint64_t)D.fn[0], (uint64_t)D.fn[1], (uint64_t)V.b * TPB + threadIdx.x,
+              (uint64_t)V.G * TPB);
+  for (uint64_t v = gw.v; v < total; v = gw.next()) {
+    const double X = a.o[0] + (double)gw.i * a.sp[0];
+    const double Y = a.o[1] + (double)gw.j * a.sp[1];
+    const double Z = a.o[2] + (double)gw.k * a.sp[2];
     const double xi = sg * (X - xs), dy = Y - a.ys, dz = Z - a.zs;
     double r = sqrt(xi * xi + dy * dy + dz * dz);
     if (r < a.r_min) r = a.r_min;
@@ -2646,13 +2668,6 @@ __global__ __launch_bounds__(TPB) void k_resample(Bind Bd) {
     double dT = base_t + a.grad[0] * X + a.grad[1] * Y + a.grad[2] * Z - rise;
     if (dT < a.dT_min) dT = a.dT_min;
     D.fgrid[v] = (float)dT;
-    i += s0;
-    const uint64_t ci = i >= n0 ? 1u : 0u;
-    i -= ci * n0;
-    j += s1 + ci;
-    const uint64_t cj = j >= n1 ? 1u : 0u;
-    j -= cj * n1;
-    k += s2 + cj;
   }
 }
 
@@ -2685,9 +2700,9 @@ __global__ __launch_bounds__(TPB) void k_field_cellmin(Bind Bd) {
   const uint32_t cx = (uint32_t)D.fn[0] - 1u, cy = (uint32_t)D.fn[1] - 1u, cz = (uint32_t)D.fn[2] - 1u;
   const uint64_t total = (uint64_t)cx * cy * cz;
   const size_t sy = (size_t)D.fn[0], sz = (size_t)D.fn[0] * (size_t)D.fn[1];
-  for (uint64_t v = (uint64_t)V.b * TPB + threadIdx.x; v < total; v += (uint64_t)V.G * TPB) {
-    const uint64_t i = v % cx, j = (v / cx) % cy, k = v / ((uint64_t)cx * cy);
-    const size_t b = k * sz + j * sy + i;
+  GridWalk gw(cx, cy, (uint64_t)V.b * TPB + threadIdx.x, (uint64_t)V.G * TPB);
+  for (uint64_t v = gw.v; v < total; v = gw.next()) {
+    const size_t b = gw.k * sz + gw.j * sy + gw.i;
     const float* g = D.fgrid;
     float m = fminf(fminf(g[b], g[b + 1]), fminf(g[b + sy], g[b + sy + 1]));
     m = fminf(m, fminf(fminf(g[b + sz], g[b + sz + 1]), fminf(g[b + sz + sy], g[b + sz + sy + 1])));
