@@ -1395,19 +1395,38 @@ __global__ __launch_bounds__(TPB) void k_scan_top(Bind Bd, int mode) {
   const uint32_t ntiles = (uint32_t)((D.n_bricks + SCAN_TILE - 1) / SCAN_TILE);
   __shared__ unsigned long long wsum[TPB / 64];
   // Each thread takes a run of consecutive tiles: their sum, one block scan
-  // of the sums, then the run's exclusive prefixes.
+  // of the sums, then the run's exclusive prefixes.  Runs of up to TOP_RUN
+  // tiles are loaded at once into registers (one round trip instead of one
+  // per tile); longer runs, for grids of more than TPB x TOP_RUN tiles, loop.
+  constexpr uint32_t TOP_RUN = 48;
   const uint32_t per = (ntiles + TPB - 1u) / TPB;
   const uint32_t t0 = threadIdx.x * per;
-  unsigned long long sum = 0;
-  for (uint32_t q = 0; q < per; ++q)
-    if (t0 + q < ntiles) sum += D.scan_tmp[t0 + q];
   unsigned long long carry;
-  unsigned long long run = block_excl_scan64(sum, wsum, carry);
-  for (uint32_t q = 0; q < per; ++q) {
-    if (t0 + q >= ntiles) break;
-    const unsigned long long v = D.scan_tmp[t0 + q];
-    D.scan_tmp[t0 + q] = run;
-    run += v;
+  if (per <= TOP_RUN) {
+    unsigned long long v[TOP_RUN];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < TOP_RUN; ++q) {
+      v[q] = q < per && t0 + q < ntiles ? D.scan_tmp[t0 + q] : 0ull;
+      sum += v[q];
+    }
+    unsigned long long run = block_excl_scan64(sum, wsum, carry);
+#pragma unroll
+    for (uint32_t q = 0; q < TOP_RUN; ++q) {
+      if (q < per && t0 + q < ntiles) D.scan_tmp[t0 + q] = run;
+      run += v[q];
+    }
+  } else {
+    unsigned long long sum = 0;
+    for (uint32_t q = 0; q < per; ++q)
+      if (t0 + q < ntiles) sum += D.scan_tmp[t0 + q];
+    unsigned long long run = block_excl_scan64(sum, wsum, carry);
+    for (uint32_t q = 0; q < per; ++q) {
+      if (t0 + q >= ntiles) break;
+      const unsigned long long x = D.scan_tmp[t0 + q];
+      D.scan_tmp[t0 + q] = run;
+      run += x;
+    }
   }
   if (threadIdx.x == 0) {
     const uint32_t n_out = (uint32_t)(carry & 0xFFFFFFFFull);
