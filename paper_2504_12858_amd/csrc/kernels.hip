@@ -2584,25 +2584,31 @@ __global__ __launch_bounds__(TPB) void k_srb_scatter(Bind Bd) {
   if (dead(D) || !resort_due(D)) return;
   const uint32_t n = min(D.cnt->n_stopped, D.cap_s);
   const Chunk ch = chunk_of(V, n, TPB);
+  // The record comes with the position and the cell start before the rank
+  // atomic: a wave's memory operations retire in order, so a load issued
+  // after the atomic would wait for its round trip.
   for (uint32_t base = ch.begin; base < ch.end; base += TPB) {
     const uint32_t j = base + threadIdx.x;
     uint32_t ckey = NIL;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
     if (j < ch.end) {
       q = D.PS[j];
+      r = D.S[j];
       if (!isnan(q.x)) {
         const C3 c = cell_of(D, p3_of(q));
         ckey = cell_index(D, c.x, c.y, c.z);
       }
     }
+    const uint32_t cs = ckey != NIL ? D.sstart[ckey] : 0u;
     const Run run = wave_run(ckey);
     uint32_t rbase = 0;
     if (ckey != NIL && run.off == 0) rbase = atomicSub(&D.ccnt[ckey], (uint32_t)run.len);
     rbase = __shfl(rbase, run.head);
     if (ckey != NIL) {
-      const uint32_t dst = D.sstart[ckey] + rbase - (uint32_t)run.len + (uint32_t)run.off;
+      const uint32_t dst = cs + rbase - (uint32_t)run.len + (uint32_t)run.off;
       if (dst < D.cap_s) {
-        D.S2[dst] = D.S[j];
+        D.S2[dst] = r;
         D.PS2[dst] = q;
       }
     }
