@@ -1535,17 +1535,15 @@ __device__ __forceinline__ void note_grain(const Dev& D, uint32_t b, uint32_t g)
   atomicMin(&D.bmeta[b].y, g);
   atomicMax(&D.bmeta[b].z, g);
 }
-// The same for children, which arrive in no order: a read first, an atomic
-// only when the range grows (most children join a grain already noted in
-// their brick).  The range only grows, so a read served by the cache (the
+// The same for children, which arrive in no order: the range is read first
+// (by the caller, clo and chi), an atomic only when it grows (most children
+// join a grain already noted in their brick).  The range only grows, so a read served by the cache (the
 // range as it was at the kernel's start, or wider) can only cost an atomic
 // that changes nothing.
-__device__ __forceinline__ void note_grain_checked(const Dev& D, uint32_t b, uint32_t g) {
-  uint32_t* lo = &D.bmeta[b].y;
-  uint32_t* hi = &D.bmeta[b].z;
-  const uint32_t clo = *lo, chi = *hi;
-  if (g < clo) atomicMin(lo, g);
-  if (g > chi) atomicMax(hi, g);
+__device__ __forceinline__ void note_grain_seen(uint32_t* range, uint32_t clo, uint32_t chi,
+                                                uint32_t g) {
+  if (g < clo) atomicMin(range, g);
+  if (g > chi) atomicMax(range + 1, g);
 }
 
 template <class Bind>
@@ -1629,14 +1627,19 @@ __global__ __launch_bounds__(TPB) void k_scatter_children(Bind Bd) {
       const float4 xc = placed4(D, frame_pos(F, dd, sc), gs);
       const C3 c = cell_of(D, p3_of(xc));
       const uint32_t ci = cell_index(D, c.x, c.y, c.z);
+      // The cell start and the brick's grain range are read before the rank
+      // atomic: a wave's memory operations retire in order, so a load issued
+      // after it would wait for its round trip.
+      uint32_t* range = &D.bmeta[ci / (uint32_t)BRICK_CELLS].y;
+      const uint32_t cs = D.cstart[ci], rlo = range[0], rhi = range[1];
       const uint32_t rank = atomicSub(&D.ccnt[ci], 1u) - 1u;
-      const uint32_t dst = D.cstart[ci] + rank;
+      const uint32_t dst = cs + rank;
       if (dst < D.cap_p) {
         D.B[dst] = make_rec(sc, gs, dd, S[0], S[1], S[2], ST_ACTIVE);
         D.P[dst] = xc;
         if (D.tagA) D.tagB[dst] = NIL;
       }
-      note_grain_checked(D, ci / (uint32_t)BRICK_CELLS, grain_of(xc));
+      note_grain_seen(range, rlo, rhi, grain_of(xc));
     }
   }
 }
