@@ -2166,11 +2166,13 @@ __device__ __forceinline__ void stencil_entries(const Dev& D, const Stencil& st,
 }
 
 
+constexpr uint32_t HIT_BUF = 64;  // stops held per wave before they are written out
 struct ContainShared {
   uint32_t n, tests;
   float4 pos[TPB];
   uint32_t hit[TPB];
   uint3 ent[TPB / 64][CE_MAX];
+  uint2 hbuf[TPB / 64][HIT_BUF];  // {position in the block's stop list, particle}
 };
 
 // Containment (particles of two grains that meet stop, Sec. 2.1.2; the
@@ -2194,6 +2196,8 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
   const uint32_t lane = (uint32_t)lane_id();
   const uint32_t w = threadIdx.x >> 6;
   uint3* ent = S.ent[w];
+  uint2* hbuf = S.hbuf[w];
+  uint32_t nbuf = 0;  // stops held in hbuf (the same in every lane)
   const float rc2 = D.rc2;
   uint32_t tests = 0;
   // The particle of the next group is fetched during this one (its list
@@ -2261,16 +2265,30 @@ __device__ __forceinline__ void contain_body(const Dev& D, const VGrid& V, uint3
       wave_lds_sync();
       if (!__any(ne > 0u)) break;
     }
+    // Stops are held in LDS and written out a few groups at a time: a wave's
+    // memory operations retire in order, so a store here would hold back the
+    // first loads of the next group.
     const bool hit = k < ch.end && S.hit[threadIdx.x] != 0u;
     const unsigned long long m = __ballot(hit);
     if (m) {
+      const uint32_t c = (uint32_t)__popcll(m);
+      if (nbuf + c > HIT_BUF) {
+        wave_lds_sync();
+        for (uint32_t t = lane; t < nbuf; t += 64u) D.newstop[ch.begin + hbuf[t].x] = hbuf[t].y;
+        wave_lds_sync();
+        nbuf = 0;
+      }
       const int leader = __ffsll((long long)m) - 1;
       uint32_t wb = 0;
-      if ((int)lane == leader) wb = atomicAdd(&S.n, (uint32_t)__popcll(m));
+      if ((int)lane == leader) wb = atomicAdd(&S.n, c);
       wb = __shfl(wb, leader);
-      if (hit) D.newstop[ch.begin + wb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+      const uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (hit) hbuf[nbuf + r] = make_uint2(wb + r, i);
+      nbuf += c;
     }
   }
+  wave_lds_sync();
+  for (uint32_t t = lane; t < nbuf; t += 64u) D.newstop[ch.begin + hbuf[t].x] = hbuf[t].y;
   // Pair tests: one shared-memory add per wave, one global add per block.
   uint32_t wtests;
   (void)wave_excl_scan(tests, wtests);
