@@ -1710,6 +1710,27 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     own1 = D.binfo[b1];
     fetch(b1, n1);
   }
+  // The stores of a brick are issued in the next iteration, once its loads
+  // are on their way: a wave's memory operations retire in order, and stores
+  // at the end of an iteration would be waited for before the next one.
+  uint32_t pb = NIL;         // brick with stores pending (the same in every lane)
+  uint32_t pbown = 0u;       // its owner word
+  bool pcells = false;       // its cell owner words are pending (a dirty brick)
+  uint32_t powner = 0u;      // this lane's cell owner word
+  bool plist = false;        // its list entry is pending (lane 0)
+  uint32_t pslot = 0u, poff = 0u;
+  unsigned long long pmask = 0ull;
+  auto flush = [&]() {
+    if (pb == NIL) return;
+    if (lane == 0) D.bown[pb] = make_uint2(epoch, pbown);
+    if (pcells) D.cown[pb * (uint32_t)BRICK_CELLS + (uint32_t)lane].x = powner;
+    if (plist) {
+      D.dlist[ch.begin + pslot] = pb;
+      D.dmask[ch.begin + pslot] = pmask;
+      D.doff[ch.begin + pslot] = poff;
+    }
+    pb = NIL;
+  };
   for (uint32_t k = k0; k < ch.end; k += W) {
     const uint32_t b = b1;
     const uint2 own = own1;
@@ -1723,6 +1744,7 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     // The brick's own owner range (lane 13).
     const uint32_t g = (uint32_t)__shfl((int)nn.y, 13);
     const uint32_t gmax = (uint32_t)__shfl((int)nn.z, 13);
+    flush();
     const bool foreign = (nn.x == epoch && !(nn.y == g && nn.z == g)) ||
                          (nn.w != NIL && nn.w != g);
     // Flagged bricks; the brick itself (bit 13) when it holds several grains
@@ -1739,7 +1761,10 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     const uint32_t flags =
         (uint32_t)__ballot(foreign) | (g != gmax || face ? (1u << 13) : 0u);
     const bool dirty = flags != 0u;
-    if (lane == 0) D.bown[b] = make_uint2(epoch, dirty ? BOWN_CELLS : g);
+    pb = b;
+    pbown = dirty ? BOWN_CELLS : g;
+    pcells = false;
+    plist = false;
     if (!dirty) continue;
     // Owner grain of the active particles of each of the brick's 64 cells
     // (one lane per cell): the brick's one grain, unless it holds several.
@@ -1755,7 +1780,8 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
       const uint32_t g2 = grain_of(D.P[min(j + 2u, l)]), g3 = grain_of(D.P[min(j + 3u, l)]);
       owner = owner_merge(owner_merge(owner_merge(owner_merge(owner, g0), g1), g2), g3);
     }
-    D.cown[ci].x = owner;
+    pcells = true;
+    powner = owner;
     const bool need = (flags & (1u << 13)) != 0u || (flags & reach) != 0u;
     const uint32_t cnt = need ? en - st : 0u;
     const unsigned long long mask = __ballot(cnt > 0u);
@@ -1763,12 +1789,13 @@ __global__ __launch_bounds__(TPB) void k_dirty(Bind Bd) {
     uint32_t tot;
     (void)wave_excl_scan(cnt, tot);
     if (lane == 0) {
-      const uint32_t slot = atomicAdd(&s_n, 1u);
-      D.dlist[ch.begin + slot] = b;
-      D.dmask[ch.begin + slot] = mask;
-      D.doff[ch.begin + slot] = atomicAdd(&s_np, tot);
+      plist = true;
+      pslot = atomicAdd(&s_n, 1u);
+      pmask = mask;
+      poff = atomicAdd(&s_np, tot);
     }
   }
+  flush();
   __syncthreads();
   if (threadIdx.x == 0) s_base = s_np ? atomicAdd(&D.cnt->n_dpart, s_np) : 0u;
   __syncthreads();
